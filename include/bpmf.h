@@ -1,0 +1,321 @@
+/*
+ * bpmf.h -- C ABI of libbpmf, the MI355X (gfx950) hot path of grid-based
+ * binding-potential-of-mean-force (BPMF) sampling, after D. D. L. Minh,
+ * "Alchemical Grid Dock (AlGDock): Binding Free Energy Calculations between
+ * Flexible Ligands and Rigid Receptors" (arXiv 1507.03703).
+ *
+ * The library samples a flexible ligand against a rigid receptor that is
+ * represented by precomputed interaction grids, with replica-exchange
+ * Hamiltonian Monte Carlo over a ladder of thermodynamic states, and builds
+ * the reduced-energy matrix u_kn that MBAR turns into free energies.
+ *
+ * Conventions shared by every entry point
+ *   Units      A, fs, amu, kJ/mol, elementary charge, K.
+ *   Status     every function returns BPMF_OK (0) or a negative BPMF_E_* code;
+ *              bpmf_last_error() returns the calling thread's last message.
+ *              Nothing aborts and no C++ exception crosses this boundary.
+ *   Memory     "host" pointers are read (or written) during the call only and
+ *              stay owned by the caller.  "device" pointers are HIP device
+ *              addresses owned by the caller; the library reads/writes them in
+ *              stream order.  Persistent device state (grid, ligands,
+ *              replicas, samples, scratch) is allocated through the allocator
+ *              callback given to bpmf_create (hipMalloc if none) and released
+ *              by bpmf_destroy.
+ *   Streams    all device work is enqueued on the stream given to
+ *              bpmf_create.  Calls that return host data synchronise that
+ *              stream; the others return without waiting.
+ *   Validation arguments are checked before anything is enqueued; a failed
+ *              check leaves all state unchanged.  Asynchronous HIP failures
+ *              surface as BPMF_E_HIP on a later call.
+ *   Numerics   a non-finite Hamiltonian or exchange exponent is not an error:
+ *              the move is rejected and counted (see bpmf_get_stats).
+ *   Threads    one context per host thread.
+ *   Determinism the same inputs, seed, build and GPU give bitwise-identical
+ *              results (no floating-point atomics on any result path).
+ */
+#ifndef BPMF_H
+#define BPMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(BPMF_BUILD)
+#define BPMF_API __attribute__((visibility("default")))
+#else
+#define BPMF_API
+#endif
+
+enum {
+  BPMF_OK = 0,
+  BPMF_E_INVAL = -1,  /* invalid argument (message says which) */
+  BPMF_E_NOMEM = -2,  /* allocation failed */
+  BPMF_E_HIP = -3,    /* HIP runtime error */
+  BPMF_E_STATE = -4,  /* call made in the wrong order */
+  BPMF_E_UNIMPL = -5  /* option not supported by this build */
+};
+
+/* Limits of this build. */
+#define BPMF_MAX_ATOMS 128     /* atoms per ligand */
+#define BPMF_MAX_CHANNELS 8    /* grid channels */
+#define BPMF_MAX_STATES 1024   /* thermodynamic states per ligand */
+#define BPMF_MAX_MBAR_STATES 128
+
+typedef struct bpmf_ctx bpmf_ctx;
+typedef void* (*bpmf_alloc_fn)(size_t bytes, void* user);
+typedef void (*bpmf_free_fn)(void* ptr, void* user);
+
+/* ------------------------------------------------------------------------
+ * Lifecycle
+ * ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.
+ *   seed       key of the counter-based generator (Philox-4x32-10) that
+ *              draws every random number of the run;
+ *   hip_stream hipStream_t to enqueue on (NULL = the null stream);
+ *   alloc/free device allocator for persistent state, or both NULL for
+ *              hipMalloc/hipFree; alloc_user is passed through.
+ * Errors: BPMF_E_INVAL (null out, one of alloc/free missing), BPMF_E_HIP. */
+BPMF_API int bpmf_create(bpmf_ctx** out, int device, uint64_t seed, void* hip_stream,
+                bpmf_alloc_fn alloc, bpmf_free_fn free_fn, void* alloc_user);
+
+/* Synchronise the stream and release every allocation of the context. */
+BPMF_API int bpmf_destroy(bpmf_ctx* ctx);
+
+/* Message of the calling thread's most recent failure ("" if none). */
+BPMF_API const char* bpmf_last_error(void);
+
+/* ABI version of this header (major*100 + minor). */
+BPMF_API int bpmf_version(void);
+
+/* Wait for all work enqueued by the context. */
+BPMF_API int bpmf_sync(bpmf_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Receptor grids
+ *   The paper represents receptor-ligand interactions by one electrostatic
+ *   and two van der Waals grids (Methodology, "Thermodynamic Cycle": grid
+ *   interaction energy Psi_g = Psi_PBSA + Psi_vdW).  Each channel is
+ *   trilinearly interpolated; a channel with transform 4 stores the quartic
+ *   root of its values and is raised to the fourth power after
+ *   interpolation (the repulsive grid's inverse transformation power of 4).
+ *   Outside the grid the value of the nearest boundary point is used (clamp
+ *   to edge), with zero normal gradient.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int nx, ny, nz;      /* nodes per axis, each >= 2 */
+  int n_channels;      /* 1..BPMF_MAX_CHANNELS */
+  double origin[3];    /* position of node (0,0,0) */
+  double spacing;      /* node spacing, > 0 */
+  const int* transform; /* host, n_channels entries: 0 = none, 4 = quartic root */
+} bpmf_grid_desc;
+
+/* Upload the grid: host_nodes is nz*ny*nx*n_channels floats, x fastest,
+ * channel innermost (node (ix,iy,iz) channel c at
+ * ((iz*ny + iy)*nx + ix)*n_channels + c).  Replaces a previous grid (only
+ * allowed before the first ligand is set up).
+ * Errors: BPMF_E_INVAL (bad sizes, non-finite node, negative node on a
+ * transform-4 channel), BPMF_E_STATE (ligands exist), BPMF_E_NOMEM. */
+BPMF_API int bpmf_grid_upload(bpmf_ctx* ctx, const bpmf_grid_desc* desc,
+                     const float* host_nodes);
+
+/* ------------------------------------------------------------------------
+ * Ligands, their force field and their ladder of thermodynamic states
+ *   Intramolecular energy (the U_s(r_L) term of the alchemical protocol,
+ *   GAFF functional forms): bonds K_r (r - r0)^2, angles
+ *   K_theta (theta - theta0)^2, proper torsions (V/2)(1 + cos(n phi - gamma))
+ *   with phi the IUPAC dihedral.  Binding-site restraint (Eq. binding_site):
+ *   U_I = k (d - d0)^2 / 2 for d > d0, where d is the distance of the
+ *   mass-weighted centre from site_center.  State k has temperature T_k and
+ *   grid weights w_kc, so that
+ *       U_k(x) = U_bond + U_angle + U_tors + U_I + sum_c w_kc Psi_c(x),
+ *       Psi_c(x) = sum_i s_ic * interp_c(x_i)   (interp^4 for transform 4),
+ *   and u_k = U_k / (R T_k) with R = 8.314462618e-3 kJ/(mol K)
+ *   (reduced potential, Thermodynamic Cycle).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int n_atoms;                /* 1..BPMF_MAX_ATOMS */
+  const double* mass;         /* host, n_atoms, > 0 (amu) */
+  const double* scale;        /* host, n_atoms x n_channels factors s_ic */
+  int n_bonds;
+  const int* bond_ij;         /* host, n_bonds x 2 atom indices */
+  const double* bond_k_r0;    /* host, n_bonds x 2: K_r, r0 */
+  int n_angles;
+  const int* angle_ijk;       /* host, n_angles x 3, j = vertex */
+  const double* angle_k_t0;   /* host, n_angles x 2: K_theta, theta0 (rad) */
+  int n_tors;
+  const int* tors_ijkl;       /* host, n_tors x 4 */
+  const double* tors_v_n_g;   /* host, n_tors x 3: V/2, n, gamma (rad) */
+  double site_center[3];
+  double d0;                  /* restraint radius (A), >= 0 */
+  double k_restraint;         /* kJ/(mol A^2), >= 0 */
+  int n_states;               /* K = replicas of this ligand, 1..BPMF_MAX_STATES */
+  const double* T;            /* host, K temperatures (K), > 0 */
+  const double* w;            /* host, K x n_channels grid weights */
+  const double* dt_fs;        /* host, K time steps (fs), > 0 */
+  const float* x0;            /* host, K x n_atoms x 3 start of replica r (state r) */
+  int sample_capacity;        /* recorded samples per state (>= 0) */
+} bpmf_ligand_desc;
+
+/* Copy a ligand to the device; replica r starts in state r at x0[r].
+ * Returns its id (0, 1, ...) in *ligand_id.  The grid must exist.
+ * Errors: BPMF_E_INVAL (any index out of range or repeated within a term,
+ * non-positive mass/T/dt, non-finite parameter), BPMF_E_STATE (no grid),
+ * BPMF_E_NOMEM. */
+BPMF_API int bpmf_ligand_setup(bpmf_ctx* ctx, const bpmf_ligand_desc* desc,
+                      int* ligand_id);
+
+/* ------------------------------------------------------------------------
+ * Sampling
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int n_sweeps;        /* >= 0 */
+  int n_leapfrog;      /* velocity-Verlet steps per HMC trial, >= 1 */
+  int exchange_every;  /* 0 = never; else exchange when counter % every == 0 */
+  int exchange_scheme; /* 0 = neighbour pairs, even/odd by counter parity;
+                          1 = all pairs 1..max_sep apart, sequential */
+  int max_sep;         /* scheme 1 only, >= 1 */
+  int sample_every;    /* 0 = never; else record when (counter+1) % every == 0 */
+} bpmf_sweep_args;
+
+/* Run n_sweeps sweeps over every ligand.  One sweep of a ligand with
+ * per-ligand counter s is:
+ *   1. one HMC move per replica (Sampling: velocity-Verlet trial moves):
+ *      momenta v_i ~ N(0, R T_k / m_i * 1e-4) (A/fs), n_leapfrog steps of
+ *      v += dt/2 a; x += dt v; v += dt/2 a with a = F/m * 1e-4, then accept
+ *      iff ln u < -(H1 - H0) / (R T_k), H = U_k + sum m v^2/2 * 1e4,
+ *      H summed in double; non-finite H or x => reject;
+ *   2. if due, one replica-exchange sweep (see bpmf_exchange);
+ *   3. if due, record one sample per state: the configuration and cached
+ *      energy components of the replica currently in that state;
+ *   4. s += 1.
+ * Random numbers: Philox-4x32-10 keyed by the context seed, counter
+ * (index, ligand<<16 | replica, s, purpose) with purpose 1 = momenta
+ * (index = atom), 2 = acceptance (index 0), 3 | sep<<8 = exchange
+ * (index = lower state, replica field 0); uniforms (u32 + 1) 2^-32.
+ * Errors: BPMF_E_INVAL (bad args, sample capacity would overflow),
+ * BPMF_E_STATE (no ligand). */
+BPMF_API int bpmf_hmc_sweep(bpmf_ctx* ctx, const bpmf_sweep_args* args);
+
+/* One replica-exchange sweep of ligand `ligand_id` (-1 = every ligand) at
+ * its current counter s (the counter is not advanced).  Each attempted pair
+ * (a, b) with configuration x in state a and y in state b is accepted with
+ * probability min(1, exp(-[u_a(y) + u_b(x) - u_a(x) - u_b(y)])) (Eq.
+ * repXacc), evaluated in double from the cached components; acceptance swaps
+ * the two state labels.  Scheme 0 attempts (a, a+1) for a = s mod 2, s mod
+ * 2 + 2, ...; scheme 1 attempts every pair 1..max_sep apart, separation
+ * ascending then a ascending, each decision seeing the previous ones
+ * (Sampling: pairs 1..min(5, K) states apart). */
+BPMF_API int bpmf_exchange(bpmf_ctx* ctx, int ligand_id, int scheme, int max_sep);
+
+/* ------------------------------------------------------------------------
+ * Reduced-energy matrix and free energies (Estimation)
+ * ------------------------------------------------------------------------ */
+
+/* u_kn = U_k(x_n) / (R T_k) for every state k of the ligand and every sample
+ * n, in double, written row-major with leading dimension ld >= n_samples to
+ * device buffer dev_ukn (K x ld doubles, caller-owned).  dev_samples is a
+ * device array of n_samples x n_atoms x 3 floats, or NULL to use the samples
+ * recorded so far (n_samples must then equal K x records, round-major).
+ * Energy components are computed once per sample; U_k is affine in them. */
+BPMF_API int bpmf_energy_matrix(bpmf_ctx* ctx, int ligand_id, const float* dev_samples,
+                       int64_t n_samples, double* dev_ukn, int64_t ld);
+
+/* MBAR (Shirts & Chodera 2008, which the paper uses for f_BC,L and f_CD'):
+ * solves f_i = -ln sum_n exp(-u_in) / sum_k N_k exp(f_k - u_kn) with f_0 = 0
+ * by Newton iterations on the convex MBAR objective, in double on the
+ * device.  dev_ukn: K x N (leading dimension ld) device doubles; N_k: host,
+ * K sample counts (all > 0, summing to N).  Outputs (host): f[K], var[K]
+ * with var[k] the asymptotic variance of f_k - f_0 (var[0] = 0; +inf when
+ * the Hessian at the solution is singular, i.e. states without overlap),
+ * *n_iter.  Each iteration is a Newton step with backtracking when the
+ * gauge-fixed Hessian is numerically positive definite, else one step of
+ * the fixed-point equation.  Stops when the largest change of f is below
+ * tol or after max_iter iterations (then *n_iter = max_iter). */
+BPMF_API int bpmf_mbar(bpmf_ctx* ctx, const double* dev_ukn, int K, int64_t N,
+              int64_t ld, const int64_t* N_k, double tol, int max_iter,
+              double* f, double* var, int* n_iter);
+
+/* ------------------------------------------------------------------------
+ * Direct evaluation (the energy/force kernel the sampler runs, exposed)
+ * ------------------------------------------------------------------------ */
+
+/* For n_conf configurations dev_x (device, n_conf x n_atoms x 3 floats) and
+ * per-configuration grid weights dev_w (device, n_conf x n_channels
+ * doubles), write dev_terms (device, n_conf x (4 + n_channels) doubles:
+ * U_bond, U_angle, U_tors, U_I, Psi_0..) and, unless NULL, dev_forces
+ * (device, n_conf x n_atoms x 3 floats) = -grad(U_bond + U_angle + U_tors +
+ * U_I + sum_c w_c Psi_c). */
+BPMF_API int bpmf_evaluate(bpmf_ctx* ctx, int ligand_id, const float* dev_x,
+                  int64_t n_conf, const double* dev_w, double* dev_terms,
+                  float* dev_forces);
+
+/* Grid term alone at n independent points: dev_pos (n x 3 floats),
+ * dev_scale (n x n_channels floats), host w (n_channels doubles).  Writes
+ * dev_energy (n x n_channels floats, e_ic = s_ic interp_c(x_i) after the
+ * transform) and dev_force (n x 3 floats, -sum_c w_c grad e_ic); either
+ * output may be NULL. */
+BPMF_API int bpmf_grid_eval(bpmf_ctx* ctx, const float* dev_pos, const float* dev_scale,
+                   int64_t n, const double* w, float* dev_energy,
+                   float* dev_force);
+
+/* ------------------------------------------------------------------------
+ * Replica state, statistics, samples (checkpoint / resume)
+ * ------------------------------------------------------------------------ */
+
+/* Host copies of a ligand's replica state: x (K x n_atoms x 3 floats),
+ * state_of_replica (K ints), comps (K x (1 + n_channels) doubles: U_bond +
+ * U_angle + U_tors + U_I, then Psi_c), counter (sweeps done).  Any output
+ * may be NULL.  Synchronises. */
+BPMF_API int bpmf_get_replicas(bpmf_ctx* ctx, int ligand_id, float* x,
+                      int* state_of_replica, double* comps, uint64_t* counter);
+
+/* Restore replica state (inverse of bpmf_get_replicas).  state_of_replica
+ * must be a permutation of 0..K-1.  comps may be NULL: then they are
+ * recomputed from x.  Clears nothing else (statistics and recorded samples
+ * are kept; see bpmf_reset_samples). */
+BPMF_API int bpmf_set_replicas(bpmf_ctx* ctx, int ligand_id, const float* x,
+                      const int* state_of_replica, const double* comps,
+                      uint64_t counter);
+
+/* Counters since setup (host outputs, any may be NULL): hmc_acc/hmc_try per
+ * state (K), ex_acc/ex_try per neighbour pair (a, a+1) (K-1), nonfinite =
+ * trial moves rejected for a non-finite Hamiltonian or position. */
+BPMF_API int bpmf_get_stats(bpmf_ctx* ctx, int ligand_id, int64_t* hmc_acc,
+                   int64_t* hmc_try, int64_t* ex_acc, int64_t* ex_try,
+                   int64_t* nonfinite);
+
+/* Recorded samples: *n_records rounds so far; x (records x K x n_atoms x 3
+ * floats) and comps (records x K x (1 + n_channels) doubles), round-major,
+ * state-minor; either may be NULL.  Synchronises. */
+BPMF_API int bpmf_get_samples(bpmf_ctx* ctx, int ligand_id, int64_t* n_records,
+                     float* x, double* comps);
+
+/* Forget recorded samples of a ligand (-1 = all). */
+BPMF_API int bpmf_reset_samples(bpmf_ctx* ctx, int ligand_id);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (HIP events on the context's stream)
+ * ------------------------------------------------------------------------ */
+enum { BPMF_TIMER_HMC = 0, BPMF_TIMER_COMPONENTS = 1, BPMF_TIMER_TAIL = 2 };
+
+/* While enabled, every `every`-th launch of each timed kernel (HMC sweep
+ * kernels of one sweep; per-sample components of energy_matrix; sweep tail)
+ * is bracketed by a pair of HIP events recorded on the context's stream
+ * (at most 8192 pairs per kernel between reads).  Enabling clears earlier
+ * records. */
+BPMF_API int bpmf_set_timing(bpmf_ctx* ctx, int enable, int every);
+
+/* Mean duration in ms of the bracketed launches of `kernel` since timing
+ * was enabled or last read, and their number; clears the records.
+ * Synchronises. */
+BPMF_API int bpmf_get_timing(bpmf_ctx* ctx, int kernel, double* mean_ms,
+                             int64_t* n_timed);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BPMF_H */

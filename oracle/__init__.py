@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH) or \
             os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
         tmp = LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+        cmd = ["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-fPIC", "-shared",
                "-std=c11", "-fno-fast-math", "-ffp-contract=off", src, "-o",
                tmp, "-lm"]
         subprocess.run(cmd, check=True)
@@ -92,6 +92,8 @@ def lib():
                                    C.POINTER(C.c_int64)]
         L.ora_ukn.argtypes = [vp, vp, C.c_int, dp, dp, C.c_int64, dp, dp]
         L.ora_components.argtypes = [vp, vp, C.c_int64, dp, dp, dp]
+        L.ora_grid_points.argtypes = [vp, C.c_int64, dp, dp, dp, dp, dp]
+        L.ora_energy_batch.argtypes = [vp, vp, C.c_int64, dp, dp, dp, dp, dp]
         L.ora_dihedral.argtypes = [dp, dp, dp, dp]
         L.ora_dihedral.restype = C.c_double
         L.ora_angle.argtypes = [dp, dp, dp]
@@ -213,6 +215,34 @@ def energy(og: OGrid, ol: OLigand, w, x, forces=True):
                      _p(terms, C.c_double), _p(mags, C.c_double),
                      _p(F, C.c_double) if forces else None)
     return terms, mags, (F.reshape(ol.n, 3) if forces else None)
+
+
+def grid_points(og, pos, scale, w):
+    """Per-point channel energies (n, C) and forces (n, 3)."""
+    pos = _d(pos).reshape(-1, 3)
+    scale = _d(scale).reshape(len(pos), og.nc)
+    w = _d(w)
+    e = np.zeros((len(pos), og.nc))
+    F = np.zeros((len(pos), 3))
+    lib().ora_grid_points(og.ref, len(pos), _p(pos, C.c_double),
+                          _p(scale, C.c_double), _p(w, C.c_double),
+                          _p(e, C.c_double), _p(F, C.c_double))
+    return e, F
+
+
+def energy_batch(og, ol, xs, w):
+    """terms (N, 4+C), mags (N, 4+C), forces (N, n, 3) for configurations
+    xs (N, n, 3) under per-configuration weights w (N, C)."""
+    xs = _d(xs)
+    N = xs.shape[0]
+    w = _d(np.broadcast_to(w, (N, og.nc)))
+    terms = np.zeros((N, 4 + og.nc))
+    mags = np.zeros((N, 4 + og.nc))
+    F = np.zeros((N, ol.n, 3))
+    lib().ora_energy_batch(og.ref, ol.ref, N, _p(w, C.c_double),
+                           _p(xs, C.c_double), _p(terms, C.c_double),
+                           _p(mags, C.c_double), _p(F, C.c_double))
+    return terms, mags, F
 
 
 def verlet(og, ol, w, dt, nleap, x, v):

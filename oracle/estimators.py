@@ -6,7 +6,8 @@
   equivalently they minimise the convex function
       F(f) = sum_n ln sum_k N_k exp(f_k - u_kn) - sum_i N_i f_i
   under the gauge f_0 = 0.  Solved here by Newton's method with a
-  backtracking line search, all in float64 with log-sum-exp.
+  backtracking line search, falling back to the fixed-point equation while
+  the Hessian is not numerically positive definite; float64, log-sum-exp.
   The asymptotic variance of f_i - f_j is (e_i - e_j)^T H^- (e_i - e_j)
   - 1/N_i - 1/N_j, with H the Hessian of F at the solution and H^- any
   generalised inverse (the gauge-fixed block inverse is used).
@@ -27,13 +28,25 @@ def _objective(f, u_kn, logN):
     return float(np.sum(logsumexp(a, axis=0)) - np.sum(np.exp(logN) * f))
 
 
-def mbar(u_kn, N_k, tol=1e-10, max_iter=200):
+def _self_consistent(f, u_kn, logN):
+    """One step of the MBAR fixed-point equation, gauge f_0 = 0."""
+    logD = logsumexp((logN + f)[:, None] - u_kn, axis=0)
+    fn = -logsumexp(-u_kn - logD[None, :], axis=1)
+    return fn - fn[0]
+
+
+def mbar(u_kn, N_k, tol=1e-10, max_iter=10000):
     """Return (f, var_diff_last, n_iter).
 
     u_kn : (K, N) reduced energies of every sample n in every state k.
     N_k  : (K,) number of samples drawn from each state (all > 0).
     f[0] == 0 (gauge); var_diff_last is the asymptotic variance of
     f[K-1] - f[0].
+
+    Each iteration takes a Newton step (with backtracking on F) when the
+    gauge-fixed Hessian is numerically positive definite, otherwise one
+    step of the fixed-point equation; far from the solution the weights of
+    whole states can underflow and leave the Hessian singular.
     """
     u_kn = np.asarray(u_kn, np.float64)
     N_k = np.asarray(N_k, np.float64)
@@ -49,18 +62,28 @@ def mbar(u_kn, N_k, tol=1e-10, max_iter=200):
         colsum = W.sum(axis=1)                        # sum_n W_ni
         g = N_k * (colsum - 1.0)
         H = np.diag(N_k * colsum) - (N_k[:, None] * N_k[None, :]) * (W @ W.T)
-        step = np.zeros(K)
-        step[1:] = -np.linalg.solve(H[1:, 1:], g[1:])
-        F0 = _objective(f, u_kn, logN)
-        t = 1.0
-        while True:
-            fn = f + t * step
-            if _objective(fn, u_kn, logN) <= F0 + 1e-4 * t * float(g @ step) \
-                    or t < 1e-8:
-                break
-            t *= 0.5
+        Hg = H[1:, 1:]
+        try:
+            Lc = np.linalg.cholesky(Hg)
+            ok = np.min(np.diag(Lc)) ** 2 > 1e-13 * np.max(np.diag(Hg))
+        except np.linalg.LinAlgError:
+            ok = False
+        if ok:
+            step = np.zeros(K)
+            step[1:] = -np.linalg.solve(Hg, g[1:])
+            F0 = _objective(f, u_kn, logN)
+            t = 1.0
+            while True:
+                fn = f + t * step
+                if _objective(fn, u_kn, logN) <= F0 + 1e-4 * t * \
+                        float(g @ step) + 1e-13 * abs(F0) or t < 1e-8:
+                    break
+                t *= 0.5
+        else:
+            fn = _self_consistent(f, u_kn, logN)
+        change = np.max(np.abs(fn - f))
         f = fn
-        if np.max(np.abs(t * step)) < tol:
+        if change < tol:
             break
     # asymptotic variance at the solution
     a = (logN + f)[:, None] - u_kn

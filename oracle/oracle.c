@@ -551,3 +551,34 @@ void ora_set_num_threads(int t) {
   (void)t;
 #endif
 }
+
+/* grid term alone at n points: e (n*nc) = per-channel energies,
+ * F (n*3) = -sum_c w_c grad e_c */
+void ora_grid_points(const ora_grid* g, int64_t n, const double* pos,
+                     const double* scale, const double* w, double* e,
+                     double* F) {
+  const int nc = g->nc;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double ee[ORA_MAXC], de[3 * ORA_MAXC];
+    ora_atom_grid(g, pos + 3 * i, scale + (size_t)i * nc, ee, de);
+    for (int a = 0; a < 3; ++a) F[3 * i + a] = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      e[(size_t)i * nc + c] = ee[c];
+      for (int a = 0; a < 3; ++a) F[3 * i + a] -= w[c] * de[3 * c + a];
+    }
+  }
+}
+
+/* energies and forces of many configurations with per-configuration
+ * weights: terms (N*(4+nc)), mags (N*(4+nc)), F (N*n*3) */
+void ora_energy_batch(const ora_grid* g, const ora_ligand* L, int64_t N,
+                      const double* w, const double* xs, double* terms,
+                      double* mags, double* F) {
+  const int n = L->n, nc = g->nc;
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < N; ++s)
+    ora_energy(g, L, w + (size_t)s * nc, xs + (size_t)s * n * 3,
+               terms + (size_t)s * (4 + nc), mags + (size_t)s * (4 + nc),
+               F + (size_t)s * n * 3);
+}

@@ -1,0 +1,379 @@
+"""ctypes binding of libbpmf (include/bpmf.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbpmf.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bpmf.h")
+
+BPMF_OK = 0
+_ERRORS = {-1: "BPMF_E_INVAL", -2: "BPMF_E_NOMEM", -3: "BPMF_E_HIP",
+           -4: "BPMF_E_STATE", -5: "BPMF_E_UNIMPL"}
+
+
+class BPMFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("n_channels", C.c_int), ("origin", C.c_double * 3),
+                ("spacing", C.c_double), ("transform", C.POINTER(C.c_int))]
+
+
+class _LigandDesc(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("mass", C.POINTER(C.c_double)),
+                ("scale", C.POINTER(C.c_double)),
+                ("n_bonds", C.c_int), ("bond_ij", C.POINTER(C.c_int)),
+                ("bond_k_r0", C.POINTER(C.c_double)),
+                ("n_angles", C.c_int), ("angle_ijk", C.POINTER(C.c_int)),
+                ("angle_k_t0", C.POINTER(C.c_double)),
+                ("n_tors", C.c_int), ("tors_ijkl", C.POINTER(C.c_int)),
+                ("tors_v_n_g", C.POINTER(C.c_double)),
+                ("site_center", C.c_double * 3), ("d0", C.c_double),
+                ("k_restraint", C.c_double), ("n_states", C.c_int),
+                ("T", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
+                ("dt_fs", C.POINTER(C.c_double)),
+                ("x0", C.POINTER(C.c_float)), ("sample_capacity", C.c_int)]
+
+
+class _SweepArgs(C.Structure):
+    _fields_ = [("n_sweeps", C.c_int), ("n_leapfrog", C.c_int),
+                ("exchange_every", C.c_int), ("exchange_scheme", C.c_int),
+                ("max_sep", C.c_int), ("sample_every", C.c_int)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+def exported_names():
+    """Function names declared in include/bpmf.h."""
+    with open(HEADER) as fh:
+        txt = fh.read()
+    return sorted(set(re.findall(r"BPMF_API\s+[\w\s\*]+?\b(bpmf_\w+)\s*\(",
+                                 txt)))
+
+
+EXPORTED = exported_names() if os.path.exists(HEADER) else []
+
+_lib = None
+
+
+def library():
+    """Load libbpmf.so; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, "
+            "gfx950).  There is no fallback implementation.")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, fp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_void_p, \
+        C.POINTER(C.c_int)
+    i64p = C.POINTER(C.c_int64)
+    sig = {
+        "bpmf_create": [C.POINTER(C.c_void_p), C.c_int, C.c_uint64, vp,
+                        ALLOC_FN, FREE_FN, vp],
+        "bpmf_destroy": [vp],
+        "bpmf_sync": [vp],
+        "bpmf_grid_upload": [vp, C.POINTER(_GridDesc), C.POINTER(C.c_float)],
+        "bpmf_ligand_setup": [vp, C.POINTER(_LigandDesc), ip],
+        "bpmf_hmc_sweep": [vp, C.POINTER(_SweepArgs)],
+        "bpmf_exchange": [vp, C.c_int, C.c_int, C.c_int],
+        "bpmf_energy_matrix": [vp, C.c_int, vp, C.c_int64, vp, C.c_int64],
+        "bpmf_mbar": [vp, vp, C.c_int, C.c_int64, C.c_int64, i64p, C.c_double,
+                      C.c_int, dp, dp, ip],
+        "bpmf_evaluate": [vp, C.c_int, vp, C.c_int64, vp, vp, vp],
+        "bpmf_grid_eval": [vp, vp, vp, C.c_int64, dp, vp, vp],
+        "bpmf_get_replicas": [vp, C.c_int, C.POINTER(C.c_float), ip, dp,
+                              C.POINTER(C.c_uint64)],
+        "bpmf_set_replicas": [vp, C.c_int, C.POINTER(C.c_float), ip, dp,
+                              C.c_uint64],
+        "bpmf_get_stats": [vp, C.c_int, i64p, i64p, i64p, i64p, i64p],
+        "bpmf_get_samples": [vp, C.c_int, i64p, C.POINTER(C.c_float), dp],
+        "bpmf_reset_samples": [vp, C.c_int],
+        "bpmf_set_timing": [vp, C.c_int, C.c_int],
+        "bpmf_get_timing": [vp, C.c_int, dp, i64p],
+        "bpmf_version": [],
+        "bpmf_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.bpmf_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != BPMF_OK:
+        msg = library().bpmf_last_error().decode(errors="replace")
+        raise BPMFError(rc, msg)
+
+
+def _pd(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _pi(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def _pf(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Context:
+    """One libbpmf context on a GPU, ordered on a torch stream and allocating
+    through torch's caching allocator."""
+
+    def __init__(self, seed: int, device: int = 0, stream=None,
+                 torch_allocator: bool = True):
+        import torch
+        self._torch = torch
+        self._lib = library()
+        self.device = int(device)
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else \
+            torch.cuda.current_stream(self.device)
+        self._keep = []
+        if torch_allocator:
+            self._alloc = ALLOC_FN(self._alloc_cb)
+            self._free = FREE_FN(self._free_cb)
+        else:
+            self._alloc = ALLOC_FN(0)
+            self._free = FREE_FN(0)
+        h = C.c_void_p()
+        _check(self._lib.bpmf_create(C.byref(h), self.device, int(seed),
+                                     C.c_void_p(self.stream.cuda_stream),
+                                     self._alloc, self._free, None))
+        self._h = h
+        self.n_channels = None
+        self.ligands = []
+
+    # -- allocator callbacks -------------------------------------------------
+    def _alloc_cb(self, size, user):
+        try:
+            return self._torch.cuda.caching_allocator_alloc(
+                int(size), self.device, self.stream)
+        except Exception:  # out of memory -> NULL -> BPMF_E_NOMEM
+            return None
+
+    def _free_cb(self, ptr, user):
+        self._torch.cuda.caching_allocator_delete(ptr)
+
+    # -- lifecycle ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.bpmf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        _check(self._lib.bpmf_sync(self._h))
+
+    # -- grid -----------------------------------------------------------------
+    def grid_upload(self, nodes, origin, spacing, transform):
+        nodes = np.ascontiguousarray(nodes, np.float32)
+        nz, ny, nx, nc = nodes.shape
+        tr = np.ascontiguousarray(transform, np.int32)
+        d = _GridDesc(nx, ny, nz, nc, (C.c_double * 3)(*map(float, origin)),
+                      float(spacing), _pi(tr))
+        _check(self._lib.bpmf_grid_upload(self._h, C.byref(d), _pf(nodes)))
+        self.n_channels = nc
+
+    # -- ligands --------------------------------------------------------------
+    def ligand_setup(self, lig, sample_capacity: int = 0) -> int:
+        """`lig` provides n_atoms, mass, scale, bonds, bond_par, angles,
+        angle_par, tors, tors_par, site_center, d0, k_restraint, T, w, dt, x0
+        (see include/bpmf.h for meaning and layout)."""
+        arrs = dict(
+            mass=np.ascontiguousarray(lig.mass, np.float64),
+            scale=np.ascontiguousarray(lig.scale, np.float64),
+            bij=np.ascontiguousarray(lig.bonds, np.int32).reshape(-1),
+            bpar=np.ascontiguousarray(lig.bond_par, np.float64).reshape(-1),
+            aijk=np.ascontiguousarray(lig.angles, np.int32).reshape(-1),
+            apar=np.ascontiguousarray(lig.angle_par, np.float64).reshape(-1),
+            tijkl=np.ascontiguousarray(lig.tors, np.int32).reshape(-1),
+            tpar=np.ascontiguousarray(lig.tors_par, np.float64).reshape(-1),
+            T=np.ascontiguousarray(lig.T, np.float64),
+            w=np.ascontiguousarray(lig.w, np.float64),
+            dt=np.ascontiguousarray(lig.dt, np.float64),
+            x0=np.ascontiguousarray(lig.x0, np.float32))
+        a = arrs
+        d = _LigandDesc(int(lig.n_atoms), _pd(a["mass"]), _pd(a["scale"]),
+                        len(a["bij"]) // 2, _pi(a["bij"]), _pd(a["bpar"]),
+                        len(a["aijk"]) // 3, _pi(a["aijk"]), _pd(a["apar"]),
+                        len(a["tijkl"]) // 4, _pi(a["tijkl"]), _pd(a["tpar"]),
+                        (C.c_double * 3)(*map(float, lig.site_center)),
+                        float(lig.d0), float(lig.k_restraint), len(a["T"]),
+                        _pd(a["T"]), _pd(a["w"]), _pd(a["dt"]), _pf(a["x0"]),
+                        int(sample_capacity))
+        out = C.c_int(-1)
+        _check(self._lib.bpmf_ligand_setup(self._h, C.byref(d),
+                                           C.byref(out)))
+        self.ligands.append(dict(n=int(lig.n_atoms), K=len(a["T"])))
+        return out.value
+
+    # -- sampling -------------------------------------------------------------
+    def hmc_sweep(self, n_sweeps, n_leapfrog, exchange_every=1,
+                  exchange_scheme=0, max_sep=1, sample_every=0):
+        a = _SweepArgs(int(n_sweeps), int(n_leapfrog), int(exchange_every),
+                       int(exchange_scheme), int(max_sep), int(sample_every))
+        _check(self._lib.bpmf_hmc_sweep(self._h, C.byref(a)))
+
+    def exchange(self, ligand_id=-1, scheme=0, max_sep=1):
+        _check(self._lib.bpmf_exchange(self._h, int(ligand_id), int(scheme),
+                                       int(max_sep)))
+
+    # -- u_kn, MBAR -----------------------------------------------------------
+    def energy_matrix(self, ligand_id, samples=None, n_samples=None, out=None):
+        """u_kn (K x N float64 CUDA tensor) for device samples (N, n, 3)
+        float32, or for the recorded samples when samples is None."""
+        torch = self._torch
+        K = self.ligands[ligand_id]["K"]
+        if samples is not None:
+            assert samples.is_cuda and samples.dtype == torch.float32 and \
+                samples.is_contiguous()
+            N = samples.shape[0]
+            ptr = samples.data_ptr()
+        else:
+            N = int(n_samples)
+            ptr = None
+        if out is None:
+            out = torch.empty((K, N), dtype=torch.float64,
+                              device=f"cuda:{self.device}")
+        assert out.is_cuda and out.dtype == torch.float64 and out.stride(1) == 1
+        _check(self._lib.bpmf_energy_matrix(self._h, int(ligand_id), ptr, N,
+                                            out.data_ptr(), out.stride(0)))
+        return out
+
+    def mbar(self, ukn, N_k, tol=1e-10, max_iter=100):
+        """Returns (f, var, n_iter): f[K] with f[0] = 0, var[k] = asymptotic
+        variance of f_k - f_0."""
+        torch = self._torch
+        assert ukn.is_cuda and ukn.dtype == torch.float64 and ukn.stride(1) == 1
+        K, N = ukn.shape
+        Nk = np.ascontiguousarray(N_k, np.int64)
+        f = np.zeros(K)
+        var = np.zeros(K)
+        it = C.c_int(0)
+        _check(self._lib.bpmf_mbar(self._h, ukn.data_ptr(), K, N,
+                                   ukn.stride(0),
+                                   Nk.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   float(tol), int(max_iter), _pd(f), _pd(var),
+                                   C.byref(it)))
+        return f, var, it.value
+
+    # -- direct evaluation ----------------------------------------------------
+    def evaluate(self, ligand_id, x, w, forces=True):
+        torch = self._torch
+        n = self.ligands[ligand_id]["n"]
+        nc = self.n_channels
+        N = x.shape[0]
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+        assert w.is_cuda and w.dtype == torch.float64 and w.is_contiguous()
+        dev = f"cuda:{self.device}"
+        terms = torch.empty((N, 4 + nc), dtype=torch.float64, device=dev)
+        F = torch.empty((N, n, 3), dtype=torch.float32, device=dev) \
+            if forces else None
+        _check(self._lib.bpmf_evaluate(self._h, int(ligand_id), x.data_ptr(),
+                                       N, w.data_ptr(), terms.data_ptr(),
+                                       F.data_ptr() if forces else None))
+        return terms, F
+
+    def grid_eval(self, pos, scale, w, energy=None, force=None):
+        torch = self._torch
+        nc = self.n_channels
+        N = pos.shape[0]
+        dev = f"cuda:{self.device}"
+        if energy is None:
+            energy = torch.empty((N, nc), dtype=torch.float32, device=dev)
+        if force is None:
+            force = torch.empty((N, 3), dtype=torch.float32, device=dev)
+        wd = np.ascontiguousarray(w, np.float64)
+        _check(self._lib.bpmf_grid_eval(self._h, pos.data_ptr(),
+                                        scale.data_ptr(), N, _pd(wd),
+                                        energy.data_ptr(), force.data_ptr()))
+        return energy, force
+
+    # -- replica state ----------------------------------------------------------
+    def get_replicas(self, ligand_id):
+        L = self.ligands[ligand_id]
+        K, n, nc = L["K"], L["n"], self.n_channels
+        x = np.zeros((K, n, 3), np.float32)
+        sor = np.zeros(K, np.int32)
+        comps = np.zeros((K, 1 + nc))
+        cnt = C.c_uint64(0)
+        _check(self._lib.bpmf_get_replicas(self._h, int(ligand_id), _pf(x),
+                                           _pi(sor), _pd(comps),
+                                           C.byref(cnt)))
+        return dict(x=x, state_of_replica=sor, comps=comps, counter=cnt.value)
+
+    def set_replicas(self, ligand_id, x, state_of_replica, comps=None,
+                     counter=0):
+        x = np.ascontiguousarray(x, np.float32)
+        sor = np.ascontiguousarray(state_of_replica, np.int32)
+        cp = None if comps is None else np.ascontiguousarray(comps, np.float64)
+        _check(self._lib.bpmf_set_replicas(self._h, int(ligand_id), _pf(x),
+                                           _pi(sor),
+                                           _pd(cp) if cp is not None else None,
+                                           int(counter)))
+
+    def get_stats(self, ligand_id):
+        K = self.ligands[ligand_id]["K"]
+        ha = np.zeros(K, np.int64)
+        ht = np.zeros(K, np.int64)
+        ea = np.zeros(max(K - 1, 1), np.int64)
+        et = np.zeros(max(K - 1, 1), np.int64)
+        nf = C.c_int64(0)
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))  # noqa: E731
+        _check(self._lib.bpmf_get_stats(self._h, int(ligand_id), p(ha), p(ht),
+                                        p(ea), p(et), C.byref(nf)))
+        return dict(hmc_acc=ha, hmc_try=ht, ex_acc=ea[:K - 1],
+                    ex_try=et[:K - 1], nonfinite=nf.value)
+
+    def get_samples(self, ligand_id):
+        L = self.ligands[ligand_id]
+        K, n, nc = L["K"], L["n"], self.n_channels
+        nr = C.c_int64(0)
+        _check(self._lib.bpmf_get_samples(self._h, int(ligand_id),
+                                          C.byref(nr), None, None))
+        x = np.zeros((nr.value, K, n, 3), np.float32)
+        comps = np.zeros((nr.value, K, 1 + nc))
+        _check(self._lib.bpmf_get_samples(self._h, int(ligand_id),
+                                          C.byref(nr), _pf(x), _pd(comps)))
+        return x, comps
+
+    TIMER_HMC, TIMER_COMPONENTS, TIMER_TAIL = 0, 1, 2
+
+    def set_timing(self, enable=True, every=1):
+        _check(self._lib.bpmf_set_timing(self._h, int(bool(enable)),
+                                         int(every)))
+
+    def get_timing(self, kernel):
+        """(mean ms per bracketed launch, number of launches timed)."""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        _check(self._lib.bpmf_get_timing(self._h, int(kernel), C.byref(ms),
+                                         C.byref(n)))
+        return ms.value, n.value
+
+    def reset_samples(self, ligand_id=-1):
+        _check(self._lib.bpmf_reset_samples(self._h, int(ligand_id)))

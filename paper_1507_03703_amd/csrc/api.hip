@@ -1,0 +1,1057 @@
+// Host side of libbpmf: argument validation, device-memory layout, kernel
+// sequencing.  Every entry point is declared in include/bpmf.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bpmf.h"
+#include "internal.h"
+
+using namespace bpmf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                      \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail(BPMF_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                     \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves one device allocation into aligned sub-arrays.
+struct Arena {
+  std::vector<size_t> offsets;
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    total = align_up(total, 256);
+    const size_t o = total;
+    offsets.push_back(o);
+    total += bytes > 0 ? bytes : 1;
+    return o;
+  }
+};
+
+struct LigHost {
+  LigDev dev;      // device pointers inside the ligand's arena
+  void* arena;     // owning allocation
+  int apl;         // atoms per lane (1 or 2)
+  int lds_force;   // dynamic LDS of force-evaluating kernels
+  int lds_energy;  // dynamic LDS of energy-only kernels
+  uint64_t counter;   // host mirror of *dev.counter
+  int64_t n_rec;      // host mirror of *dev.n_rec
+  std::vector<double> beta, wd;
+};
+
+}  // namespace
+
+struct bpmf_ctx {
+  int device = 0;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;
+  bpmf_alloc_fn alloc = nullptr;
+  bpmf_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  // grid
+  bool has_grid = false;
+  GridDev grid{};
+  void* grid_mem = nullptr;
+  // ligands
+  std::vector<LigHost> ligs;
+  LigDev* d_ligs = nullptr;  // device copy of every LigDev
+  int2* d_tasks = nullptr;   // [APL-1 tasks | APL-2 tasks]
+  int n_tasks1 = 0, n_tasks2 = 0, lds1 = 0, lds2 = 0;
+  // scratch
+  void* comps_mem = nullptr;
+  size_t comps_bytes = 0;
+  void* mbar_mem = nullptr;
+  size_t mbar_bytes = 0;
+  // kernel timing
+  static constexpr int kTimers = 3;
+  static constexpr size_t kMaxPairs = 8192;
+  bool timing = false;
+  int timing_every = 1;
+  uint64_t launches[kTimers] = {0, 0, 0};
+  std::vector<hipEvent_t> ev_pool[kTimers];  // start/stop pairs
+  size_t ev_used[kTimers] = {0, 0, 0};
+
+  // returns the event pair to bracket this launch of `k`, or false
+  bool timer_begin(int k, hipEvent_t* a, hipEvent_t* b) {
+    if (!timing) return false;
+    const uint64_t idx = launches[k]++;
+    if (idx % (uint64_t)timing_every != 0) return false;
+    if (ev_used[k] >= kMaxPairs) return false;
+    if (ev_used[k] * 2 + 2 > ev_pool[k].size()) {
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess) return false;
+      if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return false;
+      }
+      ev_pool[k].push_back(e0);
+      ev_pool[k].push_back(e1);
+    }
+    *a = ev_pool[k][ev_used[k] * 2];
+    *b = ev_pool[k][ev_used[k] * 2 + 1];
+    ++ev_used[k];
+    return true;
+  }
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    if (alloc) return alloc(bytes, user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    if (free_fn)
+      free_fn(p, user);
+    else
+      (void)hipFree(p);
+  }
+};
+
+namespace {
+
+int check_ctx(bpmf_ctx* c) {
+  if (!c) return fail(BPMF_E_INVAL, "null context");
+  if (hipSetDevice(c->device) != hipSuccess)
+    return fail(BPMF_E_HIP, "hipSetDevice(%d) failed", c->device);
+  return BPMF_OK;
+}
+
+int check_lig(bpmf_ctx* c, int id) {
+  if (id < 0 || id >= (int)c->ligs.size())
+    return fail(BPMF_E_INVAL, "ligand id %d out of range [0, %d)", id,
+                (int)c->ligs.size());
+  return BPMF_OK;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!isfinite(p[i])) return false;
+  return true;
+}
+
+// rebuild the device ligand table and the sweep task lists
+int rebuild_tables(bpmf_ctx* c) {
+  const int nl = (int)c->ligs.size();
+  std::vector<LigDev> table(nl);
+  std::vector<int2> t1, t2;
+  int lds1 = 0, lds2 = 0;
+  for (int l = 0; l < nl; ++l) {
+    table[l] = c->ligs[l].dev;
+    const LigHost& h = c->ligs[l];
+    for (int r = 0; r < h.dev.K; ++r) {
+      if (h.apl == 1)
+        t1.push_back(make_int2(l, r));
+      else
+        t2.push_back(make_int2(l, r));
+    }
+    if (h.apl == 1)
+      lds1 = std::max(lds1, h.lds_force);
+    else
+      lds2 = std::max(lds2, h.lds_force);
+  }
+  void* nd = c->dalloc(sizeof(LigDev) * std::max(nl, 1));
+  void* nt = c->dalloc(sizeof(int2) * std::max<size_t>(t1.size() + t2.size(), 1));
+  if (!nd || !nt) {
+    c->dfree(nd);
+    c->dfree(nt);
+    return fail(BPMF_E_NOMEM, "ligand table allocation failed");
+  }
+  std::vector<int2> all(t1);
+  all.insert(all.end(), t2.begin(), t2.end());
+  HIP_TRY(hipMemcpyAsync(nd, table.data(), sizeof(LigDev) * nl,
+                         hipMemcpyHostToDevice, c->stream));
+  if (!all.empty())
+    HIP_TRY(hipMemcpyAsync(nt, all.data(), sizeof(int2) * all.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->dfree(c->d_ligs);
+  c->dfree(c->d_tasks);
+  c->d_ligs = (LigDev*)nd;
+  c->d_tasks = (int2*)nt;
+  c->n_tasks1 = (int)t1.size();
+  c->n_tasks2 = (int)t2.size();
+  c->lds1 = lds1;
+  c->lds2 = lds2;
+  return BPMF_OK;
+}
+
+int ensure_scratch(bpmf_ctx* c, void** mem, size_t* have, size_t need) {
+  if (*have >= need) return BPMF_OK;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->dfree(*mem);
+  *mem = c->dalloc(need);
+  if (!*mem) {
+    *have = 0;
+    return fail(BPMF_E_NOMEM, "scratch allocation of %zu bytes failed", need);
+  }
+  *have = need;
+  return BPMF_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// lifecycle
+// ============================================================================
+extern "C" int bpmf_version(void) { return 100; }
+
+extern "C" const char* bpmf_last_error(void) { return g_err.c_str(); }
+
+extern "C" int bpmf_create(bpmf_ctx** out, int device, uint64_t seed,
+                           void* hip_stream, bpmf_alloc_fn alloc,
+                           bpmf_free_fn free_fn, void* alloc_user) {
+  if (!out) return fail(BPMF_E_INVAL, "null output pointer");
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(BPMF_E_INVAL, "alloc and free must both be given or both NULL");
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev == 0)
+    return fail(BPMF_E_HIP, "no HIP device available");
+  if (device < 0 || device >= n_dev)
+    return fail(BPMF_E_INVAL, "device %d out of range [0, %d)", device, n_dev);
+  HIP_TRY(hipSetDevice(device));
+  bpmf_ctx* c = new (std::nothrow) bpmf_ctx();
+  if (!c) return fail(BPMF_E_NOMEM, "context allocation failed");
+  c->device = device;
+  c->seed = seed;
+  c->stream = (hipStream_t)hip_stream;
+  c->alloc = alloc;
+  c->free_fn = free_fn;
+  c->user = alloc_user;
+  *out = c;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_destroy(bpmf_ctx* c) {
+  if (!c) return BPMF_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& l : c->ligs) c->dfree(l.arena);
+  c->dfree(c->grid_mem);
+  c->dfree(c->d_ligs);
+  c->dfree(c->d_tasks);
+  c->dfree(c->comps_mem);
+  c->dfree(c->mbar_mem);
+  for (int k = 0; k < bpmf_ctx::kTimers; ++k)
+    for (hipEvent_t e : c->ev_pool[k]) (void)hipEventDestroy(e);
+  delete c;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_sync(bpmf_ctx* c) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return BPMF_OK;
+}
+
+// ============================================================================
+// grid
+// ============================================================================
+extern "C" int bpmf_grid_upload(bpmf_ctx* c, const bpmf_grid_desc* d,
+                                const float* nodes) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!d || !nodes) return fail(BPMF_E_INVAL, "null grid descriptor or nodes");
+  if (!c->ligs.empty())
+    return fail(BPMF_E_STATE, "grid cannot change after ligand setup");
+  if (d->nx < 2 || d->ny < 2 || d->nz < 2)
+    return fail(BPMF_E_INVAL, "grid needs >= 2 nodes per axis (got %d %d %d)",
+                d->nx, d->ny, d->nz);
+  if (d->n_channels < 1 || d->n_channels > BPMF_MAX_CHANNELS)
+    return fail(BPMF_E_INVAL, "n_channels %d outside 1..%d", d->n_channels,
+                BPMF_MAX_CHANNELS);
+  if (!(d->spacing > 0) || !isfinite(d->spacing))
+    return fail(BPMF_E_INVAL, "grid spacing must be positive and finite");
+  if (!finite_all(d->origin, 3))
+    return fail(BPMF_E_INVAL, "grid origin must be finite");
+  if (!d->transform) return fail(BPMF_E_INVAL, "null transform array");
+  const size_t nn = (size_t)d->nx * d->ny * d->nz;
+  if (nn * d->n_channels > (size_t)INT32_MAX)
+    return fail(BPMF_E_INVAL, "grid too large (%zu values)", nn * d->n_channels);
+  int mask = 0;
+  for (int ch = 0; ch < d->n_channels; ++ch) {
+    if (d->transform[ch] == 4)
+      mask |= 1 << ch;
+    else if (d->transform[ch] != 0)
+      return fail(BPMF_E_INVAL, "channel %d: transform %d (0 or 4 allowed)", ch,
+                  d->transform[ch]);
+  }
+  for (size_t i = 0; i < nn * d->n_channels; ++i) {
+    const float v = nodes[i];
+    if (!isfinite(v))
+      return fail(BPMF_E_INVAL, "non-finite grid value at index %zu", i);
+    if (((mask >> (i % d->n_channels)) & 1) && v < 0.f)
+      return fail(BPMF_E_INVAL,
+                  "negative value %g at index %zu of a quartic-root channel", v,
+                  i);
+  }
+  void* mem = c->dalloc(nn * d->n_channels * sizeof(float));
+  if (!mem) return fail(BPMF_E_NOMEM, "grid allocation failed");
+  hipError_t e = hipMemcpyAsync(mem, nodes, nn * d->n_channels * sizeof(float),
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->dfree(mem);
+    return fail(BPMF_E_HIP, "grid upload: %s", hipGetErrorString(e));
+  }
+  c->dfree(c->grid_mem);
+  c->grid_mem = mem;
+  c->grid.nodes = (const float*)mem;
+  c->grid.nx = d->nx;
+  c->grid.ny = d->ny;
+  c->grid.nz = d->nz;
+  c->grid.C = d->n_channels;
+  c->grid.ox = (float)d->origin[0];
+  c->grid.oy = (float)d->origin[1];
+  c->grid.oz = (float)d->origin[2];
+  c->grid.inv_h = (float)(1.0 / d->spacing);
+  c->grid.quartic_mask = mask;
+  c->has_grid = true;
+  return BPMF_OK;
+}
+
+static bool supported_channels(int C) { return C == 3 || C == 5; }
+
+// ============================================================================
+// ligands
+// ============================================================================
+extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
+                                 int* ligand_id) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!d || !ligand_id) return fail(BPMF_E_INVAL, "null descriptor or id");
+  if (!c->has_grid) return fail(BPMF_E_STATE, "upload the grid first");
+  const int C = c->grid.C;
+  if (!supported_channels(C))
+    return fail(BPMF_E_UNIMPL, "this build samples with 3 or 5 channels, not %d",
+                C);
+  const int n = d->n_atoms, K = d->n_states;
+  if (n < 1 || n > BPMF_MAX_ATOMS)
+    return fail(BPMF_E_INVAL, "n_atoms %d outside 1..%d", n, BPMF_MAX_ATOMS);
+  if (K < 1 || K > BPMF_MAX_STATES)
+    return fail(BPMF_E_INVAL, "n_states %d outside 1..%d", K, BPMF_MAX_STATES);
+  if ((int)c->ligs.size() >= 65535)
+    return fail(BPMF_E_INVAL, "too many ligands");
+  if (!d->mass || !d->scale || !d->T || !d->w || !d->dt_fs || !d->x0)
+    return fail(BPMF_E_INVAL, "null per-atom or per-state array");
+  if (d->n_bonds < 0 || d->n_angles < 0 || d->n_tors < 0 ||
+      d->sample_capacity < 0)
+    return fail(BPMF_E_INVAL, "negative count");
+  if ((d->n_bonds && (!d->bond_ij || !d->bond_k_r0)) ||
+      (d->n_angles && (!d->angle_ijk || !d->angle_k_t0)) ||
+      (d->n_tors && (!d->tors_ijkl || !d->tors_v_n_g)))
+    return fail(BPMF_E_INVAL, "null term array with nonzero count");
+  for (int i = 0; i < n; ++i)
+    if (!(d->mass[i] > 0) || !isfinite(d->mass[i]))
+      return fail(BPMF_E_INVAL, "mass[%d] must be positive and finite", i);
+  if (!finite_all(d->scale, (size_t)n * C))
+    return fail(BPMF_E_INVAL, "non-finite scale factor");
+  for (int k = 0; k < K; ++k) {
+    if (!(d->T[k] > 0) || !isfinite(d->T[k]))
+      return fail(BPMF_E_INVAL, "T[%d] must be positive and finite", k);
+    if (!(d->dt_fs[k] > 0) || !isfinite(d->dt_fs[k]))
+      return fail(BPMF_E_INVAL, "dt[%d] must be positive and finite", k);
+  }
+  if (!finite_all(d->w, (size_t)K * C))
+    return fail(BPMF_E_INVAL, "non-finite state weight");
+  if (!finite_all(d->site_center, 3) || !(d->d0 >= 0) || !isfinite(d->d0) ||
+      !(d->k_restraint >= 0) || !isfinite(d->k_restraint))
+    return fail(BPMF_E_INVAL, "bad restraint parameters");
+  for (size_t i = 0; i < (size_t)K * n * 3; ++i)
+    if (!isfinite(d->x0[i]))
+      return fail(BPMF_E_INVAL, "non-finite start coordinate at %zu", i);
+  auto check_idx = [&](const int* idx, int cnt, int ar, const char* what) -> int {
+    for (int t = 0; t < cnt; ++t)
+      for (int a = 0; a < ar; ++a) {
+        const int v = idx[t * ar + a];
+        if (v < 0 || v >= n)
+          return fail(BPMF_E_INVAL, "%s %d: atom index %d out of range", what,
+                      t, v);
+        for (int b = 0; b < a; ++b)
+          if (idx[t * ar + b] == v)
+            return fail(BPMF_E_INVAL, "%s %d: repeated atom %d", what, t, v);
+      }
+    return BPMF_OK;
+  };
+  if ((rc = check_idx(d->bond_ij, d->n_bonds, 2, "bond"))) return rc;
+  if ((rc = check_idx(d->angle_ijk, d->n_angles, 3, "angle"))) return rc;
+  if ((rc = check_idx(d->tors_ijkl, d->n_tors, 4, "torsion"))) return rc;
+  if (!finite_all(d->bond_k_r0, (size_t)d->n_bonds * 2) ||
+      !finite_all(d->angle_k_t0, (size_t)d->n_angles * 2) ||
+      !finite_all(d->tors_v_n_g, (size_t)d->n_tors * 3))
+    return fail(BPMF_E_INVAL, "non-finite force-field parameter");
+
+  const int nb = d->n_bonds, na = d->n_angles, nt = d->n_tors;
+  const int n_slots = 2 * nb + 3 * na + 4 * nt;
+  const int apl = n <= kWave ? 1 : 2;
+  const int cap = d->sample_capacity;
+  const int C1 = 1 + C;
+  const int Km1 = std::max(K - 1, 1);
+
+  // host staging of every device array
+  std::vector<float> mass(n), inv_mass(n), scale((size_t)n * C);
+  double M = 0;
+  for (int i = 0; i < n; ++i) {
+    mass[i] = (float)d->mass[i];
+    inv_mass[i] = (float)(1.0 / d->mass[i]);
+    M += d->mass[i];
+  }
+  for (size_t i = 0; i < (size_t)n * C; ++i) scale[i] = (float)d->scale[i];
+  std::vector<int2> bij(nb);
+  std::vector<float2> bpar(nb);
+  for (int t = 0; t < nb; ++t) {
+    bij[t] = make_int2(d->bond_ij[2 * t], d->bond_ij[2 * t + 1]);
+    bpar[t] = make_float2((float)d->bond_k_r0[2 * t],
+                          (float)d->bond_k_r0[2 * t + 1]);
+  }
+  std::vector<int4> aijk(na);
+  std::vector<float2> apar(na);
+  for (int t = 0; t < na; ++t) {
+    aijk[t] = make_int4(d->angle_ijk[3 * t], d->angle_ijk[3 * t + 1],
+                        d->angle_ijk[3 * t + 2], 0);
+    apar[t] = make_float2((float)d->angle_k_t0[2 * t],
+                          (float)d->angle_k_t0[2 * t + 1]);
+  }
+  std::vector<int4> tijkl(nt);
+  std::vector<float4> tpar(nt);
+  for (int t = 0; t < nt; ++t) {
+    tijkl[t] = make_int4(d->tors_ijkl[4 * t], d->tors_ijkl[4 * t + 1],
+                         d->tors_ijkl[4 * t + 2], d->tors_ijkl[4 * t + 3]);
+    tpar[t] = make_float4((float)d->tors_v_n_g[3 * t],
+                          (float)d->tors_v_n_g[3 * t + 1],
+                          (float)d->tors_v_n_g[3 * t + 2], 0.f);
+  }
+  // force-slot gather lists: slot s belongs to exactly one atom
+  std::vector<std::vector<int>> per(n);
+  for (int t = 0; t < nb; ++t)
+    for (int a = 0; a < 2; ++a) per[d->bond_ij[2 * t + a]].push_back(2 * t + a);
+  for (int t = 0; t < na; ++t)
+    for (int a = 0; a < 3; ++a)
+      per[d->angle_ijk[3 * t + a]].push_back(2 * nb + 3 * t + a);
+  for (int t = 0; t < nt; ++t)
+    for (int a = 0; a < 4; ++a)
+      per[d->tors_ijkl[4 * t + a]].push_back(2 * nb + 3 * na + 4 * t + a);
+  std::vector<int> gstart(n + 1, 0), gidx;
+  gidx.reserve(n_slots);
+  for (int i = 0; i < n; ++i) {
+    gstart[i] = (int)gidx.size();
+    gidx.insert(gidx.end(), per[i].begin(), per[i].end());
+  }
+  gstart[n] = (int)gidx.size();
+  std::vector<double> beta(K), wd((size_t)K * C);
+  std::vector<float> Tf(K), dtf(K), wf((size_t)K * C);
+  for (int k = 0; k < K; ++k) {
+    beta[k] = 1.0 / (kRGas * d->T[k]);
+    Tf[k] = (float)d->T[k];
+    dtf[k] = (float)d->dt_fs[k];
+  }
+  for (size_t i = 0; i < (size_t)K * C; ++i) {
+    wd[i] = d->w[i];
+    wf[i] = (float)d->w[i];
+  }
+  std::vector<int> sor(K), ros(K);
+  for (int k = 0; k < K; ++k) sor[k] = ros[k] = k;
+
+  // one arena per ligand
+  Arena A;
+  const size_t o_mass = A.add(n * 4), o_imass = A.add(n * 4),
+               o_scale = A.add((size_t)n * C * 4), o_bij = A.add(nb * 8),
+               o_bpar = A.add(nb * 8), o_aijk = A.add(na * 16),
+               o_apar = A.add(na * 8), o_tijkl = A.add(nt * 16),
+               o_tpar = A.add(nt * 16), o_gs = A.add((n + 1) * 4),
+               o_gi = A.add(n_slots * 4), o_beta = A.add(K * 8),
+               o_Tf = A.add(K * 4), o_dt = A.add(K * 4),
+               o_wf = A.add((size_t)K * C * 4), o_wd = A.add((size_t)K * C * 8),
+               o_x = A.add((size_t)K * n * 12), o_comps = A.add((size_t)K * C1 * 8),
+               o_sor = A.add(K * 4), o_ros = A.add(K * 4),
+               o_counters = A.add(8 * 3), o_hacc = A.add(K * 8),
+               o_htry = A.add(K * 8), o_eacc = A.add(Km1 * 8),
+               o_etry = A.add(Km1 * 8),
+               o_sx = A.add((size_t)cap * K * n * 12),
+               o_sc = A.add((size_t)cap * K * C1 * 8);
+  char* base = (char*)c->dalloc(A.total);
+  if (!base) return fail(BPMF_E_NOMEM, "ligand allocation of %zu bytes failed",
+                         A.total);
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice,
+                          c->stream);
+  };
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chain(up(o_mass, mass.data(), n * 4));
+  chain(up(o_imass, inv_mass.data(), n * 4));
+  chain(up(o_scale, scale.data(), (size_t)n * C * 4));
+  chain(up(o_bij, bij.data(), nb * 8));
+  chain(up(o_bpar, bpar.data(), nb * 8));
+  chain(up(o_aijk, aijk.data(), na * 16));
+  chain(up(o_apar, apar.data(), na * 8));
+  chain(up(o_tijkl, tijkl.data(), nt * 16));
+  chain(up(o_tpar, tpar.data(), nt * 16));
+  chain(up(o_gs, gstart.data(), (n + 1) * 4));
+  chain(up(o_gi, gidx.data(), n_slots * 4));
+  chain(up(o_beta, beta.data(), K * 8));
+  chain(up(o_Tf, Tf.data(), K * 4));
+  chain(up(o_dt, dtf.data(), K * 4));
+  chain(up(o_wf, wf.data(), (size_t)K * C * 4));
+  chain(up(o_wd, wd.data(), (size_t)K * C * 8));
+  chain(up(o_x, d->x0, (size_t)K * n * 12));
+  chain(up(o_sor, sor.data(), K * 4));
+  chain(up(o_ros, ros.data(), K * 4));
+  chain(hipMemsetAsync(base + o_counters, 0, 8 * 3, c->stream));
+  chain(hipMemsetAsync(base + o_hacc, 0, K * 8, c->stream));
+  chain(hipMemsetAsync(base + o_htry, 0, K * 8, c->stream));
+  chain(hipMemsetAsync(base + o_eacc, 0, Km1 * 8, c->stream));
+  chain(hipMemsetAsync(base + o_etry, 0, Km1 * 8, c->stream));
+  chain(hipStreamSynchronize(c->stream));
+  if (e != hipSuccess) {
+    c->dfree(base);
+    return fail(BPMF_E_HIP, "ligand upload: %s", hipGetErrorString(e));
+  }
+  LigHost h{};
+  LigDev& L = h.dev;
+  L.n = n;
+  L.K = K;
+  L.C = C;
+  L.nb = nb;
+  L.na = na;
+  L.nt = nt;
+  L.n_slots = n_slots;
+  L.id = (int)c->ligs.size();
+  L.cap = cap;
+  for (int a = 0; a < 3; ++a) L.site[a] = (float)d->site_center[a];
+  L.d0 = (float)d->d0;
+  L.krest = (float)d->k_restraint;
+  L.inv_total_mass = (float)(1.0 / M);
+  L.mass = (const float*)(base + o_mass);
+  L.inv_mass = (const float*)(base + o_imass);
+  L.scale = (const float*)(base + o_scale);
+  L.bij = (const int2*)(base + o_bij);
+  L.bpar = (const float2*)(base + o_bpar);
+  L.aijk = (const int4*)(base + o_aijk);
+  L.apar = (const float2*)(base + o_apar);
+  L.tijkl = (const int4*)(base + o_tijkl);
+  L.tpar = (const float4*)(base + o_tpar);
+  L.gstart = (const int*)(base + o_gs);
+  L.gidx = (const int*)(base + o_gi);
+  L.beta = (const double*)(base + o_beta);
+  L.Tf = (const float*)(base + o_Tf);
+  L.dtf = (const float*)(base + o_dt);
+  L.wf = (const float*)(base + o_wf);
+  L.wd = (const double*)(base + o_wd);
+  L.x = (float*)(base + o_x);
+  L.comps = (double*)(base + o_comps);
+  L.state_of_replica = (int*)(base + o_sor);
+  L.replica_of_state = (int*)(base + o_ros);
+  L.counter = (unsigned long long*)(base + o_counters);
+  L.n_rec = L.counter + 1;
+  L.nonfinite = L.counter + 2;
+  L.hmc_acc = (unsigned long long*)(base + o_hacc);
+  L.hmc_try = (unsigned long long*)(base + o_htry);
+  L.ex_acc = (unsigned long long*)(base + o_eacc);
+  L.ex_try = (unsigned long long*)(base + o_etry);
+  L.samp_x = (float*)(base + o_sx);
+  L.samp_c = (double*)(base + o_sc);
+  h.arena = base;
+  h.apl = apl;
+  h.lds_force = (int)(apl * kWave * sizeof(float4) + 3 * sizeof(float) * n_slots);
+  h.lds_energy = (int)(apl * kWave * sizeof(float4));
+  h.counter = 0;
+  h.n_rec = 0;
+  h.beta = beta;
+  h.wd = wd;
+  c->ligs.push_back(h);
+  rc = rebuild_tables(c);
+  if (rc) {
+    c->dfree(base);
+    c->ligs.pop_back();
+    return rc;
+  }
+  // initial cached components
+  const LigDev* dl = c->d_ligs + (c->ligs.size() - 1);
+  HIP_TRY(launch_recompute_comps(c->grid, dl, n, K, h.lds_energy, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *ligand_id = L.id;
+  return BPMF_OK;
+}
+
+// ============================================================================
+// sampling
+// ============================================================================
+extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!a) return fail(BPMF_E_INVAL, "null sweep arguments");
+  if (c->ligs.empty()) return fail(BPMF_E_STATE, "no ligand set up");
+  if (a->n_sweeps < 0 || a->n_leapfrog < 1 || a->exchange_every < 0 ||
+      a->sample_every < 0)
+    return fail(BPMF_E_INVAL, "bad sweep arguments (n_sweeps %d, n_leapfrog %d,"
+                " exchange_every %d, sample_every %d)", a->n_sweeps,
+                a->n_leapfrog, a->exchange_every, a->sample_every);
+  if (a->exchange_scheme != 0 && a->exchange_scheme != 1)
+    return fail(BPMF_E_INVAL, "exchange_scheme must be 0 or 1");
+  if (a->exchange_scheme == 1 && a->max_sep < 1)
+    return fail(BPMF_E_INVAL, "max_sep must be >= 1");
+  // sample capacity check (host mirrors of the device counters)
+  std::vector<int64_t> add(c->ligs.size(), 0);
+  if (a->sample_every > 0) {
+    for (size_t l = 0; l < c->ligs.size(); ++l) {
+      const LigHost& h = c->ligs[l];
+      const int64_t se = a->sample_every;
+      add[l] = (int64_t)((h.counter + a->n_sweeps) / se) -
+               (int64_t)(h.counter / se);
+      if (h.n_rec + add[l] > h.dev.cap)
+        return fail(BPMF_E_INVAL,
+                    "ligand %zu: %lld recorded + %lld new samples per state "
+                    "exceed capacity %d", l, (long long)h.n_rec,
+                    (long long)add[l], h.dev.cap);
+    }
+  }
+  for (int s = 0; s < a->n_sweeps; ++s) {
+    hipEvent_t t0, t1;
+    const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1);
+    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+    if (c->n_tasks1)
+      HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs, c->d_tasks, c->n_tasks1, 1,
+                               c->lds1, a->n_leapfrog, c->seed, c->stream));
+    if (c->n_tasks2)
+      HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs, c->d_tasks + c->n_tasks1,
+                               c->n_tasks2, 2, c->lds2, a->n_leapfrog, c->seed,
+                               c->stream));
+    if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
+    const bool timed_tail = c->timer_begin(BPMF_TIMER_TAIL, &t0, &t1);
+    if (timed_tail) HIP_TRY(hipEventRecord(t0, c->stream));
+    HIP_TRY(launch_sweep_tail(c->d_ligs, (int)c->ligs.size(),
+                              a->exchange_every, a->exchange_scheme,
+                              a->max_sep, a->sample_every, c->seed,
+                              c->stream));
+    if (timed_tail) HIP_TRY(hipEventRecord(t1, c->stream));
+  }
+  for (size_t l = 0; l < c->ligs.size(); ++l) {
+    c->ligs[l].counter += (uint64_t)a->n_sweeps;
+    c->ligs[l].n_rec += add[l];
+  }
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_exchange(bpmf_ctx* c, int ligand_id, int scheme,
+                             int max_sep) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->ligs.empty()) return fail(BPMF_E_STATE, "no ligand set up");
+  if (ligand_id != -1 && (rc = check_lig(c, ligand_id))) return rc;
+  if (scheme != 0 && scheme != 1)
+    return fail(BPMF_E_INVAL, "scheme must be 0 or 1");
+  if (scheme == 1 && max_sep < 1) return fail(BPMF_E_INVAL, "max_sep must be >= 1");
+  if (ligand_id == -1)
+    HIP_TRY(launch_exchange(c->d_ligs, (int)c->ligs.size(), scheme, max_sep,
+                            c->seed, c->stream));
+  else
+    HIP_TRY(launch_exchange(c->d_ligs + ligand_id, 1, scheme, max_sep, c->seed,
+                            c->stream));
+  return BPMF_OK;
+}
+
+// ============================================================================
+// u_kn, MBAR
+// ============================================================================
+extern "C" int bpmf_energy_matrix(bpmf_ctx* c, int ligand_id,
+                                  const float* dev_samples, int64_t n_samples,
+                                  double* dev_ukn, int64_t ld) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  const LigHost& h = c->ligs[ligand_id];
+  if (n_samples < 0) return fail(BPMF_E_INVAL, "negative n_samples");
+  if (!dev_ukn && n_samples > 0) return fail(BPMF_E_INVAL, "null u_kn output");
+  if (ld < n_samples) return fail(BPMF_E_INVAL, "ld %lld < n_samples %lld",
+                                  (long long)ld, (long long)n_samples);
+  const float* xs = dev_samples;
+  if (!xs) {
+    if (n_samples != h.n_rec * h.dev.K)
+      return fail(BPMF_E_INVAL,
+                  "recorded samples: n_samples must be %lld (records x K)",
+                  (long long)(h.n_rec * h.dev.K));
+    xs = h.dev.samp_x;
+  }
+  if (n_samples == 0) return BPMF_OK;
+  const int C = h.dev.C;
+  rc = ensure_scratch(c, &c->comps_mem, &c->comps_bytes,
+                      (size_t)n_samples * (1 + C) * sizeof(double));
+  if (rc) return rc;
+  double* comps = (double*)c->comps_mem;
+  hipEvent_t t0, t1;
+  const bool timed = c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
+  if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+  HIP_TRY(launch_components(c->grid, c->d_ligs + ligand_id, h.dev.n, xs,
+                            n_samples, comps, h.lds_energy, c->stream));
+  if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
+  HIP_TRY(launch_expand(comps, n_samples, h.dev.K, C, h.dev.beta, h.dev.wd,
+                        dev_ukn, ld, c->stream));
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
+                         int64_t ld, const int64_t* N_k, double tol,
+                         int max_iter, double* f, double* var, int* n_iter) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!dev_ukn || !N_k || !f) return fail(BPMF_E_INVAL, "null MBAR argument");
+  if (K < 1 || K > BPMF_MAX_MBAR_STATES)
+    return fail(BPMF_E_INVAL, "MBAR K %d outside 1..%d", K,
+                BPMF_MAX_MBAR_STATES);
+  if (N < 1 || ld < N) return fail(BPMF_E_INVAL, "bad N or ld");
+  if (!(tol > 0) || max_iter < 1)
+    return fail(BPMF_E_INVAL, "tol must be > 0 and max_iter >= 1");
+  int64_t tot = 0;
+  for (int k = 0; k < K; ++k) {
+    if (N_k[k] <= 0) return fail(BPMF_E_INVAL, "N_k[%d] must be > 0", k);
+    tot += N_k[k];
+  }
+  if (tot != N) return fail(BPMF_E_INVAL, "sum N_k = %lld != N = %lld",
+                            (long long)tot, (long long)N);
+  if (K == 1) {
+    f[0] = 0.0;
+    if (var) var[0] = 0.0;
+    if (n_iter) *n_iter = 0;
+    return BPMF_OK;
+  }
+  const int nb = (int)std::min<int64_t>(256, std::max<int64_t>(1, (N + 255) / 256));
+  Arena A;
+  const size_t o_f = A.add(K * 8), o_ft = A.add(K * 8), o_logN = A.add(K * 8),
+               o_Nk = A.add(K * 8), o_logD = A.add((size_t)N * 8),
+               o_part = A.add((size_t)nb * (K + (size_t)K * K) * 8),
+               o_red = A.add((K + (size_t)K * K) * 8),
+               o_mat = A.add((size_t)(K - 1) * (2 * K) * 8),
+               o_step = A.add(K * 8), o_sc = A.add(8 * 8),
+               o_obj = A.add(nb * 8), o_var = A.add(K * 8);
+  rc = ensure_scratch(c, &c->mbar_mem, &c->mbar_bytes, A.total);
+  if (rc) return rc;
+  char* base = (char*)c->mbar_mem;
+  MbarScratch s;
+  double* fcur = (double*)(base + o_f);
+  double* ftry = (double*)(base + o_ft);
+  double* Nk_dev = (double*)(base + o_Nk);
+  s.f = fcur;
+  s.logN = (double*)(base + o_logN);
+  s.logD = (double*)(base + o_logD);
+  s.partial = (double*)(base + o_part);
+  s.red = (double*)(base + o_red);
+  s.mat = (double*)(base + o_mat);
+  s.step = (double*)(base + o_step);
+  s.scalars = (double*)(base + o_sc);
+  s.obj_part = (double*)(base + o_obj);
+  s.n_blocks = nb;
+  double* var_dev = (double*)(base + o_var);
+  std::vector<double> logN(K), Nkd(K);
+  for (int k = 0; k < K; ++k) {
+    Nkd[k] = (double)N_k[k];
+    logN[k] = log(Nkd[k]);
+  }
+  HIP_TRY(hipMemcpyAsync(s.logN, logN.data(), K * 8, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(Nk_dev, Nkd.data(), K * 8, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemsetAsync(fcur, 0, K * 8, c->stream));
+  double sc[4];
+  auto objective = [&](const double* fv, double* out) -> int {
+    HIP_TRY(mbar_logD(dev_ukn, K, N, ld, fv, s, c->stream));
+    HIP_TRY(mbar_objective(K, nullptr, s, fv, Nk_dev, c->stream));
+    HIP_TRY(hipMemcpyAsync(out, s.scalars, 8, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+  };
+  // Each iteration: Newton step with backtracking on the objective when the
+  // gauge-fixed Hessian is numerically positive definite, otherwise one
+  // fixed-point step (far from the solution whole states' weights can
+  // underflow, leaving the Hessian singular).
+  double Fcur = 0;
+  if ((rc = objective(fcur, &Fcur))) return rc;  // also logD at fcur
+  std::vector<double> fh(K), fn(K);
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    HIP_TRY(mbar_accumulate(dev_ukn, K, N, ld, fcur, s, c->stream));
+    HIP_TRY(mbar_newton(K, Nk_dev, s, 0, nullptr, c->stream));
+    HIP_TRY(hipMemcpyAsync(sc, s.scalars, 4 * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double change = 0.0;
+    if (sc[3] == 0.0) {
+      const double maxstep = sc[1], gs = sc[2];
+      double t = 1.0, Ftry = 0.0;
+      for (int ls = 0; ls < 60; ++ls) {
+        HIP_TRY(mbar_axpy(K, fcur, s.step, t, ftry, c->stream));
+        if ((rc = objective(ftry, &Ftry))) return rc;
+        if (Ftry <= Fcur + 1e-4 * t * gs + 1e-13 * fabs(Fcur) ||
+            t * maxstep < tol)
+          break;
+        t *= 0.5;
+      }
+      std::swap(fcur, ftry);
+      s.f = fcur;
+      Fcur = Ftry;
+      change = t * maxstep;
+    } else {
+      // fixed-point step from fcur (logD is current for fcur)
+      HIP_TRY(hipMemcpyAsync(fh.data(), fcur, K * 8, hipMemcpyDeviceToHost,
+                             c->stream));
+      HIP_TRY(mbar_self_consistent(dev_ukn, K, N, ld, s, c->stream));
+      HIP_TRY(hipMemcpyAsync(fn.data(), fcur, K * 8, hipMemcpyDeviceToHost,
+                             c->stream));
+      if ((rc = objective(fcur, &Fcur))) return rc;
+      for (int k = 0; k < K; ++k) change = std::max(change, fabs(fn[k] - fh[k]));
+    }
+    if (!(change >= tol)) break;
+  }
+  if (it > max_iter) it = max_iter;
+  // variance at the solution (logD is current for fcur)
+  HIP_TRY(mbar_logD(dev_ukn, K, N, ld, fcur, s, c->stream));
+  HIP_TRY(mbar_accumulate(dev_ukn, K, N, ld, fcur, s, c->stream));
+  HIP_TRY(mbar_newton(K, Nk_dev, s, 1, var_dev, c->stream));
+  HIP_TRY(hipMemcpyAsync(f, fcur, K * 8, hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> vh(K);
+  HIP_TRY(hipMemcpyAsync(vh.data(), var_dev, K * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(sc, s.scalars, 4 * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  // a Hessian that is not positive definite at the solution means states
+  // without overlap: their differences are not determined
+  if (sc[3] != 0.0)
+    for (int k = 1; k < K; ++k) vh[k] = INFINITY;
+  if (var) memcpy(var, vh.data(), K * 8);
+  if (n_iter) *n_iter = it;
+  return BPMF_OK;
+}
+
+// ============================================================================
+// direct evaluation
+// ============================================================================
+extern "C" int bpmf_evaluate(bpmf_ctx* c, int ligand_id, const float* dev_x,
+                             int64_t n_conf, const double* dev_w,
+                             double* dev_terms, float* dev_forces) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  if (n_conf < 0) return fail(BPMF_E_INVAL, "negative n_conf");
+  if (n_conf == 0) return BPMF_OK;
+  if (!dev_x || !dev_w || !dev_terms)
+    return fail(BPMF_E_INVAL, "null evaluate argument");
+  const LigHost& h = c->ligs[ligand_id];
+  HIP_TRY(launch_evaluate(c->grid, c->d_ligs + ligand_id, h.dev.n, dev_x,
+                          n_conf, dev_w, dev_terms, dev_forces, h.lds_force,
+                          c->stream));
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_grid_eval(bpmf_ctx* c, const float* dev_pos,
+                              const float* dev_scale, int64_t n,
+                              const double* w, float* dev_energy,
+                              float* dev_force) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->has_grid) return fail(BPMF_E_STATE, "upload the grid first");
+  if (!supported_channels(c->grid.C))
+    return fail(BPMF_E_UNIMPL, "grid_eval supports 3 or 5 channels");
+  if (n < 0) return fail(BPMF_E_INVAL, "negative n");
+  if (n == 0) return BPMF_OK;
+  if (!dev_pos || !dev_scale || !w)
+    return fail(BPMF_E_INVAL, "null grid_eval argument");
+  if (!finite_all(w, c->grid.C)) return fail(BPMF_E_INVAL, "non-finite weight");
+  HIP_TRY(launch_grid_eval(c->grid, dev_pos, dev_scale, n, w, dev_energy,
+                           dev_force, c->stream));
+  return BPMF_OK;
+}
+
+// ============================================================================
+// replica state, statistics, samples
+// ============================================================================
+extern "C" int bpmf_get_replicas(bpmf_ctx* c, int ligand_id, float* x,
+                                 int* sor, double* comps, uint64_t* counter) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  const LigDev& L = c->ligs[ligand_id].dev;
+  if (x)
+    HIP_TRY(hipMemcpyAsync(x, L.x, (size_t)L.K * L.n * 12,
+                           hipMemcpyDeviceToHost, c->stream));
+  if (sor)
+    HIP_TRY(hipMemcpyAsync(sor, L.state_of_replica, L.K * 4,
+                           hipMemcpyDeviceToHost, c->stream));
+  if (comps)
+    HIP_TRY(hipMemcpyAsync(comps, L.comps, (size_t)L.K * (1 + L.C) * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+  unsigned long long cnt = 0;
+  HIP_TRY(hipMemcpyAsync(&cnt, L.counter, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (counter) *counter = cnt;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_set_replicas(bpmf_ctx* c, int ligand_id, const float* x,
+                                 const int* sor, const double* comps,
+                                 uint64_t counter) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  LigHost& h = c->ligs[ligand_id];
+  const LigDev& L = h.dev;
+  if (!x || !sor) return fail(BPMF_E_INVAL, "null x or state_of_replica");
+  std::vector<int> ros(L.K, -1);
+  for (int r = 0; r < L.K; ++r) {
+    if (sor[r] < 0 || sor[r] >= L.K || ros[sor[r]] != -1)
+      return fail(BPMF_E_INVAL, "state_of_replica is not a permutation");
+    ros[sor[r]] = r;
+  }
+  HIP_TRY(hipMemcpyAsync(L.x, x, (size_t)L.K * L.n * 12, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(L.state_of_replica, sor, L.K * 4,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(L.replica_of_state, ros.data(), L.K * 4,
+                         hipMemcpyHostToDevice, c->stream));
+  unsigned long long cnt = counter;
+  HIP_TRY(hipMemcpyAsync(L.counter, &cnt, 8, hipMemcpyHostToDevice, c->stream));
+  if (comps)
+    HIP_TRY(hipMemcpyAsync(L.comps, comps, (size_t)L.K * (1 + L.C) * 8,
+                           hipMemcpyHostToDevice, c->stream));
+  else
+    HIP_TRY(launch_recompute_comps(c->grid, c->d_ligs + ligand_id, L.n, L.K,
+                                   h.lds_energy, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  h.counter = counter;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_get_stats(bpmf_ctx* c, int ligand_id, int64_t* hmc_acc,
+                              int64_t* hmc_try, int64_t* ex_acc,
+                              int64_t* ex_try, int64_t* nonfinite) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  const LigDev& L = c->ligs[ligand_id].dev;
+  const int Km1 = std::max(L.K - 1, 1);
+  std::vector<unsigned long long> ex_a(Km1), ex_t(Km1);
+  if (hmc_acc)
+    HIP_TRY(hipMemcpyAsync(hmc_acc, L.hmc_acc, L.K * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  if (hmc_try)
+    HIP_TRY(hipMemcpyAsync(hmc_try, L.hmc_try, L.K * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_TRY(hipMemcpyAsync(ex_a.data(), L.ex_acc, Km1 * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(ex_t.data(), L.ex_try, Km1 * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  unsigned long long nf = 0;
+  HIP_TRY(hipMemcpyAsync(&nf, L.nonfinite, 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int q = 0; q < L.K - 1; ++q) {
+    if (ex_acc) ex_acc[q] = (int64_t)ex_a[q];
+    if (ex_try) ex_try[q] = (int64_t)ex_t[q];
+  }
+  if (nonfinite) *nonfinite = (int64_t)nf;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_get_samples(bpmf_ctx* c, int ligand_id, int64_t* n_records,
+                                float* x, double* comps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  const LigHost& h = c->ligs[ligand_id];
+  const LigDev& L = h.dev;
+  unsigned long long nr = 0;
+  HIP_TRY(hipMemcpyAsync(&nr, L.n_rec, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (x && nr)
+    HIP_TRY(hipMemcpyAsync(x, L.samp_x, (size_t)nr * L.K * L.n * 12,
+                           hipMemcpyDeviceToHost, c->stream));
+  if (comps && nr)
+    HIP_TRY(hipMemcpyAsync(comps, L.samp_c, (size_t)nr * L.K * (1 + L.C) * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (n_records) *n_records = (int64_t)nr;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_reset_samples(bpmf_ctx* c, int ligand_id) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (ligand_id != -1 && (rc = check_lig(c, ligand_id))) return rc;
+  for (size_t l = 0; l < c->ligs.size(); ++l) {
+    if (ligand_id != -1 && (int)l != ligand_id) continue;
+    HIP_TRY(hipMemsetAsync(c->ligs[l].dev.n_rec, 0, 8, c->stream));
+    c->ligs[l].n_rec = 0;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return BPMF_OK;
+}
+
+// ============================================================================
+// kernel timing
+// ============================================================================
+extern "C" int bpmf_set_timing(bpmf_ctx* c, int enable, int every) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (every < 1) return fail(BPMF_E_INVAL, "every must be >= 1");
+  c->timing = enable != 0;
+  c->timing_every = every;
+  for (int k = 0; k < bpmf_ctx::kTimers; ++k) {
+    c->launches[k] = 0;
+    c->ev_used[k] = 0;
+  }
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_get_timing(bpmf_ctx* c, int kernel, double* mean_ms,
+                               int64_t* n_timed) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (kernel < 0 || kernel >= bpmf_ctx::kTimers)
+    return fail(BPMF_E_INVAL, "unknown timer %d", kernel);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  const size_t n = c->ev_used[kernel];
+  for (size_t i = 0; i < n; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[kernel][2 * i],
+                                c->ev_pool[kernel][2 * i + 1]));
+    tot += ms;
+  }
+  if (mean_ms) *mean_ms = n ? tot / (double)n : 0.0;
+  if (n_timed) *n_timed = (int64_t)n;
+  c->ev_used[kernel] = 0;
+  c->launches[kernel] = 0;
+  return BPMF_OK;
+}

@@ -1,0 +1,120 @@
+// Structures shared by the host side of libbpmf and its gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bpmf {
+
+constexpr int kWave = 64;
+constexpr double kRGas = 8.314462618e-3;  // kJ/(mol K)
+#define BPMF_MAX_MBAR_STATES_DEV 128
+
+enum Purpose : uint32_t { kMomenta = 1, kAccept = 2, kExchange = 3 };
+
+// Receptor grid as the kernels see it.  Node (ix,iy,iz) channel c is at
+// nodes[((iz*ny + iy)*nx + ix)*C + c]; channel c holds a quartic root when
+// bit c of quartic_mask is set.
+struct GridDev {
+  const float* nodes;
+  int nx, ny, nz, C;
+  float ox, oy, oz, inv_h;
+  int quartic_mask;
+};
+
+// One ligand: force field, state ladder, replica state, statistics and the
+// sample store, all resident in device memory.  Replica r of a ligand with
+// K states owns x[r*n*3 .. (r+1)*n*3).
+struct LigDev {
+  int n, K, C;
+  int nb, na, nt, n_slots;
+  int id;     // ligand id (enters the random-number counter)
+  int cap;    // recorded samples per state
+  float site[3];
+  float d0, krest, inv_total_mass;
+  const float* mass;      // n
+  const float* inv_mass;  // n
+  const float* scale;     // n*C
+  const int2* bij;        // nb
+  const float2* bpar;     // nb: K_r, r0
+  const int4* aijk;       // na: i, j(vertex), k, -
+  const float2* apar;     // na: K_theta, theta0
+  const int4* tijkl;      // nt
+  const float4* tpar;     // nt: V/2, n, gamma, -
+  const int* gstart;      // n+1 CSR offsets into gidx
+  const int* gidx;        // n_slots force-slot indices, ascending per atom
+  const double* beta;     // K: 1/(R T_k)
+  const float* Tf;        // K
+  const float* dtf;       // K
+  const float* wf;        // K*C
+  const double* wd;       // K*C
+  float* x;               // K*n*3
+  double* comps;          // K*(1+C)
+  int* state_of_replica;  // K
+  int* replica_of_state;  // K
+  unsigned long long* counter;    // sweeps done
+  unsigned long long* n_rec;      // recorded rounds
+  unsigned long long* hmc_acc;    // K
+  unsigned long long* hmc_try;    // K
+  unsigned long long* ex_acc;     // max(K-1,1)
+  unsigned long long* ex_try;     // max(K-1,1)
+  unsigned long long* nonfinite;  // 1
+  float* samp_x;                  // cap*K*n*3
+  double* samp_c;                 // cap*K*(1+C)
+};
+
+// Launch wrappers (kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
+                            const int2* d_tasks, int n_tasks, int apl,
+                            int lds_bytes, int nleap, uint64_t seed,
+                            hipStream_t st);
+hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
+                             int exchange_every, int scheme, int max_sep,
+                             int sample_every, uint64_t seed, hipStream_t st);
+hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
+                           int max_sep, uint64_t seed, hipStream_t st);
+hipError_t launch_components(const GridDev& g, const LigDev* d_lig,
+                             int n_atoms, const float* xs, int64_t N,
+                             double* comps, int lds_bytes, hipStream_t st);
+hipError_t launch_expand(const double* comps, int64_t N, int K, int C,
+                         const double* beta, const double* wd, double* ukn,
+                         int64_t ld, hipStream_t st);
+hipError_t launch_evaluate(const GridDev& g, const LigDev* d_lig,
+                           int n_atoms, const float* xs, int64_t N,
+                           const double* w, double* terms, float* forces,
+                           int lds_bytes, hipStream_t st);
+hipError_t launch_grid_eval(const GridDev& g, const float* pos,
+                            const float* scale, int64_t n, const double* w,
+                            float* energy, float* force, hipStream_t st);
+hipError_t launch_recompute_comps(const GridDev& g, const LigDev* d_lig,
+                                  int n_atoms, int K, int lds_bytes,
+                                  hipStream_t st);
+
+// MBAR kernels (mbar.hip)
+struct MbarScratch {
+  double* f;         // K
+  double* logN;      // K
+  double* logD;      // N
+  double* partial;   // n_blocks * (K + K*(K+1)/2)
+  double* red;       // K + K*(K+1)/2 (reduced sums)
+  double* mat;       // (K-1) x (2K-1) augmented system
+  double* step;      // K
+  double* scalars;   // [0] objective, [1] max|step|, [2] g.step, [3] status
+  double* obj_part;  // n_blocks
+  int n_blocks;
+};
+hipError_t mbar_logD(const double* ukn, int K, int64_t N, int64_t ld,
+                     const double* f, const MbarScratch& s, hipStream_t st);
+hipError_t mbar_objective(int K, const int64_t* dummy, const MbarScratch& s,
+                          const double* f, double* N_k_dev, hipStream_t st);
+hipError_t mbar_self_consistent(const double* ukn, int K, int64_t N,
+                                int64_t ld, const MbarScratch& s,
+                                hipStream_t st);
+hipError_t mbar_accumulate(const double* ukn, int K, int64_t N, int64_t ld,
+                           const double* f, const MbarScratch& s,
+                           hipStream_t st);
+hipError_t mbar_newton(int K, const double* N_k_dev, const MbarScratch& s,
+                       int want_inverse, double* var_out, hipStream_t st);
+hipError_t mbar_axpy(int K, const double* f, const double* step, double t,
+                     double* out, hipStream_t st);
+
+}  // namespace bpmf

@@ -1,0 +1,533 @@
+// gfx950 kernels of the BPMF sampling hot path: HMC sweep, replica exchange,
+// sample recording, per-sample energy components, u_kn expansion, and the
+// exposed energy/force and grid evaluators.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace bpmf {
+
+namespace {
+
+__device__ __forceinline__ Slots make_slots(float4* smem, int apl,
+                                            int n_slots) {
+  float* base = reinterpret_cast<float*>(smem + apl * kWave);
+  return Slots{base, base + n_slots, base + 2 * n_slots};
+}
+
+// ----------------------------------------------------------------------------
+// HMC: one trial move per replica, one wavefront per replica.
+// (Sampling: HMC trial moves from velocity-Verlet molecular dynamics.)
+// ----------------------------------------------------------------------------
+template <int C, int APL>
+__global__ __launch_bounds__(kWave) void k_hmc_sweep(
+    GridDev g, const LigDev* __restrict__ ligs, const int2* __restrict__ tasks,
+    int nleap, uint64_t seed) {
+  extern __shared__ float4 smem[];
+  const int lane = threadIdx.x;
+  const int2 task = tasks[blockIdx.x];
+  const LigDev& L = ligs[task.x];
+  const int r = task.y;
+  const int n = L.n;
+  float4* spos = smem;
+  const Slots sl = make_slots(smem, APL, L.n_slots);
+
+  const unsigned long long s = *L.counter;
+  const int k = L.state_of_replica[r];
+  float w[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) w[c] = L.wf[k * C + c];
+  const float T = L.Tf[k];
+  const float dt = L.dtf[k];
+  const double beta = L.beta[k];
+
+  float x[APL][3], v[APL][3], f[APL][3], m[APL], im[APL];
+  const float* xr = L.x + (size_t)r * n * 3;
+#pragma unroll
+  for (int a = 0; a < APL; ++a) {
+    const int atom = lane + kWave * a;
+    const bool valid = atom < n;
+    m[a] = valid ? L.mass[atom] : 0.f;
+    im[a] = valid ? L.inv_mass[atom] : 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[a][d] = valid ? xr[atom * 3 + d] : 0.f;
+    if (valid) {
+      const U4 o = draw(seed, (uint32_t)atom, L.id, r, s, kMomenta);
+      float z0, z1, z2;
+      normals3(o, z0, z1, z2);
+      const float sd = sqrtf((float)kRGas * T * im[a] * 1e-4f);
+      v[a][0] = sd * z0;
+      v[a][1] = sd * z1;
+      v[a][2] = sd * z2;
+    } else {
+      v[a][0] = v[a][1] = v[a][2] = 0.f;
+    }
+  }
+
+  double t0[4 + C], t1[4 + C];
+  eval_conf<C, APL, true, true>(g, L, w, x, m, f, t0, spos, sl, lane);
+  double U0 = t0[0] + t0[1] + t0[2] + t0[3];
+#pragma unroll
+  for (int c = 0; c < C; ++c) U0 += L.wd[k * C + c] * t0[4 + c];
+  float ke = 0.f;
+#pragma unroll
+  for (int a = 0; a < APL; ++a)
+    ke += 0.5f * m[a] * (v[a][0] * v[a][0] + v[a][1] * v[a][1] +
+                         v[a][2] * v[a][2]);
+  const double KE0 = wave_sum((double)ke) * 1e4;
+
+  const float hk = 0.5f * dt * 1e-4f;
+  for (int step = 0; step < nleap; ++step) {
+#pragma unroll
+    for (int a = 0; a < APL; ++a)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        v[a][d] = fmaf(hk * im[a], f[a][d], v[a][d]);
+        x[a][d] = fmaf(dt, v[a][d], x[a][d]);
+      }
+    if (step == nleap - 1)
+      eval_conf<C, APL, true, true>(g, L, w, x, m, f, t1, spos, sl, lane);
+    else
+      eval_conf<C, APL, true, false>(g, L, w, x, m, f, t1, spos, sl, lane);
+#pragma unroll
+    for (int a = 0; a < APL; ++a)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[a][d] = fmaf(hk * im[a], f[a][d], v[a][d]);
+  }
+  double U1 = t1[0] + t1[1] + t1[2] + t1[3];
+#pragma unroll
+  for (int c = 0; c < C; ++c) U1 += L.wd[k * C + c] * t1[4 + c];
+  ke = 0.f;
+  int bad = 0;
+#pragma unroll
+  for (int a = 0; a < APL; ++a) {
+    ke += 0.5f * m[a] * (v[a][0] * v[a][0] + v[a][1] * v[a][1] +
+                         v[a][2] * v[a][2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) bad |= !isfinite(x[a][d]);
+  }
+  const double KE1 = wave_sum((double)ke) * 1e4;
+  const bool any_bad = __any(bad);
+  const double dH = (U1 + KE1) - (U0 + KE0);
+  const U4 o = draw(seed, 0u, L.id, r, s, kAccept);
+  const double lnu = log(u01d(o.x));
+  const bool finite = isfinite(dH) && !any_bad;
+  const bool accept = finite && (lnu < -beta * dH);
+  if (accept) {
+    float* xw = L.x + (size_t)r * n * 3;
+#pragma unroll
+    for (int a = 0; a < APL; ++a) {
+      const int atom = lane + kWave * a;
+      if (atom < n)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xw[atom * 3 + d] = x[a][d];
+    }
+    if (lane == 0) {
+      double* cr = L.comps + (size_t)r * (1 + C);
+      cr[0] = t1[0] + t1[1] + t1[2] + t1[3];
+#pragma unroll
+      for (int c = 0; c < C; ++c) cr[1 + c] = t1[4 + c];
+    }
+  }
+  if (lane == 0) {
+    atomicAdd(&L.hmc_try[k], 1ull);
+    if (accept) atomicAdd(&L.hmc_acc[k], 1ull);
+    if (!finite) atomicAdd(L.nonfinite, 1ull);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// replica exchange (Eq. repXacc), state labels swapped
+// ----------------------------------------------------------------------------
+#pragma clang fp contract(off)
+__device__ double state_energy(const LigDev& L, int k, int rep) {
+  const double* cp = L.comps + (size_t)rep * (1 + L.C);
+  double E = cp[0];
+  for (int c = 0; c < L.C; ++c) E += L.wd[k * L.C + c] * cp[1 + c];
+  return E;
+}
+
+__device__ bool attempt_pair(const LigDev& L, int a, int b, int sep,
+                             uint64_t sweep, uint64_t seed) {
+  const int ra = L.replica_of_state[a], rb = L.replica_of_state[b];
+  const double ba = L.beta[a], bb = L.beta[b];
+  const double delta =
+      ba * (state_energy(L, a, rb) - state_energy(L, a, ra)) +
+      bb * (state_energy(L, b, ra) - state_energy(L, b, rb));
+  const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)sep << 8);
+  const U4 o = draw(seed, (uint32_t)a, L.id, 0, sweep, purpose);
+  const double lnu = log(u01d(o.x));
+  const bool ok = isfinite(delta) && (lnu < -delta);
+  if (sep == 1) atomicAdd(&L.ex_try[a], 1ull);
+  if (ok) {
+    L.replica_of_state[a] = rb;
+    L.replica_of_state[b] = ra;
+    L.state_of_replica[ra] = b;
+    L.state_of_replica[rb] = a;
+    if (sep == 1) atomicAdd(&L.ex_acc[a], 1ull);
+  }
+  return ok;
+}
+#pragma clang fp contract(fast)
+
+// block-wide exchange sweep for one ligand (called by all threads)
+__device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
+                               int max_sep, uint64_t seed) {
+  const int K = L.K;
+  if (K < 2) return;
+  if (scheme == 0) {
+    // disjoint neighbour pairs: independent, one thread each
+    const int a0 = (int)(sweep & 1ull);
+    for (int a = a0 + 2 * (int)threadIdx.x; a + 1 < K; a += 2 * blockDim.x)
+      attempt_pair(L, a, a + 1, 1, sweep, seed);
+  } else if (threadIdx.x == 0) {
+    const int dmax = max_sep < K - 1 ? max_sep : K - 1;
+    for (int d = 1; d <= dmax; ++d)
+      for (int a = 0; a + d < K; ++a) attempt_pair(L, a, a + d, d, sweep, seed);
+  }
+}
+
+// One block per ligand: exchange (if due), record (if due), counter += 1.
+__global__ __launch_bounds__(256) void k_sweep_tail(
+    const LigDev* __restrict__ ligs, int exchange_every, int scheme,
+    int max_sep, int sample_every, uint64_t seed) {
+  const LigDev& L = ligs[blockIdx.x];
+  const unsigned long long s = *L.counter;
+  if (exchange_every > 0 && s % (unsigned long long)exchange_every == 0ull)
+    exchange_block(L, s, scheme, max_sep, seed);
+  __syncthreads();
+  const unsigned long long rec = *L.n_rec;
+  const bool record = sample_every > 0 &&
+                      (s + 1ull) % (unsigned long long)sample_every == 0ull &&
+                      rec < (unsigned long long)L.cap;
+  if (record) {
+    const int n3 = L.n * 3, C1 = 1 + L.C;
+    float* dx = L.samp_x + (size_t)rec * L.K * n3;
+    double* dc = L.samp_c + (size_t)rec * L.K * C1;
+    for (int q = threadIdx.x; q < L.K * n3; q += blockDim.x) {
+      const int k = q / n3, e = q - k * n3;
+      dx[q] = L.x[(size_t)L.replica_of_state[k] * n3 + e];
+    }
+    for (int q = threadIdx.x; q < L.K * C1; q += blockDim.x) {
+      const int k = q / C1, e = q - k * C1;
+      dc[q] = L.comps[(size_t)L.replica_of_state[k] * C1 + e];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *L.counter = s + 1ull;
+    if (record) *L.n_rec = rec + 1ull;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_exchange(
+    const LigDev* __restrict__ ligs, int scheme, int max_sep, uint64_t seed) {
+  const LigDev& L = ligs[blockIdx.x];
+  exchange_block(L, *L.counter, scheme, max_sep, seed);
+}
+
+// ----------------------------------------------------------------------------
+// per-sample components [U_bonded + U_I, Psi_c] (energy only)
+// ----------------------------------------------------------------------------
+template <int C, int APL>
+__global__ __launch_bounds__(kWave) void k_components(
+    GridDev g, const LigDev* __restrict__ lig, const float* __restrict__ xs,
+    int64_t N, double* __restrict__ comps) {
+  extern __shared__ float4 smem[];
+  const LigDev& L = *lig;
+  const int lane = threadIdx.x;
+  const int n = L.n;
+  const Slots sl = make_slots(smem, APL, 0);
+  float m[APL];
+#pragma unroll
+  for (int a = 0; a < APL; ++a) {
+    const int atom = lane + kWave * a;
+    m[a] = atom < n ? L.mass[atom] : 0.f;
+  }
+  const float w0[C > 0 ? C : 1] = {};
+  for (int64_t smp = blockIdx.x; smp < N; smp += gridDim.x) {
+    float x[APL][3], f[APL][3];
+    const float* xr = xs + (size_t)smp * n * 3;
+#pragma unroll
+    for (int a = 0; a < APL; ++a) {
+      const int atom = lane + kWave * a;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[a][d] = atom < n ? xr[atom * 3 + d] : 0.f;
+    }
+    double t[4 + C];
+    eval_conf<C, APL, false, true>(g, L, w0, x, m, f, t, smem, sl, lane);
+    if (lane == 0) {
+      double* cp = comps + (size_t)smp * (1 + C);
+      cp[0] = t[0] + t[1] + t[2] + t[3];
+#pragma unroll
+      for (int c = 0; c < C; ++c) cp[1 + c] = t[4 + c];
+    }
+  }
+}
+
+// u_kn = beta_k (E0_n + sum_c w_kc Psi_cn), row-major with leading dim ld
+__global__ __launch_bounds__(256) void k_expand(
+    const double* __restrict__ comps, int64_t N, int K, int C,
+    const double* __restrict__ beta, const double* __restrict__ wd,
+    double* __restrict__ ukn, int64_t ld) {
+  const int k = blockIdx.y;
+  const double bk = beta[k];
+  for (int64_t nn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; nn < N;
+       nn += (int64_t)gridDim.x * blockDim.x) {
+    const double* cp = comps + (size_t)nn * (1 + C);
+    double E = cp[0];
+    for (int c = 0; c < C; ++c) E += wd[k * C + c] * cp[1 + c];
+    ukn[(size_t)k * ld + nn] = bk * E;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// exposed evaluator: terms and forces for arbitrary configurations/weights
+// ----------------------------------------------------------------------------
+template <int C, int APL>
+__global__ __launch_bounds__(kWave) void k_evaluate(
+    GridDev g, const LigDev* __restrict__ lig, const float* __restrict__ xs,
+    int64_t N, const double* __restrict__ wconf, double* __restrict__ terms,
+    float* __restrict__ forces) {
+  extern __shared__ float4 smem[];
+  const LigDev& L = *lig;
+  const int lane = threadIdx.x;
+  const int n = L.n;
+  const Slots sl = make_slots(smem, APL, L.n_slots);
+  float m[APL];
+#pragma unroll
+  for (int a = 0; a < APL; ++a) {
+    const int atom = lane + kWave * a;
+    m[a] = atom < n ? L.mass[atom] : 0.f;
+  }
+  for (int64_t cf = blockIdx.x; cf < N; cf += gridDim.x) {
+    float w[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) w[c] = (float)wconf[cf * C + c];
+    float x[APL][3], f[APL][3];
+    const float* xr = xs + (size_t)cf * n * 3;
+#pragma unroll
+    for (int a = 0; a < APL; ++a) {
+      const int atom = lane + kWave * a;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[a][d] = atom < n ? xr[atom * 3 + d] : 0.f;
+    }
+    double t[4 + C];
+    eval_conf<C, APL, true, true>(g, L, w, x, m, f, t, smem, sl, lane);
+    if (lane == 0)
+      for (int q = 0; q < 4 + C; ++q) terms[(size_t)cf * (4 + C) + q] = t[q];
+    if (forces) {
+      float* fo = forces + (size_t)cf * n * 3;
+#pragma unroll
+      for (int a = 0; a < APL; ++a) {
+        const int atom = lane + kWave * a;
+        if (atom < n)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) fo[atom * 3 + d] = f[a][d];
+      }
+    }
+  }
+}
+
+// recompute cached components of every replica from its positions
+template <int C, int APL>
+__global__ __launch_bounds__(kWave) void k_recompute(
+    GridDev g, const LigDev* __restrict__ lig) {
+  extern __shared__ float4 smem[];
+  const LigDev& L = *lig;
+  const int lane = threadIdx.x;
+  const int n = L.n;
+  const Slots sl = make_slots(smem, APL, 0);
+  const int r = blockIdx.x;
+  float m[APL], x[APL][3], f[APL][3];
+  const float w0[C] = {};
+#pragma unroll
+  for (int a = 0; a < APL; ++a) {
+    const int atom = lane + kWave * a;
+    m[a] = atom < n ? L.mass[atom] : 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      x[a][d] = atom < n ? L.x[((size_t)r * n + atom) * 3 + d] : 0.f;
+  }
+  double t[4 + C];
+  eval_conf<C, APL, false, true>(g, L, w0, x, m, f, t, smem, sl, lane);
+  if (lane == 0) {
+    double* cp = L.comps + (size_t)r * (1 + C);
+    cp[0] = t[0] + t[1] + t[2] + t[3];
+#pragma unroll
+    for (int c = 0; c < C; ++c) cp[1 + c] = t[4 + c];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// grid term alone, one thread per point
+// ----------------------------------------------------------------------------
+template <int C>
+struct WeightsC {
+  float w[C];
+};
+
+template <int C>
+__global__ __launch_bounds__(256) void k_grid_eval(
+    GridDev g, const float* __restrict__ pos, const float* __restrict__ scale,
+    int64_t n, WeightsC<C> wc, float* __restrict__ energy,
+    float* __restrict__ force) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    Corners<C> cn;
+    grid_fetch<C>(g, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], cn);
+    float s[C], e[C], de[C][3];
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] = scale[i * C + c];
+    grid_finish<C, true>(g, cn, s, e, de);
+    if (energy)
+#pragma unroll
+      for (int c = 0; c < C; ++c) energy[i * C + c] = e[c];
+    if (force) {
+      float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        fx -= wc.w[c] * de[c][0];
+        fy -= wc.w[c] * de[c][1];
+        fz -= wc.w[c] * de[c][2];
+      }
+      force[3 * i] = fx;
+      force[3 * i + 1] = fy;
+      force[3 * i + 2] = fz;
+    }
+  }
+}
+
+int grid_blocks(int64_t work, int per_block, int cap) {
+  int64_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+#define BPMF_DISPATCH_C(C_, ...)                                   \
+  switch (C_) {                                                    \
+    case 3: {                                                      \
+      constexpr int C = 3;                                         \
+      __VA_ARGS__;                                                 \
+    } break;                                                       \
+    case 5: {                                                      \
+      constexpr int C = 5;                                         \
+      __VA_ARGS__;                                                 \
+    } break;                                                       \
+    default:                                                       \
+      return hipErrorInvalidValue;                                 \
+  }
+
+hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
+                            const int2* d_tasks, int n_tasks, int apl,
+                            int lds_bytes, int nleap, uint64_t seed,
+                            hipStream_t st) {
+  if (n_tasks <= 0) return hipSuccess;
+  BPMF_DISPATCH_C(g.C, {
+    if (apl == 1)
+      hipLaunchKernelGGL((k_hmc_sweep<C, 1>), dim3(n_tasks), dim3(kWave),
+                         lds_bytes, st, g, d_ligs, d_tasks, nleap, seed);
+    else
+      hipLaunchKernelGGL((k_hmc_sweep<C, 2>), dim3(n_tasks), dim3(kWave),
+                         lds_bytes, st, g, d_ligs, d_tasks, nleap, seed);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
+                             int exchange_every, int scheme, int max_sep,
+                             int sample_every, uint64_t seed, hipStream_t st) {
+  if (n_ligs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep_tail, dim3(n_ligs), dim3(256), 0, st, d_ligs,
+                     exchange_every, scheme, max_sep, sample_every, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
+                           int max_sep, uint64_t seed, hipStream_t st) {
+  if (n_ligs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exchange, dim3(n_ligs), dim3(256), 0, st, d_lig,
+                     scheme, max_sep, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_components(const GridDev& g, const LigDev* d_lig,
+                             int n_atoms, const float* xs, int64_t N,
+                             double* comps, int lds_bytes, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  const int blocks = grid_blocks(N, 1, 1 << 20);
+  BPMF_DISPATCH_C(g.C, {
+    if (n_atoms <= kWave)
+      hipLaunchKernelGGL((k_components<C, 1>), dim3(blocks), dim3(kWave),
+                         lds_bytes, st, g, d_lig, xs, N, comps);
+    else
+      hipLaunchKernelGGL((k_components<C, 2>), dim3(blocks), dim3(kWave),
+                         lds_bytes, st, g, d_lig, xs, N, comps);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const double* comps, int64_t N, int K, int C,
+                         const double* beta, const double* wd, double* ukn,
+                         int64_t ld, hipStream_t st) {
+  if (N <= 0 || K <= 0) return hipSuccess;
+  const int bx = grid_blocks(N, 256, 4096);
+  hipLaunchKernelGGL(k_expand, dim3(bx, K), dim3(256), 0, st, comps, N, K, C,
+                     beta, wd, ukn, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_evaluate(const GridDev& g, const LigDev* d_lig,
+                           int n_atoms, const float* xs, int64_t N,
+                           const double* w, double* terms, float* forces,
+                           int lds_bytes, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  const int blocks = grid_blocks(N, 1, 1 << 20);
+  BPMF_DISPATCH_C(g.C, {
+    if (n_atoms <= kWave)
+      hipLaunchKernelGGL((k_evaluate<C, 1>), dim3(blocks), dim3(kWave),
+                         lds_bytes, st, g, d_lig, xs, N, w, terms, forces);
+    else
+      hipLaunchKernelGGL((k_evaluate<C, 2>), dim3(blocks), dim3(kWave),
+                         lds_bytes, st, g, d_lig, xs, N, w, terms, forces);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_recompute_comps(const GridDev& g, const LigDev* d_lig,
+                                  int n_atoms, int K, int lds_bytes,
+                                  hipStream_t st) {
+  BPMF_DISPATCH_C(g.C, {
+    if (n_atoms <= kWave)
+      hipLaunchKernelGGL((k_recompute<C, 1>), dim3(K), dim3(kWave), lds_bytes,
+                         st, g, d_lig);
+    else
+      hipLaunchKernelGGL((k_recompute<C, 2>), dim3(K), dim3(kWave), lds_bytes,
+                         st, g, d_lig);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_eval(const GridDev& g, const float* pos,
+                            const float* scale, int64_t n, const double* w,
+                            float* energy, float* force, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = grid_blocks(n, 256, 1 << 20);
+  BPMF_DISPATCH_C(g.C, {
+    WeightsC<C> wc;
+    for (int c = 0; c < C; ++c) wc.w[c] = (float)w[c];
+    hipLaunchKernelGGL((k_grid_eval<C>), dim3(blocks), dim3(256), 0, st, g,
+                       pos, scale, n, wc, energy, force);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace bpmf

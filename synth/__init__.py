@@ -357,6 +357,9 @@ CONFIGS = {
 }
 
 
+_GRID_CACHE = {}
+
+
 def make_system(config: int, n_ligands: Optional[int] = None,
                 with_grid: bool = True) -> System:
     """Build config `config` (1..5).  n_ligands truncates the ligand list of
@@ -380,11 +383,14 @@ def make_system(config: int, n_ligands: Optional[int] = None,
     n, h = c["n"], 0.25
     edge = (n - 1) * h
     if with_grid:
-        rrng = np.random.default_rng([gen_seed, 7])
-        avoid = np.concatenate([l.x0[0] for l in ligs], axis=0)
-        pts, q, sig, eps = make_receptor(rrng, c["n_rec"], edge, 0.3 * edge,
-                                         avoid_xyz=avoid)
-        nodes = grids_from_points(pts, q, sig, eps, n, h)
+        key = (config, len(counts))
+        if key not in _GRID_CACHE:
+            rrng = np.random.default_rng([gen_seed, 7])
+            avoid = np.concatenate([l.x0[0] for l in ligs], axis=0)
+            pts, q, sig, eps = make_receptor(rrng, c["n_rec"], edge,
+                                             0.3 * edge, avoid_xyz=avoid)
+            _GRID_CACHE[key] = grids_from_points(pts, q, sig, eps, n, h)
+        nodes = _GRID_CACHE[key].copy()
     else:
         nodes = np.zeros((0, 0, 0, 3), np.float32)
     origin = -(n - 1) * h / 2
