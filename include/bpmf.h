@@ -148,7 +148,8 @@ typedef struct {
   const double* angle_k_t0;   /* host, n_angles x 2: K_theta, theta0 (rad) */
   int n_tors;
   const int* tors_ijkl;       /* host, n_tors x 4 */
-  const double* tors_v_n_g;   /* host, n_tors x 3: V/2, n, gamma (rad) */
+  const double* tors_v_n_g;   /* host, n_tors x 3: V/2, n (integer 1..6),
+                                 gamma (rad) */
   double site_center[3];
   double d0;                  /* restraint radius (A), >= 0 */
   double k_restraint;         /* kJ/(mol A^2), >= 0 */
@@ -296,6 +297,96 @@ BPMF_API int bpmf_get_samples(bpmf_ctx* ctx, int ligand_id, int64_t* n_records,
 
 /* Forget recorded samples of a ligand (-1 = all). */
 BPMF_API int bpmf_reset_samples(bpmf_ctx* ctx, int ligand_id);
+
+/* ------------------------------------------------------------------------
+ * Learned rigid-body pose proposal
+ *   The paper's external-coordinate move proposes a random rotation about
+ *   the centre of mass and a Gaussian translation and accepts by the
+ *   Metropolis criterion (Sampling).  Here the proposal is an 8-component
+ *   Gaussian mixture over the pose (t, omega) -- t = centre of mass minus
+ *   site centre (A), omega = rotation vector of the body frame built from
+ *   three frame atoms -- produced by an MLP 16 -> 256 -> 256 -> 104 (SiLU)
+ *   from sin/cos of up to 8 conditioning torsions.  Internal coordinates are
+ *   kept; the independence Metropolis-Hastings acceptance uses the mixture
+ *   folded onto SE(3) (sum over the rotation-vector preimages
+ *   (theta + 2 pi m) n, m = -3..3, with the Haar factor
+ *   2 (1 - cos|omega|)/|omega|^2):
+ *       ln alpha = -(E_k(x') - E_k(x)) / (R T_k) + ln q(xi) - ln q(xi').
+ *   Network outputs per component j (13): logit, mu_t (3), raw mu_w (3) with
+ *   mu_w = pi tanh(raw), raw sigma_t (3), raw sigma_w (3) with
+ *   sigma = lo + (hi - lo) sigmoid(raw), sigma_t in [0.02, 3] A, sigma_w in
+ *   [0.02, 1.5] rad.  Dense layers run on bf16 matrix cores with fp32
+ *   accumulation; master weights are fp32.
+ *   Parameter vector (BPMF_PROPOSAL_PARAMS floats): W1 (16 x 256, [in][out]),
+ *   b1 (256), W2 (256 x 256), b2, W3 (256 x 104), b3 (104).
+ * ------------------------------------------------------------------------ */
+#define BPMF_PROPOSAL_PARAMS 96872
+#define BPMF_PROPOSAL_OUT 104
+#define BPMF_PROPOSAL_FEAT 16
+
+/* Attach a proposal to a ligand: frame_atoms (host, 3 distinct atoms whose
+ * positions define the body frame: e1 along a0->a1, e2 the part of a0->a2
+ * orthogonal to e1, e3 = e1 x e2), n_cond <= 8 conditioning torsions
+ * cond_ijkl (host, n_cond x 4 atom indices), initial params (host). */
+BPMF_API int bpmf_proposal_setup(bpmf_ctx* ctx, int ligand_id,
+                                 const int* frame_atoms, int n_cond,
+                                 const int* cond_ijkl, const float* params);
+
+/* Copy the fp32 parameters out (out != NULL) and/or in (in != NULL). */
+BPMF_API int bpmf_proposal_params(bpmf_ctx* ctx, int ligand_id, float* out,
+                                  const float* in);
+
+/* Pose and features of N configurations dev_x (device, N x n_atoms x 3):
+ * dev_feats (device, N x 16: sin, cos of each conditioning torsion, zero
+ * padded), dev_poses (device, N x 6: t, omega with |omega| <= pi). */
+BPMF_API int bpmf_pose_features(bpmf_ctx* ctx, int ligand_id,
+                                const float* dev_x, int64_t N,
+                                float* dev_feats, float* dev_poses);
+
+/* Network outputs dev_out (device, N x 104) for dev_feats (device, N x 16). */
+BPMF_API int bpmf_proposal_forward(bpmf_ctx* ctx, int ligand_id,
+                                   const float* dev_feats, int64_t N,
+                                   float* dev_out);
+
+/* Gradient (device, BPMF_PROPOSAL_PARAMS floats) of the mean negative
+ * log-likelihood of dev_poses under the mixture for dev_feats; *loss (host,
+ * may be NULL) receives the loss (synchronises). */
+BPMF_API int bpmf_proposal_grad(bpmf_ctx* ctx, int ligand_id,
+                                const float* dev_feats, const float* dev_poses,
+                                int64_t N, float* dev_grad, double* loss);
+
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr)
+ * on minibatches of `batch` rows drawn with replacement (Philox) from the N
+ * training pairs; loss_out (host, steps doubles, may be NULL) receives each
+ * step's minibatch loss (synchronises every step when given). */
+BPMF_API int bpmf_proposal_train(bpmf_ctx* ctx, int ligand_id,
+                                 const float* dev_feats,
+                                 const float* dev_poses, int64_t N, int batch,
+                                 int steps, double lr, double* loss_out);
+
+/* `rounds` independence MH pose moves of every replica of the ligand (-1 =
+ * every ligand with a proposal) at the current sweep counter.  Random
+ * numbers: Philox purpose 4, index 0 (component), 1 and 2 (normals of t and
+ * omega), 3 (acceptance). */
+BPMF_API int bpmf_pose_move(bpmf_ctx* ctx, int ligand_id, int rounds);
+
+/* Pose-move counts per state (host, K each) and ln alpha of each replica's
+ * last move (host, K); any output may be NULL. */
+BPMF_API int bpmf_get_pose_stats(bpmf_ctx* ctx, int ligand_id, int64_t* acc,
+                                 int64_t* tries, double* last_ln_alpha);
+
+/* ------------------------------------------------------------------------
+ * Launch shape
+ * ------------------------------------------------------------------------ */
+
+/* Wavefronts per replica in the HMC sweep (and in bpmf_evaluate): 1, 2 or 4,
+ * or 0 for the automatic choice (4 while at most 512 replicas are set up,
+ * 2 up to 2048, else 1; never fewer than ceil(n_atoms / 64)).  Results do
+ * not depend on it beyond float32 rounding of the bonded-term order. */
+BPMF_API int bpmf_set_waves(bpmf_ctx* ctx, int waves);
+
+/* Wavefronts per replica the sweep currently uses for a ligand. */
+BPMF_API int bpmf_get_waves(bpmf_ctx* ctx, int ligand_id, int* waves);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (HIP events on the context's stream)

@@ -103,6 +103,19 @@ def library():
         "bpmf_get_samples": [vp, C.c_int, i64p, C.POINTER(C.c_float), dp],
         "bpmf_reset_samples": [vp, C.c_int],
         "bpmf_set_timing": [vp, C.c_int, C.c_int],
+        "bpmf_set_waves": [vp, C.c_int],
+        "bpmf_proposal_setup": [vp, C.c_int, ip, C.c_int, ip,
+                                C.POINTER(C.c_float)],
+        "bpmf_proposal_params": [vp, C.c_int, C.POINTER(C.c_float),
+                                 C.POINTER(C.c_float)],
+        "bpmf_pose_features": [vp, C.c_int, vp, C.c_int64, vp, vp],
+        "bpmf_proposal_forward": [vp, C.c_int, vp, C.c_int64, vp],
+        "bpmf_proposal_grad": [vp, C.c_int, vp, vp, C.c_int64, vp, dp],
+        "bpmf_proposal_train": [vp, C.c_int, vp, vp, C.c_int64, C.c_int,
+                                C.c_int, C.c_double, dp],
+        "bpmf_pose_move": [vp, C.c_int, C.c_int],
+        "bpmf_get_pose_stats": [vp, C.c_int, i64p, i64p, dp],
+        "bpmf_get_waves": [vp, C.c_int, ip],
         "bpmf_get_timing": [vp, C.c_int, dp, i64p],
         "bpmf_version": [],
         "bpmf_last_error": [],
@@ -360,6 +373,90 @@ class Context:
         _check(self._lib.bpmf_get_samples(self._h, int(ligand_id),
                                           C.byref(nr), _pf(x), _pd(comps)))
         return x, comps
+
+    # -- learned pose proposal ------------------------------------------------
+    N_PARAMS, N_OUT, N_FEAT = 96872, 104, 16
+
+    def proposal_setup(self, ligand_id, frame_atoms, cond_ijkl, params):
+        fa = np.ascontiguousarray(frame_atoms, np.int32)
+        cd = np.ascontiguousarray(cond_ijkl, np.int32).reshape(-1, 4)
+        pr = np.ascontiguousarray(params, np.float32).reshape(-1)
+        assert pr.size == self.N_PARAMS
+        _check(self._lib.bpmf_proposal_setup(
+            self._h, int(ligand_id), _pi(fa), len(cd),
+            _pi(cd) if len(cd) else None, _pf(pr)))
+
+    def proposal_params(self, ligand_id, new=None):
+        out = np.zeros(self.N_PARAMS, np.float32)
+        inp = None if new is None else np.ascontiguousarray(new, np.float32)
+        _check(self._lib.bpmf_proposal_params(
+            self._h, int(ligand_id), _pf(out),
+            _pf(inp) if inp is not None else None))
+        return out if new is None else None
+
+    def pose_features(self, ligand_id, x):
+        torch = self._torch
+        N = x.shape[0]
+        dev = f"cuda:{self.device}"
+        f = torch.empty((N, self.N_FEAT), dtype=torch.float32, device=dev)
+        p = torch.empty((N, 6), dtype=torch.float32, device=dev)
+        _check(self._lib.bpmf_pose_features(self._h, int(ligand_id),
+                                            x.data_ptr(), N, f.data_ptr(),
+                                            p.data_ptr()))
+        return f, p
+
+    def proposal_forward(self, ligand_id, feats):
+        torch = self._torch
+        N = feats.shape[0]
+        out = torch.empty((N, self.N_OUT), dtype=torch.float32,
+                          device=f"cuda:{self.device}")
+        _check(self._lib.bpmf_proposal_forward(self._h, int(ligand_id),
+                                               feats.data_ptr(), N,
+                                               out.data_ptr()))
+        return out
+
+    def proposal_grad(self, ligand_id, feats, poses):
+        torch = self._torch
+        g = torch.empty(self.N_PARAMS, dtype=torch.float32,
+                        device=f"cuda:{self.device}")
+        loss = C.c_double(0.0)
+        _check(self._lib.bpmf_proposal_grad(self._h, int(ligand_id),
+                                            feats.data_ptr(), poses.data_ptr(),
+                                            feats.shape[0], g.data_ptr(),
+                                            C.byref(loss)))
+        return g, loss.value
+
+    def proposal_train(self, ligand_id, feats, poses, batch, steps, lr,
+                       losses=False):
+        out = np.zeros(max(int(steps), 1))
+        _check(self._lib.bpmf_proposal_train(
+            self._h, int(ligand_id), feats.data_ptr(), poses.data_ptr(),
+            feats.shape[0], int(batch), int(steps), float(lr),
+            _pd(out) if losses else None))
+        return out[:steps] if losses else None
+
+    def pose_move(self, ligand_id=-1, rounds=1):
+        _check(self._lib.bpmf_pose_move(self._h, int(ligand_id), int(rounds)))
+
+    def get_pose_stats(self, ligand_id):
+        K = self.ligands[ligand_id]["K"]
+        a = np.zeros(K, np.int64)
+        t = np.zeros(K, np.int64)
+        la = np.zeros(K)
+        p = lambda v: v.ctypes.data_as(C.POINTER(C.c_int64))  # noqa: E731
+        _check(self._lib.bpmf_get_pose_stats(self._h, int(ligand_id), p(a),
+                                             p(t), _pd(la)))
+        return dict(acc=a, tries=t, last_ln_alpha=la)
+
+    def set_waves(self, waves):
+        """Wavefronts per replica (1, 2, 4; 0 = automatic)."""
+        _check(self._lib.bpmf_set_waves(self._h, int(waves)))
+
+    def get_waves(self, ligand_id):
+        out = C.c_int(0)
+        _check(self._lib.bpmf_get_waves(self._h, int(ligand_id),
+                                        C.byref(out)))
+        return out.value
 
     TIMER_HMC, TIMER_COMPONENTS, TIMER_TAIL = 0, 1, 2
 

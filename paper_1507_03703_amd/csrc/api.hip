@@ -13,6 +13,7 @@
 
 #include "../../include/bpmf.h"
 #include "internal.h"
+#include "mlp.h"
 
 using namespace bpmf;
 
@@ -56,12 +57,21 @@ struct Arena {
 struct LigHost {
   LigDev dev;      // device pointers inside the ligand's arena
   void* arena;     // owning allocation
-  int apl;         // atoms per lane (1 or 2)
-  int lds_force;   // dynamic LDS of force-evaluating kernels
-  int lds_energy;  // dynamic LDS of energy-only kernels
+  int min_waves;   // wavefronts needed to give every atom a thread
+  int sweep_waves; // wavefronts per replica in the HMC sweep
   uint64_t counter;   // host mirror of *dev.counter
   int64_t n_rec;      // host mirror of *dev.n_rec
   std::vector<double> beta, wd;
+  // learned pose proposal (bpmf_proposal_setup)
+  bool has_prop = false;
+  void* prop_arena = nullptr;
+  PropDev* d_prop = nullptr;  // device copy of PropDev
+  float* params = nullptr;    // kNParams fp32 master weights
+  float* grad = nullptr;      // kNParams
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  int64_t adam_t = 0;
+  PropDev prop{};
 };
 
 }  // namespace
@@ -80,13 +90,19 @@ struct bpmf_ctx {
   // ligands
   std::vector<LigHost> ligs;
   LigDev* d_ligs = nullptr;  // device copy of every LigDev
-  int2* d_tasks = nullptr;   // [APL-1 tasks | APL-2 tasks]
-  int n_tasks1 = 0, n_tasks2 = 0, lds1 = 0, lds2 = 0;
+  int2* d_tasks = nullptr;   // sweep tasks grouped by wavefronts per replica
+  static constexpr int kWaveClasses = 4;  // W = 1, 2, 4, 8
+  int class_off[kWaveClasses] = {0, 0, 0, 0};
+  int class_n[kWaveClasses] = {0, 0, 0, 0};
+  int class_lds[kWaveClasses] = {0, 0, 0, 0};
+  int waves_override = 0;  // 0 = automatic choice
   // scratch
   void* comps_mem = nullptr;
   size_t comps_bytes = 0;
   void* mbar_mem = nullptr;
   size_t mbar_bytes = 0;
+  void* mlp_mem = nullptr;   // activations of the proposal network
+  size_t mlp_bytes = 0;
   // kernel timing
   static constexpr int kTimers = 3;
   static constexpr size_t kMaxPairs = 8192;
@@ -156,37 +172,64 @@ bool finite_all(const double* p, size_t n) {
   return true;
 }
 
+int wave_class(int w) { return w == 1 ? 0 : (w == 2 ? 1 : (w == 4 ? 2 : 3)); }
+
+int lds_of(const LigHost& h, int waves, bool forces) {
+  const LigDev& L = h.dev;
+  return block_lds_bytes(waves, forces ? L.n_slots : 0, L.n, L.nb, L.na, L.nt);
+}
+
+// wavefronts per replica for the HMC sweep: enough to own every atom; when
+// few replicas are in flight (latency-bound) spread each over up to four
+// wavefronts so that the bonded terms of a step run in parallel
+int choose_waves(const bpmf_ctx* c, const LigHost& h, int total_replicas) {
+  int w = c->waves_override ? c->waves_override : 1;
+  if (!c->waves_override) {
+    // enough waves to give every bonded term its own thread while the chip
+    // has room for them (latency-bound ladders), fewer when replicas alone
+    // fill the chip
+    const int terms = h.dev.nb + h.dev.na + h.dev.nt;
+    int want = 1;
+    while (want < 8 && want * kWave < terms) want *= 2;
+    while (want > 1 && total_replicas * want > 4096) want /= 2;
+    w = want;
+  }
+  if (w < h.min_waves) w = h.min_waves;
+  return w;
+}
+
 // rebuild the device ligand table and the sweep task lists
 int rebuild_tables(bpmf_ctx* c) {
   const int nl = (int)c->ligs.size();
   std::vector<LigDev> table(nl);
-  std::vector<int2> t1, t2;
-  int lds1 = 0, lds2 = 0;
+  std::vector<int2> cls[bpmf_ctx::kWaveClasses];
+  int lds[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
+  int total = 0;
+  for (int l = 0; l < nl; ++l) total += c->ligs[l].dev.K;
   for (int l = 0; l < nl; ++l) {
-    table[l] = c->ligs[l].dev;
-    const LigHost& h = c->ligs[l];
-    for (int r = 0; r < h.dev.K; ++r) {
-      if (h.apl == 1)
-        t1.push_back(make_int2(l, r));
-      else
-        t2.push_back(make_int2(l, r));
-    }
-    if (h.apl == 1)
-      lds1 = std::max(lds1, h.lds_force);
-    else
-      lds2 = std::max(lds2, h.lds_force);
+    LigHost& h = c->ligs[l];
+    table[l] = h.dev;
+    h.sweep_waves = choose_waves(c, h, total);
+    const int q = wave_class(h.sweep_waves);
+    for (int r = 0; r < h.dev.K; ++r) cls[q].push_back(make_int2(l, r));
+    lds[q] = std::max(lds[q], lds_of(h, h.sweep_waves, true));
+  }
+  std::vector<int2> all;
+  int off[bpmf_ctx::kWaveClasses];
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+    off[q] = (int)all.size();
+    all.insert(all.end(), cls[q].begin(), cls[q].end());
   }
   void* nd = c->dalloc(sizeof(LigDev) * std::max(nl, 1));
-  void* nt = c->dalloc(sizeof(int2) * std::max<size_t>(t1.size() + t2.size(), 1));
+  void* nt = c->dalloc(sizeof(int2) * std::max<size_t>(all.size(), 1));
   if (!nd || !nt) {
     c->dfree(nd);
     c->dfree(nt);
     return fail(BPMF_E_NOMEM, "ligand table allocation failed");
   }
-  std::vector<int2> all(t1);
-  all.insert(all.end(), t2.begin(), t2.end());
-  HIP_TRY(hipMemcpyAsync(nd, table.data(), sizeof(LigDev) * nl,
-                         hipMemcpyHostToDevice, c->stream));
+  if (nl)
+    HIP_TRY(hipMemcpyAsync(nd, table.data(), sizeof(LigDev) * nl,
+                           hipMemcpyHostToDevice, c->stream));
   if (!all.empty())
     HIP_TRY(hipMemcpyAsync(nt, all.data(), sizeof(int2) * all.size(),
                            hipMemcpyHostToDevice, c->stream));
@@ -195,10 +238,11 @@ int rebuild_tables(bpmf_ctx* c) {
   c->dfree(c->d_tasks);
   c->d_ligs = (LigDev*)nd;
   c->d_tasks = (int2*)nt;
-  c->n_tasks1 = (int)t1.size();
-  c->n_tasks2 = (int)t2.size();
-  c->lds1 = lds1;
-  c->lds2 = lds2;
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+    c->class_off[q] = off[q];
+    c->class_n[q] = (int)cls[q].size();
+    c->class_lds[q] = lds[q];
+  }
   return BPMF_OK;
 }
 
@@ -253,7 +297,11 @@ extern "C" int bpmf_destroy(bpmf_ctx* c) {
   if (!c) return BPMF_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  for (auto& l : c->ligs) c->dfree(l.arena);
+  for (auto& l : c->ligs) {
+    c->dfree(l.arena);
+    c->dfree(l.prop_arena);
+  }
+  c->dfree(c->mlp_mem);
   c->dfree(c->grid_mem);
   c->dfree(c->d_ligs);
   c->dfree(c->d_tasks);
@@ -411,7 +459,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
 
   const int nb = d->n_bonds, na = d->n_angles, nt = d->n_tors;
   const int n_slots = 2 * nb + 3 * na + 4 * nt;
-  const int apl = n <= kWave ? 1 : 2;
+  const int min_waves = n <= kWave ? 1 : 2;
   const int cap = d->sample_capacity;
   const int C1 = 1 + C;
   const int Km1 = std::max(K - 1, 1);
@@ -428,44 +476,54 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   std::vector<int2> bij(nb);
   std::vector<float2> bpar(nb);
   for (int t = 0; t < nb; ++t) {
-    bij[t] = make_int2(d->bond_ij[2 * t], d->bond_ij[2 * t + 1]);
     bpar[t] = make_float2((float)d->bond_k_r0[2 * t],
                           (float)d->bond_k_r0[2 * t + 1]);
   }
   std::vector<int4> aijk(na);
   std::vector<float2> apar(na);
   for (int t = 0; t < na; ++t) {
-    aijk[t] = make_int4(d->angle_ijk[3 * t], d->angle_ijk[3 * t + 1],
-                        d->angle_ijk[3 * t + 2], 0);
     apar[t] = make_float2((float)d->angle_k_t0[2 * t],
                           (float)d->angle_k_t0[2 * t + 1]);
   }
   std::vector<int4> tijkl(nt);
   std::vector<float4> tpar(nt);
   for (int t = 0; t < nt; ++t) {
-    tijkl[t] = make_int4(d->tors_ijkl[4 * t], d->tors_ijkl[4 * t + 1],
-                         d->tors_ijkl[4 * t + 2], d->tors_ijkl[4 * t + 3]);
-    tpar[t] = make_float4((float)d->tors_v_n_g[3 * t],
-                          (float)d->tors_v_n_g[3 * t + 1],
-                          (float)d->tors_v_n_g[3 * t + 2], 0.f);
+    const double mult = d->tors_v_n_g[3 * t + 1];
+    if (mult != floor(mult) || mult < 1 || mult > 6)
+      return fail(BPMF_E_INVAL,
+                  "torsion %d: multiplicity %g is not an integer in 1..6", t,
+                  mult);
+    const double gam = d->tors_v_n_g[3 * t + 2];
+    tpar[t] = make_float4((float)d->tors_v_n_g[3 * t], (float)mult,
+                          (float)cos(gam), (float)sin(gam));
   }
-  // force-slot gather lists: slot s belongs to exactly one atom
-  std::vector<std::vector<int>> per(n);
-  for (int t = 0; t < nb; ++t)
-    for (int a = 0; a < 2; ++a) per[d->bond_ij[2 * t + a]].push_back(2 * t + a);
-  for (int t = 0; t < na; ++t)
-    for (int a = 0; a < 3; ++a)
-      per[d->angle_ijk[3 * t + a]].push_back(2 * nb + 3 * t + a);
+  // force slots numbered atom by atom: the slots of atom i are the
+  // contiguous range gstart[i] .. gstart[i+1]-1, in term order (torsions,
+  // angles, bonds, each ascending) within the atom; every term records the
+  // slot of each of its atoms next to the atom index (atom | slot << 8)
+  std::vector<int> cnt(n, 0);
   for (int t = 0; t < nt; ++t)
-    for (int a = 0; a < 4; ++a)
-      per[d->tors_ijkl[4 * t + a]].push_back(2 * nb + 3 * na + 4 * t + a);
-  std::vector<int> gstart(n + 1, 0), gidx;
-  gidx.reserve(n_slots);
-  for (int i = 0; i < n; ++i) {
-    gstart[i] = (int)gidx.size();
-    gidx.insert(gidx.end(), per[i].begin(), per[i].end());
+    for (int a = 0; a < 4; ++a) ++cnt[d->tors_ijkl[4 * t + a]];
+  for (int t = 0; t < na; ++t)
+    for (int a = 0; a < 3; ++a) ++cnt[d->angle_ijk[3 * t + a]];
+  for (int t = 0; t < nb; ++t)
+    for (int a = 0; a < 2; ++a) ++cnt[d->bond_ij[2 * t + a]];
+  std::vector<int> gstart(n + 1, 0), next(n, 0);
+  for (int i = 0; i < n; ++i) gstart[i + 1] = gstart[i] + cnt[i];
+  for (int i = 0; i < n; ++i) next[i] = gstart[i];
+  auto pack = [&](int atom) { return atom | (next[atom]++ << 8); };
+  for (int t = 0; t < nt; ++t) {
+    const int* q = d->tors_ijkl + 4 * t;
+    tijkl[t] = make_int4(pack(q[0]), pack(q[1]), pack(q[2]), pack(q[3]));
   }
-  gstart[n] = (int)gidx.size();
+  for (int t = 0; t < na; ++t) {
+    const int* q = d->angle_ijk + 3 * t;
+    aijk[t] = make_int4(pack(q[0]), pack(q[1]), pack(q[2]), 0);
+  }
+  for (int t = 0; t < nb; ++t) {
+    const int* q = d->bond_ij + 2 * t;
+    bij[t] = make_int2(pack(q[0]), pack(q[1]));
+  }
   std::vector<double> beta(K), wd((size_t)K * C);
   std::vector<float> Tf(K), dtf(K), wf((size_t)K * C);
   for (int k = 0; k < K; ++k) {
@@ -487,7 +545,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_bpar = A.add(nb * 8), o_aijk = A.add(na * 16),
                o_apar = A.add(na * 8), o_tijkl = A.add(nt * 16),
                o_tpar = A.add(nt * 16), o_gs = A.add((n + 1) * 4),
-               o_gi = A.add(n_slots * 4), o_beta = A.add(K * 8),
+               o_beta = A.add(K * 8),
                o_Tf = A.add(K * 4), o_dt = A.add(K * 4),
                o_wf = A.add((size_t)K * C * 4), o_wd = A.add((size_t)K * C * 8),
                o_x = A.add((size_t)K * n * 12), o_comps = A.add((size_t)K * C1 * 8),
@@ -497,6 +555,14 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_etry = A.add(Km1 * 8),
                o_sx = A.add((size_t)cap * K * n * 12),
                o_sc = A.add((size_t)cap * K * C1 * 8);
+  {
+    // every kernel stages the topology in LDS next to its working areas
+    const int need = block_lds_bytes(min_waves, n_slots, n, nb, na, nt);
+    if (need > 65536)
+      return fail(BPMF_E_INVAL,
+                  "topology too large: %d bytes of LDS per replica (max 65536)",
+                  need);
+  }
   char* base = (char*)c->dalloc(A.total);
   if (!base) return fail(BPMF_E_NOMEM, "ligand allocation of %zu bytes failed",
                          A.total);
@@ -519,7 +585,6 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   chain(up(o_tijkl, tijkl.data(), nt * 16));
   chain(up(o_tpar, tpar.data(), nt * 16));
   chain(up(o_gs, gstart.data(), (n + 1) * 4));
-  chain(up(o_gi, gidx.data(), n_slots * 4));
   chain(up(o_beta, beta.data(), K * 8));
   chain(up(o_Tf, Tf.data(), K * 4));
   chain(up(o_dt, dtf.data(), K * 4));
@@ -563,7 +628,6 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.tijkl = (const int4*)(base + o_tijkl);
   L.tpar = (const float4*)(base + o_tpar);
   L.gstart = (const int*)(base + o_gs);
-  L.gidx = (const int*)(base + o_gi);
   L.beta = (const double*)(base + o_beta);
   L.Tf = (const float*)(base + o_Tf);
   L.dtf = (const float*)(base + o_dt);
@@ -583,9 +647,8 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.samp_x = (float*)(base + o_sx);
   L.samp_c = (double*)(base + o_sc);
   h.arena = base;
-  h.apl = apl;
-  h.lds_force = (int)(apl * kWave * sizeof(float4) + 3 * sizeof(float) * n_slots);
-  h.lds_energy = (int)(apl * kWave * sizeof(float4));
+  h.min_waves = min_waves;
+  h.sweep_waves = min_waves;
   h.counter = 0;
   h.n_rec = 0;
   h.beta = beta;
@@ -599,7 +662,8 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   }
   // initial cached components
   const LigDev* dl = c->d_ligs + (c->ligs.size() - 1);
-  HIP_TRY(launch_recompute_comps(c->grid, dl, n, K, h.lds_energy, c->stream));
+  HIP_TRY(launch_recompute_comps(c->grid, dl, min_waves, K,
+                                 lds_of(c->ligs.back(), min_waves, false), c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   *ligand_id = L.id;
   return BPMF_OK;
@@ -641,13 +705,12 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     hipEvent_t t0, t1;
     const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1);
     if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
-    if (c->n_tasks1)
-      HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs, c->d_tasks, c->n_tasks1, 1,
-                               c->lds1, a->n_leapfrog, c->seed, c->stream));
-    if (c->n_tasks2)
-      HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs, c->d_tasks + c->n_tasks1,
-                               c->n_tasks2, 2, c->lds2, a->n_leapfrog, c->seed,
-                               c->stream));
+    for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
+      if (c->class_n[q])
+        HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs,
+                                 c->d_tasks + c->class_off[q], c->class_n[q],
+                                 1 << q, c->class_lds[q], a->n_leapfrog,
+                                 c->seed, c->stream));
     if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
     const bool timed_tail = c->timer_begin(BPMF_TIMER_TAIL, &t0, &t1);
     if (timed_tail) HIP_TRY(hipEventRecord(t0, c->stream));
@@ -713,8 +776,9 @@ extern "C" int bpmf_energy_matrix(bpmf_ctx* c, int ligand_id,
   hipEvent_t t0, t1;
   const bool timed = c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
   if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
-  HIP_TRY(launch_components(c->grid, c->d_ligs + ligand_id, h.dev.n, xs,
-                            n_samples, comps, h.lds_energy, c->stream));
+  HIP_TRY(launch_components(c->grid, c->d_ligs + ligand_id, h.min_waves, xs,
+                            n_samples, comps,
+                            lds_of(h, h.min_waves, false), c->stream));
   if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   HIP_TRY(launch_expand(comps, n_samples, h.dev.K, C, h.dev.beta, h.dev.wd,
                         dev_ukn, ld, c->stream));
@@ -869,9 +933,11 @@ extern "C" int bpmf_evaluate(bpmf_ctx* c, int ligand_id, const float* dev_x,
   if (!dev_x || !dev_w || !dev_terms)
     return fail(BPMF_E_INVAL, "null evaluate argument");
   const LigHost& h = c->ligs[ligand_id];
-  HIP_TRY(launch_evaluate(c->grid, c->d_ligs + ligand_id, h.dev.n, dev_x,
-                          n_conf, dev_w, dev_terms, dev_forces, h.lds_force,
-                          c->stream));
+  const int wv = c->waves_override ? std::max(c->waves_override, h.min_waves)
+                                   : h.min_waves;
+  HIP_TRY(launch_evaluate(c->grid, c->d_ligs + ligand_id, wv, dev_x, n_conf,
+                          dev_w, dev_terms, dev_forces,
+                          lds_of(h, wv, true), c->stream));
   return BPMF_OK;
 }
 
@@ -946,8 +1012,9 @@ extern "C" int bpmf_set_replicas(bpmf_ctx* c, int ligand_id, const float* x,
     HIP_TRY(hipMemcpyAsync(L.comps, comps, (size_t)L.K * (1 + L.C) * 8,
                            hipMemcpyHostToDevice, c->stream));
   else
-    HIP_TRY(launch_recompute_comps(c->grid, c->d_ligs + ligand_id, L.n, L.K,
-                                   h.lds_energy, c->stream));
+    HIP_TRY(launch_recompute_comps(c->grid, c->d_ligs + ligand_id,
+                                   h.min_waves, L.K,
+                                   lds_of(h, h.min_waves, false), c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   h.counter = counter;
   return BPMF_OK;
@@ -1053,5 +1120,351 @@ extern "C" int bpmf_get_timing(bpmf_ctx* c, int kernel, double* mean_ms,
   if (n_timed) *n_timed = (int64_t)n;
   c->ev_used[kernel] = 0;
   c->launches[kernel] = 0;
+  return BPMF_OK;
+}
+
+// ============================================================================
+// launch shape
+// ============================================================================
+extern "C" int bpmf_set_waves(bpmf_ctx* c, int waves) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(BPMF_E_INVAL, "waves must be 0 (automatic), 1, 2, 4 or 8");
+  c->waves_override = waves;
+  return rebuild_tables(c);
+}
+
+extern "C" int bpmf_get_waves(bpmf_ctx* c, int ligand_id, int* waves) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  if (!waves) return fail(BPMF_E_INVAL, "null output");
+  *waves = c->ligs[ligand_id].sweep_waves;
+  return BPMF_OK;
+}
+
+// ============================================================================
+// learned pose proposal
+// ============================================================================
+namespace {
+
+struct MlpBufs {
+  float *Z1, *H1, *Z2, *H2, *out, *dout, *dZ2, *dZ1, *bf, *bp;
+  double* loss_part;
+};
+
+int mlp_scratch(bpmf_ctx* c, int B, MlpBufs* b) {
+  Arena A;
+  const size_t o_z1 = A.add((size_t)B * kNHid * 4), o_h1 = A.add((size_t)B * kNHid * 4),
+               o_z2 = A.add((size_t)B * kNHid * 4), o_h2 = A.add((size_t)B * kNHid * 4),
+               o_out = A.add((size_t)B * kNOut * 4), o_do = A.add((size_t)B * kNOut * 4),
+               o_dz2 = A.add((size_t)B * kNHid * 4), o_dz1 = A.add((size_t)B * kNHid * 4),
+               o_bf = A.add((size_t)B * kNFeat * 4), o_bp = A.add((size_t)B * 6 * 4),
+               o_lp = A.add((size_t)((B + 255) / 256) * 8);
+  int rc = ensure_scratch(c, &c->mlp_mem, &c->mlp_bytes, A.total);
+  if (rc) return rc;
+  char* base = (char*)c->mlp_mem;
+  b->Z1 = (float*)(base + o_z1);
+  b->H1 = (float*)(base + o_h1);
+  b->Z2 = (float*)(base + o_z2);
+  b->H2 = (float*)(base + o_h2);
+  b->out = (float*)(base + o_out);
+  b->dout = (float*)(base + o_do);
+  b->dZ2 = (float*)(base + o_dz2);
+  b->dZ1 = (float*)(base + o_dz1);
+  b->bf = (float*)(base + o_bf);
+  b->bp = (float*)(base + o_bp);
+  b->loss_part = (double*)(base + o_lp);
+  return BPMF_OK;
+}
+
+GemmArgs gemm(int M, int N, int K, const float* A, int64_t sam, int64_t sak,
+              const float* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
+              const float* bias, int epi, float* Zout, const float* Zin) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.sam = sam; g.sak = sak;
+  g.B = B; g.sbk = sbk; g.sbn = sbn;
+  g.C = C; g.ldc = ldc; g.bias = bias; g.epi = epi; g.Zout = Zout; g.Zin = Zin;
+  return g;
+}
+
+// out = MLP(feats) for B rows
+int mlp_forward(bpmf_ctx* c, const float* P, const float* feats, int B,
+                const MlpBufs& b, float* out) {
+  HIP_TRY(launch_gemm(gemm(B, kNHid, kNFeat, feats, kNFeat, 1, P + kOffW1, kNHid,
+                           1, b.H1, kNHid, P + kOffB1, kEpiSilu, b.Z1, nullptr),
+                      c->stream));
+  HIP_TRY(launch_gemm(gemm(B, kNHid, kNHid, b.H1, kNHid, 1, P + kOffW2, kNHid, 1,
+                           b.H2, kNHid, P + kOffB2, kEpiSilu, b.Z2, nullptr),
+                      c->stream));
+  HIP_TRY(launch_gemm(gemm(B, kNOut, kNHid, b.H2, kNHid, 1, P + kOffW3, kNOut, 1,
+                           out, kNOut, P + kOffB3, kEpiStore, nullptr, nullptr),
+                      c->stream));
+  return BPMF_OK;
+}
+
+// gradient of the mean NLL of (feats, poses) into G; loss partials in b
+int mlp_grad(bpmf_ctx* c, const float* P, const float* feats,
+             const float* poses, int B, const MlpBufs& b, float* G) {
+  int rc = mlp_forward(c, P, feats, B, b, b.out);
+  if (rc) return rc;
+  HIP_TRY(launch_nll(b.out, poses, B, b.dout, b.loss_part, c->stream));
+  // dZ2 = (dout W3^T) * silu'(Z2); dZ1 = (dZ2 W2^T) * silu'(Z1)
+  HIP_TRY(launch_gemm(gemm(B, kNHid, kNOut, b.dout, kNOut, 1, P + kOffW3, 1,
+                           kNOut, b.dZ2, kNHid, nullptr, kEpiDsilu, nullptr, b.Z2),
+                      c->stream));
+  HIP_TRY(launch_gemm(gemm(B, kNHid, kNHid, b.dZ2, kNHid, 1, P + kOffW2, 1, kNHid,
+                           b.dZ1, kNHid, nullptr, kEpiDsilu, nullptr, b.Z1),
+                      c->stream));
+  // weight gradients: H2^T dout, H1^T dZ2, feats^T dZ1
+  HIP_TRY(launch_gemm(gemm(kNHid, kNOut, B, b.H2, 1, kNHid, b.dout, kNOut, 1,
+                           G + kOffW3, kNOut, nullptr, kEpiStore, nullptr, nullptr),
+                      c->stream));
+  HIP_TRY(launch_gemm(gemm(kNHid, kNHid, B, b.H1, 1, kNHid, b.dZ2, kNHid, 1,
+                           G + kOffW2, kNHid, nullptr, kEpiStore, nullptr, nullptr),
+                      c->stream));
+  HIP_TRY(launch_gemm(gemm(kNFeat, kNHid, B, feats, 1, kNFeat, b.dZ1, kNHid, 1,
+                           G + kOffW1, kNHid, nullptr, kEpiStore, nullptr, nullptr),
+                      c->stream));
+  HIP_TRY(launch_colsum(b.dout, B, kNOut, kNOut, G + kOffB3, c->stream));
+  HIP_TRY(launch_colsum(b.dZ2, B, kNHid, kNHid, G + kOffB2, c->stream));
+  HIP_TRY(launch_colsum(b.dZ1, B, kNHid, kNHid, G + kOffB1, c->stream));
+  return BPMF_OK;
+}
+
+int read_loss(bpmf_ctx* c, const MlpBufs& b, int B, double* loss) {
+  const int nb = (B + 255) / 256;
+  std::vector<double> lp(nb);
+  HIP_TRY(hipMemcpyAsync(lp.data(), b.loss_part, nb * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (double v : lp) s += v;
+  *loss = s / B;
+  return BPMF_OK;
+}
+
+int check_prop(bpmf_ctx* c, int lid) {
+  int rc = check_lig(c, lid);
+  if (rc) return rc;
+  if (!c->ligs[lid].has_prop)
+    return fail(BPMF_E_STATE, "ligand %d has no pose proposal (call "
+                "bpmf_proposal_setup)", lid);
+  return BPMF_OK;
+}
+
+}  // namespace
+
+extern "C" int bpmf_proposal_setup(bpmf_ctx* c, int lid, const int* frame_atoms,
+                                   int n_cond, const int* cond_ijkl,
+                                   const float* params) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, lid))) return rc;
+  LigHost& h = c->ligs[lid];
+  const int n = h.dev.n;
+  if (!frame_atoms || !params)
+    return fail(BPMF_E_INVAL, "null frame atoms or parameters");
+  if (n_cond < 0 || n_cond > 8 || (n_cond && !cond_ijkl))
+    return fail(BPMF_E_INVAL, "n_cond must be 0..8 with a torsion list");
+  if (n < 3) return fail(BPMF_E_INVAL, "a pose frame needs >= 3 atoms");
+  for (int a = 0; a < 3; ++a) {
+    if (frame_atoms[a] < 0 || frame_atoms[a] >= n)
+      return fail(BPMF_E_INVAL, "frame atom %d out of range", frame_atoms[a]);
+    for (int b = 0; b < a; ++b)
+      if (frame_atoms[a] == frame_atoms[b])
+        return fail(BPMF_E_INVAL, "repeated frame atom");
+  }
+  for (int q = 0; q < 4 * n_cond; ++q)
+    if (cond_ijkl[q] < 0 || cond_ijkl[q] >= n)
+      return fail(BPMF_E_INVAL, "conditioning torsion atom out of range");
+  for (int q = 0; q < kNParams; ++q)
+    if (!isfinite(params[q])) return fail(BPMF_E_INVAL, "non-finite parameter");
+  const int K = h.dev.K;
+  Arena A;
+  const size_t o_p = A.add(kNParams * 4), o_g = A.add(kNParams * 4),
+               o_m = A.add(kNParams * 4), o_v = A.add(kNParams * 4),
+               o_acc = A.add(K * 8), o_try = A.add(K * 8), o_la = A.add(K * 8),
+               o_dev = A.add(sizeof(PropDev));
+  char* base = (char*)c->dalloc(A.total);
+  if (!base) return fail(BPMF_E_NOMEM, "proposal allocation failed");
+  PropDev pd{};
+  for (int a = 0; a < 3; ++a) pd.frame[a] = frame_atoms[a];
+  pd.n_cond = n_cond;
+  for (int q = 0; q < n_cond; ++q)
+    pd.cond[q] = make_int4(cond_ijkl[4 * q], cond_ijkl[4 * q + 1],
+                           cond_ijkl[4 * q + 2], cond_ijkl[4 * q + 3]);
+  pd.pose_acc = (unsigned long long*)(base + o_acc);
+  pd.pose_try = (unsigned long long*)(base + o_try);
+  pd.last_ln_alpha = (double*)(base + o_la);
+  hipError_t e = hipMemcpyAsync(base + o_p, params, kNParams * 4,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + o_m, 0, kNParams * 4, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + o_v, 0, kNParams * 4, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + o_acc, 0, K * 8, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + o_try, 0, K * 8, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(base + o_la, 0, K * 8, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + o_dev, &pd, sizeof(PropDev), hipMemcpyHostToDevice,
+                       c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->dfree(base);
+    return fail(BPMF_E_HIP, "proposal upload: %s", hipGetErrorString(e));
+  }
+  c->dfree(h.prop_arena);
+  h.prop_arena = base;
+  h.params = (float*)(base + o_p);
+  h.grad = (float*)(base + o_g);
+  h.adam_m = (float*)(base + o_m);
+  h.adam_v = (float*)(base + o_v);
+  h.d_prop = (PropDev*)(base + o_dev);
+  h.prop = pd;
+  h.adam_t = 0;
+  h.has_prop = true;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_proposal_params(bpmf_ctx* c, int lid, float* out,
+                                    const float* in) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_prop(c, lid))) return rc;
+  LigHost& h = c->ligs[lid];
+  if (in)
+    HIP_TRY(hipMemcpyAsync(h.params, in, kNParams * 4, hipMemcpyHostToDevice,
+                           c->stream));
+  if (out)
+    HIP_TRY(hipMemcpyAsync(out, h.params, kNParams * 4, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_pose_features(bpmf_ctx* c, int lid, const float* dev_x,
+                                  int64_t N, float* dev_feats,
+                                  float* dev_poses) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_prop(c, lid))) return rc;
+  if (N < 0) return fail(BPMF_E_INVAL, "negative N");
+  if (N == 0) return BPMF_OK;
+  if (!dev_x || !dev_feats || !dev_poses)
+    return fail(BPMF_E_INVAL, "null pose_features argument");
+  HIP_TRY(launch_pose_features(c->d_ligs + lid, c->ligs[lid].d_prop, dev_x, N,
+                               dev_feats, dev_poses, c->stream));
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_proposal_forward(bpmf_ctx* c, int lid,
+                                     const float* dev_feats, int64_t N,
+                                     float* dev_out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_prop(c, lid))) return rc;
+  if (N < 0 || N > (1 << 24)) return fail(BPMF_E_INVAL, "N outside 0..2^24");
+  if (N == 0) return BPMF_OK;
+  if (!dev_feats || !dev_out) return fail(BPMF_E_INVAL, "null argument");
+  MlpBufs b;
+  if ((rc = mlp_scratch(c, (int)N, &b))) return rc;
+  return mlp_forward(c, c->ligs[lid].params, dev_feats, (int)N, b, dev_out);
+}
+
+extern "C" int bpmf_proposal_grad(bpmf_ctx* c, int lid, const float* dev_feats,
+                                  const float* dev_poses, int64_t N,
+                                  float* dev_grad, double* loss) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_prop(c, lid))) return rc;
+  if (N < 1 || N > (1 << 24)) return fail(BPMF_E_INVAL, "N outside 1..2^24");
+  if (!dev_feats || !dev_poses || !dev_grad)
+    return fail(BPMF_E_INVAL, "null argument");
+  MlpBufs b;
+  if ((rc = mlp_scratch(c, (int)N, &b))) return rc;
+  if ((rc = mlp_grad(c, c->ligs[lid].params, dev_feats, dev_poses, (int)N, b,
+                     dev_grad)))
+    return rc;
+  if (loss) return read_loss(c, b, (int)N, loss);
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_proposal_train(bpmf_ctx* c, int lid, const float* dev_feats,
+                                   const float* dev_poses, int64_t N, int batch,
+                                   int steps, double lr, double* loss_out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_prop(c, lid))) return rc;
+  if (N < 1 || batch < 1 || batch > (1 << 20) || steps < 0 || !(lr > 0))
+    return fail(BPMF_E_INVAL, "bad training arguments");
+  if (!dev_feats || !dev_poses) return fail(BPMF_E_INVAL, "null data");
+  LigHost& h = c->ligs[lid];
+  MlpBufs b;
+  if ((rc = mlp_scratch(c, batch, &b))) return rc;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int s = 0; s < steps; ++s) {
+    HIP_TRY(launch_gather_batch(dev_feats, dev_poses, N, batch, c->seed,
+                                (uint64_t)h.adam_t, b.bf, b.bp, c->stream));
+    if ((rc = mlp_grad(c, h.params, b.bf, b.bp, batch, b, h.grad))) return rc;
+    ++h.adam_t;
+    const float c1 = 1.f - powf(b1, (float)h.adam_t);
+    const float c2 = 1.f - powf(b2, (float)h.adam_t);
+    HIP_TRY(launch_adam(h.params, h.grad, h.adam_m, h.adam_v, kNParams,
+                        (float)lr, b1, b2, eps, c1, c2, c->stream));
+    if (loss_out && (rc = read_loss(c, b, batch, &loss_out[s]))) return rc;
+  }
+  return BPMF_OK;
+}
+
+namespace {
+int pose_move_ligand(bpmf_ctx* c, int lid) {
+  LigHost& h = c->ligs[lid];
+  const int K = h.dev.K;
+  MlpBufs b;
+  int rc = mlp_scratch(c, K, &b);
+  if (rc) return rc;
+  // features of the current replicas, network, move
+  HIP_TRY(launch_pose_features(c->d_ligs + lid, h.d_prop, h.dev.x, K, b.bf,
+                               b.bp, c->stream));
+  if ((rc = mlp_forward(c, h.params, b.bf, K, b, b.out))) return rc;
+  HIP_TRY(launch_pose_move(c->grid, c->d_ligs + lid, h.d_prop, b.out, K,
+                           h.min_waves, lds_of(h, h.min_waves, false), c->seed,
+                           c->stream));
+  return BPMF_OK;
+}
+}  // namespace
+
+extern "C" int bpmf_pose_move(bpmf_ctx* c, int lid, int rounds) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (rounds < 0) return fail(BPMF_E_INVAL, "negative rounds");
+  if (lid != -1 && (rc = check_prop(c, lid))) return rc;
+  for (int r = 0; r < rounds; ++r)
+    for (size_t l = 0; l < c->ligs.size(); ++l) {
+      if (lid != -1 && (int)l != lid) continue;
+      if (!c->ligs[l].has_prop) continue;
+      if ((rc = pose_move_ligand(c, (int)l))) return rc;
+    }
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_get_pose_stats(bpmf_ctx* c, int lid, int64_t* acc,
+                                   int64_t* tries, double* last_ln_alpha) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_prop(c, lid))) return rc;
+  const LigHost& h = c->ligs[lid];
+  const int K = h.dev.K;
+  if (acc)
+    HIP_TRY(hipMemcpyAsync(acc, h.prop.pose_acc, K * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  if (tries)
+    HIP_TRY(hipMemcpyAsync(tries, h.prop.pose_try, K * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+  if (last_ln_alpha)
+    HIP_TRY(hipMemcpyAsync(last_ln_alpha, h.prop.last_ln_alpha, K * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return BPMF_OK;
 }

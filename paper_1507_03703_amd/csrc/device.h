@@ -32,16 +32,47 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Butterfly all-reduce: every lane ends with the same, order-fixed sum.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+// Wavefront sums with DPP row operations (quad permutes, half-row and row
+// mirrors, then row broadcasts 15 and 31 into the upper rows); the total
+// ends in lane 63 and is read back as a wave-uniform value.  The order of
+// the additions is fixed, so every lane sees the same, reproducible sum.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL,
+                                                    ROWMASK, 0xf, false));
 }
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL,
+                                             ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK,
+                                             0xf, false);
+  return __longlong_as_double(((long long)hi << 32) |
+                              (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ float wave_sumf(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+  v += dpp_f<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_f<0x140, 0xf>(v);  // row_mirror: every lane holds its row sum
+  v += dpp_f<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_f<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1, 0xf>(v);
+  v += dpp_d<0x4E, 0xf>(v);
+  v += dpp_d<0x141, 0xf>(v);
+  v += dpp_d<0x140, 0xf>(v);
+  v += dpp_d<0x142, 0xa>(v);
+  v += dpp_d<0x143, 0xc>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // ----------------------------------------------------------------------------
@@ -140,14 +171,17 @@ __device__ __forceinline__ void grid_fetch(const GridDev& g, float px,
   k.ay = grid_axis(py, g.oy, g.inv_h, g.ny);
   k.az = grid_axis(pz, g.oz, g.inv_h, g.nz);
   const size_t sx = C, sy = (size_t)g.nx * C, sz = (size_t)g.nx * g.ny * C;
-  const float* base = g.nodes + (size_t)k.az.i * sz + (size_t)k.ay.i * sy +
-                      (size_t)k.ax.i * sx;
+  // the grid lives in global memory: say so, so that the gathers are
+  // global (not flat) loads and LDS waits do not wait on them
+  typedef const float __attribute__((address_space(1))) gfloat;
+  gfloat* base = (gfloat*)g.nodes + (size_t)k.az.i * sz +
+                 (size_t)k.ay.i * sy + (size_t)k.ax.i * sx;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const float* p = base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) +
-                     ((q & 4) ? sz : 0);
+    gfloat* p = base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) +
+                ((q & 4) ? sz : 0);
 #pragma unroll
-    for (int c = 0; c < C; ++c) k.v[q][c] = __ldg(p + c);
+    for (int c = 0; c < C; ++c) k.v[q][c] = p[c];
   }
 }
 
@@ -221,29 +255,32 @@ __device__ __forceinline__ float3 scale3(float s, float3 a) {
   return make_float3(s * a.x, s * a.y, s * a.z);
 }
 
+// Per-(term, atom) force contributions.  Slot numbers are assigned so that
+// every atom's slots form one contiguous range (ascending term order within
+// the atom), so the owner sums a contiguous run without indirection.
 struct Slots {
-  float* x;
-  float* y;
-  float* z;
+  float4* v;
   __device__ __forceinline__ void put(int i, float3 f) const {
-    x[i] = f.x;
-    y[i] = f.y;
-    z[i] = f.z;
+    v[i] = make_float4(f.x, f.y, f.z, 0.f);
   }
 };
+
+// topology entries pack an atom index (low 8 bits) and the slot that
+// receives that atom's force from the term (upper bits)
+__device__ __forceinline__ int atom_of(int p) { return p & 0xff; }
+__device__ __forceinline__ int slot_of(int p) { return p >> 8; }
 
 // K (r - r0)^2
 template <bool FORCES>
 __device__ __forceinline__ float bond_term(const float4* pos, int2 ij,
-                                           float2 par, const Slots& sl,
-                                           int slot) {
-  const float3 d = sub(f3(pos[ij.x]), f3(pos[ij.y]));
+                                           float2 par, const Slots& sl) {
+  const float3 d = sub(f3(pos[atom_of(ij.x)]), f3(pos[atom_of(ij.y)]));
   const float r = sqrtf(dot(d, d));
   const float dr = r - par.y;
   if (FORCES) {
     const float f = -2.0f * par.x * dr / r;
-    sl.put(slot, scale3(f, d));
-    sl.put(slot + 1, scale3(-f, d));
+    sl.put(slot_of(ij.x), scale3(f, d));
+    sl.put(slot_of(ij.y), scale3(-f, d));
   }
   return par.x * dr * dr;
 }
@@ -251,11 +288,10 @@ __device__ __forceinline__ float bond_term(const float4* pos, int2 ij,
 // K (theta - theta0)^2, theta = atan2(|a x b|, a.b), a = xi-xj, b = xk-xj
 template <bool FORCES>
 __device__ __forceinline__ float angle_term(const float4* pos, int4 ijk,
-                                            float2 par, const Slots& sl,
-                                            int slot) {
-  const float3 xj = f3(pos[ijk.y]);
-  const float3 a = sub(f3(pos[ijk.x]), xj);
-  const float3 b = sub(f3(pos[ijk.z]), xj);
+                                            float2 par, const Slots& sl) {
+  const float3 xj = f3(pos[atom_of(ijk.y)]);
+  const float3 a = sub(f3(pos[atom_of(ijk.x)]), xj);
+  const float3 b = sub(f3(pos[atom_of(ijk.z)]), xj);
   const float3 c = cross(a, b);
   const float s = sqrtf(dot(c, c)), co = dot(a, b);
   const float th = atan2f(s, co);
@@ -274,30 +310,46 @@ __device__ __forceinline__ float angle_term(const float4* pos, int4 ijk,
     const float3 fk = make_float3(-ck * (cth * bh.x - ah.x),
                                   -ck * (cth * bh.y - ah.y),
                                   -ck * (cth * bh.z - ah.z));
-    sl.put(slot, fi);
-    sl.put(slot + 1, make_float3(-(fi.x + fk.x), -(fi.y + fk.y),
-                                 -(fi.z + fk.z)));
-    sl.put(slot + 2, fk);
+    sl.put(slot_of(ijk.x), fi);
+    sl.put(slot_of(ijk.y), make_float3(-(fi.x + fk.x), -(fi.y + fk.y),
+                                       -(fi.z + fk.z)));
+    sl.put(slot_of(ijk.z), fk);
   }
   return par.x * dth * dth;
 }
 
 // (V/2)(1 + cos(n phi - gamma)), IUPAC phi; forces in the singularity-free
-// form of Blondel & Karplus (J. Comput. Chem. 17, 1132, 1996)
+// form of Blondel & Karplus (J. Comput. Chem. 17, 1132, 1996).  With
+// x = n1.n2 and y = |b2| b1.n2 one has x^2 + y^2 = |n1|^2 |n2|^2, so
+// cos phi = x/r and sin phi = y/r (r = |n1||n2|); for integer
+// multiplicities 1..6 (par.w = n, else 0) cos(n phi) and sin(n phi) follow
+// by complex multiplication and no inverse trigonometric call is needed.
 template <bool FORCES>
 __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
-                                              float4 par, const Slots& sl,
-                                              int slot) {
-  const float3 xi = f3(pos[ijkl.x]), xj = f3(pos[ijkl.y]);
-  const float3 xk = f3(pos[ijkl.z]), xl = f3(pos[ijkl.w]);
+                                              float4 par, const Slots& sl) {
+  const float3 xi = f3(pos[atom_of(ijkl.x)]), xj = f3(pos[atom_of(ijkl.y)]);
+  const float3 xk = f3(pos[atom_of(ijkl.z)]), xl = f3(pos[atom_of(ijkl.w)]);
   const float3 b1 = sub(xj, xi), b2 = sub(xk, xj), b3 = sub(xl, xk);
   const float3 n1 = cross(b1, b2), n2 = cross(b2, b3);
   const float lb2 = sqrtf(dot(b2, b2));
-  const float phi = atan2f(lb2 * dot(b1, n2), dot(n1, n2));
-  float sn, cs;
-  sincosf(par.y * phi - par.z, &sn, &cs);
+  const float xx = dot(n1, n2), yy = lb2 * dot(b1, n2);
+  // par: V/2, n, cos gamma, sin gamma; integer multiplicity in the sign-free
+  // upper bits is not needed: n is an integer 1..6 (checked at setup)
+  const int mult = (int)par.y;
+  const float ir = rsqrtf(xx * xx + yy * yy);
+  const float c1 = xx * ir, s1 = yy * ir;
+  float cn = c1, sn = s1;
+  for (int q = 1; q < mult; ++q) {
+    const float c2 = cn * c1 - sn * s1;
+    sn = sn * c1 + cn * s1;
+    cn = c2;
+  }
+  // cos(n phi - gamma), sin(n phi - gamma)
+  const float cg = par.z, sg = par.w;
+  const float cs = cn * cg + sn * sg;
+  const float snm = sn * cg - cn * sg;
   if (FORCES) {
-    const float dE = -par.x * par.y * sn;
+    const float dE = -par.x * par.y * snm;
     const float in1 = 1.0f / dot(n1, n1), in2 = 1.0f / dot(n2, n2);
     const float ilb2 = 1.0f / lb2;
     const float p12 = dot(b1, b2) * ilb2 * in1;
@@ -310,123 +362,237 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
     const float3 gk = make_float3(-gl.x - p12 * n1.x - p23 * n2.x,
                                   -gl.y - p12 * n1.y - p23 * n2.y,
                                   -gl.z - p12 * n1.z - p23 * n2.z);
-    sl.put(slot, scale3(-dE, gi));
-    sl.put(slot + 1, scale3(-dE, gj));
-    sl.put(slot + 2, scale3(-dE, gk));
-    sl.put(slot + 3, scale3(-dE, gl));
+    sl.put(slot_of(ijkl.x), scale3(-dE, gi));
+    sl.put(slot_of(ijkl.y), scale3(-dE, gj));
+    sl.put(slot_of(ijkl.z), scale3(-dE, gk));
+    sl.put(slot_of(ijkl.w), scale3(-dE, gl));
   }
   return par.x * (1.0f + cs);
 }
 
 // ----------------------------------------------------------------------------
-// one full evaluation of a configuration by one wavefront
+// one full evaluation of a configuration by one workgroup of W wavefronts
 // ----------------------------------------------------------------------------
-// terms (ENERGY): [U_bond, U_angle, U_tors, U_I, Psi_0..Psi_{C-1}], identical
-// on every lane.  f (FORCES): -grad(U_bonded + U_I + sum_c w_c Psi_c) for the
-// lane's atoms.  spos: n float4; slots: 3 x n_slots floats.
-template <int C, int APL, bool FORCES, bool ENERGY>
-__device__ __forceinline__ void eval_conf(const GridDev& g, const LigDev& L,
-                                          const float* w,
-                                          const float (&x)[APL][3],
-                                          const float (&m)[APL],
-                                          float (&f)[APL][3],
-                                          double (&terms)[4 + C],
-                                          float4* spos, const Slots& sl,
-                                          int lane) {
+// Thread t owns atom t (n <= 64 W).  Bonded terms are spread over all 64 W
+// threads; the grid gathers of the owners are issued before the bonded pass
+// so that their latency overlaps it (a workgroup barrier on gfx950 waits on
+// LDS traffic only, not on outstanding global loads).
+//
+// Shared memory (Shared): positions, force slots, per-wave partial sums.
+struct Shared {
+  float4* pos;     // 64 W
+  Slots sl;        // 3 x n_slots
+  float* com;      // W x 3
+  double* red;     // W x kRed
+  // ligand topology staged once per launch (stage_topology)
+  const int2* bij;
+  const float2* bpar;
+  const int4* aijk;
+  const float2* apar;
+  const int4* tijkl;
+  const float4* tpar;
+  const int* gstart;
+};
+
+// Copy a ligand's constant topology into LDS (all threads; caller syncs).
+// `raw` points past the per-evaluation areas; layout: tpar (nt float4),
+// tijkl (nt int4), aijk (na int4), apar (na float2), bij (nb int2), bpar
+// (nb float2), gstart (n+1 int).
+__device__ __forceinline__ void stage_topology(const LigDev& L,
+                                               unsigned char* raw, Shared& sh,
+                                               int tid, int nthreads) {
+  float4* tpar = reinterpret_cast<float4*>(raw);
+  int4* tijkl = reinterpret_cast<int4*>(tpar + L.nt);
+  int4* aijk = tijkl + L.nt;
+  float2* apar = reinterpret_cast<float2*>(aijk + L.na);
+  int2* bij = reinterpret_cast<int2*>(apar + L.na);
+  float2* bpar = reinterpret_cast<float2*>(bij + L.nb);
+  int* gstart = reinterpret_cast<int*>(bpar + L.nb);
+  for (int i = tid; i < L.nt; i += nthreads) {
+    tpar[i] = L.tpar[i];
+    tijkl[i] = L.tijkl[i];
+  }
+  for (int i = tid; i < L.na; i += nthreads) {
+    aijk[i] = L.aijk[i];
+    apar[i] = L.apar[i];
+  }
+  for (int i = tid; i < L.nb; i += nthreads) {
+    bij[i] = L.bij[i];
+    bpar[i] = L.bpar[i];
+  }
+  for (int i = tid; i <= L.n; i += nthreads) gstart[i] = L.gstart[i];
+  sh.bij = bij;
+  sh.bpar = bpar;
+  sh.aijk = aijk;
+  sh.apar = apar;
+  sh.tijkl = tijkl;
+  sh.tpar = tpar;
+  sh.gstart = gstart;
+}
+
+__host__ __device__ inline int topology_lds_bytes(int n, int nb, int na,
+                                                  int nt, int n_slots) {
+  return 32 * nt + 24 * na + 16 * nb + 4 * (n + 1) + 4 * n_slots;
+}
+constexpr int kRedMax = kRedSlots;  // U_bond..U_tors, Psi_c, two extras
+
+__device__ __forceinline__ void block_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// sc: per-atom grid factors of the thread's atom (0 for non-owners).
+// terms (ENERGY): [U_bond, U_angle, U_tors, U_I, Psi_0..Psi_{C-1}, X0, X1]
+// where X0, X1 are block sums of the caller's per-thread extras; identical
+// on every thread.  f (FORCES): -grad(U_bonded + U_I + sum_c w_c Psi_c) of
+// the thread's atom.
+template <int C, int W, bool FORCES, bool ENERGY>
+__device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
+                                           const float* w, const float (&x)[3],
+                                           float m, const float (&sc)[C],
+                                           float (&f)[3],
+                                           double (&terms)[6 + C],
+                                           float ex0, float ex1,
+                                           const Shared& sh, int tid) {
   const int n = L.n;
-  // publish positions for the bonded pass
-#pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    const int atom = lane + kWave * a;
-    if (atom < n) spos[atom] = make_float4(x[a][0], x[a][1], x[a][2], 0.f);
+  const int lane = tid & (kWave - 1), wv = tid >> 6;
+  const bool owner = tid < n;
+  if (owner) sh.pos[tid] = make_float4(x[0], x[1], x[2], 0.f);
+  Corners<C> cn;
+  const bool wave_has_atoms = wv * kWave < n;
+  if (wave_has_atoms) grid_fetch<C>(g, x[0], x[1], x[2], cn);
+  // per-wave partial mass-weighted position sums
+  float px = wave_sumf(m * x[0]), py = wave_sumf(m * x[1]),
+        pz = wave_sumf(m * x[2]);
+  if (lane == 0) {
+    sh.com[3 * wv] = px;
+    sh.com[3 * wv + 1] = py;
+    sh.com[3 * wv + 2] = pz;
   }
-  // issue the grid gathers first; their latency overlaps the bonded pass
-  Corners<C> cn[APL];
-#pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    const int atom = lane + kWave * a;
-    const int src = atom < n ? a : 0;
-    grid_fetch<C>(g, x[src][0], x[src][1], x[src][2], cn[a]);
-  }
-  wave_lds_sync();
+  block_sync();
 
+  // bonded terms: one segmented index over torsions, angles, bonds, so
+  // that every thread takes at most ceil(terms / 64 W) terms
   float eb = 0.f, ea = 0.f, et = 0.f;
-  for (int t = lane; t < L.nb; t += kWave)
-    eb += bond_term<FORCES>(spos, L.bij[t], L.bpar[t], sl, 2 * t);
-  const int sa = 2 * L.nb;
-  for (int t = lane; t < L.na; t += kWave)
-    ea += angle_term<FORCES>(spos, L.aijk[t], L.apar[t], sl, sa + 3 * t);
-  const int st = sa + 3 * L.na;
-  for (int t = lane; t < L.nt; t += kWave)
-    et += torsion_term<FORCES>(spos, L.tijkl[t], L.tpar[t], sl, st + 4 * t);
-  if (FORCES) wave_lds_sync();
-
-  // centre of mass and restraint (Eq. binding_site)
+  constexpr int T = W * kWave;
+  const int n_terms = L.nt + L.na + L.nb;
+  for (int u = tid; u < n_terms; u += T) {
+    if (u < L.nt) {
+      et += torsion_term<FORCES>(sh.pos, sh.tijkl[u], sh.tpar[u], sh.sl);
+    } else if (u < L.nt + L.na) {
+      const int t = u - L.nt;
+      ea += angle_term<FORCES>(sh.pos, sh.aijk[t], sh.apar[t], sh.sl);
+    } else {
+      const int t = u - L.nt - L.na;
+      eb += bond_term<FORCES>(sh.pos, sh.bij[t], sh.bpar[t], sh.sl);
+    }
+  }
+  // centre of mass (fixed-order sum of the wave partials) and restraint
   float cx = 0.f, cy = 0.f, cz = 0.f;
 #pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    cx += m[a] * x[a][0];
-    cy += m[a] * x[a][1];
-    cz += m[a] * x[a][2];
+  for (int q = 0; q < W; ++q) {
+    cx += sh.com[3 * q];
+    cy += sh.com[3 * q + 1];
+    cz += sh.com[3 * q + 2];
   }
-  cx = wave_sumf(cx) * L.inv_total_mass - L.site[0];
-  cy = wave_sumf(cy) * L.inv_total_mass - L.site[1];
-  cz = wave_sumf(cz) * L.inv_total_mass - L.site[2];
+  cx = cx * L.inv_total_mass - L.site[0];
+  cy = cy * L.inv_total_mass - L.site[1];
+  cz = cz * L.inv_total_mass - L.site[2];
   const float d = sqrtf(cx * cx + cy * cy + cz * cz);
   const float excess = d - L.d0;
   const bool restrained = excess > 0.f;
   const float fr = restrained ? -L.krest * excess / d * L.inv_total_mass : 0.f;
+  if (FORCES) block_sync();
 
   float psi[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) psi[c] = 0.f;
+  if (wave_has_atoms) {
+    float e[C], de[C][3];
+    grid_finish<C, FORCES>(g, cn, sc, e, de);
 #pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    const int atom = lane + kWave * a;
-    const bool valid = atom < n;
-    float sc[C], e[C], de[C][3];
-#pragma unroll
-    for (int c = 0; c < C; ++c) sc[c] = valid ? L.scale[atom * C + c] : 0.f;
-    grid_finish<C, FORCES>(g, cn[a], sc, e, de);
-#pragma unroll
-    for (int c = 0; c < C; ++c) psi[c] += e[c];
-    if (FORCES) {
+    for (int c = 0; c < C; ++c) psi[c] = e[c];
+    if (FORCES && owner) {
       float fx = 0.f, fy = 0.f, fz = 0.f;
-      if (valid) {
-        const int b = L.gstart[atom], eidx = L.gstart[atom + 1];
-        for (int q = b; q < eidx; ++q) {
-          const int s = L.gidx[q];
-          fx += sl.x[s];
-          fy += sl.y[s];
-          fz += sl.z[s];
-        }
-        fx += fr * m[a] * cx;
-        fy += fr * m[a] * cy;
-        fz += fr * m[a] * cz;
+      // the atom's slots are contiguous: issue eight loads at a time
+      const int b = sh.gstart[tid], eidx = sh.gstart[tid + 1];
+      int q = b;
+      for (; q + 8 <= eidx; q += 8) {
+        float4 v[8];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          fx -= w[c] * de[c][0];
-          fy -= w[c] * de[c][1];
-          fz -= w[c] * de[c][2];
+        for (int u = 0; u < 8; ++u) v[u] = sh.sl.v[q + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          fx += v[u].x;
+          fy += v[u].y;
+          fz += v[u].z;
         }
       }
-      f[a][0] = fx;
-      f[a][1] = fy;
-      f[a][2] = fz;
+      for (; q < eidx; ++q) {
+        const float4 v = sh.sl.v[q];
+        fx += v.x;
+        fy += v.y;
+        fz += v.z;
+      }
+      fx += fr * m * cx;
+      fy += fr * m * cy;
+      fz += fr * m * cz;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        fx -= w[c] * de[c][0];
+        fy -= w[c] * de[c][1];
+        fz -= w[c] * de[c][2];
+      }
+      f[0] = fx;
+      f[1] = fy;
+      f[2] = fz;
+    } else if (FORCES) {
+      f[0] = f[1] = f[2] = 0.f;
     }
+  } else if (FORCES) {
+    f[0] = f[1] = f[2] = 0.f;
   }
   if (ENERGY) {
-    terms[0] = wave_sum((double)eb);
-    terms[1] = wave_sum((double)ea);
-    terms[2] = wave_sum((double)et);
+    // per-wave sums in double, then a fixed-order sum over the waves
+    double v[6 + C];
+    v[0] = wave_sum((double)eb);
+    v[1] = wave_sum((double)ea);
+    v[2] = wave_sum((double)et);
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[4 + c] = wave_sum((double)psi[c]);
+    v[4 + C] = wave_sum((double)ex0);
+    v[5 + C] = wave_sum((double)ex1);
+    if (lane == 0) {
+      sh.red[wv * kRedMax + 0] = v[0];
+      sh.red[wv * kRedMax + 1] = v[1];
+      sh.red[wv * kRedMax + 2] = v[2];
+#pragma unroll
+      for (int q = 4; q < 6 + C; ++q) sh.red[wv * kRedMax + q - 1] = v[q];
+    }
+    block_sync();
+    double acc[6 + C];
+#pragma unroll
+    for (int q = 0; q < 6 + C; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < W; ++ww) {
+      acc[0] += sh.red[ww * kRedMax + 0];
+      acc[1] += sh.red[ww * kRedMax + 1];
+      acc[2] += sh.red[ww * kRedMax + 2];
+#pragma unroll
+      for (int q = 4; q < 6 + C; ++q) acc[q] += sh.red[ww * kRedMax + q - 1];
+    }
+    terms[0] = acc[0];
+    terms[1] = acc[1];
+    terms[2] = acc[2];
     terms[3] = restrained ? 0.5 * (double)L.krest * (double)excess *
                                 (double)excess
                           : 0.0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) terms[4 + c] = wave_sum((double)psi[c]);
+    for (int q = 4; q < 6 + C; ++q) terms[q] = acc[q];
+    // the next evaluation overwrites red[] only after two more barriers
   }
-  // keep the next evaluation's position writes behind this one's reads
-  wave_lds_sync();
+  if (!FORCES && !ENERGY) block_sync();
 }
 
 }  // namespace bpmf

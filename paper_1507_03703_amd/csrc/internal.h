@@ -8,6 +8,17 @@ namespace bpmf {
 constexpr int kWave = 64;
 constexpr double kRGas = 8.314462618e-3;  // kJ/(mol K)
 #define BPMF_MAX_MBAR_STATES_DEV 128
+constexpr int kRedSlots = 4 + 8 + 2;  // per-wave partial sums (see Shared)
+
+// dynamic LDS bytes of a W-wave evaluation block: per-evaluation areas,
+// n_slots force slots (0 for energy-only kernels) and the staged topology
+inline int block_lds_bytes(int waves, int n_slots, int n, int nb, int na,
+                           int nt) {
+  const int head = 16 * kWave * waves + 8 * waves * kRedSlots + 16 * waves +
+                   16 * n_slots;
+  const int topo = 32 * nt + 24 * na + 16 * nb + 4 * (n + 1);
+  return head + topo;
+}
 
 enum Purpose : uint32_t { kMomenta = 1, kAccept = 2, kExchange = 3 };
 
@@ -34,14 +45,15 @@ struct LigDev {
   const float* mass;      // n
   const float* inv_mass;  // n
   const float* scale;     // n*C
+  // term atom indices are packed with the force slot of that atom in the
+  // term: atom | slot << 8; slots are numbered atom by atom (contiguous)
   const int2* bij;        // nb
   const float2* bpar;     // nb: K_r, r0
   const int4* aijk;       // na: i, j(vertex), k, -
   const float2* apar;     // na: K_theta, theta0
   const int4* tijkl;      // nt
-  const float4* tpar;     // nt: V/2, n, gamma, -
-  const int* gstart;      // n+1 CSR offsets into gidx
-  const int* gidx;        // n_slots force-slot indices, ascending per atom
+  const float4* tpar;     // nt: V/2, n (integer 1..6), cos gamma, sin gamma
+  const int* gstart;      // n+1: slots of atom i are gstart[i]..gstart[i+1]-1
   const double* beta;     // K: 1/(R T_k)
   const float* Tf;        // K
   const float* dtf;       // K
@@ -63,8 +75,9 @@ struct LigDev {
 };
 
 // Launch wrappers (kernels.hip).  All return hipError_t of the launch.
+// waves = wavefronts per replica (1, 2 or 4); n_atoms <= 64 * waves
 hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
-                            const int2* d_tasks, int n_tasks, int apl,
+                            const int2* d_tasks, int n_tasks, int waves,
                             int lds_bytes, int nleap, uint64_t seed,
                             hipStream_t st);
 hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
@@ -73,20 +86,20 @@ hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
 hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
                            int max_sep, uint64_t seed, hipStream_t st);
 hipError_t launch_components(const GridDev& g, const LigDev* d_lig,
-                             int n_atoms, const float* xs, int64_t N,
+                             int waves, const float* xs, int64_t N,
                              double* comps, int lds_bytes, hipStream_t st);
 hipError_t launch_expand(const double* comps, int64_t N, int K, int C,
                          const double* beta, const double* wd, double* ukn,
                          int64_t ld, hipStream_t st);
 hipError_t launch_evaluate(const GridDev& g, const LigDev* d_lig,
-                           int n_atoms, const float* xs, int64_t N,
+                           int waves, const float* xs, int64_t N,
                            const double* w, double* terms, float* forces,
                            int lds_bytes, hipStream_t st);
 hipError_t launch_grid_eval(const GridDev& g, const float* pos,
                             const float* scale, int64_t n, const double* w,
                             float* energy, float* force, hipStream_t st);
 hipError_t launch_recompute_comps(const GridDev& g, const LigDev* d_lig,
-                                  int n_atoms, int K, int lds_bytes,
+                                  int waves, int K, int lds_bytes,
                                   hipStream_t st);
 
 // MBAR kernels (mbar.hip)

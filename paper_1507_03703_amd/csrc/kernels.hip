@@ -11,28 +11,60 @@ namespace bpmf {
 
 namespace {
 
-__device__ __forceinline__ Slots make_slots(float4* smem, int apl,
-                                            int n_slots) {
-  float* base = reinterpret_cast<float*>(smem + apl * kWave);
-  return Slots{base, base + n_slots, base + 2 * n_slots};
+// Dynamic LDS of a W-wave block: positions (64 W float4), per-wave partial
+// sums, centre-of-mass partials, n_slots float4 force slots, then the
+// ligand's topology (staged once per launch).
+template <int W>
+__device__ __forceinline__ Shared carve(unsigned char* raw, const LigDev& L,
+                                        int n_slots, int tid) {
+  Shared sh;
+  sh.pos = reinterpret_cast<float4*>(raw);
+  sh.red = reinterpret_cast<double*>(raw + 16 * kWave * W);
+  sh.com = reinterpret_cast<float*>(raw + 16 * kWave * W +
+                                    8 * W * kRedMax);
+  // offset arithmetic on the LDS base keeps the pointers in LDS space
+  const int slot0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
+  sh.sl = Slots{reinterpret_cast<float4*>(raw + slot0)};
+  stage_topology(L, raw + slot0 + 16 * n_slots, sh, tid, W * kWave);
+  __syncthreads();
+  return sh;
+}
+
+// block-wide double sums of two per-thread floats (fixed order)
+template <int W>
+__device__ __forceinline__ void block_sum2(float a, float b, double* buf,
+                                           int tid, double& sa, double& sb) {
+  const double wa = wave_sum((double)a), wb = wave_sum((double)b);
+  if ((tid & (kWave - 1)) == 0) {
+    buf[2 * (tid >> 6)] = wa;
+    buf[2 * (tid >> 6) + 1] = wb;
+  }
+  block_sync();
+  sa = 0.0;
+  sb = 0.0;
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    sa += buf[2 * q];
+    sb += buf[2 * q + 1];
+  }
 }
 
 // ----------------------------------------------------------------------------
-// HMC: one trial move per replica, one wavefront per replica.
+// HMC: one trial move per replica, one workgroup of W wavefronts per replica.
 // (Sampling: HMC trial moves from velocity-Verlet molecular dynamics.)
 // ----------------------------------------------------------------------------
-template <int C, int APL>
-__global__ __launch_bounds__(kWave) void k_hmc_sweep(
+template <int C, int W>
+__global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     GridDev g, const LigDev* __restrict__ ligs, const int2* __restrict__ tasks,
     int nleap, uint64_t seed) {
-  extern __shared__ float4 smem[];
-  const int lane = threadIdx.x;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
   const int2 task = tasks[blockIdx.x];
-  const LigDev& L = ligs[task.x];
+  const LigDev L = ligs[task.x];  // kernel-lifetime copy (no reloads)
   const int r = task.y;
   const int n = L.n;
-  float4* spos = smem;
-  const Slots sl = make_slots(smem, APL, L.n_slots);
+  const Shared sh = carve<W>(smem, L, L.n_slots, tid);
+  __shared__ double fin[2 * W];
 
   const unsigned long long s = *L.counter;
   const int k = L.state_of_replica[r];
@@ -43,95 +75,77 @@ __global__ __launch_bounds__(kWave) void k_hmc_sweep(
   const float dt = L.dtf[k];
   const double beta = L.beta[k];
 
-  float x[APL][3], v[APL][3], f[APL][3], m[APL], im[APL];
+  const bool owner = tid < n;
+  float x[3], v[3], f[3];
+  const float m = owner ? L.mass[tid] : 0.f;
+  float sc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) sc[c] = owner ? L.scale[tid * C + c] : 0.f;
+  const float im = owner ? L.inv_mass[tid] : 0.f;
   const float* xr = L.x + (size_t)r * n * 3;
 #pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    const int atom = lane + kWave * a;
-    const bool valid = atom < n;
-    m[a] = valid ? L.mass[atom] : 0.f;
-    im[a] = valid ? L.inv_mass[atom] : 0.f;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) x[a][d] = valid ? xr[atom * 3 + d] : 0.f;
-    if (valid) {
-      const U4 o = draw(seed, (uint32_t)atom, L.id, r, s, kMomenta);
-      float z0, z1, z2;
-      normals3(o, z0, z1, z2);
-      const float sd = sqrtf((float)kRGas * T * im[a] * 1e-4f);
-      v[a][0] = sd * z0;
-      v[a][1] = sd * z1;
-      v[a][2] = sd * z2;
-    } else {
-      v[a][0] = v[a][1] = v[a][2] = 0.f;
-    }
+  for (int d = 0; d < 3; ++d) x[d] = owner ? xr[tid * 3 + d] : 0.f;
+  if (owner) {
+    const U4 o = draw(seed, (uint32_t)tid, L.id, r, s, kMomenta);
+    float z0, z1, z2;
+    normals3(o, z0, z1, z2);
+    const float sd = sqrtf((float)kRGas * T * im * 1e-4f);
+    v[0] = sd * z0;
+    v[1] = sd * z1;
+    v[2] = sd * z2;
+  } else {
+    v[0] = v[1] = v[2] = 0.f;
   }
+  const float ke0 = 0.5f * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
 
-  double t0[4 + C], t1[4 + C];
-  eval_conf<C, APL, true, true>(g, L, w, x, m, f, t0, spos, sl, lane);
+  double t0[6 + C], t1[6 + C];
+  eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t0, ke0, 0.f, sh, tid);
   double U0 = t0[0] + t0[1] + t0[2] + t0[3];
 #pragma unroll
   for (int c = 0; c < C; ++c) U0 += L.wd[k * C + c] * t0[4 + c];
-  float ke = 0.f;
-#pragma unroll
-  for (int a = 0; a < APL; ++a)
-    ke += 0.5f * m[a] * (v[a][0] * v[a][0] + v[a][1] * v[a][1] +
-                         v[a][2] * v[a][2]);
-  const double KE0 = wave_sum((double)ke) * 1e4;
+  const double KE0 = t0[4 + C] * 1e4;
 
-  const float hk = 0.5f * dt * 1e-4f;
+  const float hk = 0.5f * dt * 1e-4f * im;
   for (int step = 0; step < nleap; ++step) {
 #pragma unroll
-    for (int a = 0; a < APL; ++a)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        v[a][d] = fmaf(hk * im[a], f[a][d], v[a][d]);
-        x[a][d] = fmaf(dt, v[a][d], x[a][d]);
-      }
+    for (int d = 0; d < 3; ++d) {
+      v[d] = fmaf(hk, f[d], v[d]);
+      x[d] = fmaf(dt, v[d], x[d]);
+    }
     if (step == nleap - 1)
-      eval_conf<C, APL, true, true>(g, L, w, x, m, f, t1, spos, sl, lane);
+      eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid);
     else
-      eval_conf<C, APL, true, false>(g, L, w, x, m, f, t1, spos, sl, lane);
+      eval_block<C, W, true, false>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid);
 #pragma unroll
-    for (int a = 0; a < APL; ++a)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) v[a][d] = fmaf(hk * im[a], f[a][d], v[a][d]);
+    for (int d = 0; d < 3; ++d) v[d] = fmaf(hk, f[d], v[d]);
   }
   double U1 = t1[0] + t1[1] + t1[2] + t1[3];
 #pragma unroll
   for (int c = 0; c < C; ++c) U1 += L.wd[k * C + c] * t1[4 + c];
-  ke = 0.f;
-  int bad = 0;
-#pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    ke += 0.5f * m[a] * (v[a][0] * v[a][0] + v[a][1] * v[a][1] +
-                         v[a][2] * v[a][2]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) bad |= !isfinite(x[a][d]);
-  }
-  const double KE1 = wave_sum((double)ke) * 1e4;
-  const bool any_bad = __any(bad);
+  const float ke1 = 0.5f * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const float bad =
+      (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) ? 1.f : 0.f;
+  double KE1, nbad;
+  block_sum2<W>(ke1, bad, fin, tid, KE1, nbad);
+  KE1 *= 1e4;
   const double dH = (U1 + KE1) - (U0 + KE0);
   const U4 o = draw(seed, 0u, L.id, r, s, kAccept);
   const double lnu = log(u01d(o.x));
-  const bool finite = isfinite(dH) && !any_bad;
+  const bool finite = isfinite(dH) && nbad == 0.0;
   const bool accept = finite && (lnu < -beta * dH);
   if (accept) {
     float* xw = L.x + (size_t)r * n * 3;
+    if (owner)
 #pragma unroll
-    for (int a = 0; a < APL; ++a) {
-      const int atom = lane + kWave * a;
-      if (atom < n)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) xw[atom * 3 + d] = x[a][d];
-    }
-    if (lane == 0) {
+      for (int d = 0; d < 3; ++d) xw[tid * 3 + d] = x[d];
+    if (tid == 0) {
       double* cr = L.comps + (size_t)r * (1 + C);
       cr[0] = t1[0] + t1[1] + t1[2] + t1[3];
 #pragma unroll
       for (int c = 0; c < C; ++c) cr[1 + c] = t1[4 + c];
     }
   }
-  if (lane == 0) {
+  if (tid == 0) {
     atomicAdd(&L.hmc_try[k], 1ull);
     if (accept) atomicAdd(&L.hmc_acc[k], 1ull);
     if (!finite) atomicAdd(L.nonfinite, 1ull);
@@ -231,34 +245,29 @@ __global__ __launch_bounds__(256) void k_exchange(
 // ----------------------------------------------------------------------------
 // per-sample components [U_bonded + U_I, Psi_c] (energy only)
 // ----------------------------------------------------------------------------
-template <int C, int APL>
-__global__ __launch_bounds__(kWave) void k_components(
+template <int C, int W>
+__global__ __launch_bounds__(W * kWave) void k_components(
     GridDev g, const LigDev* __restrict__ lig, const float* __restrict__ xs,
     int64_t N, double* __restrict__ comps) {
-  extern __shared__ float4 smem[];
-  const LigDev& L = *lig;
-  const int lane = threadIdx.x;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const LigDev L = *lig;
+  const int tid = threadIdx.x;
   const int n = L.n;
-  const Slots sl = make_slots(smem, APL, 0);
-  float m[APL];
+  const Shared sh = carve<W>(smem, L, 0, tid);
+  const bool owner = tid < n;
+  const float m = owner ? L.mass[tid] : 0.f;
+  float sc[C];
 #pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    const int atom = lane + kWave * a;
-    m[a] = atom < n ? L.mass[atom] : 0.f;
-  }
-  const float w0[C > 0 ? C : 1] = {};
+  for (int c = 0; c < C; ++c) sc[c] = owner ? L.scale[tid * C + c] : 0.f;
+  const float w0[C] = {};
   for (int64_t smp = blockIdx.x; smp < N; smp += gridDim.x) {
-    float x[APL][3], f[APL][3];
+    float x[3], f[3];
     const float* xr = xs + (size_t)smp * n * 3;
 #pragma unroll
-    for (int a = 0; a < APL; ++a) {
-      const int atom = lane + kWave * a;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) x[a][d] = atom < n ? xr[atom * 3 + d] : 0.f;
-    }
-    double t[4 + C];
-    eval_conf<C, APL, false, true>(g, L, w0, x, m, f, t, smem, sl, lane);
-    if (lane == 0) {
+    for (int d = 0; d < 3; ++d) x[d] = owner ? xr[tid * 3 + d] : 0.f;
+    double t[6 + C];
+    eval_block<C, W, false, true>(g, L, w0, x, m, sc, f, t, 0.f, 0.f, sh, tid);
+    if (tid == 0) {
       double* cp = comps + (size_t)smp * (1 + C);
       cp[0] = t[0] + t[1] + t[2] + t[3];
 #pragma unroll
@@ -286,74 +295,64 @@ __global__ __launch_bounds__(256) void k_expand(
 // ----------------------------------------------------------------------------
 // exposed evaluator: terms and forces for arbitrary configurations/weights
 // ----------------------------------------------------------------------------
-template <int C, int APL>
-__global__ __launch_bounds__(kWave) void k_evaluate(
+template <int C, int W>
+__global__ __launch_bounds__(W * kWave) void k_evaluate(
     GridDev g, const LigDev* __restrict__ lig, const float* __restrict__ xs,
     int64_t N, const double* __restrict__ wconf, double* __restrict__ terms,
     float* __restrict__ forces) {
-  extern __shared__ float4 smem[];
-  const LigDev& L = *lig;
-  const int lane = threadIdx.x;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const LigDev L = *lig;
+  const int tid = threadIdx.x;
   const int n = L.n;
-  const Slots sl = make_slots(smem, APL, L.n_slots);
-  float m[APL];
+  const Shared sh = carve<W>(smem, L, L.n_slots, tid);
+  const bool owner = tid < n;
+  const float m = owner ? L.mass[tid] : 0.f;
+  float sc[C];
 #pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    const int atom = lane + kWave * a;
-    m[a] = atom < n ? L.mass[atom] : 0.f;
-  }
+  for (int c = 0; c < C; ++c) sc[c] = owner ? L.scale[tid * C + c] : 0.f;
   for (int64_t cf = blockIdx.x; cf < N; cf += gridDim.x) {
     float w[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) w[c] = (float)wconf[cf * C + c];
-    float x[APL][3], f[APL][3];
+    float x[3], f[3];
     const float* xr = xs + (size_t)cf * n * 3;
 #pragma unroll
-    for (int a = 0; a < APL; ++a) {
-      const int atom = lane + kWave * a;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) x[a][d] = atom < n ? xr[atom * 3 + d] : 0.f;
-    }
-    double t[4 + C];
-    eval_conf<C, APL, true, true>(g, L, w, x, m, f, t, smem, sl, lane);
-    if (lane == 0)
+    for (int d = 0; d < 3; ++d) x[d] = owner ? xr[tid * 3 + d] : 0.f;
+    double t[6 + C];
+    eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t, 0.f, 0.f, sh, tid);
+    if (tid == 0)
       for (int q = 0; q < 4 + C; ++q) terms[(size_t)cf * (4 + C) + q] = t[q];
-    if (forces) {
+    if (forces && owner) {
       float* fo = forces + (size_t)cf * n * 3;
 #pragma unroll
-      for (int a = 0; a < APL; ++a) {
-        const int atom = lane + kWave * a;
-        if (atom < n)
-#pragma unroll
-          for (int d = 0; d < 3; ++d) fo[atom * 3 + d] = f[a][d];
-      }
+      for (int d = 0; d < 3; ++d) fo[tid * 3 + d] = f[d];
     }
   }
 }
 
 // recompute cached components of every replica from its positions
-template <int C, int APL>
-__global__ __launch_bounds__(kWave) void k_recompute(
+template <int C, int W>
+__global__ __launch_bounds__(W * kWave) void k_recompute(
     GridDev g, const LigDev* __restrict__ lig) {
-  extern __shared__ float4 smem[];
-  const LigDev& L = *lig;
-  const int lane = threadIdx.x;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const LigDev L = *lig;
+  const int tid = threadIdx.x;
   const int n = L.n;
-  const Slots sl = make_slots(smem, APL, 0);
+  const Shared sh = carve<W>(smem, L, 0, tid);
   const int r = blockIdx.x;
-  float m[APL], x[APL][3], f[APL][3];
+  const bool owner = tid < n;
+  const float m = owner ? L.mass[tid] : 0.f;
+  float sc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) sc[c] = owner ? L.scale[tid * C + c] : 0.f;
+  float x[3], f[3];
   const float w0[C] = {};
 #pragma unroll
-  for (int a = 0; a < APL; ++a) {
-    const int atom = lane + kWave * a;
-    m[a] = atom < n ? L.mass[atom] : 0.f;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      x[a][d] = atom < n ? L.x[((size_t)r * n + atom) * 3 + d] : 0.f;
-  }
-  double t[4 + C];
-  eval_conf<C, APL, false, true>(g, L, w0, x, m, f, t, smem, sl, lane);
-  if (lane == 0) {
+  for (int d = 0; d < 3; ++d)
+    x[d] = owner ? L.x[((size_t)r * n + tid) * 3 + d] : 0.f;
+  double t[6 + C];
+  eval_block<C, W, false, true>(g, L, w0, x, m, sc, f, t, 0.f, 0.f, sh, tid);
+  if (tid == 0) {
     double* cp = L.comps + (size_t)r * (1 + C);
     cp[0] = t[0] + t[1] + t[2] + t[3];
 #pragma unroll
@@ -426,19 +425,37 @@ int grid_blocks(int64_t work, int per_block, int cap) {
       return hipErrorInvalidValue;                                 \
   }
 
+#define BPMF_DISPATCH_W(W_, ...)                                   \
+  switch (W_) {                                                    \
+    case 1: {                                                      \
+      constexpr int W = 1;                                         \
+      __VA_ARGS__;                                                 \
+    } break;                                                       \
+    case 2: {                                                      \
+      constexpr int W = 2;                                         \
+      __VA_ARGS__;                                                 \
+    } break;                                                       \
+    case 4: {                                                      \
+      constexpr int W = 4;                                         \
+      __VA_ARGS__;                                                 \
+    } break;                                                       \
+    case 8: {                                                      \
+      constexpr int W = 8;                                         \
+      __VA_ARGS__;                                                 \
+    } break;                                                       \
+    default:                                                       \
+      return hipErrorInvalidValue;                                 \
+  }
+
 hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
-                            const int2* d_tasks, int n_tasks, int apl,
+                            const int2* d_tasks, int n_tasks, int waves,
                             int lds_bytes, int nleap, uint64_t seed,
                             hipStream_t st) {
   if (n_tasks <= 0) return hipSuccess;
-  BPMF_DISPATCH_C(g.C, {
-    if (apl == 1)
-      hipLaunchKernelGGL((k_hmc_sweep<C, 1>), dim3(n_tasks), dim3(kWave),
-                         lds_bytes, st, g, d_ligs, d_tasks, nleap, seed);
-    else
-      hipLaunchKernelGGL((k_hmc_sweep<C, 2>), dim3(n_tasks), dim3(kWave),
-                         lds_bytes, st, g, d_ligs, d_tasks, nleap, seed);
-  });
+  BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
+    hipLaunchKernelGGL((k_hmc_sweep<C, W>), dim3(n_tasks), dim3(W * kWave),
+                       lds_bytes, st, g, d_ligs, d_tasks, nleap, seed);
+  }));
   return hipGetLastError();
 }
 
@@ -460,18 +477,14 @@ hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
 }
 
 hipError_t launch_components(const GridDev& g, const LigDev* d_lig,
-                             int n_atoms, const float* xs, int64_t N,
+                             int waves, const float* xs, int64_t N,
                              double* comps, int lds_bytes, hipStream_t st) {
   if (N <= 0) return hipSuccess;
   const int blocks = grid_blocks(N, 1, 1 << 20);
-  BPMF_DISPATCH_C(g.C, {
-    if (n_atoms <= kWave)
-      hipLaunchKernelGGL((k_components<C, 1>), dim3(blocks), dim3(kWave),
-                         lds_bytes, st, g, d_lig, xs, N, comps);
-    else
-      hipLaunchKernelGGL((k_components<C, 2>), dim3(blocks), dim3(kWave),
-                         lds_bytes, st, g, d_lig, xs, N, comps);
-  });
+  BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
+    hipLaunchKernelGGL((k_components<C, W>), dim3(blocks), dim3(W * kWave),
+                       lds_bytes, st, g, d_lig, xs, N, comps);
+  }));
   return hipGetLastError();
 }
 
@@ -486,33 +499,25 @@ hipError_t launch_expand(const double* comps, int64_t N, int K, int C,
 }
 
 hipError_t launch_evaluate(const GridDev& g, const LigDev* d_lig,
-                           int n_atoms, const float* xs, int64_t N,
+                           int waves, const float* xs, int64_t N,
                            const double* w, double* terms, float* forces,
                            int lds_bytes, hipStream_t st) {
   if (N <= 0) return hipSuccess;
   const int blocks = grid_blocks(N, 1, 1 << 20);
-  BPMF_DISPATCH_C(g.C, {
-    if (n_atoms <= kWave)
-      hipLaunchKernelGGL((k_evaluate<C, 1>), dim3(blocks), dim3(kWave),
-                         lds_bytes, st, g, d_lig, xs, N, w, terms, forces);
-    else
-      hipLaunchKernelGGL((k_evaluate<C, 2>), dim3(blocks), dim3(kWave),
-                         lds_bytes, st, g, d_lig, xs, N, w, terms, forces);
-  });
+  BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
+    hipLaunchKernelGGL((k_evaluate<C, W>), dim3(blocks), dim3(W * kWave),
+                       lds_bytes, st, g, d_lig, xs, N, w, terms, forces);
+  }));
   return hipGetLastError();
 }
 
 hipError_t launch_recompute_comps(const GridDev& g, const LigDev* d_lig,
-                                  int n_atoms, int K, int lds_bytes,
+                                  int waves, int K, int lds_bytes,
                                   hipStream_t st) {
-  BPMF_DISPATCH_C(g.C, {
-    if (n_atoms <= kWave)
-      hipLaunchKernelGGL((k_recompute<C, 1>), dim3(K), dim3(kWave), lds_bytes,
-                         st, g, d_lig);
-    else
-      hipLaunchKernelGGL((k_recompute<C, 2>), dim3(K), dim3(kWave), lds_bytes,
-                         st, g, d_lig);
-  });
+  BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
+    hipLaunchKernelGGL((k_recompute<C, W>), dim3(K), dim3(W * kWave),
+                       lds_bytes, st, g, d_lig);
+  }));
   return hipGetLastError();
 }
 

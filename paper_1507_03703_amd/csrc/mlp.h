@@ -1,0 +1,78 @@
+// Learned pose proposal: network shape, parameter layout, device state and
+// launchers (mlp.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace bpmf {
+
+constexpr int kNFeat = 16, kNHid = 256, kNComp = 8, kNOut = kNComp * 13;
+constexpr int kFold = 3;  // preimages (theta + 2 pi m) n, m = -3..3
+constexpr float kSt0 = 0.02f, kSt1 = 3.0f;  // translation sigma range (A)
+constexpr float kSw0 = 0.02f, kSw1 = 1.5f;  // rotation sigma range (rad)
+
+// flat fp32 parameter vector: W1 (16x256) b1 W2 (256x256) b2 W3 (256x104) b3,
+// weights row-major [in][out]
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kNFeat * kNHid;
+constexpr int kOffW2 = kOffB1 + kNHid;
+constexpr int kOffB2 = kOffW2 + kNHid * kNHid;
+constexpr int kOffW3 = kOffB2 + kNHid;
+constexpr int kOffB3 = kOffW3 + kNHid * kNOut;
+constexpr int kNParams = kOffB3 + kNOut;
+
+enum Purpose2 : uint32_t { kPose = 4, kBatch = 5 };
+
+// Device state of one ligand's proposal.
+struct PropDev {
+  int frame[3];
+  int n_cond;
+  int4 cond[8];
+  unsigned long long* pose_acc;  // K
+  unsigned long long* pose_try;  // K
+  double* last_ln_alpha;         // K, ln alpha of each replica's last move
+};
+
+enum { kEpiStore = 0, kEpiSilu = 1, kEpiDsilu = 2 };
+
+// C[m, n] = sum_k A(m, k) B(k, n) (+ bias[n]); A(m, k) = A[m*sam + k*sak],
+// B(k, n) = B[k*sbk + n*sbn]; bf16 operands, fp32 accumulation.
+// kEpiSilu: Zout = acc + bias, C = silu(Zout).  kEpiDsilu: C = acc *
+// silu'(Zin).  Row stride of C, Zout, Zin: ldc.
+struct GemmArgs {
+  int M, N, K;
+  const float* A;
+  int64_t sam, sak;
+  const float* B;
+  int64_t sbk, sbn;
+  float* C;
+  int64_t ldc;
+  const float* bias;
+  int epi;
+  float* Zout;
+  const float* Zin;
+};
+
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t st);
+hipError_t launch_colsum(const float* X, int rows, int cols, int64_t ld,
+                         float* out, hipStream_t st);
+hipError_t launch_nll(const float* out, const float* pose, int B, float* dout,
+                      double* loss_part, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n,
+                       float lr, float b1, float b2, float eps, float c1,
+                       float c2, hipStream_t st);
+hipError_t launch_pose_features(const LigDev* lig, const PropDev* prop,
+                                const float* xs, int64_t N, float* feats,
+                                float* poses, hipStream_t st);
+hipError_t launch_pose_move(const GridDev& g, const LigDev* lig,
+                            const PropDev* prop, const float* out, int K,
+                            int waves, int lds, uint64_t seed,
+                            hipStream_t st);
+hipError_t launch_gather_batch(const float* feats, const float* poses,
+                               int64_t N, int B, uint64_t seed,
+                               uint64_t step, float* bf, float* bp,
+                               hipStream_t st);
+
+}  // namespace bpmf

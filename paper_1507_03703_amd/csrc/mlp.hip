@@ -1,0 +1,641 @@
+// Learned rigid-body pose proposal on gfx950: a conditional Gaussian-mixture
+// density q(t, omega | tau) from an MLP 16 -> 256 -> 256 -> 104 (SiLU), its
+// training (negative log-likelihood, Adam) and the independence
+// Metropolis-Hastings pose move it drives.  The paper's own pose move is a
+// random rotation about the centre of mass plus a Gaussian translation with
+// Metropolis acceptance (Sampling section); here the proposal is learned and
+// the acceptance carries the exact proposal density on SE(3).
+//
+// Dense layers run on the matrix cores: v_mfma_f32_16x16x32_bf16 with bf16
+// operands rounded from fp32 when they are staged in LDS and fp32
+// accumulation.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "device.h"
+#include "internal.h"
+#include "mlp.h"
+
+namespace bpmf {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// fp32 -> bf16 bits, round to nearest even (finite inputs); NaN stays NaN
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+constexpr int kTile = 64;   // output tile edge per workgroup
+constexpr int kKStep = 32;  // K per MFMA
+constexpr int kPad = 8;     // LDS row padding (bf16 elements)
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// C[m, n] = sum_k A(m, k) B(k, n) with epilogue (see GemmArgs).  A block of
+// 256 threads computes a 64 x 64 tile; wave (wm, wn) owns a 32 x 32 quarter
+// as 2 x 2 MFMA tiles of 16 x 16.  Operand layout of the 16x16x32 bf16 MFMA:
+// lane l supplies row (l % 16) of A and column (l % 16) of B, each with the
+// 8 consecutive k = 8 (l / 16) .. + 7; it receives D rows 4 (l / 16) .. + 3
+// of column l % 16.
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ __align__(16) unsigned short As[kTile][kKStep + kPad];
+  __shared__ __align__(16) unsigned short Bs[kTile][kKStep + kPad];  // [n][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < g.K; k0 += kKStep) {
+    // stage: 64 x 32 elements of A and of B, 8 per thread
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;       // 0 .. 2047
+      const int r = e >> 5, kk = e & 31;  // row/col of tile, k in step
+      const int m = m0 + r, n = n0 + r, k = k0 + kk;
+      float av = 0.f, bv = 0.f;
+      if (m < g.M && k < g.K) av = g.A[(int64_t)m * g.sam + (int64_t)k * g.sak];
+      if (n < g.N && k < g.K) bv = g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn];
+      As[r][kk] = bf16_bits(av);
+      Bs[r][kk] = bf16_bits(bv);
+    }
+    __syncthreads();
+    const int kg = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ar = wm * 32 + i * 16 + (lane & 15);
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[ar][kg]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int bc = wn * 32 + j * 16 + (lane & 15);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[bc][kg]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0,
+                                                            0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + q;
+        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        float v = acc[i][j][q];
+        const int64_t o = (int64_t)m * g.ldc + n;
+        if (g.bias) v += g.bias[n];
+        if (g.epi == kEpiSilu) {
+          g.Zout[o] = v;
+          g.C[o] = silu(v);
+        } else if (g.epi == kEpiDsilu) {
+          g.C[o] = v * dsilu(g.Zin[o]);
+        } else {
+          g.C[o] = v;
+        }
+      }
+}
+
+// column sums of X (rows x cols, row stride ld): out[c] = sum_r X[r, c];
+// fixed summation order
+__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ X,
+                                                int rows, int cols, int64_t ld,
+                                                float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int r = 0; r < rows; ++r) s += X[(int64_t)r * ld + c];
+  out[c] = (float)s;
+}
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// Mixture parameters of one output row (13 numbers per component).
+struct Mix {
+  float lw[kNComp];           // log weights (normalised)
+  float mt[kNComp][3], mw[kNComp][3], st[kNComp][3], sw[kNComp][3];
+};
+
+__device__ __forceinline__ void mixture_of(const float* o, Mix& p) {
+  float mx = -INFINITY;
+  for (int j = 0; j < kNComp; ++j) mx = fmaxf(mx, o[13 * j]);
+  float s = 0.f;
+  for (int j = 0; j < kNComp; ++j) s += expf(o[13 * j] - mx);
+  const float lse = mx + logf(s);
+  for (int j = 0; j < kNComp; ++j) {
+    const float* r = o + 13 * j;
+    p.lw[j] = r[0] - lse;
+    for (int a = 0; a < 3; ++a) {
+      p.mt[j][a] = r[1 + a];
+      p.mw[j][a] = (float)M_PI * tanhf(r[4 + a]);
+      p.st[j][a] = kSt0 + (kSt1 - kSt0) * sigm(r[7 + a]);
+      p.sw[j][a] = kSw0 + (kSw1 - kSw0) * sigm(r[10 + a]);
+    }
+  }
+}
+
+// negative log-likelihood of (t, w) and d loss / d out (scaled by 1/B)
+__global__ __launch_bounds__(256) void k_nll(const float* __restrict__ out,
+                                             const float* __restrict__ pose,
+                                             int B, float inv_b,
+                                             float* __restrict__ dout,
+                                             double* __restrict__ loss_part) {
+  __shared__ double red[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double li = 0.0;
+  if (i < B) {
+    const float* o = out + (int64_t)i * kNOut;
+    const float* ps = pose + (int64_t)i * 6;
+    Mix p;
+    mixture_of(o, p);
+    float a[kNComp], zt[kNComp][3], zw[kNComp][3];
+    float mx = -INFINITY;
+    for (int j = 0; j < kNComp; ++j) {
+      float lg = p.lw[j] - 3.0f * logf(2.0f * (float)M_PI);
+      for (int d = 0; d < 3; ++d) {
+        zt[j][d] = (ps[d] - p.mt[j][d]) / p.st[j][d];
+        zw[j][d] = (ps[3 + d] - p.mw[j][d]) / p.sw[j][d];
+        lg += -0.5f * (zt[j][d] * zt[j][d] + zw[j][d] * zw[j][d]) -
+              logf(p.st[j][d]) - logf(p.sw[j][d]);
+      }
+      a[j] = lg;
+      mx = fmaxf(mx, lg);
+    }
+    float s = 0.f;
+    for (int j = 0; j < kNComp; ++j) s += expf(a[j] - mx);
+    const float ll = mx + logf(s);
+    li = -(double)ll;
+    float* d = dout + (int64_t)i * kNOut;
+    for (int j = 0; j < kNComp; ++j) {
+      const float r = expf(a[j] - ll);
+      const float pi = expf(p.lw[j]);
+      const float* oj = o + 13 * j;
+      float* dj = d + 13 * j;
+      dj[0] = -(r - pi) * inv_b;
+      for (int q = 0; q < 3; ++q) {
+        dj[1 + q] = -r * zt[j][q] / p.st[j][q] * inv_b;
+        const float th = tanhf(oj[4 + q]);
+        dj[4 + q] = -r * zw[j][q] / p.sw[j][q] * (float)M_PI *
+                    (1.f - th * th) * inv_b;
+        float sg = sigm(oj[7 + q]);
+        dj[7 + q] = -r * (zt[j][q] * zt[j][q] - 1.f) / p.st[j][q] *
+                    (kSt1 - kSt0) * sg * (1.f - sg) * inv_b;
+        sg = sigm(oj[10 + q]);
+        dj[10 + q] = -r * (zw[j][q] * zw[j][q] - 1.f) / p.sw[j][q] *
+                     (kSw1 - kSw0) * sg * (1.f - sg) * inv_b;
+      }
+    }
+  }
+  red[threadIdx.x] = li;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// Adam (Kingma & Ba) on fp32 master parameters
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p,
+                                              const float* __restrict__ g,
+                                              float* __restrict__ m,
+                                              float* __restrict__ v, int n,
+                                              float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ----------------------------------------------------------------------------
+// pose of a configuration: t = COM - c0, R = body frame, omega = log R,
+// features = sin/cos of the conditioning torsions
+// ----------------------------------------------------------------------------
+struct Frame {
+  float R[3][3];  // columns e1, e2, e3
+};
+
+__device__ void body_frame(const float* x, const int* fa, Frame& F) {
+  float e1[3], v[3], e2[3];
+  for (int a = 0; a < 3; ++a) {
+    e1[a] = x[3 * fa[1] + a] - x[3 * fa[0] + a];
+    v[a] = x[3 * fa[2] + a] - x[3 * fa[0] + a];
+  }
+  float l = rsqrtf(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  for (int a = 0; a < 3; ++a) e1[a] *= l;
+  const float pr = v[0] * e1[0] + v[1] * e1[1] + v[2] * e1[2];
+  for (int a = 0; a < 3; ++a) e2[a] = v[a] - pr * e1[a];
+  l = rsqrtf(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+  for (int a = 0; a < 3; ++a) e2[a] *= l;
+  const float e3[3] = {e1[1] * e2[2] - e1[2] * e2[1],
+                       e1[2] * e2[0] - e1[0] * e2[2],
+                       e1[0] * e2[1] - e1[1] * e2[0]};
+  for (int a = 0; a < 3; ++a) {
+    F.R[a][0] = e1[a];
+    F.R[a][1] = e2[a];
+    F.R[a][2] = e3[a];
+  }
+}
+
+// rotation vector of R (double), |omega| in [0, pi]
+__device__ void log_rot(const double R[3][3], double w[3]) {
+  double c = (R[0][0] + R[1][1] + R[2][2] - 1.0) * 0.5;
+  c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+  const double th = acos(c);
+  const double v[3] = {R[2][1] - R[1][2], R[0][2] - R[2][0], R[1][0] - R[0][1]};
+  if (th < 1e-6) {
+    for (int a = 0; a < 3; ++a) w[a] = 0.5 * v[a];
+    return;
+  }
+  if (M_PI - th < 1e-4) {
+    double B[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) B[a][b] = 0.5 * (R[a][b] + (a == b ? 1.0 : 0.0));
+    int k = 0;
+    if (B[1][1] > B[k][k]) k = 1;
+    if (B[2][2] > B[k][k]) k = 2;
+    double n[3] = {B[0][k], B[1][k], B[2][k]};
+    const double dn = n[0] * v[0] + n[1] * v[1] + n[2] * v[2];
+    const double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double sgn = dn < 0 ? -1.0 : 1.0;
+    for (int a = 0; a < 3; ++a) w[a] = sgn * th * n[a] / ln;
+    return;
+  }
+  const double f = th / (2.0 * sin(th));
+  for (int a = 0; a < 3; ++a) w[a] = f * v[a];
+}
+
+__device__ void rodrigues(const double w[3], double R[3][3]) {
+  const double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  const double K[3][3] = {{0, -w[2], w[1]}, {w[2], 0, -w[0]}, {-w[1], w[0], 0}};
+  double a, b;
+  if (th < 1e-8) {
+    a = 1.0;
+    b = 0.5;
+  } else {
+    a = sin(th) / th;
+    b = (1.0 - cos(th)) / (th * th);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double kk = 0.0;
+      for (int q = 0; q < 3; ++q) kk += K[i][q] * K[q][j];
+      R[i][j] = (i == j ? 1.0 : 0.0) + a * K[i][j] + b * kk;
+    }
+}
+
+__device__ float dihedral_angle(const float* x, int4 q) {
+  float b1[3], b2[3], b3[3];
+  for (int a = 0; a < 3; ++a) {
+    b1[a] = x[3 * q.y + a] - x[3 * q.x + a];
+    b2[a] = x[3 * q.z + a] - x[3 * q.y + a];
+    b3[a] = x[3 * q.w + a] - x[3 * q.z + a];
+  }
+  const float n1[3] = {b1[1] * b2[2] - b1[2] * b2[1], b1[2] * b2[0] - b1[0] * b2[2],
+                       b1[0] * b2[1] - b1[1] * b2[0]};
+  const float n2[3] = {b2[1] * b3[2] - b2[2] * b3[1], b2[2] * b3[0] - b2[0] * b3[2],
+                       b2[0] * b3[1] - b2[1] * b3[0]};
+  const float lb2 = sqrtf(b2[0] * b2[0] + b2[1] * b2[1] + b2[2] * b2[2]);
+  const float y = lb2 * (b1[0] * n2[0] + b1[1] * n2[1] + b1[2] * n2[2]);
+  const float xx = n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2];
+  return atan2f(y, xx);
+}
+
+// one thread per configuration: pose (t, omega) and features
+__global__ __launch_bounds__(128) void k_pose_features(
+    const LigDev* __restrict__ lig, const PropDev* __restrict__ prop,
+    const float* __restrict__ xs, int64_t N, float* __restrict__ feats,
+    float* __restrict__ poses) {
+  const LigDev& L = *lig;
+  const PropDev& P = *prop;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int n = L.n;
+  const float* x = xs + i * n * 3;
+  double c[3] = {0, 0, 0}, M = 0;
+  for (int a = 0; a < n; ++a) {
+    const double m = L.mass[a];
+    M += m;
+    for (int d = 0; d < 3; ++d) c[d] += m * x[3 * a + d];
+  }
+  Frame F;
+  body_frame(x, P.frame, F);
+  double R[3][3], w[3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) R[a][b] = F.R[a][b];
+  log_rot(R, w);
+  float* po = poses + i * 6;
+  for (int d = 0; d < 3; ++d) {
+    po[d] = (float)(c[d] / M - L.site[d]);
+    po[3 + d] = (float)w[d];
+  }
+  float* fo = feats + i * kNFeat;
+  for (int q = 0; q < kNFeat; ++q) fo[q] = 0.f;
+  for (int q = 0; q < P.n_cond; ++q) {
+    const float phi = dihedral_angle(x, P.cond[q]);
+    float s, cs;
+    sincosf(phi, &s, &cs);
+    fo[2 * q] = s;
+    fo[2 * q + 1] = cs;
+  }
+}
+
+// ln q(t, R) on SE(3) (Lebesgue x Haar written as J d^3 omega) of one mixture,
+// summing the preimages (theta + 2 pi m) n, m = -kFold .. kFold
+__device__ double log_q_se3(const Mix& p, const double t[3],
+                            const double w0[3]) {
+  const double th = sqrt(w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2]);
+  double lt[kNComp];
+  for (int j = 0; j < kNComp; ++j) {
+    double s = p.lw[j] - 3.0 * log(2.0 * M_PI);
+    for (int d = 0; d < 3; ++d) {
+      const double z = (t[d] - p.mt[j][d]) / p.st[j][d];
+      s += -0.5 * z * z - log((double)p.st[j][d]) - log((double)p.sw[j][d]);
+    }
+    lt[j] = s;
+  }
+  double terms[(2 * kFold + 1) * kNComp];
+  int nt = 0;
+  double mx = -INFINITY;
+  if (th < 1e-9) {
+    for (int j = 0; j < kNComp; ++j) {
+      double s = lt[j];
+      for (int d = 0; d < 3; ++d) {
+        const double z = (0.0 - p.mw[j][d]) / p.sw[j][d];
+        s += -0.5 * z * z;
+      }
+      terms[nt++] = s;
+      mx = fmax(mx, s);
+    }
+  } else {
+    const double lj = log(2.0 * (1.0 - cos(th)));
+    for (int m = -kFold; m <= kFold; ++m) {
+      const double a = th + 2.0 * M_PI * m;
+      const double la = 2.0 * log(fabs(a)) - lj;
+      for (int j = 0; j < kNComp; ++j) {
+        double s = lt[j] + la;
+        for (int d = 0; d < 3; ++d) {
+          const double z = (a * w0[d] / th - p.mw[j][d]) / p.sw[j][d];
+          s += -0.5 * z * z;
+        }
+        terms[nt++] = s;
+        mx = fmax(mx, s);
+      }
+    }
+  }
+  double sum = 0.0;
+  for (int q = 0; q < nt; ++q) sum += exp(terms[q] - mx);
+  return mx + log(sum);
+}
+
+// Independence MH pose move, one workgroup of W waves per replica.
+template <int C, int W>
+__global__ __launch_bounds__(W * kWave) void k_pose_move(
+    GridDev g, const LigDev* __restrict__ lig, const PropDev* __restrict__ prop,
+    const float* __restrict__ out, uint64_t seed) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float sR[9], st[3], scom[3];
+  __shared__ int s_ok;
+  const LigDev L = *lig;
+  const PropDev& P = *prop;
+  const int tid = threadIdx.x;
+  const int r = blockIdx.x;
+  const int n = L.n;
+  const unsigned long long s = *L.counter;
+  const int k = L.state_of_replica[r];
+  const float* xr = L.x + (size_t)r * n * 3;
+  // current pose, proposal and the proposal-density ratio (thread 0, double)
+  double lq_ratio = 0.0;
+  if (tid == 0) {
+    double c[3] = {0, 0, 0}, M = 0;
+    for (int a = 0; a < n; ++a) {
+      M += L.mass[a];
+      for (int d = 0; d < 3; ++d) c[d] += (double)L.mass[a] * xr[3 * a + d];
+    }
+    Frame F;
+    body_frame(xr, P.frame, F);
+    double R0[3][3], w0[3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) R0[a][b] = F.R[a][b];
+    log_rot(R0, w0);
+    double t0[3];
+    for (int d = 0; d < 3; ++d) {
+      c[d] /= M;
+      t0[d] = c[d] - L.site[d];
+    }
+    Mix p;
+    mixture_of(out + (size_t)r * kNOut, p);
+    // component by inverse CDF, then (t, omega) by Gaussian draws
+    const U4 o0 = draw(seed, 0u, L.id, r, s, kPose);
+    const double u = u01d(o0.x);
+    double cum[kNComp], tot = 0.0;
+    for (int j = 0; j < kNComp; ++j) {
+      tot += exp((double)p.lw[j]);
+      cum[j] = tot;
+    }
+    int j = 0;
+    while (j < kNComp - 1 && cum[j] < u * tot) ++j;
+    float z[6];
+    normals3(draw(seed, 1u, L.id, r, s, kPose), z[0], z[1], z[2]);
+    normals3(draw(seed, 2u, L.id, r, s, kPose), z[3], z[4], z[5]);
+    double t1[3], w1[3];
+    for (int d = 0; d < 3; ++d) {
+      t1[d] = (double)p.mt[j][d] + (double)p.st[j][d] * z[d];
+      w1[d] = (double)p.mw[j][d] + (double)p.sw[j][d] * z[3 + d];
+    }
+    double R1[3][3];
+    rodrigues(w1, R1);
+    double w1p[3];
+    log_rot(R1, w1p);  // principal rotation vector of the proposal
+    lq_ratio = log_q_se3(p, t0, w0) - log_q_se3(p, t1, w1p);
+    // x'_i = c0 + t' + R' R0^T (x_i - c): the rotation applied is R' R0^T
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double v = 0.0;
+        for (int q = 0; q < 3; ++q) v += R1[a][q] * R0[b][q];
+        sR[3 * a + b] = (float)v;
+      }
+    for (int d = 0; d < 3; ++d) {
+      st[d] = (float)(L.site[d] + t1[d]);
+      scom[d] = (float)c[d];
+    }
+    s_ok = isfinite(lq_ratio) ? 1 : 0;
+  }
+  __syncthreads();
+  Shared sh;
+  {
+    sh.pos = reinterpret_cast<float4*>(smem);
+    sh.red = reinterpret_cast<double*>(smem + 16 * kWave * W);
+    sh.com = reinterpret_cast<float*>(smem + 16 * kWave * W + 8 * W * kRedMax);
+    const int slot0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
+    sh.sl = Slots{reinterpret_cast<float4*>(smem + slot0)};
+    stage_topology(L, smem + slot0, sh, tid, W * kWave);
+    __syncthreads();
+  }
+  const bool owner = tid < n;
+  float x2[3] = {0.f, 0.f, 0.f}, f[3];
+  if (owner) {
+    float y[3];
+    for (int d = 0; d < 3; ++d) y[d] = xr[3 * tid + d] - scom[d];
+    for (int a = 0; a < 3; ++a)
+      x2[a] = st[a] + sR[3 * a] * y[0] + sR[3 * a + 1] * y[1] + sR[3 * a + 2] * y[2];
+  }
+  const float m = owner ? L.mass[tid] : 0.f;
+  float sc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) sc[c] = owner ? L.scale[tid * C + c] : 0.f;
+  float w[C];
+  for (int c = 0; c < C; ++c) w[c] = L.wf[k * C + c];
+  double t1e[6 + C];
+  eval_block<C, W, false, true>(g, L, w, x2, m, sc, f, t1e, 0.f, 0.f, sh, tid);
+  double E1 = t1e[0] + t1e[1] + t1e[2] + t1e[3], E0 = 0.0;
+  const double* cp = L.comps + (size_t)r * (1 + C);
+  E0 = cp[0];
+  for (int c = 0; c < C; ++c) {
+    E1 += L.wd[k * C + c] * t1e[4 + c];
+    E0 += L.wd[k * C + c] * cp[1 + c];
+  }
+  __shared__ int s_acc;
+  if (tid == 0) {
+    const double ln_a = -L.beta[k] * (E1 - E0) + lq_ratio;
+    const double lnu = log(u01d(draw(seed, 3u, L.id, r, s, kPose).x));
+    s_acc = (s_ok && isfinite(ln_a) && lnu < ln_a) ? 1 : 0;
+    P.last_ln_alpha[r] = ln_a;
+    atomicAdd(&P.pose_try[k], 1ull);
+    if (s_acc) atomicAdd(&P.pose_acc[k], 1ull);
+  }
+  __syncthreads();
+  if (s_acc) {
+    if (owner)
+      for (int d = 0; d < 3; ++d) L.x[(size_t)r * n * 3 + 3 * tid + d] = x2[d];
+    if (tid == 0) {
+      double* cw = L.comps + (size_t)r * (1 + C);
+      cw[0] = t1e[0] + t1e[1] + t1e[2] + t1e[3];
+      for (int c = 0; c < C; ++c) cw[1 + c] = t1e[4 + c];
+    }
+  }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+  dim3 grid((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* X, int rows, int cols, int64_t ld,
+                         float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3((cols + 255) / 256), dim3(256), 0, st, X,
+                     rows, cols, ld, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nll(const float* out, const float* pose, int B,
+                      float* dout, double* loss_part, hipStream_t st) {
+  hipLaunchKernelGGL(k_nll, dim3((B + 255) / 256), dim3(256), 0, st, out,
+                     pose, B, 1.0f / (float)B, dout, loss_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n,
+                       float lr, float b1, float b2, float eps, float c1,
+                       float c2, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, p, g, m,
+                     v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_features(const LigDev* lig, const PropDev* prop,
+                                const float* xs, int64_t N, float* feats,
+                                float* poses, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pose_features, dim3((unsigned)((N + 127) / 128)),
+                     dim3(128), 0, st, lig, prop, xs, N, feats, poses);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_move(const GridDev& g, const LigDev* lig,
+                            const PropDev* prop, const float* out, int K,
+                            int waves, int lds, uint64_t seed,
+                            hipStream_t st) {
+  switch (g.C) {
+    case 3:
+      if (waves == 1)
+        hipLaunchKernelGGL((k_pose_move<3, 1>), dim3(K), dim3(64), lds, st, g,
+                           lig, prop, out, seed);
+      else
+        hipLaunchKernelGGL((k_pose_move<3, 2>), dim3(K), dim3(128), lds, st, g,
+                           lig, prop, out, seed);
+      break;
+    case 5:
+      if (waves == 1)
+        hipLaunchKernelGGL((k_pose_move<5, 1>), dim3(K), dim3(64), lds, st, g,
+                           lig, prop, out, seed);
+      else
+        hipLaunchKernelGGL((k_pose_move<5, 2>), dim3(K), dim3(128), lds, st, g,
+                           lig, prop, out, seed);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace bpmf
+
+namespace bpmf {
+namespace {
+// minibatch gather: row i of step s is row philox(s, i) mod N (sampling with
+// replacement)
+__global__ __launch_bounds__(256) void k_gather(
+    const float* __restrict__ feats, const float* __restrict__ poses,
+    int64_t N, int B, uint64_t seed, uint64_t step, float* __restrict__ bf,
+    float* __restrict__ bp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const U4 o = philox4x32_10((uint32_t)i, (uint32_t)(step >> 32),
+                             (uint32_t)step, kBatch, (uint32_t)seed,
+                             (uint32_t)(seed >> 32));
+  const uint64_t r = ((uint64_t)o.x << 32) | o.y;
+  const int64_t j = (int64_t)(r % (uint64_t)N);
+  for (int q = 0; q < kNFeat; ++q) bf[(int64_t)i * kNFeat + q] = feats[j * kNFeat + q];
+  for (int q = 0; q < 6; ++q) bp[(int64_t)i * 6 + q] = poses[j * 6 + q];
+}
+}  // namespace
+
+hipError_t launch_gather_batch(const float* feats, const float* poses,
+                               int64_t N, int B, uint64_t seed,
+                               uint64_t step, float* bf, float* bp,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3((B + 255) / 256), dim3(256), 0, st, feats,
+                     poses, N, B, seed, step, bf, bp);
+  return hipGetLastError();
+}
+}  // namespace bpmf

@@ -103,9 +103,10 @@ def _configs(lig, rng, N, sigma=0.3, shift=0.0):
     return x.astype(np.float32)
 
 
-def _check_evaluate(g, lig, xs, w, label):
-    print_case("evaluate", label, lig.n_atoms, len(xs))
+def _check_evaluate(g, lig, xs, w, label, waves=0):
+    print_case("evaluate", label, lig.n_atoms, len(xs), "waves", waves)
     ctx, (lid,) = make_context(g, [lig], seed=5)
+    ctx.set_waves(waves)
     terms, F = ctx.evaluate(lid, dev(xs, torch.float32), dev(w, torch.float64))
     terms, F = terms.cpu().numpy(), F.cpu().numpy().astype(np.float64)
     og, ol = oracle.OGrid(g), oracle.OLigand(lig)
@@ -124,13 +125,14 @@ def _check_evaluate(g, lig, xs, w, label):
     ctx.close()
 
 
-def test_evaluate_config1_ligand():
+@pytest.mark.parametrize("waves", [1, 2, 4])
+def test_evaluate_config1_ligand(waves):
     system = synth.make_system(1)
     lig = system.ligands[0]
     rng = np.random.default_rng(1)
     xs = _configs(lig, rng, 96)
     w = rng.uniform(0, 1, (96, 3))
-    _check_evaluate(system.grid, lig, xs, w, "c1")
+    _check_evaluate(system.grid, lig, xs, w, "c1", waves=waves)
 
 
 def test_evaluate_restraint_active_and_outside_grid():
@@ -153,6 +155,7 @@ def test_evaluate_two_atoms_per_lane():
     xs = _configs(lig, rng, 40, 0.2)
     w = rng.uniform(0, 1, (40, 3))
     _check_evaluate(system.grid, lig, xs, w, "100 atoms")
+    _check_evaluate(system.grid, lig, xs, w, "100 atoms", waves=4)
 
 
 def test_evaluate_single_atom_and_five_channels():

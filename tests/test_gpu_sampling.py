@@ -50,11 +50,14 @@ def _exchange_margins(ol, comps, rep_of_state, sweep, seed, lig):
     return np.array(out) if out else np.array([np.inf])
 
 
-def _lockstep(g, lig, seed, n_sweeps, nleap, label, x0=None):
-    print_case("lockstep", label)
+def _lockstep(g, lig, seed, n_sweeps, nleap, label, x0=None, waves=0):
+    print_case("lockstep", label, "waves", waves)
     if x0 is not None:
         lig.x0 = x0.astype(np.float32)
     ctx, (lid,) = make_context(g, [lig], seed=seed)
+    ctx.set_waves(waves)
+    if waves:
+        assert ctx.get_waves(lid) == max(waves, -(-lig.n_atoms // 64))
     og, ol = oracle.OGrid(g), oracle.OLigand(lig)
     s = oracle.Sampler(og, ol, seed=seed, lig_id=lid, x0=lig.x0)
     n_checked = 0
@@ -91,10 +94,11 @@ def _lockstep(g, lig, seed, n_sweeps, nleap, label, x0=None):
     return n_checked
 
 
-def test_lockstep_config1():
+@pytest.mark.parametrize("waves", [0, 1, 2, 4])
+def test_lockstep_config1(waves):
     system = synth.make_system(1)
     n = _lockstep(system.grid, system.ligands[0], system.seed, 6,
-                  system.n_leapfrog, "c1")
+                  system.n_leapfrog, "c1", waves=waves)
     assert n >= 3
 
 
@@ -107,11 +111,12 @@ def test_lockstep_replicas_outside_grid_and_restrained():
     _lockstep(system.grid, lig, 11, 4, 10, "outside", x0=x0)
 
 
-def test_lockstep_two_atoms_per_lane():
+@pytest.mark.parametrize("waves", [2, 4])
+def test_lockstep_ligand_wider_than_a_wavefront(waves):
     rng = np.random.default_rng(4)
     lig = synth.make_ligand(rng, 90, 4, box=9.0)
     system = synth.make_system(1)
-    _lockstep(system.grid, lig, 21, 3, 8, "90 atoms")
+    _lockstep(system.grid, lig, 21, 3, 8, "90 atoms", waves=waves)
 
 
 def test_lockstep_five_channels():
