@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 R_GAS = 8.314462618e-3  # kJ/(mol K)
 
-P_MOMENTA, P_ACCEPT, P_EXCHANGE = 1, 2, 3
+P_MOMENTA, P_ACCEPT, P_EXCHANGE, P_POSE = 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -94,6 +94,8 @@ def lib():
         L.ora_components.argtypes = [vp, vp, C.c_int64, dp, dp, dp]
         L.ora_grid_points.argtypes = [vp, C.c_int64, dp, dp, dp, dp, dp]
         L.ora_energy_batch.argtypes = [vp, vp, C.c_int64, dp, dp, dp, dp, dp]
+        L.ora_normals3.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int,
+                                   C.c_uint64, C.c_uint32, dp]
         L.ora_dihedral.argtypes = [dp, dp, dp, dp]
         L.ora_dihedral.restype = C.c_double
         L.ora_angle.argtypes = [dp, dp, dp]
@@ -181,6 +183,13 @@ def philox(ctr, key):
 
 def uniform(seed, index, lig, rep, sweep, purpose):
     return lib().ora_uniform(seed, index, lig, rep, sweep, purpose)
+
+
+def normals3(seed, index, lig, rep, sweep, purpose):
+    z = np.zeros(3)
+    lib().ora_normals3(seed, index, lig, rep, sweep, purpose,
+                       _p(z, C.c_double))
+    return z
 
 
 def interp(og: OGrid, p):

@@ -61,23 +61,29 @@ def rodrigues(w):
 
 
 def log_rotation(R):
-    """Rotation vector omega with |omega| in [0, pi] and exp(omega) = R."""
+    """Rotation vector omega with |omega| in [0, pi] and exp(omega) = R.
+
+    theta = atan2(|v|/2, (tr R - 1)/2) with v the axial vector of R - R^T
+    (|v| = 2 sin theta), axis v/|v|: well conditioned up to theta -> pi,
+    where the axis comes from the symmetric part (R + I)/2 = n n^T."""
     R = np.asarray(R, np.float64)
     c = (np.trace(R) - 1.0) / 2.0
-    c = min(1.0, max(-1.0, c))
-    th = math.acos(c)
     v = np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
-    if th < 1e-6:
-        return 0.5 * v
-    if math.pi - th < 1e-4:
-        # axis from the symmetric part: R = 2 n n^T - I at theta = pi
-        B = (R + np.eye(3)) / 2.0
-        k = int(np.argmax(np.diag(B)))
-        n = B[:, k] / math.sqrt(max(B[k, k], 1e-300))
-        if np.dot(n, v) < 0:
-            n = -n
-        return th * n / np.linalg.norm(n)
-    return th / (2.0 * math.sin(th)) * v
+    s2 = np.linalg.norm(v)            # 2 sin theta
+    th = math.atan2(0.5 * s2, c)
+    if s2 < 1e-12:
+        if c > 0:
+            return 0.5 * v
+    elif s2 > 1e-4 or c > 0:
+        return th * v / s2
+    # theta within ~5e-5 of pi: axis from the symmetric part
+    B = (R + R.T) / 4.0 + np.eye(3) / 2.0
+    k = int(np.argmax(np.diag(B)))
+    n = B[:, k] / math.sqrt(max(B[k, k], 1e-300))
+    n /= np.linalg.norm(n)
+    if np.dot(n, v) < 0:
+        n = -n
+    return th * n
 
 
 # --------------------------------------------------------------------------

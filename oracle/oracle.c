@@ -582,3 +582,12 @@ void ora_energy_batch(const ora_grid* g, const ora_ligand* L, int64_t N,
                terms + (size_t)s * (4 + nc), mags + (size_t)s * (4 + nc),
                F + (size_t)s * n * 3);
 }
+
+/* three standard normals from the counter-based stream (Box-Muller), the
+ * draw the samplers use for any purpose */
+void ora_normals3(uint64_t seed, uint32_t index, int lig, int rep,
+                  uint64_t sweep, uint32_t purpose, double* z) {
+  uint32_t o[4];
+  draw(seed, index, lig, rep, sweep, purpose, o);
+  normals3(o, z);
+}

@@ -259,32 +259,35 @@ __device__ void body_frame(const float* x, const int* fa, Frame& F) {
   }
 }
 
-// rotation vector of R (double), |omega| in [0, pi]
+// rotation vector of R (double), |omega| in [0, pi]: theta from
+// atan2(|v|/2, (tr R - 1)/2) with v the axial vector of R - R^T, axis
+// v/|v| (well conditioned up to theta -> pi); within ~5e-5 of pi the axis
+// comes from the symmetric part (R + R^T)/4 + I/2 = n n^T
 __device__ void log_rot(const double R[3][3], double w[3]) {
-  double c = (R[0][0] + R[1][1] + R[2][2] - 1.0) * 0.5;
-  c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-  const double th = acos(c);
+  const double c = (R[0][0] + R[1][1] + R[2][2] - 1.0) * 0.5;
   const double v[3] = {R[2][1] - R[1][2], R[0][2] - R[2][0], R[1][0] - R[0][1]};
-  if (th < 1e-6) {
+  const double s2 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double th = atan2(0.5 * s2, c);
+  if (s2 < 1e-12 && c > 0) {
     for (int a = 0; a < 3; ++a) w[a] = 0.5 * v[a];
     return;
   }
-  if (M_PI - th < 1e-4) {
-    double B[3][3];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) B[a][b] = 0.5 * (R[a][b] + (a == b ? 1.0 : 0.0));
-    int k = 0;
-    if (B[1][1] > B[k][k]) k = 1;
-    if (B[2][2] > B[k][k]) k = 2;
-    double n[3] = {B[0][k], B[1][k], B[2][k]};
-    const double dn = n[0] * v[0] + n[1] * v[1] + n[2] * v[2];
-    const double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    const double sgn = dn < 0 ? -1.0 : 1.0;
-    for (int a = 0; a < 3; ++a) w[a] = sgn * th * n[a] / ln;
+  if (s2 >= 1e-12 && (s2 > 1e-4 || c > 0)) {
+    for (int a = 0; a < 3; ++a) w[a] = th * v[a] / s2;
     return;
   }
-  const double f = th / (2.0 * sin(th));
-  for (int a = 0; a < 3; ++a) w[a] = f * v[a];
+  double B[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      B[a][b] = 0.25 * (R[a][b] + R[b][a]) + (a == b ? 0.5 : 0.0);
+  int k = 0;
+  if (B[1][1] > B[k][k]) k = 1;
+  if (B[2][2] > B[k][k]) k = 2;
+  double n[3] = {B[0][k], B[1][k], B[2][k]};
+  const double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  const double dn = n[0] * v[0] + n[1] * v[1] + n[2] * v[2];
+  const double sgn = dn < 0 ? -1.0 : 1.0;
+  for (int a = 0; a < 3; ++a) w[a] = sgn * th * n[a] / ln;
 }
 
 __device__ void rodrigues(const double w[3], double R[3][3]) {

@@ -1,0 +1,217 @@
+"""GPU parity of the learned pose proposal against the FP64 oracle: bf16
+MFMA forward pass, backward pass (gradients), pose features, and the
+independence Metropolis-Hastings pose move; plus training on poses sampled
+by plain HMC.
+
+Tolerances: network outputs and gradients relative L2 <= 2e-2 and cosine
+>= 0.999 (bf16 operands, fp32 accumulation, against float64 with the same
+bf16-valued weights); poses 1e-4; the pose move's ln alpha within 1e-3 of
+the oracle (2e-2 + 1e-4 |ln alpha|: float32 energies and rotations) given
+the GPU's network outputs, identical decisions where the margin
+|ln u - ln alpha| exceeds 5e-2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, make_context, print_case, require_gpu, torch
+from oracle import learned as Lr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def bf16(a):
+    """Round float64/float32 values to bfloat16 (nearest even)."""
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def flat(p):
+    return np.concatenate([p[k].reshape(-1) for k in
+                           ("W1", "b1", "W2", "b2", "W3", "b3")]).astype(
+                               np.float32)
+
+
+def unflat(v):
+    shapes = [("W1", (16, 256)), ("b1", (256,)), ("W2", (256, 256)),
+              ("b2", (256,)), ("W3", (256, 104)), ("b3", (104,))]
+    out, o = {}, 0
+    for k, s in shapes:
+        n = int(np.prod(s))
+        out[k] = np.asarray(v[o:o + n], np.float64).reshape(s)
+        o += n
+    return out
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def cosine(a, b):
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+def _setup(seed=0, K=8):
+    rng = np.random.default_rng(seed)
+    system = synth.make_system(1)
+    lig = system.ligands[0]
+    p = Lr.init_weights(rng)
+    for k in p:
+        p[k] = p[k] + 0.05 * rng.normal(size=p[k].shape)
+    ctx, (lid,) = make_context(system.grid, [lig], seed=system.seed)
+    cond = lig.tors[lig.cond_tors]
+    ctx.proposal_setup(lid, lig.frame_atoms, cond, flat(p))
+    return rng, system, lig, p, ctx, lid, cond
+
+
+def test_forward_matches_oracle():
+    print_case("mlp forward")
+    rng, system, lig, p, ctx, lid, _ = _setup(1)
+    B = 300
+    f = rng.uniform(-1, 1, (B, 16)).astype(np.float32)
+    out = ctx.proposal_forward(lid, dev(f, torch.float32)).cpu().numpy()
+    pb = {k: bf16(v) for k, v in p.items()}
+    ref, _ = Lr.forward(pb, f.astype(np.float64))
+    assert rel_l2(out, ref) < 2e-2, rel_l2(out, ref)
+    assert cosine(out.ravel(), ref.ravel()) > 0.999
+    ctx.close()
+
+
+def test_gradients_match_oracle():
+    print_case("mlp gradients")
+    rng, system, lig, p, ctx, lid, _ = _setup(2)
+    B = 512
+    f = rng.uniform(-1, 1, (B, 16)).astype(np.float32)
+    t = rng.normal(scale=1.0, size=(B, 3))
+    w = rng.normal(scale=0.8, size=(B, 3))
+    poses = np.concatenate([t, w], 1).astype(np.float32)
+    g, loss = ctx.proposal_grad(lid, dev(f, torch.float32),
+                                dev(poses, torch.float32))
+    g = unflat(g.cpu().numpy())
+    pb = {k: bf16(v) for k, v in p.items()}
+    loss64, g64, _ = Lr.nll_grad(pb, f.astype(np.float64),
+                                 poses[:, :3].astype(np.float64),
+                                 poses[:, 3:].astype(np.float64))
+    assert abs(loss - loss64) < 1e-2 * abs(loss64)
+    for k in g64:
+        a, b = g[k].ravel(), g64[k].ravel()
+        assert rel_l2(a, b) < 2e-2, (k, rel_l2(a, b))
+        assert cosine(a, b) > 0.999, (k, cosine(a, b))
+    ctx.close()
+
+
+def test_pose_features_match_oracle():
+    print_case("pose features")
+    rng, system, lig, p, ctx, lid, cond = _setup(3)
+    from scipy.spatial.transform import Rotation
+    N = 200
+    xs = []
+    for i in range(N):
+        Q = Rotation.random(random_state=i).as_matrix()
+        x = lig.x0[0].astype(np.float64) @ Q.T + rng.normal(scale=1.5,
+                                                             size=3)
+        x += rng.normal(scale=0.1, size=x.shape)
+        xs.append(x)
+    xs = np.array(xs, np.float32)
+    f, po = ctx.pose_features(lid, dev(xs, torch.float32))
+    f, po = f.cpu().numpy(), po.cpu().numpy()
+    for i in range(N):
+        x = xs[i].astype(np.float64)
+        t, R, _ = Lr.pose(x, lig.mass, lig.frame_atoms, lig.site_center)
+        assert np.allclose(po[i, :3], t, atol=1e-4)
+        # compare rotations (the vector is ambiguous at |omega| = pi)
+        assert np.allclose(Lr.rodrigues(po[i, 3:]), R, atol=2e-4)
+        assert np.allclose(f[i], Lr.features(x, cond), atol=2e-5)
+    ctx.close()
+
+
+def test_pose_move_matches_oracle():
+    print_case("pose move")
+    rng, system, lig, p, ctx, lid, cond = _setup(4)
+    og, ol = oracle.OGrid(system.grid), oracle.OLigand(lig)
+    seed = system.seed
+    checked = 0
+    for rnd in range(4):
+        ctx.hmc_sweep(2, 10, exchange_every=1)
+        st = ctx.get_replicas(lid)
+        x = st["x"]
+        f, _ = ctx.pose_features(lid, dev(x, torch.float32))
+        out = ctx.proposal_forward(lid, f).cpu().numpy()
+        ctx.pose_move(lid, 1)
+        st2 = ctx.get_replicas(lid)
+        la = ctx.get_pose_stats(lid)["last_ln_alpha"]
+        mp = Lr.mixture(out)
+        for r in range(lig.n_states):
+            k = st["state_of_replica"][r]
+            beta = 1.0 / (oracle.R_GAS * lig.T[k])
+
+            def energy(xx, k=k):
+                t, _, _ = oracle.energy(og, ol, lig.w[k], xx, forces=False)
+                return t[:4].sum() + lig.w[k] @ t[4:]
+            row = {kk: v[r] for kk, v in mp.items()}
+            cnt = st["counter"]
+            u0 = oracle.uniform(seed, 0, lid, r, cnt, 4)
+            z1 = oracle.normals3(seed, 1, lid, r, cnt, 4)
+            z2 = oracle.normals3(seed, 2, lid, r, cnt, 4)
+            ua = oracle.uniform(seed, 3, lid, r, cnt, 4)
+            xn, acc, ln_a = Lr.pose_move(x[r].astype(np.float64), lig.mass,
+                                         lig.frame_atoms, lig.site_center,
+                                         row, energy, beta, u0, z1, z2, ua)
+            # float32 energies (|dE| <= 1e-5 of the magnitude sum, a few
+            # 1e-3 kT here) and float32 rotations enter ln alpha
+            assert abs(la[r] - ln_a) < 2e-2 + 1e-4 * abs(ln_a), \
+                (r, la[r], ln_a)
+            if abs(math.log(ua) - ln_a) > 5e-2:
+                moved = not np.array_equal(st2["x"][r], x[r])
+                assert moved == acc, (rnd, r)
+                if acc:
+                    assert np.max(np.abs(st2["x"][r] - xn)) < 1e-4
+                checked += 1
+    assert checked >= 16
+    ctx.close()
+
+
+def test_training_on_sampled_poses_improves_the_proposal():
+    print_case("training")
+    system = synth.make_system(1)
+    lig = system.ligands[0]
+    # 32 independent chains at the coupled end state (lambda = 1, 300 K)
+    import copy
+    l1 = copy.deepcopy(lig)
+    K = 32
+    l1.T = np.full(K, lig.T[-1])
+    l1.w = np.repeat(lig.w[-1:], K, axis=0)
+    l1.dt = np.full(K, 1.0)
+    l1.x0 = np.repeat(lig.x0[:1], K, axis=0)
+    ctx, (lid,) = make_context(system.grid, [l1], seed=11, capacity=200)
+    rng = np.random.default_rng(0)
+    p = Lr.init_weights(rng)
+    ctx.proposal_setup(lid, l1.frame_atoms, l1.tors[l1.cond_tors], flat(p))
+    ctx.hmc_sweep(200, 10, exchange_every=0)
+    ctx.hmc_sweep(400, 10, exchange_every=0, sample_every=2)
+    xs, _ = ctx.get_samples(lid)
+    xs = dev(xs.reshape(-1, l1.n_atoms, 3), torch.float32)
+    f, po = ctx.pose_features(lid, xs)
+    # untrained proposal
+    ctx.pose_move(lid, 20)
+    before = ctx.get_pose_stats(lid)
+    losses = ctx.proposal_train(lid, f, po, batch=512, steps=400, lr=2e-3,
+                                losses=True)
+    assert losses[-20:].mean() < losses[:20].mean() - 1.0
+    ctx.pose_move(lid, 20)
+    after = ctx.get_pose_stats(lid)
+    acc0 = before["acc"].sum() / before["tries"].sum()
+    acc1 = (after["acc"].sum() - before["acc"].sum()) / \
+        (after["tries"].sum() - before["tries"].sum())
+    assert acc1 > acc0
+    ctx.close()

@@ -22,7 +22,8 @@ def test_rodrigues_matches_scipy_and_log_inverts():
         assert np.allclose(R, Rotation.from_rotvec(w).as_matrix(), atol=1e-13)
         assert np.allclose(Lr.log_rotation(R), w, atol=1e-8)
     # near the identity and near pi
-    for th in (1e-9, 1e-5, math.pi - 1e-6, math.pi):
+    for th in (1e-9, 1e-5, math.pi - 1e-3, math.pi - 3e-5, math.pi - 1e-6,
+               math.pi):
         n = np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8])
         R = Lr.rodrigues(th * n)
         w = Lr.log_rotation(R)
