@@ -385,6 +385,14 @@ BPMF_API int bpmf_get_pose_stats(bpmf_ctx* ctx, int ligand_id, int64_t* acc,
  * not depend on it beyond float32 rounding of the bonded-term order. */
 BPMF_API int bpmf_set_waves(bpmf_ctx* ctx, int waves);
 
+/* bpmf_hmc_sweep replays a hipGraph of `chunk` captured sweeps (default 64;
+ * 0 = plain launches).  The graph is captured on a private stream once per
+ * (sweep arguments, ligand set) and launched on the context's stream; the
+ * kernels read every per-sweep quantity from device memory, so replays are
+ * identical to plain launches.  With timing enabled a graph launch is timed
+ * as a whole and counts as `chunk` sweep launches. */
+BPMF_API int bpmf_set_graph(bpmf_ctx* ctx, int chunk);
+
 /* Wavefronts per replica the sweep currently uses for a ligand. */
 BPMF_API int bpmf_get_waves(bpmf_ctx* ctx, int ligand_id, int* waves);
 
@@ -394,10 +402,10 @@ BPMF_API int bpmf_get_waves(bpmf_ctx* ctx, int ligand_id, int* waves);
 enum { BPMF_TIMER_HMC = 0, BPMF_TIMER_COMPONENTS = 1, BPMF_TIMER_TAIL = 2 };
 
 /* While enabled, every `every`-th launch of each timed kernel (HMC sweep
- * kernels of one sweep; per-sample components of energy_matrix; sweep tail)
- * is bracketed by a pair of HIP events recorded on the context's stream
- * (at most 8192 pairs per kernel between reads).  Enabling clears earlier
- * records. */
+ * kernels of one sweep -- they also run the exchange/record tail of each
+ * ligand; per-sample components of energy_matrix) is bracketed by a pair of
+ * HIP events recorded on the context's stream (at most 8192 pairs per
+ * kernel between reads).  Enabling clears earlier records. */
 BPMF_API int bpmf_set_timing(bpmf_ctx* ctx, int enable, int every);
 
 /* Mean duration in ms of the bracketed launches of `kernel` since timing

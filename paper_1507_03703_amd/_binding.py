@@ -104,6 +104,7 @@ def library():
         "bpmf_reset_samples": [vp, C.c_int],
         "bpmf_set_timing": [vp, C.c_int, C.c_int],
         "bpmf_set_waves": [vp, C.c_int],
+        "bpmf_set_graph": [vp, C.c_int],
         "bpmf_proposal_setup": [vp, C.c_int, ip, C.c_int, ip,
                                 C.POINTER(C.c_float)],
         "bpmf_proposal_params": [vp, C.c_int, C.POINTER(C.c_float),
@@ -447,6 +448,10 @@ class Context:
         _check(self._lib.bpmf_get_pose_stats(self._h, int(ligand_id), p(a),
                                              p(t), _pd(la)))
         return dict(acc=a, tries=t, last_ln_alpha=la)
+
+    def set_graph(self, chunk):
+        """Replay sweeps as hipGraphs of `chunk` sweeps (0 = plain)."""
+        _check(self._lib.bpmf_set_graph(self._h, int(chunk)))
 
     def set_waves(self, waves):
         """Wavefronts per replica (1, 2, 4; 0 = automatic)."""

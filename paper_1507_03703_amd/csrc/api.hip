@@ -110,10 +110,27 @@ struct bpmf_ctx {
   int timing_every = 1;
   uint64_t launches[kTimers] = {0, 0, 0};
   std::vector<hipEvent_t> ev_pool[kTimers];  // start/stop pairs
+  std::vector<int> ev_weight[kTimers];       // launches covered by a pair
   size_t ev_used[kTimers] = {0, 0, 0};
+  // hipGraph of a chunk of sweeps (captured on a private stream, launched on
+  // `stream`)
+  int graph_chunk = 64;  // 0 disables
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  uint64_t table_version = 0, graph_version = ~0ull;
+  int graph_key[6] = {0, 0, 0, 0, 0, 0};
+
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+    graph_version = ~0ull;
+  }
 
   // returns the event pair to bracket this launch of `k`, or false
-  bool timer_begin(int k, hipEvent_t* a, hipEvent_t* b) {
+  bool timer_begin(int k, hipEvent_t* a, hipEvent_t* b, int weight = 1) {
     if (!timing) return false;
     const uint64_t idx = launches[k]++;
     if (idx % (uint64_t)timing_every != 0) return false;
@@ -130,6 +147,8 @@ struct bpmf_ctx {
     }
     *a = ev_pool[k][ev_used[k] * 2];
     *b = ev_pool[k][ev_used[k] * 2 + 1];
+    if (ev_weight[k].size() <= ev_used[k]) ev_weight[k].resize(ev_used[k] + 1);
+    ev_weight[k][ev_used[k]] = weight;
     ++ev_used[k];
     return true;
   }
@@ -234,6 +253,8 @@ int rebuild_tables(bpmf_ctx* c) {
     HIP_TRY(hipMemcpyAsync(nt, all.data(), sizeof(int2) * all.size(),
                            hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  c->drop_graph();
+  ++c->table_version;
   c->dfree(c->d_ligs);
   c->dfree(c->d_tasks);
   c->d_ligs = (LigDev*)nd;
@@ -309,6 +330,8 @@ extern "C" int bpmf_destroy(bpmf_ctx* c) {
   c->dfree(c->mbar_mem);
   for (int k = 0; k < bpmf_ctx::kTimers; ++k)
     for (hipEvent_t e : c->ev_pool[k]) (void)hipEventDestroy(e);
+  c->drop_graph();
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return BPMF_OK;
 }
@@ -550,7 +573,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_wf = A.add((size_t)K * C * 4), o_wd = A.add((size_t)K * C * 8),
                o_x = A.add((size_t)K * n * 12), o_comps = A.add((size_t)K * C1 * 8),
                o_sor = A.add(K * 4), o_ros = A.add(K * 4),
-               o_counters = A.add(8 * 3), o_hacc = A.add(K * 8),
+               o_counters = A.add(8 * 4), o_hacc = A.add(K * 8),
                o_htry = A.add(K * 8), o_eacc = A.add(Km1 * 8),
                o_etry = A.add(Km1 * 8),
                o_sx = A.add((size_t)cap * K * n * 12),
@@ -593,7 +616,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   chain(up(o_x, d->x0, (size_t)K * n * 12));
   chain(up(o_sor, sor.data(), K * 4));
   chain(up(o_ros, ros.data(), K * 4));
-  chain(hipMemsetAsync(base + o_counters, 0, 8 * 3, c->stream));
+  chain(hipMemsetAsync(base + o_counters, 0, 8 * 4, c->stream));
   chain(hipMemsetAsync(base + o_hacc, 0, K * 8, c->stream));
   chain(hipMemsetAsync(base + o_htry, 0, K * 8, c->stream));
   chain(hipMemsetAsync(base + o_eacc, 0, Km1 * 8, c->stream));
@@ -640,6 +663,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.counter = (unsigned long long*)(base + o_counters);
   L.n_rec = L.counter + 1;
   L.nonfinite = L.counter + 2;
+  L.arrive = (unsigned int*)(L.counter + 3);
   L.hmc_acc = (unsigned long long*)(base + o_hacc);
   L.hmc_try = (unsigned long long*)(base + o_htry);
   L.ex_acc = (unsigned long long*)(base + o_eacc);
@@ -701,24 +725,61 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
                     (long long)add[l], h.dev.cap);
     }
   }
-  for (int s = 0; s < a->n_sweeps; ++s) {
-    hipEvent_t t0, t1;
-    const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1);
-    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+  TailArgs tail{a->exchange_every, a->exchange_scheme, a->max_sep,
+                a->sample_every};
+  auto enqueue_sweep = [&](hipStream_t st) -> int {
     for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
       if (c->class_n[q])
         HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs,
                                  c->d_tasks + c->class_off[q], c->class_n[q],
                                  1 << q, c->class_lds[q], a->n_leapfrog,
-                                 c->seed, c->stream));
+                                 c->seed, tail, st));
+    return BPMF_OK;
+  };
+  int done = 0;
+  const int chunk = c->graph_chunk;
+  if (chunk > 0 && a->n_sweeps >= chunk) {
+    // the sweep kernels read every per-sweep quantity (counters, state
+    // maps) from device memory, so one captured chunk replays unchanged
+    const int key[6] = {a->n_leapfrog, a->exchange_every, a->exchange_scheme,
+                        a->max_sep, a->sample_every, chunk};
+    if (!c->graph_exec || c->graph_version != c->table_version ||
+        memcmp(key, c->graph_key, sizeof(key)) != 0) {
+      c->drop_graph();
+      if (!c->cap_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(c->cap_stream,
+                                    hipStreamCaptureModeThreadLocal));
+      int crc = BPMF_OK;
+      for (int s = 0; s < chunk && crc == BPMF_OK; ++s)
+        crc = enqueue_sweep(c->cap_stream);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+      if (crc) {
+        if (g) (void)hipGraphDestroy(g);
+        return crc;
+      }
+      if (ec != hipSuccess)
+        return fail(BPMF_E_HIP, "graph capture: %s", hipGetErrorString(ec));
+      c->graph = g;
+      HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+      c->graph_version = c->table_version;
+      memcpy(c->graph_key, key, sizeof(key));
+    }
+    for (; done + chunk <= a->n_sweeps; done += chunk) {
+      hipEvent_t t0, t1;
+      const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1, chunk);
+      if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+      HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+      if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
+    }
+  }
+  for (; done < a->n_sweeps; ++done) {
+    hipEvent_t t0, t1;
+    const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1);
+    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+    if ((rc = enqueue_sweep(c->stream))) return rc;
     if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
-    const bool timed_tail = c->timer_begin(BPMF_TIMER_TAIL, &t0, &t1);
-    if (timed_tail) HIP_TRY(hipEventRecord(t0, c->stream));
-    HIP_TRY(launch_sweep_tail(c->d_ligs, (int)c->ligs.size(),
-                              a->exchange_every, a->exchange_scheme,
-                              a->max_sep, a->sample_every, c->seed,
-                              c->stream));
-    if (timed_tail) HIP_TRY(hipEventRecord(t1, c->stream));
   }
   for (size_t l = 0; l < c->ligs.size(); ++l) {
     c->ligs[l].counter += (uint64_t)a->n_sweeps;
@@ -1109,15 +1170,17 @@ extern "C" int bpmf_get_timing(bpmf_ctx* c, int kernel, double* mean_ms,
     return fail(BPMF_E_INVAL, "unknown timer %d", kernel);
   HIP_TRY(hipStreamSynchronize(c->stream));
   double tot = 0.0;
+  int64_t cnt = 0;
   const size_t n = c->ev_used[kernel];
   for (size_t i = 0; i < n; ++i) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[kernel][2 * i],
                                 c->ev_pool[kernel][2 * i + 1]));
     tot += ms;
+    cnt += c->ev_weight[kernel][i];
   }
-  if (mean_ms) *mean_ms = n ? tot / (double)n : 0.0;
-  if (n_timed) *n_timed = (int64_t)n;
+  if (mean_ms) *mean_ms = cnt ? tot / (double)cnt : 0.0;
+  if (n_timed) *n_timed = cnt;
   c->ev_used[kernel] = 0;
   c->launches[kernel] = 0;
   return BPMF_OK;
@@ -1466,5 +1529,15 @@ extern "C" int bpmf_get_pose_stats(bpmf_ctx* c, int lid, int64_t* acc,
     HIP_TRY(hipMemcpyAsync(last_ln_alpha, h.prop.last_ln_alpha, K * 8,
                            hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_set_graph(bpmf_ctx* c, int chunk) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (chunk < 0 || chunk > 4096)
+    return fail(BPMF_E_INVAL, "chunk must be 0 (no graph) .. 4096");
+  c->graph_chunk = chunk;
+  c->drop_graph();
   return BPMF_OK;
 }

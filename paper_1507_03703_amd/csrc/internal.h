@@ -70,16 +70,21 @@ struct LigDev {
   unsigned long long* ex_acc;     // max(K-1,1)
   unsigned long long* ex_try;     // max(K-1,1)
   unsigned long long* nonfinite;  // 1
+  unsigned int* arrive;           // replicas done with the current sweep
   float* samp_x;                  // cap*K*n*3
   double* samp_c;                 // cap*K*(1+C)
 };
 
 // Launch wrappers (kernels.hip).  All return hipError_t of the launch.
 // waves = wavefronts per replica (1, 2 or 4); n_atoms <= 64 * waves
+// per-sweep tail run by the last replica of each ligand to finish its move
+struct TailArgs {
+  int exchange_every, scheme, max_sep, sample_every;
+};
 hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
                             const int2* d_tasks, int n_tasks, int waves,
                             int lds_bytes, int nleap, uint64_t seed,
-                            hipStream_t st);
+                            TailArgs tail, hipStream_t st);
 hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
                              int exchange_every, int scheme, int max_sep,
                              int sample_every, uint64_t seed, hipStream_t st);

@@ -50,13 +50,104 @@ __device__ __forceinline__ void block_sum2(float a, float b, double* buf,
 }
 
 // ----------------------------------------------------------------------------
+// replica exchange (Eq. repXacc), state labels swapped
+// ----------------------------------------------------------------------------
+#pragma clang fp contract(off)
+__device__ double state_energy(const LigDev& L, int k, int rep) {
+  const double* cp = L.comps + (size_t)rep * (1 + L.C);
+  double E = cp[0];
+  for (int c = 0; c < L.C; ++c) E += L.wd[k * L.C + c] * cp[1 + c];
+  return E;
+}
+
+__device__ bool attempt_pair(const LigDev& L, int a, int b, int sep,
+                             uint64_t sweep, uint64_t seed) {
+  const int ra = L.replica_of_state[a], rb = L.replica_of_state[b];
+  const double ba = L.beta[a], bb = L.beta[b];
+  const double delta =
+      ba * (state_energy(L, a, rb) - state_energy(L, a, ra)) +
+      bb * (state_energy(L, b, ra) - state_energy(L, b, rb));
+  const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)sep << 8);
+  const U4 o = draw(seed, (uint32_t)a, L.id, 0, sweep, purpose);
+  const double lnu = log(u01d(o.x));
+  const bool ok = isfinite(delta) && (lnu < -delta);
+  if (sep == 1) atomicAdd(&L.ex_try[a], 1ull);
+  if (ok) {
+    L.replica_of_state[a] = rb;
+    L.replica_of_state[b] = ra;
+    L.state_of_replica[ra] = b;
+    L.state_of_replica[rb] = a;
+    if (sep == 1) atomicAdd(&L.ex_acc[a], 1ull);
+  }
+  return ok;
+}
+#pragma clang fp contract(fast)
+
+// block-wide exchange sweep for one ligand (called by all threads)
+__device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
+                               int max_sep, uint64_t seed) {
+  const int K = L.K;
+  if (K < 2) return;
+  if (scheme == 0) {
+    // disjoint neighbour pairs: independent, one thread each
+    const int a0 = (int)(sweep & 1ull);
+    for (int a = a0 + 2 * (int)threadIdx.x; a + 1 < K; a += 2 * blockDim.x)
+      attempt_pair(L, a, a + 1, 1, sweep, seed);
+  } else if (threadIdx.x == 0) {
+    const int dmax = max_sep < K - 1 ? max_sep : K - 1;
+    for (int d = 1; d <= dmax; ++d)
+      for (int a = 0; a + d < K; ++a) attempt_pair(L, a, a + d, d, sweep, seed);
+  }
+}
+
+// Tail of one ligand's sweep, run by one whole block: exchange (if due),
+// record one sample per state (if due), counter += 1.
+__device__ void sweep_tail(const LigDev& L, int exchange_every, int scheme,
+                           int max_sep, int sample_every, uint64_t seed) {
+  const unsigned long long s = *L.counter;
+  if (exchange_every > 0 && s % (unsigned long long)exchange_every == 0ull)
+    exchange_block(L, s, scheme, max_sep, seed);
+  __syncthreads();
+  const unsigned long long rec = *L.n_rec;
+  const bool record = sample_every > 0 &&
+                      (s + 1ull) % (unsigned long long)sample_every == 0ull &&
+                      rec < (unsigned long long)L.cap;
+  if (record) {
+    const int n3 = L.n * 3, C1 = 1 + L.C;
+    float* dx = L.samp_x + (size_t)rec * L.K * n3;
+    double* dc = L.samp_c + (size_t)rec * L.K * C1;
+    for (int q = threadIdx.x; q < L.K * n3; q += blockDim.x) {
+      const int k = q / n3, e = q - k * n3;
+      dx[q] = L.x[(size_t)L.replica_of_state[k] * n3 + e];
+    }
+    for (int q = threadIdx.x; q < L.K * C1; q += blockDim.x) {
+      const int k = q / C1, e = q - k * C1;
+      dc[q] = L.comps[(size_t)L.replica_of_state[k] * C1 + e];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *L.counter = s + 1ull;
+    if (record) *L.n_rec = rec + 1ull;
+  }
+}
+
+// One block per ligand: the tail as a kernel of its own.
+__global__ __launch_bounds__(256) void k_sweep_tail(
+    const LigDev* __restrict__ ligs, int exchange_every, int scheme,
+    int max_sep, int sample_every, uint64_t seed) {
+  sweep_tail(ligs[blockIdx.x], exchange_every, scheme, max_sep, sample_every,
+             seed);
+}
+
+// ----------------------------------------------------------------------------
 // HMC: one trial move per replica, one workgroup of W wavefronts per replica.
 // (Sampling: HMC trial moves from velocity-Verlet molecular dynamics.)
 // ----------------------------------------------------------------------------
 template <int C, int W>
 __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     GridDev g, const LigDev* __restrict__ ligs, const int2* __restrict__ tasks,
-    int nleap, uint64_t seed) {
+    int nleap, uint64_t seed, TailArgs tail) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int2 task = tasks[blockIdx.x];
@@ -150,89 +241,26 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     if (accept) atomicAdd(&L.hmc_acc[k], 1ull);
     if (!finite) atomicAdd(L.nonfinite, 1ull);
   }
-}
-
-// ----------------------------------------------------------------------------
-// replica exchange (Eq. repXacc), state labels swapped
-// ----------------------------------------------------------------------------
-#pragma clang fp contract(off)
-__device__ double state_energy(const LigDev& L, int k, int rep) {
-  const double* cp = L.comps + (size_t)rep * (1 + L.C);
-  double E = cp[0];
-  for (int c = 0; c < L.C; ++c) E += L.wd[k * L.C + c] * cp[1 + c];
-  return E;
-}
-
-__device__ bool attempt_pair(const LigDev& L, int a, int b, int sep,
-                             uint64_t sweep, uint64_t seed) {
-  const int ra = L.replica_of_state[a], rb = L.replica_of_state[b];
-  const double ba = L.beta[a], bb = L.beta[b];
-  const double delta =
-      ba * (state_energy(L, a, rb) - state_energy(L, a, ra)) +
-      bb * (state_energy(L, b, ra) - state_energy(L, b, rb));
-  const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)sep << 8);
-  const U4 o = draw(seed, (uint32_t)a, L.id, 0, sweep, purpose);
-  const double lnu = log(u01d(o.x));
-  const bool ok = isfinite(delta) && (lnu < -delta);
-  if (sep == 1) atomicAdd(&L.ex_try[a], 1ull);
-  if (ok) {
-    L.replica_of_state[a] = rb;
-    L.replica_of_state[b] = ra;
-    L.state_of_replica[ra] = b;
-    L.state_of_replica[rb] = a;
-    if (sep == 1) atomicAdd(&L.ex_acc[a], 1ull);
-  }
-  return ok;
-}
-#pragma clang fp contract(fast)
-
-// block-wide exchange sweep for one ligand (called by all threads)
-__device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
-                               int max_sep, uint64_t seed) {
-  const int K = L.K;
-  if (K < 2) return;
-  if (scheme == 0) {
-    // disjoint neighbour pairs: independent, one thread each
-    const int a0 = (int)(sweep & 1ull);
-    for (int a = a0 + 2 * (int)threadIdx.x; a + 1 < K; a += 2 * blockDim.x)
-      attempt_pair(L, a, a + 1, 1, sweep, seed);
-  } else if (threadIdx.x == 0) {
-    const int dmax = max_sep < K - 1 ? max_sep : K - 1;
-    for (int d = 1; d <= dmax; ++d)
-      for (int a = 0; a + d < K; ++a) attempt_pair(L, a, a + d, d, sweep, seed);
-  }
-}
-
-// One block per ligand: exchange (if due), record (if due), counter += 1.
-__global__ __launch_bounds__(256) void k_sweep_tail(
-    const LigDev* __restrict__ ligs, int exchange_every, int scheme,
-    int max_sep, int sample_every, uint64_t seed) {
-  const LigDev& L = ligs[blockIdx.x];
-  const unsigned long long s = *L.counter;
-  if (exchange_every > 0 && s % (unsigned long long)exchange_every == 0ull)
-    exchange_block(L, s, scheme, max_sep, seed);
+  // The last replica of the ligand to finish runs the sweep's tail (no
+  // block ever waits for another).  Release: this block's stores are made
+  // visible device-wide before its arrival is counted; the last block
+  // acquires before reading the other replicas' results.
+  __shared__ int s_last;
   __syncthreads();
-  const unsigned long long rec = *L.n_rec;
-  const bool record = sample_every > 0 &&
-                      (s + 1ull) % (unsigned long long)sample_every == 0ull &&
-                      rec < (unsigned long long)L.cap;
-  if (record) {
-    const int n3 = L.n * 3, C1 = 1 + L.C;
-    float* dx = L.samp_x + (size_t)rec * L.K * n3;
-    double* dc = L.samp_c + (size_t)rec * L.K * C1;
-    for (int q = threadIdx.x; q < L.K * n3; q += blockDim.x) {
-      const int k = q / n3, e = q - k * n3;
-      dx[q] = L.x[(size_t)L.replica_of_state[k] * n3 + e];
-    }
-    for (int q = threadIdx.x; q < L.K * C1; q += blockDim.x) {
-      const int k = q / C1, e = q - k * C1;
-      dc[q] = L.comps[(size_t)L.replica_of_state[k] * C1 + e];
+  if (tid == 0) {
+    __threadfence();
+    const unsigned int prev = atomicAdd(L.arrive, 1u);
+    s_last = (prev == (unsigned int)L.K - 1u) ? 1 : 0;
+    if (s_last) {
+      __threadfence();
+      *L.arrive = 0u;
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    *L.counter = s + 1ull;
-    if (record) *L.n_rec = rec + 1ull;
+  if (s_last) {
+    __threadfence();
+    sweep_tail(L, tail.exchange_every, tail.scheme, tail.max_sep,
+               tail.sample_every, seed);
   }
 }
 
@@ -450,11 +478,11 @@ int grid_blocks(int64_t work, int per_block, int cap) {
 hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
                             const int2* d_tasks, int n_tasks, int waves,
                             int lds_bytes, int nleap, uint64_t seed,
-                            hipStream_t st) {
+                            TailArgs tail, hipStream_t st) {
   if (n_tasks <= 0) return hipSuccess;
   BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
     hipLaunchKernelGGL((k_hmc_sweep<C, W>), dim3(n_tasks), dim3(W * kWave),
-                       lds_bytes, st, g, d_ligs, d_tasks, nleap, seed);
+                       lds_bytes, st, g, d_ligs, d_tasks, nleap, seed, tail);
   }));
   return hipGetLastError();
 }
