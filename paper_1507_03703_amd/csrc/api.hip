@@ -195,7 +195,7 @@ int wave_class(int w) { return w == 1 ? 0 : (w == 2 ? 1 : (w == 4 ? 2 : 3)); }
 
 int lds_of(const LigHost& h, int waves, bool forces) {
   const LigDev& L = h.dev;
-  return block_lds_bytes(waves, forces ? L.n_slots : 0, L.n, L.nb, L.na, L.nt);
+  return block_lds_bytes(waves, forces, L.n, L.nb, L.na, L.nt);
 }
 
 // wavefronts per replica for the HMC sweep: enough to own every atom; when
@@ -520,32 +520,17 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
     tpar[t] = make_float4((float)d->tors_v_n_g[3 * t], (float)mult,
                           (float)cos(gam), (float)sin(gam));
   }
-  // force slots numbered atom by atom: the slots of atom i are the
-  // contiguous range gstart[i] .. gstart[i+1]-1, in term order (torsions,
-  // angles, bonds, each ascending) within the atom; every term records the
-  // slot of each of its atoms next to the atom index (atom | slot << 8)
-  std::vector<int> cnt(n, 0);
-  for (int t = 0; t < nt; ++t)
-    for (int a = 0; a < 4; ++a) ++cnt[d->tors_ijkl[4 * t + a]];
-  for (int t = 0; t < na; ++t)
-    for (int a = 0; a < 3; ++a) ++cnt[d->angle_ijk[3 * t + a]];
-  for (int t = 0; t < nb; ++t)
-    for (int a = 0; a < 2; ++a) ++cnt[d->bond_ij[2 * t + a]];
-  std::vector<int> gstart(n + 1, 0), next(n, 0);
-  for (int i = 0; i < n; ++i) gstart[i + 1] = gstart[i] + cnt[i];
-  for (int i = 0; i < n; ++i) next[i] = gstart[i];
-  auto pack = [&](int atom) { return atom | (next[atom]++ << 8); };
   for (int t = 0; t < nt; ++t) {
     const int* q = d->tors_ijkl + 4 * t;
-    tijkl[t] = make_int4(pack(q[0]), pack(q[1]), pack(q[2]), pack(q[3]));
+    tijkl[t] = make_int4(q[0], q[1], q[2], q[3]);
   }
   for (int t = 0; t < na; ++t) {
     const int* q = d->angle_ijk + 3 * t;
-    aijk[t] = make_int4(pack(q[0]), pack(q[1]), pack(q[2]), 0);
+    aijk[t] = make_int4(q[0], q[1], q[2], 0);
   }
   for (int t = 0; t < nb; ++t) {
     const int* q = d->bond_ij + 2 * t;
-    bij[t] = make_int2(pack(q[0]), pack(q[1]));
+    bij[t] = make_int2(q[0], q[1]);
   }
   std::vector<double> beta(K), wd((size_t)K * C);
   std::vector<float> Tf(K), dtf(K), wf((size_t)K * C);
@@ -567,8 +552,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_scale = A.add((size_t)n * C * 4), o_bij = A.add(nb * 8),
                o_bpar = A.add(nb * 8), o_aijk = A.add(na * 16),
                o_apar = A.add(na * 8), o_tijkl = A.add(nt * 16),
-               o_tpar = A.add(nt * 16), o_gs = A.add((n + 1) * 4),
-               o_beta = A.add(K * 8),
+               o_tpar = A.add(nt * 16), o_beta = A.add(K * 8),
                o_Tf = A.add(K * 4), o_dt = A.add(K * 4),
                o_wf = A.add((size_t)K * C * 4), o_wd = A.add((size_t)K * C * 8),
                o_x = A.add((size_t)K * n * 12), o_comps = A.add((size_t)K * C1 * 8),
@@ -580,7 +564,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_sc = A.add((size_t)cap * K * C1 * 8);
   {
     // every kernel stages the topology in LDS next to its working areas
-    const int need = block_lds_bytes(min_waves, n_slots, n, nb, na, nt);
+    const int need = block_lds_bytes(min_waves, true, n, nb, na, nt);
     if (need > 65536)
       return fail(BPMF_E_INVAL,
                   "topology too large: %d bytes of LDS per replica (max 65536)",
@@ -607,7 +591,6 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   chain(up(o_apar, apar.data(), na * 8));
   chain(up(o_tijkl, tijkl.data(), nt * 16));
   chain(up(o_tpar, tpar.data(), nt * 16));
-  chain(up(o_gs, gstart.data(), (n + 1) * 4));
   chain(up(o_beta, beta.data(), K * 8));
   chain(up(o_Tf, Tf.data(), K * 4));
   chain(up(o_dt, dtf.data(), K * 4));
@@ -650,7 +633,6 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.apar = (const float2*)(base + o_apar);
   L.tijkl = (const int4*)(base + o_tijkl);
   L.tpar = (const float4*)(base + o_tpar);
-  L.gstart = (const int*)(base + o_gs);
   L.beta = (const double*)(base + o_beta);
   L.Tf = (const float*)(base + o_Tf);
   L.dtf = (const float*)(base + o_dt);

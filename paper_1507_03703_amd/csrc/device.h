@@ -255,20 +255,33 @@ __device__ __forceinline__ float3 scale3(float s, float3 a) {
   return make_float3(s * a.x, s * a.y, s * a.z);
 }
 
-// Per-(term, atom) force contributions.  Slot numbers are assigned so that
-// every atom's slots form one contiguous range (ascending term order within
-// the atom), so the owner sums a contiguous run without indirection.
+// Per-atom force accumulators in LDS, in 64-bit fixed point (2^-24
+// kJ/mol/A per unit): every bonded-term thread adds its contribution to
+// each of its atoms with an integer LDS atomic.  Integer addition is
+// associative, so the sums do not depend on the order in which threads
+// arrive and results stay bitwise reproducible; the quantisation (6e-8
+// kJ/mol/A per contribution) is far below float32 force resolution.
+constexpr float kFix = 16777216.0f;       // 2^24
+constexpr float kFixInv = 1.0f / 16777216.0f;
+constexpr float kFixMax = 1.0e11f;        // |f| clamp keeps f * 2^24 < 2^63
+
+__device__ __forceinline__ unsigned long long to_fix(float f) {
+  // NaN compares false and becomes 0; the energy still carries the NaN
+  f = fminf(fmaxf(f, -kFixMax), kFixMax);
+  return (unsigned long long)(long long)llrintf(f * kFix);
+}
+
 struct Slots {
-  float4* v;
-  __device__ __forceinline__ void put(int i, float3 f) const {
-    v[i] = make_float4(f.x, f.y, f.z, 0.f);
+  unsigned long long* acc;  // n x 3
+  __device__ __forceinline__ void put(int atom, float3 f) const {
+    atomicAdd(&acc[3 * atom], to_fix(f.x));
+    atomicAdd(&acc[3 * atom + 1], to_fix(f.y));
+    atomicAdd(&acc[3 * atom + 2], to_fix(f.z));
   }
 };
 
-// topology entries pack an atom index (low 8 bits) and the slot that
-// receives that atom's force from the term (upper bits)
-__device__ __forceinline__ int atom_of(int p) { return p & 0xff; }
-__device__ __forceinline__ int slot_of(int p) { return p >> 8; }
+__device__ __forceinline__ int atom_of(int p) { return p; }
+__device__ __forceinline__ int slot_of(int p) { return p; }
 
 // K (r - r0)^2
 template <bool FORCES>
@@ -381,7 +394,7 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
 // Shared memory (Shared): positions, force slots, per-wave partial sums.
 struct Shared {
   float4* pos;     // 64 W
-  Slots sl;        // 3 x n_slots
+  Slots sl;        // n x 3 fixed-point force accumulators
   float* com;      // W x 3
   double* red;     // W x kRed
   // ligand topology staged once per launch (stage_topology)
@@ -391,13 +404,12 @@ struct Shared {
   const float2* apar;
   const int4* tijkl;
   const float4* tpar;
-  const int* gstart;
 };
 
 // Copy a ligand's constant topology into LDS (all threads; caller syncs).
 // `raw` points past the per-evaluation areas; layout: tpar (nt float4),
 // tijkl (nt int4), aijk (na int4), apar (na float2), bij (nb int2), bpar
-// (nb float2), gstart (n+1 int).
+// (nb float2).
 __device__ __forceinline__ void stage_topology(const LigDev& L,
                                                unsigned char* raw, Shared& sh,
                                                int tid, int nthreads) {
@@ -407,7 +419,6 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
   float2* apar = reinterpret_cast<float2*>(aijk + L.na);
   int2* bij = reinterpret_cast<int2*>(apar + L.na);
   float2* bpar = reinterpret_cast<float2*>(bij + L.nb);
-  int* gstart = reinterpret_cast<int*>(bpar + L.nb);
   for (int i = tid; i < L.nt; i += nthreads) {
     tpar[i] = L.tpar[i];
     tijkl[i] = L.tijkl[i];
@@ -420,20 +431,14 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
     bij[i] = L.bij[i];
     bpar[i] = L.bpar[i];
   }
-  for (int i = tid; i <= L.n; i += nthreads) gstart[i] = L.gstart[i];
   sh.bij = bij;
   sh.bpar = bpar;
   sh.aijk = aijk;
   sh.apar = apar;
   sh.tijkl = tijkl;
   sh.tpar = tpar;
-  sh.gstart = gstart;
 }
 
-__host__ __device__ inline int topology_lds_bytes(int n, int nb, int na,
-                                                  int nt, int n_slots) {
-  return 32 * nt + 24 * na + 16 * nb + 4 * (n + 1) + 4 * n_slots;
-}
 constexpr int kRedMax = kRedSlots;  // U_bond..U_tors, Psi_c, two extras
 
 __device__ __forceinline__ void block_sync() {
@@ -514,27 +519,16 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
 #pragma unroll
     for (int c = 0; c < C; ++c) psi[c] = e[c];
     if (FORCES && owner) {
-      float fx = 0.f, fy = 0.f, fz = 0.f;
-      // the atom's slots are contiguous: issue eight loads at a time
-      const int b = sh.gstart[tid], eidx = sh.gstart[tid + 1];
-      int q = b;
-      for (; q + 8 <= eidx; q += 8) {
-        float4 v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = sh.sl.v[q + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          fx += v[u].x;
-          fy += v[u].y;
-          fz += v[u].z;
-        }
-      }
-      for (; q < eidx; ++q) {
-        const float4 v = sh.sl.v[q];
-        fx += v.x;
-        fy += v.y;
-        fz += v.z;
-      }
+      float fx, fy, fz;
+      // bonded forces: read and clear the atom's fixed-point accumulator
+      // (the next evaluation adds into it only after its first barrier)
+      unsigned long long* a3 = sh.sl.acc + 3 * tid;
+      fx = (float)(long long)a3[0] * kFixInv;
+      fy = (float)(long long)a3[1] * kFixInv;
+      fz = (float)(long long)a3[2] * kFixInv;
+      a3[0] = 0ull;
+      a3[1] = 0ull;
+      a3[2] = 0ull;
       fx += fr * m * cx;
       fy += fr * m * cy;
       fz += fr * m * cz;

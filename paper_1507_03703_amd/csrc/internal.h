@@ -11,12 +11,12 @@ constexpr double kRGas = 8.314462618e-3;  // kJ/(mol K)
 constexpr int kRedSlots = 4 + 8 + 2;  // per-wave partial sums (see Shared)
 
 // dynamic LDS bytes of a W-wave evaluation block: per-evaluation areas,
-// n_slots force slots (0 for energy-only kernels) and the staged topology
-inline int block_lds_bytes(int waves, int n_slots, int n, int nb, int na,
+// force accumulators (n x 3 int64, forces only) and the staged topology
+inline int block_lds_bytes(int waves, bool forces, int n, int nb, int na,
                            int nt) {
   const int head = 16 * kWave * waves + 8 * waves * kRedSlots + 16 * waves +
-                   16 * n_slots;
-  const int topo = 32 * nt + 24 * na + 16 * nb + 4 * (n + 1);
+                   (forces ? 24 * n : 0);
+  const int topo = 32 * nt + 24 * na + 16 * nb;
   return head + topo;
 }
 
@@ -45,15 +45,12 @@ struct LigDev {
   const float* mass;      // n
   const float* inv_mass;  // n
   const float* scale;     // n*C
-  // term atom indices are packed with the force slot of that atom in the
-  // term: atom | slot << 8; slots are numbered atom by atom (contiguous)
   const int2* bij;        // nb
   const float2* bpar;     // nb: K_r, r0
   const int4* aijk;       // na: i, j(vertex), k, -
   const float2* apar;     // na: K_theta, theta0
   const int4* tijkl;      // nt
   const float4* tpar;     // nt: V/2, n (integer 1..6), cos gamma, sin gamma
-  const int* gstart;      // n+1: slots of atom i are gstart[i]..gstart[i+1]-1
   const double* beta;     // K: 1/(R T_k)
   const float* Tf;        // K
   const float* dtf;       // K

@@ -12,20 +12,22 @@ namespace bpmf {
 namespace {
 
 // Dynamic LDS of a W-wave block: positions (64 W float4), per-wave partial
-// sums, centre-of-mass partials, n_slots float4 force slots, then the
-// ligand's topology (staged once per launch).
+// sums, centre-of-mass partials, n_acc x 3 fixed-point force accumulators,
+// then the ligand's topology (staged once per launch).
 template <int W>
 __device__ __forceinline__ Shared carve(unsigned char* raw, const LigDev& L,
-                                        int n_slots, int tid) {
+                                        int n_acc, int tid) {
   Shared sh;
   sh.pos = reinterpret_cast<float4*>(raw);
   sh.red = reinterpret_cast<double*>(raw + 16 * kWave * W);
   sh.com = reinterpret_cast<float*>(raw + 16 * kWave * W +
                                     8 * W * kRedMax);
-  // offset arithmetic on the LDS base keeps the pointers in LDS space
-  const int slot0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
-  sh.sl = Slots{reinterpret_cast<float4*>(raw + slot0)};
-  stage_topology(L, raw + slot0 + 16 * n_slots, sh, tid, W * kWave);
+  // offset arithmetic on the LDS base keeps the pointers in LDS space;
+  // force accumulators exist when n_acc > 0 (force-evaluating kernels)
+  const int acc0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
+  sh.sl = Slots{reinterpret_cast<unsigned long long*>(raw + acc0)};
+  for (int i = tid; i < 3 * n_acc; i += W * kWave) sh.sl.acc[i] = 0ull;
+  stage_topology(L, raw + acc0 + 24 * n_acc, sh, tid, W * kWave);
   __syncthreads();
   return sh;
 }
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   const LigDev L = ligs[task.x];  // kernel-lifetime copy (no reloads)
   const int r = task.y;
   const int n = L.n;
-  const Shared sh = carve<W>(smem, L, L.n_slots, tid);
+  const Shared sh = carve<W>(smem, L, L.n, tid);
   __shared__ double fin[2 * W];
 
   const unsigned long long s = *L.counter;
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(W * kWave) void k_evaluate(
   const LigDev L = *lig;
   const int tid = threadIdx.x;
   const int n = L.n;
-  const Shared sh = carve<W>(smem, L, L.n_slots, tid);
+  const Shared sh = carve<W>(smem, L, L.n, tid);
   const bool owner = tid < n;
   const float m = owner ? L.mass[tid] : 0.f;
   float sc[C];

@@ -492,9 +492,9 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     sh.pos = reinterpret_cast<float4*>(smem);
     sh.red = reinterpret_cast<double*>(smem + 16 * kWave * W);
     sh.com = reinterpret_cast<float*>(smem + 16 * kWave * W + 8 * W * kRedMax);
-    const int slot0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
-    sh.sl = Slots{reinterpret_cast<float4*>(smem + slot0)};
-    stage_topology(L, smem + slot0, sh, tid, W * kWave);
+    const int acc0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
+    sh.sl = Slots{reinterpret_cast<unsigned long long*>(smem + acc0)};
+    stage_topology(L, smem + acc0, sh, tid, W * kWave);
     __syncthreads();
   }
   const bool owner = tid < n;
