@@ -14,6 +14,11 @@ value = atom-grid energy+force evaluations of the HMC moves per second of
 whole-step time; one evaluation = one atom's trilinear interpolation of the
 three grids with gradient (96 algorithmic grid bytes) plus its share of the
 bonded terms and restraint.
+
+A second leg ("batched") runs the batched workload -- 256 ligands of 10-80
+atoms with 32 replicas each on one shared 160^3 grid, 2000 sweeps of 10
+steps, per-ligand u_kn and MBAR -- with the launch shape picked by the
+autotuner; --config 3 makes it the main workload instead.
 """
 from __future__ import annotations
 
@@ -40,6 +45,8 @@ def parse():
                    help="override sweeps per step (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-batched", dest="batched", action="store_false",
+                   help="skip the batched 256-ligand leg")
     return p.parse_args()
 
 
@@ -70,6 +77,125 @@ def cpu_baseline(system, target_s):
                        f"{el:.1f} s")
 
 
+def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
+                 tune=False):
+    """Set up every ligand of `system`, run `warmup` + `steps` timed steps
+    of the hot path and return the measurements."""
+    import numpy as np
+    g = system.grid
+    ligs = system.ligands
+    L = system.n_leapfrog
+    sweeps = sweeps or system.n_sweeps
+    every = system.sample_every
+    records = sweeps // every
+    t_setup = time.perf_counter()
+    ctx = pkg.Context(seed=system.seed, device=0)
+    ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+    ids = [ctx.ligand_setup(l, sample_capacity=records) for l in ligs]
+    ukn = [torch.empty((l.n_states, records * l.n_states),
+                       dtype=torch.float64, device="cuda:0") for l in ligs]
+    Nk = [np.full(l.n_states, records, np.int64) for l in ligs]
+    tuned = None
+    if tune:
+        sig = (f"{system.name}|L{L}|" +
+               ",".join(f"{l.n_atoms}x{l.n_states}" for l in ligs))
+        cache = os.environ.get("BPMF_TUNE_CACHE", os.path.join(
+            os.path.expanduser("~"), ".cache", "bpmf_autotune.json"))
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        chosen, table = ctx.autotune(n_sweeps=64, n_leapfrog=L,
+                                     cache_path=cache, signature=sig)
+        tuned = {"chosen_waves": chosen or "auto", "sweep_ms": table}
+    setup_s = time.perf_counter() - t_setup
+    results = []
+
+    def step():
+        for i in ids:
+            ctx.reset_samples(i)
+        ctx.hmc_sweep(sweeps, L, exchange_every=1, exchange_scheme=0,
+                      sample_every=every)
+        out = []
+        for i, u, nk in zip(ids, ukn, Nk):
+            ctx.energy_matrix(i, None, n_samples=u.shape[1], out=u)
+            out.append(ctx.mbar(u, nk, tol=1e-10, max_iter=100))
+        return out
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True, every=8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        results = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hmc_ms, hmc_n = ctx.get_timing(ctx.TIMER_HMC)
+    cmp_ms, cmp_n = ctx.get_timing(ctx.TIMER_COMPONENTS)
+    ctx.set_timing(False)
+    stats = [ctx.get_stats(i) for i in ids]
+    waves = sorted({ctx.get_waves(i) for i in ids})
+    ctx.close()
+
+    ms_per_step = el / steps * 1e3
+    evals_per_sweep = sum(l.n_states * l.n_atoms for l in ligs) * (L + 1)
+    value = sweeps * evals_per_sweep / (ms_per_step * 1e-3)
+    achieved = evals_per_sweep * GRID_BYTES_PER_EVAL / (hmc_ms * 1e-3) / 1e9
+    f, var, it = results[0]
+    acc = sum(st["hmc_acc"].sum() for st in stats) / max(
+        sum(st["hmc_try"].sum() for st in stats), 1)
+    exa = sum(st["ex_acc"].sum() for st in stats) / max(
+        sum(st["ex_try"].sum() for st in stats), 1)
+    bpmf = np.array([r[0][-1] - r[0][0] for r in results])
+    return dict(value=value, ms_per_step=ms_per_step, sweeps=sweeps,
+                records=records, hmc_ms=hmc_ms, hmc_n=hmc_n, cmp_ms=cmp_ms,
+                achieved=achieved, evals_per_sweep=evals_per_sweep,
+                setup_s=setup_s, waves=waves, tuned=tuned,
+                result={"bpmf_syn_kT": float(f[-1] - f[0]) if len(results)
+                        == 1 else None,
+                        "sigma_kT": float(np.sqrt(max(var[-1], 0.0))),
+                        "mbar_iterations": int(it),
+                        "bpmf_syn_kT_mean": float(bpmf.mean()),
+                        "bpmf_syn_kT_range": [float(bpmf.min()),
+                                              float(bpmf.max())],
+                        "hmc_acceptance": float(acc),
+                        "exchange_acceptance": float(exa)})
+
+
+def describe(system, r):
+    ligs = system.ligands
+    g = system.grid
+    L = system.n_leapfrog
+    R = sum(l.n_states for l in ligs)
+    if len(ligs) == 1:
+        l = ligs[0]
+        what = (f"{system.name}: {l.n_atoms}-atom ligand, {g.n[0]}^3 x 3 "
+                f"float32 grids at {g.spacing} A, {R} replicas, "
+                f"{r['sweeps']} sweeps x {L} leapfrog steps + neighbour "
+                f"exchange, u_kn {l.n_states}x{r['records'] * l.n_states} "
+                f"float64, MBAR")
+    else:
+        counts = [l.n_atoms for l in ligs]
+        what = (f"{system.name}: {len(ligs)} ligands of {min(counts)}-"
+                f"{max(counts)} atoms x {ligs[0].n_states} replicas ({R} "
+                f"replicas), shared {g.n[0]}^3 x 3 float32 grids at "
+                f"{g.spacing} A, {r['sweeps']} sweeps x {L} leapfrog steps "
+                f"+ neighbour exchange, per-ligand u_kn and MBAR")
+    return {"workload": what, "ligands": len(ligs), "replicas": R,
+            "atoms": [l.n_atoms for l in ligs] if len(ligs) <= 4 else
+            f"{sum(l.n_atoms for l in ligs)} total",
+            "sweeps_per_step": r["sweeps"], "leapfrog": L,
+            "samples_per_state": r["records"]}
+
+
+def roofline(r):
+    return {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
+            "traffic": None, "kernel": "k_hmc_sweep",
+            "mean_launch_ms": r["hmc_ms"], "launches_timed": r["hmc_n"],
+            "algorithmic_bytes_per_launch": r["evals_per_sweep"] *
+            GRID_BYTES_PER_EVAL}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -77,102 +203,47 @@ def main():
               "path shards by ligand/replica range without collectives, see "
               "the design notes.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import synth
     import paper_1507_03703_amd as pkg
 
-    t_setup = time.perf_counter()
-    system = synth.make_system(args.config)
-    lig = system.ligands[0]
-    g = system.grid
-    K, n = lig.n_states, lig.n_atoms
-    L = system.n_leapfrog
-    sweeps = args.sweeps or system.n_sweeps
-    every = system.sample_every
-    records = sweeps // every
-    ctx = pkg.Context(seed=system.seed, device=0)
-    ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
-    lid = ctx.ligand_setup(lig, sample_capacity=records)
-    N = records * K
-    ukn = torch.empty((K, N), dtype=torch.float64, device="cuda:0")
-    Nk = np.full(K, records, np.int64)
-    setup_s = time.perf_counter() - t_setup
-
-    def step():
-        ctx.reset_samples(lid)
-        ctx.hmc_sweep(sweeps, L, exchange_every=1, exchange_scheme=0,
-                      sample_every=every)
-        ctx.energy_matrix(lid, None, n_samples=N, out=ukn)
-        return ctx.mbar(ukn, Nk, tol=1e-10, max_iter=100)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.set_timing(True, every=8)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        f, var, it = step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    hmc_ms, hmc_n = ctx.get_timing(ctx.TIMER_HMC)
-    cmp_ms, cmp_n = ctx.get_timing(ctx.TIMER_COMPONENTS)
-    tail_ms, tail_n = ctx.get_timing(ctx.TIMER_TAIL)
-    ctx.set_timing(False)
-    stats = ctx.get_stats(lid)
-
-    ms_per_step = el / args.steps * 1e3
-    evals_per_step = sweeps * K * n * (L + 1)
-    value = evals_per_step / (ms_per_step * 1e-3)
-    # dominant kernel: the HMC sweep (one launch = one sweep of all replicas)
-    evals_per_launch = K * n * (L + 1)
-    achieved = evals_per_launch * GRID_BYTES_PER_EVAL / (hmc_ms * 1e-3) / 1e9
+    system = synth.make_system(args.config, grid_device="cuda:0")
+    r = run_workload(pkg, torch, system, args.steps, args.warmup,
+                     sweeps=args.sweeps, tune=len(system.ligands) > 1)
     out = {
         "metric": "atom-grid energy+force evals/s & HBM fraction; effective "
                   "samples/s vs plain HMC",
-        "value": value,
+        "value": r["value"],
         "unit": "atom-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": f"{system.name}: {n}-atom ligand, {g.n[0]}^3 x 3 "
-                        f"float32 grids at {g.spacing} A, {K} replicas, "
-                        f"{sweeps} sweeps x {L} leapfrog steps + neighbour "
-                        f"exchange, u_kn {K}x{N} float64, MBAR",
-            "replicas": K, "atoms": n, "sweeps_per_step": sweeps,
-            "leapfrog": L, "samples": N},
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_hmc_sweep", "mean_launch_ms": hmc_ms,
-            "launches_timed": hmc_n,
-            "algorithmic_bytes_per_launch": evals_per_launch *
-            GRID_BYTES_PER_EVAL},
-        "kernels_ms": {"hmc_sweep": hmc_ms, "sweep_tail": tail_ms,
-                       "components": cmp_ms},
-        "result": {"bpmf_syn_kT": float(f[-1] - f[0]),
-                   "sigma_kT": float(np.sqrt(max(var[-1], 0.0))),
-                   "mbar_iterations": int(it),
-                   "hmc_acceptance": float(stats["hmc_acc"].sum() /
-                                           max(stats["hmc_try"].sum(), 1)),
-                   "exchange_acceptance": float(stats["ex_acc"].sum() /
-                                                max(stats["ex_try"].sum(),
-                                                    1))},
-        "setup_s": setup_s,
+        "config": describe(system, r),
+        "roofline": roofline(r),
+        "kernels_ms": {"hmc_sweep": r["hmc_ms"], "components": r["cmp_ms"]},
+        "result": r["result"],
+        "setup_s": r["setup_s"],
     }
+    if r["tuned"]:
+        out["autotune"] = r["tuned"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_seconds)
-    ctx.close()
+    if args.batched and args.config != 3:
+        bs = synth.make_system(3, grid_device="cuda:0")
+        rb = run_workload(pkg, torch, bs, 1, 1, tune=True)
+        out["batched"] = {"value": rb["value"], "unit": "atom-evals/s",
+                          "ms_per_step": rb["ms_per_step"], "steps": 1,
+                          "warmup": 1, "config": describe(bs, rb),
+                          "roofline": roofline(rb),
+                          "autotune": rb["tuned"], "waves": rb["waves"],
+                          "result": rb["result"]}
     print(json.dumps(out))
 
 

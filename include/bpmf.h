@@ -379,10 +379,12 @@ BPMF_API int bpmf_get_pose_stats(bpmf_ctx* ctx, int ligand_id, int64_t* acc,
  * Launch shape
  * ------------------------------------------------------------------------ */
 
-/* Wavefronts per replica in the HMC sweep (and in bpmf_evaluate): 1, 2 or 4,
- * or 0 for the automatic choice (4 while at most 512 replicas are set up,
- * 2 up to 2048, else 1; never fewer than ceil(n_atoms / 64)).  Results do
- * not depend on it beyond float32 rounding of the bonded-term order. */
+/* Wavefronts per replica in the HMC sweep (and in bpmf_evaluate): 1, 2, 4
+ * or 8, or 0 for the automatic choice (per ligand the smallest power of two,
+ * at most 8, whose 64 threads per wavefront cover its bonded terms, halved
+ * while replicas x wavefronts over all ligands exceed 4096).  Never fewer
+ * than ceil(n_atoms / 64).  Results depend on it only through the rounding
+ * of the per-wavefront energy and centre-of-mass partial sums. */
 BPMF_API int bpmf_set_waves(bpmf_ctx* ctx, int waves);
 
 /* bpmf_hmc_sweep replays a hipGraph of `chunk` captured sweeps (default 64;
@@ -392,6 +394,19 @@ BPMF_API int bpmf_set_waves(bpmf_ctx* ctx, int waves);
  * identical to plain launches.  With timing enabled a graph launch is timed
  * as a whole and counts as `chunk` sweep launches. */
 BPMF_API int bpmf_set_graph(bpmf_ctx* ctx, int chunk);
+
+/* Autotuner: time `n_sweeps` sweeps of n_leapfrog steps for each launch
+ * shape -- wavefronts per replica chosen automatically, or forced to 1, 2,
+ * 4, 8 (raised per ligand to the minimum its atom count needs, as in
+ * bpmf_set_waves) -- on the ligands set up, with HIP events (eager launches
+ * below the graph chunk, graph replays from it on); keep the fastest and
+ * report it in *chosen (0 = automatic).  ms_out (host, 5 doubles, may be
+ * NULL) receives the mean sweep time of each candidate in that order.  The
+ * sampler state (positions, state maps, components, counters, statistics)
+ * is snapshotted on the device before the trials and restored after, so
+ * tuning does not change the run. */
+BPMF_API int bpmf_autotune(bpmf_ctx* ctx, int n_sweeps, int n_leapfrog,
+                           double* ms_out, int* chosen);
 
 /* Wavefronts per replica the sweep currently uses for a ligand. */
 BPMF_API int bpmf_get_waves(bpmf_ctx* ctx, int ligand_id, int* waves);

@@ -105,6 +105,7 @@ def library():
         "bpmf_set_timing": [vp, C.c_int, C.c_int],
         "bpmf_set_waves": [vp, C.c_int],
         "bpmf_set_graph": [vp, C.c_int],
+        "bpmf_autotune": [vp, C.c_int, C.c_int, dp, ip],
         "bpmf_proposal_setup": [vp, C.c_int, ip, C.c_int, ip,
                                 C.POINTER(C.c_float)],
         "bpmf_proposal_params": [vp, C.c_int, C.POINTER(C.c_float),
@@ -448,6 +449,39 @@ class Context:
         _check(self._lib.bpmf_get_pose_stats(self._h, int(ligand_id), p(a),
                                              p(t), _pd(la)))
         return dict(acc=a, tries=t, last_ln_alpha=la)
+
+    def autotune(self, n_sweeps=20, n_leapfrog=10, cache_path=None,
+                 signature=None):
+        """Pick the wavefronts per replica of the HMC sweep by timing every
+        candidate on the ligands set up (state restored afterwards).  With
+        cache_path, the choice is stored in / reused from a JSON file keyed
+        by GPU architecture and `signature` (a string describing the
+        workload).  Returns (chosen, {candidate: ms})."""
+        import json
+        import os
+        arch = self._torch.cuda.get_device_properties(
+            self.device).gcnArchName
+        key = f"{arch}|{signature}"
+        if cache_path and signature and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+            if key in cache:
+                self.set_waves(cache[key]["chosen"])
+                return cache[key]["chosen"], cache[key]["ms"]
+        ms = np.zeros(5)
+        ch = C.c_int(0)
+        _check(self._lib.bpmf_autotune(self._h, int(n_sweeps),
+                                       int(n_leapfrog), _pd(ms), C.byref(ch)))
+        table = {str(w): float(m) for w, m in zip(("auto", 1, 2, 4, 8), ms)}
+        if cache_path and signature:
+            cache = {}
+            if os.path.exists(cache_path):
+                with open(cache_path) as fh:
+                    cache = json.load(fh)
+            cache[key] = {"chosen": ch.value, "ms": table}
+            with open(cache_path, "w") as fh:
+                json.dump(cache, fh, indent=1)
+        return ch.value, table
 
     def set_graph(self, chunk):
         """Replay sweeps as hipGraphs of `chunk` sweeps (0 = plain)."""

@@ -57,6 +57,7 @@ struct Arena {
 struct LigHost {
   LigDev dev;      // device pointers inside the ligand's arena
   void* arena;     // owning allocation
+  size_t state_bytes;  // arena prefix holding everything but the samples
   int min_waves;   // wavefronts needed to give every atom a thread
   int sweep_waves; // wavefronts per replica in the HMC sweep
   uint64_t counter;   // host mirror of *dev.counter
@@ -653,6 +654,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.samp_x = (float*)(base + o_sx);
   L.samp_c = (double*)(base + o_sc);
   h.arena = base;
+  h.state_bytes = o_sx;
   h.min_waves = min_waves;
   h.sweep_waves = min_waves;
   h.counter = 0;
@@ -1521,5 +1523,87 @@ extern "C" int bpmf_set_graph(bpmf_ctx* c, int chunk) {
     return fail(BPMF_E_INVAL, "chunk must be 0 (no graph) .. 4096");
   c->graph_chunk = chunk;
   c->drop_graph();
+  return BPMF_OK;
+}
+
+// ============================================================================
+// autotuner: wavefronts per replica
+// ============================================================================
+extern "C" int bpmf_autotune(bpmf_ctx* c, int n_sweeps, int n_leapfrog,
+                             double* ms_out, int* chosen) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->ligs.empty()) return fail(BPMF_E_STATE, "no ligand set up");
+  if (n_sweeps < 1 || n_leapfrog < 1)
+    return fail(BPMF_E_INVAL, "n_sweeps and n_leapfrog must be >= 1");
+  // snapshot every ligand's state (all but its sample store) on the device
+  size_t total = 0;
+  for (auto& h : c->ligs) total += (h.state_bytes + 255) / 256 * 256;
+  char* snap = (char*)c->dalloc(total);
+  if (!snap) return fail(BPMF_E_NOMEM, "autotune snapshot allocation failed");
+  std::vector<std::pair<uint64_t, int64_t>> mirror;
+  for (auto& h : c->ligs) mirror.emplace_back(h.counter, h.n_rec);
+  auto copy_all = [&](bool save) -> int {
+    size_t off = 0;
+    if (!save)
+      for (size_t l = 0; l < c->ligs.size(); ++l) {
+        c->ligs[l].counter = mirror[l].first;
+        c->ligs[l].n_rec = mirror[l].second;
+      }
+    for (auto& h : c->ligs) {
+      char* a = (char*)h.arena;
+      HIP_TRY(hipMemcpyAsync(save ? snap + off : a, save ? a : snap + off,
+                             h.state_bytes, hipMemcpyDeviceToDevice,
+                             c->stream));
+      off += (h.state_bytes + 255) / 256 * 256;
+    }
+    return BPMF_OK;
+  };
+  const int old_override = c->waves_override;
+  const bool old_timing = c->timing;
+  const int old_every = c->timing_every;
+  const int cand[5] = {0, 1, 2, 4, 8};
+  double best = INFINITY;
+  int best_w = 0;
+  if ((rc = copy_all(true))) {
+    c->dfree(snap);
+    return rc;
+  }
+  for (int q = 0; q < 5; ++q) {
+    double ms = INFINITY;
+    {
+      c->waves_override = cand[q];
+      if ((rc = rebuild_tables(c))) break;
+      bpmf_sweep_args a{2, n_leapfrog, 1, 0, 1, 0};
+      if ((rc = bpmf_hmc_sweep(c, &a))) break;
+      c->timing = true;
+      c->timing_every = 1;
+      c->launches[BPMF_TIMER_HMC] = 0;
+      c->ev_used[BPMF_TIMER_HMC] = 0;
+      a.n_sweeps = n_sweeps;
+      if ((rc = bpmf_hmc_sweep(c, &a))) break;
+      int64_t cnt = 0;
+      if ((rc = bpmf_get_timing(c, BPMF_TIMER_HMC, &ms, &cnt))) break;
+      if ((rc = copy_all(false))) break;
+      if (ms < best) {
+        best = ms;
+        best_w = cand[q];
+      }
+    }
+    if (ms_out) ms_out[q] = ms;
+  }
+  c->timing = old_timing;
+  c->timing_every = old_every;
+  if (!rc) (void)copy_all(false);
+  (void)hipStreamSynchronize(c->stream);
+  c->dfree(snap);
+  if (rc) {
+    c->waves_override = old_override;
+    (void)rebuild_tables(c);
+    return rc;
+  }
+  c->waves_override = best_w;
+  if ((rc = rebuild_tables(c))) return rc;
+  if (chosen) *chosen = best_w;
   return BPMF_OK;
 }

@@ -116,19 +116,23 @@ def grid_axes(n, h):
 
 
 def grids_from_points(points, q, sigma, eps, n, h, delta=GRID_DELTA,
-                      cap=GRID_CAP, chunk=None):
+                      cap=GRID_CAP, chunk=None, device=None):
     """Receptor grids on an n^3 lattice from point atoms (see module doc).
 
     Returns float32 nodes (n, n, n, 3) with channels (rep^(1/4), att, ele).
+    device: torch device for the float64 sums (default CPU; the large
+    lattices are generated on a GPU in seconds).  Both run the same
+    operations in the same order; results may differ in the last bits.
     """
-    import torch  # CPU float64, multi-threaded; only input generation
+    import torch  # float64 elementwise sums; only input generation
+    dev = torch.device(device) if device is not None else torch.device("cpu")
     origin, ax = grid_axes(n, h)
-    axt = torch.from_numpy(ax)
+    axt = torch.from_numpy(ax).to(dev)
     P = torch.from_numpy(np.asarray(points, np.float64))
     c_rep = torch.from_numpy(2.0 * np.sqrt(eps) * sigma ** 6)
     c_att = torch.from_numpy(2.0 * np.sqrt(eps) * sigma ** 3)
     c_ele = torch.from_numpy(COULOMB * np.asarray(q, np.float64))
-    rep = torch.zeros((n, n, n), dtype=torch.float64)
+    rep = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
     att = torch.zeros_like(rep)
     ele = torch.zeros_like(rep)
     d2 = delta * delta
@@ -154,7 +158,7 @@ def grids_from_points(points, q, sigma, eps, n, h, delta=GRID_DELTA,
     att.clamp_(-cap, cap)
     ele.clamp_(-cap, cap)
     out = torch.stack([rep.pow(0.25), att, ele], dim=-1)
-    return out.numpy().astype(np.float32)
+    return out.cpu().numpy().astype(np.float32)
 
 
 def make_receptor(rng, n_points, edge, pocket_radius, avoid_xyz=None,
@@ -361,10 +365,11 @@ _GRID_CACHE = {}
 
 
 def make_system(config: int, n_ligands: Optional[int] = None,
-                with_grid: bool = True) -> System:
+                with_grid: bool = True, grid_device=None) -> System:
     """Build config `config` (1..5).  n_ligands truncates the ligand list of
     the batched configs (the first n_ligands ligands are identical to the
-    full system's)."""
+    full system's).  grid_device: torch device that sums the receptor grids
+    (see grids_from_points)."""
     c = CONFIGS[config]
     gen_seed = 100 + config
     rng = np.random.default_rng(gen_seed)
@@ -383,13 +388,14 @@ def make_system(config: int, n_ligands: Optional[int] = None,
     n, h = c["n"], 0.25
     edge = (n - 1) * h
     if with_grid:
-        key = (config, len(counts))
+        key = (config, len(counts), str(grid_device))
         if key not in _GRID_CACHE:
             rrng = np.random.default_rng([gen_seed, 7])
             avoid = np.concatenate([l.x0[0] for l in ligs], axis=0)
             pts, q, sig, eps = make_receptor(rrng, c["n_rec"], edge,
                                              0.3 * edge, avoid_xyz=avoid)
-            _GRID_CACHE[key] = grids_from_points(pts, q, sig, eps, n, h)
+            _GRID_CACHE[key] = grids_from_points(pts, q, sig, eps, n, h,
+                                                 device=grid_device)
         nodes = _GRID_CACHE[key].copy()
     else:
         nodes = np.zeros((0, 0, 0, 3), np.float32)

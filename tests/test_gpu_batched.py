@@ -1,0 +1,138 @@
+"""Batched sampling of many ligands of uneven size in one context: every
+ligand's replicas go through the same per-sweep launches (grouped by the
+number of wavefronts a replica uses), each ligand with its own ladder,
+Philox stream, exchange and sample store.  Parity is lock-step against one
+oracle sampler per checked ligand (tests/lockstep.py), at test size and on
+sampled ligands of the full 256-ligand, 160^3-grid workload; the autotuner
+must leave the sampler state untouched.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import make_context, print_case, require_gpu, torch
+from lockstep import lockstep
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _uneven_ligands():
+    """The 24-atom, 8-state ligand plus batched-workload ligands (32 states
+    each) spanning 10..80 atoms, so that one and two wavefront replicas
+    share a sweep."""
+    c1 = synth.make_system(1)
+    c3 = synth.make_system(3, n_ligands=60, with_grid=False)
+    counts = np.array([l.n_atoms for l in c3.ligands])
+    pick = [int(np.argmin(counts)), int(np.argmax(counts)),
+            int(np.argsort(counts)[len(counts) // 2]),
+            int(np.nonzero(counts > 64)[0][0])]
+    ligs = [c1.ligands[0]] + [c3.ligands[i] for i in dict.fromkeys(pick)]
+    return c1.grid, ligs
+
+
+@pytest.mark.parametrize("waves", [0, 4])
+def test_lockstep_uneven_batch(waves):
+    g, ligs = _uneven_ligands()
+    print_case("batched lockstep", [l.n_atoms for l in ligs], "waves", waves)
+    ctx, ids = make_context(g, ligs, seed=41)
+    ctx.set_waves(waves)
+    used = [ctx.get_waves(i) for i in ids]
+    for lig, w in zip(ligs, used):
+        assert w >= -(-lig.n_atoms // 64)
+    if waves == 0:
+        assert len(set(used)) >= 2       # several launch shapes in one sweep
+    n = lockstep(ctx, oracle.OGrid(g), list(zip(ids, ligs)), 41, 3, 10,
+                 "uneven")
+    assert sum(n.values()) >= len(ligs)
+    ctx.close()
+
+
+def _state(ctx, lid):
+    st = ctx.get_replicas(lid)
+    xs, cs = ctx.get_samples(lid)
+    return st, ctx.get_stats(lid), xs, cs
+
+
+def _same(a, b):
+    (sa, ta, xa, ca), (sb, tb, xb, cb) = a, b
+    for key in ("x", "state_of_replica", "comps", "counter"):
+        if not np.array_equal(sa[key], sb[key]):
+            return key
+    for key in ("hmc_acc", "hmc_try", "ex_acc", "ex_try", "nonfinite"):
+        if not np.array_equal(ta[key], tb[key]):
+            return key
+    if not (np.array_equal(xa, xb) and np.array_equal(ca, cb)):
+        return "samples"
+    return None
+
+
+def test_autotune_leaves_state_unchanged(tmp_path):
+    g, ligs = _uneven_ligands()
+    print_case("autotune state")
+    a, ids = make_context(g, ligs, seed=5, capacity=12)
+    a.hmc_sweep(3, 10, exchange_every=1, sample_every=1)
+    before = [_state(a, i) for i in ids]
+    cache = tmp_path / "tune.json"
+    chosen, table = a.autotune(n_sweeps=4, n_leapfrog=10,
+                               cache_path=str(cache), signature="uneven")
+    assert chosen in (0, 1, 2, 4, 8)
+    assert np.isfinite(table[str(chosen) if chosen else "auto"])
+    after = [_state(a, i) for i in ids]
+    for i, (x, y) in enumerate(zip(before, after)):
+        assert _same(x, y) is None, (i, _same(x, y))
+    # the run continues as if tuned from the start of its second half
+    a.hmc_sweep(5, 10, exchange_every=1, sample_every=1)
+    b, ids_b = make_context(g, ligs, seed=5, capacity=12)
+    b.hmc_sweep(3, 10, exchange_every=1, sample_every=1)
+    b.set_waves(chosen)
+    b.hmc_sweep(5, 10, exchange_every=1, sample_every=1)
+    for i, j in zip(ids, ids_b):
+        assert _same(_state(a, i), _state(b, j)) is None, i
+    # the cached choice is reused without timing
+    rec = json.loads(cache.read_text())
+    assert len(rec) == 1 and list(rec.values())[0]["chosen"] == chosen
+    again, table2 = b.autotune(cache_path=str(cache), signature="uneven")
+    assert again == chosen and table2 == table
+    a.close()
+    b.close()
+
+
+def test_full_batched_workload_sampled_ligands():
+    """All 256 ligands (10..80 atoms, 32 states each) on the shared 160^3
+    grid, tuned as the benchmark tunes them: two lock-step sweeps checked on
+    sampled ligands, then a 64-sweep graph replay that must equal plain
+    launches bit for bit on every ligand."""
+    system = synth.make_system(3, grid_device="cuda:0")
+    g, ligs = system.grid, system.ligands
+    counts = np.array([l.n_atoms for l in ligs])
+    print_case("c3 full", len(ligs), counts.min(), counts.max())
+    ctx, ids = make_context(g, ligs, seed=system.seed)
+    chosen, _ = ctx.autotune(n_sweeps=8, n_leapfrog=system.n_leapfrog)
+    print_case("c3 waves", chosen)
+    check = sorted({0, int(np.argmin(counts)), int(np.argmax(counts)),
+                    len(ligs) // 2, len(ligs) - 1})
+    lockstep(ctx, oracle.OGrid(g), [(ids[i], ligs[i]) for i in check],
+             system.seed, 2, system.n_leapfrog, "c3")
+    ref, ids_r = make_context(g, ligs, seed=system.seed)
+    ref.set_waves(chosen)
+    ref.set_graph(0)
+    ref.hmc_sweep(2, system.n_leapfrog, exchange_every=1)
+    ctx.hmc_sweep(64, system.n_leapfrog, exchange_every=1)
+    ref.hmc_sweep(64, system.n_leapfrog, exchange_every=1)
+    torch.cuda.synchronize()
+    for i, j in zip(ids, ids_r):
+        a, b = ctx.get_replicas(i), ref.get_replicas(j)
+        for key in ("x", "state_of_replica", "comps", "counter"):
+            assert np.array_equal(a[key], b[key]), (i, key)
+    acc = np.concatenate([ctx.get_stats(i)["hmc_acc"] for i in ids])
+    assert acc.sum() > 0.5 * 66 * 32 * len(ids)
+    ctx.close()
+    ref.close()

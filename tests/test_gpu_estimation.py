@@ -52,7 +52,7 @@ def test_energy_matrix_full_size_config2_sampled_entries():
     """64 states x 32000 samples (the production u_kn of the 48-atom
     system), checked on 1000 sampled entries against brute force."""
     print_case("energy_matrix c2 full size")
-    system = synth.make_system(2)
+    system = synth.make_system(2, grid_device="cuda:0")
     lig, g = system.ligands[0], system.grid
     rng = np.random.default_rng(2)
     N = 64 * 500
@@ -144,7 +144,7 @@ def test_mbar_production_ladder_full_size():
     u_kn 64 x 32000 recomputed from the recorded samples, device MBAR
     against the oracle's MBAR on the same matrix."""
     print_case("mbar c2 full size")
-    system = synth.make_system(2)
+    system = synth.make_system(2, grid_device="cuda:0")
     lig, g = system.ligands[0], system.grid
     ctx, (lid,) = make_context(g, [lig], seed=system.seed, capacity=500)
     ctx.hmc_sweep(5000, 20, exchange_every=1, sample_every=10)

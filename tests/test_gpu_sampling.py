@@ -2,11 +2,12 @@
 Verlet + Metropolis, Sampling section), replica exchange (Eq. repXacc),
 sample recording, checkpoint/resume and determinism.
 
-Lock-step parity: before every sweep the oracle is set to the GPU's state,
-both run one sweep with the same Philox streams, and the results must agree:
-positions to 1e-4 A, accept decisions exactly except where the oracle's own
-margin |ln u + beta dH| < 1e-3 (there float32 rounding may decide), state
-maps exactly unless an exchange exponent lies within 1e-6 of its uniform.
+Lock-step parity (tests/lockstep.py): before every sweep the oracle is set
+to the GPU's state, both run one sweep with the same Philox streams, and the
+results must agree: positions to 1e-4 A, accept decisions exactly except
+where the oracle's own margin |ln u + beta dH| < 1e-3 (there float32
+rounding may decide), state maps exactly unless an exchange exponent lies
+within 1e-6 of its uniform.
 """
 import numpy as np
 import pytest
@@ -14,6 +15,7 @@ import pytest
 import oracle
 import synth
 from gpu_util import dev, make_context, print_case, require_gpu, torch
+from lockstep import lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -21,33 +23,6 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     require_gpu()
-
-
-def _sync_oracle(s, st):
-    s.x = np.ascontiguousarray(st["x"].astype(np.float64))
-    s.state = np.ascontiguousarray(st["state_of_replica"].astype(np.int32))
-    s.rep_of_state = np.ascontiguousarray(np.argsort(s.state).astype(np.int32))
-    s.comps = np.ascontiguousarray(st["comps"].copy())
-    s.sweep_count = int(st["counter"])
-
-
-def _exchange_margins(ol, comps, rep_of_state, sweep, seed, lig):
-    """|ln u + delta| of every neighbour attempt the oracle makes this sweep
-    (even/odd scheme)."""
-    K = ol.K
-    out = []
-    beta = 1.0 / (oracle.R_GAS * ol.T)
-    ros = rep_of_state.copy()
-    for a in range(sweep & 1, K - 1, 2):
-        ra, rb = ros[a], ros[a + 1]
-
-        def E(k, r):
-            return comps[r, 0] + ol.w[k] @ comps[r, 1:]
-        delta = beta[a] * (E(a, rb) - E(a, ra)) + \
-            beta[a + 1] * (E(a + 1, ra) - E(a + 1, rb))
-        lnu = np.log(oracle.uniform(seed, a, lig, 0, sweep, 3 | (1 << 8)))
-        out.append(abs(lnu + delta))
-    return np.array(out) if out else np.array([np.inf])
 
 
 def _lockstep(g, lig, seed, n_sweeps, nleap, label, x0=None, waves=0):
@@ -58,40 +33,12 @@ def _lockstep(g, lig, seed, n_sweeps, nleap, label, x0=None, waves=0):
     ctx.set_waves(waves)
     if waves:
         assert ctx.get_waves(lid) == max(waves, -(-lig.n_atoms // 64))
-    og, ol = oracle.OGrid(g), oracle.OLigand(lig)
-    s = oracle.Sampler(og, ol, seed=seed, lig_id=lid, x0=lig.x0)
-    n_checked = 0
-    for sweep in range(n_sweeps):
-        st = ctx.get_replicas(lid)
-        _sync_oracle(s, st)
-        state_before = s.state.copy()
-        acc, dH, lnu = s.hmc(nleap)
-        ex_margin = _exchange_margins(ol, s.comps, s.rep_of_state,
-                                      s.sweep_count, seed, lid)
-        s.exchange()
-        s.sweep_count += 1
-        ctx.hmc_sweep(1, nleap, exchange_every=1)
-        st2 = ctx.get_replicas(lid)
-        beta = 1.0 / (oracle.R_GAS * lig.T[state_before])
-        ok = np.abs(lnu + beta * dH) > 1e-3
-        err = np.abs(st2["x"].astype(np.float64) - s.x).max(axis=(1, 2))
-        assert np.all(err[ok] < 1e-4), (label, sweep, err)
-        if np.all(ok):
-            n_checked += 1
-            # cached components of every replica
-            t, m, _ = oracle.energy_batch(og, ol, s.x,
-                                          np.zeros((ol.K, og.nc)))
-            S = m.sum(axis=1)
-            assert np.all(np.abs(st2["comps"] - s.comps) <= 1e-5 * S[:, None]
-                          + 1e-9), (label, sweep)
-            if ex_margin.min() > 1e-6:
-                assert np.array_equal(st2["state_of_replica"], s.state), \
-                    (label, sweep)
-        assert int(st2["counter"]) == sweep + 1
+    n = lockstep(ctx, oracle.OGrid(g), [(lid, lig)], seed, n_sweeps, nleap,
+                 label)
     stats = ctx.get_stats(lid)
-    assert stats["hmc_try"].sum() == n_sweeps * ol.K
+    assert stats["hmc_try"].sum() == n_sweeps * lig.n_states
     ctx.close()
-    return n_checked
+    return n[lid]
 
 
 @pytest.mark.parametrize("waves", [0, 1, 2, 4])
