@@ -381,10 +381,12 @@ BPMF_API int bpmf_get_pose_stats(bpmf_ctx* ctx, int ligand_id, int64_t* acc,
 
 /* Wavefronts per replica in the HMC sweep (and in bpmf_evaluate): 1, 2, 4
  * or 8, or 0 for the automatic choice (per ligand the smallest power of two,
- * at most 8, whose 64 threads per wavefront cover its bonded terms, halved
- * while replicas x wavefronts over all ligands exceed 4096).  Never fewer
- * than ceil(n_atoms / 64).  Results depend on it only through the rounding
- * of the per-wavefront energy and centre-of-mass partial sums. */
+ * at most 8, that gives every bonded term a thread -- each kind of term
+ * starting on a wavefront boundary, and from four wavefronts on only the
+ * wavefronts without atoms taking terms -- halved while replicas x
+ * wavefronts over all ligands exceed 4096).  Never fewer than
+ * ceil(n_atoms / 64).  Results depend on it only through the rounding of
+ * the per-wavefront energy partial sums. */
 BPMF_API int bpmf_set_waves(bpmf_ctx* ctx, int waves);
 
 /* bpmf_hmc_sweep replays a hipGraph of `chunk` captured sweeps (default 64;

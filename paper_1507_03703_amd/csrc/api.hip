@@ -205,12 +205,21 @@ int lds_of(const LigHost& h, int waves, bool forces) {
 int choose_waves(const bpmf_ctx* c, const LigHost& h, int total_replicas) {
   int w = c->waves_override ? c->waves_override : 1;
   if (!c->waves_override) {
-    // enough waves to give every bonded term its own thread while the chip
-    // has room for them (latency-bound ladders), fewer when replicas alone
-    // fill the chip
-    const int terms = h.dev.nb + h.dev.na + h.dev.nt;
+    // enough waves to give every slot of the wave-aligned bonded index its
+    // own thread while the chip has room for them (latency-bound ladders),
+    // fewer when replicas alone fill the chip; from four waves on the atom
+    // waves leave the bonded terms to the others
+    const int pad = kWave - 1;
+    const int index = ((h.dev.nt + pad) & ~pad) + ((h.dev.na + pad) & ~pad) +
+                      h.dev.nb;
+    const int atom_waves = (h.dev.n + pad) / kWave;
+    auto bonded_threads = [&](int waves) {
+      const int first =
+          (waves >= 4 && waves >= 2 * atom_waves) ? atom_waves : 0;
+      return (waves - first) * kWave;
+    };
     int want = 1;
-    while (want < 8 && want * kWave < terms) want *= 2;
+    while (want < 8 && bonded_threads(want) < index) want *= 2;
     while (want > 1 && total_replicas * want > 4096) want /= 2;
     w = want;
   }

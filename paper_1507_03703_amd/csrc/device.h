@@ -62,6 +62,32 @@ __device__ __forceinline__ float wave_sumf(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// three independent sums with the stages interleaved (each value sees the
+// same additions in the same order as wave_sumf)
+__device__ __forceinline__ void wave_sumf3(float& a, float& b, float& c) {
+  a += dpp_f<0xB1, 0xf>(a);
+  b += dpp_f<0xB1, 0xf>(b);
+  c += dpp_f<0xB1, 0xf>(c);
+  a += dpp_f<0x4E, 0xf>(a);
+  b += dpp_f<0x4E, 0xf>(b);
+  c += dpp_f<0x4E, 0xf>(c);
+  a += dpp_f<0x141, 0xf>(a);
+  b += dpp_f<0x141, 0xf>(b);
+  c += dpp_f<0x141, 0xf>(c);
+  a += dpp_f<0x140, 0xf>(a);
+  b += dpp_f<0x140, 0xf>(b);
+  c += dpp_f<0x140, 0xf>(c);
+  a += dpp_f<0x142, 0xa>(a);
+  b += dpp_f<0x142, 0xa>(b);
+  c += dpp_f<0x142, 0xa>(c);
+  a += dpp_f<0x143, 0xc>(a);
+  b += dpp_f<0x143, 0xc>(b);
+  c += dpp_f<0x143, 0xc>(c);
+  a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 63));
+  b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 63));
+  c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c), 63));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_d<0xB1, 0xf>(v);
   v += dpp_d<0x4E, 0xf>(v);
@@ -255,30 +281,42 @@ __device__ __forceinline__ float3 scale3(float s, float3 a) {
   return make_float3(s * a.x, s * a.y, s * a.z);
 }
 
-// Per-atom force accumulators in LDS, in 64-bit fixed point (2^-24
+// Per-atom force accumulators in LDS, in 32-bit fixed point (2^-16
 // kJ/mol/A per unit): every bonded-term thread adds its contribution to
 // each of its atoms with an integer LDS atomic.  Integer addition is
 // associative, so the sums do not depend on the order in which threads
-// arrive and results stay bitwise reproducible; the quantisation (6e-8
-// kJ/mol/A per contribution) is far below float32 force resolution.
-constexpr float kFix = 16777216.0f;       // 2^24
-constexpr float kFixInv = 1.0f / 16777216.0f;
-constexpr float kFixMax = 1.0e11f;        // |f| clamp keeps f * 2^24 < 2^63
+// arrive and results stay bitwise reproducible.  Quantisation is 7.6e-6
+// kJ/mol/A per contribution; a contribution is clamped to +-32767 kJ/mol/A
+// (a bonded force that large only arises on a diverging trajectory, which
+// the exact energy rejects; leapfrog with any deterministic force keeps HMC
+// exact).
+constexpr float kFix = 65536.0f;          // 2^16
+constexpr float kFixInv = 1.0f / 65536.0f;
+constexpr float kFixMax = 32767.0f;
 
-__device__ __forceinline__ unsigned long long to_fix(float f) {
-  // NaN compares false and becomes 0; the energy still carries the NaN
-  f = fminf(fmaxf(f, -kFixMax), kFixMax);
-  return (unsigned long long)(long long)llrintf(f * kFix);
+__device__ __forceinline__ unsigned int to_fix(float f) {
+  // NaN becomes 0; the energy still carries the NaN
+  f = (f == f) ? fminf(fmaxf(f, -kFixMax), kFixMax) : 0.f;
+  return (unsigned int)__float2int_rn(f * kFix);
+}
+
+__device__ __forceinline__ float from_fix(unsigned int a) {
+  return (float)(int)a * kFixInv;
 }
 
 struct Slots {
-  unsigned long long* acc;  // n x 3
+  unsigned int* acc;  // n x 3
   __device__ __forceinline__ void put(int atom, float3 f) const {
     atomicAdd(&acc[3 * atom], to_fix(f.x));
     atomicAdd(&acc[3 * atom + 1], to_fix(f.y));
     atomicAdd(&acc[3 * atom + 2], to_fix(f.z));
   }
 };
+
+// hardware reciprocal (1 ulp), for the bonded-term geometry
+__device__ __forceinline__ float rcp(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
 
 __device__ __forceinline__ int atom_of(int p) { return p; }
 __device__ __forceinline__ int slot_of(int p) { return p; }
@@ -291,7 +329,7 @@ __device__ __forceinline__ float bond_term(const float4* pos, int2 ij,
   const float r = sqrtf(dot(d, d));
   const float dr = r - par.y;
   if (FORCES) {
-    const float f = -2.0f * par.x * dr / r;
+    const float f = -2.0f * par.x * dr * rcp(r);
     sl.put(slot_of(ij.x), scale3(f, d));
     sl.put(slot_of(ij.y), scale3(-f, d));
   }
@@ -312,8 +350,8 @@ __device__ __forceinline__ float angle_term(const float4* pos, int4 ijk,
   if (FORCES) {
     const float la = sqrtf(dot(a, a)), lb = sqrtf(dot(b, b));
     const float dE = 2.0f * par.x * dth;
-    const float ila = 1.0f / la, ilb = 1.0f / lb;
-    const float cth = co * ila * ilb, isth = la * lb / s;
+    const float ila = rcp(la), ilb = rcp(lb);
+    const float cth = co * ila * ilb, isth = la * lb * rcp(s);
     const float3 ah = scale3(ila, a), bh = scale3(ilb, b);
     // d theta / d xi = (cos a^ - b^) / (|a| sin), d theta / d xk likewise
     const float ci = dE * isth * ila, ck = dE * isth * ilb;
@@ -363,8 +401,8 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
   const float snm = sn * cg - cn * sg;
   if (FORCES) {
     const float dE = -par.x * par.y * snm;
-    const float in1 = 1.0f / dot(n1, n1), in2 = 1.0f / dot(n2, n2);
-    const float ilb2 = 1.0f / lb2;
+    const float in1 = rcp(dot(n1, n1)), in2 = rcp(dot(n2, n2));
+    const float ilb2 = rcp(lb2);
     const float p12 = dot(b1, b2) * ilb2 * in1;
     const float p23 = dot(b2, b3) * ilb2 * in2;
     const float3 gi = scale3(-lb2 * in1, n1);
@@ -386,10 +424,17 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
 // ----------------------------------------------------------------------------
 // one full evaluation of a configuration by one workgroup of W wavefronts
 // ----------------------------------------------------------------------------
-// Thread t owns atom t (n <= 64 W).  Bonded terms are spread over all 64 W
-// threads; the grid gathers of the owners are issued before the bonded pass
-// so that their latency overlaps it (a workgroup barrier on gfx950 waits on
-// LDS traffic only, not on outstanding global loads).
+// Thread t owns atom t (n <= 64 W); the A = ceil(n / 64) wavefronts that
+// hold atoms are the atom waves.  Bonded terms run on bonded_first_wave(..)
+// onwards: with four or more wavefronts and at least as many spare as atom
+// waves, only the spare ones take bonded terms, so that the atom waves'
+// restraint and grid interpolation run beside them; otherwise every thread
+// takes terms.  The term index is segmented (torsions, angles, bonds) with
+// every segment starting on a wavefront boundary, so a wavefront never
+// diverges over term kinds.  The owners' grid gathers are issued before the
+// first barrier so that their latency overlaps the bonded pass (a workgroup
+// barrier on gfx950 waits on LDS traffic only, not on outstanding global
+// loads).
 //
 // Shared memory (Shared): positions, force slots, per-wave partial sums.
 struct Shared {
@@ -441,6 +486,11 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
 
 constexpr int kRedMax = kRedSlots;  // U_bond..U_tors, Psi_c, two extras
 
+// first wavefront that takes bonded terms (see eval_block)
+__device__ __forceinline__ int bonded_first_wave(int waves, int atom_waves) {
+  return (waves >= 4 && waves >= 2 * atom_waves) ? atom_waves : 0;
+}
+
 __device__ __forceinline__ void block_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_barrier();
@@ -463,40 +513,53 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   const int n = L.n;
   const int lane = tid & (kWave - 1), wv = tid >> 6;
   const bool owner = tid < n;
+  const int n_atom_waves = (n + kWave - 1) / kWave;
+  const bool wave_has_atoms = wv < n_atom_waves;
   if (owner) sh.pos[tid] = make_float4(x[0], x[1], x[2], 0.f);
   Corners<C> cn;
-  const bool wave_has_atoms = wv * kWave < n;
-  if (wave_has_atoms) grid_fetch<C>(g, x[0], x[1], x[2], cn);
-  // per-wave partial mass-weighted position sums
-  float px = wave_sumf(m * x[0]), py = wave_sumf(m * x[1]),
-        pz = wave_sumf(m * x[2]);
-  if (lane == 0) {
-    sh.com[3 * wv] = px;
-    sh.com[3 * wv + 1] = py;
-    sh.com[3 * wv + 2] = pz;
+  if (wave_has_atoms) {
+    grid_fetch<C>(g, x[0], x[1], x[2], cn);
+    // per-wave partial mass-weighted position sums
+    float px = m * x[0], py = m * x[1], pz = m * x[2];
+    wave_sumf3(px, py, pz);
+    if (lane == 0) {
+      sh.com[3 * wv] = px;
+      sh.com[3 * wv + 1] = py;
+      sh.com[3 * wv + 2] = pz;
+    }
   }
   block_sync();
 
-  // bonded terms: one segmented index over torsions, angles, bonds, so
-  // that every thread takes at most ceil(terms / 64 W) terms
+  // bonded terms over the wave-aligned segmented index
   float eb = 0.f, ea = 0.f, et = 0.f;
-  constexpr int T = W * kWave;
-  const int n_terms = L.nt + L.na + L.nb;
-  for (int u = tid; u < n_terms; u += T) {
-    if (u < L.nt) {
-      et += torsion_term<FORCES>(sh.pos, sh.tijkl[u], sh.tpar[u], sh.sl);
-    } else if (u < L.nt + L.na) {
-      const int t = u - L.nt;
-      ea += angle_term<FORCES>(sh.pos, sh.aijk[t], sh.apar[t], sh.sl);
-    } else {
-      const int t = u - L.nt - L.na;
-      eb += bond_term<FORCES>(sh.pos, sh.bij[t], sh.bpar[t], sh.sl);
+  {
+    const int first = bonded_first_wave(W, n_atom_waves);
+    const int tb = tid - kWave * first;
+    const int nthr = kWave * (W - first);
+    const int ntp = (L.nt + kWave - 1) & ~(kWave - 1);
+    const int nap = (L.na + kWave - 1) & ~(kWave - 1);
+    const int n_index = ntp + nap + L.nb;
+    if (tb >= 0) {
+      for (int u = tb; u < n_index; u += nthr) {
+        if (u < ntp) {
+          if (u < L.nt)
+            et += torsion_term<FORCES>(sh.pos, sh.tijkl[u], sh.tpar[u],
+                                       sh.sl);
+        } else if (u < ntp + nap) {
+          const int t = u - ntp;
+          if (t < L.na)
+            ea += angle_term<FORCES>(sh.pos, sh.aijk[t], sh.apar[t], sh.sl);
+        } else {
+          const int t = u - ntp - nap;
+          eb += bond_term<FORCES>(sh.pos, sh.bij[t], sh.bpar[t], sh.sl);
+        }
+      }
     }
   }
-  // centre of mass (fixed-order sum of the wave partials) and restraint
+  // centre of mass (fixed-order sum of the atom waves' partials) and
+  // restraint
   float cx = 0.f, cy = 0.f, cz = 0.f;
-#pragma unroll
-  for (int q = 0; q < W; ++q) {
+  for (int q = 0; q < n_atom_waves; ++q) {
     cx += sh.com[3 * q];
     cy += sh.com[3 * q + 1];
     cz += sh.com[3 * q + 2];
@@ -508,44 +571,43 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   const float excess = d - L.d0;
   const bool restrained = excess > 0.f;
   const float fr = restrained ? -L.krest * excess / d * L.inv_total_mass : 0.f;
-  if (FORCES) block_sync();
-
+  // grid values and gradients of the atom waves (beside the bonded waves)
   float psi[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) psi[c] = 0.f;
+  float ge[3] = {0.f, 0.f, 0.f};
   if (wave_has_atoms) {
     float e[C], de[C][3];
     grid_finish<C, FORCES>(g, cn, sc, e, de);
 #pragma unroll
     for (int c = 0; c < C; ++c) psi[c] = e[c];
-    if (FORCES && owner) {
-      float fx, fy, fz;
-      // bonded forces: read and clear the atom's fixed-point accumulator
-      // (the next evaluation adds into it only after its first barrier)
-      unsigned long long* a3 = sh.sl.acc + 3 * tid;
-      fx = (float)(long long)a3[0] * kFixInv;
-      fy = (float)(long long)a3[1] * kFixInv;
-      fz = (float)(long long)a3[2] * kFixInv;
-      a3[0] = 0ull;
-      a3[1] = 0ull;
-      a3[2] = 0ull;
-      fx += fr * m * cx;
-      fy += fr * m * cy;
-      fz += fr * m * cz;
+    if (FORCES) {
+      ge[0] = fr * m * cx;
+      ge[1] = fr * m * cy;
+      ge[2] = fr * m * cz;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        fx -= w[c] * de[c][0];
-        fy -= w[c] * de[c][1];
-        fz -= w[c] * de[c][2];
+        ge[0] -= w[c] * de[c][0];
+        ge[1] -= w[c] * de[c][1];
+        ge[2] -= w[c] * de[c][2];
       }
-      f[0] = fx;
-      f[1] = fy;
-      f[2] = fz;
-    } else if (FORCES) {
+    }
+  }
+  if (FORCES) {
+    block_sync();
+    if (owner) {
+      // bonded forces: read and clear the atom's fixed-point accumulator
+      // (the next evaluation adds into it only after its first barrier)
+      unsigned int* a3 = sh.sl.acc + 3 * tid;
+      f[0] = from_fix(a3[0]) + ge[0];
+      f[1] = from_fix(a3[1]) + ge[1];
+      f[2] = from_fix(a3[2]) + ge[2];
+      a3[0] = 0u;
+      a3[1] = 0u;
+      a3[2] = 0u;
+    } else {
       f[0] = f[1] = f[2] = 0.f;
     }
-  } else if (FORCES) {
-    f[0] = f[1] = f[2] = 0.f;
   }
   if (ENERGY) {
     // per-wave sums in double, then a fixed-order sum over the waves

@@ -10,12 +10,18 @@ constexpr double kRGas = 8.314462618e-3;  // kJ/(mol K)
 #define BPMF_MAX_MBAR_STATES_DEV 128
 constexpr int kRedSlots = 4 + 8 + 2;  // per-wave partial sums (see Shared)
 
+// LDS bytes of the fixed-point force accumulators (n x 3 int32), rounded
+// up to 16 so that the topology staged after them stays 16-byte aligned
+__host__ __device__ inline int acc_lds_bytes(int n) {
+  return (12 * n + 15) & ~15;
+}
+
 // dynamic LDS bytes of a W-wave evaluation block: per-evaluation areas,
-// force accumulators (n x 3 int64, forces only) and the staged topology
+// force accumulators (forces only) and the staged topology
 inline int block_lds_bytes(int waves, bool forces, int n, int nb, int na,
                            int nt) {
   const int head = 16 * kWave * waves + 8 * waves * kRedSlots + 16 * waves +
-                   (forces ? 24 * n : 0);
+                   (forces ? acc_lds_bytes(n) : 0);
   const int topo = 32 * nt + 24 * na + 16 * nb;
   return head + topo;
 }
