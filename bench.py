@@ -107,6 +107,8 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
         tuned = {"chosen_waves": chosen or "auto", "sweep_ms": table}
     setup_s = time.perf_counter() - t_setup
     results = []
+    # MBAR of each cycle starts from the previous cycle's free energies
+    f_prev = [None] * len(ids)
 
     def step():
         for i in ids:
@@ -114,9 +116,11 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
         ctx.hmc_sweep(sweeps, L, exchange_every=1, exchange_scheme=0,
                       sample_every=every)
         out = []
-        for i, u, nk in zip(ids, ukn, Nk):
+        for q, (i, u, nk) in enumerate(zip(ids, ukn, Nk)):
             ctx.energy_matrix(i, None, n_samples=u.shape[1], out=u)
-            out.append(ctx.mbar(u, nk, tol=1e-10, max_iter=100))
+            r = ctx.mbar(u, nk, tol=1e-10, max_iter=100, f_init=f_prev[q])
+            f_prev[q] = r[0] if np.all(np.isfinite(r[0])) else None
+            out.append(r)
         return out
 
     for _ in range(warmup):

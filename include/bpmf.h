@@ -183,7 +183,9 @@ typedef struct {
 } bpmf_sweep_args;
 
 /* Run n_sweeps sweeps over every ligand.  One sweep of a ligand with
- * per-ligand counter s is:
+ * per-ligand counter s is (the order of effects; with scheme 0 the kernels
+ * apply steps 2-3 of a sweep at the start of the next one, and of the last
+ * sweep before returning):
  *   1. one HMC move per replica (Sampling: velocity-Verlet trial moves):
  *      momenta v_i ~ N(0, R T_k / m_i * 1e-4) (A/fs), n_leapfrog steps of
  *      v += dt/2 a; x += dt v; v += dt/2 a with a = F/m * 1e-4, then accept
@@ -235,10 +237,13 @@ BPMF_API int bpmf_energy_matrix(bpmf_ctx* ctx, int ligand_id, const float* dev_s
  * *n_iter.  Each iteration is a Newton step with backtracking when the
  * gauge-fixed Hessian is numerically positive definite, else one step of
  * the fixed-point equation.  Stops when the largest change of f is below
- * tol or after max_iter iterations (then *n_iter = max_iter). */
+ * tol or after max_iter iterations (then *n_iter = max_iter).  warm_start
+ * != 0: f holds the initial guess on entry (shifted so that f_0 = 0; e.g.
+ * the previous cycle's estimate), else the iteration starts from f = 0. */
 BPMF_API int bpmf_mbar(bpmf_ctx* ctx, const double* dev_ukn, int K, int64_t N,
               int64_t ld, const int64_t* N_k, double tol, int max_iter,
-              double* f, double* var, int* n_iter);
+              double* f, double* var, int* n_iter,
+                       int warm_start);
 
 /* ------------------------------------------------------------------------
  * Direct evaluation (the energy/force kernel the sampler runs, exposed)
@@ -418,11 +423,13 @@ BPMF_API int bpmf_get_waves(bpmf_ctx* ctx, int ligand_id, int* waves);
  * ------------------------------------------------------------------------ */
 enum { BPMF_TIMER_HMC = 0, BPMF_TIMER_COMPONENTS = 1, BPMF_TIMER_TAIL = 2 };
 
-/* While enabled, every `every`-th launch of each timed kernel (HMC sweep
- * kernels of one sweep -- they also run the exchange/record tail of each
- * ligand; per-sample components of energy_matrix) is bracketed by a pair of
- * HIP events recorded on the context's stream (at most 8192 pairs per
- * kernel between reads).  Enabling clears earlier records. */
+/* While enabled, every `every`-th launch of each timed kernel (HMC: the
+ * kernels of one sweep, which with scheme 0 also apply the previous sweep's
+ * exchange and record, with scheme 1 followed by the tail kernel; TAIL: the
+ * kernel that closes a scheme-0 call; COMPONENTS: per-sample components of
+ * energy_matrix) is bracketed by a pair of HIP events recorded on the
+ * context's stream (at most 8192 pairs per kernel between reads).  Enabling
+ * clears earlier records. */
 BPMF_API int bpmf_set_timing(bpmf_ctx* ctx, int enable, int every);
 
 /* Mean duration in ms of the bracketed launches of `kernel` since timing

@@ -92,7 +92,7 @@ def library():
         "bpmf_exchange": [vp, C.c_int, C.c_int, C.c_int],
         "bpmf_energy_matrix": [vp, C.c_int, vp, C.c_int64, vp, C.c_int64],
         "bpmf_mbar": [vp, vp, C.c_int, C.c_int64, C.c_int64, i64p, C.c_double,
-                      C.c_int, dp, dp, ip],
+                      C.c_int, dp, dp, ip, C.c_int],
         "bpmf_evaluate": [vp, C.c_int, vp, C.c_int64, vp, vp, vp],
         "bpmf_grid_eval": [vp, vp, vp, C.c_int64, dp, vp, vp],
         "bpmf_get_replicas": [vp, C.c_int, C.POINTER(C.c_float), ip, dp,
@@ -279,21 +279,22 @@ class Context:
                                             out.data_ptr(), out.stride(0)))
         return out
 
-    def mbar(self, ukn, N_k, tol=1e-10, max_iter=100):
+    def mbar(self, ukn, N_k, tol=1e-10, max_iter=100, f_init=None):
         """Returns (f, var, n_iter): f[K] with f[0] = 0, var[k] = asymptotic
-        variance of f_k - f_0."""
+        variance of f_k - f_0.  f_init: optional initial guess (K)."""
         torch = self._torch
         assert ukn.is_cuda and ukn.dtype == torch.float64 and ukn.stride(1) == 1
         K, N = ukn.shape
         Nk = np.ascontiguousarray(N_k, np.int64)
-        f = np.zeros(K)
+        f = np.zeros(K) if f_init is None else \
+            np.array(f_init, dtype=np.float64).reshape(K).copy()
         var = np.zeros(K)
         it = C.c_int(0)
         _check(self._lib.bpmf_mbar(self._h, ukn.data_ptr(), K, N,
                                    ukn.stride(0),
                                    Nk.ctypes.data_as(C.POINTER(C.c_int64)),
                                    float(tol), int(max_iter), _pd(f), _pd(var),
-                                   C.byref(it)))
+                                   C.byref(it), int(f_init is not None)))
         return f, var, it.value
 
     # -- direct evaluation ----------------------------------------------------

@@ -569,7 +569,10 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_sor = A.add(K * 4), o_ros = A.add(K * 4),
                o_counters = A.add(8 * 4), o_hacc = A.add(K * 8),
                o_htry = A.add(K * 8), o_eacc = A.add(Km1 * 8),
-               o_etry = A.add(Km1 * 8),
+               o_etry = A.add(Km1 * 8), o_rcnt = A.add(K * 8),
+               o_rnrec = A.add(K * 8), o_rpend = A.add(2 * K * 4),
+               o_rsor = A.add(2 * K * 4),
+               o_scomp = A.add((size_t)2 * K * C1 * 8),
                o_sx = A.add((size_t)cap * K * n * 12),
                o_sc = A.add((size_t)cap * K * C1 * 8);
   {
@@ -614,6 +617,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   chain(hipMemsetAsync(base + o_htry, 0, K * 8, c->stream));
   chain(hipMemsetAsync(base + o_eacc, 0, Km1 * 8, c->stream));
   chain(hipMemsetAsync(base + o_etry, 0, Km1 * 8, c->stream));
+  chain(hipMemsetAsync(base + o_rcnt, 0, o_sx - o_rcnt, c->stream));
   chain(hipStreamSynchronize(c->stream));
   if (e != hipSuccess) {
     c->dfree(base);
@@ -655,7 +659,11 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.counter = (unsigned long long*)(base + o_counters);
   L.n_rec = L.counter + 1;
   L.nonfinite = L.counter + 2;
-  L.arrive = (unsigned int*)(L.counter + 3);
+  L.rcnt = (unsigned long long*)(base + o_rcnt);
+  L.rnrec = (unsigned long long*)(base + o_rnrec);
+  L.rpend = (int*)(base + o_rpend);
+  L.rsor = (int*)(base + o_rsor);
+  L.scomp = (double*)(base + o_scomp);
   L.hmc_acc = (unsigned long long*)(base + o_hacc);
   L.hmc_try = (unsigned long long*)(base + o_htry);
   L.ex_acc = (unsigned long long*)(base + o_eacc);
@@ -720,6 +728,10 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
   }
   TailArgs tail{a->exchange_every, a->exchange_scheme, a->max_sep,
                 a->sample_every};
+  const int nl = (int)c->ligs.size();
+  // scheme 0: each sweep applies the previous one's exchange and record in
+  // its own blocks (begin/finish kernels bracket the run); scheme 1: a tail
+  // kernel after every sweep
   auto enqueue_sweep = [&](hipStream_t st) -> int {
     for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
       if (c->class_n[q])
@@ -727,8 +739,14 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
                                  c->d_tasks + c->class_off[q], c->class_n[q],
                                  1 << q, c->class_lds[q], a->n_leapfrog,
                                  c->seed, tail, st));
+    if (tail.scheme == 1)
+      HIP_TRY(launch_sweep_tail(c->d_ligs, nl, tail.exchange_every,
+                                tail.scheme, tail.max_sep, tail.sample_every,
+                                c->seed, st));
     return BPMF_OK;
   };
+  if (a->n_sweeps == 0) return BPMF_OK;
+  if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(c->d_ligs, nl, c->stream));
   int done = 0;
   const int chunk = c->graph_chunk;
   if (chunk > 0 && a->n_sweeps >= chunk) {
@@ -772,6 +790,14 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1);
     if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
     if ((rc = enqueue_sweep(c->stream))) return rc;
+    if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
+  }
+  if (tail.scheme == 0) {
+    hipEvent_t t0, t1;
+    const bool timed = c->timer_begin(BPMF_TIMER_TAIL, &t0, &t1);
+    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+    HIP_TRY(launch_sweep_finish(c->d_ligs, nl, tail.exchange_every,
+                                tail.sample_every, c->seed, c->stream));
     if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   }
   for (size_t l = 0; l < c->ligs.size(); ++l) {
@@ -841,7 +867,8 @@ extern "C" int bpmf_energy_matrix(bpmf_ctx* c, int ligand_id,
 
 extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
                          int64_t ld, const int64_t* N_k, double tol,
-                         int max_iter, double* f, double* var, int* n_iter) {
+                         int max_iter, double* f, double* var, int* n_iter,
+                         int warm_start) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!dev_ukn || !N_k || !f) return fail(BPMF_E_INVAL, "null MBAR argument");
@@ -858,6 +885,14 @@ extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
   }
   if (tot != N) return fail(BPMF_E_INVAL, "sum N_k = %lld != N = %lld",
                             (long long)tot, (long long)N);
+  std::vector<double> f0(K, 0.0);
+  if (warm_start) {
+    for (int k = 0; k < K; ++k) {
+      if (!std::isfinite(f[k]))
+        return fail(BPMF_E_INVAL, "non-finite initial f[%d]", k);
+      f0[k] = f[k] - f[0];
+    }
+  }
   if (K == 1) {
     f[0] = 0.0;
     if (var) var[0] = 0.0;
@@ -868,7 +903,8 @@ extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
   Arena A;
   const size_t o_f = A.add(K * 8), o_ft = A.add(K * 8), o_logN = A.add(K * 8),
                o_Nk = A.add(K * 8), o_logD = A.add((size_t)N * 8),
-               o_part = A.add((size_t)nb * (K + (size_t)K * K) * 8),
+               o_part = A.add((size_t)std::max(nb, mbar_acc_blocks(K, N)) *
+                              (K + (size_t)K * K) * 8),
                o_red = A.add((K + (size_t)K * K) * 8),
                o_mat = A.add((size_t)(K - 1) * (2 * K) * 8),
                o_step = A.add(K * 8), o_sc = A.add(8 * 8),
@@ -900,7 +936,8 @@ extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
                          c->stream));
   HIP_TRY(hipMemcpyAsync(Nk_dev, Nkd.data(), K * 8, hipMemcpyHostToDevice,
                          c->stream));
-  HIP_TRY(hipMemsetAsync(fcur, 0, K * 8, c->stream));
+  HIP_TRY(hipMemcpyAsync(fcur, f0.data(), K * 8, hipMemcpyHostToDevice,
+                         c->stream));
   double sc[4];
   auto objective = [&](const double* fv, double* out) -> int {
     HIP_TRY(mbar_logD(dev_ukn, K, N, ld, fv, s, c->stream));
@@ -917,6 +954,11 @@ extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
   double Fcur = 0;
   if ((rc = objective(fcur, &Fcur))) return rc;  // also logD at fcur
   std::vector<double> fh(K), fn(K);
+  // trust length: while accepted moves are large (>= 1 kT), the first trial
+  // of a Newton step moves no component by more than twice the last
+  // accepted move (far from the solution full Newton steps overshoot and
+  // would be halved many times)
+  double trust = INFINITY;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
     HIP_TRY(mbar_accumulate(dev_ukn, K, N, ld, fcur, s, c->stream));
@@ -927,7 +969,8 @@ extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
     double change = 0.0;
     if (sc[3] == 0.0) {
       const double maxstep = sc[1], gs = sc[2];
-      double t = 1.0, Ftry = 0.0;
+      double t = trust >= 1.0 ? std::min(1.0, 2.0 * trust / maxstep) : 1.0;
+      double Ftry = 0.0;
       for (int ls = 0; ls < 60; ++ls) {
         HIP_TRY(mbar_axpy(K, fcur, s.step, t, ftry, c->stream));
         if ((rc = objective(ftry, &Ftry))) return rc;
@@ -940,6 +983,7 @@ extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
       s.f = fcur;
       Fcur = Ftry;
       change = t * maxstep;
+      trust = change;
     } else {
       // fixed-point step from fcur (logD is current for fcur)
       HIP_TRY(hipMemcpyAsync(fh.data(), fcur, K * 8, hipMemcpyDeviceToHost,

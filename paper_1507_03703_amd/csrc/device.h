@@ -515,25 +515,19 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   const bool owner = tid < n;
   const int n_atom_waves = (n + kWave - 1) / kWave;
   const bool wave_has_atoms = wv < n_atom_waves;
+  const int first = bonded_first_wave(W, n_atom_waves);
   if (owner) sh.pos[tid] = make_float4(x[0], x[1], x[2], 0.f);
+  // grid gathers: before the barrier when the atom waves also take bonded
+  // terms (the loads fly during them), after it when they do not (the
+  // bonded waves then start without waiting for the address work)
   Corners<C> cn;
-  if (wave_has_atoms) {
-    grid_fetch<C>(g, x[0], x[1], x[2], cn);
-    // per-wave partial mass-weighted position sums
-    float px = m * x[0], py = m * x[1], pz = m * x[2];
-    wave_sumf3(px, py, pz);
-    if (lane == 0) {
-      sh.com[3 * wv] = px;
-      sh.com[3 * wv + 1] = py;
-      sh.com[3 * wv + 2] = pz;
-    }
-  }
+  if (wave_has_atoms && first == 0) grid_fetch<C>(g, x[0], x[1], x[2], cn);
   block_sync();
+  if (wave_has_atoms && first != 0) grid_fetch<C>(g, x[0], x[1], x[2], cn);
 
   // bonded terms over the wave-aligned segmented index
   float eb = 0.f, ea = 0.f, et = 0.f;
   {
-    const int first = bonded_first_wave(W, n_atom_waves);
     const int tb = tid - kWave * first;
     const int nthr = kWave * (W - first);
     const int ntp = (L.nt + kWave - 1) & ~(kWave - 1);
@@ -556,35 +550,29 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
       }
     }
   }
-  // centre of mass (fixed-order sum of the atom waves' partials) and
-  // restraint
-  float cx = 0.f, cy = 0.f, cz = 0.f;
-  for (int q = 0; q < n_atom_waves; ++q) {
-    cx += sh.com[3 * q];
-    cy += sh.com[3 * q + 1];
-    cz += sh.com[3 * q + 2];
-  }
-  cx = cx * L.inv_total_mass - L.site[0];
-  cy = cy * L.inv_total_mass - L.site[1];
-  cz = cz * L.inv_total_mass - L.site[2];
-  const float d = sqrtf(cx * cx + cy * cy + cz * cz);
-  const float excess = d - L.d0;
-  const bool restrained = excess > 0.f;
-  const float fr = restrained ? -L.krest * excess / d * L.inv_total_mass : 0.f;
-  // grid values and gradients of the atom waves (beside the bonded waves)
+
+  // atom waves: mass-weighted position sums (restraint) and the grid
+  // values and gradients, beside the bonded waves
   float psi[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) psi[c] = 0.f;
   float ge[3] = {0.f, 0.f, 0.f};
+  float px = 0.f, py = 0.f, pz = 0.f;
   if (wave_has_atoms) {
+    px = m * x[0];
+    py = m * x[1];
+    pz = m * x[2];
+    wave_sumf3(px, py, pz);
+    if (lane == 0) {
+      sh.com[3 * wv] = px;
+      sh.com[3 * wv + 1] = py;
+      sh.com[3 * wv + 2] = pz;
+    }
     float e[C], de[C][3];
     grid_finish<C, FORCES>(g, cn, sc, e, de);
 #pragma unroll
     for (int c = 0; c < C; ++c) psi[c] = e[c];
     if (FORCES) {
-      ge[0] = fr * m * cx;
-      ge[1] = fr * m * cy;
-      ge[2] = fr * m * cz;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         ge[0] -= w[c] * de[c][0];
@@ -593,9 +581,43 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
       }
     }
   }
+  // centre of mass offset from the site (fixed-order sum of the atom waves'
+  // partials; with one atom wave its own sums are the total)
+  float cx, cy, cz;
+  auto com_offset = [&]() {
+    if (n_atom_waves == 1 && wv == 0) {
+      cx = px;
+      cy = py;
+      cz = pz;
+    } else {
+      cx = cy = cz = 0.f;
+      for (int q = 0; q < n_atom_waves; ++q) {
+        cx += sh.com[3 * q];
+        cy += sh.com[3 * q + 1];
+        cz += sh.com[3 * q + 2];
+      }
+    }
+    cx = cx * L.inv_total_mass - L.site[0];
+    cy = cy * L.inv_total_mass - L.site[1];
+    cz = cz * L.inv_total_mass - L.site[2];
+  };
   if (FORCES) {
+    // restraint force -(m_i/M) k (d - d0) (c - c0)/d, before the barrier
+    // when this wave's sums are the whole centre of mass
+    auto add_restraint = [&]() {
+      com_offset();
+      const float d = sqrtf(cx * cx + cy * cy + cz * cz);
+      const float excess = d - L.d0;
+      const float fr =
+          excess > 0.f ? -L.krest * excess / d * L.inv_total_mass : 0.f;
+      ge[0] += fr * m * cx;
+      ge[1] += fr * m * cy;
+      ge[2] += fr * m * cz;
+    };
+    if (n_atom_waves == 1 && wv == 0) add_restraint();
     block_sync();
     if (owner) {
+      if (n_atom_waves > 1) add_restraint();
       // bonded forces: read and clear the atom's fixed-point accumulator
       // (the next evaluation adds into it only after its first barrier)
       unsigned int* a3 = sh.sl.acc + 3 * tid;
@@ -615,38 +637,37 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
     v[0] = wave_sum((double)eb);
     v[1] = wave_sum((double)ea);
     v[2] = wave_sum((double)et);
+    v[3] = 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) v[4 + c] = wave_sum((double)psi[c]);
     v[4 + C] = wave_sum((double)ex0);
     v[5 + C] = wave_sum((double)ex1);
     if (lane == 0) {
-      sh.red[wv * kRedMax + 0] = v[0];
-      sh.red[wv * kRedMax + 1] = v[1];
-      sh.red[wv * kRedMax + 2] = v[2];
 #pragma unroll
-      for (int q = 4; q < 6 + C; ++q) sh.red[wv * kRedMax + q - 1] = v[q];
+      for (int q = 0; q < 6 + C; ++q) sh.red[wv * kRedMax + q] = v[q];
     }
     block_sync();
     double acc[6 + C];
 #pragma unroll
     for (int q = 0; q < 6 + C; ++q) acc[q] = 0.0;
-#pragma unroll
+    // waves one at a time: an unrolled loop would hold W x (6 + C)
+    // doubles in registers at once
+#pragma unroll 1
     for (int ww = 0; ww < W; ++ww) {
-      acc[0] += sh.red[ww * kRedMax + 0];
-      acc[1] += sh.red[ww * kRedMax + 1];
-      acc[2] += sh.red[ww * kRedMax + 2];
 #pragma unroll
-      for (int q = 4; q < 6 + C; ++q) acc[q] += sh.red[ww * kRedMax + q - 1];
+      for (int q = 0; q < 6 + C; ++q) acc[q] += sh.red[ww * kRedMax + q];
     }
-    terms[0] = acc[0];
-    terms[1] = acc[1];
-    terms[2] = acc[2];
-    terms[3] = restrained ? 0.5 * (double)L.krest * (double)excess *
-                                (double)excess
-                          : 0.0;
 #pragma unroll
-    for (int q = 4; q < 6 + C; ++q) terms[q] = acc[q];
-    // the next evaluation overwrites red[] only after two more barriers
+    for (int q = 0; q < 6 + C; ++q) terms[q] = acc[q];
+    // restraint energy: every thread from the published partials
+    com_offset();
+    const float d = sqrtf(cx * cx + cy * cy + cz * cz);
+    const float excess = d - L.d0;
+    terms[3] = excess > 0.f
+                   ? 0.5 * (double)L.krest * (double)excess * (double)excess
+                   : 0.0;
+    // the next evaluation overwrites red[] and com[] only after at least
+    // one more barrier
   }
   if (!FORCES && !ENERGY) block_sync();
 }

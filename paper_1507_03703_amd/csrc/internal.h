@@ -73,14 +73,24 @@ struct LigDev {
   unsigned long long* ex_acc;     // max(K-1,1)
   unsigned long long* ex_try;     // max(K-1,1)
   unsigned long long* nonfinite;  // 1
-  unsigned int* arrive;           // replicas done with the current sweep
+  // Neighbour-scheme sweeps apply the exchange (and record) that ends sweep
+  // s-1 at the start of sweep s, in every replica's own block: sweep s
+  // reads buffer (s-1)&1 and writes buffer s&1 (k_sweep_begin fills the
+  // first from the canonical arrays above, k_sweep_finish applies the last
+  // pending exchange and writes them back).
+  unsigned long long* rcnt;   // K: sweep counter of each replica
+  unsigned long long* rnrec;  // K: recorded rounds seen by each replica
+  int* rpend;                 // 2K: exchange/record of the previous sweep due
+  int* rsor;                  // 2K: state of each replica
+  double* scomp;              // 2K(1+C): components of the replica in each state
   float* samp_x;                  // cap*K*n*3
   double* samp_c;                 // cap*K*(1+C)
 };
 
 // Launch wrappers (kernels.hip).  All return hipError_t of the launch.
 // waves = wavefronts per replica (1, 2 or 4); n_atoms <= 64 * waves
-// per-sweep tail run by the last replica of each ligand to finish its move
+// exchange/record schedule of a sweep (scheme 0: deferred into the next
+// sweep's blocks; scheme 1: a tail kernel after every sweep)
 struct TailArgs {
   int exchange_every, scheme, max_sep, sample_every;
 };
@@ -91,6 +101,11 @@ hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
 hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
                              int exchange_every, int scheme, int max_sep,
                              int sample_every, uint64_t seed, hipStream_t st);
+hipError_t launch_sweep_begin(const LigDev* d_ligs, int n_ligs,
+                              hipStream_t st);
+hipError_t launch_sweep_finish(const LigDev* d_ligs, int n_ligs,
+                               int exchange_every, int sample_every,
+                               uint64_t seed, hipStream_t st);
 hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
                            int max_sep, uint64_t seed, hipStream_t st);
 hipError_t launch_components(const GridDev& g, const LigDev* d_lig,
@@ -115,8 +130,8 @@ struct MbarScratch {
   double* f;         // K
   double* logN;      // K
   double* logD;      // N
-  double* partial;   // n_blocks * (K + K*(K+1)/2)
-  double* red;       // K + K*(K+1)/2 (reduced sums)
+  double* partial;   // mbar_acc_blocks(K, N) * (K + K*K)
+  double* red;       // K + K*K (reduced sums)
   double* mat;       // (K-1) x (2K-1) augmented system
   double* step;      // K
   double* scalars;   // [0] objective, [1] max|step|, [2] g.step, [3] status
@@ -130,6 +145,7 @@ hipError_t mbar_objective(int K, const int64_t* dummy, const MbarScratch& s,
 hipError_t mbar_self_consistent(const double* ukn, int K, int64_t N,
                                 int64_t ld, const MbarScratch& s,
                                 hipStream_t st);
+int mbar_acc_blocks(int K, int64_t N);
 hipError_t mbar_accumulate(const double* ukn, int K, int64_t N, int64_t ld,
                            const double* f, const MbarScratch& s,
                            hipStream_t st);

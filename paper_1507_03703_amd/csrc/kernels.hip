@@ -143,6 +143,122 @@ __global__ __launch_bounds__(256) void k_sweep_tail(
 }
 
 // ----------------------------------------------------------------------------
+// neighbour-scheme exchange deferred into the next sweep
+// ----------------------------------------------------------------------------
+// State after the exchange that ends sweep s - 1 of the replica that held
+// state a during it, from buffer `pin` (components indexed by state).  Only
+// the replica's own pair (a, a +- 1) matters in the even/odd scheme; both
+// replicas of a pair evaluate the same expression as attempt_pair on the same
+// numbers and take the same decision.  `stats`: count the attempt (once per
+// pair, by its lower state).
+#pragma clang fp contract(off)
+__device__ double state_energy_of(const LigDev& L, int k, const double* cp) {
+  double E = cp[0];
+  for (int c = 0; c < L.C; ++c) E += L.wd[k * L.C + c] * cp[1 + c];
+  return E;
+}
+
+__device__ int deferred_state(const LigDev& L, int a, unsigned long long s,
+                              int pin, int exchange_every, uint64_t seed,
+                              bool stats) {
+  if (exchange_every <= 0 || s == 0ull || L.K < 2) return a;
+  const unsigned long long sw = s - 1ull;
+  if (sw % (unsigned long long)exchange_every != 0ull) return a;
+  const int a0 = (int)(sw & 1ull);
+  if (a < a0) return a;
+  int lo, hi;
+  if (((a - a0) & 1) == 0) {
+    lo = a;
+    hi = a + 1;
+    if (hi >= L.K) return a;
+  } else {
+    lo = a - 1;
+    hi = a;
+  }
+  const int C1 = 1 + L.C;
+  const double* clo = L.scomp + ((size_t)pin * L.K + lo) * C1;
+  const double* chi = L.scomp + ((size_t)pin * L.K + hi) * C1;
+  const double delta =
+      L.beta[lo] * (state_energy_of(L, lo, chi) - state_energy_of(L, lo, clo)) +
+      L.beta[hi] * (state_energy_of(L, hi, clo) - state_energy_of(L, hi, chi));
+  const uint32_t purpose = (uint32_t)kExchange | (1u << 8);
+  const U4 o = draw(seed, (uint32_t)lo, L.id, 0, sw, purpose);
+  const double lnu = log(u01d(o.x));
+  const bool ok = isfinite(delta) && (lnu < -delta);
+  if (stats && a == lo) {
+    atomicAdd(&L.ex_try[lo], 1ull);
+    if (ok) atomicAdd(&L.ex_acc[lo], 1ull);
+  }
+  return ok ? (a == lo ? hi : lo) : a;
+}
+#pragma clang fp contract(fast)
+
+// the exchange ending sweep s - 1 records a round when s % every == 0
+__device__ __forceinline__ bool record_due(unsigned long long s, int every) {
+  return every > 0 && s > 0ull && s % (unsigned long long)every == 0ull;
+}
+
+// Start of a run of neighbour-scheme sweeps: buffer (s-1)&1 from the
+// canonical state, nothing pending.  One block per ligand.
+__global__ __launch_bounds__(256) void k_sweep_begin(
+    const LigDev* __restrict__ ligs) {
+  const LigDev& L = ligs[blockIdx.x];
+  const unsigned long long s = *L.counter, nrec = *L.n_rec;
+  const int pin = (int)((s - 1ull) & 1ull), K = L.K, C1 = 1 + L.C;
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    const int k = L.state_of_replica[r];
+    L.rsor[pin * K + r] = k;
+    L.rpend[pin * K + r] = 0;
+    L.rcnt[r] = s;
+    L.rnrec[r] = nrec;
+    for (int e = 0; e < C1; ++e)
+      L.scomp[((size_t)pin * K + k) * C1 + e] = L.comps[(size_t)r * C1 + e];
+  }
+}
+
+// End of a run: apply the pending exchange and record of the last sweep and
+// write the canonical state maps, components and counters back.  One block
+// per ligand.
+__global__ __launch_bounds__(256) void k_sweep_finish(
+    const LigDev* __restrict__ ligs, int exchange_every, int sample_every,
+    uint64_t seed) {
+  const LigDev& L = ligs[blockIdx.x];
+  const unsigned long long s = L.rcnt[0];
+  const int pin = (int)((s - 1ull) & 1ull), K = L.K, C1 = 1 + L.C;
+  const bool pend = L.rpend[pin * K] != 0;
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    const int a = L.rsor[pin * K + r];
+    const int k =
+        pend ? deferred_state(L, a, s, pin, exchange_every, seed, true) : a;
+    L.state_of_replica[r] = k;
+    L.replica_of_state[k] = r;
+    for (int e = 0; e < C1; ++e)
+      L.comps[(size_t)r * C1 + e] = L.scomp[((size_t)pin * K + a) * C1 + e];
+  }
+  __syncthreads();
+  const unsigned long long rec = L.rnrec[0];
+  const bool record =
+      pend && record_due(s, sample_every) && rec < (unsigned long long)L.cap;
+  if (record) {
+    const int n3 = L.n * 3;
+    float* dx = L.samp_x + (size_t)rec * K * n3;
+    double* dc = L.samp_c + (size_t)rec * K * C1;
+    for (int q = threadIdx.x; q < K * n3; q += blockDim.x) {
+      const int k = q / n3, e = q - k * n3;
+      dx[q] = L.x[(size_t)L.replica_of_state[k] * n3 + e];
+    }
+    for (int q = threadIdx.x; q < K * C1; q += blockDim.x) {
+      const int k = q / C1, e = q - k * C1;
+      dc[q] = L.comps[(size_t)L.replica_of_state[k] * C1 + e];
+    }
+  }
+  if (threadIdx.x == 0) {
+    *L.counter = s;
+    *L.n_rec = record ? rec + 1ull : rec;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // HMC: one trial move per replica, one workgroup of W wavefronts per replica.
 // (Sampling: HMC trial moves from velocity-Verlet molecular dynamics.)
 // ----------------------------------------------------------------------------
@@ -159,8 +275,24 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   const Shared sh = carve<W>(smem, L, L.n, tid);
   __shared__ double fin[2 * W];
 
-  const unsigned long long s = *L.counter;
-  const int k = L.state_of_replica[r];
+  // sweep index and state: scheme 0 first applies the exchange (and
+  // record) that ended the previous sweep, from the double buffer
+  const bool deferred = tail.scheme == 0;
+  unsigned long long s;
+  int k, a = 0, pin = 0;
+  bool pend = false;
+  if (deferred) {
+    s = L.rcnt[r];
+    pin = (int)((s - 1ull) & 1ull);
+    pend = L.rpend[pin * L.K + r] != 0;
+    a = L.rsor[pin * L.K + r];
+    k = pend ? deferred_state(L, a, s, pin, tail.exchange_every, seed,
+                              tid == 0)
+             : a;
+  } else {
+    s = *L.counter;
+    k = L.state_of_replica[r];
+  }
   float w[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) w[c] = L.wf[k * C + c];
@@ -178,6 +310,26 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   const float* xr = L.x + (size_t)r * n * 3;
 #pragma unroll
   for (int d = 0; d < 3; ++d) x[d] = owner ? xr[tid * 3 + d] : 0.f;
+  const int C1 = 1 + C;
+  // the previous sweep's round: this replica's configuration and components
+  // go to the slot of its state after that exchange.  The replica's record
+  // counter is advanced at the end of the kernel, after the barriers, so that
+  // every wavefront has read it first.
+  bool recorded = false;
+  unsigned long long rec = 0ull;
+  if (deferred && pend && record_due(s, tail.sample_every)) {
+    rec = L.rnrec[r];
+    if (rec < (unsigned long long)L.cap) {
+      recorded = true;
+      if (owner)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          L.samp_x[((size_t)rec * L.K + k) * n * 3 + tid * 3 + d] = x[d];
+      if (tid < C1)
+        L.samp_c[((size_t)rec * L.K + k) * C1 + tid] =
+            L.scomp[((size_t)pin * L.K + a) * C1 + tid];
+    }
+  }
   if (owner) {
     const U4 o = draw(seed, (uint32_t)tid, L.id, r, s, kMomenta);
     float z0, z1, z2;
@@ -191,27 +343,37 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   }
   const float ke0 = 0.5f * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
 
-  double t0[6 + C], t1[6 + C];
-  eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t0, ke0, 0.f, sh, tid);
-  double U0 = t0[0] + t0[1] + t0[2] + t0[3];
+  double U0, KE0;
+  {
+    double t0[6 + C];
+    eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t0, ke0, 0.f, sh, tid);
+    U0 = t0[0] + t0[1] + t0[2] + t0[3];
 #pragma unroll
-  for (int c = 0; c < C; ++c) U0 += L.wd[k * C + c] * t0[4 + c];
-  const double KE0 = t0[4 + C] * 1e4;
+    for (int c = 0; c < C; ++c) U0 += L.wd[k * C + c] * t0[4 + c];
+    KE0 = t0[4 + C] * 1e4;
+  }
 
+  // nleap velocity-Verlet steps; the last one also evaluates the energy
   const float hk = 0.5f * dt * 1e-4f * im;
-  for (int step = 0; step < nleap; ++step) {
+  double t1[6 + C];
+  for (int step = 0; step < nleap - 1; ++step) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       v[d] = fmaf(hk, f[d], v[d]);
       x[d] = fmaf(dt, v[d], x[d]);
     }
-    if (step == nleap - 1)
-      eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid);
-    else
-      eval_block<C, W, true, false>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid);
+    eval_block<C, W, true, false>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid);
 #pragma unroll
     for (int d = 0; d < 3; ++d) v[d] = fmaf(hk, f[d], v[d]);
   }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    v[d] = fmaf(hk, f[d], v[d]);
+    x[d] = fmaf(dt, v[d], x[d]);
+  }
+  eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) v[d] = fmaf(hk, f[d], v[d]);
   double U1 = t1[0] + t1[1] + t1[2] + t1[3];
 #pragma unroll
   for (int c = 0; c < C; ++c) U1 += L.wd[k * C + c] * t1[4 + c];
@@ -231,38 +393,36 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     if (owner)
 #pragma unroll
       for (int d = 0; d < 3; ++d) xw[tid * 3 + d] = x[d];
-    if (tid == 0) {
-      double* cr = L.comps + (size_t)r * (1 + C);
-      cr[0] = t1[0] + t1[1] + t1[2] + t1[3];
+  }
+  // components of the replica after the move (scheme 0: into the output
+  // buffer, indexed by state)
+  if (tid < C1 && (accept || deferred)) {
+    double cv;
+    if (accept) {
+      // select without a register-array index
+      cv = t1[0] + t1[1] + t1[2] + t1[3];
 #pragma unroll
-      for (int c = 0; c < C; ++c) cr[1 + c] = t1[4 + c];
+      for (int c = 0; c < C; ++c)
+        if (tid == 1 + c) cv = t1[4 + c];
+    } else {
+      cv = L.scomp[((size_t)pin * L.K + a) * C1 + tid];
     }
+    if (deferred)
+      L.scomp[((size_t)(s & 1ull) * L.K + k) * C1 + tid] = cv;
+    else
+      L.comps[(size_t)r * C1 + tid] = cv;
   }
   if (tid == 0) {
     atomicAdd(&L.hmc_try[k], 1ull);
     if (accept) atomicAdd(&L.hmc_acc[k], 1ull);
     if (!finite) atomicAdd(L.nonfinite, 1ull);
-  }
-  // The last replica of the ligand to finish runs the sweep's tail (no
-  // block ever waits for another).  Release: this block's stores are made
-  // visible device-wide before its arrival is counted; the last block
-  // acquires before reading the other replicas' results.
-  __shared__ int s_last;
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const unsigned int prev = atomicAdd(L.arrive, 1u);
-    s_last = (prev == (unsigned int)L.K - 1u) ? 1 : 0;
-    if (s_last) {
-      __threadfence();
-      *L.arrive = 0u;
+    if (deferred) {
+      const int pout = (int)(s & 1ull);
+      L.rsor[pout * L.K + r] = k;
+      L.rpend[pout * L.K + r] = 1;
+      L.rcnt[r] = s + 1ull;
+      if (recorded) L.rnrec[r] = rec + 1ull;
     }
-  }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    sweep_tail(L, tail.exchange_every, tail.scheme, tail.max_sep,
-               tail.sample_every, seed);
   }
 }
 
@@ -495,6 +655,22 @@ hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
   if (n_ligs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sweep_tail, dim3(n_ligs), dim3(256), 0, st, d_ligs,
                      exchange_every, scheme, max_sep, sample_every, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_begin(const LigDev* d_ligs, int n_ligs,
+                              hipStream_t st) {
+  if (n_ligs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep_begin, dim3(n_ligs), dim3(256), 0, st, d_ligs);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_finish(const LigDev* d_ligs, int n_ligs,
+                               int exchange_every, int sample_every,
+                               uint64_t seed, hipStream_t st) {
+  if (n_ligs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep_finish, dim3(n_ligs), dim3(256), 0, st, d_ligs,
+                     exchange_every, sample_every, seed);
   return hipGetLastError();
 }
 

@@ -105,77 +105,101 @@ __global__ void k_gauge(const double* __restrict__ fnew, int K,
   for (int k = threadIdx.x; k < K; k += blockDim.x) f[k] = fnew[k] - fnew[0];
 }
 
-// partial[b] = [colsum_i (K) | M_ij (K*K)] over the block's sample chunks;
-// PER = entries of M per thread (K*K <= PER * blockDim)
-template <int PER>
+// partial[b] = [colsum_i (K) | M_ij (K*K)] over the block's sample chunks,
+// M = W W^T with W_in = exp(f_i - u_in - logD_n).  A chunk of W sits in LDS
+// sample-major, row stride Kp + 2 doubles (16-byte aligned rows, staggered
+// banks); the 256 threads form a 16 x 16 grid of TS x TS register tiles of
+// M (Kp = 16 TS >= K, rows and columns past K are zero).
+template <int TS>
 __global__ __launch_bounds__(kT) void k_accumulate(
     const double* __restrict__ ukn, int K, int64_t N, int64_t ld,
     const double* __restrict__ f, const double* __restrict__ logD,
     double* __restrict__ partial, int chunk) {
-  extern __shared__ double W[];  // K x chunk
-  double acc[PER];
-  double col = 0.0;
-  const int KK = K * K;
+  constexpr int Kp = 16 * TS, RS = Kp + 2;
+  extern __shared__ __align__(16) double W[];  // chunk x RS
+  __shared__ double fk[Kp];
+  const int tid = threadIdx.x;
+  const int ta = tid >> 4, tb = tid & 15;
+  for (int k = tid; k < Kp; k += kT) fk[k] = k < K ? f[k] : 0.0;
+  double acc[TS][TS];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+  for (int i = 0; i < TS; ++i)
+#pragma unroll
+    for (int j = 0; j < TS; ++j) acc[i][j] = 0.0;
+  double col = 0.0;
   const int64_t n_chunks = (N + chunk - 1) / chunk;
   for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
     const int64_t n0 = ch * chunk;
     const int cnt = (int)((N - n0) < chunk ? (N - n0) : chunk);
     __syncthreads();
-    for (int e = threadIdx.x; e < K * chunk; e += blockDim.x) {
-      const int k = e / chunk, j = e - k * chunk;
-      W[e] = j < cnt ? exp(f[k] - ukn[(size_t)k * ld + n0 + j] - logD[n0 + j])
-                     : 0.0;
+    // fill: consecutive threads take consecutive samples of one state
+    for (int e = tid; e < Kp * chunk; e += kT) {
+      const int k = e / chunk, t = e - k * chunk;
+      double v = 0.0;
+      if (k < K && t < cnt)
+        v = exp(fk[k] - ukn[(size_t)k * ld + n0 + t] - logD[n0 + t]);
+      W[t * RS + k] = v;
     }
     __syncthreads();
-    if ((int)threadIdx.x < K) {
-      const double* wi = W + threadIdx.x * chunk;
-      for (int j = 0; j < cnt; ++j) col += wi[j];
-    }
+    if (tid < Kp)
+      for (int t = 0; t < cnt; ++t) col += W[t * RS + tid];
+    for (int t = 0; t < cnt; ++t) {
+      const double* row = W + t * RS;
+      double wi[TS], wj[TS];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + kT * q;
-      if (e < KK) {
-        const int i = e / K, j = e - i * K;
-        const double* wi = W + i * chunk;
-        const double* wj = W + j * chunk;
-        double s = 0.0;
-        for (int t = 0; t < cnt; ++t) s += wi[t] * wj[t];
-        acc[q] += s;
-      }
+      for (int i = 0; i < TS; ++i) wi[i] = row[ta * TS + i];
+#pragma unroll
+      for (int j = 0; j < TS; ++j) wj[j] = row[tb * TS + j];
+#pragma unroll
+      for (int i = 0; i < TS; ++i)
+#pragma unroll
+        for (int j = 0; j < TS; ++j) acc[i][j] = fma(wi[i], wj[j], acc[i][j]);
     }
   }
+  const int KK = K * K;
   double* out = partial + (size_t)blockIdx.x * (K + KK);
-  if ((int)threadIdx.x < K) out[threadIdx.x] = col;
+  if (tid < K) out[tid] = col;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + kT * q;
-    if (e < KK) out[K + e] = acc[q];
-  }
+  for (int i = 0; i < TS; ++i)
+#pragma unroll
+    for (int j = 0; j < TS; ++j) {
+      const int r = ta * TS + i, c = tb * TS + j;
+      if (r < K && c < K) out[K + r * K + c] = acc[i][j];
+    }
 }
 
-// Newton step (single block): reduce partials, build the gauge-fixed system
-// [H~ | -g~ | I], Gauss-Jordan eliminate (H~ is symmetric positive definite),
-// write step, max|step|, g.step and, on request, var(f_k - f_0).
-__global__ __launch_bounds__(1024) void k_newton(
-    const double* __restrict__ partial, int nb, int K,
-    const double* __restrict__ Nk, double* __restrict__ red,
-    double* __restrict__ mat, double* __restrict__ step,
+// red[e] = sum over blocks of partial[b][e], in block order (small blocks:
+// many of them keep enough loads in flight)
+constexpr int kRedT = 64;
+__global__ __launch_bounds__(kRedT) void k_reduce_partials(
+    const double* __restrict__ partial, int nb, int width,
+    double* __restrict__ red) {
+  const int e = blockIdx.x * kRedT + threadIdx.x;
+  if (e >= width) return;
+  double s = 0.0;
+#pragma unroll 16
+  for (int b = 0; b < nb; ++b) s += partial[(size_t)b * width + e];
+  red[e] = s;
+}
+
+// Newton step (single block): from the reduced sums build the gauge-fixed
+// system [H~ | -g~ (| I)], Gauss-Jordan eliminate it (H~ is symmetric
+// positive definite), write step, max|step|, g.step and, on request,
+// var(f_k - f_0).  `mat` is LDS (dynamic) when the system fits, else global.
+constexpr int kNewtonT = 256;
+template <bool LDS>
+__global__ __launch_bounds__(kNewtonT) void k_newton(
+    const double* __restrict__ red, int K, const double* __restrict__ Nk,
+    double* __restrict__ gmat, double* __restrict__ step,
     double* __restrict__ scalars, int want_inverse,
     double* __restrict__ var_out) {
+  extern __shared__ __align__(16) double lmat[];
+  double* mat = LDS ? lmat : gmat;
   __shared__ double fac[BPMF_MAX_MBAR_STATES_DEV];
   __shared__ double gsh[BPMF_MAX_MBAR_STATES_DEV];
   __shared__ double piv_sh, dmax_sh;
   __shared__ int bad;
-  const int KK = K * K, stride = K + KK;
-  for (int e = threadIdx.x; e < stride; e += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[(size_t)b * stride + e];
-    red[e] = s;
-  }
   if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
   const int m = K - 1;
   const int wcols = m + 1 + (want_inverse ? m : 0);
   for (int k = threadIdx.x; k < K; k += blockDim.x)
@@ -277,34 +301,57 @@ hipError_t mbar_self_consistent(const double* ukn, int K, int64_t N,
   return hipGetLastError();
 }
 
+int mbar_acc_chunk(int K) {
+  const int TS = K <= 16 ? 1 : K <= 32 ? 2 : K <= 64 ? 4 : 8;
+  return 4096 / (16 * TS);
+}
+
+int mbar_acc_blocks(int K, int64_t N) {
+  const int64_t chunks = (N + mbar_acc_chunk(K) - 1) / mbar_acc_chunk(K);
+  return (int)(chunks < 256 ? chunks : 256);
+}
+
 hipError_t mbar_accumulate(const double* ukn, int K, int64_t N, int64_t ld,
                            const double* f, const MbarScratch& s,
                            hipStream_t st) {
-  const int chunk = 4096 / K < 1 ? 1 : 4096 / K;
-  const size_t lds = (size_t)K * chunk * sizeof(double);
-  const int KK = K * K;
-  if (KK <= kT)
-    hipLaunchKernelGGL(k_accumulate<1>, dim3(s.n_blocks), dim3(kT), lds, st,
-                       ukn, K, N, ld, f, s.logD, s.partial, chunk);
-  else if (KK <= 4 * kT)
-    hipLaunchKernelGGL(k_accumulate<4>, dim3(s.n_blocks), dim3(kT), lds, st,
-                       ukn, K, N, ld, f, s.logD, s.partial, chunk);
-  else if (KK <= 16 * kT)
-    hipLaunchKernelGGL(k_accumulate<16>, dim3(s.n_blocks), dim3(kT), lds, st,
-                       ukn, K, N, ld, f, s.logD, s.partial, chunk);
-  else if (KK <= 64 * kT)
-    hipLaunchKernelGGL(k_accumulate<64>, dim3(s.n_blocks), dim3(kT), lds, st,
-                       ukn, K, N, ld, f, s.logD, s.partial, chunk);
+  const int chunk = mbar_acc_chunk(K);
+  const int nb = mbar_acc_blocks(K, N);
+  const int TS = K <= 16 ? 1 : K <= 32 ? 2 : K <= 64 ? 4 : 8;
+  const size_t lds = (size_t)chunk * (16 * TS + 2) * sizeof(double);
+  if (TS == 1)
+    hipLaunchKernelGGL(k_accumulate<1>, dim3(nb), dim3(kT), lds, st, ukn, K,
+                       N, ld, f, s.logD, s.partial, chunk);
+  else if (TS == 2)
+    hipLaunchKernelGGL(k_accumulate<2>, dim3(nb), dim3(kT), lds, st, ukn, K,
+                       N, ld, f, s.logD, s.partial, chunk);
+  else if (TS == 4)
+    hipLaunchKernelGGL(k_accumulate<4>, dim3(nb), dim3(kT), lds, st, ukn, K,
+                       N, ld, f, s.logD, s.partial, chunk);
   else
-    return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_accumulate<8>, dim3(nb), dim3(kT), lds, st, ukn, K,
+                       N, ld, f, s.logD, s.partial, chunk);
+  const int width = K + K * K;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((width + kRedT - 1) / kRedT),
+                     dim3(kRedT), 0, st, s.partial, nb, width, s.red);
   return hipGetLastError();
 }
 
 hipError_t mbar_newton(int K, const double* N_k_dev, const MbarScratch& s,
                        int want_inverse, double* var_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_newton, dim3(1), dim3(1024), 0, st, s.partial,
-                     s.n_blocks, K, N_k_dev, s.red, s.mat, s.step, s.scalars,
-                     want_inverse, var_out);
+  const int m = K - 1;
+  const size_t bytes =
+      (size_t)m * (m + 1 + (want_inverse ? m : 0)) * sizeof(double);
+  // LDS when the system fits beside the kernel's static arrays
+  if (bytes <= 60 * 1024)
+    hipLaunchKernelGGL(k_newton<true>, dim3(1), dim3(kNewtonT), bytes, st,
+                       s.red,
+                       K, N_k_dev, s.mat, s.step, s.scalars, want_inverse,
+                       var_out);
+  else
+    hipLaunchKernelGGL(k_newton<false>, dim3(1), dim3(kNewtonT), 0, st, s.red,
+                       K,
+                       N_k_dev, s.mat, s.step, s.scalars, want_inverse,
+                       var_out);
   return hipGetLastError();
 }
 

@@ -157,6 +157,16 @@ def test_mbar_production_ladder_full_size():
     assert np.max(np.abs(f - f64)) < 1e-6 * max(1.0, np.abs(f64).max())
     assert abs(var[-1] / v64 - 1) < 1e-4
     assert np.all(np.isfinite(var))
+    # warm starts (the solution, a perturbed solution, another gauge) reach
+    # the same solution; from the solution itself in at most two iterations
+    f2, var2, it2 = ctx.mbar(u, Nk, tol=1e-10, max_iter=200, f_init=f)
+    assert it2 <= 2 and np.max(np.abs(f2 - f)) < 1e-8 * max(1.0,
+                                                            np.abs(f).max())
+    rng = np.random.default_rng(0)
+    f3, _, it3 = ctx.mbar(u, Nk, tol=1e-10, max_iter=200,
+                          f_init=f + 5.0 + rng.normal(scale=2.0, size=K))
+    assert np.max(np.abs(f3 - f64)) < 1e-6 * max(1.0, np.abs(f64).max())
+    assert np.array_equal(var2 > 0, var > 0)
     ctx.close()
 
 

@@ -157,6 +157,38 @@ def test_same_seed_same_bits_and_recorded_samples():
     assert np.array_equal(xa, xb) and np.array_equal(ca, cb)
 
 
+@pytest.mark.parametrize("waves", [2, 4])
+def test_records_of_a_ligand_wider_than_a_wavefront(waves):
+    """Samples recorded inside multi-sweep calls (the exchange and record of
+    a sweep run in the next sweep's blocks) by replicas of several
+    wavefronts: every recorded configuration carries the components the
+    oracle computes for it, and the last round is the final state."""
+    print_case("records 90 atoms", waves)
+    rng = np.random.default_rng(14)
+    lig = synth.make_ligand(rng, 90, 6, box=9.0)
+    system = synth.make_system(1)
+    g = system.grid
+    ctx, (lid,) = make_context(g, [lig], seed=23, capacity=12)
+    ctx.set_waves(waves)
+    ctx.hmc_sweep(16, 6, exchange_every=1, sample_every=2)
+    ctx.hmc_sweep(8, 6, exchange_every=1, sample_every=2)
+    xs, cs = ctx.get_samples(lid)
+    st = ctx.get_replicas(lid)
+    assert xs.shape[0] == 12 and np.all(np.isfinite(xs))
+    ros = np.argsort(st["state_of_replica"])
+    assert np.array_equal(xs[-1], st["x"][ros])
+    assert np.array_equal(cs[-1], st["comps"][ros])
+    og, ol = oracle.OGrid(g), oracle.OLigand(lig)
+    X = xs.reshape(-1, lig.n_atoms, 3)
+    t, m, _ = oracle.energy_batch(og, ol, X, np.zeros((len(X), og.nc)))
+    ref = np.concatenate([t[:, :4].sum(1, keepdims=True), t[:, 4:4 + og.nc]],
+                         axis=1)
+    S = m.sum(axis=1)
+    assert np.all(np.abs(cs.reshape(len(X), -1) - ref) <= 1e-5 * S[:, None]
+                  + 1e-9)
+    ctx.close()
+
+
 def test_nonfinite_positions_are_rejected_and_counted():
     print_case("nonfinite")
     system = synth.make_system(1)
