@@ -18,7 +18,12 @@ bonded terms and restraint.
 A second leg ("batched") runs the batched workload -- 256 ligands of 10-80
 atoms with 32 replicas each on one shared 160^3 grid, 2000 sweeps of 10
 steps, per-ligand u_kn and MBAR -- with the launch shape picked by the
-autotuner; --config 3 makes it the main workload instead.
+autotuner; --config 3 makes it the main workload instead.  A third leg
+("learned_proposal") compares plain HMC with HMC plus learned independence
+pose moves on the 24-atom, 64-state system (the paper's soft-grid switching
+protocol): BPMF error against a long plain run and effective samples per
+second of the fully coupled state, both continuing from the long run's
+equilibrated end.
 """
 from __future__ import annotations
 
@@ -34,6 +39,32 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 GRID_BYTES_PER_EVAL = 96  # 8 corners x 3 channels x 4 B
 
+# HBM bytes moved by one sweep-kernel launch of the production workload,
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled
+# by what the same counters read for a 1 GiB device copy (x2.0 and x1.0);
+# valid while the sweep kernel's sources hash to `sources`.
+SWEEP_TRAFFIC = {"workload": "c2_plain_production",
+                 "sources": "c565caf47659e6f2",
+                 "fetch_kib": 940.070, "write_kib": 52.710,
+                 "fetch_scale": 2.0, "write_scale": 1.0}
+SWEEP_SOURCES = ("device.h", "kernels.hip", "internal.h")
+
+
+def sweep_traffic(workload):
+    """Measured HBM bytes per sweep launch, or None when the workload or the
+    kernel sources differ from those the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1507_03703_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    t = SWEEP_TRAFFIC
+    if workload != t["workload"] or h.hexdigest()[:16] != t["sources"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] +
+                     t["write_kib"] * t["write_scale"])
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -47,6 +78,20 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-batched", dest="batched", action="store_false",
                    help="skip the batched 256-ligand leg")
+    p.add_argument("--no-learned", dest="learned", action="store_false",
+                   help="skip the learned-proposal leg")
+    p.add_argument("--learned-only", action="store_true",
+                   help="only the learned-proposal leg (with --long-sweeps, "
+                        "--prod-sweeps, --train-steps)")
+    p.add_argument("--long-sweeps", type=int, default=200000)
+    p.add_argument("--prod-sweeps", type=int, default=50000)
+    p.add_argument("--train-steps", type=int, default=4000)
+    p.add_argument("--grid-device", default="cuda:0",
+                   help="torch device that sums the synthetic receptor grids "
+                        "(input generation, outside the timed region)")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                   help="only run a plain device-to-device copy of BYTES "
+                        "bytes five times (reference for memory counters)")
     return p.parse_args()
 
 
@@ -191,13 +236,160 @@ def describe(system, r):
             "samples_per_state": r["records"]}
 
 
-def roofline(r):
+def roofline(r, workload):
     return {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "k_hmc_sweep",
+            "traffic": sweep_traffic(workload), "kernel": "k_hmc_sweep",
             "mean_launch_ms": r["hmc_ms"], "launches_timed": r["hmc_n"],
             "algorithmic_bytes_per_launch": r["evals_per_sweep"] *
             GRID_BYTES_PER_EVAL}
+
+
+def stat_inefficiency(a):
+    """g = 1 + 2 sum_t (1 - t/N) rho(t), summed while the normalised
+    autocorrelation rho stays positive (ESS = N / g)."""
+    import numpy as np
+    a = np.asarray(a, np.float64)
+    N = len(a)
+    d = a - a.mean()
+    var = float(d @ d) / N
+    if N < 3 or var <= 0.0:
+        return 1.0
+    g = 1.0
+    for t in range(1, N - 1):
+        rho = float(d[:N - t] @ d[t:]) / (N - t) / var
+        if rho <= 0.0:
+            break
+        g += 2.0 * rho * (1.0 - t / N)
+    return max(g, 1.0)
+
+
+def init_params(rng):
+    """Random fan-in-scaled weights of the 16-256-256-104 proposal network in
+    the library's flat layout (W1 b1 W2 b2 W3 b3, weights [in][out])."""
+    import numpy as np
+    parts = []
+    for i, o, gain in ((16, 256, 1.0), (256, 256, 1.0), (256, 104, 0.1)):
+        parts.append(rng.normal(size=(i, o)) * gain / np.sqrt(i))
+        parts.append(np.zeros(o))
+    return np.concatenate([q.reshape(-1) for q in parts]).astype(np.float32)
+
+
+def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
+                long_sweeps=200000, prod_sweeps=50000):
+    """Plain HMC vs HMC + learned independence pose moves on the 24-atom,
+    64-state system with the paper's soft-grid switching protocol.  A long
+    plain run gives the reference BPMF (its second half) and the 200k
+    coupled-state poses the network is trained on; both samplers then
+    continue from the long run's final state, and each reports its BPMF
+    error against the reference and the effective samples per second of
+    the coupled state."""
+    import numpy as np
+    import synth
+    system = synth.make_system(4, grid_device="cuda:0")
+    g, (lig,) = synth.add_soft_grids(system.grid, system.ligands)
+    K, L, n = lig.n_states, system.n_leapfrog, lig.n_atoms
+    every = system.sample_every
+    burn = 5000
+
+    def fresh(capacity):
+        ctx = pkg.Context(seed=system.seed, device=0)
+        ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+        return ctx, ctx.ligand_setup(lig, sample_capacity=capacity)
+
+    def estimate(ctx, lid, n_rec, xs=None):
+        u = ctx.energy_matrix(lid, xs, n_samples=n_rec * K)
+        f, var, _ = ctx.mbar(u, np.full(K, n_rec), tol=1e-10, max_iter=200)
+        # coupled state's reduced potential on its own samples (round-major)
+        obs = u[K - 1, K - 1::K].cpu().numpy()
+        gi = stat_inefficiency(obs)
+        return float(f[-1] - f[0]), float(np.sqrt(max(var[-1], 0.0))), \
+            n_rec / gi, gi
+
+    # long plain run: reference BPMF and training poses
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx, lid = fresh(long_sweeps)
+    ctx.hmc_sweep(burn, L, exchange_every=1)
+    ctx.hmc_sweep(long_sweeps, L, exchange_every=1, sample_every=1)
+    torch.cuda.synchronize()
+    long_s = time.perf_counter() - t0
+    xs, _ = ctx.get_samples(lid)                   # (rounds, K, n, 3)
+    final = ctx.get_replicas(lid)
+    half = torch.as_tensor(np.ascontiguousarray(
+        xs[long_sweeps // 2::20]).reshape(-1, n, 3), device="cuda:0")
+    ref, ref_sd, _, _ = estimate(ctx, lid, half.shape[0] // K, half)
+    del half
+    poses_x = torch.as_tensor(np.ascontiguousarray(xs[:, K - 1]),
+                              device="cuda:0")
+    del xs
+    ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors],
+                       init_params(np.random.default_rng(system.seed)))
+    feats, poses = ctx.pose_features(lid, poses_x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = ctx.proposal_train(lid, feats, poses, batch=512,
+                                steps=train_steps, lr=2e-3, losses=True)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    params = ctx.proposal_params(lid)
+    n_poses = int(feats.shape[0])
+    ctx.close()
+    del poses_x, feats, poses
+
+    def production(learned):
+        records = prod_sweeps // every
+        ctx, lid = fresh(records)
+        ctx.set_replicas(lid, final["x"], final["state_of_replica"],
+                         final["comps"], int(final["counter"]))
+        if learned:
+            ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors],
+                               params)
+        ctx.hmc_sweep(2 * pose_every, L, exchange_every=1,
+                      pose_move_every=pose_every if learned else 0)
+        ctx.reset_samples(lid)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.hmc_sweep(prod_sweeps, L, exchange_every=1, sample_every=every,
+                      pose_move_every=pose_every if learned else 0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        b, sd, ess, gi = estimate(ctx, lid, records)
+        out = dict(seconds=el, bpmf_kT=b, sigma_kT=sd,
+                   error_vs_long_run_kT=abs(b - ref),
+                   within_1kT=bool(abs(b - ref) <= 1.0), ess=ess,
+                   stat_inefficiency=gi, ess_per_s=ess / el)
+        if learned:
+            ps = ctx.get_pose_stats(lid)
+            out["pose_acceptance"] = float(ps["acc"].sum() /
+                                           max(ps["tries"].sum(), 1))
+            out["pose_acceptance_coupled_state"] = float(
+                ps["acc"][-1] / max(ps["tries"][-1], 1))
+        ctx.close()
+        return out
+
+    plain = production(False)
+    learned = production(True)
+    return {
+        "workload": f"{system.name} with the soft-grid switching protocol "
+                    f"(5 channels): {n}-atom ligand, {g.n[0]}^3 grids, {K} "
+                    f"replicas, {prod_sweeps} sweeps x {L} leapfrog steps "
+                    f"from the equilibrated end of a {long_sweeps}-sweep "
+                    f"plain run, a sample per state every {every}; learned: "
+                    f"one independence pose move per replica every "
+                    f"{pose_every} sweeps (captured with the sweeps)",
+        "ess_observable": "reduced potential of the fully coupled state on "
+                          "its own samples",
+        "reference": {"sweeps": long_sweeps, "seconds": long_s,
+                      "bpmf_kT": ref, "sigma_kT": ref_sd,
+                      "estimated_on": "second half, every 20th round"},
+        "plain": plain, "learned": learned,
+        "ess_per_s_ratio": learned["ess_per_s"] / plain["ess_per_s"],
+        "training": {"poses": n_poses, "steps": train_steps, "batch": 512,
+                     "train_s": train_s,
+                     "loss_first": float(np.mean(losses[:20])),
+                     "loss_last": float(np.mean(losses[-20:]))},
+    }
 
 
 def main():
@@ -209,10 +401,26 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "repeats": 5}))
+        return
+
     import synth
     import paper_1507_03703_amd as pkg
 
-    system = synth.make_system(args.config, grid_device="cuda:0")
+    if args.learned_only:
+        print(json.dumps(learned_leg(pkg, torch, train_steps=args.train_steps,
+                                     long_sweeps=args.long_sweeps,
+                                     prod_sweeps=args.prod_sweeps)))
+        return
+
+    system = synth.make_system(args.config, grid_device=args.grid_device)
     r = run_workload(pkg, torch, system, args.steps, args.warmup,
                      sweeps=args.sweeps, tune=len(system.ligands) > 1)
     out = {
@@ -230,7 +438,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": describe(system, r),
-        "roofline": roofline(r),
+        "roofline": roofline(r, system.name),
         "kernels_ms": {"hmc_sweep": r["hmc_ms"], "components": r["cmp_ms"]},
         "result": r["result"],
         "setup_s": r["setup_s"],
@@ -240,14 +448,18 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_seconds)
     if args.batched and args.config != 3:
-        bs = synth.make_system(3, grid_device="cuda:0")
+        bs = synth.make_system(3, grid_device=args.grid_device)
         rb = run_workload(pkg, torch, bs, 1, 1, tune=True)
         out["batched"] = {"value": rb["value"], "unit": "atom-evals/s",
                           "ms_per_step": rb["ms_per_step"], "steps": 1,
                           "warmup": 1, "config": describe(bs, rb),
-                          "roofline": roofline(rb),
+                          "roofline": roofline(rb, bs.name),
                           "autotune": rb["tuned"], "waves": rb["waves"],
                           "result": rb["result"]}
+    if args.learned:
+        out["learned_proposal"] = learned_leg(
+            pkg, torch, train_steps=args.train_steps,
+            long_sweeps=args.long_sweeps, prod_sweeps=args.prod_sweeps)
     print(json.dumps(out))
 
 

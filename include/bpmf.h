@@ -180,6 +180,9 @@ typedef struct {
                           1 = all pairs 1..max_sep apart, sequential */
   int max_sep;         /* scheme 1 only, >= 1 */
   int sample_every;    /* 0 = never; else record when (counter+1) % every == 0 */
+  int pose_move_every; /* 0 = never; else after the call's sweeps P, 2P, ...
+                          one pose move (bpmf_pose_move) of every ligand with
+                          a proposal */
 } bpmf_sweep_args;
 
 /* Run n_sweeps sweeps over every ligand.  One sweep of a ligand with
@@ -195,6 +198,11 @@ typedef struct {
  *   3. if due, record one sample per state: the configuration and cached
  *      energy components of the replica currently in that state;
  *   4. s += 1.
+ * With pose_move_every = P > 0 the call runs units of P sweeps, each
+ * closed by one independence pose move per replica of every ligand that has
+ * a proposal (the moves see the state after the unit's last exchange and
+ * record); sweeps past the last whole unit run without a move.  One unit is
+ * captured as a hipGraph and replayed (see bpmf_set_graph).
  * Random numbers: Philox-4x32-10 keyed by the context seed, counter
  * (index, ligand<<16 | replica, s, purpose) with purpose 1 = momenta
  * (index = atom), 2 = acceptance (index 0), 3 | sep<<8 = exchange

@@ -47,7 +47,8 @@ class _LigandDesc(C.Structure):
 class _SweepArgs(C.Structure):
     _fields_ = [("n_sweeps", C.c_int), ("n_leapfrog", C.c_int),
                 ("exchange_every", C.c_int), ("exchange_scheme", C.c_int),
-                ("max_sep", C.c_int), ("sample_every", C.c_int)]
+                ("max_sep", C.c_int), ("sample_every", C.c_int),
+                ("pose_move_every", C.c_int)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -248,9 +249,11 @@ class Context:
 
     # -- sampling -------------------------------------------------------------
     def hmc_sweep(self, n_sweeps, n_leapfrog, exchange_every=1,
-                  exchange_scheme=0, max_sep=1, sample_every=0):
+                  exchange_scheme=0, max_sep=1, sample_every=0,
+                  pose_move_every=0):
         a = _SweepArgs(int(n_sweeps), int(n_leapfrog), int(exchange_every),
-                       int(exchange_scheme), int(max_sep), int(sample_every))
+                       int(exchange_scheme), int(max_sep), int(sample_every),
+                       int(pose_move_every))
         _check(self._lib.bpmf_hmc_sweep(self._h, C.byref(a)))
 
     def exchange(self, ligand_id=-1, scheme=0, max_sep=1):

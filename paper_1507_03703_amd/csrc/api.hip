@@ -120,7 +120,7 @@ struct bpmf_ctx {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   uint64_t table_version = 0, graph_version = ~0ull;
-  int graph_key[6] = {0, 0, 0, 0, 0, 0};
+  int graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   void drop_graph() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -694,6 +694,16 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   return BPMF_OK;
 }
 
+namespace {
+// proposal network scratch (see mlp_scratch); pose moves of one ligand
+struct MlpBufs {
+  float *Z1, *H1, *Z2, *H2, *out, *dout, *dZ2, *dZ1, *bf, *bp;
+  double* loss_part;
+};
+int mlp_scratch(bpmf_ctx* c, int B, MlpBufs* b);
+int pose_move_ligand(bpmf_ctx* c, int lid, hipStream_t st);
+}  // namespace
+
 // ============================================================================
 // sampling
 // ============================================================================
@@ -711,6 +721,8 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     return fail(BPMF_E_INVAL, "exchange_scheme must be 0 or 1");
   if (a->exchange_scheme == 1 && a->max_sep < 1)
     return fail(BPMF_E_INVAL, "max_sep must be >= 1");
+  if (a->pose_move_every < 0)
+    return fail(BPMF_E_INVAL, "pose_move_every must be >= 0");
   // sample capacity check (host mirrors of the device counters)
   std::vector<int64_t> add(c->ligs.size(), 0);
   if (a->sample_every > 0) {
@@ -746,59 +758,129 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     return BPMF_OK;
   };
   if (a->n_sweeps == 0) return BPMF_OK;
-  if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(c->d_ligs, nl, c->stream));
-  int done = 0;
-  const int chunk = c->graph_chunk;
-  if (chunk > 0 && a->n_sweeps >= chunk) {
-    // the sweep kernels read every per-sweep quantity (counters, state
-    // maps) from device memory, so one captured chunk replays unchanged
-    const int key[6] = {a->n_leapfrog, a->exchange_every, a->exchange_scheme,
-                        a->max_sep, a->sample_every, chunk};
-    if (!c->graph_exec || c->graph_version != c->table_version ||
-        memcmp(key, c->graph_key, sizeof(key)) != 0) {
-      c->drop_graph();
-      if (!c->cap_stream)
-        HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-      HIP_TRY(hipStreamBeginCapture(c->cap_stream,
-                                    hipStreamCaptureModeThreadLocal));
-      int crc = BPMF_OK;
-      for (int s = 0; s < chunk && crc == BPMF_OK; ++s)
-        crc = enqueue_sweep(c->cap_stream);
-      hipGraph_t g = nullptr;
-      const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
-      if (crc) {
-        if (g) (void)hipGraphDestroy(g);
-        return crc;
-      }
-      if (ec != hipSuccess)
-        return fail(BPMF_E_HIP, "graph capture: %s", hipGetErrorString(ec));
-      c->graph = g;
-      HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
-      c->graph_version = c->table_version;
-      memcpy(c->graph_key, key, sizeof(key));
+  const int P = a->pose_move_every;
+  // a run of `count` sweeps with its exchange/record bookkeeping
+  auto enqueue_run = [&](hipStream_t st, int count) -> int {
+    if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(c->d_ligs, nl, st));
+    for (int s = 0; s < count; ++s) {
+      const int r = enqueue_sweep(st);
+      if (r) return r;
     }
-    for (; done + chunk <= a->n_sweeps; done += chunk) {
+    if (tail.scheme == 0)
+      HIP_TRY(launch_sweep_finish(c->d_ligs, nl, tail.exchange_every,
+                                  tail.sample_every, c->seed, st));
+    return BPMF_OK;
+  };
+  // one pose move of every ligand that has a proposal
+  auto enqueue_pose = [&](hipStream_t st) -> int {
+    for (int l = 0; l < nl; ++l)
+      if (c->ligs[l].has_prop) {
+        const int r = pose_move_ligand(c, l, st);
+        if (r) return r;
+      }
+    return BPMF_OK;
+  };
+  // (re)capture `fn` into the context's graph under `key`; the kernels read
+  // every per-sweep quantity (counters, state maps) from device memory, so
+  // one capture replays unchanged
+  auto ensure_graph = [&](const int (&key)[8], auto&& fn) -> int {
+    if (c->graph_exec && c->graph_version == c->table_version &&
+        memcmp(key, c->graph_key, sizeof(key)) == 0)
+      return BPMF_OK;
+    c->drop_graph();
+    if (!c->cap_stream)
+      HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream,
+                                  hipStreamCaptureModeThreadLocal));
+    const int crc = fn(c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    if (crc) {
+      if (g) (void)hipGraphDestroy(g);
+      return crc;
+    }
+    if (ec != hipSuccess)
+      return fail(BPMF_E_HIP, "graph capture: %s", hipGetErrorString(ec));
+    c->graph = g;
+    HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    c->graph_version = c->table_version;
+    memcpy(c->graph_key, key, sizeof(key));
+    return BPMF_OK;
+  };
+  auto launch_timed = [&](int weight, auto&& fn) -> int {
+    hipEvent_t t0, t1;
+    const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1, weight);
+    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+    const int r = fn();
+    if (r) return r;
+    if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
+    return BPMF_OK;
+  };
+  const int chunk = c->graph_chunk;
+  if (P > 0) {
+    // units of P sweeps, each followed by a pose move; the network's
+    // scratch is sized before any capture
+    int maxK = 0;
+    for (auto& h : c->ligs)
+      if (h.has_prop) maxK = std::max(maxK, h.dev.K);
+    if (maxK > 0) {
+      MlpBufs b;
+      if ((rc = mlp_scratch(c, maxK, &b))) return rc;
+    }
+    const int units = a->n_sweeps / P, rest = a->n_sweeps % P;
+    auto unit = [&](hipStream_t st) -> int {
+      const int r = enqueue_run(st, P);
+      return r ? r : enqueue_pose(st);
+    };
+    if (chunk > 0 && units > 0) {
+      const int key[8] = {a->n_leapfrog, a->exchange_every, a->exchange_scheme,
+                          a->max_sep, a->sample_every, 0, P, 1};
+      if ((rc = ensure_graph(key, unit))) return rc;
+      for (int u = 0; u < units; ++u)
+        if ((rc = launch_timed(P, [&]() -> int {
+               HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+               return BPMF_OK;
+             })))
+          return rc;
+    } else {
+      for (int u = 0; u < units; ++u)
+        if ((rc = launch_timed(P, [&] { return unit(c->stream); }))) return rc;
+    }
+    if (rest > 0 &&
+        (rc = launch_timed(rest, [&] { return enqueue_run(c->stream, rest); })))
+      return rc;
+  } else {
+    if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(c->d_ligs, nl, c->stream));
+    int done = 0;
+    if (chunk > 0 && a->n_sweeps >= chunk) {
+      const int key[8] = {a->n_leapfrog, a->exchange_every, a->exchange_scheme,
+                          a->max_sep, a->sample_every, chunk, 0, 0};
+      if ((rc = ensure_graph(key, [&](hipStream_t st) -> int {
+             for (int s = 0; s < chunk; ++s) {
+               const int r = enqueue_sweep(st);
+               if (r) return r;
+             }
+             return BPMF_OK;
+           })))
+        return rc;
+      for (; done + chunk <= a->n_sweeps; done += chunk)
+        if ((rc = launch_timed(chunk, [&]() -> int {
+               HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+               return BPMF_OK;
+             })))
+          return rc;
+    }
+    for (; done < a->n_sweeps; ++done)
+      if ((rc = launch_timed(1, [&] { return enqueue_sweep(c->stream); })))
+        return rc;
+    if (tail.scheme == 0) {
       hipEvent_t t0, t1;
-      const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1, chunk);
+      const bool timed = c->timer_begin(BPMF_TIMER_TAIL, &t0, &t1);
       if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
-      HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+      HIP_TRY(launch_sweep_finish(c->d_ligs, nl, tail.exchange_every,
+                                  tail.sample_every, c->seed, c->stream));
       if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
     }
-  }
-  for (; done < a->n_sweeps; ++done) {
-    hipEvent_t t0, t1;
-    const bool timed = c->timer_begin(BPMF_TIMER_HMC, &t0, &t1);
-    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
-    if ((rc = enqueue_sweep(c->stream))) return rc;
-    if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
-  }
-  if (tail.scheme == 0) {
-    hipEvent_t t0, t1;
-    const bool timed = c->timer_begin(BPMF_TIMER_TAIL, &t0, &t1);
-    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
-    HIP_TRY(launch_sweep_finish(c->d_ligs, nl, tail.exchange_every,
-                                tail.sample_every, c->seed, c->stream));
-    if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   }
   for (size_t l = 0; l < c->ligs.size(); ++l) {
     c->ligs[l].counter += (uint64_t)a->n_sweeps;
@@ -1249,10 +1331,7 @@ extern "C" int bpmf_get_waves(bpmf_ctx* c, int ligand_id, int* waves) {
 // ============================================================================
 namespace {
 
-struct MlpBufs {
-  float *Z1, *H1, *Z2, *H2, *out, *dout, *dZ2, *dZ1, *bf, *bp;
-  double* loss_part;
-};
+
 
 int mlp_scratch(bpmf_ctx* c, int B, MlpBufs* b) {
   Arena A;
@@ -1292,23 +1371,23 @@ GemmArgs gemm(int M, int N, int K, const float* A, int64_t sam, int64_t sak,
 
 // out = MLP(feats) for B rows
 int mlp_forward(bpmf_ctx* c, const float* P, const float* feats, int B,
-                const MlpBufs& b, float* out) {
+                const MlpBufs& b, float* out, hipStream_t st) {
   HIP_TRY(launch_gemm(gemm(B, kNHid, kNFeat, feats, kNFeat, 1, P + kOffW1, kNHid,
                            1, b.H1, kNHid, P + kOffB1, kEpiSilu, b.Z1, nullptr),
-                      c->stream));
+                      st));
   HIP_TRY(launch_gemm(gemm(B, kNHid, kNHid, b.H1, kNHid, 1, P + kOffW2, kNHid, 1,
                            b.H2, kNHid, P + kOffB2, kEpiSilu, b.Z2, nullptr),
-                      c->stream));
+                      st));
   HIP_TRY(launch_gemm(gemm(B, kNOut, kNHid, b.H2, kNHid, 1, P + kOffW3, kNOut, 1,
                            out, kNOut, P + kOffB3, kEpiStore, nullptr, nullptr),
-                      c->stream));
+                      st));
   return BPMF_OK;
 }
 
 // gradient of the mean NLL of (feats, poses) into G; loss partials in b
 int mlp_grad(bpmf_ctx* c, const float* P, const float* feats,
              const float* poses, int B, const MlpBufs& b, float* G) {
-  int rc = mlp_forward(c, P, feats, B, b, b.out);
+  int rc = mlp_forward(c, P, feats, B, b, b.out, c->stream);
   if (rc) return rc;
   HIP_TRY(launch_nll(b.out, poses, B, b.dout, b.loss_part, c->stream));
   // dZ2 = (dout W3^T) * silu'(Z2); dZ1 = (dZ2 W2^T) * silu'(Z1)
@@ -1469,7 +1548,8 @@ extern "C" int bpmf_proposal_forward(bpmf_ctx* c, int lid,
   if (!dev_feats || !dev_out) return fail(BPMF_E_INVAL, "null argument");
   MlpBufs b;
   if ((rc = mlp_scratch(c, (int)N, &b))) return rc;
-  return mlp_forward(c, c->ligs[lid].params, dev_feats, (int)N, b, dev_out);
+  return mlp_forward(c, c->ligs[lid].params, dev_feats, (int)N, b, dev_out,
+                     c->stream);
 }
 
 extern "C" int bpmf_proposal_grad(bpmf_ctx* c, int lid, const float* dev_feats,
@@ -1518,7 +1598,7 @@ extern "C" int bpmf_proposal_train(bpmf_ctx* c, int lid, const float* dev_feats,
 }
 
 namespace {
-int pose_move_ligand(bpmf_ctx* c, int lid) {
+int pose_move_ligand(bpmf_ctx* c, int lid, hipStream_t st) {
   LigHost& h = c->ligs[lid];
   const int K = h.dev.K;
   MlpBufs b;
@@ -1526,11 +1606,11 @@ int pose_move_ligand(bpmf_ctx* c, int lid) {
   if (rc) return rc;
   // features of the current replicas, network, move
   HIP_TRY(launch_pose_features(c->d_ligs + lid, h.d_prop, h.dev.x, K, b.bf,
-                               b.bp, c->stream));
-  if ((rc = mlp_forward(c, h.params, b.bf, K, b, b.out))) return rc;
+                               b.bp, st));
+  if ((rc = mlp_forward(c, h.params, b.bf, K, b, b.out, st))) return rc;
   HIP_TRY(launch_pose_move(c->grid, c->d_ligs + lid, h.d_prop, b.out, K,
                            h.min_waves, lds_of(h, h.min_waves, false), c->seed,
-                           c->stream));
+                           st));
   return BPMF_OK;
 }
 }  // namespace
@@ -1544,7 +1624,7 @@ extern "C" int bpmf_pose_move(bpmf_ctx* c, int lid, int rounds) {
     for (size_t l = 0; l < c->ligs.size(); ++l) {
       if (lid != -1 && (int)l != lid) continue;
       if (!c->ligs[l].has_prop) continue;
-      if ((rc = pose_move_ligand(c, (int)l))) return rc;
+      if ((rc = pose_move_ligand(c, (int)l, c->stream))) return rc;
     }
   return BPMF_OK;
 }
@@ -1627,7 +1707,7 @@ extern "C" int bpmf_autotune(bpmf_ctx* c, int n_sweeps, int n_leapfrog,
     {
       c->waves_override = cand[q];
       if ((rc = rebuild_tables(c))) break;
-      bpmf_sweep_args a{2, n_leapfrog, 1, 0, 1, 0};
+      bpmf_sweep_args a{2, n_leapfrog, 1, 0, 1, 0, 0};
       if ((rc = bpmf_hmc_sweep(c, &a))) break;
       c->timing = true;
       c->timing_every = 1;

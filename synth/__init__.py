@@ -291,6 +291,58 @@ def ladder(K, T_hot=600.0, T_target=300.0, n_channels=3):
     return T, w
 
 
+def soft_schedule(K, T_hot=600.0, T_target=300.0):
+    """The paper's switching protocol between milestones C and D
+    (Thermodynamic Cycle): alpha_k = k/(K-1),
+        alpha_sg = 1 - (2 alpha - 1)^2,
+        alpha_g  = (2 alpha - 1)^2 / (1 + exp(-1000 (alpha - 1/2))),
+        T = (T_target - T_hot) alpha + T_hot,
+    the soft grids switched on first, then the original grids.  Returns T
+    (K,) and weights (K, 5) on the channels (rep, att, ele, soft rep, soft
+    ele), in float64 (exp(500) overflows float32)."""
+    a = np.linspace(0.0, 1.0, K)
+    sq = (2.0 * a - 1.0) ** 2
+    a_sg = 1.0 - sq
+    with np.errstate(over="ignore"):
+        a_g = sq / (1.0 + np.exp(-1000.0 * (a - 0.5)))
+    T = (T_target - T_hot) * a + T_hot
+    w = np.stack([a_g, a_g, a_g, a_sg, a_sg], axis=1)
+    return T, w
+
+
+def add_soft_grids(grid, ligands, cap_energy=10.0):
+    """Append the soft repulsive and electrostatic channels v_max tanh(v /
+    v_max) to a three-channel receptor grid and the matching per-atom
+    factors to the ligands (Thermodynamic Cycle, soft grids).
+
+    Readings: the paper's v_max = 10 is in its own grid units; here the
+    repulsive cap makes the soft repulsion of the median ligand atom at most
+    cap_energy kJ/mol (v_max = cap_energy / median s_rep), and, as in the
+    paper, the electrostatic cap keeps every atom's soft electrostatic
+    energy at or below its soft repulsive cap (v_max = v_max_rep x the
+    minimum over atoms of s_rep / |q|).  Both soft channels are stored and
+    interpolated untransformed."""
+    rep = grid.nodes[..., 0].astype(np.float64) ** 4
+    ele = grid.nodes[..., 2].astype(np.float64)
+    s_rep = np.concatenate([l.scale[:, 0] for l in ligands])
+    q = np.concatenate([np.abs(l.scale[:, 2]) for l in ligands])
+    vr = cap_energy / float(np.median(s_rep))
+    ratio = s_rep[q > 0] / q[q > 0]
+    ve = vr * float(ratio.min()) if ratio.size else vr
+    soft = np.stack([vr * np.tanh(rep / vr), ve * np.tanh(ele / ve)], axis=-1)
+    nodes = np.concatenate([grid.nodes, soft.astype(np.float32)], axis=-1)
+    out = Grid(grid.n, grid.origin, grid.spacing, tuple(grid.transform) +
+               (0, 0), nodes)
+    ligs = []
+    for l in ligands:
+        l2 = dataclasses.replace(l)
+        l2.scale = np.concatenate([l.scale, l.scale[:, [0, 2]]], axis=1)
+        T, w = soft_schedule(l.n_states)
+        l2.T, l2.w = T, w
+        ligs.append(l2)
+    return out, ligs
+
+
 def make_ligand(rng, n_atoms, K, box=6.0, dt=1.0, n_channels=3,
                 mass=MASS_C, ligand_seed=0):
     x, bonds, nbr = random_tree(rng, n_atoms, box=box)

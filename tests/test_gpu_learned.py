@@ -215,3 +215,40 @@ def test_training_on_sampled_poses_improves_the_proposal():
         (after["tries"].sum() - before["tries"].sum())
     assert acc1 > acc0
     ctx.close()
+
+
+def test_pose_moves_inside_sweep_calls_match_host_loop():
+    """hmc_sweep(pose_move_every=5) -- units of five sweeps and a pose move,
+    replayed from a captured graph or launched plainly -- gives the same bits
+    as the host alternating five-sweep calls and pose_move calls."""
+    print_case("pose_move_every")
+    system = synth.make_system(1)
+    lig = system.ligands[0]
+    p = flat(Lr.init_weights(np.random.default_rng(4)))
+    runs = []
+    for mode in ("host", "graph", "plain"):
+        ctx, (lid,) = make_context(system.grid, [lig], seed=13, capacity=10)
+        ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors], p)
+        if mode == "plain":
+            ctx.set_graph(0)
+        if mode == "host":
+            for _ in range(6):
+                ctx.hmc_sweep(5, 10, exchange_every=1, sample_every=3)
+                ctx.pose_move(lid, 1)
+            ctx.hmc_sweep(2, 10, exchange_every=1, sample_every=3)
+        else:
+            ctx.hmc_sweep(32, 10, exchange_every=1, sample_every=3,
+                          pose_move_every=5)
+        st = ctx.get_replicas(lid)
+        xs, cs = ctx.get_samples(lid)
+        ps = ctx.get_pose_stats(lid)
+        runs.append((st, xs, cs, ps))
+        ctx.close()
+    st0, xs0, cs0, ps0 = runs[0]
+    assert ps0["tries"].sum() == 6 * lig.n_states
+    for st, xs, cs, ps in runs[1:]:
+        for key in ("x", "state_of_replica", "comps", "counter"):
+            assert np.array_equal(st[key], st0[key]), key
+        assert np.array_equal(xs, xs0) and np.array_equal(cs, cs0)
+        assert np.array_equal(ps["acc"], ps0["acc"])
+        assert np.array_equal(ps["tries"], ps0["tries"])
