@@ -113,16 +113,24 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-// column sums of X (rows x cols, row stride ld): out[c] = sum_r X[r, c];
-// fixed summation order
+// column sums of X (rows x cols, row stride ld): out[c] = sum_r X[r, c].
+// 64 columns per block, each summed by 4 threads over interleaved rows and
+// the 4 partials added in a fixed order.
 __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ X,
                                                 int rows, int cols, int64_t ld,
                                                 float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+  __shared__ double part[4][64];
+  const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
   double s = 0.0;
-  for (int r = 0; r < rows; ++r) s += X[(int64_t)r * ld + c];
-  out[c] = (float)s;
+  if (c < cols) {
+#pragma unroll 8
+    for (int r = g; r < rows; r += 4) s += X[(int64_t)r * ld + c];
+  }
+  part[g][cl] = s;
+  __syncthreads();
+  if (g == 0 && c < cols)
+    out[c] = (float)(((part[0][cl] + part[1][cl]) + part[2][cl]) + part[3][cl]);
 }
 
 __device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
@@ -365,52 +373,63 @@ __global__ __launch_bounds__(128) void k_pose_features(
   }
 }
 
-// ln q(t, R) on SE(3) (Lebesgue x Haar written as J d^3 omega) of one mixture,
-// summing the preimages (theta + 2 pi m) n, m = -kFold .. kFold
-__device__ double log_q_se3(const Mix& p, const double t[3],
-                            const double w0[3]) {
+// wavefront maximum of a double (DPP tree as in wave_sum)
+__device__ __forceinline__ double wave_max_d(double v) {
+  v = fmax(v, dpp_d<0xB1, 0xf>(v));
+  v = fmax(v, dpp_d<0x4E, 0xf>(v));
+  v = fmax(v, dpp_d<0x141, 0xf>(v));
+  v = fmax(v, dpp_d<0x140, 0xf>(v));
+  // rows that receive no broadcast keep their value (bound_ctrl off): the
+  // update_dpp "old" operand is 0 there, so take max with the lane's own
+  const double b15 = dpp_d<0x142, 0xa>(v);
+  if ((threadIdx.x & 63) >= 16 && ((threadIdx.x >> 4) & 1)) v = fmax(v, b15);
+  const double b31 = dpp_d<0x143, 0xc>(v);
+  if ((threadIdx.x & 63) >= 32) v = fmax(v, b31);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// log q_SE3(t, omega): the mixture density of (t, omega') summed over the
+// preimages omega' = omega/|omega| (|omega| + 2 pi m), m = -kFold..kFold, of
+// the same rotation, each with the Haar-measure factor |omega'|^2 /
+// (2 (1 - cos|omega|)); one (preimage, component) term per lane of the
+// calling wavefront (all 64 lanes call; lanes past the terms add nothing)
+// and a log-sum-exp across the wavefront.  |omega| < 1e-9: the identity
+// rotation, one term per component.
+__device__ double log_q_se3_wave(const Mix& p, const double t[3],
+                                 const double w0[3]) {
+  const int lane = threadIdx.x & 63;
   const double th = sqrt(w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2]);
-  double lt[kNComp];
-  for (int j = 0; j < kNComp; ++j) {
+  const bool small = th < 1e-9;
+  const int n_terms = small ? kNComp : (2 * kFold + 1) * kNComp;
+  double term = -INFINITY;
+  if (lane < n_terms) {
+    const int j = lane % kNComp, m = lane / kNComp - kFold;
     double s = p.lw[j] - 3.0 * log(2.0 * M_PI);
     for (int d = 0; d < 3; ++d) {
       const double z = (t[d] - p.mt[j][d]) / p.st[j][d];
       s += -0.5 * z * z - log((double)p.st[j][d]) - log((double)p.sw[j][d]);
     }
-    lt[j] = s;
-  }
-  double terms[(2 * kFold + 1) * kNComp];
-  int nt = 0;
-  double mx = -INFINITY;
-  if (th < 1e-9) {
-    for (int j = 0; j < kNComp; ++j) {
-      double s = lt[j];
+    if (small) {
       for (int d = 0; d < 3; ++d) {
         const double z = (0.0 - p.mw[j][d]) / p.sw[j][d];
         s += -0.5 * z * z;
       }
-      terms[nt++] = s;
-      mx = fmax(mx, s);
-    }
-  } else {
-    const double lj = log(2.0 * (1.0 - cos(th)));
-    for (int m = -kFold; m <= kFold; ++m) {
+    } else {
       const double a = th + 2.0 * M_PI * m;
-      const double la = 2.0 * log(fabs(a)) - lj;
-      for (int j = 0; j < kNComp; ++j) {
-        double s = lt[j] + la;
-        for (int d = 0; d < 3; ++d) {
-          const double z = (a * w0[d] / th - p.mw[j][d]) / p.sw[j][d];
-          s += -0.5 * z * z;
-        }
-        terms[nt++] = s;
-        mx = fmax(mx, s);
+      s += 2.0 * log(fabs(a)) - log(2.0 * (1.0 - cos(th)));
+      for (int d = 0; d < 3; ++d) {
+        const double z = (a * w0[d] / th - p.mw[j][d]) / p.sw[j][d];
+        s += -0.5 * z * z;
       }
     }
+    term = s;
   }
-  double sum = 0.0;
-  for (int q = 0; q < nt; ++q) sum += exp(terms[q] - mx);
-  return mx + log(sum);
+  const double mx = wave_max_d(term);
+  const double e = lane < n_terms ? exp(term - mx) : 0.0;
+  return mx + log(wave_sum(e));
 }
 
 // Independence MH pose move, one workgroup of W waves per replica.
@@ -429,13 +448,52 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
   const unsigned long long s = *L.counter;
   const int k = L.state_of_replica[r];
   const float* xr = L.x + (size_t)r * n * 3;
-  // current pose, proposal and the proposal-density ratio (thread 0, double)
+  // current pose, proposal and the proposal-density ratio (double): the
+  // centre of mass by a block reduction, the mixture parsed one component
+  // per lane, the two proposal densities one term per lane of wave 0, the
+  // frames and the draws on thread 0
+  __shared__ double s_cp[2 * W * 3];
+  __shared__ Mix s_mix;
+  __shared__ double s_pose[12];  // t0, w0, t1, w1p
   double lq_ratio = 0.0;
+  {
+    const bool own = tid < n;
+    const double mi = own ? (double)L.mass[tid] : 0.0;
+    const double cx = wave_sum(own ? mi * xr[3 * tid] : 0.0);
+    const double cy = wave_sum(own ? mi * xr[3 * tid + 1] : 0.0);
+    const double cz = wave_sum(own ? mi * xr[3 * tid + 2] : 0.0);
+    const double cm = wave_sum(mi);
+    if ((tid & 63) == 0) {
+      const int wv = tid >> 6;
+      s_cp[4 * wv] = cx;
+      s_cp[4 * wv + 1] = cy;
+      s_cp[4 * wv + 2] = cz;
+      s_cp[4 * wv + 3] = cm;
+    }
+    if (tid < kNComp) {
+      const float* o = out + (size_t)r * kNOut + 13 * tid;
+      s_mix.lw[tid] = o[0];
+      for (int a = 0; a < 3; ++a) {
+        s_mix.mt[tid][a] = o[1 + a];
+        s_mix.mw[tid][a] = (float)M_PI * tanhf(o[4 + a]);
+        s_mix.st[tid][a] = kSt0 + (kSt1 - kSt0) * sigm(o[7 + a]);
+        s_mix.sw[tid][a] = kSw0 + (kSw1 - kSw0) * sigm(o[10 + a]);
+      }
+    }
+  }
+  __syncthreads();
   if (tid == 0) {
+    // normalised log weights (log-softmax of the raw logits)
+    float mx = -INFINITY;
+    for (int j = 0; j < kNComp; ++j) mx = fmaxf(mx, s_mix.lw[j]);
+    float sm = 0.f;
+    for (int j = 0; j < kNComp; ++j) sm += expf(s_mix.lw[j] - mx);
+    const float lse = mx + logf(sm);
+    for (int j = 0; j < kNComp; ++j) s_mix.lw[j] -= lse;
     double c[3] = {0, 0, 0}, M = 0;
-    for (int a = 0; a < n; ++a) {
-      M += L.mass[a];
-      for (int d = 0; d < 3; ++d) c[d] += (double)L.mass[a] * xr[3 * a + d];
+    for (int q = 0; q < W; ++q) {
+      for (int d = 0; d < 3; ++d) c[d] += s_cp[4 * q + d];
+      M += s_cp[4 * q + 3];
     }
     Frame F;
     body_frame(xr, P.frame, F);
@@ -443,19 +501,17 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) R0[a][b] = F.R[a][b];
     log_rot(R0, w0);
-    double t0[3];
     for (int d = 0; d < 3; ++d) {
       c[d] /= M;
-      t0[d] = c[d] - L.site[d];
+      s_pose[d] = c[d] - L.site[d];
+      s_pose[3 + d] = w0[d];
     }
-    Mix p;
-    mixture_of(out + (size_t)r * kNOut, p);
     // component by inverse CDF, then (t, omega) by Gaussian draws
     const U4 o0 = draw(seed, 0u, L.id, r, s, kPose);
     const double u = u01d(o0.x);
     double cum[kNComp], tot = 0.0;
     for (int j = 0; j < kNComp; ++j) {
-      tot += exp((double)p.lw[j]);
+      tot += exp((double)s_mix.lw[j]);
       cum[j] = tot;
     }
     int j = 0;
@@ -465,14 +521,17 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     normals3(draw(seed, 2u, L.id, r, s, kPose), z[3], z[4], z[5]);
     double t1[3], w1[3];
     for (int d = 0; d < 3; ++d) {
-      t1[d] = (double)p.mt[j][d] + (double)p.st[j][d] * z[d];
-      w1[d] = (double)p.mw[j][d] + (double)p.sw[j][d] * z[3 + d];
+      t1[d] = (double)s_mix.mt[j][d] + (double)s_mix.st[j][d] * z[d];
+      w1[d] = (double)s_mix.mw[j][d] + (double)s_mix.sw[j][d] * z[3 + d];
     }
     double R1[3][3];
     rodrigues(w1, R1);
     double w1p[3];
     log_rot(R1, w1p);  // principal rotation vector of the proposal
-    lq_ratio = log_q_se3(p, t0, w0) - log_q_se3(p, t1, w1p);
+    for (int d = 0; d < 3; ++d) {
+      s_pose[6 + d] = t1[d];
+      s_pose[9 + d] = w1p[d];
+    }
     // x'_i = c0 + t' + R' R0^T (x_i - c): the rotation applied is R' R0^T
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
@@ -484,7 +543,14 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
       st[d] = (float)(L.site[d] + t1[d]);
       scom[d] = (float)c[d];
     }
-    s_ok = isfinite(lq_ratio) ? 1 : 0;
+  }
+  __syncthreads();
+  if (tid < kWave) {
+    const Mix& p = s_mix;
+    const double lq0 = log_q_se3_wave(p, s_pose, s_pose + 3);
+    const double lq1 = log_q_se3_wave(p, s_pose + 6, s_pose + 9);
+    lq_ratio = lq0 - lq1;
+    if (tid == 0) s_ok = isfinite(lq_ratio) ? 1 : 0;
   }
   __syncthreads();
   Shared sh;
@@ -555,7 +621,7 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t st) {
 
 hipError_t launch_colsum(const float* X, int rows, int cols, int64_t ld,
                          float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_colsum, dim3((cols + 255) / 256), dim3(256), 0, st, X,
+  hipLaunchKernelGGL(k_colsum, dim3((cols + 63) / 64), dim3(256), 0, st, X,
                      rows, cols, ld, out);
   return hipGetLastError();
 }
