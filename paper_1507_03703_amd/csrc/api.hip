@@ -96,6 +96,7 @@ struct bpmf_ctx {
   int class_off[kWaveClasses] = {0, 0, 0, 0};
   int class_n[kWaveClasses] = {0, 0, 0, 0};
   int class_lds[kWaveClasses] = {0, 0, 0, 0};
+  int class_single[kWaveClasses] = {-1, -1, -1, -1};  // sole ligand or -1
   int waves_override = 0;  // 0 = automatic choice
   // scratch
   void* comps_mem = nullptr;
@@ -273,6 +274,11 @@ int rebuild_tables(bpmf_ctx* c) {
     c->class_off[q] = off[q];
     c->class_n[q] = (int)cls[q].size();
     c->class_lds[q] = lds[q];
+    // a class holding the replicas of one ligand (0..K-1 in order) passes
+    // that ligand's table entry as a kernel argument
+    c->class_single[q] = -1;
+    if (!cls[q].empty() && cls[q].front().x == cls[q].back().x)
+      c->class_single[q] = cls[q].front().x;
   }
   return BPMF_OK;
 }
@@ -747,10 +753,12 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
   auto enqueue_sweep = [&](hipStream_t st) -> int {
     for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
       if (c->class_n[q])
-        HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs,
-                                 c->d_tasks + c->class_off[q], c->class_n[q],
-                                 1 << q, c->class_lds[q], a->n_leapfrog,
-                                 c->seed, tail, st));
+        HIP_TRY(launch_hmc_sweep(
+            c->grid, c->d_ligs, c->d_tasks + c->class_off[q], c->class_n[q],
+            1 << q, c->class_lds[q], a->n_leapfrog, c->seed, tail,
+            c->class_single[q] >= 0 ? &c->ligs[c->class_single[q]].dev
+                                    : nullptr,
+            st));
     if (tail.scheme == 1)
       HIP_TRY(launch_sweep_tail(c->d_ligs, nl, tail.exchange_every,
                                 tail.scheme, tail.max_sep, tail.sample_every,

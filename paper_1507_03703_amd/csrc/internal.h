@@ -94,10 +94,13 @@ struct LigDev {
 struct TailArgs {
   int exchange_every, scheme, max_sep, sample_every;
 };
+// one: the host copy of the table entry when the launch covers a single
+// ligand (its replicas 0..n_tasks-1 in order), else null
 hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
                             const int2* d_tasks, int n_tasks, int waves,
                             int lds_bytes, int nleap, uint64_t seed,
-                            TailArgs tail, hipStream_t st);
+                            TailArgs tail, const LigDev* one,
+                            hipStream_t st);
 hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
                              int exchange_every, int scheme, int max_sep,
                              int sample_every, uint64_t seed, hipStream_t st);

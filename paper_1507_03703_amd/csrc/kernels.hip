@@ -158,38 +158,61 @@ __device__ double state_energy_of(const LigDev& L, int k, const double* cp) {
   return E;
 }
 
+// The neighbour pair (lo, hi) of state a in the exchange that ends sweep
+// s - 1, if that exchange is due and a has a partner.
+struct Pair {
+  int lo, hi;
+  bool active;
+};
+__device__ __forceinline__ Pair own_pair(int K, int a, unsigned long long s,
+                                         int exchange_every) {
+  Pair p{a, a, false};
+  if (exchange_every <= 0 || s == 0ull || K < 2) return p;
+  const unsigned long long sw = s - 1ull;
+  if (sw % (unsigned long long)exchange_every != 0ull) return p;
+  const int a0 = (int)(sw & 1ull);
+  if (a < a0) return p;
+  if (((a - a0) & 1) == 0) {
+    if (a + 1 >= K) return p;
+    p.lo = a;
+    p.hi = a + 1;
+  } else {
+    p.lo = a - 1;
+    p.hi = a;
+  }
+  p.active = true;
+  return p;
+}
+
+// Metropolis decision on pair p from buffer `pin` (attempt_pair's expression
+// on the same numbers).
+__device__ bool pair_accepts(const LigDev& L, Pair p, int pin,
+                             unsigned long long s, uint64_t seed) {
+  const int C1 = 1 + L.C;
+  const double* clo = L.scomp + ((size_t)pin * L.K + p.lo) * C1;
+  const double* chi = L.scomp + ((size_t)pin * L.K + p.hi) * C1;
+  const double delta =
+      L.beta[p.lo] * (state_energy_of(L, p.lo, chi) -
+                      state_energy_of(L, p.lo, clo)) +
+      L.beta[p.hi] * (state_energy_of(L, p.hi, clo) -
+                      state_energy_of(L, p.hi, chi));
+  const uint32_t purpose = (uint32_t)kExchange | (1u << 8);
+  const U4 o = draw(seed, (uint32_t)p.lo, L.id, 0, s - 1ull, purpose);
+  const double lnu = log(u01d(o.x));
+  return isfinite(delta) && (lnu < -delta);
+}
+
 __device__ int deferred_state(const LigDev& L, int a, unsigned long long s,
                               int pin, int exchange_every, uint64_t seed,
                               bool stats) {
-  if (exchange_every <= 0 || s == 0ull || L.K < 2) return a;
-  const unsigned long long sw = s - 1ull;
-  if (sw % (unsigned long long)exchange_every != 0ull) return a;
-  const int a0 = (int)(sw & 1ull);
-  if (a < a0) return a;
-  int lo, hi;
-  if (((a - a0) & 1) == 0) {
-    lo = a;
-    hi = a + 1;
-    if (hi >= L.K) return a;
-  } else {
-    lo = a - 1;
-    hi = a;
+  const Pair p = own_pair(L.K, a, s, exchange_every);
+  if (!p.active) return a;
+  const bool ok = pair_accepts(L, p, pin, s, seed);
+  if (stats && a == p.lo) {
+    atomicAdd(&L.ex_try[p.lo], 1ull);
+    if (ok) atomicAdd(&L.ex_acc[p.lo], 1ull);
   }
-  const int C1 = 1 + L.C;
-  const double* clo = L.scomp + ((size_t)pin * L.K + lo) * C1;
-  const double* chi = L.scomp + ((size_t)pin * L.K + hi) * C1;
-  const double delta =
-      L.beta[lo] * (state_energy_of(L, lo, chi) - state_energy_of(L, lo, clo)) +
-      L.beta[hi] * (state_energy_of(L, hi, clo) - state_energy_of(L, hi, chi));
-  const uint32_t purpose = (uint32_t)kExchange | (1u << 8);
-  const U4 o = draw(seed, (uint32_t)lo, L.id, 0, sw, purpose);
-  const double lnu = log(u01d(o.x));
-  const bool ok = isfinite(delta) && (lnu < -delta);
-  if (stats && a == lo) {
-    atomicAdd(&L.ex_try[lo], 1ull);
-    if (ok) atomicAdd(&L.ex_acc[lo], 1ull);
-  }
-  return ok ? (a == lo ? hi : lo) : a;
+  return ok ? (a == p.lo ? p.hi : p.lo) : a;
 }
 #pragma clang fp contract(fast)
 
@@ -262,44 +285,37 @@ __global__ __launch_bounds__(256) void k_sweep_finish(
 // HMC: one trial move per replica, one workgroup of W wavefronts per replica.
 // (Sampling: HMC trial moves from velocity-Verlet molecular dynamics.)
 // ----------------------------------------------------------------------------
-template <int C, int W>
+// ONE: the launch covers the replicas of a single ligand, whose table entry
+// comes in the kernel arguments (block b = replica b) instead of through the
+// task list.
+template <int C, int W, bool ONE>
 __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     GridDev g, const LigDev* __restrict__ ligs, const int2* __restrict__ tasks,
-    int nleap, uint64_t seed, TailArgs tail) {
+    LigDev one, int nleap, uint64_t seed, TailArgs tail) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
-  const int2 task = tasks[blockIdx.x];
-  const LigDev L = ligs[task.x];  // kernel-lifetime copy (no reloads)
+  const int2 task = ONE ? make_int2(0, (int)blockIdx.x) : tasks[blockIdx.x];
+  const LigDev L = ONE ? one : ligs[task.x];  // kernel-lifetime copy
   const int r = task.y;
   const int n = L.n;
-  const Shared sh = carve<W>(smem, L, L.n, tid);
-  __shared__ double fin[2 * W];
-
-  // sweep index and state: scheme 0 first applies the exchange (and
-  // record) that ended the previous sweep, from the double buffer
   const bool deferred = tail.scheme == 0;
+
+  // per-replica state and per-atom data: issued before the topology is
+  // staged so that both latencies overlap
   unsigned long long s;
-  int k, a = 0, pin = 0;
+  int a = 0, pin = 0;
   bool pend = false;
   if (deferred) {
     s = L.rcnt[r];
+    const int a0 = L.rsor[r], a1 = L.rsor[L.K + r];
+    const int p0 = L.rpend[r], p1 = L.rpend[L.K + r];
     pin = (int)((s - 1ull) & 1ull);
-    pend = L.rpend[pin * L.K + r] != 0;
-    a = L.rsor[pin * L.K + r];
-    k = pend ? deferred_state(L, a, s, pin, tail.exchange_every, seed,
-                              tid == 0)
-             : a;
+    a = pin ? a1 : a0;
+    pend = (pin ? p1 : p0) != 0;
   } else {
     s = *L.counter;
-    k = L.state_of_replica[r];
+    a = L.state_of_replica[r];
   }
-  float w[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) w[c] = L.wf[k * C + c];
-  const float T = L.Tf[k];
-  const float dt = L.dtf[k];
-  const double beta = L.beta[k];
-
   const bool owner = tid < n;
   float x[3], v[3], f[3];
   const float m = owner ? L.mass[tid] : 0.f;
@@ -310,6 +326,40 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   const float* xr = L.x + (size_t)r * n * 3;
 #pragma unroll
   for (int d = 0; d < 3; ++d) x[d] = owner ? xr[tid * 3 + d] : 0.f;
+
+  // scheme 0 first applies the exchange (and record) that ended the previous
+  // sweep, from the double buffer; the parameters of both states of the
+  // replica's pair are loaded with the pair's components
+  const Pair pr = (deferred && pend) ? own_pair(L.K, a, s, tail.exchange_every)
+                                     : Pair{a, a, false};
+  const int kb = pr.active ? (a == pr.lo ? pr.hi : pr.lo) : a;
+  float wa[C], wb[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    wa[c] = L.wf[a * C + c];
+    wb[c] = L.wf[kb * C + c];
+  }
+  const float Ta = L.Tf[a], Tb = L.Tf[kb];
+  const float dta = L.dtf[a], dtb = L.dtf[kb];
+  const double ba = L.beta[a], bb = L.beta[kb];
+  bool swap = false;
+  if (pr.active) {
+    swap = pair_accepts(L, pr, pin, s, seed);
+    if (tid == 0 && a == pr.lo) {
+      atomicAdd(&L.ex_try[pr.lo], 1ull);
+      if (swap) atomicAdd(&L.ex_acc[pr.lo], 1ull);
+    }
+  }
+  const int k = swap ? kb : a;
+  float w[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) w[c] = swap ? wb[c] : wa[c];
+  const float T = swap ? Tb : Ta;
+  const float dt = swap ? dtb : dta;
+  const double beta = swap ? bb : ba;
+
+  const Shared sh = carve<W>(smem, L, L.n, tid);
+  __shared__ double fin[2 * W];
   const int C1 = 1 + C;
   // the previous sweep's round: this replica's configuration and components
   // go to the slot of its state after that exchange.  The replica's record
@@ -640,12 +690,23 @@ int grid_blocks(int64_t work, int per_block, int cap) {
 hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
                             const int2* d_tasks, int n_tasks, int waves,
                             int lds_bytes, int nleap, uint64_t seed,
-                            TailArgs tail, hipStream_t st) {
+                            TailArgs tail, const LigDev* one,
+                            hipStream_t st) {
   if (n_tasks <= 0) return hipSuccess;
-  BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
-    hipLaunchKernelGGL((k_hmc_sweep<C, W>), dim3(n_tasks), dim3(W * kWave),
-                       lds_bytes, st, g, d_ligs, d_tasks, nleap, seed, tail);
-  }));
+  if (one) {
+    BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
+      hipLaunchKernelGGL((k_hmc_sweep<C, W, true>), dim3(n_tasks),
+                         dim3(W * kWave), lds_bytes, st, g, d_ligs, d_tasks,
+                         *one, nleap, seed, tail);
+    }));
+  } else {
+    const LigDev none{};
+    BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
+      hipLaunchKernelGGL((k_hmc_sweep<C, W, false>), dim3(n_tasks),
+                         dim3(W * kWave), lds_bytes, st, g, d_ligs, d_tasks,
+                         none, nleap, seed, tail);
+    }));
+  }
   return hipGetLastError();
 }
 
