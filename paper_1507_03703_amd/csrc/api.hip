@@ -579,6 +579,8 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_rnrec = A.add(K * 8), o_rpend = A.add(2 * K * 4),
                o_rsor = A.add(2 * K * 4),
                o_scomp = A.add((size_t)2 * K * C1 * 8),
+               o_fcache = A.add((size_t)2 * K * n * (3 + 3 * C) * 4),
+               o_frc = A.add((size_t)2 * K * 4 * 4), o_fvalid = A.add(K * 4),
                o_sx = A.add((size_t)cap * K * n * 12),
                o_sc = A.add((size_t)cap * K * C1 * 8);
   {
@@ -670,6 +672,9 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.rpend = (int*)(base + o_rpend);
   L.rsor = (int*)(base + o_rsor);
   L.scomp = (double*)(base + o_scomp);
+  L.fcache = (float*)(base + o_fcache);
+  L.frc = (float*)(base + o_frc);
+  L.fvalid = (int*)(base + o_fvalid);
   L.hmc_acc = (unsigned long long*)(base + o_hacc);
   L.hmc_try = (unsigned long long*)(base + o_htry);
   L.ex_acc = (unsigned long long*)(base + o_eacc);
@@ -1196,6 +1201,8 @@ extern "C" int bpmf_set_replicas(bpmf_ctx* c, int ligand_id, const float* x,
                          hipMemcpyHostToDevice, c->stream));
   unsigned long long cnt = counter;
   HIP_TRY(hipMemcpyAsync(L.counter, &cnt, 8, hipMemcpyHostToDevice, c->stream));
+  // new positions: no reusable start-of-trajectory forces
+  HIP_TRY(hipMemsetAsync(L.fvalid, 0, (size_t)L.K * 4, c->stream));
   if (comps)
     HIP_TRY(hipMemcpyAsync(L.comps, comps, (size_t)L.K * (1 + L.C) * 8,
                            hipMemcpyHostToDevice, c->stream));

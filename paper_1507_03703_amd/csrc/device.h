@@ -486,6 +486,29 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
 
 constexpr int kRedMax = kRedSlots;  // U_bond..U_tors, Psi_c, two extras
 
+// Force assembly of one atom, shared by eval_block and the sweep kernel's
+// start-of-trajectory reuse so that both give the same bits:
+// ge = -sum_c w_c grad e_c (channels in order), then + the restraint force
+// fr m (c - c0), then f = bonded + ge.
+template <int C>
+__device__ __forceinline__ void grid_force(const float* w,
+                                           const float (&de)[C][3],
+                                           float (&ge)[3]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    ge[0] -= w[c] * de[c][0];
+    ge[1] -= w[c] * de[c][1];
+    ge[2] -= w[c] * de[c][2];
+  }
+}
+__device__ __forceinline__ void restraint_force(float fr, float m, float cx,
+                                                float cy, float cz,
+                                                float (&ge)[3]) {
+  ge[0] += fr * m * cx;
+  ge[1] += fr * m * cy;
+  ge[2] += fr * m * cz;
+}
+
 // first wavefront that takes bonded terms (see eval_block)
 __device__ __forceinline__ int bonded_first_wave(int waves, int atom_waves) {
   return (waves >= 4 && waves >= 2 * atom_waves) ? atom_waves : 0;
@@ -509,7 +532,9 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
                                            float (&f)[3],
                                            double (&terms)[6 + C],
                                            float ex0, float ex1,
-                                           const Shared& sh, int tid) {
+                                           const Shared& sh, int tid,
+                                           float* cache_atom = nullptr,
+                                           float* cache_rep = nullptr) {
   const int n = L.n;
   const int lane = tid & (kWave - 1), wv = tid >> 6;
   const bool owner = tid < n;
@@ -557,6 +582,7 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
 #pragma unroll
   for (int c = 0; c < C; ++c) psi[c] = 0.f;
   float ge[3] = {0.f, 0.f, 0.f};
+  float de[C][3];
   float px = 0.f, py = 0.f, pz = 0.f;
   if (wave_has_atoms) {
     px = m * x[0];
@@ -568,18 +594,11 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
       sh.com[3 * wv + 1] = py;
       sh.com[3 * wv + 2] = pz;
     }
-    float e[C], de[C][3];
+    float e[C];
     grid_finish<C, FORCES>(g, cn, sc, e, de);
 #pragma unroll
     for (int c = 0; c < C; ++c) psi[c] = e[c];
-    if (FORCES) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        ge[0] -= w[c] * de[c][0];
-        ge[1] -= w[c] * de[c][1];
-        ge[2] -= w[c] * de[c][2];
-      }
-    }
+    if (FORCES) grid_force<C>(w, de, ge);
   }
   // centre of mass offset from the site (fixed-order sum of the atom waves'
   // partials; with one atom wave its own sums are the total)
@@ -604,15 +623,13 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   if (FORCES) {
     // restraint force -(m_i/M) k (d - d0) (c - c0)/d, before the barrier
     // when this wave's sums are the whole centre of mass
+    float fr = 0.f;
     auto add_restraint = [&]() {
       com_offset();
       const float d = sqrtf(cx * cx + cy * cy + cz * cz);
       const float excess = d - L.d0;
-      const float fr =
-          excess > 0.f ? -L.krest * excess / d * L.inv_total_mass : 0.f;
-      ge[0] += fr * m * cx;
-      ge[1] += fr * m * cy;
-      ge[2] += fr * m * cz;
+      fr = excess > 0.f ? -L.krest * excess / d * L.inv_total_mass : 0.f;
+      restraint_force(fr, m, cx, cy, cz, ge);
     };
     if (n_atom_waves == 1 && wv == 0) add_restraint();
     block_sync();
@@ -621,12 +638,31 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
       // bonded forces: read and clear the atom's fixed-point accumulator
       // (the next evaluation adds into it only after its first barrier)
       unsigned int* a3 = sh.sl.acc + 3 * tid;
-      f[0] = from_fix(a3[0]) + ge[0];
-      f[1] = from_fix(a3[1]) + ge[1];
-      f[2] = from_fix(a3[2]) + ge[2];
+      const float b[3] = {from_fix(a3[0]), from_fix(a3[1]), from_fix(a3[2])};
+      f[0] = b[0] + ge[0];
+      f[1] = b[1] + ge[1];
+      f[2] = b[2] + ge[2];
       a3[0] = 0u;
       a3[1] = 0u;
       a3[2] = 0u;
+      // the parts of the force that do not depend on the state weights
+      if (cache_atom) {
+        cache_atom[0] = b[0];
+        cache_atom[1] = b[1];
+        cache_atom[2] = b[2];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          cache_atom[3 + 3 * c] = de[c][0];
+          cache_atom[4 + 3 * c] = de[c][1];
+          cache_atom[5 + 3 * c] = de[c][2];
+        }
+      }
+      if (cache_rep && tid == 0) {
+        cache_rep[0] = fr;
+        cache_rep[1] = cx;
+        cache_rep[2] = cy;
+        cache_rep[3] = cz;
+      }
     } else {
       f[0] = f[1] = f[2] = 0.f;
     }

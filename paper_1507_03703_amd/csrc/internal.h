@@ -83,6 +83,14 @@ struct LigDev {
   int* rpend;                 // 2K: exchange/record of the previous sweep due
   int* rsor;                  // 2K: state of each replica
   double* scomp;              // 2K(1+C): components of the replica in each state
+  // start-of-trajectory force reuse: per replica two slots of the parts of
+  // the force at its current positions that do not depend on the state
+  // (per atom: bonded force, grid gradients of every channel; per replica:
+  // restraint factor and centre-of-mass offset); fvalid[r] = 0 (none) or
+  // 1 + the slot holding the current positions' parts
+  float* fcache;              // 2K x n x (3 + 3C)
+  float* frc;                 // 2K x 4
+  int* fvalid;                // K
   float* samp_x;                  // cap*K*n*3
   double* samp_c;                 // cap*K*(1+C)
 };

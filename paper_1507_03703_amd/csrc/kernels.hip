@@ -316,6 +316,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     s = *L.counter;
     a = L.state_of_replica[r];
   }
+  const int fv = L.fvalid[r];
   const bool owner = tid < n;
   float x[3], v[3], f[3];
   const float m = owner ? L.mass[tid] : 0.f;
@@ -393,10 +394,45 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   }
   const float ke0 = 0.5f * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
 
+  // start of the trajectory: force and energy at the current positions,
+  // rebuilt from the state-independent parts stored when these positions
+  // were last evaluated (same arithmetic, same bits), or evaluated
+  constexpr int kFC = 3 + 3 * C;
+  const int cur = fv > 0 ? fv - 1 : 0, nxt = 1 - cur;
+  float* const fc_cur = L.fcache + ((size_t)cur * L.K + r) * n * kFC;
+  float* const fc_nxt = L.fcache + ((size_t)nxt * L.K + r) * n * kFC;
   double U0, KE0;
-  {
+  if (fv > 0) {
+    const double* cp = deferred ? L.scomp + ((size_t)pin * L.K + a) * C1
+                                : L.comps + (size_t)r * C1;
+    U0 = cp[0];
+#pragma unroll
+    for (int c = 0; c < C; ++c) U0 += L.wd[k * C + c] * cp[1 + c];
+    if (owner) {
+      const float* ca = fc_cur + (size_t)tid * kFC;
+      const float* cr = L.frc + ((size_t)cur * L.K + r) * 4;
+      float de[C][3], ge[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) de[c][d] = ca[3 + 3 * c + d];
+      grid_force<C>(w, de, ge);
+      restraint_force(cr[0], m, cr[1], cr[2], cr[3], ge);
+      f[0] = ca[0] + ge[0];
+      f[1] = ca[1] + ge[1];
+      f[2] = ca[2] + ge[2];
+    } else {
+      f[0] = f[1] = f[2] = 0.f;
+    }
+    double ke, unused;
+    block_sum2<W>(ke0, 0.f, fin, tid, ke, unused);
+    KE0 = ke * 1e4;
+  } else {
     double t0[6 + C];
-    eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t0, ke0, 0.f, sh, tid);
+    eval_block<C, W, true, true>(
+        g, L, w, x, m, sc, f, t0, ke0, 0.f, sh, tid,
+        owner ? fc_cur + (size_t)tid * kFC : nullptr,
+        L.frc + ((size_t)cur * L.K + r) * 4);
     U0 = t0[0] + t0[1] + t0[2] + t0[3];
 #pragma unroll
     for (int c = 0; c < C; ++c) U0 += L.wd[k * C + c] * t0[4 + c];
@@ -421,7 +457,9 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     v[d] = fmaf(hk, f[d], v[d]);
     x[d] = fmaf(dt, v[d], x[d]);
   }
-  eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid);
+  eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid,
+                               owner ? fc_nxt + (size_t)tid * kFC : nullptr,
+                               L.frc + ((size_t)nxt * L.K + r) * 4);
 #pragma unroll
   for (int d = 0; d < 3; ++d) v[d] = fmaf(hk, f[d], v[d]);
   double U1 = t1[0] + t1[1] + t1[2] + t1[3];
@@ -463,6 +501,8 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
       L.comps[(size_t)r * C1 + tid] = cv;
   }
   if (tid == 0) {
+    // the stored parts of the replica's (new or kept) positions
+    L.fvalid[r] = 1 + (accept ? nxt : cur);
     atomicAdd(&L.hmc_try[k], 1ull);
     if (accept) atomicAdd(&L.hmc_acc[k], 1ull);
     if (!finite) atomicAdd(L.nonfinite, 1ull);

@@ -603,6 +603,7 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
       double* cw = L.comps + (size_t)r * (1 + C);
       cw[0] = t1e[0] + t1e[1] + t1e[2] + t1e[3];
       for (int c = 0; c < C; ++c) cw[1 + c] = t1e[4 + c];
+      L.fvalid[r] = 0;  // the stored start-of-trajectory forces are stale
     }
   }
 }
