@@ -3,8 +3,9 @@ ligand's replicas go through the same per-sweep launches (grouped by the
 number of wavefronts a replica uses), each ligand with its own ladder,
 Philox stream, exchange and sample store.  Parity is lock-step against one
 oracle sampler per checked ligand (tests/lockstep.py), at test size and on
-sampled ligands of the full 256-ligand, 160^3-grid workload; the autotuner
-must leave the sampler state untouched.
+sampled ligands of the full 256-ligand, 160^3-grid workload and of the
+32-ligand, 256^3-grid workload; the autotuner must leave the sampler state
+untouched.
 """
 import json
 
@@ -136,3 +137,34 @@ def test_full_batched_workload_sampled_ligands():
     assert acc.sum() > 0.5 * 66 * 32 * len(ids)
     ctx.close()
     ref.close()
+
+
+def test_large_grid_workload_sampled_ligands():
+    """32 ligands of 40..100 atoms (one or two wavefronts of atoms) with 32
+    states each on the shared 256^3 grid (201 MB, flat indices up to 5e7):
+    lock-step sweeps on sampled ligands, including the widest, and the
+    energy matrix of recorded samples against the oracle's brute force."""
+    system = synth.make_system(5, grid_device="cuda:0")
+    g, ligs = system.grid, system.ligands
+    counts = np.array([l.n_atoms for l in ligs])
+    print_case("c5 full", len(ligs), counts.min(), counts.max())
+    ctx, ids = make_context(g, ligs, seed=system.seed, capacity=2)
+    check = sorted({int(np.argmin(counts)), int(np.argmax(counts)),
+                    len(ligs) // 2})
+    og = oracle.OGrid(g)
+    lockstep(ctx, og, [(ids[i], ligs[i]) for i in check], system.seed, 2,
+             system.n_leapfrog, "c5")
+    ctx.hmc_sweep(4, system.n_leapfrog, exchange_every=1, sample_every=2)
+    i = check[-1]
+    lig, lid = ligs[i], ids[i]
+    K = lig.n_states
+    u = ctx.energy_matrix(lid, None, n_samples=2 * K).cpu().numpy()
+    xs, _ = ctx.get_samples(lid)
+    X = xs.reshape(-1, lig.n_atoms, 3)
+    ol = oracle.OLigand(lig)
+    ref = oracle.ukn(og, ol, X)
+    _, mags = oracle.components(og, ol, X)
+    beta = 1.0 / (oracle.R_GAS * lig.T)
+    assert np.all(np.abs(u - ref) <=
+                  1e-5 * beta[:, None] * mags.sum(axis=1)[None, :] + 1e-12)
+    ctx.close()
