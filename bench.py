@@ -160,12 +160,13 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
             ctx.reset_samples(i)
         ctx.hmc_sweep(sweeps, L, exchange_every=1, exchange_scheme=0,
                       sample_every=every)
-        out = []
-        for q, (i, u, nk) in enumerate(zip(ids, ukn, Nk)):
+        for i, u in zip(ids, ukn):
             ctx.energy_matrix(i, None, n_samples=u.shape[1], out=u)
-            r = ctx.mbar(u, nk, tol=1e-10, max_iter=100, f_init=f_prev[q])
+        # every ligand's MBAR in one batched call
+        out = ctx.mbar_batch(ukn, Nk, tol=1e-10, max_iter=100,
+                             f_init=f_prev)
+        for q, r in enumerate(out):
             f_prev[q] = r[0] if np.all(np.isfinite(r[0])) else None
-            out.append(r)
         return out
 
     for _ in range(warmup):
@@ -203,6 +204,8 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
                         == 1 else None,
                         "sigma_kT": float(np.sqrt(max(var[-1], 0.0))),
                         "mbar_iterations": int(it),
+                        "mbar_iterations_max": int(max(r[2] for r in
+                                                       results)),
                         "bpmf_syn_kT_mean": float(bpmf.mean()),
                         "bpmf_syn_kT_range": [float(bpmf.min()),
                                               float(bpmf.max())],

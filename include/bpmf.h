@@ -63,6 +63,7 @@ enum {
 #define BPMF_MAX_CHANNELS 8    /* grid channels */
 #define BPMF_MAX_STATES 1024   /* thermodynamic states per ligand */
 #define BPMF_MAX_MBAR_STATES 128
+#define BPMF_MAX_MBAR_BATCH 65535  /* problems per bpmf_mbar_batch call */
 
 typedef struct bpmf_ctx bpmf_ctx;
 typedef void* (*bpmf_alloc_fn)(size_t bytes, void* user);
@@ -252,6 +253,27 @@ BPMF_API int bpmf_mbar(bpmf_ctx* ctx, const double* dev_ukn, int K, int64_t N,
               int64_t ld, const int64_t* N_k, double tol, int max_iter,
               double* f, double* var, int* n_iter,
                        int warm_start);
+
+/* MBAR for n_problems independent problems (e.g. every ligand of a batch)
+ * in one call: problem p has K[p] states (1..BPMF_MAX_MBAR_STATES) and
+ * N[p] samples in the device matrix dev_ukn[p] (K[p] x N[p], leading
+ * dimension ld[p]).  dev_ukn, K, N and ld are host arrays of n_problems
+ * entries; N_k, f and var hold the problems' K-vectors back to back (host,
+ * sum of K entries; var may be NULL), n_iter n_problems ints (may be NULL).
+ * Each problem gets exactly the iteration, stopping rule and result
+ * bpmf_mbar gives it alone (bpmf_mbar is this call with one problem); the
+ * batch advances every unfinished problem by one step per round, so the
+ * host waits for the device about three times per iteration of the slowest
+ * problem, not per problem.  Scratch grows with the sum over problems of
+ * N + 8 (K + K^2) x (N / (4096 / Kp)) doubles (Kp = K rounded up to 16, 32,
+ * 64 or 128).  Errors: BPMF_E_INVAL naming the offending problem (nothing is
+ * computed). */
+BPMF_API int bpmf_mbar_batch(bpmf_ctx* ctx, int n_problems,
+                             const double* const* dev_ukn, const int* K,
+                             const int64_t* N, const int64_t* ld,
+                             const int64_t* N_k, double tol, int max_iter,
+                             double* f, double* var, int* n_iter,
+                             int warm_start);
 
 /* ------------------------------------------------------------------------
  * Direct evaluation (the energy/force kernel the sampler runs, exposed)

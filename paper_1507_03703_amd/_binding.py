@@ -94,6 +94,8 @@ def library():
         "bpmf_energy_matrix": [vp, C.c_int, vp, C.c_int64, vp, C.c_int64],
         "bpmf_mbar": [vp, vp, C.c_int, C.c_int64, C.c_int64, i64p, C.c_double,
                       C.c_int, dp, dp, ip, C.c_int],
+        "bpmf_mbar_batch": [vp, C.c_int, C.POINTER(C.c_void_p), ip, i64p, i64p,
+                            i64p, C.c_double, C.c_int, dp, dp, ip, C.c_int],
         "bpmf_evaluate": [vp, C.c_int, vp, C.c_int64, vp, vp, vp],
         "bpmf_grid_eval": [vp, vp, vp, C.c_int64, dp, vp, vp],
         "bpmf_get_replicas": [vp, C.c_int, C.POINTER(C.c_float), ip, dp,
@@ -299,6 +301,48 @@ class Context:
                                    float(tol), int(max_iter), _pd(f), _pd(var),
                                    C.byref(it), int(f_init is not None)))
         return f, var, it.value
+
+    def mbar_batch(self, ukns, N_ks, tol=1e-10, max_iter=100, f_init=None):
+        """MBAR for several independent problems in one call (each solved
+        exactly as `mbar` solves it alone).  ukns: list of K_p x N_p float64
+        device matrices; N_ks: list of sample counts; f_init: None, or a
+        list with one initial guess (or None) per problem.  Returns a list
+        of (f, var, n_iter)."""
+        torch = self._torch
+        P = len(ukns)
+        assert len(N_ks) == P
+        Ks = np.zeros(P, np.int32)
+        Ns = np.zeros(P, np.int64)
+        lds = np.zeros(P, np.int64)
+        ptrs = (C.c_void_p * max(P, 1))()
+        for p, u in enumerate(ukns):
+            assert u.is_cuda and u.dtype == torch.float64 and u.stride(1) == 1
+            Ks[p], Ns[p] = u.shape
+            lds[p] = u.stride(0)
+            ptrs[p] = u.data_ptr()
+        Nk = np.concatenate([np.asarray(n, np.int64).reshape(-1)
+                             for n in N_ks]) if P else np.zeros(0, np.int64)
+        assert Nk.size == Ks.sum()
+        off = np.concatenate([[0], np.cumsum(Ks)]).astype(np.int64)
+        f = np.zeros(int(Ks.sum()))
+        warm = f_init is not None and any(x is not None for x in f_init)
+        if warm:
+            for p in range(P):
+                # a problem without a guess starts from zero
+                if f_init[p] is not None:
+                    f[off[p]:off[p + 1]] = np.asarray(
+                        f_init[p], np.float64).reshape(Ks[p])
+        var = np.zeros_like(f)
+        its = np.zeros(max(P, 1), np.int32)
+        _check(self._lib.bpmf_mbar_batch(
+            self._h, P, ptrs, Ks.ctypes.data_as(C.POINTER(C.c_int)),
+            Ns.ctypes.data_as(C.POINTER(C.c_int64)),
+            lds.ctypes.data_as(C.POINTER(C.c_int64)),
+            np.ascontiguousarray(Nk).ctypes.data_as(C.POINTER(C.c_int64)),
+            float(tol), int(max_iter), _pd(f), _pd(var),
+            its.ctypes.data_as(C.POINTER(C.c_int)), int(warm)))
+        return [(f[off[p]:off[p + 1]].copy(), var[off[p]:off[p + 1]].copy(),
+                 int(its[p])) for p in range(P)]
 
     # -- direct evaluation ----------------------------------------------------
     def evaluate(self, ligand_id, x, w, forces=True):

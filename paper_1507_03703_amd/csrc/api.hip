@@ -960,156 +960,332 @@ extern "C" int bpmf_energy_matrix(bpmf_ctx* c, int ligand_id,
   return BPMF_OK;
 }
 
+namespace {
+// host side of one problem of an MBAR batch
+struct MbarSolve {
+  enum Phase { kNewtonStep, kSearch, kFixedPoint, kDone };
+  Phase phase = kNewtonStep;
+  int it = 1;         // current iteration (1-based)
+  int ls = 0;         // line-search trials made in this iteration
+  bool accept = false;  // ftry becomes f at the start of the next round
+  double trust = INFINITY, Fcur = 0.0, t = 1.0, maxstep = 0.0, gs = 0.0;
+  int n_iter = 0;
+};
+}  // namespace
+
+// Solves every problem of the batch with the same sequence of steps a lone
+// solve takes, advancing all unfinished problems by one step per round (one
+// host synchronisation per round for the whole batch).  Per problem and
+// iteration: a Newton step with backtracking on the objective when the
+// gauge-fixed Hessian is numerically positive definite, otherwise one
+// fixed-point step (far from the solution whole states' weights can
+// underflow, leaving the Hessian singular).  While accepted moves are large
+// (>= 1 kT) the first trial of a Newton step moves no component by more than
+// twice the last accepted move (far from the solution full Newton steps
+// overshoot and would be halved many times).
+extern "C" int bpmf_mbar_batch(bpmf_ctx* c, int n_problems,
+                               const double* const* dev_ukn, const int* Ks,
+                               const int64_t* Ns, const int64_t* lds,
+                               const int64_t* N_k, double tol, int max_iter,
+                               double* f, double* var, int* n_iter,
+                               int warm_start) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (n_problems < 0 || n_problems > BPMF_MAX_MBAR_BATCH)
+    return fail(BPMF_E_INVAL, "MBAR batch of %d problems outside 0..%d",
+                n_problems, BPMF_MAX_MBAR_BATCH);
+  if (n_problems == 0) return BPMF_OK;
+  if (!dev_ukn || !Ks || !Ns || !lds || !N_k || !f)
+    return fail(BPMF_E_INVAL, "null MBAR argument");
+  if (!(tol > 0) || max_iter < 1)
+    return fail(BPMF_E_INVAL, "tol must be > 0 and max_iter >= 1");
+  const int P = n_problems;
+  std::vector<int64_t> koff(P + 1, 0);
+  for (int p = 0; p < P; ++p) {
+    const int K = Ks[p];
+    const int64_t N = Ns[p];
+    if (!dev_ukn[p]) return fail(BPMF_E_INVAL, "null u_kn of problem %d", p);
+    if (K < 1 || K > BPMF_MAX_MBAR_STATES)
+      return fail(BPMF_E_INVAL, "MBAR K %d of problem %d outside 1..%d", K, p,
+                  BPMF_MAX_MBAR_STATES);
+    if (N < 1 || lds[p] < N)
+      return fail(BPMF_E_INVAL, "bad N or ld of problem %d", p);
+    int64_t tot = 0;
+    for (int k = 0; k < K; ++k) {
+      if (N_k[koff[p] + k] <= 0)
+        return fail(BPMF_E_INVAL, "N_k[%d] of problem %d must be > 0", k, p);
+      tot += N_k[koff[p] + k];
+    }
+    if (tot != N)
+      return fail(BPMF_E_INVAL, "problem %d: sum N_k = %lld != N = %lld", p,
+                  (long long)tot, (long long)N);
+    if (warm_start)
+      for (int k = 0; k < K; ++k)
+        if (!std::isfinite(f[koff[p] + k]))
+          return fail(BPMF_E_INVAL, "non-finite initial f[%d] of problem %d",
+                      k, p);
+    koff[p + 1] = koff[p] + K;
+  }
+  // problems with one state are solved by definition
+  std::vector<int> act;
+  for (int p = 0; p < P; ++p) {
+    if (Ks[p] == 1) {
+      f[koff[p]] = 0.0;
+      if (var) var[koff[p]] = 0.0;
+      if (n_iter) n_iter[p] = 0;
+    } else {
+      act.push_back(p);
+    }
+  }
+  if (act.empty()) return BPMF_OK;
+  const int64_t sumK = koff[P];
+  int max_K = 0, max_nb = 0, max_acc[9] = {0};
+  size_t n_logD = 0, n_obj = 0, n_part = 0, n_red = 0, n_mat = 0;
+  for (int p : act) {
+    const int K = Ks[p];
+    const int ts = mbar_acc_ts(K);
+    max_K = std::max(max_K, K);
+    max_nb = std::max(max_nb, mbar_logD_blocks(Ns[p]));
+    max_acc[ts] = std::max(max_acc[ts], mbar_acc_blocks(K, Ns[p]));
+    n_logD += Ns[p];
+    n_obj += mbar_logD_blocks(Ns[p]);
+    n_part += (size_t)mbar_acc_blocks(K, Ns[p]) * (K + (size_t)K * K);
+    n_red += K + (size_t)K * K;
+    n_mat += (size_t)(K - 1) * (2 * K - 1);
+  }
+  Arena A;
+  const size_t o_tab = A.add(P * sizeof(MbarProb)),
+               o_vec = A.add((size_t)6 * sumK * 8),
+               o_sc = A.add((size_t)P * 8 * 8), o_logD = A.add(n_logD * 8),
+               o_obj = A.add(n_obj * 8), o_part = A.add(n_part * 8),
+               o_red = A.add(n_red * 8), o_mat = A.add(n_mat * 8),
+               o_list = A.add((size_t)P * 4 * sizeof(int)),
+               o_t = A.add((size_t)P * 8);
+  rc = ensure_scratch(c, &c->mbar_mem, &c->mbar_bytes, A.total);
+  if (rc) return rc;
+  char* base = (char*)c->mbar_mem;
+  double* vec = (double*)(base + o_vec);
+  double *d_f = vec, *d_ftry = vec + sumK, *d_logN = vec + 2 * sumK,
+         *d_Nk = vec + 3 * sumK, *d_step = vec + 4 * sumK,
+         *d_var = vec + 5 * sumK;
+  double* d_sc = (double*)(base + o_sc);
+  const MbarProb* d_tab = (const MbarProb*)(base + o_tab);
+  int* d_list = (int*)(base + o_list);
+  double* d_t = (double*)(base + o_t);
+  std::vector<MbarProb> tab(P);
+  std::vector<double> h_logN(sumK, 0.0), h_Nk(sumK, 1.0), h_f(sumK, 0.0);
+  {
+    size_t qd = 0, qo = 0, qp = 0, qr = 0, qm = 0;
+    for (int p : act) {
+      const int K = Ks[p];
+      MbarProb& q = tab[p];
+      q.ukn = dev_ukn[p];
+      q.N = Ns[p];
+      q.ld = lds[p];
+      q.K = K;
+      q.nb = mbar_logD_blocks(Ns[p]);
+      q.nb_acc = mbar_acc_blocks(K, Ns[p]);
+      q.ts = mbar_acc_ts(K);
+      q.f = d_f + koff[p];
+      q.ftry = d_ftry + koff[p];
+      q.logN = d_logN + koff[p];
+      q.Nk = d_Nk + koff[p];
+      q.step = d_step + koff[p];
+      q.var = d_var + koff[p];
+      q.scalars = d_sc + (size_t)p * 8;
+      q.logD = (double*)(base + o_logD) + qd;
+      q.obj_part = (double*)(base + o_obj) + qo;
+      q.partial = (double*)(base + o_part) + qp;
+      q.red = (double*)(base + o_red) + qr;
+      q.mat = (double*)(base + o_mat) + qm;
+      qd += Ns[p];
+      qo += q.nb;
+      qp += (size_t)q.nb_acc * (K + (size_t)K * K);
+      qr += K + (size_t)K * K;
+      qm += (size_t)(K - 1) * (2 * K - 1);
+      for (int k = 0; k < K; ++k) {
+        h_Nk[koff[p] + k] = (double)N_k[koff[p] + k];
+        h_logN[koff[p] + k] = log(h_Nk[koff[p] + k]);
+        if (warm_start) h_f[koff[p] + k] = f[koff[p] + k] - f[koff[p]];
+      }
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(base + o_tab, tab.data(), P * sizeof(MbarProb),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(d_f, h_f.data(), sumK * 8, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(d_logN, h_logN.data(), sumK * 8,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(d_Nk, h_Nk.data(), sumK * 8, hipMemcpyHostToDevice,
+                         c->stream));
+  std::vector<MbarSolve> S(P);
+  std::vector<double> sc((size_t)P * 8);
+  // lists of one round, uploaded together: [accept | newton (by tile) |
+  // line search | fixed point]
+  std::vector<int> lists;
+  std::vector<double> tv(P, 0.0);
+  auto upload = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(d_list, lists.data(), lists.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(d_t, tv.data(), P * 8, hipMemcpyHostToDevice,
+                           c->stream));
+    return BPMF_OK;
+  };
+  auto fetch = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(sc.data(), d_sc, (size_t)P * 64,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+  };
+  // objective (and logD) at every starting point
+  lists = act;
+  if ((rc = upload())) return rc;
+  HIP_TRY(mbar_objective(d_tab, d_list, (int)act.size(), max_nb, 0,
+                         c->stream));
+  if ((rc = fetch())) return rc;
+  for (int p : act) S[p].Fcur = sc[(size_t)p * 8];
+  auto finish = [&](MbarSolve& s, double change) {
+    if (!(change >= tol)) {
+      s.phase = MbarSolve::kDone;
+      s.n_iter = s.it;
+    } else if (s.it >= max_iter) {
+      s.phase = MbarSolve::kDone;
+      s.n_iter = max_iter;
+    } else {
+      ++s.it;
+      s.phase = MbarSolve::kNewtonStep;
+    }
+  };
+  static const int kTiles[4] = {1, 2, 4, 8};
+  for (;;) {
+    lists.clear();
+    std::vector<int> newt, search, fixed;
+    for (int p : act)
+      if (S[p].accept) lists.push_back(p);
+    const int n_acc = (int)lists.size();
+    int n_tile[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 4; ++i)
+      for (int p : act)
+        if (S[p].phase == MbarSolve::kNewtonStep && tab[p].ts == kTiles[i]) {
+          lists.push_back(p);
+          newt.push_back(p);
+          ++n_tile[i];
+        }
+    for (int p : act)
+      if (S[p].phase == MbarSolve::kSearch) {
+        lists.push_back(p);
+        search.push_back(p);
+        tv[p] = S[p].t;
+      }
+    for (int p : act)
+      if (S[p].phase == MbarSolve::kFixedPoint) {
+        lists.push_back(p);
+        fixed.push_back(p);
+      }
+    if (newt.empty() && search.empty() && fixed.empty()) break;
+    if ((rc = upload())) return rc;
+    const int* L = d_list;
+    HIP_TRY(mbar_accept(d_tab, L, n_acc, c->stream));
+    L += n_acc;
+    for (int p : act) S[p].accept = false;
+    const int* Ln = L;
+    for (int i = 0; i < 4; ++i) {
+      HIP_TRY(mbar_accumulate(d_tab, L, n_tile[i], kTiles[i],
+                              max_acc[kTiles[i]], c->stream));
+      L += n_tile[i];
+    }
+    HIP_TRY(mbar_newton(d_tab, Ln, (int)newt.size(), max_K, 0, c->stream));
+    HIP_TRY(mbar_axpy(d_tab, L, (int)search.size(), d_t, c->stream));
+    HIP_TRY(mbar_objective(d_tab, L, (int)search.size(), max_nb, 1,
+                           c->stream));
+    L += search.size();
+    HIP_TRY(mbar_fixed_point(d_tab, L, (int)fixed.size(), max_K, c->stream));
+    HIP_TRY(mbar_objective(d_tab, L, (int)fixed.size(), max_nb, 0,
+                           c->stream));
+    if ((rc = fetch())) return rc;
+    for (int p : newt) {
+      MbarSolve& s = S[p];
+      const double* q = &sc[(size_t)p * 8];
+      if (q[3] == 0.0) {
+        s.maxstep = q[1];
+        s.gs = q[2];
+        s.t = s.trust >= 1.0 ? std::min(1.0, 2.0 * s.trust / s.maxstep) : 1.0;
+        s.ls = 0;
+        s.phase = MbarSolve::kSearch;
+      } else {
+        s.phase = MbarSolve::kFixedPoint;
+      }
+    }
+    for (int p : search) {
+      MbarSolve& s = S[p];
+      const double Ftry = sc[(size_t)p * 8];
+      const bool ok = Ftry <= s.Fcur + 1e-4 * s.t * s.gs + 1e-13 * fabs(s.Fcur)
+                      || s.t * s.maxstep < tol;
+      if (!ok) {
+        s.t *= 0.5;
+        // after 60 trials the last one is taken anyway
+        if (++s.ls < 60) continue;
+      }
+      s.accept = true;
+      s.Fcur = Ftry;
+      const double change = s.t * s.maxstep;
+      s.trust = change;
+      finish(s, change);
+    }
+    for (int p : fixed) {
+      MbarSolve& s = S[p];
+      s.Fcur = sc[(size_t)p * 8];
+      finish(s, sc[(size_t)p * 8 + 4]);
+    }
+  }
+  // variances at the solutions (logD recomputed at f)
+  lists.clear();
+  for (int p : act)
+    if (S[p].accept) lists.push_back(p);
+  const int n_acc = (int)lists.size();
+  int n_tile[4] = {0, 0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+    for (int p : act)
+      if (tab[p].ts == kTiles[i]) {
+        lists.push_back(p);
+        ++n_tile[i];
+      }
+  if ((rc = upload())) return rc;
+  HIP_TRY(mbar_accept(d_tab, d_list, n_acc, c->stream));
+  const int* Ln = d_list + n_acc;
+  HIP_TRY(mbar_objective(d_tab, Ln, (int)act.size(), max_nb, 0, c->stream));
+  const int* L = Ln;
+  for (int i = 0; i < 4; ++i) {
+    HIP_TRY(mbar_accumulate(d_tab, L, n_tile[i], kTiles[i],
+                            max_acc[kTiles[i]], c->stream));
+    L += n_tile[i];
+  }
+  HIP_TRY(mbar_newton(d_tab, Ln, (int)act.size(), max_K, 1, c->stream));
+  std::vector<double> hf(sumK), hv(sumK);
+  HIP_TRY(hipMemcpyAsync(hf.data(), d_f, sumK * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(hv.data(), d_var, sumK * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  if ((rc = fetch())) return rc;
+  for (int p : act) {
+    const int K = Ks[p];
+    memcpy(f + koff[p], hf.data() + koff[p], K * 8);
+    // a Hessian that is not positive definite at the solution means states
+    // without overlap: their differences are not determined
+    if (sc[(size_t)p * 8 + 3] != 0.0)
+      for (int k = 1; k < K; ++k) hv[koff[p] + k] = INFINITY;
+    if (var) memcpy(var + koff[p], hv.data() + koff[p], K * 8);
+    if (n_iter) n_iter[p] = S[p].n_iter;
+  }
+  return BPMF_OK;
+}
+
 extern "C" int bpmf_mbar(bpmf_ctx* c, const double* dev_ukn, int K, int64_t N,
                          int64_t ld, const int64_t* N_k, double tol,
                          int max_iter, double* f, double* var, int* n_iter,
                          int warm_start) {
-  int rc = check_ctx(c);
-  if (rc) return rc;
-  if (!dev_ukn || !N_k || !f) return fail(BPMF_E_INVAL, "null MBAR argument");
-  if (K < 1 || K > BPMF_MAX_MBAR_STATES)
-    return fail(BPMF_E_INVAL, "MBAR K %d outside 1..%d", K,
-                BPMF_MAX_MBAR_STATES);
-  if (N < 1 || ld < N) return fail(BPMF_E_INVAL, "bad N or ld");
-  if (!(tol > 0) || max_iter < 1)
-    return fail(BPMF_E_INVAL, "tol must be > 0 and max_iter >= 1");
-  int64_t tot = 0;
-  for (int k = 0; k < K; ++k) {
-    if (N_k[k] <= 0) return fail(BPMF_E_INVAL, "N_k[%d] must be > 0", k);
-    tot += N_k[k];
-  }
-  if (tot != N) return fail(BPMF_E_INVAL, "sum N_k = %lld != N = %lld",
-                            (long long)tot, (long long)N);
-  std::vector<double> f0(K, 0.0);
-  if (warm_start) {
-    for (int k = 0; k < K; ++k) {
-      if (!std::isfinite(f[k]))
-        return fail(BPMF_E_INVAL, "non-finite initial f[%d]", k);
-      f0[k] = f[k] - f[0];
-    }
-  }
-  if (K == 1) {
-    f[0] = 0.0;
-    if (var) var[0] = 0.0;
-    if (n_iter) *n_iter = 0;
-    return BPMF_OK;
-  }
-  const int nb = (int)std::min<int64_t>(256, std::max<int64_t>(1, (N + 255) / 256));
-  Arena A;
-  const size_t o_f = A.add(K * 8), o_ft = A.add(K * 8), o_logN = A.add(K * 8),
-               o_Nk = A.add(K * 8), o_logD = A.add((size_t)N * 8),
-               o_part = A.add((size_t)std::max(nb, mbar_acc_blocks(K, N)) *
-                              (K + (size_t)K * K) * 8),
-               o_red = A.add((K + (size_t)K * K) * 8),
-               o_mat = A.add((size_t)(K - 1) * (2 * K) * 8),
-               o_step = A.add(K * 8), o_sc = A.add(8 * 8),
-               o_obj = A.add(nb * 8), o_var = A.add(K * 8);
-  rc = ensure_scratch(c, &c->mbar_mem, &c->mbar_bytes, A.total);
-  if (rc) return rc;
-  char* base = (char*)c->mbar_mem;
-  MbarScratch s;
-  double* fcur = (double*)(base + o_f);
-  double* ftry = (double*)(base + o_ft);
-  double* Nk_dev = (double*)(base + o_Nk);
-  s.f = fcur;
-  s.logN = (double*)(base + o_logN);
-  s.logD = (double*)(base + o_logD);
-  s.partial = (double*)(base + o_part);
-  s.red = (double*)(base + o_red);
-  s.mat = (double*)(base + o_mat);
-  s.step = (double*)(base + o_step);
-  s.scalars = (double*)(base + o_sc);
-  s.obj_part = (double*)(base + o_obj);
-  s.n_blocks = nb;
-  double* var_dev = (double*)(base + o_var);
-  std::vector<double> logN(K), Nkd(K);
-  for (int k = 0; k < K; ++k) {
-    Nkd[k] = (double)N_k[k];
-    logN[k] = log(Nkd[k]);
-  }
-  HIP_TRY(hipMemcpyAsync(s.logN, logN.data(), K * 8, hipMemcpyHostToDevice,
-                         c->stream));
-  HIP_TRY(hipMemcpyAsync(Nk_dev, Nkd.data(), K * 8, hipMemcpyHostToDevice,
-                         c->stream));
-  HIP_TRY(hipMemcpyAsync(fcur, f0.data(), K * 8, hipMemcpyHostToDevice,
-                         c->stream));
-  double sc[4];
-  auto objective = [&](const double* fv, double* out) -> int {
-    HIP_TRY(mbar_logD(dev_ukn, K, N, ld, fv, s, c->stream));
-    HIP_TRY(mbar_objective(K, nullptr, s, fv, Nk_dev, c->stream));
-    HIP_TRY(hipMemcpyAsync(out, s.scalars, 8, hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    return BPMF_OK;
-  };
-  // Each iteration: Newton step with backtracking on the objective when the
-  // gauge-fixed Hessian is numerically positive definite, otherwise one
-  // fixed-point step (far from the solution whole states' weights can
-  // underflow, leaving the Hessian singular).
-  double Fcur = 0;
-  if ((rc = objective(fcur, &Fcur))) return rc;  // also logD at fcur
-  std::vector<double> fh(K), fn(K);
-  // trust length: while accepted moves are large (>= 1 kT), the first trial
-  // of a Newton step moves no component by more than twice the last
-  // accepted move (far from the solution full Newton steps overshoot and
-  // would be halved many times)
-  double trust = INFINITY;
-  int it = 0;
-  for (it = 1; it <= max_iter; ++it) {
-    HIP_TRY(mbar_accumulate(dev_ukn, K, N, ld, fcur, s, c->stream));
-    HIP_TRY(mbar_newton(K, Nk_dev, s, 0, nullptr, c->stream));
-    HIP_TRY(hipMemcpyAsync(sc, s.scalars, 4 * 8, hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    double change = 0.0;
-    if (sc[3] == 0.0) {
-      const double maxstep = sc[1], gs = sc[2];
-      double t = trust >= 1.0 ? std::min(1.0, 2.0 * trust / maxstep) : 1.0;
-      double Ftry = 0.0;
-      for (int ls = 0; ls < 60; ++ls) {
-        HIP_TRY(mbar_axpy(K, fcur, s.step, t, ftry, c->stream));
-        if ((rc = objective(ftry, &Ftry))) return rc;
-        if (Ftry <= Fcur + 1e-4 * t * gs + 1e-13 * fabs(Fcur) ||
-            t * maxstep < tol)
-          break;
-        t *= 0.5;
-      }
-      std::swap(fcur, ftry);
-      s.f = fcur;
-      Fcur = Ftry;
-      change = t * maxstep;
-      trust = change;
-    } else {
-      // fixed-point step from fcur (logD is current for fcur)
-      HIP_TRY(hipMemcpyAsync(fh.data(), fcur, K * 8, hipMemcpyDeviceToHost,
-                             c->stream));
-      HIP_TRY(mbar_self_consistent(dev_ukn, K, N, ld, s, c->stream));
-      HIP_TRY(hipMemcpyAsync(fn.data(), fcur, K * 8, hipMemcpyDeviceToHost,
-                             c->stream));
-      if ((rc = objective(fcur, &Fcur))) return rc;
-      for (int k = 0; k < K; ++k) change = std::max(change, fabs(fn[k] - fh[k]));
-    }
-    if (!(change >= tol)) break;
-  }
-  if (it > max_iter) it = max_iter;
-  // variance at the solution (logD is current for fcur)
-  HIP_TRY(mbar_logD(dev_ukn, K, N, ld, fcur, s, c->stream));
-  HIP_TRY(mbar_accumulate(dev_ukn, K, N, ld, fcur, s, c->stream));
-  HIP_TRY(mbar_newton(K, Nk_dev, s, 1, var_dev, c->stream));
-  HIP_TRY(hipMemcpyAsync(f, fcur, K * 8, hipMemcpyDeviceToHost, c->stream));
-  std::vector<double> vh(K);
-  HIP_TRY(hipMemcpyAsync(vh.data(), var_dev, K * 8, hipMemcpyDeviceToHost,
-                         c->stream));
-  HIP_TRY(hipMemcpyAsync(sc, s.scalars, 4 * 8, hipMemcpyDeviceToHost,
-                         c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  // a Hessian that is not positive definite at the solution means states
-  // without overlap: their differences are not determined
-  if (sc[3] != 0.0)
-    for (int k = 1; k < K; ++k) vh[k] = INFINITY;
-  if (var) memcpy(var, vh.data(), K * 8);
-  if (n_iter) *n_iter = it;
-  return BPMF_OK;
+  return bpmf_mbar_batch(c, 1, &dev_ukn, &K, &N, &ld, N_k, tol, max_iter, f,
+                         var, n_iter, warm_start);
 }
 
 // ============================================================================

@@ -136,33 +136,49 @@ hipError_t launch_recompute_comps(const GridDev& g, const LigDev* d_lig,
                                   int waves, int K, int lds_bytes,
                                   hipStream_t st);
 
-// MBAR kernels (mbar.hip)
-struct MbarScratch {
-  double* f;         // K
-  double* logN;      // K
-  double* logD;      // N
-  double* partial;   // mbar_acc_blocks(K, N) * (K + K*K)
-  double* red;       // K + K*K (reduced sums)
-  double* mat;       // (K-1) x (2K-1) augmented system
-  double* step;      // K
-  double* scalars;   // [0] objective, [1] max|step|, [2] g.step, [3] status
-  double* obj_part;  // n_blocks
-  int n_blocks;
+// MBAR kernels (mbar.hip).  One entry per problem of a batch, in device
+// memory; kernels take the table and a device list of problem indices and
+// put the list position in blockIdx.y.
+struct MbarProb {
+  const double* ukn;  // K x N, leading dimension ld
+  int64_t N, ld;
+  int K;
+  int nb;             // blocks of the logD / objective pass
+  int nb_acc;         // blocks of the W W^T accumulation
+  int ts;             // register tile of the accumulation (mbar_acc_ts)
+  double* f;          // K current point (f_0 = 0)
+  double* ftry;       // K line-search trial
+  double* logN;       // K
+  double* Nk;         // K
+  double* logD;       // N
+  double* partial;    // max(nb, nb_acc) x (K + K*K)
+  double* red;        // K + K*K reduced sums
+  double* mat;        // (K-1) x (2K-1) augmented system (large K only)
+  double* step;       // K Newton step / fixed-point values
+  double* scalars;    // [0] objective [1] max|step| [2] g.step [3] status
+                      // [4] fixed-point change
+  double* var;        // K variances
+  double* obj_part;   // nb
 };
-hipError_t mbar_logD(const double* ukn, int K, int64_t N, int64_t ld,
-                     const double* f, const MbarScratch& s, hipStream_t st);
-hipError_t mbar_objective(int K, const int64_t* dummy, const MbarScratch& s,
-                          const double* f, double* N_k_dev, hipStream_t st);
-hipError_t mbar_self_consistent(const double* ukn, int K, int64_t N,
-                                int64_t ld, const MbarScratch& s,
-                                hipStream_t st);
+int mbar_logD_blocks(int64_t N);
+int mbar_acc_ts(int K);
 int mbar_acc_blocks(int K, int64_t N);
-hipError_t mbar_accumulate(const double* ukn, int K, int64_t N, int64_t ld,
-                           const double* f, const MbarScratch& s,
-                           hipStream_t st);
-hipError_t mbar_newton(int K, const double* N_k_dev, const MbarScratch& s,
-                       int want_inverse, double* var_out, hipStream_t st);
-hipError_t mbar_axpy(int K, const double* f, const double* step, double t,
-                     double* out, hipStream_t st);
+size_t mbar_newton_lds(int K, int want_inverse);
+// logD and scalars[0] at f (use_try = 0) or ftry
+hipError_t mbar_objective(const MbarProb* P, const int* list, int n,
+                          int max_nb, int use_try, hipStream_t st);
+// fixed-point update of f in place (logD current for f), change in [4]
+hipError_t mbar_fixed_point(const MbarProb* P, const int* list, int n,
+                            int max_K, hipStream_t st);
+// partial sums of W W^T at f; every listed problem has register tile ts
+hipError_t mbar_accumulate(const MbarProb* P, const int* list, int n, int ts,
+                           int max_blocks, hipStream_t st);
+// reduce the partial sums and solve for the Newton step (and variances)
+hipError_t mbar_newton(const MbarProb* P, const int* list, int n, int max_K,
+                       int want_inverse, hipStream_t st);
+hipError_t mbar_axpy(const MbarProb* P, const int* list, int n,
+                     const double* tvec, hipStream_t st);
+hipError_t mbar_accept(const MbarProb* P, const int* list, int n,
+                       hipStream_t st);
 
 }  // namespace bpmf

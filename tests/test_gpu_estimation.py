@@ -197,3 +197,67 @@ def test_exact_toy_pipeline_gpu():
     st = ctx.get_stats(lid)
     assert np.all(st["ex_acc"] / st["ex_try"] > 0.05)
     ctx.close()
+
+
+def _harmonic_problem(rng, K, n_per, spread):
+    """K harmonic states with force constants spread over `spread` decades;
+    exact f_k - f_0 = 1.5 ln(k_k / k_0)."""
+    ks = np.logspace(0, spread, K)
+    Nk = rng.integers(n_per // 2, n_per + 1, K)
+    xs = np.concatenate([rng.normal(0, 1 / math.sqrt(k), (n, 3))
+                         for k, n in zip(ks, Nk)])
+    return 0.5 * ks[:, None] * (xs ** 2).sum(1)[None, :], Nk
+
+
+def test_mbar_batch_equals_lone_solves():
+    """A batch mixing every register-tile class of the accumulation (K = 12,
+    24, 40, 70), a one-state problem, a padded leading dimension and a
+    problem far from overlap (fixed-point steps first) gives each problem
+    bit for bit what a lone solve gives, with or without warm starts, and
+    the oracle's MBAR within the float64 tolerance."""
+    print_case("mbar batch")
+    rng = np.random.default_rng(11)
+    probs = [_harmonic_problem(rng, 12, 300, 1.0),
+             _harmonic_problem(rng, 24, 200, 1.5),
+             _harmonic_problem(rng, 1, 50, 0.0),
+             _harmonic_problem(rng, 40, 120, 2.0),
+             _harmonic_problem(rng, 70, 60, 2.5),
+             _harmonic_problem(rng, 6, 80, 4.0)]
+    us = []
+    for p, (u, _) in enumerate(probs):
+        if p == 1:      # leading dimension larger than N
+            buf = torch.zeros((u.shape[0], u.shape[1] + 37),
+                              dtype=torch.float64, device="cuda:0")
+            buf[:, :u.shape[1]] = dev(u, torch.float64)
+            us.append(buf[:, :u.shape[1]])
+        else:
+            us.append(dev(u, torch.float64))
+    Nks = [nk for _, nk in probs]
+    ctx = __import__("paper_1507_03703_amd").Context(seed=0)
+    batch = ctx.mbar_batch(us, Nks, tol=1e-11, max_iter=200)
+    lone = [ctx.mbar(u, nk, tol=1e-11, max_iter=200) for u, nk in
+            zip(us, Nks)]
+    for p, ((fb, vb, ib), (fl, vl, il)) in enumerate(zip(batch, lone)):
+        assert np.array_equal(fb, fl) and np.array_equal(vb, vl), p
+        assert ib == il, p
+    assert batch[2][2] == 0 and batch[2][0].tolist() == [0.0]
+    for p, (u, nk) in enumerate(probs):
+        if u.shape[0] == 1:
+            continue
+        f64, _, _ = estimators.mbar(u, nk, tol=1e-12)
+        assert np.max(np.abs(batch[p][0] - f64)) < 1e-7 * max(
+            1.0, np.abs(f64).max()), p
+    # warm starts for some problems only
+    init = [None if p % 2 else batch[p][0] + 0.3 for p in range(len(us))]
+    wb = ctx.mbar_batch(us, Nks, tol=1e-11, max_iter=200, f_init=init)
+    for p, (u, nk) in enumerate(zip(us, Nks)):
+        wl = ctx.mbar(u, nk, tol=1e-11, max_iter=200, f_init=init[p])
+        assert np.array_equal(wb[p][0], wl[0]) and wb[p][2] == wl[2], p
+        assert np.array_equal(wb[p][1], wl[1]), p
+    # argument errors name the problem and compute nothing
+    bad = [np.array(n) for n in Nks]
+    bad[3] = bad[3] + 1
+    with pytest.raises(RuntimeError, match="problem 3"):
+        ctx.mbar_batch(us, bad)
+    assert ctx.mbar_batch([], []) == []
+    ctx.close()
