@@ -39,28 +39,39 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 GRID_BYTES_PER_EVAL = 96  # 8 corners x 3 channels x 4 B
 
-# HBM bytes moved by one sweep-kernel launch of the production workload,
-# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled
-# by what the same counters read for a 1 GiB device copy (x2.0 and x1.0);
-# valid while the sweep kernel's sources hash to `sources`.
-SWEEP_TRAFFIC = {"workload": "c2_plain_production",
-                 "sources": "c565caf47659e6f2",
-                 "fetch_kib": 940.070, "write_kib": 52.710,
-                 "fetch_scale": 2.0, "write_scale": 1.0}
+# HBM traffic of one sweep launch measured with rocprofv3 counters
+# (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, scaled by what they read for a
+# 1 GiB device copy), per workload and wavefronts per replica; valid only
+# while the sweep-kernel sources hash to `sources`
+SWEEP_TRAFFIC = {
+    "c2_plain_production": {"sources": "ecbe91860c777ed2", "waves": None,
+                            "fetch_kib": 988.066, "write_kib": 201.280,
+                            "fetch_scale": 2.0, "write_scale": 1.0},
+    "c3_batched_uneven": {"sources": "ecbe91860c777ed2", "waves": 2,
+                          "fetch_kib": 24054.703, "write_kib": 24091.441,
+                          "fetch_scale": 2.0, "write_scale": 1.0},
+}
 SWEEP_SOURCES = ("device.h", "kernels.hip", "internal.h")
 
 
-def sweep_traffic(workload):
-    """Measured HBM bytes per sweep launch, or None when the workload or the
-    kernel sources differ from those the counters were taken on."""
+def sweep_sources_hash():
     import hashlib
     h = hashlib.sha256()
     for f in SWEEP_SOURCES:
         with open(os.path.join(ROOT, "paper_1507_03703_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
-    t = SWEEP_TRAFFIC
-    if workload != t["workload"] or h.hexdigest()[:16] != t["sources"]:
+    return h.hexdigest()[:16]
+
+
+def sweep_traffic(workload, waves=None):
+    """Measured HBM bytes per sweep launch, or None when the workload, its
+    launch shape or the kernel sources differ from those the counters were
+    taken on."""
+    t = SWEEP_TRAFFIC.get(workload)
+    if t is None or sweep_sources_hash() != t["sources"]:
+        return None
+    if t["waves"] is not None and list(waves or []) != [t["waves"]]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] +
                      t["write_kib"] * t["write_scale"])
@@ -78,6 +89,12 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-batched", dest="batched", action="store_false",
                    help="skip the batched 256-ligand leg")
+    p.add_argument("--no-bulk", dest="bulk", action="store_false",
+                   help="skip the bulk interpolation leg")
+    p.add_argument("--bulk-configs", default="3,5",
+                   help="batched workloads whose sample sets the bulk leg "
+                        "uses")
+    p.add_argument("--bulk-only", action="store_true")
     p.add_argument("--no-learned", dest="learned", action="store_false",
                    help="skip the learned-proposal leg")
     p.add_argument("--learned-only", action="store_true",
@@ -86,6 +103,9 @@ def parse():
     p.add_argument("--long-sweeps", type=int, default=200000)
     p.add_argument("--prod-sweeps", type=int, default=50000)
     p.add_argument("--train-steps", type=int, default=4000)
+    p.add_argument("--waves", type=int, default=None,
+                   help="wavefronts per replica for every ligand instead of "
+                        "the autotuner's choice (0 = per-ligand minimum)")
     p.add_argument("--grid-device", default="cuda:0",
                    help="torch device that sums the synthetic receptor grids "
                         "(input generation, outside the timed region)")
@@ -123,7 +143,7 @@ def cpu_baseline(system, target_s):
 
 
 def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
-                 tune=False):
+                 tune=False, waves=None):
     """Set up every ligand of `system`, run `warmup` + `steps` timed steps
     of the hot path and return the measurements."""
     import numpy as np
@@ -141,7 +161,10 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
                        dtype=torch.float64, device="cuda:0") for l in ligs]
     Nk = [np.full(l.n_states, records, np.int64) for l in ligs]
     tuned = None
-    if tune:
+    if waves is not None:
+        ctx.set_waves(waves)
+        tuned = {"chosen_waves": waves or "auto", "fixed": True}
+    elif tune:
         sig = (f"{system.name}|L{L}|" +
                ",".join(f"{l.n_atoms}x{l.n_states}" for l in ligs))
         cache = os.environ.get("BPMF_TUNE_CACHE", os.path.join(
@@ -160,9 +183,9 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
             ctx.reset_samples(i)
         ctx.hmc_sweep(sweeps, L, exchange_every=1, exchange_scheme=0,
                       sample_every=every)
-        for i, u in zip(ids, ukn):
-            ctx.energy_matrix(i, None, n_samples=u.shape[1], out=u)
-        # every ligand's MBAR in one batched call
+        # every ligand's u_kn, then every ligand's MBAR, in batched calls
+        ctx.energy_matrix_batch(ids, n_samples=[u.shape[1] for u in ukn],
+                                outs=ukn)
         out = ctx.mbar_batch(ukn, Nk, tol=1e-10, max_iter=100,
                              f_init=f_prev)
         for q, r in enumerate(out):
@@ -213,6 +236,95 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
                         "exchange_acceptance": float(exa)})
 
 
+def bulk_leg(pkg, torch, system, reps=3, harness_min=10 ** 8):
+    """Throughput of the bulk interpolation kernels on the sample set of a
+    batched workload: every ligand's ladder is sampled for the workload's
+    sweeps (a record per state every `sample_every`), then (1) u_kn is
+    recomputed from every recorded configuration (the component kernel,
+    energy only) and (2) the interpolation harness (bpmf_grid_eval: energy
+    and force of all channels) runs at every atom position of those
+    configurations, tiled to at least `harness_min` points.  Both are timed
+    with HIP events around every launch on the context's stream."""
+    import numpy as np
+    g, ligs = system.grid, system.ligands
+    L = system.n_leapfrog
+    every = system.sample_every
+    records = system.n_sweeps // every
+    ctx = pkg.Context(seed=system.seed, device=0)
+    ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+    ids = [ctx.ligand_setup(l, sample_capacity=records) for l in ligs]
+    t0 = time.perf_counter()
+    ctx.hmc_sweep(system.n_sweeps, L, exchange_every=1, sample_every=every)
+    torch.cuda.synchronize()
+    sample_s = time.perf_counter() - t0
+    ukn = [torch.empty((l.n_states, records * l.n_states),
+                       dtype=torch.float64, device="cuda:0") for l in ligs]
+
+    def all_ukn():
+        ctx.energy_matrix_batch(ids, n_samples=[u.shape[1] for u in ukn],
+                                outs=ukn)
+
+    all_ukn()
+    torch.cuda.synchronize()
+    ctx.set_timing(True, every=1)
+    for _ in range(reps):
+        all_ukn()
+    cmp_ms, cmp_n = ctx.get_timing(ctx.TIMER_COMPONENTS)
+    ctx.set_timing(False)
+    evals_ukn = sum(records * l.n_states * l.n_atoms for l in ligs)
+    ukn_s = cmp_ms * cmp_n * 1e-3 / reps
+    # harness points: every atom of every recorded configuration, with the
+    # atom's per-channel scale
+    pos, scl = [], []
+    for i, l in zip(ids, ligs):
+        xs, _ = ctx.get_samples(i)
+        pos.append(xs.reshape(-1, 3))
+        scl.append(np.tile(l.scale.astype(np.float32), (xs.shape[0] *
+                                                         xs.shape[1], 1)))
+    pos = torch.from_numpy(np.concatenate(pos)).to("cuda:0")
+    scl = torch.from_numpy(np.concatenate(scl)).to("cuda:0")
+    tile = -(-harness_min // pos.shape[0])
+    pos = pos.repeat(tile, 1).contiguous()
+    scl = scl.repeat(tile, 1).contiguous()
+    npts = pos.shape[0]
+    w = np.ones(g.nodes.shape[-1])
+    energy, force = ctx.grid_eval(pos, scl, w)
+    torch.cuda.synchronize()
+    ctx.set_timing(True, every=1)
+    for _ in range(reps):
+        ctx.grid_eval(pos, scl, w, energy=energy, force=force)
+    ge_ms, ge_n = ctx.get_timing(ctx.TIMER_GRID_EVAL)
+    ctx.set_timing(False)
+    finite = bool(torch.isfinite(energy).all() and torch.isfinite(force).all())
+    ctx.close()
+    io = 4 * (3 + 2 * g.nodes.shape[-1] + 3)   # pos, scale, energy, force
+
+    def line(evals, sec, io_bytes):
+        gbs = evals * GRID_BYTES_PER_EVAL / sec / 1e9
+        return {"value": evals / sec, "unit": "atom-evals/s",
+                "roofline": {"bound": "hbm", "achieved": gbs,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": gbs / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_eval":
+                                 GRID_BYTES_PER_EVAL,
+                             "streamed_bytes_per_eval": io_bytes}}
+    counts = [l.n_atoms for l in ligs]
+    return {
+        "workload": f"{system.name} sample set: {len(ligs)} ligands of "
+                    f"{min(counts)}-{max(counts)} atoms x "
+                    f"{ligs[0].n_states} states x {records} records, "
+                    f"{g.n[0]}^3 x {g.nodes.shape[-1]} float32 grids",
+        "sampling_s": sample_s,
+        "energy_matrix": dict(line(evals_ukn, ukn_s, 12),
+                              atom_evals=evals_ukn, kernel="k_energy_matrix",
+                              launches=cmp_n // reps,
+                              kernel_ms_total=ukn_s * 1e3),
+        "harness": dict(line(npts, ge_ms * 1e-3, io), points=npts,
+                        kernel="k_grid_eval", launch_ms=ge_ms,
+                        outputs_finite=finite),
+    }
+
+
 def describe(system, r):
     ligs = system.ligands
     g = system.grid
@@ -242,7 +354,8 @@ def describe(system, r):
 def roofline(r, workload):
     return {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
-            "traffic": sweep_traffic(workload), "kernel": "k_hmc_sweep",
+            "traffic": sweep_traffic(workload, r["waves"]),
+            "kernel": "k_hmc_sweep",
             "mean_launch_ms": r["hmc_ms"], "launches_timed": r["hmc_n"],
             "algorithmic_bytes_per_launch": r["evals_per_sweep"] *
             GRID_BYTES_PER_EVAL}
@@ -423,9 +536,19 @@ def main():
                                      prod_sweeps=args.prod_sweeps)))
         return
 
+    def bulk():
+        return [bulk_leg(pkg, torch, synth.make_system(
+            int(c), grid_device=args.grid_device))
+            for c in args.bulk_configs.split(",") if c]
+
+    if args.bulk_only:
+        print(json.dumps({"bulk_interpolation": bulk()}))
+        return
+
     system = synth.make_system(args.config, grid_device=args.grid_device)
     r = run_workload(pkg, torch, system, args.steps, args.warmup,
-                     sweeps=args.sweeps, tune=len(system.ligands) > 1)
+                     sweeps=args.sweeps, tune=len(system.ligands) > 1,
+                     waves=args.waves)
     out = {
         "metric": "atom-grid energy+force evals/s & HBM fraction; effective "
                   "samples/s vs plain HMC",
@@ -442,7 +565,7 @@ def main():
         "data": "synthetic",
         "config": describe(system, r),
         "roofline": roofline(r, system.name),
-        "kernels_ms": {"hmc_sweep": r["hmc_ms"], "components": r["cmp_ms"]},
+        "kernels_ms": {"hmc_sweep": r["hmc_ms"], "energy_matrix": r["cmp_ms"]},
         "result": r["result"],
         "setup_s": r["setup_s"],
     }
@@ -452,13 +575,15 @@ def main():
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_seconds)
     if args.batched and args.config != 3:
         bs = synth.make_system(3, grid_device=args.grid_device)
-        rb = run_workload(pkg, torch, bs, 1, 1, tune=True)
+        rb = run_workload(pkg, torch, bs, 1, 1, tune=True, waves=args.waves)
         out["batched"] = {"value": rb["value"], "unit": "atom-evals/s",
                           "ms_per_step": rb["ms_per_step"], "steps": 1,
                           "warmup": 1, "config": describe(bs, rb),
                           "roofline": roofline(rb, bs.name),
                           "autotune": rb["tuned"], "waves": rb["waves"],
                           "result": rb["result"]}
+    if args.bulk:
+        out["bulk_interpolation"] = bulk()
     if args.learned:
         out["learned_proposal"] = learned_leg(
             pkg, torch, train_steps=args.train_steps,

@@ -117,9 +117,14 @@ typedef struct {
 /* Upload the grid: host_nodes is nz*ny*nx*n_channels floats, x fastest,
  * channel innermost (node (ix,iy,iz) channel c at
  * ((iz*ny + iy)*nx + ix)*n_channels + c).  Replaces a previous grid (only
- * allowed before the first ligand is set up).
- * Errors: BPMF_E_INVAL (bad sizes, non-finite node, negative node on a
- * transform-4 channel), BPMF_E_STATE (ligands exist), BPMF_E_NOMEM. */
+ * allowed before the first ligand is set up).  The library keeps a
+ * cell-major copy on the device: per cell the values of its 8 corners,
+ * padded to 8, 16, 32 or 64 floats (128 bytes for 3 or 4 channels), so one
+ * interpolation reads one aligned record; device memory is about 8x the
+ * node grid (0.5 GB for 160^3 x 3, 2.1 GB for 256^3 x 3).
+ * Errors: BPMF_E_INVAL (bad sizes, more than 64 GiB of cell records,
+ * non-finite node, negative node on a transform-4 channel), BPMF_E_STATE
+ * (ligands exist), BPMF_E_NOMEM. */
 BPMF_API int bpmf_grid_upload(bpmf_ctx* ctx, const bpmf_grid_desc* desc,
                      const float* host_nodes);
 
@@ -235,6 +240,19 @@ BPMF_API int bpmf_exchange(bpmf_ctx* ctx, int ligand_id, int scheme, int max_sep
  * Energy components are computed once per sample; U_k is affine in them. */
 BPMF_API int bpmf_energy_matrix(bpmf_ctx* ctx, int ligand_id, const float* dev_samples,
                        int64_t n_samples, double* dev_ukn, int64_t ld);
+
+/* bpmf_energy_matrix for n ligands in one call (host arrays of n entries;
+ * dev_samples may be NULL, or have NULL entries, for recorded samples).
+ * Every sample of every listed ligand is evaluated by one persistent
+ * launch per wavefront class, so many small ligands fill the chip together;
+ * each entry's u_kn is the one bpmf_energy_matrix writes.  Errors:
+ * BPMF_E_INVAL naming the entry (nothing is launched). */
+BPMF_API int bpmf_energy_matrix_batch(bpmf_ctx* ctx, int n,
+                                      const int* ligand_ids,
+                                      const float* const* dev_samples,
+                                      const int64_t* n_samples,
+                                      double* const* dev_ukn,
+                                      const int64_t* ld);
 
 /* MBAR (Shirts & Chodera 2008, which the paper uses for f_BC,L and f_CD'):
  * solves f_i = -ln sum_n exp(-u_in) / sum_k N_k exp(f_k - u_kn) with f_0 = 0
@@ -451,15 +469,20 @@ BPMF_API int bpmf_get_waves(bpmf_ctx* ctx, int ligand_id, int* waves);
 /* ------------------------------------------------------------------------
  * Kernel timing (HIP events on the context's stream)
  * ------------------------------------------------------------------------ */
-enum { BPMF_TIMER_HMC = 0, BPMF_TIMER_COMPONENTS = 1, BPMF_TIMER_TAIL = 2 };
+enum {
+  BPMF_TIMER_HMC = 0,
+  BPMF_TIMER_COMPONENTS = 1,
+  BPMF_TIMER_TAIL = 2,
+  BPMF_TIMER_GRID_EVAL = 3
+};
 
 /* While enabled, every `every`-th launch of each timed kernel (HMC: the
  * kernels of one sweep, which with scheme 0 also apply the previous sweep's
  * exchange and record, with scheme 1 followed by the tail kernel; TAIL: the
  * kernel that closes a scheme-0 call; COMPONENTS: per-sample components of
- * energy_matrix) is bracketed by a pair of HIP events recorded on the
- * context's stream (at most 8192 pairs per kernel between reads).  Enabling
- * clears earlier records. */
+ * energy_matrix; GRID_EVAL: the kernel of bpmf_grid_eval) is bracketed by a
+ * pair of HIP events recorded on the context's stream (at most 8192 pairs
+ * per kernel between reads).  Enabling clears earlier records. */
 BPMF_API int bpmf_set_timing(bpmf_ctx* ctx, int enable, int every);
 
 /* Mean duration in ms of the bracketed launches of `kernel` since timing

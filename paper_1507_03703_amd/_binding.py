@@ -92,6 +92,8 @@ def library():
         "bpmf_hmc_sweep": [vp, C.POINTER(_SweepArgs)],
         "bpmf_exchange": [vp, C.c_int, C.c_int, C.c_int],
         "bpmf_energy_matrix": [vp, C.c_int, vp, C.c_int64, vp, C.c_int64],
+        "bpmf_energy_matrix_batch": [vp, C.c_int, ip, C.POINTER(C.c_void_p),
+                                     i64p, C.POINTER(C.c_void_p), i64p],
         "bpmf_mbar": [vp, vp, C.c_int, C.c_int64, C.c_int64, i64p, C.c_double,
                       C.c_int, dp, dp, ip, C.c_int],
         "bpmf_mbar_batch": [vp, C.c_int, C.POINTER(C.c_void_p), ip, i64p, i64p,
@@ -283,6 +285,44 @@ class Context:
         _check(self._lib.bpmf_energy_matrix(self._h, int(ligand_id), ptr, N,
                                             out.data_ptr(), out.stride(0)))
         return out
+
+    def energy_matrix_batch(self, ligand_ids, samples=None, n_samples=None,
+                            outs=None):
+        """u_kn of several ligands in one call.  samples: None (recorded
+        samples of every ligand, n_samples[i] each) or a list of device
+        tensors (N_i, n_i, 3) float32 / None; outs: optional list of K_i x
+        N_i float64 tensors.  Returns the list of u_kn tensors."""
+        torch = self._torch
+        m = len(ligand_ids)
+        ids = np.ascontiguousarray(ligand_ids, np.int32)
+        ptrs = (C.c_void_p * max(m, 1))()
+        uptrs = (C.c_void_p * max(m, 1))()
+        ns = np.zeros(max(m, 1), np.int64)
+        lds = np.zeros(max(m, 1), np.int64)
+        res = []
+        for i, lid in enumerate(ligand_ids):
+            x = None if samples is None else samples[i]
+            if x is not None:
+                assert x.is_cuda and x.dtype == torch.float32 and \
+                    x.is_contiguous()
+                ns[i] = x.shape[0]
+                ptrs[i] = x.data_ptr()
+            else:
+                ns[i] = int(n_samples[i])
+            K = self.ligands[lid]["K"]
+            u = outs[i] if outs is not None else torch.empty(
+                (K, int(ns[i])), dtype=torch.float64,
+                device=f"cuda:{self.device}")
+            assert u.is_cuda and u.dtype == torch.float64 and \
+                u.stride(1) == 1
+            uptrs[i] = u.data_ptr()
+            lds[i] = u.stride(0)
+            res.append(u)
+        _check(self._lib.bpmf_energy_matrix_batch(
+            self._h, m, _pi(ids), ptrs,
+            ns.ctypes.data_as(C.POINTER(C.c_int64)), uptrs,
+            lds.ctypes.data_as(C.POINTER(C.c_int64))))
+        return res
 
     def mbar(self, ukn, N_k, tol=1e-10, max_iter=100, f_init=None):
         """Returns (f, var, n_iter): f[K] with f[0] = 0, var[k] = asymptotic
@@ -545,7 +585,7 @@ class Context:
                                         C.byref(out)))
         return out.value
 
-    TIMER_HMC, TIMER_COMPONENTS, TIMER_TAIL = 0, 1, 2
+    TIMER_HMC, TIMER_COMPONENTS, TIMER_TAIL, TIMER_GRID_EVAL = 0, 1, 2, 3
 
     def set_timing(self, enable=True, every=1):
         _check(self._lib.bpmf_set_timing(self._h, int(bool(enable)),

@@ -98,22 +98,26 @@ struct bpmf_ctx {
   int class_lds[kWaveClasses] = {0, 0, 0, 0};
   int class_single[kWaveClasses] = {-1, -1, -1, -1};  // sole ligand or -1
   int waves_override = 0;  // 0 = automatic choice
+  int n_cu = 1;  // compute units of the device
   // scratch
-  void* comps_mem = nullptr;
+  void* comps_mem = nullptr;  // energy-matrix job table (device)
   size_t comps_bytes = 0;
+  UknJob* jobs_host = nullptr;  // pinned staging of the job table
+  size_t jobs_host_n = 0;
+  hipEvent_t jobs_copied = nullptr;  // last upload of the staging buffer
   void* mbar_mem = nullptr;
   size_t mbar_bytes = 0;
   void* mlp_mem = nullptr;   // activations of the proposal network
   size_t mlp_bytes = 0;
   // kernel timing
-  static constexpr int kTimers = 3;
+  static constexpr int kTimers = 4;
   static constexpr size_t kMaxPairs = 8192;
   bool timing = false;
   int timing_every = 1;
-  uint64_t launches[kTimers] = {0, 0, 0};
+  uint64_t launches[kTimers] = {0, 0, 0, 0};
   std::vector<hipEvent_t> ev_pool[kTimers];  // start/stop pairs
   std::vector<int> ev_weight[kTimers];       // launches covered by a pair
-  size_t ev_used[kTimers] = {0, 0, 0};
+  size_t ev_used[kTimers] = {0, 0, 0, 0};
   // hipGraph of a chunk of sweeps (captured on a private stream, launched on
   // `stream`)
   int graph_chunk = 64;  // 0 disables
@@ -321,6 +325,10 @@ extern "C" int bpmf_create(bpmf_ctx** out, int device, uint64_t seed,
   bpmf_ctx* c = new (std::nothrow) bpmf_ctx();
   if (!c) return fail(BPMF_E_NOMEM, "context allocation failed");
   c->device = device;
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
+                            device) != hipSuccess ||
+      c->n_cu < 1)
+    c->n_cu = 1;
   c->seed = seed;
   c->stream = (hipStream_t)hip_stream;
   c->alloc = alloc;
@@ -343,6 +351,8 @@ extern "C" int bpmf_destroy(bpmf_ctx* c) {
   c->dfree(c->d_ligs);
   c->dfree(c->d_tasks);
   c->dfree(c->comps_mem);
+  if (c->jobs_host) (void)hipHostFree(c->jobs_host);
+  if (c->jobs_copied) (void)hipEventDestroy(c->jobs_copied);
   c->dfree(c->mbar_mem);
   for (int k = 0; k < bpmf_ctx::kTimers; ++k)
     for (hipEvent_t e : c->ev_pool[k]) (void)hipEventDestroy(e);
@@ -400,18 +410,36 @@ extern "C" int bpmf_grid_upload(bpmf_ctx* c, const bpmf_grid_desc* d,
                   "negative value %g at index %zu of a quartic-root channel", v,
                   i);
   }
-  void* mem = c->dalloc(nn * d->n_channels * sizeof(float));
-  if (!mem) return fail(BPMF_E_NOMEM, "grid allocation failed");
-  hipError_t e = hipMemcpyAsync(mem, nodes, nn * d->n_channels * sizeof(float),
+  // the kernels read the cell-major copy (8 corners of a cell in one
+  // record); the node-major upload is a staging buffer
+  const size_t cell_bytes = (size_t)(d->nx - 1) * (d->ny - 1) * (d->nz - 1) *
+                            cell_stride(d->n_channels) * sizeof(float);
+  if (cell_bytes > ((size_t)64 << 30))
+    return fail(BPMF_E_INVAL, "grid too large: %zu bytes of cell records",
+                cell_bytes);
+  void* stage = c->dalloc(nn * d->n_channels * sizeof(float));
+  if (!stage) return fail(BPMF_E_NOMEM, "grid staging allocation failed");
+  void* mem = c->dalloc(cell_bytes);
+  if (!mem) {
+    c->dfree(stage);
+    return fail(BPMF_E_NOMEM, "grid allocation failed (%zu bytes)",
+                cell_bytes);
+  }
+  hipError_t e = hipMemcpyAsync(stage, nodes,
+                                nn * d->n_channels * sizeof(float),
                                 hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = launch_expand_cells((const float*)stage, d->nx, d->ny, d->nz,
+                            d->n_channels, (float*)mem, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->dfree(stage);
   if (e != hipSuccess) {
     c->dfree(mem);
     return fail(BPMF_E_HIP, "grid upload: %s", hipGetErrorString(e));
   }
   c->dfree(c->grid_mem);
   c->grid_mem = mem;
-  c->grid.nodes = (const float*)mem;
+  c->grid.cells = (const float*)mem;
   c->grid.nx = d->nx;
   c->grid.ny = d->ny;
   c->grid.nz = d->nz;
@@ -923,41 +951,125 @@ extern "C" int bpmf_exchange(bpmf_ctx* c, int ligand_id, int scheme,
 // ============================================================================
 // u_kn, MBAR
 // ============================================================================
+// u_kn of several ligands: one persistent launch per wavefront class, the
+// job table staged through pinned memory (the previous upload must have
+// left it before it is rewritten)
+extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
+                                        const int* ligand_ids,
+                                        const float* const* dev_samples,
+                                        const int64_t* n_samples,
+                                        double* const* dev_ukn,
+                                        const int64_t* ld) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (n < 0) return fail(BPMF_E_INVAL, "negative batch size");
+  if (n == 0) return BPMF_OK;
+  if (!ligand_ids || !n_samples || !dev_ukn || !ld)
+    return fail(BPMF_E_INVAL, "null energy-matrix argument");
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if ((rc = check_lig(c, ligand_ids[i]))) return rc;
+    const LigHost& h = c->ligs[ligand_ids[i]];
+    const int64_t ns = n_samples[i];
+    if (ns < 0)
+      return fail(BPMF_E_INVAL, "entry %d: negative n_samples", i);
+    if (!dev_ukn[i] && ns > 0)
+      return fail(BPMF_E_INVAL, "entry %d: null u_kn output", i);
+    if (ld[i] < ns)
+      return fail(BPMF_E_INVAL, "entry %d: ld %lld < n_samples %lld", i,
+                  (long long)ld[i], (long long)ns);
+    if ((!dev_samples || !dev_samples[i]) && ns != h.n_rec * h.dev.K)
+      return fail(BPMF_E_INVAL,
+                  "entry %d: recorded samples: n_samples must be %lld "
+                  "(records x K)",
+                  i, (long long)(h.n_rec * h.dev.K));
+    total += ns;
+  }
+  if (total == 0) return BPMF_OK;
+  for (int i = 0; i < n; ++i) {
+    const LigHost& h = c->ligs[ligand_ids[i]];
+    const int need = lds_of(h, h.min_waves, false) +
+                     (int)(h.dev.K * (h.dev.C + 1) * sizeof(double));
+    if (need > 65536)
+      return fail(BPMF_E_UNIMPL,
+                  "entry %d: %d bytes of LDS per block (topology and %d "
+                  "states' weights; max 65536)",
+                  i, need, h.dev.K);
+  }
+  // chunks of up to 16 samples (a 128-byte line of each u_kn row), fewer
+  // when that would leave the chip without enough of them
+  int chunk = 16;
+  while (chunk > 1 && total / chunk < (int64_t)8 * 8 * c->n_cu) chunk /= 2;
+  // jobs grouped by wavefront class, each group followed by a sentinel
+  std::vector<UknJob> jobs;
+  int64_t group_chunks[bpmf_ctx::kWaveClasses] = {0};
+  int group_off[bpmf_ctx::kWaveClasses] = {0}, group_lds[bpmf_ctx::kWaveClasses] = {0};
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+    const int W = 1 << q;
+    group_off[q] = (int)jobs.size();
+    int64_t ch = 0;
+    for (int i = 0; i < n; ++i) {
+      const LigHost& h = c->ligs[ligand_ids[i]];
+      if (h.min_waves != W || n_samples[i] == 0) continue;
+      UknJob J;
+      J.lig = ligand_ids[i];
+      J.pad = 0;
+      J.xs = dev_samples && dev_samples[i] ? dev_samples[i] : h.dev.samp_x;
+      J.ukn = dev_ukn[i];
+      J.n = n_samples[i];
+      J.ld = ld[i];
+      J.chunk0 = ch;
+      ch += (J.n + chunk - 1) / chunk;
+      jobs.push_back(J);
+      // the block's evaluation areas and topology, then the state weights
+      // and beta_k of the expansion
+      group_lds[q] =
+          std::max(group_lds[q],
+                   lds_of(h, W, false) +
+                       (int)(h.dev.K * (h.dev.C + 1) * sizeof(double)));
+    }
+    group_chunks[q] = ch;
+    UknJob end{};
+    end.chunk0 = ch;
+    jobs.push_back(end);
+  }
+  rc = ensure_scratch(c, &c->comps_mem, &c->comps_bytes,
+                      jobs.size() * sizeof(UknJob));
+  if (rc) return rc;
+  if (!c->jobs_copied) HIP_TRY(hipEventCreate(&c->jobs_copied));
+  HIP_TRY(hipEventSynchronize(c->jobs_copied));
+  if (c->jobs_host_n < jobs.size()) {
+    if (c->jobs_host) HIP_TRY(hipHostFree(c->jobs_host));
+    c->jobs_host = nullptr;
+    c->jobs_host_n = 0;
+    HIP_TRY(hipHostMalloc((void**)&c->jobs_host,
+                          jobs.size() * sizeof(UknJob)));
+    c->jobs_host_n = jobs.size();
+  }
+  memcpy(c->jobs_host, jobs.data(), jobs.size() * sizeof(UknJob));
+  UknJob* d_jobs = (UknJob*)c->comps_mem;
+  HIP_TRY(hipMemcpyAsync(d_jobs, c->jobs_host, jobs.size() * sizeof(UknJob),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->jobs_copied, c->stream));
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+    if (group_chunks[q] == 0) continue;
+    hipEvent_t t0, t1;
+    const bool timed = c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
+    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+    HIP_TRY(launch_energy_matrix(c->grid, c->d_ligs, 1 << q,
+                                 d_jobs + group_off[q],
+                                 group_chunks[q], chunk, group_lds[q],
+                                 c->n_cu, c->stream));
+    if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
+  }
+  return BPMF_OK;
+}
+
 extern "C" int bpmf_energy_matrix(bpmf_ctx* c, int ligand_id,
                                   const float* dev_samples, int64_t n_samples,
                                   double* dev_ukn, int64_t ld) {
-  int rc = check_ctx(c);
-  if (rc) return rc;
-  if ((rc = check_lig(c, ligand_id))) return rc;
-  const LigHost& h = c->ligs[ligand_id];
-  if (n_samples < 0) return fail(BPMF_E_INVAL, "negative n_samples");
-  if (!dev_ukn && n_samples > 0) return fail(BPMF_E_INVAL, "null u_kn output");
-  if (ld < n_samples) return fail(BPMF_E_INVAL, "ld %lld < n_samples %lld",
-                                  (long long)ld, (long long)n_samples);
-  const float* xs = dev_samples;
-  if (!xs) {
-    if (n_samples != h.n_rec * h.dev.K)
-      return fail(BPMF_E_INVAL,
-                  "recorded samples: n_samples must be %lld (records x K)",
-                  (long long)(h.n_rec * h.dev.K));
-    xs = h.dev.samp_x;
-  }
-  if (n_samples == 0) return BPMF_OK;
-  const int C = h.dev.C;
-  rc = ensure_scratch(c, &c->comps_mem, &c->comps_bytes,
-                      (size_t)n_samples * (1 + C) * sizeof(double));
-  if (rc) return rc;
-  double* comps = (double*)c->comps_mem;
-  hipEvent_t t0, t1;
-  const bool timed = c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
-  if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
-  HIP_TRY(launch_components(c->grid, c->d_ligs + ligand_id, h.min_waves, xs,
-                            n_samples, comps,
-                            lds_of(h, h.min_waves, false), c->stream));
-  if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
-  HIP_TRY(launch_expand(comps, n_samples, h.dev.K, C, h.dev.beta, h.dev.wd,
-                        dev_ukn, ld, c->stream));
-  return BPMF_OK;
+  return bpmf_energy_matrix_batch(c, 1, &ligand_id, &dev_samples, &n_samples,
+                                  &dev_ukn, &ld);
 }
 
 namespace {
@@ -1324,8 +1436,12 @@ extern "C" int bpmf_grid_eval(bpmf_ctx* c, const float* dev_pos,
   if (!dev_pos || !dev_scale || !w)
     return fail(BPMF_E_INVAL, "null grid_eval argument");
   if (!finite_all(w, c->grid.C)) return fail(BPMF_E_INVAL, "non-finite weight");
+  hipEvent_t t0, t1;
+  const bool timed = c->timer_begin(BPMF_TIMER_GRID_EVAL, &t0, &t1);
+  if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
   HIP_TRY(launch_grid_eval(c->grid, dev_pos, dev_scale, n, w, dev_energy,
                            dev_force, c->stream));
+  if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   return BPMF_OK;
 }
 

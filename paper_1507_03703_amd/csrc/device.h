@@ -181,34 +181,44 @@ __device__ __forceinline__ AxisPos grid_axis(float x, float o, float inv_h,
 }
 
 // Raw corner values of the cell containing p: g[corner][c], corner bits
-// (x, y<<1, z<<2).  Issued as independent loads so that callers can overlap
-// their latency with other work before consuming them.
+// (x, y<<1, z<<2), read from the cell's record with 16-byte loads.  Issued
+// as independent loads so that callers can overlap their latency with other
+// work before consuming them.
 template <int C>
 struct Corners {
   float v[8][C];
   AxisPos ax, ay, az;
 };
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <int C>
 __device__ __forceinline__ void grid_fetch(const GridDev& g, float px,
                                            float py, float pz,
                                            Corners<C>& k) {
+  static_assert((8 * C) % 4 == 0, "records are read as float4");
   k.ax = grid_axis(px, g.ox, g.inv_h, g.nx);
   k.ay = grid_axis(py, g.oy, g.inv_h, g.ny);
   k.az = grid_axis(pz, g.oz, g.inv_h, g.nz);
-  const size_t sx = C, sy = (size_t)g.nx * C, sz = (size_t)g.nx * g.ny * C;
+  const size_t cell =
+      ((size_t)k.az.i * (g.ny - 1) + k.ay.i) * (size_t)(g.nx - 1) + k.ax.i;
   // the grid lives in global memory: say so, so that the gathers are
   // global (not flat) loads and LDS waits do not wait on them
-  typedef const float __attribute__((address_space(1))) gfloat;
-  gfloat* base = (gfloat*)g.nodes + (size_t)k.az.i * sz +
-                 (size_t)k.ay.i * sy + (size_t)k.ax.i * sx;
+  typedef const f32x4 __attribute__((address_space(1))) gvec;
+  gvec* rec = (gvec*)g.cells + cell * (cell_stride(C) / 4);
+  float b[8 * C];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    gfloat* p = base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) +
-                ((q & 4) ? sz : 0);
-#pragma unroll
-    for (int c = 0; c < C; ++c) k.v[q][c] = p[c];
+  for (int j = 0; j < 2 * C; ++j) {
+    const f32x4 t = rec[j];
+    b[4 * j] = t.x;
+    b[4 * j + 1] = t.y;
+    b[4 * j + 2] = t.z;
+    b[4 * j + 3] = t.w;
   }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int c = 0; c < C; ++c) k.v[q][c] = b[q * C + c];
 }
 
 // value e_c = s_c * v_c (or s_c * v_c^4) and gradient de_c of every channel

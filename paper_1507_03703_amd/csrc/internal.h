@@ -18,8 +18,8 @@ __host__ __device__ inline int acc_lds_bytes(int n) {
 
 // dynamic LDS bytes of a W-wave evaluation block: per-evaluation areas,
 // force accumulators (forces only) and the staged topology
-inline int block_lds_bytes(int waves, bool forces, int n, int nb, int na,
-                           int nt) {
+__host__ __device__ inline int block_lds_bytes(int waves, bool forces, int n,
+                                                int nb, int na, int nt) {
   const int head = 16 * kWave * waves + 8 * waves * kRedSlots + 16 * waves +
                    (forces ? acc_lds_bytes(n) : 0);
   const int topo = 32 * nt + 24 * na + 16 * nb;
@@ -28,11 +28,22 @@ inline int block_lds_bytes(int waves, bool forces, int n, int nb, int na,
 
 enum Purpose : uint32_t { kMomenta = 1, kAccept = 2, kExchange = 3 };
 
-// Receptor grid as the kernels see it.  Node (ix,iy,iz) channel c is at
-// nodes[((iz*ny + iy)*nx + ix)*C + c]; channel c holds a quartic root when
-// bit c of quartic_mask is set.
+// Floats per cell record of the cell-major grid: the 8 corners x C channels
+// rounded up to a power of two, so that a record of up to 4 channels is one
+// aligned 128-byte cache line.
+constexpr int cell_stride(int C) {
+  return 8 * C <= 8 ? 8 : 8 * C <= 16 ? 16 : 8 * C <= 32 ? 32 : 64;
+}
+
+// Receptor grid as the kernels see it, cell-major: cell (i, j, k) (i < nx-1,
+// j < ny-1, k < nz-1) owns the record at cells + ((k*(ny-1) + j)*(nx-1) + i)
+// * cell_stride(C) holding the values of its corners, corner q = (i + (q&1),
+// j + ((q>>1)&1), k + (q>>2)) at [q*C + c] for channel c.  Each node value
+// appears in up to 8 records: one interpolation reads one record instead of
+// 8 scattered corners.  Channel c holds a quartic root when bit c of
+// quartic_mask is set.
 struct GridDev {
-  const float* nodes;
+  const float* cells;
   int nx, ny, nz, C;
   float ox, oy, oz, inv_h;
   int quartic_mask;
@@ -119,16 +130,30 @@ hipError_t launch_sweep_finish(const LigDev* d_ligs, int n_ligs,
                                uint64_t seed, hipStream_t st);
 hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
                            int max_sep, uint64_t seed, hipStream_t st);
-hipError_t launch_components(const GridDev& g, const LigDev* d_lig,
-                             int waves, const float* xs, int64_t N,
-                             double* comps, int lds_bytes, hipStream_t st);
-hipError_t launch_expand(const double* comps, int64_t N, int K, int C,
-                         const double* beta, const double* wd, double* ukn,
-                         int64_t ld, hipStream_t st);
+// one ligand's share of an energy-matrix launch: samples xs (n x n_atoms x
+// 3), output u_kn (K x ld), chunks [chunk0, chunk0 + ceil(n / chunk))
+struct UknJob {
+  int lig;  // index into the ligand table
+  int pad;
+  const float* xs;
+  double* ukn;
+  int64_t n, ld;
+  int64_t chunk0;
+};
+// d_jobs: jobs sorted by chunk0, every ligand needing `waves` wavefronts,
+// followed by a sentinel whose chunk0 = n_chunks
+hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
+                                int waves, const UknJob* d_jobs,
+                                int64_t n_chunks, int chunk, int lds_bytes,
+                                int n_cu, hipStream_t st);
 hipError_t launch_evaluate(const GridDev& g, const LigDev* d_lig,
                            int waves, const float* xs, int64_t N,
                            const double* w, double* terms, float* forces,
                            int lds_bytes, hipStream_t st);
+// cell-major records (GridDev) from a node-major grid nodes[((k*ny + j)*nx +
+// i)*C + c]
+hipError_t launch_expand_cells(const float* nodes, int nx, int ny, int nz,
+                               int C, float* cells, hipStream_t st);
 hipError_t launch_grid_eval(const GridDev& g, const float* pos,
                             const float* scale, int64_t n, const double* w,
                             float* energy, float* force, hipStream_t st);

@@ -523,52 +523,77 @@ __global__ __launch_bounds__(256) void k_exchange(
 }
 
 // ----------------------------------------------------------------------------
-// per-sample components [U_bonded + U_I, Psi_c] (energy only)
+// reduced-energy matrix u_kn = beta_k (U0_n + sum_c w_kc Psi_cn) of samples
+// of one or many ligands (Estimation), energy only
 // ----------------------------------------------------------------------------
+// One W-wave block evaluates one sample at a time, persistent over the
+// launch.  The work is the flat list of chunks of `chunk` consecutive
+// samples of one ligand (jobs sorted by first chunk, sentinel at n_jobs);
+// chunks are dealt out round-robin over XCD-major virtual block ids (blocks
+// are spread over the 8 XCDs round-robin), so the blocks of one XCD take
+// neighbouring chunks and its L2 assembles whole lines of each u_kn row.
+// Lane k of the block writes state k's entry of the sample's column.
 template <int C, int W>
-__global__ __launch_bounds__(W * kWave) void k_components(
-    GridDev g, const LigDev* __restrict__ lig, const float* __restrict__ xs,
-    int64_t N, double* __restrict__ comps) {
+__global__ __launch_bounds__(W * kWave) void k_energy_matrix(
+    GridDev g, const LigDev* __restrict__ ligs,
+    const UknJob* __restrict__ jobs, int64_t n_chunks, int chunk) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const LigDev L = *lig;
   const int tid = threadIdx.x;
-  const int n = L.n;
-  const Shared sh = carve<W>(smem, L, 0, tid);
-  const bool owner = tid < n;
-  const float m = owner ? L.mass[tid] : 0.f;
-  float sc[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) sc[c] = owner ? L.scale[tid * C + c] : 0.f;
+  const int nb = gridDim.x;  // a multiple of 8
+  const int vb = (int)(blockIdx.x % 8) * (nb / 8) + (int)(blockIdx.x / 8);
   const float w0[C] = {};
-  for (int64_t smp = blockIdx.x; smp < N; smp += gridDim.x) {
-    float x[3], f[3];
-    const float* xr = xs + (size_t)smp * n * 3;
+  int jn = 0;
+  for (int64_t ch = vb; ch < n_chunks; ch += nb) {
+    while (jobs[jn].chunk0 <= ch) ++jn;  // the sentinel stops the scan
+    // ligands and jobs come from restrict arguments: the u_kn stores
+    // cannot clobber them, so they load into scalar registers
+    const UknJob J = jobs[jn - 1];
+    const LigDev L = ligs[J.lig];
+    // topology staged per chunk (the chunk's samples share it); the barrier
+    // in carve also keeps the previous chunk's readers ahead of the copy
+    const Shared sh = carve<W>(smem, L, 0, tid);
+    // state weights and beta_k after the topology, for the expansion (the
+    // evaluation's first barrier orders these writes before their reads)
+    const int K = L.K;
+    double* ew = reinterpret_cast<double*>(
+        smem + block_lds_bytes(W, false, L.n, L.nb, L.na, L.nt));
+    for (int i = tid; i < K * (C + 1); i += W * kWave)
+      ew[i] = i < K * C ? L.wd[i] : L.beta[i - K * C];
+    // per-lane data through global (not flat) loads, so that the waits of
+    // the evaluation's LDS reads do not wait on them
+    typedef const float __attribute__((address_space(1))) gfloat;
+    const int n = L.n;
+    const bool owner = tid < n;
+    const float m = owner ? ((const gfloat*)L.mass)[tid] : 0.f;
+    float sc[C];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) x[d] = owner ? xr[tid * 3 + d] : 0.f;
-    double t[6 + C];
-    eval_block<C, W, false, true>(g, L, w0, x, m, sc, f, t, 0.f, 0.f, sh, tid);
-    if (tid == 0) {
-      double* cp = comps + (size_t)smp * (1 + C);
-      cp[0] = t[0] + t[1] + t[2] + t[3];
+    for (int c = 0; c < C; ++c)
+      sc[c] = owner ? ((const gfloat*)L.scale)[tid * C + c] : 0.f;
+    const int64_t s0 = (ch - J.chunk0) * chunk;
+    const int64_t s1 = s0 + chunk < J.n ? s0 + chunk : J.n;
+    const gfloat* xb = (const gfloat*)J.xs + (size_t)tid * 3;
+    // positions of the next sample load during the current evaluation
+    float xn[3];
 #pragma unroll
-      for (int c = 0; c < C; ++c) cp[1 + c] = t[4 + c];
+    for (int d = 0; d < 3; ++d) xn[d] = owner ? xb[(size_t)s0 * n * 3 + d] : 0.f;
+    for (int64_t s = s0; s < s1; ++s) {
+      float x[3] = {xn[0], xn[1], xn[2]}, f[3];
+      if (s + 1 < s1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          xn[d] = owner ? xb[(size_t)(s + 1) * n * 3 + d] : 0.f;
+      }
+      double t[6 + C];
+      eval_block<C, W, false, true>(g, L, w0, x, m, sc, f, t, 0.f, 0.f, sh,
+                                    tid);
+      const double U0 = t[0] + t[1] + t[2] + t[3];
+      for (int k = tid; k < K; k += W * kWave) {
+        double E = U0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) E = fma(ew[k * C + c], t[4 + c], E);
+        J.ukn[(size_t)k * J.ld + s] = ew[K * C + k] * E;
+      }
     }
-  }
-}
-
-// u_kn = beta_k (E0_n + sum_c w_kc Psi_cn), row-major with leading dim ld
-__global__ __launch_bounds__(256) void k_expand(
-    const double* __restrict__ comps, int64_t N, int K, int C,
-    const double* __restrict__ beta, const double* __restrict__ wd,
-    double* __restrict__ ukn, int64_t ld) {
-  const int k = blockIdx.y;
-  const double bk = beta[k];
-  for (int64_t nn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; nn < N;
-       nn += (int64_t)gridDim.x * blockDim.x) {
-    const double* cp = comps + (size_t)nn * (1 + C);
-    double E = cp[0];
-    for (int c = 0; c < C; ++c) E += wd[k * C + c] * cp[1 + c];
-    ukn[(size_t)k * ld + nn] = bk * E;
   }
 }
 
@@ -679,6 +704,30 @@ __global__ __launch_bounds__(256) void k_grid_eval(
   }
 }
 
+// cell-major records from the node-major grid (one thread per record float,
+// pads zero)
+__global__ __launch_bounds__(256) void k_expand_cells(
+    const float* __restrict__ nodes, int nx, int ny, int nz, int C,
+    float* __restrict__ cells) {
+  const int stride = cell_stride(C);
+  const size_t cx = nx - 1, cy = ny - 1;
+  const size_t total = cx * cy * (size_t)(nz - 1) * stride;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t cell = e / stride;
+    const int o = (int)(e - cell * stride);
+    float v = 0.f;
+    if (o < 8 * C) {
+      const int q = o / C, c = o - q * C;
+      const size_t i = cell % cx + (q & 1);
+      const size_t j = (cell / cx) % cy + ((q >> 1) & 1);
+      const size_t k = cell / (cx * cy) + (q >> 2);
+      v = nodes[((k * ny + j) * nx + i) * C + c];
+    }
+    cells[e] = v;
+  }
+}
+
 int grid_blocks(int64_t work, int per_block, int cap) {
   int64_t b = (work + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -783,25 +832,24 @@ hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
   return hipGetLastError();
 }
 
-hipError_t launch_components(const GridDev& g, const LigDev* d_lig,
-                             int waves, const float* xs, int64_t N,
-                             double* comps, int lds_bytes, hipStream_t st) {
-  if (N <= 0) return hipSuccess;
-  const int blocks = grid_blocks(N, 1, 1 << 20);
+hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
+                                int waves, const UknJob* d_jobs,
+                                int64_t n_chunks, int chunk, int lds_bytes,
+                                int n_cu, hipStream_t st) {
+  if (n_chunks <= 0) return hipSuccess;
   BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
-    hipLaunchKernelGGL((k_components<C, W>), dim3(blocks), dim3(W * kWave),
-                       lds_bytes, st, g, d_lig, xs, N, comps);
+    auto kern = k_energy_matrix<C, W>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, kern, W * kWave, lds_bytes);
+    if (e != hipSuccess) return e;
+    int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * n_cu;
+    const int64_t want = (n_chunks + 7) / 8 * 8;
+    if (blocks > want) blocks = want;
+    blocks = (blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(W * kWave),
+                       lds_bytes, st, g, d_ligs, d_jobs, n_chunks, chunk);
   }));
-  return hipGetLastError();
-}
-
-hipError_t launch_expand(const double* comps, int64_t N, int K, int C,
-                         const double* beta, const double* wd, double* ukn,
-                         int64_t ld, hipStream_t st) {
-  if (N <= 0 || K <= 0) return hipSuccess;
-  const int bx = grid_blocks(N, 256, 4096);
-  hipLaunchKernelGGL(k_expand, dim3(bx, K), dim3(256), 0, st, comps, N, K, C,
-                     beta, wd, ukn, ld);
   return hipGetLastError();
 }
 
@@ -825,6 +873,15 @@ hipError_t launch_recompute_comps(const GridDev& g, const LigDev* d_lig,
     hipLaunchKernelGGL((k_recompute<C, W>), dim3(K), dim3(W * kWave),
                        lds_bytes, st, g, d_lig);
   }));
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_cells(const float* nodes, int nx, int ny, int nz,
+                               int C, float* cells, hipStream_t st) {
+  const int64_t total =
+      (int64_t)(nx - 1) * (ny - 1) * (nz - 1) * cell_stride(C);
+  hipLaunchKernelGGL(k_expand_cells, dim3(grid_blocks(total, 256, 1 << 16)),
+                     dim3(256), 0, st, nodes, nx, ny, nz, C, cells);
   return hipGetLastError();
 }
 

@@ -168,3 +168,47 @@ def test_large_grid_workload_sampled_ligands():
     assert np.all(np.abs(u - ref) <=
                   1e-5 * beta[:, None] * mags.sum(axis=1)[None, :] + 1e-12)
     ctx.close()
+
+
+def test_energy_matrix_batch_equals_per_ligand_calls():
+    """One batched u_kn call over ligands of one and two wavefronts (recorded
+    samples for some, explicit device samples for others) writes exactly
+    the matrices of per-ligand calls, and matches the oracle's brute force."""
+    g, ligs = _uneven_ligands()
+    print_case("energy_matrix batch", [l.n_atoms for l in ligs])
+    ctx, ids = make_context(g, ligs, seed=9, capacity=6)
+    ctx.hmc_sweep(12, 10, exchange_every=1, sample_every=2)
+    rng = np.random.default_rng(9)
+    samples, ns = [], []
+    for p, l in enumerate(ligs):
+        if p % 2:
+            x = l.x0[0][None] + rng.normal(scale=0.3, size=(37, l.n_atoms, 3))
+            samples.append(torch.tensor(x, dtype=torch.float32,
+                                        device="cuda:0"))
+            ns.append(37)
+        else:
+            samples.append(None)
+            ns.append(6 * l.n_states)
+    batch = ctx.energy_matrix_batch(ids, samples=samples, n_samples=ns)
+    og = oracle.OGrid(g)
+    for p, (lid, l) in enumerate(zip(ids, ligs)):
+        one = ctx.energy_matrix(lid, samples[p], n_samples=ns[p])
+        assert torch.equal(batch[p], one), p
+        if samples[p] is None:
+            xs, _ = ctx.get_samples(lid)
+            X = xs.reshape(-1, l.n_atoms, 3)
+        else:
+            X = samples[p].cpu().numpy()
+        ol = oracle.OLigand(l)
+        ref = oracle.ukn(og, ol, X)
+        _, mags = oracle.components(og, ol, X)
+        beta = 1.0 / (oracle.R_GAS * l.T)
+        u = batch[p].cpu().numpy()
+        assert np.all(np.abs(u - ref) <=
+                      1e-5 * beta[:, None] * mags.sum(axis=1)[None, :] +
+                      1e-12), p
+    with pytest.raises(RuntimeError, match="entry 1"):
+        ctx.energy_matrix_batch(ids[:2], samples=[None, None],
+                                n_samples=[6 * ligs[0].n_states, 5])
+    assert ctx.energy_matrix_batch([], samples=[]) == []
+    ctx.close()
