@@ -986,28 +986,37 @@ extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
     total += ns;
   }
   if (total == 0) return BPMF_OK;
+  // columns staged in groups of up to 16 samples (a 128-byte line of each
+  // u_kn row), fewer when group x K doubles would exceed 16 KB of LDS
+  int group = 16, max_K = 0;
+  for (int i = 0; i < n; ++i)
+    max_K = std::max(max_K, c->ligs[ligand_ids[i]].dev.K);
+  while (group > 1 && (int64_t)group * max_K * 8 > 16384) group /= 2;
+  // LDS of a block: evaluation areas and topology, the states' weights and
+  // beta_k, the group's columns
+  auto ukn_lds = [&](const LigHost& h, int W) {
+    return lds_of(h, W, false) +
+           (int)((size_t)h.dev.K * (h.dev.C + 1 + group) * sizeof(double));
+  };
   for (int i = 0; i < n; ++i) {
     const LigHost& h = c->ligs[ligand_ids[i]];
-    const int need = lds_of(h, h.min_waves, false) +
-                     (int)(h.dev.K * (h.dev.C + 1) * sizeof(double));
+    const int need = ukn_lds(h, h.min_waves);
     if (need > 65536)
       return fail(BPMF_E_UNIMPL,
                   "entry %d: %d bytes of LDS per block (topology and %d "
-                  "states' weights; max 65536)",
+                  "states' weights and columns; max 65536)",
                   i, need, h.dev.K);
   }
-  // chunks of up to 16 samples (a 128-byte line of each u_kn row), fewer
-  // when that would leave the chip without enough of them
-  int chunk = 16;
-  while (chunk > 1 && total / chunk < (int64_t)8 * 8 * c->n_cu) chunk /= 2;
   // jobs grouped by wavefront class, each group followed by a sentinel
   std::vector<UknJob> jobs;
-  int64_t group_chunks[bpmf_ctx::kWaveClasses] = {0};
-  int group_off[bpmf_ctx::kWaveClasses] = {0}, group_lds[bpmf_ctx::kWaveClasses] = {0};
+  int64_t group_total[bpmf_ctx::kWaveClasses] = {0};
+  int group_off[bpmf_ctx::kWaveClasses] = {0};
+  int group_n[bpmf_ctx::kWaveClasses] = {0};
+  int group_lds[bpmf_ctx::kWaveClasses] = {0};
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
     const int W = 1 << q;
     group_off[q] = (int)jobs.size();
-    int64_t ch = 0;
+    int64_t first = 0;
     for (int i = 0; i < n; ++i) {
       const LigHost& h = c->ligs[ligand_ids[i]];
       if (h.min_waves != W || n_samples[i] == 0) continue;
@@ -1018,19 +1027,15 @@ extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
       J.ukn = dev_ukn[i];
       J.n = n_samples[i];
       J.ld = ld[i];
-      J.chunk0 = ch;
-      ch += (J.n + chunk - 1) / chunk;
+      J.first = first;
+      first += J.n;
       jobs.push_back(J);
-      // the block's evaluation areas and topology, then the state weights
-      // and beta_k of the expansion
-      group_lds[q] =
-          std::max(group_lds[q],
-                   lds_of(h, W, false) +
-                       (int)(h.dev.K * (h.dev.C + 1) * sizeof(double)));
+      group_lds[q] = std::max(group_lds[q], ukn_lds(h, W));
     }
-    group_chunks[q] = ch;
+    group_n[q] = (int)jobs.size() - group_off[q];
+    group_total[q] = first;
     UknJob end{};
-    end.chunk0 = ch;
+    end.first = first;
     jobs.push_back(end);
   }
   rc = ensure_scratch(c, &c->comps_mem, &c->comps_bytes,
@@ -1052,13 +1057,13 @@ extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipEventRecord(c->jobs_copied, c->stream));
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
-    if (group_chunks[q] == 0) continue;
+    if (group_total[q] == 0) continue;
     hipEvent_t t0, t1;
     const bool timed = c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
     if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
     HIP_TRY(launch_energy_matrix(c->grid, c->d_ligs, 1 << q,
-                                 d_jobs + group_off[q],
-                                 group_chunks[q], chunk, group_lds[q],
+                                 d_jobs + group_off[q], group_n[q],
+                                 group_total[q], group, group_lds[q],
                                  c->n_cu, c->stream));
     if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   }

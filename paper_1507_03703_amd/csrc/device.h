@@ -323,6 +323,12 @@ struct Slots {
   }
 };
 
+// Global-memory view of a device pointer.  Pointers read from a table in
+// memory reach a kernel as generic (flat) addresses, and flat loads and
+// stores also count against the LDS wait counter: every LDS wait after one
+// would wait on memory.  Accesses through this view are global ones.
+#define BPMF_GMEM(T, p) ((T __attribute__((address_space(1)))*)(p))
+
 // hardware reciprocal (1 ulp), for the bonded-term geometry
 __device__ __forceinline__ float rcp(float x) {
   return __builtin_amdgcn_rcpf(x);
@@ -474,17 +480,33 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
   float2* apar = reinterpret_cast<float2*>(aijk + L.na);
   int2* bij = reinterpret_cast<int2*>(apar + L.na);
   float2* bpar = reinterpret_cast<float2*>(bij + L.nb);
+  // global (not flat) loads: they cannot alias the LDS stores, so several
+  // stay in flight at once
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  typedef int i4v __attribute__((ext_vector_type(4)));
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef int i2v __attribute__((ext_vector_type(2)));
+  typedef const f4v __attribute__((address_space(1))) gf4;
+  typedef const i4v __attribute__((address_space(1))) gi4;
+  typedef const f2v __attribute__((address_space(1))) gf2;
+  typedef const i2v __attribute__((address_space(1))) gi2;
   for (int i = tid; i < L.nt; i += nthreads) {
-    tpar[i] = L.tpar[i];
-    tijkl[i] = L.tijkl[i];
+    const f4v p = ((gf4*)L.tpar)[i];
+    const i4v q = ((gi4*)L.tijkl)[i];
+    tpar[i] = make_float4(p.x, p.y, p.z, p.w);
+    tijkl[i] = make_int4(q.x, q.y, q.z, q.w);
   }
   for (int i = tid; i < L.na; i += nthreads) {
-    aijk[i] = L.aijk[i];
-    apar[i] = L.apar[i];
+    const i4v q = ((gi4*)L.aijk)[i];
+    const f2v p = ((gf2*)L.apar)[i];
+    aijk[i] = make_int4(q.x, q.y, q.z, q.w);
+    apar[i] = make_float2(p.x, p.y);
   }
   for (int i = tid; i < L.nb; i += nthreads) {
-    bij[i] = L.bij[i];
-    bpar[i] = L.bpar[i];
+    const i2v q = ((gi2*)L.bij)[i];
+    const f2v p = ((gf2*)L.bpar)[i];
+    bij[i] = make_int2(q.x, q.y);
+    bpar[i] = make_float2(p.x, p.y);
   }
   sh.bij = bij;
   sh.bpar = bpar;
@@ -532,10 +554,11 @@ __device__ __forceinline__ void block_sync() {
 
 // sc: per-atom grid factors of the thread's atom (0 for non-owners).
 // terms (ENERGY): [U_bond, U_angle, U_tors, U_I, Psi_0..Psi_{C-1}, X0, X1]
+// (LEAN: [U_bond + U_angle + U_tors, 0, 0, U_I, Psi_c, 0, 0])
 // where X0, X1 are block sums of the caller's per-thread extras; identical
 // on every thread.  f (FORCES): -grad(U_bonded + U_I + sum_c w_c Psi_c) of
 // the thread's atom.
-template <int C, int W, bool FORCES, bool ENERGY>
+template <int C, int W, bool FORCES, bool ENERGY, bool LEAN = false>
 __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
                                            const float* w, const float (&x)[3],
                                            float m, const float (&sc)[C],
@@ -657,37 +680,47 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
       a3[2] = 0u;
       // the parts of the force that do not depend on the state weights
       if (cache_atom) {
-        cache_atom[0] = b[0];
-        cache_atom[1] = b[1];
-        cache_atom[2] = b[2];
+        auto ca = BPMF_GMEM(float, cache_atom);
+        ca[0] = b[0];
+        ca[1] = b[1];
+        ca[2] = b[2];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          cache_atom[3 + 3 * c] = de[c][0];
-          cache_atom[4 + 3 * c] = de[c][1];
-          cache_atom[5 + 3 * c] = de[c][2];
+          ca[3 + 3 * c] = de[c][0];
+          ca[4 + 3 * c] = de[c][1];
+          ca[5 + 3 * c] = de[c][2];
         }
       }
       if (cache_rep && tid == 0) {
-        cache_rep[0] = fr;
-        cache_rep[1] = cx;
-        cache_rep[2] = cy;
-        cache_rep[3] = cz;
+        auto cr = BPMF_GMEM(float, cache_rep);
+        cr[0] = fr;
+        cr[1] = cx;
+        cr[2] = cy;
+        cr[3] = cz;
       }
     } else {
       f[0] = f[1] = f[2] = 0.f;
     }
   }
   if (ENERGY) {
-    // per-wave sums in double, then a fixed-order sum over the waves
+    // per-wave sums in double, then a fixed-order sum over the waves.
+    // LEAN: only the bonded total (in terms[0]) and the grid sums; the
+    // extras are not reduced (their terms are 0)
     double v[6 + C];
-    v[0] = wave_sum((double)eb);
-    v[1] = wave_sum((double)ea);
-    v[2] = wave_sum((double)et);
+    if (LEAN) {
+      v[0] = wave_sum((double)eb + (double)ea + (double)et);
+      v[1] = 0.0;
+      v[2] = 0.0;
+    } else {
+      v[0] = wave_sum((double)eb);
+      v[1] = wave_sum((double)ea);
+      v[2] = wave_sum((double)et);
+    }
     v[3] = 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) v[4 + c] = wave_sum((double)psi[c]);
-    v[4 + C] = wave_sum((double)ex0);
-    v[5 + C] = wave_sum((double)ex1);
+    v[4 + C] = LEAN ? 0.0 : wave_sum((double)ex0);
+    v[5 + C] = LEAN ? 0.0 : wave_sum((double)ex1);
     if (lane == 0) {
 #pragma unroll
       for (int q = 0; q < 6 + C; ++q) sh.red[wv * kRedMax + q] = v[q];

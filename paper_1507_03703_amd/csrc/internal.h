@@ -131,20 +131,22 @@ hipError_t launch_sweep_finish(const LigDev* d_ligs, int n_ligs,
 hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
                            int max_sep, uint64_t seed, hipStream_t st);
 // one ligand's share of an energy-matrix launch: samples xs (n x n_atoms x
-// 3), output u_kn (K x ld), chunks [chunk0, chunk0 + ceil(n / chunk))
+// 3), output u_kn (K x ld); its samples are [first, first + n) of the
+// launch's flat sample index
 struct UknJob {
   int lig;  // index into the ligand table
   int pad;
   const float* xs;
   double* ukn;
   int64_t n, ld;
-  int64_t chunk0;
+  int64_t first;
 };
-// d_jobs: jobs sorted by chunk0, every ligand needing `waves` wavefronts,
-// followed by a sentinel whose chunk0 = n_chunks
+// d_jobs: n_jobs jobs in flat order, every ligand needing `waves`
+// wavefronts, then a sentinel with first = total; group = samples whose
+// columns are staged in LDS before they are written
 hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
-                                int waves, const UknJob* d_jobs,
-                                int64_t n_chunks, int chunk, int lds_bytes,
+                                int waves, const UknJob* d_jobs, int n_jobs,
+                                int64_t total, int group, int lds_bytes,
                                 int n_cu, hipStream_t st);
 hipError_t launch_evaluate(const GridDev& g, const LigDev* d_lig,
                            int waves, const float* xs, int64_t N,

@@ -152,11 +152,6 @@ __global__ __launch_bounds__(256) void k_sweep_tail(
 // numbers and take the same decision.  `stats`: count the attempt (once per
 // pair, by its lower state).
 #pragma clang fp contract(off)
-__device__ double state_energy_of(const LigDev& L, int k, const double* cp) {
-  double E = cp[0];
-  for (int c = 0; c < L.C; ++c) E += L.wd[k * L.C + c] * cp[1 + c];
-  return E;
-}
 
 // The neighbour pair (lo, hi) of state a in the exchange that ends sweep
 // s - 1, if that exchange is due and a has a partner.
@@ -185,17 +180,35 @@ __device__ __forceinline__ Pair own_pair(int K, int a, unsigned long long s,
 }
 
 // Metropolis decision on pair p from buffer `pin` (attempt_pair's expression
-// on the same numbers).
+// on the same numbers), every operand loaded before the arithmetic.
+template <int C>
 __device__ bool pair_accepts(const LigDev& L, Pair p, int pin,
                              unsigned long long s, uint64_t seed) {
-  const int C1 = 1 + L.C;
-  const double* clo = L.scomp + ((size_t)pin * L.K + p.lo) * C1;
-  const double* chi = L.scomp + ((size_t)pin * L.K + p.hi) * C1;
-  const double delta =
-      L.beta[p.lo] * (state_energy_of(L, p.lo, chi) -
-                      state_energy_of(L, p.lo, clo)) +
-      L.beta[p.hi] * (state_energy_of(L, p.hi, clo) -
-                      state_energy_of(L, p.hi, chi));
+  constexpr int C1 = 1 + C;
+  auto sc = BPMF_GMEM(const double, L.scomp);
+  auto wd = BPMF_GMEM(const double, L.wd);
+  double clo[C1], chi[C1], wlo[C], whi[C];
+#pragma unroll
+  for (int e = 0; e < C1; ++e) {
+    clo[e] = sc[((size_t)pin * L.K + p.lo) * C1 + e];
+    chi[e] = sc[((size_t)pin * L.K + p.hi) * C1 + e];
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    wlo[c] = wd[p.lo * C + c];
+    whi[c] = wd[p.hi * C + c];
+  }
+  const double blo = BPMF_GMEM(const double, L.beta)[p.lo];
+  const double bhi = BPMF_GMEM(const double, L.beta)[p.hi];
+  // E_k(x) = U0 + sum_c w_kc Psi_c, channels in order
+  auto energy = [](const double* w, const double* cp) {
+    double E = cp[0];
+#pragma unroll
+    for (int c = 0; c < C; ++c) E += w[c] * cp[1 + c];
+    return E;
+  };
+  const double delta = blo * (energy(wlo, chi) - energy(wlo, clo)) +
+                       bhi * (energy(whi, clo) - energy(whi, chi));
   const uint32_t purpose = (uint32_t)kExchange | (1u << 8);
   const U4 o = draw(seed, (uint32_t)p.lo, L.id, 0, s - 1ull, purpose);
   const double lnu = log(u01d(o.x));
@@ -207,7 +220,9 @@ __device__ int deferred_state(const LigDev& L, int a, unsigned long long s,
                               bool stats) {
   const Pair p = own_pair(L.K, a, s, exchange_every);
   if (!p.active) return a;
-  const bool ok = pair_accepts(L, p, pin, s, seed);
+  // the sweep kernels run 3 or 5 channels only
+  const bool ok = L.C == 5 ? pair_accepts<5>(L, p, pin, s, seed)
+                           : pair_accepts<3>(L, p, pin, s, seed);
   if (stats && a == p.lo) {
     atomicAdd(&L.ex_try[p.lo], 1ull);
     if (ok) atomicAdd(&L.ex_acc[p.lo], 1ull);
@@ -306,25 +321,28 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   int a = 0, pin = 0;
   bool pend = false;
   if (deferred) {
-    s = L.rcnt[r];
-    const int a0 = L.rsor[r], a1 = L.rsor[L.K + r];
-    const int p0 = L.rpend[r], p1 = L.rpend[L.K + r];
+    s = BPMF_GMEM(const unsigned long long, L.rcnt)[r];
+    auto rsor = BPMF_GMEM(const int, L.rsor);
+    auto rpend = BPMF_GMEM(const int, L.rpend);
+    const int a0 = rsor[r], a1 = rsor[L.K + r];
+    const int p0 = rpend[r], p1 = rpend[L.K + r];
     pin = (int)((s - 1ull) & 1ull);
     a = pin ? a1 : a0;
     pend = (pin ? p1 : p0) != 0;
   } else {
-    s = *L.counter;
-    a = L.state_of_replica[r];
+    s = *BPMF_GMEM(const unsigned long long, L.counter);
+    a = BPMF_GMEM(const int, L.state_of_replica)[r];
   }
-  const int fv = L.fvalid[r];
+  const int fv = BPMF_GMEM(const int, L.fvalid)[r];
   const bool owner = tid < n;
   float x[3], v[3], f[3];
-  const float m = owner ? L.mass[tid] : 0.f;
+  const float m = owner ? BPMF_GMEM(const float, L.mass)[tid] : 0.f;
   float sc[C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) sc[c] = owner ? L.scale[tid * C + c] : 0.f;
-  const float im = owner ? L.inv_mass[tid] : 0.f;
-  const float* xr = L.x + (size_t)r * n * 3;
+  for (int c = 0; c < C; ++c)
+    sc[c] = owner ? BPMF_GMEM(const float, L.scale)[tid * C + c] : 0.f;
+  const float im = owner ? BPMF_GMEM(const float, L.inv_mass)[tid] : 0.f;
+  auto xr = BPMF_GMEM(const float, L.x) + (size_t)r * n * 3;
 #pragma unroll
   for (int d = 0; d < 3; ++d) x[d] = owner ? xr[tid * 3 + d] : 0.f;
 
@@ -335,17 +353,21 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
                                      : Pair{a, a, false};
   const int kb = pr.active ? (a == pr.lo ? pr.hi : pr.lo) : a;
   float wa[C], wb[C];
+  auto wf = BPMF_GMEM(const float, L.wf);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    wa[c] = L.wf[a * C + c];
-    wb[c] = L.wf[kb * C + c];
+    wa[c] = wf[a * C + c];
+    wb[c] = wf[kb * C + c];
   }
-  const float Ta = L.Tf[a], Tb = L.Tf[kb];
-  const float dta = L.dtf[a], dtb = L.dtf[kb];
-  const double ba = L.beta[a], bb = L.beta[kb];
+  auto Tf = BPMF_GMEM(const float, L.Tf);
+  auto dtf = BPMF_GMEM(const float, L.dtf);
+  auto bt = BPMF_GMEM(const double, L.beta);
+  const float Ta = Tf[a], Tb = Tf[kb];
+  const float dta = dtf[a], dtb = dtf[kb];
+  const double ba = bt[a], bb = bt[kb];
   bool swap = false;
   if (pr.active) {
-    swap = pair_accepts(L, pr, pin, s, seed);
+    swap = pair_accepts<C>(L, pr, pin, s, seed);
     if (tid == 0 && a == pr.lo) {
       atomicAdd(&L.ex_try[pr.lo], 1ull);
       if (swap) atomicAdd(&L.ex_acc[pr.lo], 1ull);
@@ -369,16 +391,18 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   bool recorded = false;
   unsigned long long rec = 0ull;
   if (deferred && pend && record_due(s, tail.sample_every)) {
-    rec = L.rnrec[r];
+    rec = BPMF_GMEM(const unsigned long long, L.rnrec)[r];
     if (rec < (unsigned long long)L.cap) {
       recorded = true;
       if (owner)
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          L.samp_x[((size_t)rec * L.K + k) * n * 3 + tid * 3 + d] = x[d];
+          BPMF_GMEM(float, L.samp_x)[((size_t)rec * L.K + k) * n * 3 +
+                                     tid * 3 + d] = x[d];
       if (tid < C1)
-        L.samp_c[((size_t)rec * L.K + k) * C1 + tid] =
-            L.scomp[((size_t)pin * L.K + a) * C1 + tid];
+        BPMF_GMEM(double, L.samp_c)[((size_t)rec * L.K + k) * C1 + tid] =
+            BPMF_GMEM(const double, L.scomp)[((size_t)pin * L.K + a) * C1 +
+                                             tid];
     }
   }
   if (owner) {
@@ -403,14 +427,16 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   float* const fc_nxt = L.fcache + ((size_t)nxt * L.K + r) * n * kFC;
   double U0, KE0;
   if (fv > 0) {
-    const double* cp = deferred ? L.scomp + ((size_t)pin * L.K + a) * C1
-                                : L.comps + (size_t)r * C1;
+    auto cp = BPMF_GMEM(const double,
+                        deferred ? L.scomp + ((size_t)pin * L.K + a) * C1
+                                 : L.comps + (size_t)r * C1);
+    auto wd = BPMF_GMEM(const double, L.wd);
     U0 = cp[0];
 #pragma unroll
-    for (int c = 0; c < C; ++c) U0 += L.wd[k * C + c] * cp[1 + c];
+    for (int c = 0; c < C; ++c) U0 += wd[k * C + c] * cp[1 + c];
     if (owner) {
-      const float* ca = fc_cur + (size_t)tid * kFC;
-      const float* cr = L.frc + ((size_t)cur * L.K + r) * 4;
+      auto ca = BPMF_GMEM(const float, fc_cur + (size_t)tid * kFC);
+      auto cr = BPMF_GMEM(const float, L.frc + ((size_t)cur * L.K + r) * 4);
       float de[C][3], ge[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < C; ++c)
@@ -435,7 +461,8 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
         L.frc + ((size_t)cur * L.K + r) * 4);
     U0 = t0[0] + t0[1] + t0[2] + t0[3];
 #pragma unroll
-    for (int c = 0; c < C; ++c) U0 += L.wd[k * C + c] * t0[4 + c];
+    for (int c = 0; c < C; ++c)
+      U0 += BPMF_GMEM(const double, L.wd)[k * C + c] * t0[4 + c];
     KE0 = t0[4 + C] * 1e4;
   }
 
@@ -464,7 +491,8 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   for (int d = 0; d < 3; ++d) v[d] = fmaf(hk, f[d], v[d]);
   double U1 = t1[0] + t1[1] + t1[2] + t1[3];
 #pragma unroll
-  for (int c = 0; c < C; ++c) U1 += L.wd[k * C + c] * t1[4 + c];
+  for (int c = 0; c < C; ++c)
+    U1 += BPMF_GMEM(const double, L.wd)[k * C + c] * t1[4 + c];
   const float ke1 = 0.5f * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   const float bad =
       (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) ? 1.f : 0.f;
@@ -477,7 +505,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   const bool finite = isfinite(dH) && nbad == 0.0;
   const bool accept = finite && (lnu < -beta * dH);
   if (accept) {
-    float* xw = L.x + (size_t)r * n * 3;
+    auto xw = BPMF_GMEM(float, L.x) + (size_t)r * n * 3;
     if (owner)
 #pragma unroll
       for (int d = 0; d < 3; ++d) xw[tid * 3 + d] = x[d];
@@ -493,25 +521,27 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
       for (int c = 0; c < C; ++c)
         if (tid == 1 + c) cv = t1[4 + c];
     } else {
-      cv = L.scomp[((size_t)pin * L.K + a) * C1 + tid];
+      cv = BPMF_GMEM(const double, L.scomp)[((size_t)pin * L.K + a) * C1 +
+                                            tid];
     }
     if (deferred)
-      L.scomp[((size_t)(s & 1ull) * L.K + k) * C1 + tid] = cv;
+      BPMF_GMEM(double, L.scomp)[((size_t)(s & 1ull) * L.K + k) * C1 + tid] =
+          cv;
     else
-      L.comps[(size_t)r * C1 + tid] = cv;
+      BPMF_GMEM(double, L.comps)[(size_t)r * C1 + tid] = cv;
   }
   if (tid == 0) {
     // the stored parts of the replica's (new or kept) positions
-    L.fvalid[r] = 1 + (accept ? nxt : cur);
+    BPMF_GMEM(int, L.fvalid)[r] = 1 + (accept ? nxt : cur);
     atomicAdd(&L.hmc_try[k], 1ull);
     if (accept) atomicAdd(&L.hmc_acc[k], 1ull);
     if (!finite) atomicAdd(L.nonfinite, 1ull);
     if (deferred) {
       const int pout = (int)(s & 1ull);
-      L.rsor[pout * L.K + r] = k;
-      L.rpend[pout * L.K + r] = 1;
-      L.rcnt[r] = s + 1ull;
-      if (recorded) L.rnrec[r] = rec + 1ull;
+      BPMF_GMEM(int, L.rsor)[pout * L.K + r] = k;
+      BPMF_GMEM(int, L.rpend)[pout * L.K + r] = 1;
+      BPMF_GMEM(unsigned long long, L.rcnt)[r] = s + 1ull;
+      if (recorded) BPMF_GMEM(unsigned long long, L.rnrec)[r] = rec + 1ull;
     }
   }
 }
@@ -527,72 +557,99 @@ __global__ __launch_bounds__(256) void k_exchange(
 // of one or many ligands (Estimation), energy only
 // ----------------------------------------------------------------------------
 // One W-wave block evaluates one sample at a time, persistent over the
-// launch.  The work is the flat list of chunks of `chunk` consecutive
-// samples of one ligand (jobs sorted by first chunk, sentinel at n_jobs);
-// chunks are dealt out round-robin over XCD-major virtual block ids (blocks
-// are spread over the 8 XCDs round-robin), so the blocks of one XCD take
-// neighbouring chunks and its L2 assembles whole lines of each u_kn row.
-// Lane k of the block writes state k's entry of the sample's column.
+// launch: block b takes the b-th contiguous share of the flat sample index
+// over all jobs (job j's samples are [jobs[j].first, jobs[j+1].first); a
+// sentinel ends the list), so it stages a ligand's topology once per
+// segment.  Each sample's column (K entries) goes to LDS; every `group`
+// samples (at most 16: a 128-byte line of each row) the columns are written
+// out row by row by consecutive lanes.
 template <int C, int W>
 __global__ __launch_bounds__(W * kWave) void k_energy_matrix(
     GridDev g, const LigDev* __restrict__ ligs,
-    const UknJob* __restrict__ jobs, int64_t n_chunks, int chunk) {
+    const UknJob* __restrict__ jobs, int n_jobs, int64_t total,
+    int group) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
-  const int nb = gridDim.x;  // a multiple of 8
-  const int vb = (int)(blockIdx.x % 8) * (nb / 8) + (int)(blockIdx.x / 8);
   const float w0[C] = {};
-  int jn = 0;
-  for (int64_t ch = vb; ch < n_chunks; ch += nb) {
-    while (jobs[jn].chunk0 <= ch) ++jn;  // the sentinel stops the scan
-    // ligands and jobs come from restrict arguments: the u_kn stores
-    // cannot clobber them, so they load into scalar registers
-    const UknJob J = jobs[jn - 1];
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = b0 + per < total ? b0 + per : total;
+  if (b0 >= b1) return;
+  // ligands and jobs come from restrict arguments: the u_kn stores cannot
+  // clobber them, so they load into scalar registers
+  int j = 0, hi = n_jobs;  // jobs[j].first <= b0 < jobs[hi].first
+  while (hi - j > 1) {
+    const int mid = (j + hi) / 2;
+    if (jobs[mid].first <= b0) j = mid; else hi = mid;
+  }
+  typedef const float __attribute__((address_space(1))) gfloat;
+  typedef const double __attribute__((address_space(1))) gcdouble;
+  for (int64_t s = b0; s < b1; ++j) {
+    const UknJob J = jobs[j];
+    const int64_t e = jobs[j + 1].first < b1 ? jobs[j + 1].first : b1;
+    if (s >= e) continue;  // empty job
     const LigDev L = ligs[J.lig];
-    // topology staged per chunk (the chunk's samples share it); the barrier
-    // in carve also keeps the previous chunk's readers ahead of the copy
+    // topology staged for the segment; the barrier in carve also keeps the
+    // previous segment's readers ahead of the copy
     const Shared sh = carve<W>(smem, L, 0, tid);
-    // state weights and beta_k after the topology, for the expansion (the
-    // evaluation's first barrier orders these writes before their reads)
+    // state weights and beta_k after the topology, for the expansion, then
+    // the group's columns (the evaluation's first barrier orders these
+    // writes before their reads)
     const int K = L.K;
     double* ew = reinterpret_cast<double*>(
         smem + block_lds_bytes(W, false, L.n, L.nb, L.na, L.nt));
+    double* col = ew + K * (C + 1);
     for (int i = tid; i < K * (C + 1); i += W * kWave)
-      ew[i] = i < K * C ? L.wd[i] : L.beta[i - K * C];
+      ew[i] = i < K * C ? ((gcdouble*)L.wd)[i]
+                        : ((gcdouble*)L.beta)[i - K * C];
     // per-lane data through global (not flat) loads, so that the waits of
     // the evaluation's LDS reads do not wait on them
-    typedef const float __attribute__((address_space(1))) gfloat;
     const int n = L.n;
     const bool owner = tid < n;
-    const float m = owner ? ((const gfloat*)L.mass)[tid] : 0.f;
+    const float m = owner ? ((gfloat*)L.mass)[tid] : 0.f;
     float sc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      sc[c] = owner ? ((const gfloat*)L.scale)[tid * C + c] : 0.f;
-    const int64_t s0 = (ch - J.chunk0) * chunk;
-    const int64_t s1 = s0 + chunk < J.n ? s0 + chunk : J.n;
+      sc[c] = owner ? ((gfloat*)L.scale)[tid * C + c] : 0.f;
     const gfloat* xb = (const gfloat*)J.xs + (size_t)tid * 3;
     // positions of the next sample load during the current evaluation
     float xn[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xn[d] = owner ? xb[(size_t)s0 * n * 3 + d] : 0.f;
-    for (int64_t s = s0; s < s1; ++s) {
-      float x[3] = {xn[0], xn[1], xn[2]}, f[3];
-      if (s + 1 < s1) {
+    for (int d = 0; d < 3; ++d)
+      xn[d] = owner ? xb[(size_t)(s - J.first) * n * 3 + d] : 0.f;
+    for (; s < e;) {
+      const int64_t g1 = s + group < e ? s + group : e;
+      for (int64_t q = s; q < g1; ++q) {
+        float x[3] = {xn[0], xn[1], xn[2]}, f[3];
+        if (q + 1 < e) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          xn[d] = owner ? xb[(size_t)(s + 1) * n * 3 + d] : 0.f;
-      }
-      double t[6 + C];
-      eval_block<C, W, false, true>(g, L, w0, x, m, sc, f, t, 0.f, 0.f, sh,
-                                    tid);
-      const double U0 = t[0] + t[1] + t[2] + t[3];
-      for (int k = tid; k < K; k += W * kWave) {
-        double E = U0;
+          for (int d = 0; d < 3; ++d)
+            xn[d] = owner ? xb[(size_t)(q + 1 - J.first) * n * 3 + d] : 0.f;
+        }
+        double t[6 + C];
+        eval_block<C, W, false, true, true>(g, L, w0, x, m, sc, f, t, 0.f,
+                                            0.f, sh, tid);
+        const double U0 = t[0] + t[1] + t[2] + t[3];
+        double* cs = col + (q - s) * K;
+        for (int k = tid; k < K; k += W * kWave) {
+          double E = U0;
 #pragma unroll
-        for (int c = 0; c < C; ++c) E = fma(ew[k * C + c], t[4 + c], E);
-        J.ukn[(size_t)k * J.ld + s] = ew[K * C + k] * E;
+          for (int c = 0; c < C; ++c) E = fma(ew[k * C + c], t[4 + c], E);
+          cs[k] = ew[K * C + k] * E;
+        }
       }
+      // the group's columns: each row's run of consecutive samples written
+      // by consecutive lanes (global stores: no wait of the next LDS access
+      // depends on them)
+      block_sync();
+      const int cnt = (int)(g1 - s);
+      const int64_t n0 = s - J.first;
+      auto out = BPMF_GMEM(double, J.ukn);
+      for (int i = tid; i < cnt * K; i += W * kWave) {
+        const int k = i / cnt, qq = i - k * cnt;
+        out[(size_t)k * J.ld + n0 + qq] = col[qq * K + k];
+      }
+      s = g1;
     }
   }
 }
@@ -833,10 +890,10 @@ hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
 }
 
 hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
-                                int waves, const UknJob* d_jobs,
-                                int64_t n_chunks, int chunk, int lds_bytes,
+                                int waves, const UknJob* d_jobs, int n_jobs,
+                                int64_t total, int group, int lds_bytes,
                                 int n_cu, hipStream_t st) {
-  if (n_chunks <= 0) return hipSuccess;
+  if (total <= 0) return hipSuccess;
   BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
     auto kern = k_energy_matrix<C, W>;
     int per_cu = 0;
@@ -844,11 +901,10 @@ hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
         &per_cu, kern, W * kWave, lds_bytes);
     if (e != hipSuccess) return e;
     int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * n_cu;
-    const int64_t want = (n_chunks + 7) / 8 * 8;
-    if (blocks > want) blocks = want;
-    blocks = (blocks + 7) / 8 * 8;
+    if (blocks > total) blocks = total;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(W * kWave),
-                       lds_bytes, st, g, d_ligs, d_jobs, n_chunks, chunk);
+                       lds_bytes, st, g, d_ligs, d_jobs, n_jobs, total,
+                       group);
   }));
   return hipGetLastError();
 }
