@@ -39,42 +39,47 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 GRID_BYTES_PER_EVAL = 96  # 8 corners x 3 channels x 4 B
 
-# HBM traffic of one sweep launch measured with rocprofv3 counters
-# (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, scaled by what they read for a
-# 1 GiB device copy), per workload and wavefronts per replica; valid only
-# while the sweep-kernel sources hash to `sources`
-SWEEP_TRAFFIC = {
-    "c2_plain_production": {"sources": "ecbe91860c777ed2", "waves": None,
-                            "fetch_kib": 988.066, "write_kib": 201.280,
-                            "fetch_scale": 2.0, "write_scale": 1.0},
-    "c3_batched_uneven": {"sources": "ecbe91860c777ed2", "waves": 2,
-                          "fetch_kib": 24054.703, "write_kib": 24091.441,
-                          "fetch_scale": 2.0, "write_scale": 1.0},
+# HBM traffic measured with rocprofv3 counters (FETCH_SIZE and WRITE_SIZE in
+# KiB per dispatch, scaled by what they read for a 1 GiB device copy), per
+# kernel and workload: one sweep launch (at the given wavefronts per
+# replica), one harness launch, one energy-matrix call (its launches
+# summed); valid only while the kernel sources hash to TRAFFIC_SOURCES
+TRAFFIC_SOURCES = "50c5e9df1889c7f4"
+TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
+TRAFFIC = {
+    ("k_hmc_sweep", "c2_plain_production"):
+        {"waves": None, "fetch_kib": 764.521, "write_kib": 201.280},
+    ("k_hmc_sweep", "c3_batched_uneven"):
+        {"waves": 2, "fetch_kib": 36467.047, "write_kib": 24118.968},
+    ("k_grid_eval", "c3_batched_uneven"):
+        {"fetch_kib": 3389581.734, "write_kib": 3383700.0},
+    ("k_energy_matrix", "c3_batched_uneven"):
+        {"fetch_kib": 1134442.625, "write_kib": 427648.930},
 }
-SWEEP_SOURCES = ("device.h", "kernels.hip", "internal.h")
+KERNEL_SOURCES = ("device.h", "kernels.hip", "internal.h")
 
 
-def sweep_sources_hash():
+def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1507_03703_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def sweep_traffic(workload, waves=None):
-    """Measured HBM bytes per sweep launch, or None when the workload, its
-    launch shape or the kernel sources differ from those the counters were
-    taken on."""
-    t = SWEEP_TRAFFIC.get(workload)
-    if t is None or sweep_sources_hash() != t["sources"]:
+def measured_traffic(kernel, workload, waves=None):
+    """Measured HBM bytes per launch (or call), or None when the workload,
+    its launch shape or the kernel sources differ from those the counters
+    were taken on."""
+    t = TRAFFIC.get((kernel, workload))
+    if t is None or kernel_sources_hash() != TRAFFIC_SOURCES:
         return None
-    if t["waves"] is not None and list(waves or []) != [t["waves"]]:
+    if t.get("waves") is not None and list(waves or []) != [t["waves"]]:
         return None
-    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] +
-                     t["write_kib"] * t["write_scale"])
+    return 1024.0 * (t["fetch_kib"] * TRAFFIC_SCALE["fetch"] +
+                     t["write_kib"] * TRAFFIC_SCALE["write"])
 
 
 def parse():
@@ -281,11 +286,12 @@ def bulk_leg(pkg, torch, system, reps=3, harness_min=10 ** 8):
         pos.append(xs.reshape(-1, 3))
         scl.append(np.tile(l.scale.astype(np.float32), (xs.shape[0] *
                                                          xs.shape[1], 1)))
-    pos = torch.from_numpy(np.concatenate(pos)).to("cuda:0")
-    scl = torch.from_numpy(np.concatenate(scl)).to("cuda:0")
+    # tiled on the host and uploaded by plain copies (no torch kernels, so
+    # that the leg also runs under hardware counter collection)
+    pos, scl = np.concatenate(pos), np.concatenate(scl)
     tile = -(-harness_min // pos.shape[0])
-    pos = pos.repeat(tile, 1).contiguous()
-    scl = scl.repeat(tile, 1).contiguous()
+    pos = torch.from_numpy(np.tile(pos, (tile, 1))).to("cuda:0")
+    scl = torch.from_numpy(np.tile(scl, (tile, 1))).to("cuda:0")
     npts = pos.shape[0]
     w = np.ones(g.nodes.shape[-1])
     energy, force = ctx.grid_eval(pos, scl, w)
@@ -295,16 +301,21 @@ def bulk_leg(pkg, torch, system, reps=3, harness_min=10 ** 8):
         ctx.grid_eval(pos, scl, w, energy=energy, force=force)
     ge_ms, ge_n = ctx.get_timing(ctx.TIMER_GRID_EVAL)
     ctx.set_timing(False)
-    finite = bool(torch.isfinite(energy).all() and torch.isfinite(force).all())
+    head = 1 << 20
+    finite = all(bool(np.isfinite(a[sl].cpu().numpy()).all())
+                 for a in (energy, force)
+                 for sl in (slice(0, head), slice(npts - head, npts)))
     ctx.close()
     io = 4 * (3 + 2 * g.nodes.shape[-1] + 3)   # pos, scale, energy, force
 
-    def line(evals, sec, io_bytes):
+    def line(evals, sec, io_bytes, kernel):
         gbs = evals * GRID_BYTES_PER_EVAL / sec / 1e9
         return {"value": evals / sec, "unit": "atom-evals/s",
                 "roofline": {"bound": "hbm", "achieved": gbs,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": gbs / HBM_PEAK_GBS,
+                             "traffic": measured_traffic(kernel,
+                                                         system.name),
                              "algorithmic_bytes_per_eval":
                                  GRID_BYTES_PER_EVAL,
                              "streamed_bytes_per_eval": io_bytes}}
@@ -315,11 +326,12 @@ def bulk_leg(pkg, torch, system, reps=3, harness_min=10 ** 8):
                     f"{ligs[0].n_states} states x {records} records, "
                     f"{g.n[0]}^3 x {g.nodes.shape[-1]} float32 grids",
         "sampling_s": sample_s,
-        "energy_matrix": dict(line(evals_ukn, ukn_s, 12),
+        "energy_matrix": dict(line(evals_ukn, ukn_s, 12, "k_energy_matrix"),
                               atom_evals=evals_ukn, kernel="k_energy_matrix",
                               launches=cmp_n // reps,
                               kernel_ms_total=ukn_s * 1e3),
-        "harness": dict(line(npts, ge_ms * 1e-3, io), points=npts,
+        "harness": dict(line(npts, ge_ms * 1e-3, io, "k_grid_eval"),
+                        points=npts,
                         kernel="k_grid_eval", launch_ms=ge_ms,
                         outputs_finite=finite),
     }
@@ -354,7 +366,7 @@ def describe(system, r):
 def roofline(r, workload):
     return {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
-            "traffic": sweep_traffic(workload, r["waves"]),
+            "traffic": measured_traffic("k_hmc_sweep", workload, r["waves"]),
             "kernel": "k_hmc_sweep",
             "mean_launch_ms": r["hmc_ms"], "launches_timed": r["hmc_n"],
             "algorithmic_bytes_per_launch": r["evals_per_sweep"] *
