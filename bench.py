@@ -105,8 +105,9 @@ def parse():
     p.add_argument("--learned-only", action="store_true",
                    help="only the learned-proposal leg (with --long-sweeps, "
                         "--prod-sweeps, --train-steps)")
-    p.add_argument("--long-sweeps", type=int, default=200000)
-    p.add_argument("--prod-sweeps", type=int, default=50000)
+    p.add_argument("--long-sweeps", type=int, default=1000000)
+    p.add_argument("--prod-sweeps", type=int, default=300000)
+    p.add_argument("--burn-sweeps", type=int, default=100000)
     p.add_argument("--train-steps", type=int, default=4000)
     p.add_argument("--waves", type=int, default=None,
                    help="wavefronts per replica for every ligand instead of "
@@ -375,7 +376,8 @@ def roofline(r, workload):
 
 def stat_inefficiency(a):
     """g = 1 + 2 sum_t (1 - t/N) rho(t), summed while the normalised
-    autocorrelation rho stays positive (ESS = N / g)."""
+    autocorrelation rho stays positive (ESS = N / g); the lagged sums come
+    from one FFT."""
     import numpy as np
     a = np.asarray(a, np.float64)
     N = len(a)
@@ -383,13 +385,29 @@ def stat_inefficiency(a):
     var = float(d @ d) / N
     if N < 3 or var <= 0.0:
         return 1.0
-    g = 1.0
-    for t in range(1, N - 1):
-        rho = float(d[:N - t] @ d[t:]) / (N - t) / var
-        if rho <= 0.0:
-            break
-        g += 2.0 * rho * (1.0 - t / N)
+    m = 1 << int(np.ceil(np.log2(2 * N)))
+    f = np.fft.rfft(d, m)
+    lag = np.fft.irfft(f * np.conj(f), m)[:N - 1]   # sum_i d_i d_{i+t}
+    t = np.arange(1, N - 1)
+    rho = lag[1:] / (N - t) / var
+    stop = np.nonzero(rho <= 0.0)[0]
+    k = int(stop[0]) if len(stop) else len(rho)
+    g = 1.0 + 2.0 * float(np.sum(rho[:k] * (1.0 - t[:k] / N)))
     return max(g, 1.0)
+
+
+def batch_means_inefficiency(a, n_batches=30):
+    """g = b var(batch means) / var(a) over n_batches consecutive batches of
+    b samples: for slow observables, whose autocorrelation estimate turns
+    negative from noise long before it has decayed."""
+    import numpy as np
+    a = np.asarray(a, np.float64)
+    b = len(a) // n_batches
+    var = float(a.var())
+    if b < 2 or var <= 0.0:
+        return 1.0
+    means = a[:b * n_batches].reshape(n_batches, b).mean(axis=1)
+    return max(b * float(means.var(ddof=1)) / var, 1.0)
 
 
 def init_params(rng):
@@ -404,50 +422,70 @@ def init_params(rng):
 
 
 def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
-                long_sweeps=200000, prod_sweeps=50000):
+                long_sweeps=1000000, prod_sweeps=300000, n_blocks=10,
+                burn=100000):
     """Plain HMC vs HMC + learned independence pose moves on the 24-atom,
-    64-state system with the paper's soft-grid switching protocol.  A long
-    plain run gives the reference BPMF (its second half) and the 200k
-    coupled-state poses the network is trained on; both samplers then
-    continue from the long run's final state, and each reports its BPMF
-    error against the reference and the effective samples per second of
-    the coupled state."""
+    64-state system with the paper's soft-grid switching protocol.
+
+    After `burn` sweeps of equilibration, a long plain run (a record every
+    `sample_every` sweeps) gives the reference BPMF (MBAR over all its
+    records) with a batch-means standard error from `n_blocks` consecutive
+    blocks, and its coupled-state records are the poses the network is
+    trained on.  Both samplers then continue
+    from the long run's final state for `prod_sweeps` sweeps; each reports
+    its BPMF, the error against the reference, the spread of its own block
+    estimates, and effective samples per second of two observables of the
+    coupled state: its reduced potential (fast) and the distance of its
+    centre of mass from the site (the pose, which the learned move acts
+    on).  The BPMF's asymptotic MBAR error assumes independent samples; the
+    block estimates show how far slow modes make it understate the error."""
     import numpy as np
     import synth
     system = synth.make_system(4, grid_device="cuda:0")
     g, (lig,) = synth.add_soft_grids(system.grid, system.ligands)
     K, L, n = lig.n_states, system.n_leapfrog, lig.n_atoms
     every = system.sample_every
-    burn = 5000
+    mass = lig.mass / lig.mass.sum()
 
     def fresh(capacity):
         ctx = pkg.Context(seed=system.seed, device=0)
         ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
         return ctx, ctx.ligand_setup(lig, sample_capacity=capacity)
 
-    def estimate(ctx, lid, n_rec, xs=None):
-        u = ctx.energy_matrix(lid, xs, n_samples=n_rec * K)
+    def estimate(ctx, lid, n_rec, blocks):
+        """BPMF over all records, the BPMF of `blocks` consecutive blocks
+        (one batched MBAR call) and the coupled state's observables."""
+        u = ctx.energy_matrix(lid, None, n_samples=n_rec * K)
         f, var, _ = ctx.mbar(u, np.full(K, n_rec), tol=1e-10, max_iter=200)
-        # coupled state's reduced potential on its own samples (round-major)
-        obs = u[K - 1, K - 1::K].cpu().numpy()
-        gi = stat_inefficiency(obs)
-        return float(f[-1] - f[0]), float(np.sqrt(max(var[-1], 0.0))), \
-            n_rec / gi, gi
+        per = n_rec // blocks
+        parts = [u[:, b * per * K:(b + 1) * per * K] for b in range(blocks)]
+        fb = ctx.mbar_batch(parts, [np.full(K, per)] * blocks, tol=1e-10,
+                            max_iter=200)
+        blk = np.array([r[0][-1] - r[0][0] for r in fb])
+        # the coupled state's reduced potential on its own samples
+        # (round-major) and its pose: centre-of-mass distance from the site
+        pot = u[K - 1, K - 1::K].cpu().numpy()
+        xs, _ = ctx.get_samples(lid)
+        com = (xs[:, K - 1].astype(np.float64) * mass[None, :, None]).sum(1)
+        dist = np.linalg.norm(com - lig.site_center[None, :], axis=1)
+        return dict(bpmf=float(f[-1] - f[0]),
+                    sigma_mbar=float(np.sqrt(max(var[-1], 0.0))),
+                    blocks=blk, block_sd=float(blk.std(ddof=1)),
+                    g_pot=stat_inefficiency(pot),
+                    g_pose=batch_means_inefficiency(dist), n_rec=n_rec), xs
 
     # long plain run: reference BPMF and training poses
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx, lid = fresh(long_sweeps)
+    long_rec = long_sweeps // every
+    ctx, lid = fresh(long_rec)
     ctx.hmc_sweep(burn, L, exchange_every=1)
-    ctx.hmc_sweep(long_sweeps, L, exchange_every=1, sample_every=1)
+    ctx.hmc_sweep(long_sweeps, L, exchange_every=1, sample_every=every)
     torch.cuda.synchronize()
     long_s = time.perf_counter() - t0
-    xs, _ = ctx.get_samples(lid)                   # (rounds, K, n, 3)
     final = ctx.get_replicas(lid)
-    half = torch.as_tensor(np.ascontiguousarray(
-        xs[long_sweeps // 2::20]).reshape(-1, n, 3), device="cuda:0")
-    ref, ref_sd, _, _ = estimate(ctx, lid, half.shape[0] // K, half)
-    del half
+    ref, xs = estimate(ctx, lid, long_rec, n_blocks)
+    ref_se = ref["block_sd"] / np.sqrt(n_blocks)
     poses_x = torch.as_tensor(np.ascontiguousarray(xs[:, K - 1]),
                               device="cuda:0")
     del xs
@@ -482,11 +520,18 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
                       pose_move_every=pose_every if learned else 0)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        b, sd, ess, gi = estimate(ctx, lid, records)
-        out = dict(seconds=el, bpmf_kT=b, sigma_kT=sd,
-                   error_vs_long_run_kT=abs(b - ref),
-                   within_1kT=bool(abs(b - ref) <= 1.0), ess=ess,
-                   stat_inefficiency=gi, ess_per_s=ess / el)
+        e, _ = estimate(ctx, lid, records, 5)
+        err = abs(e["bpmf"] - ref["bpmf"])
+        out = dict(seconds=el, bpmf_kT=e["bpmf"],
+                   sigma_mbar_kT=e["sigma_mbar"],
+                   block_sd_kT=e["block_sd"],
+                   error_vs_long_run_kT=err, within_1kT=bool(err <= 1.0),
+                   stat_inefficiency_potential=e["g_pot"],
+                   stat_inefficiency_pose=e["g_pose"],
+                   ess_potential=records / e["g_pot"],
+                   ess_pose=records / e["g_pose"],
+                   ess_per_s=records / e["g_pot"] / el,
+                   ess_pose_per_s=records / e["g_pose"] / el)
         if learned:
             ps = ctx.get_pose_stats(lid)
             out["pose_acceptance"] = float(ps["acc"].sum() /
@@ -502,17 +547,27 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
         "workload": f"{system.name} with the soft-grid switching protocol "
                     f"(5 channels): {n}-atom ligand, {g.n[0]}^3 grids, {K} "
                     f"replicas, {prod_sweeps} sweeps x {L} leapfrog steps "
-                    f"from the equilibrated end of a {long_sweeps}-sweep "
-                    f"plain run, a sample per state every {every}; learned: "
-                    f"one independence pose move per replica every "
+                    f"from the end of a {burn}-sweep burn-in and a "
+                    f"{long_sweeps}-sweep plain run, a "
+                    f"sample per state every {every}; learned: one "
+                    f"independence pose move per replica every "
                     f"{pose_every} sweeps (captured with the sweeps)",
-        "ess_observable": "reduced potential of the fully coupled state on "
-                          "its own samples",
-        "reference": {"sweeps": long_sweeps, "seconds": long_s,
-                      "bpmf_kT": ref, "sigma_kT": ref_sd,
-                      "estimated_on": "second half, every 20th round"},
+        "ess_observables": "coupled state: reduced potential on its own "
+                           "samples (initial positive autocorrelation sum); "
+                           "centre-of-mass distance from the site (batch "
+                           "means over 30 batches)",
+        "reference": {"burn_in_sweeps": burn, "sweeps": long_sweeps,
+                      "seconds": long_s,
+                      "bpmf_kT": ref["bpmf"],
+                      "sigma_mbar_kT": ref["sigma_mbar"],
+                      "block_bpmf_kT": [float(v) for v in ref["blocks"]],
+                      "block_sd_kT": ref["block_sd"],
+                      "standard_error_kT": float(ref_se),
+                      "stat_inefficiency_pose": ref["g_pose"]},
         "plain": plain, "learned": learned,
         "ess_per_s_ratio": learned["ess_per_s"] / plain["ess_per_s"],
+        "ess_pose_per_s_ratio": learned["ess_pose_per_s"] /
+                                plain["ess_pose_per_s"],
         "training": {"poses": n_poses, "steps": train_steps, "batch": 512,
                      "train_s": train_s,
                      "loss_first": float(np.mean(losses[:20])),
@@ -544,6 +599,7 @@ def main():
 
     if args.learned_only:
         print(json.dumps(learned_leg(pkg, torch, train_steps=args.train_steps,
+                                     burn=args.burn_sweeps,
                                      long_sweeps=args.long_sweeps,
                                      prod_sweeps=args.prod_sweeps)))
         return
@@ -598,7 +654,7 @@ def main():
         out["bulk_interpolation"] = bulk()
     if args.learned:
         out["learned_proposal"] = learned_leg(
-            pkg, torch, train_steps=args.train_steps,
+            pkg, torch, train_steps=args.train_steps, burn=args.burn_sweeps,
             long_sweeps=args.long_sweeps, prod_sweeps=args.prod_sweeps)
     print(json.dumps(out))
 
