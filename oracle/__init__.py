@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 R_GAS = 8.314462618e-3  # kJ/(mol K)
 
 P_MOMENTA, P_ACCEPT, P_EXCHANGE, P_POSE = 1, 2, 3, 4
+P_EXTERNAL = 6
 
 
 def build(force: bool = True) -> str:
@@ -95,6 +96,8 @@ def lib():
         L.ora_grid_points.argtypes = [vp, C.c_int64, dp, dp, dp, dp, dp]
         L.ora_energy_batch.argtypes = [vp, vp, C.c_int64, dp, dp, dp, dp, dp]
         L.ora_normals3.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int,
+                                   C.c_uint64, C.c_uint32, dp]
+        L.ora_uniform4.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int,
                                    C.c_uint64, C.c_uint32, dp]
         L.ora_dihedral.argtypes = [dp, dp, dp, dp]
         L.ora_dihedral.restype = C.c_double
@@ -183,6 +186,13 @@ def philox(ctr, key):
 
 def uniform(seed, index, lig, rep, sweep, purpose):
     return lib().ora_uniform(seed, index, lig, rep, sweep, purpose)
+
+
+def uniform4(seed, index, lig, rep, sweep, purpose):
+    u = np.zeros(4)
+    lib().ora_uniform4(seed, index, lig, rep, sweep, purpose,
+                       _p(u, C.c_double))
+    return u
 
 
 def normals3(seed, index, lig, rep, sweep, purpose):

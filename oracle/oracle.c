@@ -585,6 +585,14 @@ void ora_energy_batch(const ora_grid* g, const ora_ligand* L, int64_t N,
 
 /* three standard normals from the counter-based stream (Box-Muller), the
  * draw the samplers use for any purpose */
+/* the four uniforms in (0, 1] of one draw */
+void ora_uniform4(uint64_t seed, uint32_t index, int lig, int rep,
+                  uint64_t sweep, uint32_t purpose, double* u) {
+  uint32_t o[4];
+  draw(seed, index, lig, rep, sweep, purpose, o);
+  for (int i = 0; i < 4; ++i) u[i] = u01(o[i]);
+}
+
 void ora_normals3(uint64_t seed, uint32_t index, int lig, int rep,
                   uint64_t sweep, uint32_t purpose, double* z) {
   uint32_t o[4];
