@@ -189,6 +189,11 @@ typedef struct {
   int pose_move_every; /* 0 = never; else after the call's sweeps P, 2P, ...
                           one pose move (bpmf_pose_move) of every ligand with
                           a proposal */
+  int external_moves;  /* 0 = none; else after every unit (P sweeps, or one
+                          sweep when pose_move_every = 0) this many external
+                          moves (bpmf_external_move) of every ligand */
+  int external_k_max;  /* states 0..external_k_max-1 take external moves */
+  double external_sigma; /* translation per axis (A), > 0 when used */
 } bpmf_sweep_args;
 
 /* Run n_sweeps sweeps over every ligand.  One sweep of a ligand with
@@ -207,8 +212,14 @@ typedef struct {
  * With pose_move_every = P > 0 the call runs units of P sweeps, each
  * closed by one independence pose move per replica of every ligand that has
  * a proposal (the moves see the state after the unit's last exchange and
- * record); sweeps past the last whole unit run without a move.  One unit is
- * captured as a hipGraph and replayed (see bpmf_set_graph).
+ * record); sweeps past the last whole unit run without a move.  With
+ * external_moves = n > 0 every unit (of P sweeps, or of one sweep when P =
+ * 0) is closed, after its pose move, by n external moves per replica in the
+ * states below external_k_max (Sampling: the paper attempts them in the
+ * states whose grid coupling is below 0.01, after each HMC move; here they
+ * follow the unit's exchange, an equally valid order of moves that each
+ * keep the target).  One unit is captured as a hipGraph and replayed (see
+ * bpmf_set_graph).
  * Random numbers: Philox-4x32-10 keyed by the context seed, counter
  * (index, ligand<<16 | replica, s, purpose) with purpose 1 = momenta
  * (index = atom), 2 = acceptance (index 0), 3 | sep<<8 = exchange
@@ -422,6 +433,33 @@ BPMF_API int bpmf_proposal_train(bpmf_ctx* ctx, int ligand_id,
  * numbers: Philox purpose 4, index 0 (component), 1 and 2 (normals of t and
  * omega), 3 (acceptance). */
 BPMF_API int bpmf_pose_move(bpmf_ctx* ctx, int ligand_id, int rounds);
+
+/* ------------------------------------------------------------------------
+ * External-coordinate moves (Sampling: external coordinate Markov chain
+ * Monte Carlo)
+ * ------------------------------------------------------------------------ */
+
+/* n_moves external moves in a row of every replica of the ligand (-1 =
+ * every ligand) whose state is below k_max, at the current sweep counter s
+ * (not advanced; calls at the same s repeat their random numbers).  A move
+ * rotates the ligand rigidly about its (mass-weighted) centre of mass by
+ * the rotation of a uniform random unit quaternion -- with uniforms u1, u2,
+ * u3: (w, x, y, z) = (sqrt(u1) cos 2 pi u3, sqrt(1-u1) sin 2 pi u2,
+ * sqrt(1-u1) cos 2 pi u2, sqrt(u1) sin 2 pi u3) -- translates it by sigma z
+ * (z standard normal per axis; the paper uses 0.6 A) and is accepted iff
+ * ln u < -(U_k(x') - U_k(x)) / (R T_k), energies in double; the proposal is
+ * symmetric.  Accepted moves update the positions and cached components.
+ * Random numbers: Philox purpose 6, index 3m (u1, u2, u3 of move m), 3m + 1
+ * (the three normals), 3m + 2 (acceptance, first word).
+ * Errors: BPMF_E_INVAL (n_moves < 0, k_max < 0, sigma not positive and
+ * finite). */
+BPMF_API int bpmf_external_move(bpmf_ctx* ctx, int ligand_id, int n_moves,
+                                int k_max, double sigma);
+
+/* Attempted and accepted external moves per state (host arrays of K, may
+ * be NULL). */
+BPMF_API int bpmf_get_external_stats(bpmf_ctx* ctx, int ligand_id,
+                                     int64_t* accepted, int64_t* tried);
 
 /* Pose-move counts per state (host, K each) and ln alpha of each replica's
  * last move (host, K); any output may be NULL. */

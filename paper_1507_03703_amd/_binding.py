@@ -48,7 +48,8 @@ class _SweepArgs(C.Structure):
     _fields_ = [("n_sweeps", C.c_int), ("n_leapfrog", C.c_int),
                 ("exchange_every", C.c_int), ("exchange_scheme", C.c_int),
                 ("max_sep", C.c_int), ("sample_every", C.c_int),
-                ("pose_move_every", C.c_int)]
+                ("pose_move_every", C.c_int), ("external_moves", C.c_int),
+                ("external_k_max", C.c_int), ("external_sigma", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -122,6 +123,8 @@ def library():
                                 C.c_int, C.c_double, dp],
         "bpmf_pose_move": [vp, C.c_int, C.c_int],
         "bpmf_get_pose_stats": [vp, C.c_int, i64p, i64p, dp],
+        "bpmf_external_move": [vp, C.c_int, C.c_int, C.c_int, C.c_double],
+        "bpmf_get_external_stats": [vp, C.c_int, i64p, i64p],
         "bpmf_get_waves": [vp, C.c_int, ip],
         "bpmf_get_timing": [vp, C.c_int, dp, i64p],
         "bpmf_version": [],
@@ -254,10 +257,12 @@ class Context:
     # -- sampling -------------------------------------------------------------
     def hmc_sweep(self, n_sweeps, n_leapfrog, exchange_every=1,
                   exchange_scheme=0, max_sep=1, sample_every=0,
-                  pose_move_every=0):
+                  pose_move_every=0, external_moves=0, external_k_max=0,
+                  external_sigma=0.6):
         a = _SweepArgs(int(n_sweeps), int(n_leapfrog), int(exchange_every),
                        int(exchange_scheme), int(max_sep), int(sample_every),
-                       int(pose_move_every))
+                       int(pose_move_every), int(external_moves),
+                       int(external_k_max), float(external_sigma))
         _check(self._lib.bpmf_hmc_sweep(self._h, C.byref(a)))
 
     def exchange(self, ligand_id=-1, scheme=0, max_sep=1):
@@ -527,6 +532,21 @@ class Context:
 
     def pose_move(self, ligand_id=-1, rounds=1):
         _check(self._lib.bpmf_pose_move(self._h, int(ligand_id), int(rounds)))
+
+    def external_move(self, ligand_id=-1, n_moves=1, k_max=1, sigma=0.6):
+        """n_moves external moves of every replica in states < k_max."""
+        _check(self._lib.bpmf_external_move(self._h, int(ligand_id),
+                                            int(n_moves), int(k_max),
+                                            float(sigma)))
+
+    def get_external_stats(self, ligand_id):
+        K = self.ligands[ligand_id]["K"]
+        a = np.zeros(K, np.int64)
+        t = np.zeros(K, np.int64)
+        p = lambda v: v.ctypes.data_as(C.POINTER(C.c_int64))  # noqa: E731
+        _check(self._lib.bpmf_get_external_stats(self._h, int(ligand_id),
+                                                 p(a), p(t)))
+        return dict(acc=a, tries=t)
 
     def get_pose_stats(self, ligand_id):
         K = self.ligands[ligand_id]["K"]

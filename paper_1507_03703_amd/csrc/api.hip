@@ -13,6 +13,7 @@
 
 #include "../../include/bpmf.h"
 #include "internal.h"
+#include "moves.h"
 #include "mlp.h"
 
 using namespace bpmf;
@@ -63,6 +64,9 @@ struct LigHost {
   uint64_t counter;   // host mirror of *dev.counter
   int64_t n_rec;      // host mirror of *dev.n_rec
   std::vector<double> beta, wd;
+  // external-move statistics per state (in the arena's state region)
+  unsigned long long* ext_acc = nullptr;
+  unsigned long long* ext_try = nullptr;
   // learned pose proposal (bpmf_proposal_setup)
   bool has_prop = false;
   void* prop_arena = nullptr;
@@ -125,7 +129,8 @@ struct bpmf_ctx {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   uint64_t table_version = 0, graph_version = ~0ull;
-  int graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int kKey = 12;
+  int graph_key[kKey] = {0};
 
   void drop_graph() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -609,6 +614,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_scomp = A.add((size_t)2 * K * C1 * 8),
                o_fcache = A.add((size_t)2 * K * n * (3 + 3 * C) * 4),
                o_frc = A.add((size_t)2 * K * 4 * 4), o_fvalid = A.add(K * 4),
+               o_xacc = A.add(K * 8), o_xtry = A.add(K * 8),
                o_sx = A.add((size_t)cap * K * n * 12),
                o_sc = A.add((size_t)cap * K * C1 * 8);
   {
@@ -711,6 +717,8 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.samp_c = (double*)(base + o_sc);
   h.arena = base;
   h.state_bytes = o_sx;
+  h.ext_acc = (unsigned long long*)(base + o_xacc);
+  h.ext_try = (unsigned long long*)(base + o_xtry);
   h.min_waves = min_waves;
   h.sweep_waves = min_waves;
   h.counter = 0;
@@ -741,6 +749,9 @@ struct MlpBufs {
 };
 int mlp_scratch(bpmf_ctx* c, int B, MlpBufs* b);
 int pose_move_ligand(bpmf_ctx* c, int lid, hipStream_t st);
+int external_move_ligand(bpmf_ctx* c, int lid, int n_moves, int k_max,
+                         double sigma, hipStream_t st);
+int check_external(int n_moves, int k_max, double sigma);
 }  // namespace
 
 // ============================================================================
@@ -762,6 +773,9 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     return fail(BPMF_E_INVAL, "max_sep must be >= 1");
   if (a->pose_move_every < 0)
     return fail(BPMF_E_INVAL, "pose_move_every must be >= 0");
+  if ((rc = check_external(a->external_moves, a->external_k_max,
+                           a->external_sigma)))
+    return rc;
   // sample capacity check (host mirrors of the device counters)
   std::vector<int64_t> add(c->ligs.size(), 0);
   if (a->sample_every > 0) {
@@ -799,7 +813,9 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     return BPMF_OK;
   };
   if (a->n_sweeps == 0) return BPMF_OK;
-  const int P = a->pose_move_every;
+  // units of P sweeps closed by pose moves and/or external moves
+  const int NX = a->external_moves;
+  const int P = a->pose_move_every > 0 ? a->pose_move_every : (NX > 0 ? 1 : 0);
   // a run of `count` sweeps with its exchange/record bookkeeping
   auto enqueue_run = [&](hipStream_t st, int count) -> int {
     if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(c->d_ligs, nl, st));
@@ -812,11 +828,19 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
                                   tail.sample_every, c->seed, st));
     return BPMF_OK;
   };
-  // one pose move of every ligand that has a proposal
+  // one pose move of every ligand that has a proposal (when asked), then
+  // the external moves of every ligand
   auto enqueue_pose = [&](hipStream_t st) -> int {
-    for (int l = 0; l < nl; ++l)
-      if (c->ligs[l].has_prop) {
-        const int r = pose_move_ligand(c, l, st);
+    if (a->pose_move_every > 0)
+      for (int l = 0; l < nl; ++l)
+        if (c->ligs[l].has_prop) {
+          const int r = pose_move_ligand(c, l, st);
+          if (r) return r;
+        }
+    if (NX > 0)
+      for (int l = 0; l < nl; ++l) {
+        const int r = external_move_ligand(c, l, NX, a->external_k_max,
+                                           a->external_sigma, st);
         if (r) return r;
       }
     return BPMF_OK;
@@ -824,7 +848,7 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
   // (re)capture `fn` into the context's graph under `key`; the kernels read
   // every per-sweep quantity (counters, state maps) from device memory, so
   // one capture replays unchanged
-  auto ensure_graph = [&](const int (&key)[8], auto&& fn) -> int {
+  auto ensure_graph = [&](const int (&key)[bpmf_ctx::kKey], auto&& fn) -> int {
     if (c->graph_exec && c->graph_version == c->table_version &&
         memcmp(key, c->graph_key, sizeof(key)) == 0)
       return BPMF_OK;
@@ -859,11 +883,11 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
   };
   const int chunk = c->graph_chunk;
   if (P > 0) {
-    // units of P sweeps, each followed by a pose move; the network's
+    // units of P sweeps, each followed by the unit's moves; the network's
     // scratch is sized before any capture
     int maxK = 0;
     for (auto& h : c->ligs)
-      if (h.has_prop) maxK = std::max(maxK, h.dev.K);
+      if (h.has_prop && a->pose_move_every > 0) maxK = std::max(maxK, h.dev.K);
     if (maxK > 0) {
       MlpBufs b;
       if ((rc = mlp_scratch(c, maxK, &b))) return rc;
@@ -874,8 +898,12 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
       return r ? r : enqueue_pose(st);
     };
     if (chunk > 0 && units > 0) {
-      const int key[8] = {a->n_leapfrog, a->exchange_every, a->exchange_scheme,
-                          a->max_sep, a->sample_every, 0, P, 1};
+      int sg[2];
+      memcpy(sg, &a->external_sigma, sizeof(sg));
+      const int key[bpmf_ctx::kKey] = {
+          a->n_leapfrog, a->exchange_every, a->exchange_scheme, a->max_sep,
+          a->sample_every, 0, P, a->pose_move_every, NX, a->external_k_max,
+          sg[0], sg[1]};
       if ((rc = ensure_graph(key, unit))) return rc;
       for (int u = 0; u < units; ++u)
         if ((rc = launch_timed(P, [&]() -> int {
@@ -894,8 +922,9 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(c->d_ligs, nl, c->stream));
     int done = 0;
     if (chunk > 0 && a->n_sweeps >= chunk) {
-      const int key[8] = {a->n_leapfrog, a->exchange_every, a->exchange_scheme,
-                          a->max_sep, a->sample_every, chunk, 0, 0};
+      const int key[bpmf_ctx::kKey] = {
+          a->n_leapfrog, a->exchange_every, a->exchange_scheme, a->max_sep,
+          a->sample_every, chunk, 0, 0, 0, 0, 0, -1};
       if ((rc = ensure_graph(key, [&](hipStream_t st) -> int {
              for (int s = 0; s < chunk; ++s) {
                const int r = enqueue_sweep(st);
@@ -1938,6 +1967,64 @@ extern "C" int bpmf_pose_move(bpmf_ctx* c, int lid, int rounds) {
       if (!c->ligs[l].has_prop) continue;
       if ((rc = pose_move_ligand(c, (int)l, c->stream))) return rc;
     }
+  return BPMF_OK;
+}
+
+// ============================================================================
+// external-coordinate moves
+// ============================================================================
+namespace {
+int external_move_ligand(bpmf_ctx* c, int lid, int n_moves, int k_max,
+                         double sigma, hipStream_t st) {
+  LigHost& h = c->ligs[lid];
+  HIP_TRY(launch_external_move(c->grid, c->d_ligs + lid, h.dev.K, h.min_waves,
+                               n_moves, std::min(k_max, h.dev.K),
+                               (float)sigma, h.ext_acc, h.ext_try,
+                               lds_of(h, h.min_waves, false), c->seed, st));
+  return BPMF_OK;
+}
+
+int check_external(int n_moves, int k_max, double sigma) {
+  if (n_moves < 0) return fail(BPMF_E_INVAL, "negative n_moves");
+  if (k_max < 0) return fail(BPMF_E_INVAL, "negative k_max");
+  if (n_moves > 0 && !(sigma > 0 && std::isfinite(sigma)))
+    return fail(BPMF_E_INVAL, "translation sigma must be positive and finite");
+  return BPMF_OK;
+}
+}  // namespace
+
+extern "C" int bpmf_external_move(bpmf_ctx* c, int lid, int n_moves,
+                                  int k_max, double sigma) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (lid != -1 && (rc = check_lig(c, lid))) return rc;
+  if ((rc = check_external(n_moves, k_max, sigma))) return rc;
+  for (size_t l = 0; l < c->ligs.size(); ++l) {
+    if (lid != -1 && (int)l != lid) continue;
+    if ((rc = external_move_ligand(c, (int)l, n_moves, k_max, sigma,
+                                   c->stream)))
+      return rc;
+  }
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_get_external_stats(bpmf_ctx* c, int lid, int64_t* acc,
+                                       int64_t* tries) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, lid))) return rc;
+  const LigHost& h = c->ligs[lid];
+  const int K = h.dev.K;
+  std::vector<unsigned long long> a(K), t(K);
+  HIP_TRY(hipMemcpyAsync(a.data(), h.ext_acc, K * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(t.data(), h.ext_try, K * 8, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < K; ++k) {
+    if (acc) acc[k] = (int64_t)a[k];
+    if (tries) tries[k] = (int64_t)t[k];
+  }
   return BPMF_OK;
 }
 

@@ -1,0 +1,201 @@
+// External-coordinate Monte Carlo moves of the ligand (Sampling: external
+// coordinate Markov chain Monte Carlo).  A move rotates the ligand rigidly
+// about its centre of mass by the rotation of a random unit quaternion,
+// translates it by sigma z (z standard normal per axis; the paper uses
+// sigma = 0.6 A) and is accepted by the Metropolis criterion at the
+// replica's state.  The proposal is symmetric (the rotation is uniform on
+// SO(3), so a rotation and its inverse are equally likely, and so are t and
+// -t), so no proposal-density ratio enters.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "device.h"
+#include "internal.h"
+#include "moves.h"
+
+namespace bpmf {
+
+namespace {
+
+// One workgroup of W waves per replica; replicas in states >= k_max return
+// at once (the paper attempts the moves only where the grids are nearly
+// off).  Move m of the call uses Philox draw 3m (three uniforms: the
+// quaternion by Shoemake's construction), 3m + 1 (three normals: the
+// translation) and 3m + 2 (the acceptance uniform), keyed by the ligand,
+// the replica and the sweep counter.
+template <int C, int W>
+__global__ __launch_bounds__(W * kWave) void k_external_move(
+    GridDev g, const LigDev* __restrict__ lig, int n_moves, int k_max,
+    float sigma, unsigned long long* __restrict__ acc_k,
+    unsigned long long* __restrict__ try_k, uint64_t seed) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float sR[9], sc0[3], st[3];
+  __shared__ double s_cp[4 * W];
+  __shared__ int s_acc;
+  const LigDev L = *lig;
+  const int tid = threadIdx.x;
+  const int r = blockIdx.x;
+  const int n = L.n;
+  const int k = L.state_of_replica[r];
+  if (k >= k_max || n_moves <= 0) return;  // uniform over the block
+  const unsigned long long s = *L.counter;
+  Shared sh;
+  {
+    sh.pos = reinterpret_cast<float4*>(smem);
+    sh.red = reinterpret_cast<double*>(smem + 16 * kWave * W);
+    sh.com = reinterpret_cast<float*>(smem + 16 * kWave * W + 8 * W * kRedMax);
+    const int acc0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
+    sh.sl = Slots{reinterpret_cast<unsigned int*>(smem + acc0)};
+    stage_topology(L, smem + acc0, sh, tid, W * kWave);
+    __syncthreads();
+  }
+  const bool owner = tid < n;
+  float x[3] = {0.f, 0.f, 0.f}, f[3];
+  if (owner)
+    for (int d = 0; d < 3; ++d) x[d] = L.x[(size_t)r * n * 3 + 3 * tid + d];
+  const float m = owner ? L.mass[tid] : 0.f;
+  float sc[C], w[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    sc[c] = owner ? L.scale[tid * C + c] : 0.f;
+    w[c] = L.wf[k * C + c];
+  }
+  const double beta = L.beta[k];
+  // energy and components of the current configuration (stored)
+  double comp[1 + C];
+  {
+    const double* cp = L.comps + (size_t)r * (1 + C);
+#pragma unroll
+    for (int e = 0; e <= C; ++e) comp[e] = cp[e];
+  }
+  double e_cur = comp[0];
+#pragma unroll
+  for (int c = 0; c < C; ++c) e_cur += L.wd[k * C + c] * comp[1 + c];
+  bool moved = false;
+  for (int mv = 0; mv < n_moves; ++mv) {
+    // centre of mass in double (fixed-order: wave sums, then waves)
+    {
+      const double mi = (double)m;
+      const double cx = wave_sum(mi * x[0]), cy = wave_sum(mi * x[1]);
+      const double cz = wave_sum(mi * x[2]), cm = wave_sum(mi);
+      if ((tid & (kWave - 1)) == 0) {
+        const int wv = tid >> 6;
+        s_cp[4 * wv] = cx;
+        s_cp[4 * wv + 1] = cy;
+        s_cp[4 * wv + 2] = cz;
+        s_cp[4 * wv + 3] = cm;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double c[3] = {0.0, 0.0, 0.0}, M = 0.0;
+      for (int q = 0; q < W; ++q) {
+        for (int d = 0; d < 3; ++d) c[d] += s_cp[4 * q + d];
+        M += s_cp[4 * q + 3];
+      }
+      // uniform unit quaternion (w, x, y, z) from three uniforms
+      const U4 o = draw(seed, 3u * mv, L.id, r, s, kExternal);
+      const double u1 = u01d(o.x), u2 = u01d(o.y), u3 = u01d(o.z);
+      const double a = sqrt(1.0 - u1), b = sqrt(u1);
+      double s2, c2, s3, c3;
+      sincos(2.0 * M_PI * u2, &s2, &c2);
+      sincos(2.0 * M_PI * u3, &s3, &c3);
+      const double qw = b * c3, qx = a * s2, qy = a * c2, qz = b * s3;
+      const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qz * qw),
+                           2 * (qx * qz + qy * qw),     2 * (qx * qy + qz * qw),
+                           1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qx * qw),
+                           2 * (qx * qz - qy * qw),     2 * (qy * qz + qx * qw),
+                           1 - 2 * (qx * qx + qy * qy)};
+      for (int e = 0; e < 9; ++e) sR[e] = (float)R[e];
+      float z[3];
+      normals3(draw(seed, 3u * mv + 1u, L.id, r, s, kExternal), z[0], z[1],
+               z[2]);
+      for (int d = 0; d < 3; ++d) {
+        c[d] /= M;
+        sc0[d] = (float)c[d];
+        st[d] = (float)(c[d] + (double)sigma * z[d]);
+      }
+    }
+    __syncthreads();
+    // x' = c + sigma z + R (x - c)
+    float xn[3] = {0.f, 0.f, 0.f};
+    if (owner) {
+      const float y[3] = {x[0] - sc0[0], x[1] - sc0[1], x[2] - sc0[2]};
+      for (int a = 0; a < 3; ++a)
+        xn[a] = st[a] + sR[3 * a] * y[0] + sR[3 * a + 1] * y[1] +
+                sR[3 * a + 2] * y[2];
+    }
+    double t[6 + C];
+    eval_block<C, W, false, true>(g, L, w, xn, m, sc, f, t, 0.f, 0.f, sh,
+                                  tid);
+    const double u0 = t[0] + t[1] + t[2] + t[3];
+    double e_new = u0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) e_new += L.wd[k * C + c] * t[4 + c];
+    if (tid == 0) {
+      const double ln_a = -beta * (e_new - e_cur);
+      const double lnu =
+          log(u01d(draw(seed, 3u * mv + 2u, L.id, r, s, kExternal).x));
+      s_acc = (isfinite(ln_a) && lnu < ln_a) ? 1 : 0;
+      atomicAdd(&try_k[k], 1ull);
+      if (s_acc) atomicAdd(&acc_k[k], 1ull);
+    }
+    __syncthreads();
+    if (s_acc) {
+      for (int d = 0; d < 3; ++d) x[d] = xn[d];
+      e_cur = e_new;
+      comp[0] = u0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) comp[1 + c] = t[4 + c];
+      moved = true;
+    }
+  }
+  if (moved) {
+    if (owner)
+      for (int d = 0; d < 3; ++d) L.x[(size_t)r * n * 3 + 3 * tid + d] = x[d];
+    if (tid == 0) {
+      double* cw = L.comps + (size_t)r * (1 + C);
+#pragma unroll
+      for (int e = 0; e <= C; ++e) cw[e] = comp[e];
+      L.fvalid[r] = 0;  // the stored start-of-trajectory forces are stale
+    }
+  }
+}
+
+template <int C>
+hipError_t launch_c(const GridDev& g, const LigDev* lig, int K, int waves,
+                    int n_moves, int k_max, float sigma,
+                    unsigned long long* acc, unsigned long long* tries,
+                    int lds, uint64_t seed, hipStream_t st) {
+  if (waves == 1)
+    hipLaunchKernelGGL((k_external_move<C, 1>), dim3(K), dim3(kWave), lds, st,
+                       g, lig, n_moves, k_max, sigma, acc, tries, seed);
+  else if (waves == 2)
+    hipLaunchKernelGGL((k_external_move<C, 2>), dim3(K), dim3(2 * kWave), lds,
+                       st, g, lig, n_moves, k_max, sigma, acc, tries, seed);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_external_move(const GridDev& g, const LigDev* lig, int K,
+                                int waves, int n_moves, int k_max,
+                                float sigma, unsigned long long* acc,
+                                unsigned long long* tries, int lds,
+                                uint64_t seed, hipStream_t st) {
+  if (K <= 0 || n_moves <= 0 || k_max <= 0) return hipSuccess;
+  switch (g.C) {
+    case 3:
+      return launch_c<3>(g, lig, K, waves, n_moves, k_max, sigma, acc, tries,
+                         lds, seed, st);
+    case 5:
+      return launch_c<5>(g, lig, K, waves, n_moves, k_max, sigma, acc, tries,
+                         lds, seed, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace bpmf
