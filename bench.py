@@ -431,8 +431,10 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
     `sample_every` sweeps) gives the reference BPMF (MBAR over all its
     records) with a batch-means standard error from `n_blocks` consecutive
     blocks, and its coupled-state records are the poses the network is
-    trained on.  Both samplers then continue
-    from the long run's final state for `prod_sweeps` sweeps; each reports
+    trained on.  Three samplers then continue from the long run's final
+    state for `prod_sweeps` sweeps -- plain HMC, HMC with the paper's
+    external moves (20 per sweep in the states with alpha < 0.01) and HMC
+    with learned pose moves; each reports
     its BPMF, the error against the reference, the spread of its own block
     estimates, and effective samples per second of two observables of the
     coupled state: its reduced potential (fast) and the distance of its
@@ -503,21 +505,30 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
     ctx.close()
     del poses_x, feats, poses
 
-    def production(learned):
+    # the paper's external moves: 20 per sweep in the states whose grid
+    # coupling alpha is below 0.01
+    alpha = np.linspace(0.0, 1.0, K)
+    k_ext = int(np.sum(alpha < 0.01))
+
+    def production(mode):
         records = prod_sweeps // every
         ctx, lid = fresh(records)
         ctx.set_replicas(lid, final["x"], final["state_of_replica"],
                          final["comps"], int(final["counter"]))
+        learned = mode == "learned"
         if learned:
             ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors],
                                params)
-        ctx.hmc_sweep(2 * pose_every, L, exchange_every=1,
-                      pose_move_every=pose_every if learned else 0)
+        moves = dict(pose_move_every=pose_every if learned else 0)
+        if mode == "external":
+            moves.update(external_moves=20, external_k_max=k_ext,
+                         external_sigma=0.6)
+        ctx.hmc_sweep(2 * pose_every, L, exchange_every=1, **moves)
         ctx.reset_samples(lid)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.hmc_sweep(prod_sweeps, L, exchange_every=1, sample_every=every,
-                      pose_move_every=pose_every if learned else 0)
+                      **moves)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         e, _ = estimate(ctx, lid, records, 5)
@@ -538,11 +549,17 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
                                            max(ps["tries"].sum(), 1))
             out["pose_acceptance_coupled_state"] = float(
                 ps["acc"][-1] / max(ps["tries"][-1], 1))
+        if mode == "external":
+            es = ctx.get_external_stats(lid)
+            out["external_states"] = k_ext
+            out["external_acceptance"] = float(es["acc"].sum() /
+                                               max(es["tries"].sum(), 1))
         ctx.close()
         return out
 
-    plain = production(False)
-    learned = production(True)
+    plain = production("plain")
+    external = production("external")
+    learned = production("learned")
     return {
         "workload": f"{system.name} with the soft-grid switching protocol "
                     f"(5 channels): {n}-atom ligand, {g.n[0]}^3 grids, {K} "
@@ -551,7 +568,9 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
                     f"{long_sweeps}-sweep plain run, a "
                     f"sample per state every {every}; learned: one "
                     f"independence pose move per replica every "
-                    f"{pose_every} sweeps (captured with the sweeps)",
+                    f"{pose_every} sweeps (captured with the sweeps); "
+                    f"external: 20 of the paper's external moves per sweep "
+                    f"in the states with alpha < 0.01",
         "ess_observables": "coupled state: reduced potential on its own "
                            "samples (initial positive autocorrelation sum); "
                            "centre-of-mass distance from the site (batch "
@@ -564,10 +583,14 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
                       "block_sd_kT": ref["block_sd"],
                       "standard_error_kT": float(ref_se),
                       "stat_inefficiency_pose": ref["g_pose"]},
-        "plain": plain, "learned": learned,
+        "plain": plain, "external": external, "learned": learned,
         "ess_per_s_ratio": learned["ess_per_s"] / plain["ess_per_s"],
         "ess_pose_per_s_ratio": learned["ess_pose_per_s"] /
                                 plain["ess_pose_per_s"],
+        "external_ess_per_s_ratio": external["ess_per_s"] /
+                                    plain["ess_per_s"],
+        "external_ess_pose_per_s_ratio": external["ess_pose_per_s"] /
+                                         plain["ess_pose_per_s"],
         "training": {"poses": n_poses, "steps": train_steps, "batch": 512,
                      "train_s": train_s,
                      "loss_first": float(np.mean(losses[:20])),

@@ -22,14 +22,18 @@ namespace {
 // off).  Move m of the call uses Philox draw 3m (three uniforms: the
 // quaternion by Shoemake's construction), 3m + 1 (three normals: the
 // translation) and 3m + 2 (the acceptance uniform), keyed by the ligand,
-// the replica and the sweep counter.
+// the replica and the sweep counter.  The moves are a chain, but their
+// random numbers are not: each batch of up to kBatch moves has its
+// rotations, translations and ln u made first, one lane per move.
+constexpr int kBatch = 64;
 template <int C, int W>
 __global__ __launch_bounds__(W * kWave) void k_external_move(
     GridDev g, const LigDev* __restrict__ lig, int n_moves, int k_max,
     float sigma, unsigned long long* __restrict__ acc_k,
     unsigned long long* __restrict__ try_k, uint64_t seed) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ float sR[9], sc0[3], st[3];
+  __shared__ float sRm[kBatch][9], stm[kBatch][3], sc0[3], st[3];
+  __shared__ double s_lnu[kBatch];
   __shared__ double s_cp[4 * W];
   __shared__ int s_acc;
   const LigDev L = *lig;
@@ -73,6 +77,36 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
   for (int c = 0; c < C; ++c) e_cur += L.wd[k * C + c] * comp[1 + c];
   bool moved = false;
   for (int mv = 0; mv < n_moves; ++mv) {
+    const int j = mv % kBatch;
+    if (j == 0) {
+      // this batch's rotations, translations and ln u (the previous
+      // batch's last reader passed the barrier that ended its move)
+      const int b = mv + tid;
+      if (tid < kBatch && b < n_moves) {
+        // uniform unit quaternion (w, x, y, z) from three uniforms
+        const U4 o = draw(seed, 3u * b, L.id, r, s, kExternal);
+        const double u1 = u01d(o.x), u2 = u01d(o.y), u3 = u01d(o.z);
+        const double a = sqrt(1.0 - u1), bb = sqrt(u1);
+        double s2, c2, s3, c3;
+        sincos(2.0 * M_PI * u2, &s2, &c2);
+        sincos(2.0 * M_PI * u3, &s3, &c3);
+        const double qw = bb * c3, qx = a * s2, qy = a * c2, qz = bb * s3;
+        const double R[9] = {1 - 2 * (qy * qy + qz * qz),
+                             2 * (qx * qy - qz * qw), 2 * (qx * qz + qy * qw),
+                             2 * (qx * qy + qz * qw),
+                             1 - 2 * (qx * qx + qz * qz),
+                             2 * (qy * qz - qx * qw), 2 * (qx * qz - qy * qw),
+                             2 * (qy * qz + qx * qw),
+                             1 - 2 * (qx * qx + qy * qy)};
+        for (int e = 0; e < 9; ++e) sRm[tid][e] = (float)R[e];
+        float z[3];
+        normals3(draw(seed, 3u * b + 1u, L.id, r, s, kExternal), z[0], z[1],
+                 z[2]);
+        for (int d = 0; d < 3; ++d) stm[tid][d] = sigma * z[d];
+        s_lnu[tid] =
+            log(u01d(draw(seed, 3u * b + 2u, L.id, r, s, kExternal).x));
+      }
+    }
     // centre of mass in double (fixed-order: wave sums, then waves)
     {
       const double mi = (double)m;
@@ -93,30 +127,14 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
         for (int d = 0; d < 3; ++d) c[d] += s_cp[4 * q + d];
         M += s_cp[4 * q + 3];
       }
-      // uniform unit quaternion (w, x, y, z) from three uniforms
-      const U4 o = draw(seed, 3u * mv, L.id, r, s, kExternal);
-      const double u1 = u01d(o.x), u2 = u01d(o.y), u3 = u01d(o.z);
-      const double a = sqrt(1.0 - u1), b = sqrt(u1);
-      double s2, c2, s3, c3;
-      sincos(2.0 * M_PI * u2, &s2, &c2);
-      sincos(2.0 * M_PI * u3, &s3, &c3);
-      const double qw = b * c3, qx = a * s2, qy = a * c2, qz = b * s3;
-      const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qz * qw),
-                           2 * (qx * qz + qy * qw),     2 * (qx * qy + qz * qw),
-                           1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qx * qw),
-                           2 * (qx * qz - qy * qw),     2 * (qy * qz + qx * qw),
-                           1 - 2 * (qx * qx + qy * qy)};
-      for (int e = 0; e < 9; ++e) sR[e] = (float)R[e];
-      float z[3];
-      normals3(draw(seed, 3u * mv + 1u, L.id, r, s, kExternal), z[0], z[1],
-               z[2]);
       for (int d = 0; d < 3; ++d) {
         c[d] /= M;
         sc0[d] = (float)c[d];
-        st[d] = (float)(c[d] + (double)sigma * z[d]);
+        st[d] = (float)(c[d] + (double)stm[j][d]);
       }
     }
     __syncthreads();
+    const float* sR = sRm[j];
     // x' = c + sigma z + R (x - c)
     float xn[3] = {0.f, 0.f, 0.f};
     if (owner) {
@@ -126,17 +144,15 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
                 sR[3 * a + 2] * y[2];
     }
     double t[6 + C];
-    eval_block<C, W, false, true>(g, L, w, xn, m, sc, f, t, 0.f, 0.f, sh,
-                                  tid);
+    eval_block<C, W, false, true, true>(g, L, w, xn, m, sc, f, t, 0.f, 0.f,
+                                        sh, tid);
     const double u0 = t[0] + t[1] + t[2] + t[3];
     double e_new = u0;
 #pragma unroll
     for (int c = 0; c < C; ++c) e_new += L.wd[k * C + c] * t[4 + c];
     if (tid == 0) {
       const double ln_a = -beta * (e_new - e_cur);
-      const double lnu =
-          log(u01d(draw(seed, 3u * mv + 2u, L.id, r, s, kExternal).x));
-      s_acc = (isfinite(ln_a) && lnu < ln_a) ? 1 : 0;
+      s_acc = (isfinite(ln_a) && s_lnu[j] < ln_a) ? 1 : 0;
       atomicAdd(&try_k[k], 1ull);
       if (s_acc) atomicAdd(&acc_k[k], 1ull);
     }
