@@ -88,7 +88,8 @@ def lib():
                                     C.c_int, C.c_int, C.c_uint64, C.c_int,
                                     dp, ip, dp, ip, dp, dp]
         L.ora_exchange.argtypes = [C.c_int, C.c_int, dp, dp, C.c_uint64,
-                                   C.c_int, C.c_uint64, C.c_int, C.c_int, dp,
+                                   C.c_int, C.c_uint64, C.c_int, C.c_int,
+                                   C.c_int, dp,
                                    ip, ip, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64)]
         L.ora_ukn.argtypes = [vp, vp, C.c_int, dp, dp, C.c_int64, dp, dp]
@@ -348,16 +349,20 @@ class Sampler:
             self.hmc_acc[self.state[r]] += acc[r]
         return acc, dH, lnu
 
-    def exchange(self, scheme=0, max_sep=1):
+    def exchange(self, scheme=0, max_sep=1, n_sweeps=1):
+        """n_sweeps exchange sweeps in a row at the current counter (the
+        paper ends each iteration with 25); sweep j draws with replica
+        field j."""
         ol = self.ol
-        lib().ora_exchange(ol.K, self.og.nc, _p(ol.T, C.c_double),
-                           _p(ol.w, C.c_double), self.seed, self.lig,
-                           self.sweep_count, scheme, max_sep,
-                           _p(self.comps, C.c_double),
-                           _p(self.state, C.c_int),
-                           _p(self.rep_of_state, C.c_int),
-                           _p(self.ex_acc, C.c_int64),
-                           _p(self.ex_try, C.c_int64))
+        for j in range(int(n_sweeps)):
+            lib().ora_exchange(ol.K, self.og.nc, _p(ol.T, C.c_double),
+                               _p(ol.w, C.c_double), self.seed, self.lig,
+                               self.sweep_count, scheme, max_sep, j,
+                               _p(self.comps, C.c_double),
+                               _p(self.state, C.c_int),
+                               _p(self.rep_of_state, C.c_int),
+                               _p(self.ex_acc, C.c_int64),
+                               _p(self.ex_try, C.c_int64))
 
     def record(self):
         for k in range(self.ol.K):
@@ -367,11 +372,11 @@ class Sampler:
             self.samples_state.append(k)
 
     def sweep(self, nleap, exchange_every=1, sample_every=0, scheme=0,
-              max_sep=1):
+              max_sep=1, exchange_sweeps=1):
         out = self.hmc(nleap)
         s = self.sweep_count
         if exchange_every > 0 and s % exchange_every == 0:
-            self.exchange(scheme, max_sep)
+            self.exchange(scheme, max_sep, max(int(exchange_sweeps), 1))
         if sample_every > 0 and (s + 1) % sample_every == 0:
             self.record()
         self.sweep_count += 1

@@ -459,6 +459,9 @@ void ora_hmc_sweep(const ora_grid* g, const ora_ligand* L, int K,
 /* scheme 0: neighbour pairs, (0,1),(2,3).. on even sweeps, (1,2),.. on odd. */
 /* scheme 1: pairs 1..max_sep apart, separation ascending, lower state       */
 /*           ascending, applied sequentially (Gibbs sweep).                 */
+/* sub: which of the exchange sweeps run back to back at one sweep counter  */
+/*      this is (Equilibration and production: an iteration ends with 25);  */
+/*      it fills the replica field of the uniforms' counter.                 */
 /* ------------------------------------------------------------------------ */
 static double state_energy(int nc, const double* w_k, const double* comp) {
   double E = comp[0];
@@ -468,7 +471,8 @@ static double state_energy(int nc, const double* w_k, const double* comp) {
 
 void ora_exchange(int K, int nc, const double* T, const double* w,
                   uint64_t seed, int lig, uint64_t sweep, int scheme,
-                  int max_sep, const double* comps, int* state_of_replica,
+                  int max_sep, int sub, const double* comps,
+                  int* state_of_replica,
                   int* replica_of_state, int64_t* acc, int64_t* tries) {
   int dmax = scheme == 0 ? 1 : (max_sep < K - 1 ? max_sep : K - 1);
   for (int d = 1; d <= dmax; ++d) {
@@ -485,7 +489,8 @@ void ora_exchange(int K, int nc, const double* T, const double* w,
       double delta = ba * (state_energy(nc, wa, cy) - state_energy(nc, wa, cx)) +
                      bb * (state_energy(nc, wb, cx) - state_energy(nc, wb, cy));
       uint32_t purpose = (uint32_t)ORA_P_EXCHANGE | ((uint32_t)d << 8);
-      double lnu = log(ora_uniform(seed, (uint32_t)a, lig, 0, sweep, purpose));
+      double lnu =
+          log(ora_uniform(seed, (uint32_t)a, lig, sub, sweep, purpose));
       int ok = isfinite(delta) && (lnu < -delta);
       if (d == 1 && tries) tries[a] += 1;
       if (ok) {

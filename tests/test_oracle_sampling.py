@@ -176,7 +176,7 @@ def test_exchange_acceptance_frequency(oracle_lib):
             oracle.lib().ora_exchange(
                 K, 3, T.ctypes.data_as(C.POINTER(C.c_double)),
                 w.ctypes.data_as(C.POINTER(C.c_double)), 99, 0, sweep, 0, 1,
-                comps.ctypes.data_as(C.POINTER(C.c_double)),
+                0, comps.ctypes.data_as(C.POINTER(C.c_double)),
                 st.ctypes.data_as(C.POINTER(C.c_int)),
                 rp.ctypes.data_as(C.POINTER(C.c_int)),
                 a.ctypes.data_as(C.POINTER(C.c_int64)),
@@ -219,6 +219,76 @@ def test_exchange_detailed_balance_and_permutation(oracle_lib):
         s.exchange(scheme=1 if sweep % 3 == 0 else 0, max_sep=5)
         assert np.all(s.rep_of_state[s.state] == np.arange(K))
     assert s.ex_try.sum() > 0
+
+
+def test_repeated_exchange_sweeps_two_state_chain(oracle_lib):
+    """n exchange sweeps in a row at one counter are n steps of the two-state
+    Markov chain: from the favoured labelling a swap is accepted with
+    p = exp(-delta), the swap back always.  Independent uniforms per sweep
+    give P(swapped after n) = (e0 M^n)[1] with M = [[1-p, p], [1, 0]];
+    reusing one uniform for every sweep would give 0 for n = 2."""
+    K = 2
+    T = np.array([600.0, 300.0])
+    w = np.array([[0.0, 0.0, 0.0], [1.0, 1.0, 1.0]])
+    lig = synth.toy_ligand(np.zeros((2, 3)), [[0, 1]], 1.0, T, w[:, 0])
+    og, ol = oracle.OGrid(_zero_grid()), oracle.OLigand(lig)
+    delta = math.log(2.0)
+    comps = _comps_for_delta(K, T, w, delta)
+    p = math.exp(-delta)
+    M = np.array([[1 - p, p], [1.0, 0.0]])
+    trials = 3000
+    for n in (1, 2, 3, 4):
+        s = oracle.Sampler(og, ol, seed=17, x0=lig.x0)
+        swapped = 0
+        for t in range(trials):
+            s.comps = np.ascontiguousarray(comps)
+            s.state = np.arange(K, dtype=np.int32)
+            s.rep_of_state = np.arange(K, dtype=np.int32)
+            s.sweep_count = t
+            s.exchange(scheme=1, max_sep=1, n_sweeps=n)
+            assert np.all(s.rep_of_state[s.state] == np.arange(K))
+            swapped += int(s.state[0] == 1)
+        q = np.linalg.matrix_power(M, n)[0, 1]
+        sd = math.sqrt(q * (1 - q) / trials)
+        assert abs(swapped / trials - q) < 5 * sd + 1e-9, (n, swapped, q)
+        assert s.ex_try[0] == n * trials
+
+
+def test_repeated_exchange_sweeps_stationary_law(oracle_lib):
+    """Exchange is Gibbs sampling of the state labelling: with fixed
+    configurations, repeated sweeps (scheme 1, all separations) leave the
+    law P(labelling) ~ exp(-sum_k beta_k E_k(x_replica in k)) invariant, so
+    the labellings seen after each call follow it."""
+    import itertools
+    K = 3
+    T = np.array([600.0, 450.0, 300.0])
+    w = np.array([[0.0] * 3, [0.5] * 3, [1.0] * 3])
+    R = oracle.R_GAS
+    beta = 1 / (R * T)
+    rng = np.random.default_rng(8)
+    comps = np.ascontiguousarray(rng.normal(scale=1.0, size=(K, 4)))
+    lig = synth.toy_ligand(np.zeros((2, 3)), [[0, 1]], 1.0, T, w[:, 0])
+    og, ol = oracle.OGrid(_zero_grid()), oracle.OLigand(lig)
+
+    def E(k, c):
+        return c[0] + w[k] @ c[1:]
+    perms = list(itertools.permutations(range(K)))   # replica in state k
+    logp = np.array([-sum(beta[k] * E(k, comps[pm[k]]) for k in range(K))
+                     for pm in perms])
+    pi = np.exp(logp - logp.max())
+    pi /= pi.sum()
+    assert pi.min() > 0.02    # a law with every labelling visible
+    s = oracle.Sampler(og, ol, seed=23, x0=lig.x0)
+    s.comps = comps
+    calls = 6000
+    seen = np.zeros(len(perms))
+    for t in range(calls):
+        s.sweep_count = t
+        s.exchange(scheme=1, max_sep=2, n_sweeps=4)
+        seen[perms.index(tuple(int(r) for r in s.rep_of_state))] += 1
+    f = seen / calls
+    sd = np.sqrt(pi * (1 - pi) / calls)
+    assert np.all(np.abs(f - pi) < 6 * sd), (f, pi)
 
 
 def test_identical_hamiltonians_always_exchange(oracle_lib):
