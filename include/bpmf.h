@@ -64,6 +64,7 @@ enum {
 #define BPMF_MAX_STATES 1024   /* thermodynamic states per ligand */
 #define BPMF_MAX_MBAR_STATES 128
 #define BPMF_MAX_MBAR_BATCH 65535  /* problems per bpmf_mbar_batch call */
+#define BPMF_MAX_EXCHANGE_SWEEPS 1024  /* exchange sweeps per due exchange */
 
 typedef struct bpmf_ctx bpmf_ctx;
 typedef void* (*bpmf_alloc_fn)(size_t bytes, void* user);
@@ -194,6 +195,10 @@ typedef struct {
                           moves (bpmf_external_move) of every ligand */
   int external_k_max;  /* states 0..external_k_max-1 take external moves */
   double external_sigma; /* translation per axis (A), > 0 when used */
+  int exchange_sweeps; /* 0 or 1 = one exchange sweep when an exchange is
+                          due; n > 1 (scheme 1 only, <= BPMF_MAX_EXCHANGE_
+                          SWEEPS) = n sweeps in a row (Equilibration and
+                          production: each iteration ends with 25) */
 } bpmf_sweep_args;
 
 /* Run n_sweeps sweeps over every ligand.  One sweep of a ligand with
@@ -205,7 +210,7 @@ typedef struct {
  *      v += dt/2 a; x += dt v; v += dt/2 a with a = F/m * 1e-4, then accept
  *      iff ln u < -(H1 - H0) / (R T_k), H = U_k + sum m v^2/2 * 1e4,
  *      H summed in double; non-finite H or x => reject;
- *   2. if due, one replica-exchange sweep (see bpmf_exchange);
+ *   2. if due, exchange_sweeps replica-exchange sweeps (see bpmf_exchange);
  *   3. if due, record one sample per state: the configuration and cached
  *      energy components of the replica currently in that state;
  *   4. s += 1.
@@ -223,13 +228,15 @@ typedef struct {
  * Random numbers: Philox-4x32-10 keyed by the context seed, counter
  * (index, ligand<<16 | replica, s, purpose) with purpose 1 = momenta
  * (index = atom), 2 = acceptance (index 0), 3 | sep<<8 = exchange
- * (index = lower state, replica field 0); uniforms (u32 + 1) 2^-32.
+ * (index = lower state, replica field = exchange sweep j of the due
+ * exchange, 0-based); uniforms (u32 + 1) 2^-32.
  * Errors: BPMF_E_INVAL (bad args, sample capacity would overflow),
  * BPMF_E_STATE (no ligand). */
 BPMF_API int bpmf_hmc_sweep(bpmf_ctx* ctx, const bpmf_sweep_args* args);
 
-/* One replica-exchange sweep of ligand `ligand_id` (-1 = every ligand) at
- * its current counter s (the counter is not advanced).  Each attempted pair
+/* n_sweeps (1..BPMF_MAX_EXCHANGE_SWEEPS) replica-exchange sweeps in a row
+ * of ligand `ligand_id` (-1 = every ligand) at its current counter s (the
+ * counter is not advanced; sweep j draws its uniforms with replica field j).  Each attempted pair
  * (a, b) with configuration x in state a and y in state b is accepted with
  * probability min(1, exp(-[u_a(y) + u_b(x) - u_a(x) - u_b(y)])) (Eq.
  * repXacc), evaluated in double from the cached components; acceptance swaps
@@ -237,7 +244,8 @@ BPMF_API int bpmf_hmc_sweep(bpmf_ctx* ctx, const bpmf_sweep_args* args);
  * 2 + 2, ...; scheme 1 attempts every pair 1..max_sep apart, separation
  * ascending then a ascending, each decision seeing the previous ones
  * (Sampling: pairs 1..min(5, K) states apart). */
-BPMF_API int bpmf_exchange(bpmf_ctx* ctx, int ligand_id, int scheme, int max_sep);
+BPMF_API int bpmf_exchange(bpmf_ctx* ctx, int ligand_id, int scheme, int max_sep,
+                           int n_sweeps);
 
 /* ------------------------------------------------------------------------
  * Reduced-energy matrix and free energies (Estimation)

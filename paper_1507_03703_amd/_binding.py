@@ -49,7 +49,8 @@ class _SweepArgs(C.Structure):
                 ("exchange_every", C.c_int), ("exchange_scheme", C.c_int),
                 ("max_sep", C.c_int), ("sample_every", C.c_int),
                 ("pose_move_every", C.c_int), ("external_moves", C.c_int),
-                ("external_k_max", C.c_int), ("external_sigma", C.c_double)]
+                ("external_k_max", C.c_int), ("external_sigma", C.c_double),
+                ("exchange_sweeps", C.c_int)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -91,7 +92,7 @@ def library():
         "bpmf_grid_upload": [vp, C.POINTER(_GridDesc), C.POINTER(C.c_float)],
         "bpmf_ligand_setup": [vp, C.POINTER(_LigandDesc), ip],
         "bpmf_hmc_sweep": [vp, C.POINTER(_SweepArgs)],
-        "bpmf_exchange": [vp, C.c_int, C.c_int, C.c_int],
+        "bpmf_exchange": [vp, C.c_int, C.c_int, C.c_int, C.c_int],
         "bpmf_energy_matrix": [vp, C.c_int, vp, C.c_int64, vp, C.c_int64],
         "bpmf_energy_matrix_batch": [vp, C.c_int, ip, C.POINTER(C.c_void_p),
                                      i64p, C.POINTER(C.c_void_p), i64p],
@@ -258,16 +259,17 @@ class Context:
     def hmc_sweep(self, n_sweeps, n_leapfrog, exchange_every=1,
                   exchange_scheme=0, max_sep=1, sample_every=0,
                   pose_move_every=0, external_moves=0, external_k_max=0,
-                  external_sigma=0.6):
+                  external_sigma=0.6, exchange_sweeps=1):
         a = _SweepArgs(int(n_sweeps), int(n_leapfrog), int(exchange_every),
                        int(exchange_scheme), int(max_sep), int(sample_every),
                        int(pose_move_every), int(external_moves),
-                       int(external_k_max), float(external_sigma))
+                       int(external_k_max), float(external_sigma),
+                       int(exchange_sweeps))
         _check(self._lib.bpmf_hmc_sweep(self._h, C.byref(a)))
 
-    def exchange(self, ligand_id=-1, scheme=0, max_sep=1):
+    def exchange(self, ligand_id=-1, scheme=0, max_sep=1, n_sweeps=1):
         _check(self._lib.bpmf_exchange(self._h, int(ligand_id), int(scheme),
-                                       int(max_sep)))
+                                       int(max_sep), int(n_sweeps)))
 
     # -- u_kn, MBAR -----------------------------------------------------------
     def energy_matrix(self, ligand_id, samples=None, n_samples=None, out=None):

@@ -129,7 +129,7 @@ struct bpmf_ctx {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   uint64_t table_version = 0, graph_version = ~0ull;
-  static constexpr int kKey = 12;
+  static constexpr int kKey = 13;
   int graph_key[kKey] = {0};
 
   void drop_graph() {
@@ -771,6 +771,12 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     return fail(BPMF_E_INVAL, "exchange_scheme must be 0 or 1");
   if (a->exchange_scheme == 1 && a->max_sep < 1)
     return fail(BPMF_E_INVAL, "max_sep must be >= 1");
+  if (a->exchange_sweeps < 0 || a->exchange_sweeps > BPMF_MAX_EXCHANGE_SWEEPS)
+    return fail(BPMF_E_INVAL, "exchange_sweeps must be in 0..%d",
+                BPMF_MAX_EXCHANGE_SWEEPS);
+  const int n_sub = a->exchange_sweeps > 1 ? a->exchange_sweeps : 1;
+  if (n_sub > 1 && a->exchange_scheme != 1)
+    return fail(BPMF_E_INVAL, "exchange_sweeps > 1 needs exchange_scheme 1");
   if (a->pose_move_every < 0)
     return fail(BPMF_E_INVAL, "pose_move_every must be >= 0");
   if ((rc = check_external(a->external_moves, a->external_k_max,
@@ -792,7 +798,7 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     }
   }
   TailArgs tail{a->exchange_every, a->exchange_scheme, a->max_sep,
-                a->sample_every};
+                a->sample_every, n_sub};
   const int nl = (int)c->ligs.size();
   // scheme 0: each sweep applies the previous one's exchange and record in
   // its own blocks (begin/finish kernels bracket the run); scheme 1: a tail
@@ -808,8 +814,8 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
             st));
     if (tail.scheme == 1)
       HIP_TRY(launch_sweep_tail(c->d_ligs, nl, tail.exchange_every,
-                                tail.scheme, tail.max_sep, tail.sample_every,
-                                c->seed, st));
+                                tail.scheme, tail.max_sep, n_sub,
+                                tail.sample_every, c->seed, st));
     return BPMF_OK;
   };
   if (a->n_sweeps == 0) return BPMF_OK;
@@ -903,7 +909,7 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
       const int key[bpmf_ctx::kKey] = {
           a->n_leapfrog, a->exchange_every, a->exchange_scheme, a->max_sep,
           a->sample_every, 0, P, a->pose_move_every, NX, a->external_k_max,
-          sg[0], sg[1]};
+          sg[0], sg[1], n_sub};
       if ((rc = ensure_graph(key, unit))) return rc;
       for (int u = 0; u < units; ++u)
         if ((rc = launch_timed(P, [&]() -> int {
@@ -924,7 +930,7 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     if (chunk > 0 && a->n_sweeps >= chunk) {
       const int key[bpmf_ctx::kKey] = {
           a->n_leapfrog, a->exchange_every, a->exchange_scheme, a->max_sep,
-          a->sample_every, chunk, 0, 0, 0, 0, 0, -1};
+          a->sample_every, chunk, 0, 0, 0, 0, 0, -1, n_sub};
       if ((rc = ensure_graph(key, [&](hipStream_t st) -> int {
              for (int s = 0; s < chunk; ++s) {
                const int r = enqueue_sweep(st);
@@ -960,7 +966,7 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
 }
 
 extern "C" int bpmf_exchange(bpmf_ctx* c, int ligand_id, int scheme,
-                             int max_sep) {
+                             int max_sep, int n_sweeps) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (c->ligs.empty()) return fail(BPMF_E_STATE, "no ligand set up");
@@ -968,12 +974,15 @@ extern "C" int bpmf_exchange(bpmf_ctx* c, int ligand_id, int scheme,
   if (scheme != 0 && scheme != 1)
     return fail(BPMF_E_INVAL, "scheme must be 0 or 1");
   if (scheme == 1 && max_sep < 1) return fail(BPMF_E_INVAL, "max_sep must be >= 1");
+  if (n_sweeps < 1 || n_sweeps > BPMF_MAX_EXCHANGE_SWEEPS)
+    return fail(BPMF_E_INVAL, "n_sweeps must be in 1..%d",
+                BPMF_MAX_EXCHANGE_SWEEPS);
   if (ligand_id == -1)
     HIP_TRY(launch_exchange(c->d_ligs, (int)c->ligs.size(), scheme, max_sep,
-                            c->seed, c->stream));
+                            n_sweeps, c->seed, c->stream));
   else
-    HIP_TRY(launch_exchange(c->d_ligs + ligand_id, 1, scheme, max_sep, c->seed,
-                            c->stream));
+    HIP_TRY(launch_exchange(c->d_ligs + ligand_id, 1, scheme, max_sep,
+                            n_sweeps, c->seed, c->stream));
   return BPMF_OK;
 }
 

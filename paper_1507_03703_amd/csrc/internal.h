@@ -109,9 +109,10 @@ struct LigDev {
 // Launch wrappers (kernels.hip).  All return hipError_t of the launch.
 // waves = wavefronts per replica (1, 2 or 4); n_atoms <= 64 * waves
 // exchange/record schedule of a sweep (scheme 0: deferred into the next
-// sweep's blocks; scheme 1: a tail kernel after every sweep)
+// sweep's blocks; scheme 1: a tail kernel after every sweep, running
+// exchange_sweeps exchange sweeps when an exchange is due)
 struct TailArgs {
-  int exchange_every, scheme, max_sep, sample_every;
+  int exchange_every, scheme, max_sep, sample_every, exchange_sweeps;
 };
 // one: the host copy of the table entry when the launch covers a single
 // ligand (its replicas 0..n_tasks-1 in order), else null
@@ -122,14 +123,17 @@ hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
                             hipStream_t st);
 hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
                              int exchange_every, int scheme, int max_sep,
-                             int sample_every, uint64_t seed, hipStream_t st);
+                             int n_sub, int sample_every, uint64_t seed,
+                             hipStream_t st);
 hipError_t launch_sweep_begin(const LigDev* d_ligs, int n_ligs,
                               hipStream_t st);
 hipError_t launch_sweep_finish(const LigDev* d_ligs, int n_ligs,
                                int exchange_every, int sample_every,
                                uint64_t seed, hipStream_t st);
+// n_sub exchange sweeps in a row (sweep j draws with replica field j)
 hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
-                           int max_sep, uint64_t seed, hipStream_t st);
+                           int max_sep, int n_sub, uint64_t seed,
+                           hipStream_t st);
 // one ligand's share of an energy-matrix launch: samples xs (n x n_atoms x
 // 3), output u_kn (K x ld); its samples are [first, first + n) of the
 // launch's flat sample index

@@ -63,14 +63,14 @@ __device__ double state_energy(const LigDev& L, int k, int rep) {
 }
 
 __device__ bool attempt_pair(const LigDev& L, int a, int b, int sep,
-                             uint64_t sweep, uint64_t seed) {
+                             uint64_t sweep, int sub, uint64_t seed) {
   const int ra = L.replica_of_state[a], rb = L.replica_of_state[b];
   const double ba = L.beta[a], bb = L.beta[b];
   const double delta =
       ba * (state_energy(L, a, rb) - state_energy(L, a, ra)) +
       bb * (state_energy(L, b, ra) - state_energy(L, b, rb));
   const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)sep << 8);
-  const U4 o = draw(seed, (uint32_t)a, L.id, 0, sweep, purpose);
+  const U4 o = draw(seed, (uint32_t)a, L.id, sub, sweep, purpose);
   const double lnu = log(u01d(o.x));
   const bool ok = isfinite(delta) && (lnu < -delta);
   if (sep == 1) atomicAdd(&L.ex_try[a], 1ull);
@@ -85,30 +85,37 @@ __device__ bool attempt_pair(const LigDev& L, int a, int b, int sep,
 }
 #pragma clang fp contract(fast)
 
-// block-wide exchange sweep for one ligand (called by all threads)
+// block-wide exchange for one ligand (called by all threads): n_sub
+// exchange sweeps in a row, sweep j drawing its uniforms with replica field j
 __device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
-                               int max_sep, uint64_t seed) {
+                               int max_sep, int n_sub, uint64_t seed) {
   const int K = L.K;
   if (K < 2) return;
   if (scheme == 0) {
     // disjoint neighbour pairs: independent, one thread each
     const int a0 = (int)(sweep & 1ull);
-    for (int a = a0 + 2 * (int)threadIdx.x; a + 1 < K; a += 2 * blockDim.x)
-      attempt_pair(L, a, a + 1, 1, sweep, seed);
+    for (int j = 0; j < n_sub; ++j) {
+      if (j > 0) __syncthreads();
+      for (int a = a0 + 2 * (int)threadIdx.x; a + 1 < K; a += 2 * blockDim.x)
+        attempt_pair(L, a, a + 1, 1, sweep, j, seed);
+    }
   } else if (threadIdx.x == 0) {
     const int dmax = max_sep < K - 1 ? max_sep : K - 1;
-    for (int d = 1; d <= dmax; ++d)
-      for (int a = 0; a + d < K; ++a) attempt_pair(L, a, a + d, d, sweep, seed);
+    for (int j = 0; j < n_sub; ++j)
+      for (int d = 1; d <= dmax; ++d)
+        for (int a = 0; a + d < K; ++a)
+          attempt_pair(L, a, a + d, d, sweep, j, seed);
   }
 }
 
 // Tail of one ligand's sweep, run by one whole block: exchange (if due),
 // record one sample per state (if due), counter += 1.
 __device__ void sweep_tail(const LigDev& L, int exchange_every, int scheme,
-                           int max_sep, int sample_every, uint64_t seed) {
+                           int max_sep, int n_sub, int sample_every,
+                           uint64_t seed) {
   const unsigned long long s = *L.counter;
   if (exchange_every > 0 && s % (unsigned long long)exchange_every == 0ull)
-    exchange_block(L, s, scheme, max_sep, seed);
+    exchange_block(L, s, scheme, max_sep, n_sub, seed);
   __syncthreads();
   const unsigned long long rec = *L.n_rec;
   const bool record = sample_every > 0 &&
@@ -137,9 +144,9 @@ __device__ void sweep_tail(const LigDev& L, int exchange_every, int scheme,
 // One block per ligand: the tail as a kernel of its own.
 __global__ __launch_bounds__(256) void k_sweep_tail(
     const LigDev* __restrict__ ligs, int exchange_every, int scheme,
-    int max_sep, int sample_every, uint64_t seed) {
-  sweep_tail(ligs[blockIdx.x], exchange_every, scheme, max_sep, sample_every,
-             seed);
+    int max_sep, int n_sub, int sample_every, uint64_t seed) {
+  sweep_tail(ligs[blockIdx.x], exchange_every, scheme, max_sep, n_sub,
+             sample_every, seed);
 }
 
 // ----------------------------------------------------------------------------
@@ -547,9 +554,10 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
 }
 
 __global__ __launch_bounds__(256) void k_exchange(
-    const LigDev* __restrict__ ligs, int scheme, int max_sep, uint64_t seed) {
+    const LigDev* __restrict__ ligs, int scheme, int max_sep, int n_sub,
+    uint64_t seed) {
   const LigDev& L = ligs[blockIdx.x];
-  exchange_block(L, *L.counter, scheme, max_sep, seed);
+  exchange_block(L, *L.counter, scheme, max_sep, n_sub, seed);
 }
 
 // ----------------------------------------------------------------------------
@@ -858,10 +866,12 @@ hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
 
 hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
                              int exchange_every, int scheme, int max_sep,
-                             int sample_every, uint64_t seed, hipStream_t st) {
+                             int n_sub, int sample_every, uint64_t seed,
+                             hipStream_t st) {
   if (n_ligs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sweep_tail, dim3(n_ligs), dim3(256), 0, st, d_ligs,
-                     exchange_every, scheme, max_sep, sample_every, seed);
+                     exchange_every, scheme, max_sep, n_sub, sample_every,
+                     seed);
   return hipGetLastError();
 }
 
@@ -882,10 +892,11 @@ hipError_t launch_sweep_finish(const LigDev* d_ligs, int n_ligs,
 }
 
 hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
-                           int max_sep, uint64_t seed, hipStream_t st) {
+                           int max_sep, int n_sub, uint64_t seed,
+                           hipStream_t st) {
   if (n_ligs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_exchange, dim3(n_ligs), dim3(256), 0, st, d_lig,
-                     scheme, max_sep, seed);
+                     scheme, max_sep, n_sub, seed);
   return hipGetLastError();
 }
 

@@ -94,15 +94,16 @@ def test_exchange_decisions_bitwise():
         counter = int(rng.integers(0, 1000))
         scheme = trial % 2
         max_sep = 1 + trial % 5
+        n_sweeps = (1, 2, 3, 25)[(trial // 2) % 4]
         ctx.set_replicas(lid, lig.x0, sor, comps, counter)
-        ctx.exchange(lid, scheme=scheme, max_sep=max_sep)
+        ctx.exchange(lid, scheme=scheme, max_sep=max_sep, n_sweeps=n_sweeps)
         st = ctx.get_replicas(lid)
         s = oracle.Sampler(og, ol, seed=99, lig_id=lid, x0=lig.x0)
         s.comps = np.ascontiguousarray(comps)
         s.state = sor.copy()
         s.rep_of_state = np.ascontiguousarray(np.argsort(sor).astype(np.int32))
         s.sweep_count = counter
-        s.exchange(scheme=scheme, max_sep=max_sep)
+        s.exchange(scheme=scheme, max_sep=max_sep, n_sweeps=n_sweeps)
         assert np.array_equal(st["state_of_replica"], s.state), trial
     ctx.close()
 
@@ -266,10 +267,90 @@ def test_validation_errors():
         ctx.set_replicas(lid, lig.x0, np.zeros(lig.n_states, np.int32))
     with pytest.raises(pkg.BPMFError):
         ctx.exchange(5)
+    for n in (0, 1025):
+        with pytest.raises(pkg.BPMFError):
+            ctx.exchange(lid, scheme=1, max_sep=2, n_sweeps=n)
+    for kw in (dict(exchange_sweeps=-1), dict(exchange_sweeps=1025),
+               dict(exchange_scheme=0, exchange_sweeps=2)):
+        kw.setdefault("exchange_scheme", 1)
+        with pytest.raises(pkg.BPMFError) as ei:
+            ctx.hmc_sweep(1, 5, max_sep=2, **kw)
+        assert "exchange_sweeps" in str(ei.value)
     with pytest.raises(pkg.BPMFError) as ei:
         ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
     assert ei.value.code == -4
     ctx.close()
+
+
+def test_repeated_exchange_sweeps_inside_sweeps():
+    """Sweeps with scheme 1 and 25 exchange sweeps per due exchange (the
+    paper's iteration): the labelling after each sweep is the oracle's 25
+    exchange sweeps applied to the labelling before it and the sweep's
+    post-HMC components, bitwise; the attempt counts add up."""
+    print_case("exchange sweeps in sweeps")
+    system = synth.make_system(1)
+    lig, g = system.ligands[0], system.grid
+    og, ol = oracle.OGrid(g), oracle.OLigand(lig)
+    ctx, (lid,) = make_context(g, [lig], seed=41)
+    s = oracle.Sampler(og, ol, seed=41, lig_id=lid, x0=lig.x0)
+    moved = 0
+    for sweep in range(6):
+        st0 = ctx.get_replicas(lid)
+        ctx.hmc_sweep(1, 10, exchange_every=1, exchange_scheme=1, max_sep=5,
+                      exchange_sweeps=25)
+        st1 = ctx.get_replicas(lid)
+        s.comps = np.ascontiguousarray(st1["comps"].copy())
+        s.state = np.ascontiguousarray(
+            st0["state_of_replica"].astype(np.int32))
+        s.rep_of_state = np.ascontiguousarray(
+            np.argsort(s.state).astype(np.int32))
+        s.sweep_count = int(st0["counter"])
+        s.exchange(scheme=1, max_sep=5, n_sweeps=25)
+        assert np.array_equal(st1["state_of_replica"], s.state), sweep
+        moved += int(not np.array_equal(st0["state_of_replica"],
+                                        st1["state_of_replica"]))
+    stats = ctx.get_stats(lid)
+    assert np.array_equal(stats["ex_try"], s.ex_try)
+    assert np.array_equal(stats["ex_acc"], s.ex_acc)
+    assert stats["ex_try"].sum() == 6 * 25 * (lig.n_states - 1)
+    assert moved > 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("exchange_sweeps", [1, 25])
+def test_exchange_sweeps_graph_replays_match_plain_launches(exchange_sweeps):
+    """Scheme-1 sweeps replayed from captured graphs (chunks of 8 sweeps, and
+    units closed by external moves) equal plain launches bitwise, with and
+    without repeated exchange sweeps."""
+    print_case("exchange sweeps graph", exchange_sweeps)
+    system = synth.make_system(1)
+    lig, g = system.ligands[0], system.grid
+    runs = []
+    for chunk in (0, 8):
+        ctx, (lid,) = make_context(g, [lig], seed=19, capacity=40)
+        ctx.set_graph(chunk)
+        states = []
+        for rep in range(3):
+            ctx.hmc_sweep(16, 10, exchange_every=1, exchange_scheme=1,
+                          max_sep=5, sample_every=2,
+                          exchange_sweeps=exchange_sweeps)
+            states.append(ctx.get_replicas(lid))
+            ctx.hmc_sweep(4, 10, exchange_every=2, exchange_scheme=1,
+                          max_sep=3, exchange_sweeps=exchange_sweeps,
+                          external_moves=3, external_k_max=2)
+            states.append(ctx.get_replicas(lid))
+        xs, cs = ctx.get_samples(lid)
+        runs.append((states, xs, cs, ctx.get_stats(lid)))
+        ctx.close()
+    (sa, xa, ca, ta), (sb, xb, cb, tb) = runs
+    for a, b in zip(sa, sb):
+        for key in ("x", "state_of_replica", "comps", "counter"):
+            assert np.array_equal(a[key], b[key]), key
+    assert np.array_equal(xa, xb) and np.array_equal(ca, cb)
+    for key in ("hmc_acc", "hmc_try", "ex_acc", "ex_try"):
+        assert np.array_equal(ta[key], tb[key]), key
+    n_ex = 3 * (16 + 2) * exchange_sweeps * (lig.n_states - 1)
+    assert ta["ex_try"].sum() == n_ex
 
 
 def test_graph_replays_match_plain_launches():
