@@ -475,6 +475,192 @@ BPMF_API int bpmf_get_pose_stats(bpmf_ctx* ctx, int ligand_id, int64_t* acc,
                                  int64_t* tries, double* last_ln_alpha);
 
 /* ------------------------------------------------------------------------
+ * Ligand information, state parameters, single-ligand sweeps
+ * ------------------------------------------------------------------------ */
+
+/* Sizes of a ligand (host outputs, any may be NULL). */
+BPMF_API int bpmf_ligand_info(bpmf_ctx* ctx, int ligand_id, int* n_atoms,
+                              int* n_states, int* n_channels,
+                              int* sample_capacity);
+
+/* Replace the K thermodynamic states of a ligand: T (K temperatures, > 0),
+ * w (K x n_channels grid weights), dt_fs (K time steps, > 0), host arrays.
+ * Replicas, cached energy components (which do not depend on the state),
+ * statistics and samples are kept; captured sweep graphs stay valid.
+ * Synchronises. */
+BPMF_API int bpmf_set_states(bpmf_ctx* ctx, int ligand_id, const double* T,
+                             const double* w, const double* dt_fs);
+
+/* bpmf_hmc_sweep restricted to one ligand: only its replicas move, only its
+ * counter, statistics and samples change. */
+BPMF_API int bpmf_hmc_sweep_ligand(bpmf_ctx* ctx, int ligand_id,
+                                   const bpmf_sweep_args* args);
+
+/* ------------------------------------------------------------------------
+ * Ladder initialisation (Initialization; state insertion and equilibration
+ * detection from Equilibration and production)
+ * ------------------------------------------------------------------------ */
+#define BPMF_SCHEDULE_LINEAR 0 /* every channel weighted by alpha */
+#define BPMF_SCHEDULE_SOFT 1   /* Thermodynamic Cycle: channels rep, att, ele
+                                  weighted by alpha_g = (2a-1)^2 / (1 +
+                                  exp(-1000 (a - 1/2))), soft rep and soft ele
+                                  by alpha_sg = 1 - (2a-1)^2 */
+
+/* Temperature T(alpha) = (T_cold - T_hot) alpha + T_hot and the n_channels
+ * weights w of the state at alpha in [0, 1] (host outputs). */
+BPMF_API int bpmf_protocol_state(double alpha, int kind, int n_channels,
+                                 double T_hot, double T_cold, double* T,
+                                 double* w);
+
+/* Population standard deviations over n samples with cached components
+ * comps (host, n x (1 + n_channels): U0, Psi_c) in the state at alpha:
+ * sigma[0] of Psi_g (the original grids' channels summed), sigma[1] of
+ * Psi_sg (the soft grids'; 0 for the linear schedule), sigma[2] of the
+ * reduced energy u = (U0 + sum_c w_c Psi_c) / (R T). */
+BPMF_API int bpmf_protocol_sigmas(const double* comps, int64_t n,
+                                  int n_channels, double alpha, int kind,
+                                  double T_hot, double T_cold, double* sigma);
+
+/* Parameter selection (Initialization, thermodynamic length): the next
+ * alpha = alpha + speed / [ |d alpha_sg / d alpha| sigma[1] / (R T) +
+ * |d alpha_g / d alpha| sigma[0] / (R T) + |T_cold - T_hot| sigma[2] / T ]
+ * (the linear schedule: d alpha_g / d alpha = 1, no soft term), never past
+ * 1; 1 when the bracket is 0.  The paper's speed is 0.2. */
+BPMF_API int bpmf_protocol_next_alpha(double alpha, const double* sigma,
+                                      int kind, double speed, double T_hot,
+                                      double T_cold, double* next);
+
+/* Temperature-only path: T moves towards T_target by speed R T^2 /
+ * sigma_U and stops there (the paper's speed is 20). */
+BPMF_API int bpmf_protocol_next_temperature(double T, double sigma_U,
+                                            double speed, double T_target,
+                                            double* next);
+
+/* Seed selection by sampling importance resampling: n_draw indices into n
+ * samples (host idx), drawn with replacement with probability proportional
+ * to exp(log_w) (non-finite log_w: weight 0).  Draw j inverts the
+ * cumulative weights (summed in index order after subtracting the largest
+ * log_w) at u_j times the total, u_j the Philox uniform (index j, ligand
+ * ligand_id, replica 0, counter `state`, purpose 7). */
+BPMF_API int bpmf_protocol_sir(const double* log_w, int64_t n, int n_draw,
+                               uint64_t seed, int ligand_id, int state,
+                               int64_t* idx);
+
+/* Time-step rule: acceptance above 0.8: dt + 0.125 fs; below 0.1: dt -
+ * 0.5 fs; below 0.4: dt - 0.25 fs (never below dt_min); *done = 1 when the
+ * acceptance lies in [0.4, 0.8] or dt is already at dt_min. */
+BPMF_API int bpmf_protocol_adapt_dt(double dt, double acc, double dt_min,
+                                    double* new_dt, int* done);
+
+/* Mean over n pairs of min(1, exp(-[u_k(y) + u_k+1(x) - u_k(x) -
+ * u_k+1(y)])) (Eq. repXacc; a non-finite exponent counts 0), host arrays
+ * of the four reduced energies per pair. */
+BPMF_API int bpmf_protocol_mean_pacc(const double* uk_x, const double* uk1_x,
+                                     const double* uk_y, const double* uk1_y,
+                                     int64_t n, double* mean);
+
+/* State insertion between cycles: out (host, up to max_out) is the ladder
+ * alpha (K states) with a state at the midpoint of every neighbour pair
+ * whose exchange acceptance pacc[k] (K - 1 values) is below threshold (the
+ * paper: 0.4). */
+BPMF_API int bpmf_protocol_insert(const double* alpha, int K,
+                                  const double* pacc, double threshold,
+                                  int max_out, double* out, int* K_out);
+
+/* Equilibration detection (Chodera 2016): among the n_candidates starts
+ * t0 = floor(i n / n_candidates) the one that maximises the number of
+ * uncorrelated samples (n - t0) / g(a[t0:]) (ties: the earlier), g = 1 + 2
+ * sum_t (1 - t/N) C_t / C_0 stopped at the first C_t <= 0. */
+BPMF_API int bpmf_detect_equilibration(const double* a, int64_t n,
+                                       int n_candidates, int64_t* t0,
+                                       double* g, double* n_eff);
+
+/* Random placements (Initialization: configurations put at random
+ * centre-of-mass positions in the binding site with random orientations):
+ * poses [first, first + count) of n_conf configurations dev_confs (device,
+ * n_conf x n_atoms x 3) at n_com site positions x n_orient orientations,
+ * pose (c * n_com + i) * n_orient + o, written to dev_out (device, count x
+ * n_atoms x 3; count x n_atoms < 2^32).  Position i: the ligand's site
+ * centre + d0 u^(1/3) (sin t cos p, sin t sin p, cos t), cos t = 2u - 1,
+ * p = 2 pi u (Philox index i, purpose 7 | 1<<8); orientation o: the
+ * rotation of the uniform unit quaternion of three uniforms (index o,
+ * purpose 7 | 2<<8), applied about the configuration's mass-weighted
+ * centre. */
+BPMF_API int bpmf_place_poses(bpmf_ctx* ctx, int ligand_id,
+                              const float* dev_confs, int n_conf, int n_com,
+                              int n_orient, int64_t first, int64_t count,
+                              float* dev_out);
+
+typedef struct {
+  int ligand_id;      /* ligand whose K replicas run the seeds of each state
+                         (K seeds per state); its states, replicas and
+                         samples are overwritten */
+  int kind;           /* BPMF_SCHEDULE_LINEAR or BPMF_SCHEDULE_SOFT */
+  double T_hot;       /* T at alpha = 0 (K) */
+  double T_cold;      /* T at alpha = 1 (K) */
+  double speed;       /* thermodynamic speed s (the paper: 0.2) */
+  int n_trials;       /* HMC trials per seed and run, <= sample capacity */
+  int n_leapfrog;     /* velocity-Verlet steps per trial */
+  double dt_start;    /* time step of state 0 (fs) */
+  double dt_min;      /* floor of the adapted time step (fs) */
+  int max_dt_rounds;  /* runs per selection at most while adapting dt */
+  int max_selections; /* selections per state at most (speed x 4/5 between) */
+  int n_conf, n_com, n_orient; /* n_com > 0: state 0's sample set is the
+                         placements (bpmf_place_poses) of the final
+                         configurations of its first n_conf (<= K) replicas
+                         at n_com positions x n_orient orientations (the
+                         paper: 50 x 453 x 100); 0: its own samples */
+  int max_states;     /* capacity of the result arrays, >= 2 */
+} bpmf_init_args;
+
+#define BPMF_TRACE_FIELDS 10
+typedef struct {
+  /* outputs */
+  int n_states;       /* states in the ladder */
+  int reached_target; /* 1 when the last state has alpha = 1 */
+  int n_selections;   /* selections made, repeats included */
+  int n_runs;         /* sampling runs made, time-step repeats included */
+  int n_removed;      /* states dropped for p_acc above 0.99 */
+  int n_trace;        /* trace records written */
+  /* host arrays, sized by max_states */
+  double* alpha;
+  double* T;
+  double* w;          /* max_states x n_channels */
+  double* dt;         /* time step of the state's last run (fs) */
+  double* acc;        /* HMC acceptance of that run */
+  double* pacc;       /* verified mean exchange acceptance with the state it
+                         was selected from (1 for state 0) */
+  double* sigma;      /* may be NULL; max_states x 3 (bpmf_protocol_sigmas
+                         of the state's sample set) */
+  float* x;           /* may be NULL; max_states x K x n_atoms x 3 final
+                         configurations of the state's last run */
+  double* trace;      /* may be NULL; trace_cap x BPMF_TRACE_FIELDS, one
+                         record per selection: alpha_from, its sigma[0..2],
+                         speed, alpha_new, dt, acceptance, p_acc, outcome (0
+                         appended, 1 repeated with speed x 4/5, 2 replaced
+                         the state it came from) */
+  int trace_cap;
+} bpmf_init_result;
+
+/* Initialise a ladder of states from alpha = 0 (T_hot, grids off) to alpha
+ * = 1 (T_cold, grids on) (Initialization).  State 0 runs from the ligand's
+ * current replicas.  Then, until alpha = 1 or max_states: the next alpha
+ * by bpmf_protocol_next_alpha from the last state's sample set; K seeds by
+ * bpmf_protocol_sir with weights exp[u_k - u_new] (counter = the new
+ * state's index); K runs of n_trials HMC trials from the seeds, repeated
+ * with the time step changed by bpmf_protocol_adapt_dt until it is done or
+ * max_dt_rounds runs were made (the first run starts from the previous
+ * state's time step); p_acc by bpmf_protocol_mean_pacc over pairs spread
+ * evenly over both sample sets (sample i with sample i when the sets are
+ * equal in size).  p_acc below 0.4: select again with speed x 4/5 (at most
+ * max_selections times); above 0.99: the new state replaces the previous
+ * one unless that is state 0.  A state's sample set is its last run's
+ * recorded samples (n_trials x K).  Synchronises; leaves the ligand's
+ * replicas, states and samples at the last state's last run. */
+BPMF_API int bpmf_initialize_ladder(bpmf_ctx* ctx, const bpmf_init_args* args,
+                                    bpmf_init_result* result);
+
+/* ------------------------------------------------------------------------
  * Launch shape
  * ------------------------------------------------------------------------ */
 

@@ -11,6 +11,14 @@ importing fails if the library has not been built.
 from __future__ import annotations
 
 from ._binding import (BPMFError, Context, LIB_PATH, library,  # noqa: F401
-                       EXPORTED)
+                       EXPORTED, SCHEDULE_LINEAR, SCHEDULE_SOFT,
+                       detect_equilibration, protocol_adapt_dt,
+                       protocol_insert, protocol_mean_pacc,
+                       protocol_next_alpha, protocol_next_temperature,
+                       protocol_sigmas, protocol_sir, protocol_state)
 
-__all__ = ["BPMFError", "Context", "LIB_PATH", "library", "EXPORTED"]
+__all__ = ["BPMFError", "Context", "LIB_PATH", "library", "EXPORTED",
+           "SCHEDULE_LINEAR", "SCHEDULE_SOFT", "detect_equilibration",
+           "protocol_adapt_dt", "protocol_insert", "protocol_mean_pacc",
+           "protocol_next_alpha", "protocol_next_temperature",
+           "protocol_sigmas", "protocol_sir", "protocol_state"]

@@ -53,6 +53,33 @@ class _SweepArgs(C.Structure):
                 ("exchange_sweeps", C.c_int)]
 
 
+class _InitArgs(C.Structure):
+    _fields_ = [("ligand_id", C.c_int), ("kind", C.c_int),
+                ("T_hot", C.c_double), ("T_cold", C.c_double),
+                ("speed", C.c_double), ("n_trials", C.c_int),
+                ("n_leapfrog", C.c_int), ("dt_start", C.c_double),
+                ("dt_min", C.c_double), ("max_dt_rounds", C.c_int),
+                ("max_selections", C.c_int), ("n_conf", C.c_int),
+                ("n_com", C.c_int), ("n_orient", C.c_int),
+                ("max_states", C.c_int)]
+
+
+class _InitResult(C.Structure):
+    _fields_ = [("n_states", C.c_int), ("reached_target", C.c_int),
+                ("n_selections", C.c_int), ("n_runs", C.c_int),
+                ("n_removed", C.c_int), ("n_trace", C.c_int),
+                ("alpha", C.POINTER(C.c_double)), ("T", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double)), ("dt", C.POINTER(C.c_double)),
+                ("acc", C.POINTER(C.c_double)),
+                ("pacc", C.POINTER(C.c_double)),
+                ("sigma", C.POINTER(C.c_double)),
+                ("x", C.POINTER(C.c_float)),
+                ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int)]
+
+
+TRACE_FIELDS = 10
+SCHEDULE_LINEAR, SCHEDULE_SOFT = 0, 1
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -128,6 +155,27 @@ def library():
         "bpmf_get_external_stats": [vp, C.c_int, i64p, i64p],
         "bpmf_get_waves": [vp, C.c_int, ip],
         "bpmf_get_timing": [vp, C.c_int, dp, i64p],
+        "bpmf_ligand_info": [vp, C.c_int, ip, ip, ip, ip],
+        "bpmf_set_states": [vp, C.c_int, dp, dp, dp],
+        "bpmf_hmc_sweep_ligand": [vp, C.c_int, C.POINTER(_SweepArgs)],
+        "bpmf_place_poses": [vp, C.c_int, vp, C.c_int, C.c_int, C.c_int,
+                             C.c_int64, C.c_int64, vp],
+        "bpmf_protocol_state": [C.c_double, C.c_int, C.c_int, C.c_double,
+                                C.c_double, dp, dp],
+        "bpmf_protocol_sigmas": [dp, C.c_int64, C.c_int, C.c_double, C.c_int,
+                                 C.c_double, C.c_double, dp],
+        "bpmf_protocol_next_alpha": [C.c_double, dp, C.c_int, C.c_double,
+                                     C.c_double, C.c_double, dp],
+        "bpmf_protocol_next_temperature": [C.c_double, C.c_double,
+                                           C.c_double, C.c_double, dp],
+        "bpmf_protocol_sir": [dp, C.c_int64, C.c_int, C.c_uint64, C.c_int,
+                              C.c_int, i64p],
+        "bpmf_protocol_adapt_dt": [C.c_double, C.c_double, C.c_double, dp, ip],
+        "bpmf_protocol_mean_pacc": [dp, dp, dp, dp, C.c_int64, dp],
+        "bpmf_protocol_insert": [dp, C.c_int, dp, C.c_double, C.c_int, dp, ip],
+        "bpmf_detect_equilibration": [dp, C.c_int64, C.c_int, i64p, dp, dp],
+        "bpmf_initialize_ladder": [vp, C.POINTER(_InitArgs),
+                                   C.POINTER(_InitResult)],
         "bpmf_version": [],
         "bpmf_last_error": [],
     }
@@ -156,6 +204,93 @@ def _pi(a):
 
 def _pf(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+# -- ladder initialisation: host-side steps (no context, no device) ----------
+def protocol_state(alpha, kind, n_channels, T_hot, T_cold):
+    T = C.c_double(0.0)
+    w = np.zeros(n_channels)
+    _check(library().bpmf_protocol_state(float(alpha), int(kind),
+                                         int(n_channels), float(T_hot),
+                                         float(T_cold), C.byref(T), _pd(w)))
+    return T.value, w
+
+
+def protocol_sigmas(comps, alpha, kind, T_hot, T_cold):
+    comps = np.ascontiguousarray(comps, np.float64)
+    out = np.zeros(3)
+    _check(library().bpmf_protocol_sigmas(_pd(comps), comps.shape[0],
+                                          comps.shape[1] - 1, float(alpha),
+                                          int(kind), float(T_hot),
+                                          float(T_cold), _pd(out)))
+    return out
+
+
+def protocol_next_alpha(alpha, sigma, kind, speed, T_hot, T_cold):
+    sg = np.ascontiguousarray(sigma, np.float64)
+    out = C.c_double(0.0)
+    _check(library().bpmf_protocol_next_alpha(float(alpha), _pd(sg), int(kind),
+                                              float(speed), float(T_hot),
+                                              float(T_cold), C.byref(out)))
+    return out.value
+
+
+def protocol_next_temperature(T, sigma_U, speed, T_target):
+    out = C.c_double(0.0)
+    _check(library().bpmf_protocol_next_temperature(
+        float(T), float(sigma_U), float(speed), float(T_target),
+        C.byref(out)))
+    return out.value
+
+
+def protocol_sir(log_w, n_draw, seed, ligand_id, state):
+    lw = np.ascontiguousarray(log_w, np.float64)
+    idx = np.zeros(int(n_draw), np.int64)
+    _check(library().bpmf_protocol_sir(
+        _pd(lw), lw.shape[0], int(n_draw), int(seed), int(ligand_id),
+        int(state), idx.ctypes.data_as(C.POINTER(C.c_int64))))
+    return idx
+
+
+def protocol_adapt_dt(dt, acc, dt_min):
+    nd = C.c_double(0.0)
+    done = C.c_int(0)
+    _check(library().bpmf_protocol_adapt_dt(float(dt), float(acc),
+                                            float(dt_min), C.byref(nd),
+                                            C.byref(done)))
+    return nd.value, bool(done.value)
+
+
+def protocol_mean_pacc(uk_x, uk1_x, uk_y, uk1_y):
+    a = [np.ascontiguousarray(v, np.float64) for v in (uk_x, uk1_x, uk_y,
+                                                       uk1_y)]
+    out = C.c_double(0.0)
+    _check(library().bpmf_protocol_mean_pacc(*[_pd(v) for v in a],
+                                             a[0].shape[0], C.byref(out)))
+    return out.value
+
+
+def protocol_insert(alpha, pacc, threshold=0.4):
+    al = np.ascontiguousarray(alpha, np.float64)
+    pa = np.ascontiguousarray(pacc, np.float64)
+    out = np.zeros(2 * len(al))
+    K = C.c_int(0)
+    _check(library().bpmf_protocol_insert(_pd(al), len(al), _pd(pa),
+                                          float(threshold), len(out),
+                                          _pd(out), C.byref(K)))
+    return out[:K.value].copy()
+
+
+def detect_equilibration(a, n_candidates=100):
+    a = np.ascontiguousarray(a, np.float64)
+    t0 = C.c_int64(0)
+    g = C.c_double(0.0)
+    ne = C.c_double(0.0)
+    _check(library().bpmf_detect_equilibration(_pd(a), a.shape[0],
+                                               int(n_candidates),
+                                               C.byref(t0), C.byref(g),
+                                               C.byref(ne)))
+    return t0.value, g.value, ne.value
 
 
 class Context:
@@ -623,3 +758,84 @@ class Context:
 
     def reset_samples(self, ligand_id=-1):
         _check(self._lib.bpmf_reset_samples(self._h, int(ligand_id)))
+
+    # -- single-ligand control, ladder initialisation --------------------------
+    def ligand_info(self, ligand_id):
+        v = [C.c_int(0) for _ in range(4)]
+        _check(self._lib.bpmf_ligand_info(self._h, int(ligand_id),
+                                          *[C.byref(x) for x in v]))
+        return dict(n_atoms=v[0].value, n_states=v[1].value,
+                    n_channels=v[2].value, sample_capacity=v[3].value)
+
+    def set_states(self, ligand_id, T, w, dt):
+        T = np.ascontiguousarray(T, np.float64)
+        w = np.ascontiguousarray(w, np.float64)
+        dt = np.ascontiguousarray(dt, np.float64)
+        _check(self._lib.bpmf_set_states(self._h, int(ligand_id), _pd(T),
+                                         _pd(w), _pd(dt)))
+
+    def hmc_sweep_ligand(self, ligand_id, n_sweeps, n_leapfrog,
+                         exchange_every=1, exchange_scheme=0, max_sep=1,
+                         sample_every=0, pose_move_every=0, external_moves=0,
+                         external_k_max=0, external_sigma=0.6,
+                         exchange_sweeps=1):
+        a = _SweepArgs(int(n_sweeps), int(n_leapfrog), int(exchange_every),
+                       int(exchange_scheme), int(max_sep), int(sample_every),
+                       int(pose_move_every), int(external_moves),
+                       int(external_k_max), float(external_sigma),
+                       int(exchange_sweeps))
+        _check(self._lib.bpmf_hmc_sweep_ligand(self._h, int(ligand_id),
+                                               C.byref(a)))
+
+    def place_poses(self, ligand_id, confs, n_com, n_orient, first=0,
+                    count=None, out=None):
+        torch = self._torch
+        assert confs.is_cuda and confs.dtype == torch.float32 \
+            and confs.is_contiguous()
+        n_conf, n = confs.shape[0], confs.shape[1]
+        total = n_conf * int(n_com) * int(n_orient)
+        if count is None:
+            count = total - int(first)
+        if out is None:
+            out = torch.empty((int(count), n, 3), dtype=torch.float32,
+                              device=f"cuda:{self.device}")
+        _check(self._lib.bpmf_place_poses(
+            self._h, int(ligand_id), confs.data_ptr(), int(n_conf),
+            int(n_com), int(n_orient), int(first), int(count),
+            out.data_ptr()))
+        return out
+
+    def initialize_ladder(self, ligand_id, kind, T_hot, T_cold, speed=0.2,
+                          n_trials=200, n_leapfrog=10, dt_start=1.0,
+                          dt_min=0.125, max_dt_rounds=8, max_selections=6,
+                          n_conf=0, n_com=0, n_orient=0, max_states=256,
+                          trace_cap=1024, want_x=True):
+        info = self.ligand_info(ligand_id)
+        K, n, nc = info["n_states"], info["n_atoms"], info["n_channels"]
+        M = int(max_states)
+        a = _InitArgs(int(ligand_id), int(kind), float(T_hot), float(T_cold),
+                      float(speed), int(n_trials), int(n_leapfrog),
+                      float(dt_start), float(dt_min), int(max_dt_rounds),
+                      int(max_selections), int(n_conf), int(n_com),
+                      int(n_orient), M)
+        arr = dict(alpha=np.zeros(M), T=np.zeros(M), w=np.zeros((M, nc)),
+                   dt=np.zeros(M), acc=np.zeros(M), pacc=np.zeros(M),
+                   sigma=np.zeros((M, 3)),
+                   trace=np.zeros((int(trace_cap), TRACE_FIELDS)))
+        x = np.zeros((M, K, n, 3), np.float32) if want_x else None
+        r = _InitResult()
+        for k in ("alpha", "T", "w", "dt", "acc", "pacc", "sigma", "trace"):
+            setattr(r, k, _pd(arr[k]))
+        r.x = _pf(x) if want_x else None
+        r.trace_cap = int(trace_cap)
+        _check(self._lib.bpmf_initialize_ladder(self._h, C.byref(a),
+                                                C.byref(r)))
+        m = r.n_states
+        out = {k: arr[k][:m].copy() for k in ("alpha", "T", "w", "dt", "acc",
+                                              "pacc", "sigma")}
+        out["trace"] = arr["trace"][:r.n_trace].copy()
+        out["x"] = x[:m].copy() if want_x else None
+        out.update(n_states=m, reached_target=bool(r.reached_target),
+                   n_selections=r.n_selections, n_runs=r.n_runs,
+                   n_removed=r.n_removed)
+        return out

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbpmf.so")
-SOURCES = ["api.hip", "kernels.hip", "mbar.hip", "mlp.hip", "moves.hip"]
+SOURCES = ["api.hip", "kernels.hip", "mbar.hip", "mlp.hip", "moves.hip",
+           "protocol.hip"]
 ARCH = os.environ.get("BPMF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

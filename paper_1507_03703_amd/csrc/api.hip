@@ -15,6 +15,7 @@
 #include "internal.h"
 #include "moves.h"
 #include "mlp.h"
+#include "protocol.h"
 
 using namespace bpmf;
 
@@ -113,6 +114,8 @@ struct bpmf_ctx {
   size_t mbar_bytes = 0;
   void* mlp_mem = nullptr;   // activations of the proposal network
   size_t mlp_bytes = 0;
+  void* place_mem = nullptr;  // centres of mass of placed configurations
+  size_t place_bytes = 0;
   // kernel timing
   static constexpr int kTimers = 4;
   static constexpr size_t kMaxPairs = 8192;
@@ -129,7 +132,7 @@ struct bpmf_ctx {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   uint64_t table_version = 0, graph_version = ~0ull;
-  static constexpr int kKey = 13;
+  static constexpr int kKey = 14;
   int graph_key[kKey] = {0};
 
   void drop_graph() {
@@ -352,6 +355,7 @@ extern "C" int bpmf_destroy(bpmf_ctx* c) {
     c->dfree(l.prop_arena);
   }
   c->dfree(c->mlp_mem);
+  c->dfree(c->place_mem);
   c->dfree(c->grid_mem);
   c->dfree(c->d_ligs);
   c->dfree(c->d_tasks);
@@ -757,11 +761,16 @@ int check_external(int n_moves, int k_max, double sigma);
 // ============================================================================
 // sampling
 // ============================================================================
-extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
+// sweeps of every ligand (only = -1) or of ligand `only` alone
+static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!a) return fail(BPMF_E_INVAL, "null sweep arguments");
   if (c->ligs.empty()) return fail(BPMF_E_STATE, "no ligand set up");
+  if (only >= 0 && (rc = check_lig(c, only))) return rc;
+  // the ligands this call advances: [l0, l1)
+  const int l0 = only >= 0 ? only : 0;
+  const int l1 = only >= 0 ? only + 1 : (int)c->ligs.size();
   if (a->n_sweeps < 0 || a->n_leapfrog < 1 || a->exchange_every < 0 ||
       a->sample_every < 0)
     return fail(BPMF_E_INVAL, "bad sweep arguments (n_sweeps %d, n_leapfrog %d,"
@@ -785,37 +794,45 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
   // sample capacity check (host mirrors of the device counters)
   std::vector<int64_t> add(c->ligs.size(), 0);
   if (a->sample_every > 0) {
-    for (size_t l = 0; l < c->ligs.size(); ++l) {
+    for (int l = l0; l < l1; ++l) {
       const LigHost& h = c->ligs[l];
       const int64_t se = a->sample_every;
       add[l] = (int64_t)((h.counter + a->n_sweeps) / se) -
                (int64_t)(h.counter / se);
       if (h.n_rec + add[l] > h.dev.cap)
         return fail(BPMF_E_INVAL,
-                    "ligand %zu: %lld recorded + %lld new samples per state "
+                    "ligand %d: %lld recorded + %lld new samples per state "
                     "exceed capacity %d", l, (long long)h.n_rec,
                     (long long)add[l], h.dev.cap);
     }
   }
   TailArgs tail{a->exchange_every, a->exchange_scheme, a->max_sep,
                 a->sample_every, n_sub};
-  const int nl = (int)c->ligs.size();
+  const int nl = l1 - l0;
+  const LigDev* dl = c->d_ligs + l0;  // table entries of the call's ligands
   // scheme 0: each sweep applies the previous one's exchange and record in
   // its own blocks (begin/finish kernels bracket the run); scheme 1: a tail
   // kernel after every sweep
   auto enqueue_sweep = [&](hipStream_t st) -> int {
-    for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
-      if (c->class_n[q])
-        HIP_TRY(launch_hmc_sweep(
-            c->grid, c->d_ligs, c->d_tasks + c->class_off[q], c->class_n[q],
-            1 << q, c->class_lds[q], a->n_leapfrog, c->seed, tail,
-            c->class_single[q] >= 0 ? &c->ligs[c->class_single[q]].dev
-                                    : nullptr,
-            st));
+    if (only >= 0) {
+      const LigHost& h = c->ligs[only];
+      HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs, nullptr, h.dev.K,
+                               h.sweep_waves, lds_of(h, h.sweep_waves, true),
+                               a->n_leapfrog, c->seed, tail, &h.dev, st));
+    } else {
+      for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
+        if (c->class_n[q])
+          HIP_TRY(launch_hmc_sweep(
+              c->grid, c->d_ligs, c->d_tasks + c->class_off[q], c->class_n[q],
+              1 << q, c->class_lds[q], a->n_leapfrog, c->seed, tail,
+              c->class_single[q] >= 0 ? &c->ligs[c->class_single[q]].dev
+                                      : nullptr,
+              st));
+    }
     if (tail.scheme == 1)
-      HIP_TRY(launch_sweep_tail(c->d_ligs, nl, tail.exchange_every,
-                                tail.scheme, tail.max_sep, n_sub,
-                                tail.sample_every, c->seed, st));
+      HIP_TRY(launch_sweep_tail(dl, nl, tail.exchange_every, tail.scheme,
+                                tail.max_sep, n_sub, tail.sample_every,
+                                c->seed, st));
     return BPMF_OK;
   };
   if (a->n_sweeps == 0) return BPMF_OK;
@@ -824,13 +841,13 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
   const int P = a->pose_move_every > 0 ? a->pose_move_every : (NX > 0 ? 1 : 0);
   // a run of `count` sweeps with its exchange/record bookkeeping
   auto enqueue_run = [&](hipStream_t st, int count) -> int {
-    if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(c->d_ligs, nl, st));
+    if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(dl, nl, st));
     for (int s = 0; s < count; ++s) {
       const int r = enqueue_sweep(st);
       if (r) return r;
     }
     if (tail.scheme == 0)
-      HIP_TRY(launch_sweep_finish(c->d_ligs, nl, tail.exchange_every,
+      HIP_TRY(launch_sweep_finish(dl, nl, tail.exchange_every,
                                   tail.sample_every, c->seed, st));
     return BPMF_OK;
   };
@@ -838,13 +855,13 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
   // the external moves of every ligand
   auto enqueue_pose = [&](hipStream_t st) -> int {
     if (a->pose_move_every > 0)
-      for (int l = 0; l < nl; ++l)
+      for (int l = l0; l < l1; ++l)
         if (c->ligs[l].has_prop) {
           const int r = pose_move_ligand(c, l, st);
           if (r) return r;
         }
     if (NX > 0)
-      for (int l = 0; l < nl; ++l) {
+      for (int l = l0; l < l1; ++l) {
         const int r = external_move_ligand(c, l, NX, a->external_k_max,
                                            a->external_sigma, st);
         if (r) return r;
@@ -892,8 +909,10 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
     // units of P sweeps, each followed by the unit's moves; the network's
     // scratch is sized before any capture
     int maxK = 0;
-    for (auto& h : c->ligs)
+    for (int l = l0; l < l1; ++l) {
+      const LigHost& h = c->ligs[l];
       if (h.has_prop && a->pose_move_every > 0) maxK = std::max(maxK, h.dev.K);
+    }
     if (maxK > 0) {
       MlpBufs b;
       if ((rc = mlp_scratch(c, maxK, &b))) return rc;
@@ -909,7 +928,7 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
       const int key[bpmf_ctx::kKey] = {
           a->n_leapfrog, a->exchange_every, a->exchange_scheme, a->max_sep,
           a->sample_every, 0, P, a->pose_move_every, NX, a->external_k_max,
-          sg[0], sg[1], n_sub};
+          sg[0], sg[1], n_sub, only};
       if ((rc = ensure_graph(key, unit))) return rc;
       for (int u = 0; u < units; ++u)
         if ((rc = launch_timed(P, [&]() -> int {
@@ -925,12 +944,12 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
         (rc = launch_timed(rest, [&] { return enqueue_run(c->stream, rest); })))
       return rc;
   } else {
-    if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(c->d_ligs, nl, c->stream));
+    if (tail.scheme == 0) HIP_TRY(launch_sweep_begin(dl, nl, c->stream));
     int done = 0;
     if (chunk > 0 && a->n_sweeps >= chunk) {
       const int key[bpmf_ctx::kKey] = {
           a->n_leapfrog, a->exchange_every, a->exchange_scheme, a->max_sep,
-          a->sample_every, chunk, 0, 0, 0, 0, 0, -1, n_sub};
+          a->sample_every, chunk, 0, 0, 0, 0, 0, -1, n_sub, only};
       if ((rc = ensure_graph(key, [&](hipStream_t st) -> int {
              for (int s = 0; s < chunk; ++s) {
                const int r = enqueue_sweep(st);
@@ -953,16 +972,26 @@ extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
       hipEvent_t t0, t1;
       const bool timed = c->timer_begin(BPMF_TIMER_TAIL, &t0, &t1);
       if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
-      HIP_TRY(launch_sweep_finish(c->d_ligs, nl, tail.exchange_every,
+      HIP_TRY(launch_sweep_finish(dl, nl, tail.exchange_every,
                                   tail.sample_every, c->seed, c->stream));
       if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
     }
   }
-  for (size_t l = 0; l < c->ligs.size(); ++l) {
+  for (int l = l0; l < l1; ++l) {
     c->ligs[l].counter += (uint64_t)a->n_sweeps;
     c->ligs[l].n_rec += add[l];
   }
   return BPMF_OK;
+}
+
+extern "C" int bpmf_hmc_sweep(bpmf_ctx* c, const bpmf_sweep_args* a) {
+  return hmc_sweep_impl(c, a, -1);
+}
+
+extern "C" int bpmf_hmc_sweep_ligand(bpmf_ctx* c, int ligand_id,
+                                     const bpmf_sweep_args* a) {
+  if (c && check_lig(c, ligand_id)) return BPMF_E_INVAL;
+  return hmc_sweep_impl(c, a, ligand_id);
 }
 
 extern "C" int bpmf_exchange(bpmf_ctx* c, int ligand_id, int scheme,
@@ -1549,6 +1578,100 @@ extern "C" int bpmf_set_replicas(bpmf_ctx* c, int ligand_id, const float* x,
   h.counter = counter;
   return BPMF_OK;
 }
+
+extern "C" int bpmf_ligand_info(bpmf_ctx* c, int ligand_id, int* n_atoms,
+                                int* n_states, int* n_channels,
+                                int* sample_capacity) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  const LigDev& L = c->ligs[ligand_id].dev;
+  if (n_atoms) *n_atoms = L.n;
+  if (n_states) *n_states = L.K;
+  if (n_channels) *n_channels = L.C;
+  if (sample_capacity) *sample_capacity = L.cap;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_set_states(bpmf_ctx* c, int ligand_id, const double* T,
+                               const double* w, const double* dt_fs) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  if (!T || !w || !dt_fs) return fail(BPMF_E_INVAL, "null state array");
+  LigHost& h = c->ligs[ligand_id];
+  const LigDev& L = h.dev;
+  const int K = L.K, C = L.C;
+  for (int k = 0; k < K; ++k) {
+    if (!(T[k] > 0) || !isfinite(T[k]))
+      return fail(BPMF_E_INVAL, "T[%d] must be positive and finite", k);
+    if (!(dt_fs[k] > 0) || !isfinite(dt_fs[k]))
+      return fail(BPMF_E_INVAL, "dt[%d] must be positive and finite", k);
+  }
+  if (!finite_all(w, (size_t)K * C))
+    return fail(BPMF_E_INVAL, "non-finite state weight");
+  std::vector<double> beta(K), wd(w, w + (size_t)K * C);
+  std::vector<float> Tf(K), dtf(K), wf((size_t)K * C);
+  for (int k = 0; k < K; ++k) {
+    beta[k] = 1.0 / (kRGas * T[k]);
+    Tf[k] = (float)T[k];
+    dtf[k] = (float)dt_fs[k];
+  }
+  for (size_t i = 0; i < wf.size(); ++i) wf[i] = (float)w[i];
+  // the arrays are read by kernels already in the stream: replace them in
+  // stream order, then wait so that the host buffers can go
+  HIP_TRY(hipMemcpyAsync((void*)L.beta, beta.data(), K * 8,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync((void*)L.Tf, Tf.data(), K * 4, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync((void*)L.dtf, dtf.data(), K * 4,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync((void*)L.wf, wf.data(), wf.size() * 4,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync((void*)L.wd, wd.data(), wd.size() * 8,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  h.beta = beta;
+  h.wd = wd;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_place_poses(bpmf_ctx* c, int ligand_id,
+                                const float* dev_confs, int n_conf, int n_com,
+                                int n_orient, int64_t first, int64_t count,
+                                float* dev_out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  if (n_conf < 1 || n_com < 1 || n_orient < 1)
+    return fail(BPMF_E_INVAL, "n_conf, n_com and n_orient must be >= 1");
+  if (n_com > (1 << 24) || n_orient > (1 << 24))
+    return fail(BPMF_E_INVAL, "n_com and n_orient are limited to 2^24");
+  const int64_t total = (int64_t)n_conf * n_com * n_orient;
+  if (first < 0 || count < 0 || first + count > total)
+    return fail(BPMF_E_INVAL, "poses [%lld, %lld) outside [0, %lld)",
+                (long long)first, (long long)(first + count),
+                (long long)total);
+  if (count == 0) return BPMF_OK;
+  if (!dev_confs || !dev_out) return fail(BPMF_E_INVAL, "null pose buffer");
+  if ((rc = ensure_scratch(c, &c->place_mem, &c->place_bytes,
+                           (size_t)n_conf * 3 * sizeof(double))))
+    return rc;
+  HIP_TRY(launch_place_poses(c->d_ligs + ligand_id, c->ligs[ligand_id].dev.n,
+                             dev_confs, n_conf, n_com, n_orient, first, count,
+                             (double*)c->place_mem, c->seed, dev_out,
+                             c->stream));
+  return BPMF_OK;
+}
+
+// accessors for the ladder-initialisation driver (protocol.hip)
+namespace bpmf {
+void* ctx_alloc(bpmf_ctx* c, size_t bytes) { return c->dalloc(bytes); }
+void ctx_free(bpmf_ctx* c, void* p) { c->dfree(p); }
+hipStream_t ctx_stream(bpmf_ctx* c) { return c->stream; }
+uint64_t ctx_seed(bpmf_ctx* c) { return c->seed; }
+int ctx_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace bpmf
 
 extern "C" int bpmf_get_stats(bpmf_ctx* c, int ligand_id, int64_t* hmc_acc,
                               int64_t* hmc_try, int64_t* ex_acc,

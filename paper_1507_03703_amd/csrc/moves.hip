@@ -215,3 +215,106 @@ hipError_t launch_external_move(const GridDev& g, const LigDev* lig, int K,
 }
 
 }  // namespace bpmf
+
+// ----------------------------------------------------------------------------
+// Random placements in the binding site (Initialization: configurations put
+// at random centre-of-mass positions in the site, each with random
+// orientations).  Site position i: radius d0 u^(1/3), cos(theta) = 2u - 1,
+// phi = 2 pi u about the site centre; orientation o: the rotation of a
+// uniform unit quaternion, applied about the configuration's centre of mass.
+// ----------------------------------------------------------------------------
+#include "protocol.h"
+
+namespace bpmf {
+
+namespace {
+
+// centre of mass of each configuration, in double
+__global__ __launch_bounds__(64) void k_conf_com(const LigDev* __restrict__ lig,
+                                                 const float* __restrict__ confs,
+                                                 int n_conf, double* com) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_conf) return;
+  const LigDev& L = *lig;
+  const int n = L.n;
+  double sx = 0, sy = 0, sz = 0, sm = 0;
+  for (int a = 0; a < n; ++a) {
+    const double m = L.mass[a];
+    const float* p = confs + ((size_t)c * n + a) * 3;
+    sx += m * p[0];
+    sy += m * p[1];
+    sz += m * p[2];
+    sm += m;
+  }
+  com[3 * c] = sx / sm;
+  com[3 * c + 1] = sy / sm;
+  com[3 * c + 2] = sz / sm;
+}
+
+// one thread per (pose, atom)
+__global__ __launch_bounds__(256) void k_place_poses(
+    const LigDev* __restrict__ lig, const float* __restrict__ confs,
+    const double* __restrict__ com, int n_com, int n_orient, int64_t first,
+    int64_t total, uint64_t seed, float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const LigDev& L = *lig;
+  const int n = L.n;
+  const int64_t q = t / n;
+  const int a = (int)(t - q * n);
+  const int64_t p = first + q;
+  const int o = (int)(p % n_orient);
+  const int64_t ci = p / n_orient;
+  const int i = (int)(ci % n_com);
+  const int c = (int)(ci / n_com);
+  // site position i
+  const U4 up = draw(seed, (uint32_t)i, L.id, 0, 0, kInit | (kSubCom << 8));
+  const double r = (double)L.d0 * cbrt(u01d(up.x));
+  const double ct = 2.0 * u01d(up.y) - 1.0;
+  const double stt = sqrt(fmax(0.0, 1.0 - ct * ct));
+  double sp, cp;
+  sincos(2.0 * M_PI * u01d(up.z), &sp, &cp);
+  const double tx = (double)L.site[0] + r * stt * cp;
+  const double ty = (double)L.site[1] + r * stt * sp;
+  const double tz = (double)L.site[2] + r * ct;
+  // orientation o: uniform unit quaternion (w, x, y, z) from three uniforms
+  const U4 uo = draw(seed, (uint32_t)o, L.id, 0, 0, kInit | (kSubOrient << 8));
+  const double u1 = u01d(uo.x), u2 = u01d(uo.y), u3 = u01d(uo.z);
+  const double qa = sqrt(1.0 - u1), qb = sqrt(u1);
+  double s2, c2, s3, c3;
+  sincos(2.0 * M_PI * u2, &s2, &c2);
+  sincos(2.0 * M_PI * u3, &s3, &c3);
+  const double qw = qb * c3, qx = qa * s2, qy = qa * c2, qz = qb * s3;
+  const float* src = confs + ((size_t)c * n + a) * 3;
+  const double dx = src[0] - com[3 * c], dy = src[1] - com[3 * c + 1],
+               dz = src[2] - com[3 * c + 2];
+  float* dst = out + t * 3;
+  dst[0] = (float)(tx + (1 - 2 * (qy * qy + qz * qz)) * dx +
+                   2 * (qx * qy - qz * qw) * dy + 2 * (qx * qz + qy * qw) * dz);
+  dst[1] = (float)(ty + 2 * (qx * qy + qz * qw) * dx +
+                   (1 - 2 * (qx * qx + qz * qz)) * dy +
+                   2 * (qy * qz - qx * qw) * dz);
+  dst[2] = (float)(tz + 2 * (qx * qz - qy * qw) * dx +
+                   2 * (qy * qz + qx * qw) * dy +
+                   (1 - 2 * (qx * qx + qy * qy)) * dz);
+}
+
+}  // namespace
+
+hipError_t launch_place_poses(const LigDev* lig, int n, const float* confs,
+                              int n_conf, int n_com, int n_orient,
+                              int64_t first, int64_t count, double* com,
+                              uint64_t seed, float* out, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_conf_com, dim3((n_conf + 63) / 64), dim3(64), 0, st,
+                     lig, confs, n_conf, com);
+  const int64_t total = count * n;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > (1ll << 24) - 1) return hipErrorInvalidValue;  // 2^32 threads
+  hipLaunchKernelGGL(k_place_poses, dim3((unsigned)blocks), dim3(256), 0, st,
+                     lig, confs, com, n_com, n_orient, first, total, seed,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace bpmf
