@@ -23,7 +23,11 @@ autotuner; --config 3 makes it the main workload instead.  A third leg
 pose moves on the 24-atom, 64-state system (the paper's soft-grid switching
 protocol): BPMF error against a long plain run and effective samples per
 second of the fully coupled state, both continuing from the long run's
-equilibrated end.
+equilibrated end.  A fourth leg ("initialization") builds that system's
+ladder with the paper's initialisation (50 seeds per state, 200 x 10-step
+HMC runs, 50 x 453 x 100 random placements as state 0's sample set, speed
+0.2) and compares neighbour exchange rates of the built ladder with the
+fixed 64-state ladder in a short production run.
 """
 from __future__ import annotations
 
@@ -105,6 +109,9 @@ def parse():
     p.add_argument("--learned-only", action="store_true",
                    help="only the learned-proposal leg (with --long-sweeps, "
                         "--prod-sweeps, --train-steps)")
+    p.add_argument("--no-init", dest="init", action="store_false",
+                   help="skip the ladder-initialisation leg")
+    p.add_argument("--init-only", action="store_true")
     p.add_argument("--long-sweeps", type=int, default=1000000)
     p.add_argument("--prod-sweeps", type=int, default=300000)
     p.add_argument("--burn-sweeps", type=int, default=100000)
@@ -598,6 +605,79 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
     }
 
 
+def init_leg(pkg, torch, n_seeds=50, n_trials=200, n_com=453, n_orient=100,
+             prod_sweeps=2000):
+    """The paper's ladder initialisation on the 24-atom soft-grid system:
+    wall time of bpmf_initialize_ladder, the ladder it builds, and the
+    neighbour exchange acceptance of a production run on it next to the
+    fixed 64-state ladder (alpha_k = k/63) of the learned-proposal leg."""
+    import dataclasses
+    import numpy as np
+    import synth
+    system = synth.make_system(4, grid_device="cuda:0")
+    g, (lig,) = synth.add_soft_grids(system.grid, system.ligands)
+    L = system.n_leapfrog
+    init = dataclasses.replace(
+        lig, T=np.full(n_seeds, 600.0), w=np.zeros((n_seeds, 5)),
+        dt=np.full(n_seeds, float(lig.dt[0])),
+        x0=np.repeat(lig.x0[:1], n_seeds, axis=0).astype(np.float32))
+    ctx = pkg.Context(seed=system.seed + 7, device=0)
+    ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+    lid = ctx.ligand_setup(init, sample_capacity=n_trials)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.initialize_ladder(lid, pkg.SCHEDULE_SOFT, 600.0, 300.0,
+                                speed=0.2, n_trials=n_trials, n_leapfrog=L,
+                                dt_start=float(lig.dt[0]), dt_min=0.25,
+                                max_dt_rounds=8, max_selections=6,
+                                n_conf=n_seeds, n_com=n_com,
+                                n_orient=n_orient, max_states=1024)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ctx.close()
+    K = res["n_states"]
+
+    def exchange_rates(T, w, dt, x0):
+        lg = dataclasses.replace(lig, T=np.asarray(T), w=np.asarray(w),
+                                 dt=np.asarray(dt),
+                                 x0=np.ascontiguousarray(x0, np.float32))
+        c = pkg.Context(seed=system.seed + 11, device=0)
+        c.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+        i = c.ligand_setup(lg)
+        c.hmc_sweep(prod_sweeps // 4, L, exchange_every=1)   # equilibration
+        s0 = c.get_stats(i)
+        c.hmc_sweep(prod_sweeps, L, exchange_every=1)
+        s1 = c.get_stats(i)
+        c.close()
+        acc = (s1["ex_acc"] - s0["ex_acc"]) / np.maximum(
+            s1["ex_try"] - s0["ex_try"], 1)
+        hmc = (s1["hmc_acc"] - s0["hmc_acc"]) / np.maximum(
+            s1["hmc_try"] - s0["hmc_try"], 1)
+        return {"states": int(len(T)), "exchange_min": float(acc.min()),
+                "exchange_mean": float(acc.mean()),
+                "pairs_below_0.4": int((acc < 0.4).sum()),
+                "hmc_acceptance_min": float(hmc.min())}
+
+    built = exchange_rates(res["T"], res["w"], res["dt"], res["x"][:, 0])
+    fixed = exchange_rates(lig.T, lig.w, lig.dt, lig.x0)
+    pv = res["pacc"][1:]
+    return {
+        "workload": "c4_soft_grid_ladder_initialisation",
+        "seconds": sec, "states": K, "selections": res["n_selections"],
+        "runs": res["n_runs"], "removed": res["n_removed"],
+        "reached_target": res["reached_target"],
+        "seeds_per_state": n_seeds, "trials_per_run": n_trials,
+        "leapfrog": L, "placements": n_seeds * n_com * n_orient,
+        "verified_pacc_min": float(pv.min()) if len(pv) else None,
+        "verified_pacc_median": float(np.median(pv)) if len(pv) else None,
+        "dt_fs_range": [float(res["dt"].min()), float(res["dt"].max())],
+        "hmc_acceptance_range": [float(res["acc"].min()),
+                                 float(res["acc"].max())],
+        "production_sweeps": prod_sweeps,
+        "built_ladder": built, "fixed_ladder": fixed,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -619,6 +699,10 @@ def main():
 
     import synth
     import paper_1507_03703_amd as pkg
+
+    if args.init_only:
+        print(json.dumps(init_leg(pkg, torch)))
+        return
 
     if args.learned_only:
         print(json.dumps(learned_leg(pkg, torch, train_steps=args.train_steps,
@@ -675,6 +759,8 @@ def main():
                           "result": rb["result"]}
     if args.bulk:
         out["bulk_interpolation"] = bulk()
+    if args.init:
+        out["initialization"] = init_leg(pkg, torch)
     if args.learned:
         out["learned_proposal"] = learned_leg(
             pkg, torch, train_steps=args.train_steps, burn=args.burn_sweeps,
