@@ -517,3 +517,36 @@ def toy_ligand(x, bonds, bond_K, T, lam, q=0.3, mass=1.0, dt=2.0, d0=2.0,
                   dt=np.full(K, float(dt)),
                   x0=np.repeat(x32[None], K, axis=0), frame_atoms=(0, 1, 2),
                   cond_tors=np.zeros(0, np.int32))
+
+
+def pair_params(lig, seed=0):
+    """Intramolecular nonbonded and implicit-solvent parameters of a
+    synthetic ligand: its own per-atom LJ sigma, eps and charge (recovered
+    from the grid factors s_rep = 2 sqrt(eps) sigma^6, s_att = -2 sqrt(eps)
+    sigma^3, s_ele = q), GB intrinsic radii ~ U(1.3, 1.9) A and HCT scale
+    factors ~ U(0.72, 0.9) (the span of common radius sets), exclusions of
+    the 1-2 and 1-3 pairs, the torsions' end pairs as 1-4 pairs (LJ x 1/2,
+    Coulomb x 1/1.2), water outside (78.5) and a dielectric of 1 inside,
+    surface tension 0.0225936 kJ/mol/A^2 with a 1.4 A probe."""
+    rng = np.random.default_rng([seed, 4242, lig.n_atoms])
+    s_rep, s_att, q = lig.scale[:, 0], lig.scale[:, 1], lig.scale[:, 2]
+    sig3 = s_rep / (-s_att)
+    sigma = np.cbrt(sig3)
+    eps = (s_att / (2.0 * sig3)) ** 2
+    n = lig.n_atoms
+    excl = set()
+    for i, j in np.asarray(lig.bonds).reshape(-1, 2):
+        excl.add((min(i, j), max(i, j)))
+    for i, _, k in np.asarray(lig.angles).reshape(-1, 3):
+        excl.add((min(i, k), max(i, k)))
+    p14 = set()
+    for i, _, _, l in np.asarray(lig.tors).reshape(-1, 4):
+        key = (min(i, l), max(i, l))
+        if key not in excl:
+            p14.add(key)
+    return dict(charge=np.asarray(q, np.float64), sigma=sigma, eps=eps,
+                rho=rng.uniform(1.3, 1.9, n), S=rng.uniform(0.72, 0.9, n),
+                exclusions=np.array(sorted(excl), np.int32).reshape(-1, 2),
+                pairs14=np.array(sorted(p14), np.int32).reshape(-1, 2),
+                lj14=0.5, el14=1.0 / 1.2, eps_solute=1.0, eps_solvent=78.5,
+                gamma=0.0225936, probe=1.4)
