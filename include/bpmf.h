@@ -475,6 +475,53 @@ BPMF_API int bpmf_get_pose_stats(bpmf_ctx* ctx, int ligand_id, int64_t* acc,
                                  int64_t* tries, double* last_ln_alpha);
 
 /* ------------------------------------------------------------------------
+ * Intramolecular nonbonded and implicit-solvent terms of a ligand
+ * (Thermodynamic Cycle: the ligand force field and its OBC generalised-
+ * Born/surface-area solvent)
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const double* charge;     /* host, n_atoms partial charges (e) */
+  const double* lj_sigma;   /* host, n_atoms LJ sigma (A), > 0 */
+  const double* lj_eps;     /* host, n_atoms LJ epsilon (kJ/mol), >= 0 */
+  const double* gb_radius;  /* host, n_atoms intrinsic radii rho (A), > 0.09 */
+  const double* gb_scale;   /* host, n_atoms HCT scale factors S, > 0 */
+  int n_exclusions;         /* pairs without LJ and Coulomb (1-2, 1-3) */
+  const int* exclusions;    /* host, n_exclusions x 2 atom indices */
+  int n_pairs14;            /* 1-4 pairs (an excluded pair stays excluded) */
+  const int* pairs14;       /* host, n_pairs14 x 2 */
+  double lj14, el14;        /* 1-4 scale factors of LJ and Coulomb */
+  double eps_solute;        /* dielectric inside (1) */
+  double eps_solvent;       /* dielectric of the solvent (78.5) */
+  double sa_gamma;          /* surface tension (kJ/mol/A^2), 0 = no SA term */
+  double probe_radius;      /* solvent probe radius (A), 1.4 */
+} bpmf_pair_desc;
+
+/* Attach pair parameters to a ligand (up to 128 atoms; replaces earlier
+ * ones).  Synchronises. */
+BPMF_API int bpmf_pair_setup(bpmf_ctx* ctx, int ligand_id,
+                             const bpmf_pair_desc* desc);
+
+/* For n_conf configurations dev_x (device, n_conf x n_atoms x 3 floats)
+ * write dev_terms (device, n_conf x 4 doubles):
+ *   E_LJ   = sum over pairs not excluded of 4 eps_ij ((s/r)^12 - (s/r)^6),
+ *            s = (sigma_i + sigma_j)/2, eps_ij = sqrt(eps_i eps_j), 1-4
+ *            pairs x lj14;
+ *   E_Coul = the same pairs' k_e q_i q_j / (eps_solute r), 1-4 x el14;
+ *   E_GB   = -(k_e/2)(1/eps_solute - 1/eps_solvent) sum_i sum_j q_i q_j /
+ *            f_ij, f_ij = sqrt(r^2 + R_i R_j exp(-r^2/(4 R_i R_j))), f_ii =
+ *            R_i; Born radii 1/R_i = 1/rt_i - tanh(psi - 0.8 psi^2 + 4.85
+ *            psi^3)/rho_i (OBC II), psi = I_i rt_i, rt = rho - 0.09, I_i
+ *            the HCT descreening sum over j of the integral of r^-4/(4 pi)
+ *            over the ball of radius S_j rt_j outside radius rt_i;
+ *   E_SA   = sum_i 4 pi sa_gamma (rho_i + probe)^2 (rho_i / R_i)^6;
+ * k_e = 1389.3546 kJ/mol A e^-2; and, unless NULL, dev_forces (device,
+ * n_conf x n_atoms x 3 floats) = -grad of their sum.  Float32 arithmetic,
+ * energies summed in double. */
+BPMF_API int bpmf_pair_evaluate(bpmf_ctx* ctx, int ligand_id,
+                                const float* dev_x, int64_t n_conf,
+                                double* dev_terms, float* dev_forces);
+
+/* ------------------------------------------------------------------------
  * Ligand information, state parameters, single-ligand sweeps
  * ------------------------------------------------------------------------ */
 

@@ -77,6 +77,19 @@ class _InitResult(C.Structure):
                 ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int)]
 
 
+class _PairDesc(C.Structure):
+    _fields_ = [("charge", C.POINTER(C.c_double)),
+                ("lj_sigma", C.POINTER(C.c_double)),
+                ("lj_eps", C.POINTER(C.c_double)),
+                ("gb_radius", C.POINTER(C.c_double)),
+                ("gb_scale", C.POINTER(C.c_double)),
+                ("n_exclusions", C.c_int), ("exclusions", C.POINTER(C.c_int)),
+                ("n_pairs14", C.c_int), ("pairs14", C.POINTER(C.c_int)),
+                ("lj14", C.c_double), ("el14", C.c_double),
+                ("eps_solute", C.c_double), ("eps_solvent", C.c_double),
+                ("sa_gamma", C.c_double), ("probe_radius", C.c_double)]
+
+
 TRACE_FIELDS = 10
 SCHEDULE_LINEAR, SCHEDULE_SOFT = 0, 1
 
@@ -176,6 +189,8 @@ def library():
         "bpmf_detect_equilibration": [dp, C.c_int64, C.c_int, i64p, dp, dp],
         "bpmf_initialize_ladder": [vp, C.POINTER(_InitArgs),
                                    C.POINTER(_InitResult)],
+        "bpmf_pair_setup": [vp, C.c_int, C.POINTER(_PairDesc)],
+        "bpmf_pair_evaluate": [vp, C.c_int, vp, C.c_int64, vp, vp],
         "bpmf_version": [],
         "bpmf_last_error": [],
     }
@@ -758,6 +773,37 @@ class Context:
 
     def reset_samples(self, ligand_id=-1):
         _check(self._lib.bpmf_reset_samples(self._h, int(ligand_id)))
+
+    # -- intramolecular nonbonded / implicit solvent ----------------------------
+    def pair_setup(self, ligand_id, p):
+        """p: dict with charge, sigma, eps, rho, S (per atom), exclusions and
+        pairs14 (k x 2), lj14, el14, eps_solute, eps_solvent, gamma,
+        probe."""
+        arr = {k: np.ascontiguousarray(p[k], np.float64)
+               for k in ("charge", "sigma", "eps", "rho", "S")}
+        ex = np.ascontiguousarray(p["exclusions"], np.int32).reshape(-1, 2)
+        o4 = np.ascontiguousarray(p["pairs14"], np.int32).reshape(-1, 2)
+        d = _PairDesc(_pd(arr["charge"]), _pd(arr["sigma"]), _pd(arr["eps"]),
+                      _pd(arr["rho"]), _pd(arr["S"]), len(ex), _pi(ex),
+                      len(o4), _pi(o4), float(p["lj14"]), float(p["el14"]),
+                      float(p["eps_solute"]), float(p["eps_solvent"]),
+                      float(p["gamma"]), float(p["probe"]))
+        _check(self._lib.bpmf_pair_setup(self._h, int(ligand_id),
+                                         C.byref(d)))
+
+    def pair_evaluate(self, ligand_id, x, forces=True):
+        torch = self._torch
+        n = self.ligands[ligand_id]["n"]
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+        N = x.shape[0]
+        dev = f"cuda:{self.device}"
+        terms = torch.empty((N, 4), dtype=torch.float64, device=dev)
+        F = torch.empty((N, n, 3), dtype=torch.float32, device=dev) \
+            if forces else None
+        _check(self._lib.bpmf_pair_evaluate(
+            self._h, int(ligand_id), x.data_ptr(), N, terms.data_ptr(),
+            F.data_ptr() if forces else None))
+        return terms, F
 
     # -- single-ligand control, ladder initialisation --------------------------
     def ligand_info(self, ligand_id):

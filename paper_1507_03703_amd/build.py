@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbpmf.so")
 SOURCES = ["api.hip", "kernels.hip", "mbar.hip", "mlp.hip", "moves.hip",
-           "protocol.hip"]
+           "protocol.hip", "pairs.hip"]
 ARCH = os.environ.get("BPMF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -16,6 +16,7 @@
 #include "moves.h"
 #include "mlp.h"
 #include "protocol.h"
+#include "pairs.h"
 
 using namespace bpmf;
 
@@ -78,6 +79,10 @@ struct LigHost {
   float* adam_v = nullptr;
   int64_t adam_t = 0;
   PropDev prop{};
+  // intramolecular nonbonded / implicit-solvent terms (bpmf_pair_setup)
+  bool has_pairs = false;
+  void* pair_arena = nullptr;
+  PairDev pair{};
 };
 
 }  // namespace
@@ -353,6 +358,7 @@ extern "C" int bpmf_destroy(bpmf_ctx* c) {
   for (auto& l : c->ligs) {
     c->dfree(l.arena);
     c->dfree(l.prop_arena);
+    c->dfree(l.pair_arena);
   }
   c->dfree(c->mlp_mem);
   c->dfree(c->place_mem);
@@ -1661,6 +1667,123 @@ extern "C" int bpmf_place_poses(bpmf_ctx* c, int ligand_id,
                              dev_confs, n_conf, n_com, n_orient, first, count,
                              (double*)c->place_mem, c->seed, dev_out,
                              c->stream));
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_pair_setup(bpmf_ctx* c, int ligand_id,
+                               const bpmf_pair_desc* d) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  if (!d || !d->charge || !d->lj_sigma || !d->lj_eps || !d->gb_radius ||
+      !d->gb_scale)
+    return fail(BPMF_E_INVAL, "null pair parameter array");
+  LigHost& h = c->ligs[ligand_id];
+  const int n = h.dev.n;
+  if (n > kPairMaxAtoms)
+    return fail(BPMF_E_UNIMPL, "pair terms support up to %d atoms, not %d",
+                kPairMaxAtoms, n);
+  for (int i = 0; i < n; ++i) {
+    if (!isfinite(d->charge[i]) || !(d->lj_sigma[i] > 0) ||
+        !(d->lj_eps[i] >= 0) || !isfinite(d->lj_eps[i]) ||
+        !isfinite(d->lj_sigma[i]))
+      return fail(BPMF_E_INVAL, "atom %d: bad charge or LJ parameters", i);
+    if (!(d->gb_radius[i] > 0.09 + 1e-6) || !isfinite(d->gb_radius[i]) ||
+        !(d->gb_scale[i] > 0) || !isfinite(d->gb_scale[i]))
+      return fail(BPMF_E_INVAL,
+                  "atom %d: GB radius must exceed 0.09 A and scale be > 0", i);
+  }
+  if (d->n_exclusions < 0 || d->n_pairs14 < 0 ||
+      (d->n_exclusions && !d->exclusions) || (d->n_pairs14 && !d->pairs14))
+    return fail(BPMF_E_INVAL, "bad exclusion or 1-4 list");
+  if (!(d->eps_solute > 0) || !(d->eps_solvent > 0) || !(d->sa_gamma >= 0) ||
+      !(d->probe_radius >= 0) || !isfinite(d->lj14) || !isfinite(d->el14))
+    return fail(BPMF_E_INVAL, "bad dielectric, surface or 1-4 constants");
+  std::vector<uint32_t> ex((size_t)n * kPairWords, 0u),
+      o4((size_t)n * kPairWords, 0u);
+  auto set = [&](std::vector<uint32_t>& m, int i, int j) {
+    m[(size_t)i * kPairWords + (j >> 5)] |= 1u << (j & 31);
+    m[(size_t)j * kPairWords + (i >> 5)] |= 1u << (i & 31);
+  };
+  auto get = [&](const std::vector<uint32_t>& m, int i, int j) {
+    return (m[(size_t)i * kPairWords + (j >> 5)] >> (j & 31)) & 1u;
+  };
+  for (int t = 0; t < d->n_exclusions; ++t) {
+    const int i = d->exclusions[2 * t], j = d->exclusions[2 * t + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j)
+      return fail(BPMF_E_INVAL, "exclusion %d: bad pair (%d, %d)", t, i, j);
+    set(ex, i, j);
+  }
+  for (int t = 0; t < d->n_pairs14; ++t) {
+    const int i = d->pairs14[2 * t], j = d->pairs14[2 * t + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j)
+      return fail(BPMF_E_INVAL, "1-4 pair %d: bad pair (%d, %d)", t, i, j);
+    if (!get(ex, i, j)) set(o4, i, j);
+  }
+  std::vector<float4> p0(n);
+  std::vector<float2> p1(n);
+  for (int i = 0; i < n; ++i) {
+    const double rt = d->gb_radius[i] - 0.09;
+    p0[i] = make_float4((float)d->charge[i], (float)d->lj_sigma[i],
+                        (float)sqrt(d->lj_eps[i]), (float)d->gb_radius[i]);
+    p1[i] = make_float2((float)rt, (float)(d->gb_scale[i] * rt));
+  }
+  Arena A;
+  const size_t o_p0 = A.add((size_t)n * 16), o_p1 = A.add((size_t)n * 8),
+               o_ex = A.add(ex.size() * 4), o_o4 = A.add(o4.size() * 4);
+  char* base = (char*)c->dalloc(A.total);
+  if (!base) return fail(BPMF_E_NOMEM, "pair parameter allocation failed");
+  hipError_t e = hipMemcpyAsync(base + o_p0, p0.data(), (size_t)n * 16,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + o_p1, p1.data(), (size_t)n * 8,
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + o_ex, ex.data(), ex.size() * 4,
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + o_o4, o4.data(), o4.size() * 4,
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->dfree(base);
+    return fail(BPMF_E_HIP, "pair parameter upload: %s", hipGetErrorString(e));
+  }
+  c->dfree(h.pair_arena);
+  h.pair_arena = base;
+  PairDev& P = h.pair;
+  P.n = n;
+  P.p0 = (const float4*)(base + o_p0);
+  P.p1 = (const float2*)(base + o_p1);
+  P.excl = (const uint32_t*)(base + o_ex);
+  P.o14 = (const uint32_t*)(base + o_o4);
+  P.lj14 = (float)d->lj14;
+  P.el14 = (float)d->el14;
+  const double ke = 1389.35457644382;  // e^2 / (4 pi eps0), kJ/mol A
+  P.kc = (float)(ke / d->eps_solute);
+  P.kgb = (float)(-ke * (1.0 / d->eps_solute - 1.0 / d->eps_solvent));
+  P.sa = (float)(4.0 * M_PI * d->sa_gamma);
+  P.probe = (float)d->probe_radius;
+  h.has_pairs = true;
+  return BPMF_OK;
+}
+
+extern "C" int bpmf_pair_evaluate(bpmf_ctx* c, int ligand_id,
+                                  const float* dev_x, int64_t n_conf,
+                                  double* dev_terms, float* dev_forces) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  const LigHost& h = c->ligs[ligand_id];
+  if (!h.has_pairs)
+    return fail(BPMF_E_STATE, "ligand %d has no pair parameters", ligand_id);
+  if (n_conf < 0 || n_conf > 0x7fffffffll)
+    return fail(BPMF_E_INVAL, "n_conf %lld outside 0..2^31-1",
+                (long long)n_conf);
+  if (n_conf == 0) return BPMF_OK;
+  if (!dev_x || !dev_terms) return fail(BPMF_E_INVAL, "null pair buffer");
+  HIP_TRY(launch_pair_terms(h.pair, dev_x, n_conf, dev_terms, dev_forces,
+                            c->stream));
   return BPMF_OK;
 }
 

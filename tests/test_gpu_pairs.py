@@ -1,0 +1,127 @@
+"""GPU parity of the intramolecular nonbonded / implicit-solvent terms
+(pairs.hip) against the FP64 oracle (oracle/pairs.py): the four energies
+per configuration and the forces against the oracle's central differences,
+for a 24-atom ligand (one wavefront), a 90-atom ligand (two), and a
+three-atom case whose close, large descreening spheres reach every branch of
+the descreening integral (an atom inside another's sphere, a sphere inside
+an atom's own radius)."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import dev, make_context, print_case, require_gpu, torch
+from oracle import pairs as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _oracle_params(p, n):
+    ex, o4 = O.masks(n, p["exclusions"], p["pairs14"])
+    q = dict(p)
+    q.update(excluded=ex, one_four=o4)
+    return q
+
+
+def _check(ctx, lid, xs, p, fd_atoms=None):
+    n = xs.shape[1]
+    terms, F = ctx.pair_evaluate(lid, dev(xs, torch.float32))
+    terms, F = terms.cpu().numpy(), F.cpu().numpy()
+    t2, _ = ctx.pair_evaluate(lid, dev(xs, torch.float32), forces=False)
+    assert np.array_equal(t2.cpu().numpy(), terms)
+    po = _oracle_params(p, n)
+    for c in range(len(xs)):
+        x = xs[c].astype(np.float64)
+        ref = O.energy_terms(x, po)
+        assert np.allclose(terms[c], ref, rtol=3e-5, atol=2e-3), (c, terms[c],
+                                                                 ref)
+        atoms = range(n) if fd_atoms is None else fd_atoms
+        Fr = np.zeros((n, 3))
+        for i in atoms:
+            for d in range(3):
+                h = 1e-5
+                xp, xm = x.copy(), x.copy()
+                xp[i, d] += h
+                xm[i, d] -= h
+                Fr[i, d] = -(O.energy_terms(xp, po).sum() -
+                             O.energy_terms(xm, po).sum()) / (2 * h)
+        idx = list(atoms)
+        scale = np.abs(Fr[idx]).max()
+        err = np.abs(F[c][idx] - Fr[idx]).max()
+        assert err <= 1e-4 * scale + 2e-3, (c, err, scale)
+
+
+def test_pair_terms_24_atoms():
+    print_case("pairs 24 atoms")
+    system = synth.make_system(1)
+    lig, g = system.ligands[0], system.grid
+    ctx, (lid,) = make_context(g, [lig], seed=1)
+    p = synth.pair_params(lig, seed=1)
+    ctx.pair_setup(lid, p)
+    rng = np.random.default_rng(4)
+    xs = (lig.x0[:3] + rng.normal(scale=0.15, size=(3, lig.n_atoms, 3))
+          ).astype(np.float32)
+    _check(ctx, lid, xs, p)
+    ctx.close()
+
+
+def test_pair_terms_90_atoms_two_wavefronts():
+    print_case("pairs 90 atoms")
+    rng = np.random.default_rng(12)
+    lig = synth.make_ligand(rng, 90, 2)
+    system = synth.make_system(1)
+    ctx, (lid,) = make_context(system.grid, [lig], seed=1)
+    p = synth.pair_params(lig, seed=2)
+    ctx.pair_setup(lid, p)
+    xs = (lig.x0[:2] + rng.normal(scale=0.1, size=(2, 90, 3))
+          ).astype(np.float32)
+    _check(ctx, lid, xs, p, fd_atoms=[0, 17, 45, 89])
+    ctx.close()
+
+
+def test_pair_terms_close_spheres_reach_every_branch():
+    print_case("pairs close spheres")
+    x = np.array([[0.0, 0.0, 0.0], [0.35, 0.0, 0.0], [0.0, 2.6, 0.3]])
+    lig = synth.toy_ligand(x, [[0, 1]], 10.0, np.array([300.0]),
+                           np.array([1.0]))
+    system = synth.make_system(1)
+    ctx, (lid,) = make_context(system.grid, [lig], seed=1)
+    p = dict(charge=np.array([0.4, -0.3, 0.2]), sigma=np.array([3.0, 3.2, 3.4]),
+             eps=np.array([0.1, 0.2, 0.15]), rho=np.array([1.2, 1.8, 1.5]),
+             S=np.array([0.8, 1.9, 0.5]), exclusions=np.array([[0, 1]]),
+             pairs14=np.zeros((0, 2), np.int32), lj14=0.5, el14=1 / 1.2,
+             eps_solute=1.0, eps_solvent=78.5, gamma=0.0225936, probe=1.4)
+    # atom 0 sits inside atom 1's descreening sphere (s = 1.9 x 1.71 > r +
+    # rt_0); atom 1 sees atom 0's small sphere partly inside its own radius
+    assert 1.9 * (1.8 - 0.09) > 0.35 + (1.2 - 0.09)
+    ctx.pair_setup(lid, p)
+    rng = np.random.default_rng(5)
+    xs = (x[None] + rng.normal(scale=0.02, size=(4, 3, 3))).astype(np.float32)
+    _check(ctx, lid, xs, p)
+    ctx.close()
+
+
+def test_pair_setup_errors():
+    print_case("pairs errors")
+    import paper_1507_03703_amd as pkg
+    system = synth.make_system(1)
+    lig = system.ligands[0]
+    ctx, (lid,) = make_context(system.grid, [lig], seed=1)
+    x = dev(lig.x0[:1], torch.float32)
+    with pytest.raises(pkg.BPMFError) as ei:
+        ctx.pair_evaluate(lid, x)
+    assert ei.value.code == -4
+    p = synth.pair_params(lig)
+    bad = dict(p)
+    bad["rho"] = np.full(lig.n_atoms, 0.05)
+    with pytest.raises(pkg.BPMFError):
+        ctx.pair_setup(lid, bad)
+    bad = dict(p)
+    bad["exclusions"] = np.array([[0, lig.n_atoms]])
+    with pytest.raises(pkg.BPMFError):
+        ctx.pair_setup(lid, bad)
+    ctx.close()
