@@ -27,7 +27,10 @@ equilibrated end.  A fourth leg ("initialization") builds that system's
 ladder with the paper's initialisation (50 seeds per state, 200 x 10-step
 HMC runs, 50 x 453 x 100 random placements as state 0's sample set, speed
 0.2) and compares neighbour exchange rates of the built ladder with the
-fixed 64-state ladder in a short production run.
+fixed 64-state ladder in a short production run.  A fifth leg
+("pair_terms") times the ligand's intramolecular nonbonded and OBC GB/SA
+energies and forces over the 32000 recorded samples of a production step,
+for the 48-atom production ligand and a 100-atom ligand.
 """
 from __future__ import annotations
 
@@ -112,6 +115,9 @@ def parse():
     p.add_argument("--no-init", dest="init", action="store_false",
                    help="skip the ladder-initialisation leg")
     p.add_argument("--init-only", action="store_true")
+    p.add_argument("--no-pairs", dest="pairs", action="store_false",
+                   help="skip the intramolecular pair-term leg")
+    p.add_argument("--pairs-only", action="store_true")
     p.add_argument("--long-sweeps", type=int, default=1000000)
     p.add_argument("--prod-sweeps", type=int, default=300000)
     p.add_argument("--burn-sweeps", type=int, default=100000)
@@ -678,6 +684,61 @@ def init_leg(pkg, torch, n_seeds=50, n_trials=200, n_com=453, n_orient=100,
     }
 
 
+def pair_leg(pkg, torch, n_conf=32000, reps=5):
+    """Intramolecular LJ + Coulomb + OBC GB/SA energies and forces of
+    n_conf configurations per call (bpmf_pair_evaluate), timed with HIP
+    events on the library's stream: the 48-atom production ligand and a
+    100-atom ligand (the largest of the large batched workload)."""
+    import numpy as np
+    import synth
+    g = synth.make_system(1).grid
+    lig48 = synth.make_system(2, with_grid=False).ligands[0]
+    lig100 = synth.make_ligand(np.random.default_rng([105, 7]), 100, 2)
+    out = []
+    for name, lig in (("c2_ligand_48_atoms", lig48),
+                      ("ligand_100_atoms", lig100)):
+        ctx = pkg.Context(seed=1, device=0)
+        ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+        lid = ctx.ligand_setup(dataclasses_replace_states(lig, 1))
+        ctx.pair_setup(lid, synth.pair_params(lig))
+        rng = np.random.default_rng(3)
+        xs = torch.as_tensor(
+            (lig.x0[0][None] + rng.normal(scale=0.1, size=(n_conf,
+                                                           lig.n_atoms, 3))
+             ).astype(np.float32), device="cuda:0").contiguous()
+        res = {}
+        for forces in (True, False):
+            ctx.pair_evaluate(lid, xs, forces=forces)       # warm-up
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                terms, _f = ctx.pair_evaluate(lid, xs, forces=forces)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            assert np.isfinite(terms.cpu().numpy()).all()
+            n = lig.n_atoms
+            res["forces" if forces else "energies_only"] = {
+                "ms_per_call": ms, "configs_per_s": n_conf / ms * 1e3,
+                "ordered_pairs_per_s": n_conf * n * (n - 1) / ms * 1e3}
+        ctx.close()
+        out.append({"workload": name, "atoms": lig.n_atoms,
+                    "configurations": n_conf, **res})
+    return out
+
+
+def dataclasses_replace_states(lig, K):
+    """The ligand with a K-state ladder (the pair terms do not depend on
+    the state)."""
+    import dataclasses
+    import numpy as np
+    return dataclasses.replace(lig, T=np.full(K, 300.0),
+                               w=np.ones((K, lig.scale.shape[1])),
+                               dt=np.ones(K), x0=lig.x0[:K])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -699,6 +760,10 @@ def main():
 
     import synth
     import paper_1507_03703_amd as pkg
+
+    if args.pairs_only:
+        print(json.dumps({"pair_terms": pair_leg(pkg, torch)}))
+        return
 
     if args.init_only:
         print(json.dumps(init_leg(pkg, torch)))
@@ -761,6 +826,8 @@ def main():
         out["bulk_interpolation"] = bulk()
     if args.init:
         out["initialization"] = init_leg(pkg, torch)
+    if args.pairs:
+        out["pair_terms"] = pair_leg(pkg, torch)
     if args.learned:
         out["learned_proposal"] = learned_leg(
             pkg, torch, train_steps=args.train_steps, burn=args.burn_sweeps,
