@@ -643,29 +643,46 @@ def init_leg(pkg, torch, n_seeds=50, n_trials=200, n_com=453, n_orient=100,
     ctx.close()
     K = res["n_states"]
 
-    def exchange_rates(T, w, dt, x0):
+    def exchange_rates(T, w, dt, x0, alpha=None):
+        """Neighbour exchange (even/odd) sweeps, or the paper's iteration:
+        an HMC move, 20 external moves in the states with alpha < 0.01,
+        then 25 exchange sweeps over separations 1..5."""
         lg = dataclasses.replace(lig, T=np.asarray(T), w=np.asarray(w),
                                  dt=np.asarray(dt),
                                  x0=np.ascontiguousarray(x0, np.float32))
         c = pkg.Context(seed=system.seed + 11, device=0)
         c.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
         i = c.ligand_setup(lg)
-        c.hmc_sweep(prod_sweeps // 4, L, exchange_every=1)   # equilibration
+        kw = dict(exchange_every=1)
+        if alpha is not None:
+            kw.update(exchange_scheme=1, max_sep=5, exchange_sweeps=25,
+                      external_moves=20,
+                      external_k_max=int((np.asarray(alpha) < 0.01).sum()))
+        c.hmc_sweep(prod_sweeps // 4, L, **kw)   # equilibration
         s0 = c.get_stats(i)
-        c.hmc_sweep(prod_sweeps, L, exchange_every=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.hmc_sweep(prod_sweeps, L, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / prod_sweeps * 1e3
         s1 = c.get_stats(i)
         c.close()
         acc = (s1["ex_acc"] - s0["ex_acc"]) / np.maximum(
             s1["ex_try"] - s0["ex_try"], 1)
         hmc = (s1["hmc_acc"] - s0["hmc_acc"]) / np.maximum(
             s1["hmc_try"] - s0["hmc_try"], 1)
-        return {"states": int(len(T)), "exchange_min": float(acc.min()),
+        return {"states": int(len(T)), "ms_per_iteration": ms,
+                "exchange_min": float(acc.min()),
                 "exchange_mean": float(acc.mean()),
                 "pairs_below_0.4": int((acc < 0.4).sum()),
                 "hmc_acceptance_min": float(hmc.min())}
 
     built = exchange_rates(res["T"], res["w"], res["dt"], res["x"][:, 0])
     fixed = exchange_rates(lig.T, lig.w, lig.dt, lig.x0)
+    built_paper = exchange_rates(res["T"], res["w"], res["dt"],
+                                 res["x"][:, 0], alpha=res["alpha"])
+    fixed_paper = exchange_rates(lig.T, lig.w, lig.dt, lig.x0,
+                                 alpha=np.linspace(0.0, 1.0, lig.n_states))
     pv = res["pacc"][1:]
     return {
         "workload": "c4_soft_grid_ladder_initialisation",
@@ -681,6 +698,8 @@ def init_leg(pkg, torch, n_seeds=50, n_trials=200, n_com=453, n_orient=100,
                                  float(res["acc"].max())],
         "production_sweeps": prod_sweeps,
         "built_ladder": built, "fixed_ladder": fixed,
+        "built_ladder_paper_iteration": built_paper,
+        "fixed_ladder_paper_iteration": fixed_paper,
     }
 
 

@@ -83,12 +83,111 @@ __device__ bool attempt_pair(const LigDev& L, int a, int b, int sep,
   }
   return ok;
 }
+
+// The all-separations sweep with the state data staged in LDS.  Within one
+// separation d, pair (a, a + d) only touches states of residue a mod d, so
+// the d residue classes are independent chains: running each chain in
+// ascending a gives the decisions of the ascending order over all a.  The
+// uniforms of a separation are drawn first, in parallel; the energies are
+// the same double sums as state_energy, so every decision is the one the
+// one-thread order takes.  E_cur[k] holds the energy of the replica in
+// state k at state k.
+constexpr int kXStates = 256, kXChannels = 5;
+struct XStage {
+  double cp[kXStates * (1 + kXChannels)];  // components per replica
+  double wd[kXStates * kXChannels];        // weights per state
+  double beta[kXStates];
+  double ecur[kXStates];
+  double lnu[kXStates];  // ln u of the current separation, by lower state
+  int ros[kXStates];
+  int ntry[kXStates], nacc[kXStates];  // separation-1 counts, by lower state
+};
+
+// unrolled over the channels, so that all loads of a step are in flight
+// together
+template <int C>
+__device__ __forceinline__ double staged_energy(const XStage& X, int k,
+                                                int r) {
+  const double* cp = X.cp + r * (1 + C);
+  const double* w = X.wd + k * C;
+  double v[1 + C], u[C];
+#pragma unroll
+  for (int e = 0; e <= C; ++e) v[e] = cp[e];
+#pragma unroll
+  for (int c = 0; c < C; ++c) u[c] = w[c];
+  double E = v[0];
+#pragma unroll
+  for (int c = 0; c < C; ++c) E += u[c] * v[1 + c];
+  return E;
+}
+
+template <int C>
+__device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
+                                    int max_sep, int n_sub, uint64_t seed,
+                                    XStage& X) {
+  const int K = L.K, C1 = 1 + C;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < K * C1; i += nt) X.cp[i] = L.comps[i];
+  for (int i = tid; i < K * C; i += nt) X.wd[i] = L.wd[i];
+  for (int k = tid; k < K; k += nt) {
+    X.beta[k] = L.beta[k];
+    X.ros[k] = L.replica_of_state[k];
+    X.ntry[k] = 0;
+    X.nacc[k] = 0;
+  }
+  __syncthreads();
+  for (int k = tid; k < K; k += nt) X.ecur[k] = staged_energy<C>(X, k, X.ros[k]);
+  const int dmax = max_sep < K - 1 ? max_sep : K - 1;
+  for (int j = 0; j < n_sub; ++j) {
+    for (int d = 1; d <= dmax; ++d) {
+      for (int a = tid; a + d < K; a += nt) {
+        const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)d << 8);
+        X.lnu[a] = log(u01d(draw(seed, (uint32_t)a, L.id, j, sweep,
+                                 purpose).x));
+      }
+      __syncthreads();
+      // residue classes of d, one thread each
+      for (int rho = tid; rho < d; rho += nt) {
+        for (int a = rho; a + d < K; a += d) {
+          const int b = a + d;
+          const int ra = X.ros[a], rb = X.ros[b];
+          const double eab = staged_energy<C>(X, a, rb);
+          const double eba = staged_energy<C>(X, b, ra);
+          const double delta = X.beta[a] * (eab - X.ecur[a]) +
+                               X.beta[b] * (eba - X.ecur[b]);
+          const bool ok = isfinite(delta) && (X.lnu[a] < -delta);
+          if (d == 1) {
+            X.ntry[a] += 1;
+            X.nacc[a] += ok ? 1 : 0;
+          }
+          if (ok) {
+            X.ros[a] = rb;
+            X.ros[b] = ra;
+            X.ecur[a] = eab;
+            X.ecur[b] = eba;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int k = tid; k < K; k += nt) {
+    const int r = X.ros[k];
+    L.replica_of_state[k] = r;
+    L.state_of_replica[r] = k;
+    if (k + 1 < K && X.ntry[k]) {
+      atomicAdd(&L.ex_try[k], (unsigned long long)X.ntry[k]);
+      if (X.nacc[k]) atomicAdd(&L.ex_acc[k], (unsigned long long)X.nacc[k]);
+    }
+  }
+}
 #pragma clang fp contract(fast)
 
 // block-wide exchange for one ligand (called by all threads): n_sub
 // exchange sweeps in a row, sweep j drawing its uniforms with replica field j
 __device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
                                int max_sep, int n_sub, uint64_t seed) {
+  __shared__ XStage X;
   const int K = L.K;
   if (K < 2) return;
   if (scheme == 0) {
@@ -99,6 +198,10 @@ __device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
       for (int a = a0 + 2 * (int)threadIdx.x; a + 1 < K; a += 2 * blockDim.x)
         attempt_pair(L, a, a + 1, 1, sweep, j, seed);
     }
+  } else if (K <= kXStates && L.C == 3) {
+    exchange_all_staged<3>(L, sweep, max_sep, n_sub, seed, X);
+  } else if (K <= kXStates && L.C == 5) {
+    exchange_all_staged<5>(L, sweep, max_sep, n_sub, seed, X);
   } else if (threadIdx.x == 0) {
     const int dmax = max_sep < K - 1 ? max_sep : K - 1;
     for (int j = 0; j < n_sub; ++j)

@@ -108,6 +108,38 @@ def test_exchange_decisions_bitwise():
     ctx.close()
 
 
+@pytest.mark.parametrize("K", [64, 256, 300])
+def test_exchange_decisions_bitwise_large_ladders(K):
+    """All-separation sweeps at the staged kernel's limit (256 states) and
+    beyond it (one thread, global memory): labels and attempt counts equal
+    the oracle's."""
+    print_case("exchange large ladder", K)
+    rng = np.random.default_rng(K)
+    T, w = synth.ladder(K)
+    lig = synth.toy_ligand(np.array([[0.0, 0, 0], [1.5, 0, 0]]), [[0, 1]],
+                           10.0, T, w[:, 0])
+    grid = synth.linear_field_grid(8, 1.0, (0.5, 0.0, 0.0), 0.0)
+    ctx, (lid,) = make_context(grid, [lig], seed=7)
+    og, ol = oracle.OGrid(grid), oracle.OLigand(lig)
+    comps = rng.normal(scale=2.0, size=(K, 4))
+    sor = rng.permutation(K).astype(np.int32)
+    ctx.set_replicas(lid, lig.x0, sor, comps, 11)
+    ctx.exchange(lid, scheme=1, max_sep=5, n_sweeps=3)
+    st = ctx.get_replicas(lid)
+    s = oracle.Sampler(og, ol, seed=7, lig_id=lid, x0=lig.x0)
+    s.comps = np.ascontiguousarray(comps)
+    s.state = sor.copy()
+    s.rep_of_state = np.ascontiguousarray(np.argsort(sor).astype(np.int32))
+    s.sweep_count = 11
+    s.exchange(scheme=1, max_sep=5, n_sweeps=3)
+    assert np.array_equal(st["state_of_replica"], s.state)
+    stats = ctx.get_stats(lid)
+    assert np.array_equal(stats["ex_try"], s.ex_try)
+    assert np.array_equal(stats["ex_acc"], s.ex_acc)
+    assert stats["ex_acc"].sum() > 0
+    ctx.close()
+
+
 def test_checkpoint_resume_is_bitwise():
     print_case("checkpoint")
     system = synth.make_system(1)
