@@ -49,6 +49,17 @@ def test_lockstep_config1(waves):
     assert n >= 3
 
 
+def test_lockstep_config2_full_size():
+    """The benchmark's production workload at full size (48 atoms, 64
+    replicas, 128^3 x 3 grids, 20-step trials) in the launch shape the
+    benchmark times (automatic wavefronts, the single-ligand kernel)."""
+    system = synth.make_system(2, grid_device="cuda:0")
+    lig = system.ligands[0]
+    n = _lockstep(system.grid, lig, system.seed, 3, system.n_leapfrog,
+                  "config 2 full size")
+    assert n >= 1
+
+
 def test_lockstep_replicas_outside_grid_and_restrained():
     system = synth.make_system(1)
     lig = system.ligands[0]
