@@ -55,10 +55,10 @@ enum {
   BPMF_E_NOMEM = -2,  /* allocation failed */
   BPMF_E_HIP = -3,    /* HIP runtime error */
   BPMF_E_STATE = -4,  /* call made in the wrong order */
-  BPMF_E_UNIMPL = -5  /* option not supported by this build */
+  BPMF_E_UNIMPL = -5  /* option the library does not support */
 };
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define BPMF_MAX_ATOMS 128     /* atoms per ligand */
 #define BPMF_MAX_CHANNELS 8    /* grid channels */
 #define BPMF_MAX_STATES 1024   /* thermodynamic states per ligand */

@@ -481,7 +481,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   if (!c->has_grid) return fail(BPMF_E_STATE, "upload the grid first");
   const int C = c->grid.C;
   if (!supported_channels(C))
-    return fail(BPMF_E_UNIMPL, "this build samples with 3 or 5 channels, not %d",
+    return fail(BPMF_E_UNIMPL, "the sampler takes 3 or 5 channels, not %d",
                 C);
   const int n = d->n_atoms, K = d->n_states;
   if (n < 1 || n > BPMF_MAX_ATOMS)
@@ -1787,7 +1787,7 @@ extern "C" int bpmf_pair_evaluate(bpmf_ctx* c, int ligand_id,
   return BPMF_OK;
 }
 
-// accessors for the ladder-initialisation driver (protocol.hip)
+// accessors for the ladder initialisation (protocol.hip)
 namespace bpmf {
 void* ctx_alloc(bpmf_ctx* c, size_t bytes) { return c->dalloc(bytes); }
 void ctx_free(bpmf_ctx* c, void* p) { c->dfree(p); }

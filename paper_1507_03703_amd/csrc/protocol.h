@@ -1,5 +1,5 @@
 // Ladder initialisation: placement kernel (moves.hip) and the context
-// accessors the host driver (protocol.hip) uses.
+// accessors the host-side ladder initialisation (protocol.hip) uses.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -334,7 +334,7 @@ extern "C" int bpmf_detect_equilibration(const double* a, int64_t n,
 }
 
 // ============================================================================
-// the driver
+// bpmf_initialize_ladder: the steps run on the sampler
 // ============================================================================
 namespace {
 

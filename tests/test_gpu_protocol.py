@@ -1,9 +1,10 @@
 """GPU side of the ladder initialisation (Initialization): single-ligand
-sweeps and state replacement that the driver runs on, random placements in
-the site against the oracle, and the driver end to end -- every selection
-it made replayed with the oracle's formula, the ladder's states equal to
-the schedule at their alpha, the last state's spreads equal to the oracle's
-on the samples the driver left, state 0's spreads equal to the oracle's on
+sweeps and state replacement that bpmf_initialize_ladder runs on, random
+placements in the site against the oracle, and bpmf_initialize_ladder end
+to end -- every selection it made replayed with the oracle's formula, the
+ladder's states equal to the schedule at their alpha, the last state's
+spreads equal to the oracle's on the samples it left, state 0's spreads
+equal to the oracle's on
 the oracle's own placements and energies."""
 import dataclasses
 
@@ -166,7 +167,7 @@ def test_initialize_ladder_end_to_end():
     # p_acc of accepted states is >= 0.4 unless the selections ran out
     low = (kept[:, 8] < P.P_LOW).sum()
     assert low <= max(1, len(kept) // 10)
-    # the last state's spreads from the samples the driver left behind
+    # the last state's spreads from the samples left in the seed ligand
     xs, comps = ctx.get_samples(lid)
     comps = comps.reshape(-1, 6)
     so = P.state_sigmas(comps, al[-1], P.SOFT, TH, TT)
