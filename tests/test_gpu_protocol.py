@@ -187,6 +187,51 @@ def test_initialize_ladder_end_to_end():
     ctx.close()
 
 
+def test_initialize_ladder_linear_schedule_and_state_cap():
+    """The linear schedule on three channels with state 0's own samples (no
+    placements): selections replayed with the oracle, the ladder equal to
+    the schedule; with room for three states the ladder stops short of
+    alpha = 1 and says so."""
+    print_case("initialize ladder linear")
+    system = synth.make_system(1)
+    lig, g = system.ligands[0], system.grid
+    n_seeds = 8
+    init = dataclasses.replace(
+        lig, T=np.full(n_seeds, 600.0), w=np.zeros((n_seeds, 3)),
+        dt=np.ones(n_seeds),
+        x0=np.repeat(lig.x0[:1], n_seeds, axis=0).astype(np.float32))
+    TH, TT = 600.0, 300.0
+    for cap in (400, 3):
+        ctx, (lid,) = make_context(g, [init], seed=13, capacity=40)
+        res = ctx.initialize_ladder(lid, P.LINEAR, TH, TT, speed=0.5,
+                                    n_trials=40, n_leapfrog=10,
+                                    dt_start=1.0, dt_min=0.25,
+                                    max_dt_rounds=4, max_selections=3,
+                                    max_states=cap)
+        al = res["alpha"]
+        print("cap", cap, "states", res["n_states"], flush=True)
+        assert al[0] == 0.0 and np.all(np.diff(al) > 0)
+        assert res["reached_target"] == (al[-1] == 1.0)
+        if cap == 3:
+            assert res["n_states"] <= 3
+        else:
+            assert res["reached_target"]
+        for k in range(res["n_states"]):
+            T, w = P.state_of(al[k], P.LINEAR, 3, TH, TT)
+            assert res["T"][k] == pytest.approx(T, rel=1e-15)
+            assert np.allclose(res["w"][k], w, rtol=1e-15, atol=0)
+        for r in res["trace"]:
+            a_new = P.next_alpha(r[0], r[1], r[2], r[3], P.LINEAR, r[4], TH,
+                                 TT)
+            assert r[5] == pytest.approx(a_new, rel=1e-12, abs=1e-15)
+        # state 0's spreads from its own recorded samples: the sample set
+        # of a state is its last run, so only the last state's is left; for
+        # a ladder of one selection the trace's first record carries state
+        # 0's spreads
+        assert np.allclose(res["trace"][0][1:4], res["sigma"][0], rtol=0)
+        ctx.close()
+
+
 def test_initialize_ladder_argument_errors():
     print_case("initialize ladder errors")
     import paper_1507_03703_amd as pkg
