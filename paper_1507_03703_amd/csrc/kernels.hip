@@ -103,22 +103,24 @@ struct XStage {
   int ntry[kXStates], nacc[kXStates];  // separation-1 counts, by lower state
 };
 
-// unrolled over the channels, so that all loads of a step are in flight
-// together
+// state-k energy of components v, in the order of state_energy
 template <int C>
-__device__ __forceinline__ double staged_energy(const XStage& X, int k,
-                                                int r) {
-  const double* cp = X.cp + r * (1 + C);
-  const double* w = X.wd + k * C;
-  double v[1 + C], u[C];
-#pragma unroll
-  for (int e = 0; e <= C; ++e) v[e] = cp[e];
-#pragma unroll
-  for (int c = 0; c < C; ++c) u[c] = w[c];
+__device__ __forceinline__ double staged_sum(const double (&v)[1 + C],
+                                             const double (&u)[C]) {
   double E = v[0];
 #pragma unroll
   for (int c = 0; c < C; ++c) E += u[c] * v[1 + c];
   return E;
+}
+template <int C>
+__device__ __forceinline__ double staged_energy(const XStage& X, int k,
+                                                int r) {
+  double v[1 + C], u[C];
+#pragma unroll
+  for (int e = 0; e <= C; ++e) v[e] = X.cp[r * (1 + C) + e];
+#pragma unroll
+  for (int c = 0; c < C; ++c) u[c] = X.wd[k * C + c];
+  return staged_sum<C>(v, u);
 }
 
 template <int C>
@@ -126,6 +128,7 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
                                     int max_sep, int n_sub, uint64_t seed,
                                     XStage& X) {
   const int K = L.K, C1 = 1 + C;
+  __shared__ unsigned long long acc_bits[kXStates / 64];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < K * C1; i += nt) X.cp[i] = L.comps[i];
   for (int i = tid; i < K * C; i += nt) X.wd[i] = L.wd[i];
@@ -146,20 +149,33 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
                                  purpose).x));
       }
       __syncthreads();
-      // residue classes of d, one thread each
+      // residue classes of d, one thread each.  A step issues every load
+      // that does not depend on the labels with the label loads, then the
+      // two replicas' components: two LDS round trips per step.  The
+      // separation-1 chain keeps its accept bits in registers.
       for (int rho = tid; rho < d; rho += nt) {
+        unsigned long long bits[kXStates / 64] = {0ull, 0ull, 0ull, 0ull};
         for (int a = rho; a + d < K; a += d) {
           const int b = a + d;
           const int ra = X.ros[a], rb = X.ros[b];
-          const double eab = staged_energy<C>(X, a, rb);
-          const double eba = staged_energy<C>(X, b, ra);
-          const double delta = X.beta[a] * (eab - X.ecur[a]) +
-                               X.beta[b] * (eba - X.ecur[b]);
-          const bool ok = isfinite(delta) && (X.lnu[a] < -delta);
-          if (d == 1) {
-            X.ntry[a] += 1;
-            X.nacc[a] += ok ? 1 : 0;
+          const double ba = X.beta[a], bb = X.beta[b];
+          const double ea = X.ecur[a], eb = X.ecur[b], lnu = X.lnu[a];
+          double wa[C], wb[C], va[1 + C], vb[1 + C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            wa[c] = X.wd[a * C + c];
+            wb[c] = X.wd[b * C + c];
           }
+#pragma unroll
+          for (int e = 0; e <= C; ++e) {
+            vb[e] = X.cp[rb * C1 + e];
+            va[e] = X.cp[ra * C1 + e];
+          }
+          const double eab = staged_sum<C>(vb, wa);
+          const double eba = staged_sum<C>(va, wb);
+          const double delta = ba * (eab - ea) + bb * (eba - eb);
+          const bool ok = isfinite(delta) && (lnu < -delta);
+          if (d == 1 && ok) bits[a >> 6] |= 1ull << (a & 63);
           if (ok) {
             X.ros[a] = rb;
             X.ros[b] = ra;
@@ -167,8 +183,17 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
             X.ecur[b] = eba;
           }
         }
+        if (d == 1)
+          for (int q = 0; q < kXStates / 64; ++q) acc_bits[q] = bits[q];
       }
       __syncthreads();
+      if (d == 1) {
+        // every pair (a, a+1) was attempted once in this sweep
+        for (int a = tid; a + 1 < K; a += nt) {
+          X.ntry[a] += 1;
+          X.nacc[a] += (int)((acc_bits[a >> 6] >> (a & 63)) & 1ull);
+        }
+      }
     }
   }
   for (int k = tid; k < K; k += nt) {
