@@ -51,17 +51,17 @@ GRID_BYTES_PER_EVAL = 96  # 8 corners x 3 channels x 4 B
 # kernel and workload: one sweep launch (at the given wavefronts per
 # replica), one harness launch, one energy-matrix call (its launches
 # summed); valid only while the kernel sources hash to TRAFFIC_SOURCES
-TRAFFIC_SOURCES = "e792137113d79b69"
+TRAFFIC_SOURCES = "fbfe410448e2dea4"
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     ("k_hmc_sweep", "c2_plain_production"):
-        {"waves": None, "fetch_kib": 769.484, "write_kib": 201.280},
+        {"waves": None, "fetch_kib": 764.519, "write_kib": 201.280},
     ("k_hmc_sweep", "c3_batched_uneven"):
-        {"waves": 2, "fetch_kib": 36439.184, "write_kib": 24116.336},
+        {"waves": 2, "fetch_kib": 36451.566, "write_kib": 24113.681},
     ("k_grid_eval", "c3_batched_uneven"):
-        {"fetch_kib": 3389578.078, "write_kib": 3383700.0},
+        {"fetch_kib": 3389701.219, "write_kib": 3383700.0},
     ("k_energy_matrix", "c3_batched_uneven"):
-        {"fetch_kib": 1134483.312, "write_kib": 427643.836},
+        {"fetch_kib": 1134494.843, "write_kib": 427634.734},
 }
 KERNEL_SOURCES = ("device.h", "kernels.hip", "internal.h")
 
