@@ -123,10 +123,15 @@ __device__ __forceinline__ double staged_energy(const XStage& X, int k,
   return staged_sum<C>(v, u);
 }
 
-template <int C>
+// ladders of up to kXTable states also keep the whole table E(k, r) of
+// every replica's energy at every state, computed once per call: a chain
+// step then reads two entries instead of summing components
+constexpr int kXTable = 64;
+
+template <int C, bool TABLE>
 __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
                                     int max_sep, int n_sub, uint64_t seed,
-                                    XStage& X) {
+                                    XStage& X, double* em) {
   const int K = L.K, C1 = 1 + C;
   __shared__ unsigned long long acc_bits[kXStates / 64];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -140,6 +145,9 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
   }
   __syncthreads();
   for (int k = tid; k < K; k += nt) X.ecur[k] = staged_energy<C>(X, k, X.ros[k]);
+  if (TABLE)
+    for (int q = tid; q < K * K; q += nt)
+      em[(q / K) * kXTable + q % K] = staged_energy<C>(X, q / K, q % K);
   const int dmax = max_sep < K - 1 ? max_sep : K - 1;
   for (int j = 0; j < n_sub; ++j) {
     for (int d = 1; d <= dmax; ++d) {
@@ -160,19 +168,25 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
           const int ra = X.ros[a], rb = X.ros[b];
           const double ba = X.beta[a], bb = X.beta[b];
           const double ea = X.ecur[a], eb = X.ecur[b], lnu = X.lnu[a];
-          double wa[C], wb[C], va[1 + C], vb[1 + C];
+          double eab, eba;
+          if (TABLE) {
+            eab = em[a * kXTable + rb];
+            eba = em[b * kXTable + ra];
+          } else {
+            double wa[C], wb[C], va[1 + C], vb[1 + C];
 #pragma unroll
-          for (int c = 0; c < C; ++c) {
-            wa[c] = X.wd[a * C + c];
-            wb[c] = X.wd[b * C + c];
-          }
+            for (int c = 0; c < C; ++c) {
+              wa[c] = X.wd[a * C + c];
+              wb[c] = X.wd[b * C + c];
+            }
 #pragma unroll
-          for (int e = 0; e <= C; ++e) {
-            vb[e] = X.cp[rb * C1 + e];
-            va[e] = X.cp[ra * C1 + e];
+            for (int e = 0; e <= C; ++e) {
+              vb[e] = X.cp[rb * C1 + e];
+              va[e] = X.cp[ra * C1 + e];
+            }
+            eab = staged_sum<C>(vb, wa);
+            eba = staged_sum<C>(va, wb);
           }
-          const double eab = staged_sum<C>(vb, wa);
-          const double eba = staged_sum<C>(va, wb);
           const double delta = ba * (eab - ea) + bb * (eba - eb);
           const bool ok = isfinite(delta) && (lnu < -delta);
           if (d == 1 && ok) bits[a >> 6] |= 1ull << (a & 63);
@@ -213,6 +227,7 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
 __device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
                                int max_sep, int n_sub, uint64_t seed) {
   __shared__ XStage X;
+  __shared__ double em[kXTable * kXTable];
   const int K = L.K;
   if (K < 2) return;
   if (scheme == 0) {
@@ -223,10 +238,14 @@ __device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
       for (int a = a0 + 2 * (int)threadIdx.x; a + 1 < K; a += 2 * blockDim.x)
         attempt_pair(L, a, a + 1, 1, sweep, j, seed);
     }
+  } else if (K <= kXTable && L.C == 3) {
+    exchange_all_staged<3, true>(L, sweep, max_sep, n_sub, seed, X, em);
+  } else if (K <= kXTable && L.C == 5) {
+    exchange_all_staged<5, true>(L, sweep, max_sep, n_sub, seed, X, em);
   } else if (K <= kXStates && L.C == 3) {
-    exchange_all_staged<3>(L, sweep, max_sep, n_sub, seed, X);
+    exchange_all_staged<3, false>(L, sweep, max_sep, n_sub, seed, X, em);
   } else if (K <= kXStates && L.C == 5) {
-    exchange_all_staged<5>(L, sweep, max_sep, n_sub, seed, X);
+    exchange_all_staged<5, false>(L, sweep, max_sep, n_sub, seed, X, em);
   } else if (threadIdx.x == 0) {
     const int dmax = max_sep < K - 1 ? max_sep : K - 1;
     for (int j = 0; j < n_sub; ++j)
