@@ -105,6 +105,28 @@ def test_pair_terms_close_spheres_reach_every_branch():
     ctx.close()
 
 
+def test_pair_setup_replaces_earlier_parameters():
+    """A second bpmf_pair_setup replaces the first: evaluations then equal
+    those of a context that only ever had the second parameters."""
+    print_case("pairs re-setup")
+    system = synth.make_system(1)
+    lig, g = system.ligands[0], system.grid
+    p1 = synth.pair_params(lig, seed=1)
+    p2 = synth.pair_params(lig, seed=2)
+    p2["eps_solvent"] = 40.0
+    xs = dev(lig.x0[:2], torch.float32)
+    ca, (la,) = make_context(g, [lig], seed=1)
+    ca.pair_setup(la, p1)
+    ca.pair_setup(la, p2)
+    ta, fa = ca.pair_evaluate(la, xs)
+    cb, (lb,) = make_context(g, [lig], seed=1)
+    cb.pair_setup(lb, p2)
+    tb, fb = cb.pair_evaluate(lb, xs)
+    assert torch.equal(ta, tb) and torch.equal(fa, fb)
+    ca.close()
+    cb.close()
+
+
 def test_pair_setup_errors():
     print_case("pairs errors")
     import paper_1507_03703_amd as pkg

@@ -86,6 +86,58 @@ def test_replaced_states_equal_states_set_up_from_the_start():
     ctx_b.close()
 
 
+def test_graphs_captured_before_a_state_change_replay_the_new_states():
+    """Sweep graphs read the state parameters from device memory: replays
+    of a graph captured before bpmf_set_states equal plain launches after
+    it, bit for bit."""
+    print_case("set_states then graph replay")
+    system = synth.make_system(1)
+    lig, g = system.ligands[0], system.grid
+    K = lig.n_states
+    rng = np.random.default_rng(8)
+    T2 = rng.uniform(300, 600, size=K)
+    w2 = rng.uniform(0, 1, size=(K, 3))
+    dt2 = rng.uniform(0.5, 1.2, size=K)
+    runs = []
+    for chunk in (0, 8):
+        ctx, (lid,) = make_context(g, [lig], seed=21, capacity=20)
+        ctx.set_graph(chunk)
+        ctx.hmc_sweep(16, 10, exchange_every=1, sample_every=2)
+        ctx.set_states(lid, T2, w2, dt2)
+        ctx.hmc_sweep(16, 10, exchange_every=1, sample_every=2)
+        runs.append((ctx.get_replicas(lid), ctx.get_samples(lid),
+                     ctx.get_stats(lid)))
+        ctx.close()
+    (ra, sa, ta), (rb, sb, tb) = runs
+    for key in ("x", "state_of_replica", "comps", "counter"):
+        assert np.array_equal(ra[key], rb[key]), key
+    assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1])
+    for key in ("hmc_acc", "hmc_try", "ex_acc", "ex_try"):
+        assert np.array_equal(ta[key], tb[key]), key
+
+
+def test_single_ligand_sweeps_run_only_that_ligands_moves():
+    """External moves inside single-ligand sweep calls touch only that
+    ligand; its result equals the same units run over every ligand."""
+    print_case("single-ligand sweeps with external moves")
+    system = synth.make_system(1)
+    lig, g = system.ligands[0], system.grid
+    ctx_a, (a0, a1) = make_context(g, [lig, lig], seed=3)
+    ctx_b, (b0, b1) = make_context(g, [lig, lig], seed=3)
+    kw = dict(exchange_every=1, external_moves=4, external_k_max=3)
+    before = ctx_a.get_replicas(a0)
+    ctx_a.hmc_sweep_ligand(a1, 6, 10, **kw)
+    ctx_b.hmc_sweep(6, 10, **kw)
+    _same_ligand_state(ctx_a, a1, ctx_b, b1)
+    sa, sb = ctx_a.get_external_stats(a1), ctx_b.get_external_stats(b1)
+    assert np.array_equal(sa["tries"], sb["tries"]) and sa["tries"].sum() > 0
+    assert ctx_a.get_external_stats(a0)["tries"].sum() == 0
+    after = ctx_a.get_replicas(a0)
+    assert np.array_equal(before["x"], after["x"])
+    ctx_a.close()
+    ctx_b.close()
+
+
 def test_placements_match_oracle():
     print_case("placements")
     system = synth.make_system(1)
