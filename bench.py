@@ -677,6 +677,7 @@ def init_leg(pkg, torch, n_seeds=50, n_trials=200, n_com=453, n_orient=100,
                 "pairs_below_0.4": int((acc < 0.4).sum()),
                 "hmc_acceptance_min": float(hmc.min())}
 
+    protocol = paper_production(pkg, torch, g, lig, res, L, system.seed)
     built = exchange_rates(res["T"], res["w"], res["dt"], res["x"][:, 0])
     fixed = exchange_rates(lig.T, lig.w, lig.dt, lig.x0)
     built_paper = exchange_rates(res["T"], res["w"], res["dt"],
@@ -700,6 +701,7 @@ def init_leg(pkg, torch, n_seeds=50, n_trials=200, n_com=453, n_orient=100,
         "built_ladder": built, "fixed_ladder": fixed,
         "built_ladder_paper_iteration": built_paper,
         "fixed_ladder_paper_iteration": fixed_paper,
+        "paper_protocol": protocol,
     }
 
 
@@ -756,6 +758,88 @@ def dataclasses_replace_states(lig, K):
     return dataclasses.replace(lig, T=np.full(K, 300.0),
                                w=np.ones((K, lig.scale.shape[1])),
                                dt=np.ones(K), x0=lig.x0[:K])
+
+
+def paper_production(pkg, torch, g, lig, res, L, seed, n_cycles=15,
+                     iters=1000, snaps=50):
+    """Production on the initialised ladder as the paper runs it (Equilibration
+    and production): cycles of `iters` iterations of an HMC move, 20
+    external moves in the states with alpha < 0.01 and 25 exchange sweeps
+    over separations 1..5, `snaps` snapshots per cycle; between cycles the
+    state-insertion check (neighbour exchange acceptance below 0.4); the
+    equilibrated start by equilibration detection on the sum over states of
+    each state's reduced potential; BPMF by MBAR over every other state of the ladder
+    (one solve holds at most 128 states), with its spread over cycles."""
+    import dataclasses
+    import numpy as np
+    K = res["n_states"]
+    alpha = np.asarray(res["alpha"])
+    every = iters // snaps
+    lg = dataclasses.replace(lig, T=res["T"], w=res["w"], dt=res["dt"],
+                             x0=np.ascontiguousarray(res["x"][:, 0],
+                                                     np.float32))
+    ctx = pkg.Context(seed=seed + 13, device=0)
+    ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+    lid = ctx.ligand_setup(lg, sample_capacity=n_cycles * snaps)
+    kw = dict(exchange_every=1, exchange_scheme=1, max_sep=5,
+              exchange_sweeps=25, external_moves=20,
+              external_k_max=int((alpha < 0.01).sum()), sample_every=every)
+    inserts = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prev = ctx.get_stats(lid)
+    for _ in range(n_cycles):
+        ctx.hmc_sweep(iters, L, **kw)
+        st = ctx.get_stats(lid)
+        acc = (st["ex_acc"] - prev["ex_acc"]) / np.maximum(
+            st["ex_try"] - prev["ex_try"], 1)
+        prev = st
+        inserts.append(len(pkg.protocol_insert(alpha, acc, 0.4)) - K)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    n_rec = n_cycles * snaps
+    u = ctx.energy_matrix(lid, None, n_samples=n_rec * K)
+    # equilibration detected on the whole ladder: the sum over states of
+    # each state's reduced potential on its own sample of that snapshot
+    tot = torch.diagonal(u.view(K, n_rec, K), dim1=0, dim2=2).sum(dim=1)
+    t_eq, g_eq, _ = pkg.detect_equilibration(tot.cpu().numpy(), 50)
+    sub = np.arange(0, K, 2)
+    if sub[-1] != K - 1:
+        sub = np.append(sub, K - 1)
+    rec = np.arange(t_eq, n_rec)
+    cols = torch.as_tensor((rec[:, None] * K + sub[None, :]).reshape(-1),
+                           device=u.device)
+    rows = torch.as_tensor(sub, device=u.device)
+    us = u.index_select(0, rows).index_select(1, cols).contiguous()
+    f, var, _ = ctx.mbar(us, np.full(len(sub), len(rec)), tol=1e-10,
+                         max_iter=200)
+    per = snaps
+    parts, ns = [], []
+    for cyc in range(n_cycles):
+        r = np.arange(max(cyc * per, t_eq), (cyc + 1) * per)
+        if len(r) < per // 2:
+            continue
+        cc = torch.as_tensor((r[:, None] * K + sub[None, :]).reshape(-1),
+                             device=u.device)
+        parts.append(u.index_select(0, rows).index_select(1, cc).contiguous())
+        ns.append(np.full(len(sub), len(r)))
+    fb = ctx.mbar_batch(parts, ns, tol=1e-10, max_iter=200)
+    blk = np.array([r[0][-1] - r[0][0] for r in fb])
+    st = ctx.get_stats(lid)
+    acc = st["ex_acc"] / np.maximum(st["ex_try"], 1)
+    ctx.close()
+    return {"states": int(K), "cycles": n_cycles, "iterations_per_cycle": iters,
+            "snapshots_per_cycle": snaps, "seconds": sec,
+            "ms_per_iteration": sec / (n_cycles * iters) * 1e3,
+            "states_to_insert_per_cycle": inserts,
+            "neighbour_exchange_min": float(acc.min()),
+            "equilibrated_from_snapshot": int(t_eq),
+            "equilibration_observable_inefficiency": float(g_eq),
+            "mbar_states": int(len(sub)),
+            "bpmf_kT": float(f[-1] - f[0]),
+            "sigma_mbar_kT": float(np.sqrt(max(var[-1], 0.0))),
+            "cycle_bpmf_kT": [float(b) for b in blk],
+            "cycle_sd_kT": float(blk.std(ddof=1)) if len(blk) > 1 else None}
 
 
 def main():
@@ -851,6 +935,11 @@ def main():
         out["learned_proposal"] = learned_leg(
             pkg, torch, train_steps=args.train_steps, burn=args.burn_sweeps,
             long_sweeps=args.long_sweeps, prod_sweeps=args.prod_sweeps)
+        if args.init:
+            # both ladders end in the same two states: the same BPMF
+            pp = out["initialization"]["paper_protocol"]
+            ref = out["learned_proposal"]["reference"]
+            pp["bpmf_minus_long_plain_run_kT"] = pp["bpmf_kT"] - ref["bpmf_kT"]
     print(json.dumps(out))
 
 
