@@ -86,20 +86,31 @@ __device__ bool attempt_pair(const LigDev& L, int a, int b, int sep,
 
 // The all-separations sweep with the state data staged in LDS.  Within one
 // separation d, pair (a, a + d) only touches states of residue a mod d, so
-// the d residue classes are independent chains: running each chain in
-// ascending a gives the decisions of the ascending order over all a.  The
-// uniforms of a separation are drawn first, in parallel; the energies are
-// the same double sums as state_energy, so every decision is the one the
-// one-thread order takes.  E_cur[k] holds the energy of the replica in
-// state k at state k.
+// the d residue classes are independent chains, each taken in ascending a.
+// A chain is a sequence of runs: the replica of the run's first state q is
+// carried up the chain while its swaps are accepted and stays at the state
+// where one is rejected (or where the chain ends); the next run starts one
+// step further up with that state's own replica.  When pair (a, a + d) is
+// attempted, state a + d still holds its replica from the start of the
+// pass, so the run that starts at q depends only on q and the labels at
+// the start of the pass.  Every possible run is therefore followed at once,
+// one thread per first state; then one thread per class walks the runs that
+// actually happen (first state of the class, then one state past each
+// run's end) and every state takes its new replica.  The energies are the
+// same double sums as state_energy and each attempt sees the replicas the
+// one-thread order gives it, so every decision is that order's.
 constexpr int kXStates = 256, kXChannels = 5;
 struct XStage {
   double cp[kXStates * (1 + kXChannels)];  // components per replica
   double wd[kXStates * kXChannels];        // weights per state
   double beta[kXStates];
-  double ecur[kXStates];
-  double lnu[kXStates];  // ln u of the current separation, by lower state
-  int ros[kXStates];
+  double ecur[2][kXStates];  // energy of the replica in state k at state k
+  double lnu[kXStates];      // ln u of the current separation, by lower state
+  double eo[kXStates];       // energy of the replica in a + d at state a
+  double erest[kXStates];    // run from q: energy of its replica where it stays
+  int ros[2][kXStates];      // replica of each state (two buffers)
+  int rest[kXStates];        // run from q: the state where its replica stays
+  int owner[kXStates];       // first state of the run that ends at k, or -1
   int ntry[kXStates], nacc[kXStates];  // separation-1 counts, by lower state
 };
 
@@ -124,8 +135,8 @@ __device__ __forceinline__ double staged_energy(const XStage& X, int k,
 }
 
 // ladders of up to kXTable states also keep the whole table E(k, r) of
-// every replica's energy at every state, computed once per call: a chain
-// step then reads two entries instead of summing components
+// every replica's energy at every state, computed once per call: a run
+// step then reads one entry instead of summing components
 constexpr int kXTable = 64;
 
 template <int C, bool TABLE>
@@ -133,85 +144,126 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
                                     int max_sep, int n_sub, uint64_t seed,
                                     XStage& X, double* em) {
   const int K = L.K, C1 = 1 + C;
-  __shared__ unsigned long long acc_bits[kXStates / 64];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < K * C1; i += nt) X.cp[i] = L.comps[i];
   for (int i = tid; i < K * C; i += nt) X.wd[i] = L.wd[i];
   for (int k = tid; k < K; k += nt) {
     X.beta[k] = L.beta[k];
-    X.ros[k] = L.replica_of_state[k];
+    X.ros[0][k] = L.replica_of_state[k];
     X.ntry[k] = 0;
     X.nacc[k] = 0;
   }
   __syncthreads();
-  for (int k = tid; k < K; k += nt) X.ecur[k] = staged_energy<C>(X, k, X.ros[k]);
+  for (int k = tid; k < K; k += nt)
+    X.ecur[0][k] = staged_energy<C>(X, k, X.ros[0][k]);
   if (TABLE)
     for (int q = tid; q < K * K; q += nt)
       em[(q / K) * kXTable + q % K] = staged_energy<C>(X, q / K, q % K);
+  __syncthreads();
+  int cur = 0;
   const int dmax = max_sep < K - 1 ? max_sep : K - 1;
   for (int j = 0; j < n_sub; ++j) {
     for (int d = 1; d <= dmax; ++d) {
-      for (int a = tid; a + d < K; a += nt) {
-        const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)d << 8);
-        X.lnu[a] = log(u01d(draw(seed, (uint32_t)a, L.id, j, sweep,
-                                 purpose).x));
+      const int* ros = X.ros[cur];
+      const double* ecur = X.ecur[cur];
+      // uniforms, and the upper replica's energy at the lower state
+      for (int a = tid; a < K; a += nt) {
+        X.owner[a] = -1;
+        if (a + d < K) {
+          const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)d << 8);
+          X.lnu[a] = log(u01d(draw(seed, (uint32_t)a, L.id, j, sweep,
+                                   purpose).x));
+          X.eo[a] = TABLE ? em[a * kXTable + ros[a + d]]
+                          : staged_energy<C>(X, a, ros[a + d]);
+        }
       }
       __syncthreads();
-      // residue classes of d, one thread each.  A step issues every load
-      // that does not depend on the labels with the label loads, then the
-      // two replicas' components: two LDS round trips per step.  The
-      // separation-1 chain keeps its accept bits in registers.
-      for (int rho = tid; rho < d; rho += nt) {
-        unsigned long long bits[kXStates / 64] = {0ull, 0ull, 0ull, 0ull};
-        for (int a = rho; a + d < K; a += d) {
-          const int b = a + d;
-          const int ra = X.ros[a], rb = X.ros[b];
-          const double ba = X.beta[a], bb = X.beta[b];
-          const double ea = X.ecur[a], eb = X.ecur[b], lnu = X.lnu[a];
-          double eab, eba;
-          if (TABLE) {
-            eab = em[a * kXTable + rb];
-            eba = em[b * kXTable + ra];
-          } else {
-            double wa[C], wb[C], va[1 + C], vb[1 + C];
+      // the run that starts at q, for every q; each step's operands are
+      // loaded while the step before it is decided
+      for (int q = tid; q < K; q += nt) {
+        int a = q;
+        double e = ecur[q];  // energy of the carried replica at state a
+        if (q + d < K) {
+          const int r = ros[q];
+          double v[1 + C], wb[C], et = 0.0;
+          if (!TABLE)
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-              wa[c] = X.wd[a * C + c];
-              wb[c] = X.wd[b * C + c];
-            }
+            for (int i = 0; i <= C; ++i) v[i] = X.cp[r * C1 + i];
+          int b = a + d;
+          double ba = X.beta[a], eoa = X.eo[a], lna = X.lnu[a];
+          double bb = X.beta[b], ebb = ecur[b];
+          if (TABLE)
+            et = em[b * kXTable + r];
+          else
 #pragma unroll
-            for (int e = 0; e <= C; ++e) {
-              vb[e] = X.cp[rb * C1 + e];
-              va[e] = X.cp[ra * C1 + e];
-            }
-            eab = staged_sum<C>(vb, wa);
-            eba = staged_sum<C>(va, wb);
-          }
-          const double delta = ba * (eab - ea) + bb * (eba - eb);
-          const bool ok = isfinite(delta) && (lnu < -delta);
-          if (d == 1 && ok) bits[a >> 6] |= 1ull << (a & 63);
-          if (ok) {
-            X.ros[a] = rb;
-            X.ros[b] = ra;
-            X.ecur[a] = eab;
-            X.ecur[b] = eba;
+            for (int c = 0; c < C; ++c) wb[c] = X.wd[b * C + c];
+          for (;;) {
+            // the next step's operands (unused when this step ends the run)
+            const int b2 = b + d < K ? b + d : b;
+            const double neo = X.eo[b], nln = X.lnu[b];
+            const double nbb = X.beta[b2], neb = ecur[b2];
+            double nwb[C], net = 0.0;
+            if (TABLE)
+              net = em[b2 * kXTable + r];
+            else
+#pragma unroll
+              for (int c = 0; c < C; ++c) nwb[c] = X.wd[b2 * C + c];
+            // the carried replica at state b
+            const double eba = TABLE ? et : staged_sum<C>(v, wb);
+            const double delta = ba * (eoa - e) + bb * (eba - ebb);
+            const bool ok = isfinite(delta) && (lna < -delta);
+            if (!ok) break;
+            e = eba;
+            a = b;
+            if (a + d >= K) break;
+            b = b2;
+            ba = bb;
+            eoa = neo;
+            lna = nln;
+            bb = nbb;
+            ebb = neb;
+            et = net;
+#pragma unroll
+            for (int c = 0; c < C; ++c) wb[c] = nwb[c];
           }
         }
-        if (d == 1)
-          for (int q = 0; q < kXStates / 64; ++q) acc_bits[q] = bits[q];
+        X.rest[q] = a;
+        X.erest[q] = e;
       }
       __syncthreads();
-      if (d == 1) {
-        // every pair (a, a+1) was attempted once in this sweep
-        for (int a = tid; a + 1 < K; a += nt) {
+      // the runs that happen: from the class's first state, each one
+      // starting one step past the previous one's end
+      for (int rho = tid; rho < d; rho += nt)
+        for (int q = rho; q < K;) {
+          const int a = X.rest[q];
+          X.owner[a] = q;
+          q = a + d;
+        }
+      __syncthreads();
+      // a state where a run ends takes the run's replica; any other state
+      // had its swap with the state d above accepted
+      int* nros = X.ros[cur ^ 1];
+      double* necur = X.ecur[cur ^ 1];
+      for (int a = tid; a < K; a += nt) {
+        const int q = X.owner[a];
+        if (q >= 0) {
+          nros[a] = ros[q];
+          necur[a] = X.erest[q];
+        } else {
+          nros[a] = ros[a + d];
+          necur[a] = X.eo[a];
+        }
+        if (d == 1 && a + 1 < K) {
           X.ntry[a] += 1;
-          X.nacc[a] += (int)((acc_bits[a >> 6] >> (a & 63)) & 1ull);
+          X.nacc[a] += (int)(q < 0);
         }
       }
+      cur ^= 1;
+      __syncthreads();
     }
   }
   for (int k = tid; k < K; k += nt) {
-    const int r = X.ros[k];
+    const int r = X.ros[cur][k];
     L.replica_of_state[k] = r;
     L.state_of_replica[r] = k;
     if (k + 1 < K && X.ntry[k]) {

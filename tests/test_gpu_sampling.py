@@ -9,6 +9,8 @@ where the oracle's own margin |ln u + beta dH| < 1e-3 (there float32
 rounding may decide), state maps exactly unless an exchange exponent lies
 within 1e-6 of its uniform.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -150,6 +152,69 @@ def test_exchange_decisions_bitwise_large_ladders(K):
     assert stats["ex_acc"].sum() > 0
     ctx.close()
 
+
+
+def _exchange_ligand(K, C):
+    """A ligand with K states on C channels: the two-atom toy on the linear
+    ladder (C = 3) or a config-1 ligand with the soft grids on their
+    schedule (C = 5)."""
+    if C == 3:
+        T, w = synth.ladder(K)
+        lig = synth.toy_ligand(np.array([[0.0, 0, 0], [1.5, 0, 0]]),
+                               [[0, 1]], 10.0, T, w[:, 0])
+        return synth.linear_field_grid(8, 1.0, (0.5, 0.0, 0.0), 0.0), lig
+    system = synth.make_system(1)
+    g, (lig,) = synth.add_soft_grids(system.grid, system.ligands[:1])
+    T, w = synth.soft_schedule(K)
+    lig = dataclasses.replace(
+        lig, T=T, w=w, dt=np.ones(K),
+        x0=np.repeat(lig.x0[:1], K, axis=0).astype(np.float32))
+    return g, lig
+
+
+@pytest.mark.parametrize("K,C", [(40, 3), (163, 5)])
+@pytest.mark.parametrize("mode", ["all_accepted", "all_rejected",
+                                  "long_runs"])
+def test_exchange_runs_edge_cases(K, C, mode):
+    """All-separation sweeps in which every swap is accepted (equal energies:
+    each chain carries its first replica to its top), none is (non-finite
+    energies) or nearly all are (long runs of accepted swaps), on the
+    energy-table path (40 states) and the staged-component path (163 states,
+    five channels): labels and counts equal the oracle's."""
+    print_case("exchange runs", K, C, mode)
+    g, lig = _exchange_ligand(K, C)
+    rng = np.random.default_rng(K + C)
+    comps = rng.normal(scale=0.02, size=(K, 1 + C))
+    if mode == "all_accepted":
+        comps[:] = 0.0
+    elif mode == "all_rejected":
+        comps[:, 0] = np.inf
+    sor = rng.permutation(K).astype(np.int32)
+    ctx, (lid,) = make_context(g, [lig], seed=13)
+    ctx.set_replicas(lid, lig.x0, sor, comps, 5)
+    ctx.exchange(lid, scheme=1, max_sep=5, n_sweeps=25)
+    st = ctx.get_replicas(lid)
+    s = oracle.Sampler(oracle.OGrid(g), oracle.OLigand(lig), seed=13,
+                       lig_id=lid, x0=lig.x0)
+    s.comps = np.ascontiguousarray(comps)
+    s.state = sor.copy()
+    s.rep_of_state = np.ascontiguousarray(np.argsort(sor).astype(np.int32))
+    s.sweep_count = 5
+    s.exchange(scheme=1, max_sep=5, n_sweeps=25)
+    assert np.array_equal(st["state_of_replica"], s.state)
+    stats = ctx.get_stats(lid)
+    assert np.array_equal(stats["ex_try"], s.ex_try)
+    assert np.array_equal(stats["ex_acc"], s.ex_acc)
+    n_try = 25 * (K - 1)
+    assert stats["ex_try"].sum() == n_try
+    if mode == "all_accepted":
+        assert stats["ex_acc"].sum() == n_try
+    elif mode == "all_rejected":
+        assert stats["ex_acc"].sum() == 0
+        assert np.array_equal(st["state_of_replica"], sor)
+    else:
+        assert stats["ex_acc"].sum() > 0.9 * n_try
+    ctx.close()
 
 def test_checkpoint_resume_is_bitwise():
     print_case("checkpoint")
