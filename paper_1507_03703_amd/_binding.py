@@ -422,9 +422,18 @@ class Context:
                                        int(max_sep), int(n_sweeps)))
 
     # -- u_kn, MBAR -----------------------------------------------------------
+    def n_records(self, ligand_id):
+        """Number of sample records so far (each holds one sample per
+        state)."""
+        nr = C.c_int64(0)
+        _check(self._lib.bpmf_get_samples(self._h, int(ligand_id),
+                                          C.byref(nr), None, None))
+        return int(nr.value)
+
     def energy_matrix(self, ligand_id, samples=None, n_samples=None, out=None):
         """u_kn (K x N float64 CUDA tensor) for device samples (N, n, 3)
-        float32, or for the recorded samples when samples is None."""
+        float32, or for the recorded samples when samples is None (all of
+        them, K x records, unless n_samples says otherwise)."""
         torch = self._torch
         K = self.ligands[ligand_id]["K"]
         if samples is not None:
@@ -433,7 +442,8 @@ class Context:
             N = samples.shape[0]
             ptr = samples.data_ptr()
         else:
-            N = int(n_samples)
+            N = (K * self.n_records(ligand_id) if n_samples is None
+                 else int(n_samples))
             ptr = None
         if out is None:
             out = torch.empty((K, N), dtype=torch.float64,
@@ -446,7 +456,8 @@ class Context:
     def energy_matrix_batch(self, ligand_ids, samples=None, n_samples=None,
                             outs=None):
         """u_kn of several ligands in one call.  samples: None (recorded
-        samples of every ligand, n_samples[i] each) or a list of device
+        samples of every ligand, n_samples[i] each, or all of them when
+        n_samples or its entry is None) or a list of device
         tensors (N_i, n_i, 3) float32 / None; outs: optional list of K_i x
         N_i float64 tensors.  Returns the list of u_kn tensors."""
         torch = self._torch
@@ -464,9 +475,11 @@ class Context:
                     x.is_contiguous()
                 ns[i] = x.shape[0]
                 ptrs[i] = x.data_ptr()
-            else:
-                ns[i] = int(n_samples[i])
             K = self.ligands[lid]["K"]
+            if x is None:
+                ns[i] = (K * self.n_records(lid)
+                         if n_samples is None or n_samples[i] is None
+                         else int(n_samples[i]))
             u = outs[i] if outs is not None else torch.empty(
                 (K, int(ns[i])), dtype=torch.float64,
                 device=f"cuda:{self.device}")

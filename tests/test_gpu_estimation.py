@@ -87,6 +87,11 @@ def test_energy_matrix_of_recorded_samples():
     u_exp = ctx.energy_matrix(lid, dev(xs.reshape(R * K, lig.n_atoms, 3),
                                        torch.float32))
     assert torch.equal(u_rec, u_exp)
+    # without n_samples: every recorded sample
+    assert ctx.n_records(lid) == R
+    assert torch.equal(ctx.energy_matrix(lid), u_rec)
+    (u_b,) = ctx.energy_matrix_batch([lid])
+    assert torch.equal(u_b, u_rec)
     # the recorded components give the same u_kn through the affine form
     beta = 1.0 / (oracle.R_GAS * lig.T)
     c = cs.reshape(R * K, -1)
