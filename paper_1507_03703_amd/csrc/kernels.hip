@@ -105,7 +105,7 @@ struct XStage {
   double wd[kXStates * kXChannels];        // weights per state
   double beta[kXStates];
   double ecur[2][kXStates];  // energy of the replica in state k at state k
-  double lnu[kXStates];      // ln u of the current separation, by lower state
+  double lnu[2][kXStates];   // ln u of a pass, by lower state (two buffers)
   double eo[kXStates];       // energy of the replica in a + d at state a
   double erest[kXStates];    // run from q: energy of its replica where it stays
   int ros[2][kXStates];      // replica of each state (two buffers)
@@ -160,22 +160,27 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
     for (int q = tid; q < K * K; q += nt)
       em[(q / K) * kXTable + q % K] = staged_energy<C>(X, q / K, q % K);
   __syncthreads();
-  int cur = 0;
+  int cur = 0, lb = 0;
   const int dmax = max_sep < K - 1 ? max_sep : K - 1;
+  // ln u of the pass (j, d) into buffer b, by threads t0, t0 + stride, ...
+  auto draw_pass = [&](int j, int d, int b, int t0, int stride) {
+    const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)d << 8);
+    for (int a = t0; a + d < K; a += stride)
+      X.lnu[b][a] =
+          log(u01d(draw(seed, (uint32_t)a, L.id, j, sweep, purpose).x));
+  };
+  if (n_sub > 0 && dmax > 0) draw_pass(0, 1, 0, tid, nt);
   for (int j = 0; j < n_sub; ++j) {
     for (int d = 1; d <= dmax; ++d) {
       const int* ros = X.ros[cur];
       const double* ecur = X.ecur[cur];
-      // uniforms, and the upper replica's energy at the lower state
+      const double* lnu = X.lnu[lb];
+      // the upper replica's energy at the lower state
       for (int a = tid; a < K; a += nt) {
         X.owner[a] = -1;
-        if (a + d < K) {
-          const uint32_t purpose = (uint32_t)kExchange | ((uint32_t)d << 8);
-          X.lnu[a] = log(u01d(draw(seed, (uint32_t)a, L.id, j, sweep,
-                                   purpose).x));
+        if (a + d < K)
           X.eo[a] = TABLE ? em[a * kXTable + ros[a + d]]
                           : staged_energy<C>(X, a, ros[a + d]);
-        }
       }
       __syncthreads();
       // the run that starts at q, for every q; each step's operands are
@@ -190,7 +195,7 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
 #pragma unroll
             for (int i = 0; i <= C; ++i) v[i] = X.cp[r * C1 + i];
           int b = a + d;
-          double ba = X.beta[a], eoa = X.eo[a], lna = X.lnu[a];
+          double ba = X.beta[a], eoa = X.eo[a], lna = lnu[a];
           double bb = X.beta[b], ebb = ecur[b];
           if (TABLE)
             et = em[b * kXTable + r];
@@ -200,7 +205,7 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
           for (;;) {
             // the next step's operands (unused when this step ends the run)
             const int b2 = b + d < K ? b + d : b;
-            const double neo = X.eo[b], nln = X.lnu[b];
+            const double neo = X.eo[b], nln = lnu[b];
             const double nbb = X.beta[b2], neb = ecur[b2];
             double nwb[C], net = 0.0;
             if (TABLE)
@@ -231,6 +236,15 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
         X.erest[q] = e;
       }
       __syncthreads();
+      // the next pass's uniforms, by the threads past the first wavefront
+      // while it walks (by every thread, before its walk, in a block of
+      // one wavefront)
+      {
+        const int dn = d < dmax ? d + 1 : 1, jn = d < dmax ? j : j + 1;
+        const int t0 = nt > kWave ? kWave : 0;
+        if (jn < n_sub && tid >= t0)
+          draw_pass(jn, dn, lb ^ 1, tid - t0, nt - t0);
+      }
       // the runs that happen: from the class's first state, each one
       // starting one step past the previous one's end
       for (int rho = tid; rho < d; rho += nt)
@@ -259,6 +273,7 @@ __device__ void exchange_all_staged(const LigDev& L, uint64_t sweep,
         }
       }
       cur ^= 1;
+      lb ^= 1;
       __syncthreads();
     }
   }
