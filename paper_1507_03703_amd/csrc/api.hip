@@ -1968,15 +1968,7 @@ GemmArgs gemm(int M, int N, int K, const float* A, int64_t sam, int64_t sak,
 // out = MLP(feats) for B rows
 int mlp_forward(bpmf_ctx* c, const float* P, const float* feats, int B,
                 const MlpBufs& b, float* out, hipStream_t st) {
-  HIP_TRY(launch_gemm(gemm(B, kNHid, kNFeat, feats, kNFeat, 1, P + kOffW1, kNHid,
-                           1, b.H1, kNHid, P + kOffB1, kEpiSilu, b.Z1, nullptr),
-                      st));
-  HIP_TRY(launch_gemm(gemm(B, kNHid, kNHid, b.H1, kNHid, 1, P + kOffW2, kNHid, 1,
-                           b.H2, kNHid, P + kOffB2, kEpiSilu, b.Z2, nullptr),
-                      st));
-  HIP_TRY(launch_gemm(gemm(B, kNOut, kNHid, b.H2, kNHid, 1, P + kOffW3, kNOut, 1,
-                           out, kNOut, P + kOffB3, kEpiStore, nullptr, nullptr),
-                      st));
+  HIP_TRY(launch_mlp_forward(P, feats, B, b.Z1, b.H1, b.Z2, b.H2, out, st));
   return BPMF_OK;
 }
 

@@ -56,6 +56,11 @@ struct GemmArgs {
 };
 
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t st);
+// the whole network for B rows (features B x kNFeat): Z1, H1, Z2, H2 (B x
+// kNHid) and out (B x kNOut), equal to three launch_gemm calls
+hipError_t launch_mlp_forward(const float* P, const float* X, int B,
+                              float* Z1, float* H1, float* Z2, float* H2,
+                              float* out, hipStream_t st);
 hipError_t launch_colsum(const float* X, int rows, int cols, int64_t ld,
                          float* out, hipStream_t st);
 hipError_t launch_nll(const float* out, const float* pose, int B, float* dout,

@@ -25,10 +25,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // fp32 -> bf16 bits, round to nearest even (finite inputs); NaN stays NaN
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
-  unsigned int u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  const unsigned int u = __float_as_uint(f);
+  const unsigned int rn = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  const unsigned int qn = (u >> 16) | 0x40u;
+  return (unsigned short)((u & 0x7fffffffu) > 0x7f800000u ? qn : rn);
 }
 
 constexpr int kTile = 64;   // output tile edge per workgroup
@@ -111,6 +111,108 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
           g.C[o] = v;
         }
       }
+}
+
+// The three dense layers for kFRows rows per workgroup.  A row's path
+// through the network does not involve the other rows, so one workgroup
+// takes its rows through all three layers with the activations held in LDS
+// as the next layer's bf16 operand; each wave owns every fourth 16-column
+// output tile.  Every tile is accumulated by the same MFMA over the same
+// 32-wide k chunks in the same order, from operands rounded to bf16 in the
+// same way, and finished by the same epilogue as k_gemm, so the outputs are
+// those of three k_gemm launches.
+constexpr int kFRows = 16;
+constexpr int kFLd = kNHid + kPad;  // LDS row length (bf16 elements)
+
+// one layer: out(16 x N) = act(A(16 x Kin) W(Kin x N) + bias), A in LDS.
+// A wave accumulates all its tiles in one pass over k, so the weight loads
+// of every tile of a k chunk are in flight together.
+template <int KIN, int N, bool HIDDEN>
+__device__ __forceinline__ void dense_rows(
+    const unsigned short (*A)[kFLd], const float* __restrict__ W,
+    const float* __restrict__ bias, int row0, int B, float* __restrict__ Z,
+    float* __restrict__ H, unsigned short (*Hn)[kFLd], int lane, int wv) {
+  constexpr int kTiles = (N + 15) / 16, kTPW = (kTiles + 3) / 4;
+  const int kg = (lane >> 4) * 8;
+  f32x4 acc[kTPW];
+#pragma unroll
+  for (int i = 0; i < kTPW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int k0 = 0; k0 < KIN; k0 += kKStep) {
+    bf16x8 a, b[kTPW];
+    // loads at clamped (in-bounds) indices, unconditionally, so that they
+    // issue together; out-of-range operands are then zeroed
+    float w[kTPW][8];
+    unsigned short av[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + kg + e, kc = k < KIN ? k : KIN - 1;
+      av[e] = A[lane & 15][kc];
+#pragma unroll
+      for (int i = 0; i < kTPW; ++i) {
+        const int n = (wv + 4 * i) * 16 + (lane & 15), nc = n < N ? n : N - 1;
+        w[i][e] = W[(int64_t)kc * N + nc];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const bool in = k0 + kg + e < KIN;
+      a[e] = __builtin_bit_cast(__bf16, in ? av[e] : (unsigned short)0);
+#pragma unroll
+      for (int i = 0; i < kTPW; ++i) {
+        const int n = (wv + 4 * i) * 16 + (lane & 15);
+        b[i][e] = __builtin_bit_cast(
+            __bf16, (in && n < N) ? bf16_bits(w[i][e]) : (unsigned short)0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kTPW; ++i)
+      if (wv + 4 * i < kTiles)  // uniform over the wave
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[i], acc[i], 0,
+                                                         0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < kTPW; ++i) {
+    const int n = (wv + 4 * i) * 16 + (lane & 15);
+    if (n >= N) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = (lane >> 4) * 4 + q, m = row0 + r;
+      const float v = acc[i][q] + bias[n];
+      if (HIDDEN) {
+        const float h = silu(v);
+        Hn[r][n] = bf16_bits(h);
+        if (m < B) {
+          Z[(int64_t)m * N + n] = v;
+          H[(int64_t)m * N + n] = h;
+        }
+      } else if (m < B) {
+        H[(int64_t)m * N + n] = v;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(
+    const float* __restrict__ P, const float* __restrict__ X, int B,
+    float* __restrict__ Z1, float* __restrict__ H1, float* __restrict__ Z2,
+    float* __restrict__ H2, float* __restrict__ out) {
+  __shared__ __align__(16) unsigned short S[2][kFRows][kFLd];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int row0 = blockIdx.x * kFRows;
+  for (int e = tid; e < kFRows * kNFeat; e += 256) {
+    const int r = e / kNFeat, k = e - r * kNFeat, m = row0 + r;
+    S[0][r][k] = bf16_bits(m < B ? X[(int64_t)m * kNFeat + k] : 0.f);
+  }
+  __syncthreads();
+  dense_rows<kNFeat, kNHid, true>(S[0], P + kOffW1, P + kOffB1, row0, B, Z1,
+                                  H1, S[1], lane, wv);
+  __syncthreads();
+  dense_rows<kNHid, kNHid, true>(S[1], P + kOffW2, P + kOffB2, row0, B, Z2,
+                                 H2, S[0], lane, wv);
+  __syncthreads();
+  dense_rows<kNHid, kNOut, false>(S[0], P + kOffW3, P + kOffB3, row0, B,
+                                  nullptr, out, nullptr, lane, wv);
 }
 
 // column sums of X (rows x cols, row stride ld): out[c] = sum_r X[r, c].
@@ -617,6 +719,15 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0) return hipSuccess;
   dim3 grid((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* P, const float* X, int B,
+                              float* Z1, float* H1, float* Z2, float* H2,
+                              float* out, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((B + kFRows - 1) / kFRows),
+                     dim3(256), 0, st, P, X, B, Z1, H1, Z2, H2, out);
   return hipGetLastError();
 }
 
