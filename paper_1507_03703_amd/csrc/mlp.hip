@@ -116,12 +116,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // The three dense layers for kFRows rows per workgroup.  A row's path
 // through the network does not involve the other rows, so one workgroup
 // takes its rows through all three layers with the activations held in LDS
-// as the next layer's bf16 operand; each wave owns every fourth 16-column
-// output tile.  Every tile is accumulated by the same MFMA over the same
+// as the next layer's bf16 operand; each wave owns every kFWaves-th
+// 16-column output tile.  Every tile is accumulated by the same MFMA over the same
 // 32-wide k chunks in the same order, from operands rounded to bf16 in the
 // same way, and finished by the same epilogue as k_gemm, so the outputs are
 // those of three k_gemm launches.
 constexpr int kFRows = 16;
+constexpr int kFWaves = 16;  // wavefronts per workgroup
 constexpr int kFLd = kNHid + kPad;  // LDS row length (bf16 elements)
 
 // one layer: out(16 x N) = act(A(16 x Kin) W(Kin x N) + bias), A in LDS.
@@ -132,7 +133,8 @@ __device__ __forceinline__ void dense_rows(
     const unsigned short (*A)[kFLd], const float* __restrict__ W,
     const float* __restrict__ bias, int row0, int B, float* __restrict__ Z,
     float* __restrict__ H, unsigned short (*Hn)[kFLd], int lane, int wv) {
-  constexpr int kTiles = (N + 15) / 16, kTPW = (kTiles + 3) / 4;
+  constexpr int kTiles = (N + 15) / 16;
+  constexpr int kTPW = (kTiles + kFWaves - 1) / kFWaves;
   const int kg = (lane >> 4) * 8;
   f32x4 acc[kTPW];
 #pragma unroll
@@ -150,7 +152,8 @@ __device__ __forceinline__ void dense_rows(
       av[e] = A[lane & 15][kc];
 #pragma unroll
       for (int i = 0; i < kTPW; ++i) {
-        const int n = (wv + 4 * i) * 16 + (lane & 15), nc = n < N ? n : N - 1;
+        const int n = (wv + kFWaves * i) * 16 + (lane & 15);
+        const int nc = n < N ? n : N - 1;
         w[i][e] = W[(int64_t)kc * N + nc];
       }
     }
@@ -160,20 +163,20 @@ __device__ __forceinline__ void dense_rows(
       a[e] = __builtin_bit_cast(__bf16, in ? av[e] : (unsigned short)0);
 #pragma unroll
       for (int i = 0; i < kTPW; ++i) {
-        const int n = (wv + 4 * i) * 16 + (lane & 15);
+        const int n = (wv + kFWaves * i) * 16 + (lane & 15);
         b[i][e] = __builtin_bit_cast(
             __bf16, (in && n < N) ? bf16_bits(w[i][e]) : (unsigned short)0);
       }
     }
 #pragma unroll
     for (int i = 0; i < kTPW; ++i)
-      if (wv + 4 * i < kTiles)  // uniform over the wave
+      if (wv + kFWaves * i < kTiles)  // uniform over the wave
         acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[i], acc[i], 0,
                                                          0, 0);
   }
 #pragma unroll
   for (int i = 0; i < kTPW; ++i) {
-    const int n = (wv + 4 * i) * 16 + (lane & 15);
+    const int n = (wv + kFWaves * i) * 16 + (lane & 15);
     if (n >= N) continue;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -193,14 +196,14 @@ __device__ __forceinline__ void dense_rows(
   }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_forward(
+__global__ __launch_bounds__(kFWaves * 64) void k_mlp_forward(
     const float* __restrict__ P, const float* __restrict__ X, int B,
     float* __restrict__ Z1, float* __restrict__ H1, float* __restrict__ Z2,
     float* __restrict__ H2, float* __restrict__ out) {
   __shared__ __align__(16) unsigned short S[2][kFRows][kFLd];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blockIdx.x * kFRows;
-  for (int e = tid; e < kFRows * kNFeat; e += 256) {
+  for (int e = tid; e < kFRows * kNFeat; e += kFWaves * 64) {
     const int r = e / kNFeat, k = e - r * kNFeat, m = row0 + r;
     S[0][r][k] = bf16_bits(m < B ? X[(int64_t)m * kNFeat + k] : 0.f);
   }
@@ -727,7 +730,7 @@ hipError_t launch_mlp_forward(const float* P, const float* X, int B,
                               float* out, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_forward, dim3((B + kFRows - 1) / kFRows),
-                     dim3(256), 0, st, P, X, B, Z1, H1, Z2, H2, out);
+                     dim3(kFWaves * 64), 0, st, P, X, B, Z1, H1, Z2, H2, out);
   return hipGetLastError();
 }
 
