@@ -85,15 +85,19 @@ def born_radii(x, rho, S):
     return R
 
 
-def energy_terms(x, p):
+def energy_terms(x, p, magnitudes=False):
     """(E_LJ, E_Coulomb, E_GB, E_SA) of one configuration x (n, 3); p is a
     dict with charge, sigma, eps, rho, S (n each), excluded and one_four
-    (n x n), lj14, el14, eps_solute, eps_solvent, gamma, probe."""
+    (n x n), lj14, el14, eps_solute, eps_solvent, gamma, probe.  With
+    magnitudes, also the sums of the absolute values of each energy's
+    contributions (pair terms, GB pair terms, per-atom SA terms): the scale
+    against which the rounding of a float32 evaluation is judged."""
     x = np.asarray(x, np.float64)
     n = len(x)
     q, sg, ep = p["charge"], p["sigma"], p["eps"]
     ex, o4 = p["excluded"], p["one_four"]
     e_lj = e_c = 0.0
+    m_lj = m_c = m_gb = 0.0
     for i in range(n):
         for j in range(i + 1, n):
             if ex[i, j]:
@@ -109,6 +113,8 @@ def energy_terms(x, p):
                 cl *= p["el14"]
             e_lj += lj
             e_c += cl
+            m_lj += abs(lj)
+            m_c += abs(cl)
     R = born_radii(x, p["rho"], p["S"])
     tau = 1.0 / p["eps_solute"] - 1.0 / p["eps_solvent"]
     e_gb = 0.0
@@ -121,12 +127,17 @@ def energy_terms(x, p):
                 RR = R[i] * R[j]
                 f = math.sqrt(r2 + RR * math.exp(-r2 / (4.0 * RR)))
             e_gb += q[i] * q[j] / f
+            m_gb += abs(q[i] * q[j] / f)
     e_gb *= -0.5 * K_COULOMB * tau
+    m_gb *= 0.5 * K_COULOMB * abs(tau)
     e_sa = 0.0
     for i in range(n):
         e_sa += (4.0 * math.pi * p["gamma"] * (p["rho"][i] + p["probe"]) ** 2 *
                  (p["rho"][i] / R[i]) ** 6)
-    return np.array([e_lj, e_c, e_gb, e_sa])
+    e = np.array([e_lj, e_c, e_gb, e_sa])
+    if magnitudes:
+        return e, np.array([m_lj, m_c, m_gb, e_sa])
+    return e
 
 
 def forces(x, p, h=1e-5):

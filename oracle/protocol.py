@@ -106,6 +106,37 @@ def state_of(a, kind, C, T_H, T_T):
     return T, np.array([g, g, g, sg, sg])
 
 
+def soft_caps(s_rep, q, cap_energy=10.0):
+    """Caps (v_max,rep, v_max,ele) of the soft grids (Thermodynamic Cycle,
+    soft grids between milestones C and D).
+
+    The paper caps the soft repulsive grid at 10 in its own grid units and
+    sets the electrostatic cap so that no atom's soft electrostatic energy
+    exceeds its soft repulsive energy: the repulsive cap times the smallest
+    ratio of repulsive to electrostatic scaling factor over the atoms.
+    Reading for grids in this build's units (repulsive factor times grid
+    value is an energy): the repulsive cap makes the soft repulsion of the
+    median atom (median over the listed atoms' repulsive factors) equal to
+    cap_energy kJ/mol; atoms without charge do not bound the electrostatic
+    cap (and with no charged atom it equals the repulsive one)."""
+    s_rep = np.asarray(s_rep, np.float64)
+    q = np.abs(np.asarray(q, np.float64))
+    v_rep = cap_energy / float(np.median(s_rep))
+    charged = q > 0.0
+    if not charged.any():
+        return v_rep, v_rep
+    return v_rep, v_rep * float(np.min(s_rep[charged] / q[charged]))
+
+
+def soft_grid(values, v_max):
+    """Soft grid value v_max tanh(v / v_max) of original grid values v
+    (Thermodynamic Cycle: the hyperbolic-tangent cap of the soft repulsive
+    and electrostatic grids), in double.  A repulsive grid stored as a
+    quartic root is raised to the fourth power first by the caller: the cap
+    acts on the grid's value, not on its stored root."""
+    return v_max * np.tanh(np.asarray(values, np.float64) / v_max)
+
+
 def channel_groups(kind, C):
     """Boolean masks (original grids, soft grids) over the C channels."""
     g = np.ones(C, bool)

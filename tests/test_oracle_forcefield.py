@@ -166,3 +166,43 @@ def test_restraint_closed_form_and_force_split(oracle_lib):
             assert np.allclose(Ftot, -100.0 * (d - 1.0) * com / d, atol=1e-10)
         else:
             assert np.all(F == 0)
+
+
+def test_angle_energy_closed_form(oracle_lib):
+    """Harmonic angle term K_theta (theta - theta0)^2 on a 3-atom ligand
+    with one angle and nothing else: the energy at a placed angle theta and
+    the force on the end atoms from the planar geometry.  With i on the x
+    axis at distance r1 from the vertex j and k at distance r2 in direction
+    (cos theta, sin theta, 0), increasing theta moves k along (-sin theta,
+    cos theta, 0) / r2 per radian and i along (0, -1, 0) / r1, so
+    F_k = -dE/dtheta (-sin theta, cos theta, 0) / r2,
+    F_i = -dE/dtheta (0, -1, 0) / r1 and F_j = -(F_i + F_k),
+    with dE/dtheta = 2 K (theta - theta0).  theta0 is in radians: a
+    degree/radian slip or a factor 1/2 in the energy fails here."""
+    K, th0 = 250.0, 1.9
+    x = np.zeros((3, 3))
+    lig = synth.toy_ligand(x, np.zeros((0, 2)), 0.0, [300.0], [0.0],
+                           d0=100.0)
+    lig.scale = np.zeros((3, 3))
+    lig.angles = np.array([[0, 1, 2]], np.int32)
+    lig.angle_par = np.array([[K, th0]])
+    ol = oracle.OLigand(lig)
+    og = oracle.OGrid(_zero_grid())
+    r1, r2 = 1.3, 0.7
+    for th in (0.6, 1.5, 1.9, 2.4, 3.0):
+        xx = np.array([[r1, 0.0, 0.0], [0.0, 0.0, 0.0],
+                       [r2 * math.cos(th), r2 * math.sin(th), 0.0]])
+        t, _, F = oracle.energy(og, ol, np.zeros(3), xx)
+        E = K * (th - th0) ** 2
+        assert abs(t[1] - E) <= 1e-12 * max(E, 1.0), (th, t[1], E)
+        assert abs(t[0]) == 0.0 and abs(t[2]) == 0.0
+        dE = 2.0 * K * (th - th0)
+        Fk = -dE * np.array([-math.sin(th), math.cos(th), 0.0]) / r2
+        Fi = -dE * np.array([0.0, -1.0, 0.0]) / r1
+        ref = np.stack([Fi, -(Fi + Fk), Fk])
+        assert np.allclose(F, ref, atol=1e-10 * max(abs(dE), 1.0)), (th, F,
+                                                                    ref)
+    # the bent-at-right-angle case written out: theta = pi/2, theta0 = 1.9
+    xx = np.array([[r1, 0, 0], [0, 0, 0], [0, r2, 0]], np.float64)
+    t, _, _ = oracle.energy(og, ol, np.zeros(3), xx, forces=False)
+    assert abs(t[1] - 250.0 * (math.pi / 2 - 1.9) ** 2) < 1e-12
