@@ -26,11 +26,21 @@ def _gpu():
     require_gpu()
 
 
-@pytest.mark.parametrize("sigma,n_moves", [(0.6, 4), (0.25, 8)])
-def test_external_moves_match_oracle(sigma, n_moves):
-    print_case("external moves", sigma, n_moves)
+@pytest.mark.parametrize("which,sigma,n_moves", [
+    ("c1", 0.6, 4), ("c1", 0.25, 8), ("wide90", 0.6, 4),
+    ("wide100", 0.3, 6)])
+def test_external_moves_match_oracle(which, sigma, n_moves):
+    """The 24-atom ligand (one wavefront) and ligands of 90 and 100 atoms
+    (two wavefronts: the move's two-wavefront centre of mass and
+    evaluation)."""
+    print_case("external moves", which, sigma, n_moves)
     system = synth.make_system(1)
-    lig, g = system.ligands[0], system.grid
+    g = system.grid
+    if which == "c1":
+        lig = system.ligands[0]
+    else:
+        n = int(which[4:])
+        lig = synth.make_ligand(np.random.default_rng(n + 1), n, 8, box=9.0)
     og, ol = oracle.OGrid(g), oracle.OLigand(lig)
     ctx, (lid,) = make_context(g, [lig], seed=system.seed)
     K = lig.n_states

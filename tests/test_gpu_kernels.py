@@ -13,8 +13,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import dev, make_context, near_face, print_case, require_gpu, \
-    torch
+from gpu_util import dev, grid_grad_magnitude, make_context, near_face, \
+    print_case, require_gpu, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +29,26 @@ def _grid_case(rng, shape=(20, 18, 16), C=3):
     g = synth.random_grid(rng, n=shape, spacing=0.5, origin=(-4.5, -4.0, -3.5),
                           n_channels=C, transform=tr)
     return g
+
+
+def _check_forces_by_group(F, F64, ok, mag, group=24):
+    """The force tolerance |F32 - F64| <= 1e-4 RMS(F64) per configuration,
+    with independent points taken as configurations of `group` consecutive
+    points (the 24-atom ligand's size), plus 1e-5 of the gradient's
+    magnitude sum `mag` (grid_grad_magnitude: deep in the capped region a
+    float32 gradient is a difference of large, nearly equal corner values;
+    the rounding there is about 2e-6 of that sum); points within float32
+    rounding of a cell face are exempt and do not enter the RMS."""
+    n = len(F) // group * group
+    d = np.abs(F - F64)[:n].reshape(-1, group, 3)
+    f2 = np.where(ok[:n, None], F64[:n] ** 2, 0.0).reshape(-1, group, 3)
+    cnt = np.maximum(ok[:n].reshape(-1, group).sum(axis=1), 1)
+    rms = np.sqrt(f2.sum(axis=(1, 2)) / (3 * cnt))
+    allow = 1e-4 * rms[:, None, None] + 1e-5 * mag[:n].reshape(-1, group, 3)
+    bad = (d > allow) & ok[:n].reshape(-1, group)[..., None]
+    worst = np.max(np.where(ok[:n].reshape(-1, group)[..., None],
+                            d / allow, 0))
+    assert not bad.any(), (int(bad.sum()), float(worst))
 
 
 @pytest.mark.parametrize("C", [3, 5])
@@ -59,8 +79,8 @@ def test_grid_eval_random_grid(C):
     mag = np.abs(scale) * np.where(np.array(g.transform) == 4, gmax ** 4, gmax)
     assert np.all(np.abs(e - e64) <= 1e-5 * mag + 1e-30)
     ok = ~near_face(pos, g)
+    _check_forces_by_group(F, F64, ok, grid_grad_magnitude(g, pos, scale, w))
     fscale = np.sqrt(np.mean(F64[ok] ** 2))
-    assert np.max(np.abs(F - F64)[ok]) <= 1e-4 * fscale * 10
     # per-point relative check where the force is not tiny
     big = ok & (np.linalg.norm(F64, axis=1) > 0.1 * fscale)
     rel = np.linalg.norm(F - F64, axis=1)[big] / np.linalg.norm(F64, axis=1)[big]
@@ -90,10 +110,7 @@ def test_grid_eval_config1_grid_at_ligand_positions():
     S = np.abs(e64).sum(axis=1)
     assert np.all(np.abs(e - e64).sum(axis=1) <= 1e-5 * S + 1e-12)
     ok = ~near_face(pos, g)
-    nrm = np.linalg.norm(F64, axis=1)
-    big = ok & (nrm > 1e-3)
-    rel = np.linalg.norm(F - F64, axis=1)[big] / nrm[big]
-    assert np.percentile(rel, 99.9) < 1e-4 and np.max(rel) < 1e-3
+    _check_forces_by_group(F, F64, ok, grid_grad_magnitude(g, pos, sc, w))
     ctx.close()
 
 

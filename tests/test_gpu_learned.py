@@ -61,10 +61,20 @@ def cosine(a, b):
     return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
 
 
-def _setup(seed=0, K=8):
-    rng = np.random.default_rng(seed)
+def _ligand(which):
+    """The 24-atom config-1 system, or a ligand of 90 or 100 atoms (two
+    wavefronts of atoms, as the large batched workload's) on its grid."""
     system = synth.make_system(1)
-    lig = system.ligands[0]
+    if which == "c1":
+        return system, system.ligands[0]
+    n = int(which[4:])
+    lig = synth.make_ligand(np.random.default_rng(n), n, 8, box=9.0)
+    return system, lig
+
+
+def _setup(seed=0, which="c1"):
+    rng = np.random.default_rng(seed)
+    system, lig = _ligand(which)
     p = Lr.init_weights(rng)
     for k in p:
         p[k] = p[k] + 0.05 * rng.normal(size=p[k].shape)
@@ -110,9 +120,11 @@ def test_gradients_match_oracle():
     ctx.close()
 
 
-def test_pose_features_match_oracle():
-    print_case("pose features")
-    rng, system, lig, p, ctx, lid, cond = _setup(3)
+@pytest.mark.parametrize("which", ["c1", "wide90", "wide100"])
+def test_pose_features_match_oracle(which):
+    print_case("pose features", which)
+    rng, system, lig, p, ctx, lid, cond = _setup(3, which)
+    assert len(cond) == 8 or which == "c1"
     from scipy.spatial.transform import Rotation
     N = 200
     xs = []
@@ -135,19 +147,20 @@ def test_pose_features_match_oracle():
     ctx.close()
 
 
-def test_pose_move_matches_oracle():
-    print_case("pose move")
-    rng, system, lig, p, ctx, lid, cond = _setup(4)
-    og, ol = oracle.OGrid(system.grid), oracle.OLigand(lig)
-    seed = system.seed
+def _check_pose_moves(ctx, og, lig, lid, seed, rounds, sweeps=2):
+    """`rounds` times: a few sweeps of every ligand, then one pose move of
+    every ligand with a proposal (ligand -1), checked replica by replica on
+    `lig` against the oracle's move given the GPU's network outputs.
+    Returns the number of replicas whose decision was compared."""
+    ol = oracle.OLigand(lig)
     checked = 0
-    for rnd in range(4):
-        ctx.hmc_sweep(2, 10, exchange_every=1)
+    for rnd in range(rounds):
+        ctx.hmc_sweep(sweeps, 10, exchange_every=1)
         st = ctx.get_replicas(lid)
         x = st["x"]
         f, _ = ctx.pose_features(lid, dev(x, torch.float32))
         out = ctx.proposal_forward(lid, f).cpu().numpy()
-        ctx.pose_move(lid, 1)
+        ctx.pose_move(-1, 1)
         st2 = ctx.get_replicas(lid)
         la = ctx.get_pose_stats(lid)["last_ln_alpha"]
         mp = Lr.mixture(out)
@@ -170,15 +183,82 @@ def test_pose_move_matches_oracle():
             # float32 energies (|dE| <= 1e-5 of the magnitude sum, a few
             # 1e-3 kT here) and float32 rotations enter ln alpha
             assert abs(la[r] - ln_a) < 2e-2 + 1e-4 * abs(ln_a), \
-                (r, la[r], ln_a)
+                (lid, r, la[r], ln_a)
             if abs(math.log(ua) - ln_a) > 5e-2:
                 moved = not np.array_equal(st2["x"][r], x[r])
-                assert moved == acc, (rnd, r)
+                assert moved == acc, (lid, rnd, r)
                 if acc:
                     assert np.max(np.abs(st2["x"][r] - xn)) < 1e-4
                 checked += 1
+    return checked
+
+
+@pytest.mark.parametrize("which", ["c1", "wide90", "wide100"])
+def test_pose_move_matches_oracle(which):
+    """One wavefront of atoms (24) and two (90, 100: the pose move's
+    two-wavefront centre of mass and evaluation)."""
+    print_case("pose move", which)
+    rng, system, lig, p, ctx, lid, cond = _setup(4, which)
+    og = oracle.OGrid(system.grid)
+    checked = _check_pose_moves(ctx, og, lig, lid, system.seed, 4)
     assert checked >= 16
     ctx.close()
+
+
+def test_pose_moves_of_several_ligands_in_one_call():
+    """Three ligands of 24, 57 and 96 atoms, each with its own proposal, in
+    one context: every pose move call moves all three, each checked against
+    the oracle, and sweep calls with pose_move_every = 5 (graph and plain
+    launches) equal the host loop of five-sweep calls and pose moves bit
+    for bit."""
+    print_case("pose moves, three ligands")
+    system = synth.make_system(1)
+    rng = np.random.default_rng(9)
+    ligs = [system.ligands[0], synth.make_ligand(rng, 57, 8, box=8.0),
+            synth.make_ligand(rng, 96, 8, box=9.0)]
+    params = []
+    for q, lig in enumerate(ligs):
+        p = Lr.init_weights(np.random.default_rng(30 + q))
+        for k in p:
+            p[k] = p[k] + 0.05 * rng.normal(size=p[k].shape)
+        params.append(flat(p))
+    ctx, ids = make_context(system.grid, ligs, seed=system.seed)
+    for lid, lig, p in zip(ids, ligs, params):
+        ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors], p)
+    og = oracle.OGrid(system.grid)
+    for lid, lig in zip(ids, ligs):
+        checked = _check_pose_moves(ctx, og, lig, lid, system.seed, 2,
+                                    sweeps=1)
+        assert checked >= 6, (lid, checked)
+    ctx.close()
+    runs = []
+    for mode in ("host", "graph", "plain"):
+        ctx, ids = make_context(system.grid, ligs, seed=13, capacity=10)
+        for lid, lig, p in zip(ids, ligs, params):
+            ctx.proposal_setup(lid, lig.frame_atoms,
+                               lig.tors[lig.cond_tors], p)
+        if mode == "plain":
+            ctx.set_graph(0)
+        if mode == "host":
+            for _ in range(4):
+                ctx.hmc_sweep(5, 10, exchange_every=1, sample_every=3)
+                ctx.pose_move(-1, 1)
+            ctx.hmc_sweep(3, 10, exchange_every=1, sample_every=3)
+        else:
+            ctx.hmc_sweep(23, 10, exchange_every=1, sample_every=3,
+                          pose_move_every=5)
+        runs.append([(ctx.get_replicas(i), ctx.get_samples(i),
+                      ctx.get_pose_stats(i)) for i in ids])
+        ctx.close()
+    for per in runs[1:]:
+        for (st, (xs, cs), ps), (st0, (xs0, cs0), ps0), lig in zip(
+                per, runs[0], ligs):
+            assert ps0["tries"].sum() == 4 * lig.n_states
+            for key in ("x", "state_of_replica", "comps", "counter"):
+                assert np.array_equal(st[key], st0[key]), key
+            assert np.array_equal(xs, xs0) and np.array_equal(cs, cs0)
+            assert np.array_equal(ps["acc"], ps0["acc"])
+            assert np.array_equal(ps["tries"], ps0["tries"])
 
 
 def test_training_on_sampled_poses_improves_the_proposal():
