@@ -273,6 +273,29 @@ BPMF_API int bpmf_energy_matrix_batch(bpmf_ctx* ctx, int n,
                                       double* const* dev_ukn,
                                       const int64_t* ld);
 
+/* bpmf_energy_matrix_batch for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same validation, kernels and results (bit for bit), but
+ * the call allocates nothing -- no device, pinned or staging memory, no
+ * events.  Its job table (one entry per listed ligand with samples, plus
+ * one per wavefront class) lives in a fixed device array of
+ * BPMF_NOALLOC_MAX_JOBS + 4 entries (about 49 KB) that each device running
+ * the library holds until the process ends; it is written by small kernels
+ * on the context's stream, then read by the u_kn launches.  Every call on a
+ * device shares that array: calls that overlap on one device (different
+ * streams or contexts, not ordered by the caller) race and may compute
+ * wrong results; calls ordered on one stream do not.  Its launches are not
+ * covered by bpmf_set_timing.  Errors: as bpmf_energy_matrix_batch, plus
+ * BPMF_E_INVAL when n exceeds BPMF_NOALLOC_MAX_JOBS and BPMF_E_UNIMPL when
+ * the device index is 64 or more (no table address kept for it). */
+#define BPMF_NOALLOC_MAX_JOBS 1024
+BPMF_API int bpmf_energy_matrix_batch_noalloc(bpmf_ctx* ctx, int n,
+                                              const int* ligand_ids,
+                                              const float* const* dev_samples,
+                                              const int64_t* n_samples,
+                                              double* const* dev_ukn,
+                                              const int64_t* ld);
+
 /* MBAR (Shirts & Chodera 2008, which the paper uses for f_BC,L and f_CD'):
  * solves f_i = -ln sum_n exp(-u_in) / sum_k N_k exp(f_k - u_kn) with f_0 = 0
  * by Newton iterations on the convex MBAR objective, in double on the

@@ -136,6 +136,9 @@ def library():
         "bpmf_energy_matrix": [vp, C.c_int, vp, C.c_int64, vp, C.c_int64],
         "bpmf_energy_matrix_batch": [vp, C.c_int, ip, C.POINTER(C.c_void_p),
                                      i64p, C.POINTER(C.c_void_p), i64p],
+        "bpmf_energy_matrix_batch_noalloc": [
+            vp, C.c_int, ip, C.POINTER(C.c_void_p), i64p,
+            C.POINTER(C.c_void_p), i64p],
         "bpmf_mbar": [vp, vp, C.c_int, C.c_int64, C.c_int64, i64p, C.c_double,
                       C.c_int, dp, dp, ip, C.c_int],
         "bpmf_mbar_batch": [vp, C.c_int, C.POINTER(C.c_void_p), ip, i64p, i64p,
@@ -454,12 +457,15 @@ class Context:
         return out
 
     def energy_matrix_batch(self, ligand_ids, samples=None, n_samples=None,
-                            outs=None):
+                            outs=None, noalloc=False):
         """u_kn of several ligands in one call.  samples: None (recorded
         samples of every ligand, n_samples[i] each, or all of them when
         n_samples or its entry is None) or a list of device
         tensors (N_i, n_i, 3) float32 / None; outs: optional list of K_i x
-        N_i float64 tensors.  Returns the list of u_kn tensors."""
+        N_i float64 tensors.  noalloc: call the entry point that allocates
+        nothing (bpmf_energy_matrix_batch_noalloc; give `outs` so that the
+        binding allocates nothing either).  Returns the list of u_kn
+        tensors."""
         torch = self._torch
         m = len(ligand_ids)
         ids = np.ascontiguousarray(ligand_ids, np.int32)
@@ -488,7 +494,9 @@ class Context:
             uptrs[i] = u.data_ptr()
             lds[i] = u.stride(0)
             res.append(u)
-        _check(self._lib.bpmf_energy_matrix_batch(
+        fn = (self._lib.bpmf_energy_matrix_batch_noalloc if noalloc else
+              self._lib.bpmf_energy_matrix_batch)
+        _check(fn(
             self._h, m, _pi(ids), ptrs,
             ns.ctypes.data_as(C.POINTER(C.c_int64)), uptrs,
             lds.ctypes.data_as(C.POINTER(C.c_int64))))

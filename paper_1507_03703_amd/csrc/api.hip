@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -121,6 +122,8 @@ struct bpmf_ctx {
   size_t mlp_bytes = 0;
   void* place_mem = nullptr;  // centres of mass of placed configurations
   size_t place_bytes = 0;
+  // this device's address of the no-allocation job table (or null)
+  void* scratch_addr = nullptr;
   // kernel timing
   static constexpr int kTimers = 4;
   static constexpr size_t kMaxPairs = 8192;
@@ -318,6 +321,10 @@ int ensure_scratch(bpmf_ctx* c, void** mem, size_t* have, size_t need) {
 // ============================================================================
 // lifecycle
 // ============================================================================
+namespace {
+int scratch_address(int device, void** out);
+}  // namespace
+
 extern "C" int bpmf_version(void) { return 100; }
 
 extern "C" const char* bpmf_last_error(void) { return g_err.c_str(); }
@@ -347,6 +354,11 @@ extern "C" int bpmf_create(bpmf_ctx** out, int device, uint64_t seed,
   c->alloc = alloc;
   c->free_fn = free_fn;
   c->user = alloc_user;
+  const int src = scratch_address(device, &c->scratch_addr);
+  if (src) {
+    delete c;
+    return src;
+  }
   *out = c;
   return BPMF_OK;
 }
@@ -1027,14 +1039,27 @@ extern "C" int bpmf_exchange(bpmf_ctx* c, int ligand_id, int scheme,
 // u_kn of several ligands: one persistent launch per wavefront class, the
 // job table staged through pinned memory (the previous upload must have
 // left it before it is rewritten)
-extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
-                                        const int* ligand_ids,
-                                        const float* const* dev_samples,
-                                        const int64_t* n_samples,
-                                        double* const* dev_ukn,
-                                        const int64_t* ld) {
+namespace {
+// launch plan of an energy-matrix batch: jobs grouped by wavefront class,
+// each group followed by a sentinel
+struct UknPlan {
+  int group = 16;  // samples whose columns are staged before being written
+  int n_jobs = 0;  // table entries, sentinels included (0: nothing to do)
+  int64_t total[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
+  int off[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
+  int cnt[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
+  int lds[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
+};
+
+// Validates an energy-matrix batch and writes its job table into `jobs`
+// (room for n + kWaveClasses entries); allocates nothing.
+int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
+             const float* const* dev_samples, const int64_t* n_samples,
+             double* const* dev_ukn, const int64_t* ld, UknJob* jobs,
+             UknPlan* p) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  *p = UknPlan{};
   if (n < 0) return fail(BPMF_E_INVAL, "negative batch size");
   if (n == 0) return BPMF_OK;
   if (!ligand_ids || !n_samples || !dev_ukn || !ld)
@@ -1080,15 +1105,10 @@ extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
                   "states' weights and columns; max 65536)",
                   i, need, h.dev.K);
   }
-  // jobs grouped by wavefront class, each group followed by a sentinel
-  std::vector<UknJob> jobs;
-  int64_t group_total[bpmf_ctx::kWaveClasses] = {0};
-  int group_off[bpmf_ctx::kWaveClasses] = {0};
-  int group_n[bpmf_ctx::kWaveClasses] = {0};
-  int group_lds[bpmf_ctx::kWaveClasses] = {0};
+  int nj = 0;
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
     const int W = 1 << q;
-    group_off[q] = (int)jobs.size();
+    p->off[q] = nj;
     int64_t first = 0;
     for (int i = 0; i < n; ++i) {
       const LigHost& h = c->ligs[ligand_ids[i]];
@@ -1102,45 +1122,126 @@ extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
       J.ld = ld[i];
       J.first = first;
       first += J.n;
-      jobs.push_back(J);
-      group_lds[q] = std::max(group_lds[q], ukn_lds(h, W));
+      jobs[nj++] = J;
+      p->lds[q] = std::max(p->lds[q], ukn_lds(h, W));
     }
-    group_n[q] = (int)jobs.size() - group_off[q];
-    group_total[q] = first;
+    p->cnt[q] = nj - p->off[q];
+    p->total[q] = first;
     UknJob end{};
     end.first = first;
-    jobs.push_back(end);
+    jobs[nj++] = end;
   }
-  rc = ensure_scratch(c, &c->comps_mem, &c->comps_bytes,
-                      jobs.size() * sizeof(UknJob));
-  if (rc) return rc;
-  if (!c->jobs_copied) HIP_TRY(hipEventCreate(&c->jobs_copied));
-  HIP_TRY(hipEventSynchronize(c->jobs_copied));
-  if (c->jobs_host_n < jobs.size()) {
-    if (c->jobs_host) HIP_TRY(hipHostFree(c->jobs_host));
-    c->jobs_host = nullptr;
-    c->jobs_host_n = 0;
-    HIP_TRY(hipHostMalloc((void**)&c->jobs_host,
-                          jobs.size() * sizeof(UknJob)));
-    c->jobs_host_n = jobs.size();
-  }
-  memcpy(c->jobs_host, jobs.data(), jobs.size() * sizeof(UknJob));
-  UknJob* d_jobs = (UknJob*)c->comps_mem;
-  HIP_TRY(hipMemcpyAsync(d_jobs, c->jobs_host, jobs.size() * sizeof(UknJob),
-                         hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipEventRecord(c->jobs_copied, c->stream));
+  p->group = group;
+  p->n_jobs = nj;
+  return BPMF_OK;
+}
+
+// the launches of a planned batch, the job table at d_jobs on the device
+int ukn_launch(bpmf_ctx* c, const UknPlan& p, const UknJob* d_jobs,
+               bool timed_ok) {
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
-    if (group_total[q] == 0) continue;
+    if (p.total[q] == 0) continue;
     hipEvent_t t0, t1;
-    const bool timed = c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
+    const bool timed =
+        timed_ok && c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
     if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
     HIP_TRY(launch_energy_matrix(c->grid, c->d_ligs, 1 << q,
-                                 d_jobs + group_off[q], group_n[q],
-                                 group_total[q], group, group_lds[q],
-                                 c->n_cu, c->stream));
+                                 d_jobs + p.off[q], p.cnt[q], p.total[q],
+                                 p.group, p.lds[q], c->n_cu, c->stream));
     if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   }
   return BPMF_OK;
+}
+}  // namespace
+
+extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
+                                        const int* ligand_ids,
+                                        const float* const* dev_samples,
+                                        const int64_t* n_samples,
+                                        double* const* dev_ukn,
+                                        const int64_t* ld) {
+  std::vector<UknJob> jobs((size_t)std::max(n, 0) + bpmf_ctx::kWaveClasses);
+  UknPlan p;
+  int rc = ukn_plan(c, n, ligand_ids, dev_samples, n_samples, dev_ukn, ld,
+                    jobs.data(), &p);
+  if (rc || p.n_jobs == 0) return rc;
+  rc = ensure_scratch(c, &c->comps_mem, &c->comps_bytes,
+                      p.n_jobs * sizeof(UknJob));
+  if (rc) return rc;
+  if (!c->jobs_copied) HIP_TRY(hipEventCreate(&c->jobs_copied));
+  HIP_TRY(hipEventSynchronize(c->jobs_copied));
+  if (c->jobs_host_n < (size_t)p.n_jobs) {
+    if (c->jobs_host) HIP_TRY(hipHostFree(c->jobs_host));
+    c->jobs_host = nullptr;
+    c->jobs_host_n = 0;
+    HIP_TRY(hipHostMalloc((void**)&c->jobs_host, p.n_jobs * sizeof(UknJob)));
+    c->jobs_host_n = p.n_jobs;
+  }
+  memcpy(c->jobs_host, jobs.data(), p.n_jobs * sizeof(UknJob));
+  UknJob* d_jobs = (UknJob*)c->comps_mem;
+  HIP_TRY(hipMemcpyAsync(d_jobs, c->jobs_host, p.n_jobs * sizeof(UknJob),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->jobs_copied, c->stream));
+  return ukn_launch(c, p, d_jobs, true);
+}
+
+// ----------------------------------------------------------------------------
+// energy matrix without allocation: the job table lives in `scratch`, a
+// file-scope device array of BPMF_NOALLOC_MAX_JOBS entries plus the
+// sentinels; every device that runs the library holds its own copy until the
+// process ends.  Host code never uses the array's name as an address: its
+// per-device address comes from hipGetSymbolAddress at context creation.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) UknJob
+    scratch[BPMF_NOALLOC_MAX_JOBS + bpmf_ctx::kWaveClasses];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// address of `scratch` on `device` (the current device), looked up once per
+// device; null where the lookup failed or the device index is too large
+int scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return BPMF_OK;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(BPMF_E_HIP, "address of the no-allocation job table: %s",
+                  hipGetErrorString(e));
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return BPMF_OK;
+}
+}  // namespace
+
+extern "C" int bpmf_energy_matrix_batch_noalloc(
+    bpmf_ctx* c, int n, const int* ligand_ids,
+    const float* const* dev_samples, const int64_t* n_samples,
+    double* const* dev_ukn, const int64_t* ld) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (n > BPMF_NOALLOC_MAX_JOBS)
+    return fail(BPMF_E_INVAL,
+                "no-allocation energy matrix: %d entries exceed the limit %d",
+                n, BPMF_NOALLOC_MAX_JOBS);
+  if (!c->scratch_addr)
+    return fail(BPMF_E_UNIMPL,
+                "no-allocation energy matrix: no job table on device %d",
+                c->device);
+  UknJob jobs[BPMF_NOALLOC_MAX_JOBS + bpmf_ctx::kWaveClasses];
+  UknPlan p;
+  if ((rc = ukn_plan(c, n, ligand_ids, dev_samples, n_samples, dev_ukn, ld,
+                     jobs, &p)) ||
+      p.n_jobs == 0)
+    return rc;
+  UknJob* d_jobs = (UknJob*)c->scratch_addr;
+  HIP_TRY(launch_put_jobs(d_jobs, jobs, p.n_jobs, c->stream));
+  return ukn_launch(c, p, d_jobs, false);
 }
 
 extern "C" int bpmf_energy_matrix(bpmf_ctx* c, int ligand_id,

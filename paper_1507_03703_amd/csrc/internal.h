@@ -152,6 +152,10 @@ hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
                                 int waves, const UknJob* d_jobs, int n_jobs,
                                 int64_t total, int group, int lds_bytes,
                                 int n_cu, hipStream_t st);
+// copy n jobs from host memory into the device table dst by kernels that
+// take the jobs as arguments (no host staging buffer, no copy engine)
+hipError_t launch_put_jobs(UknJob* dst, const UknJob* jobs, int n,
+                           hipStream_t st);
 hipError_t launch_evaluate(const GridDev& g, const LigDev* d_lig,
                            int waves, const float* xs, int64_t N,
                            const double* w, double* terms, float* forces,

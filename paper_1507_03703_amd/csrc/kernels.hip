@@ -1114,6 +1114,32 @@ hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
   return hipGetLastError();
 }
 
+namespace {
+constexpr int kJobChunk = 32;
+struct JobChunk {
+  UknJob j[kJobChunk];
+  int n;
+};
+__global__ __launch_bounds__(kJobChunk) void k_put_jobs(UknJob* dst,
+                                                        JobChunk ch) {
+  if ((int)threadIdx.x < ch.n) dst[threadIdx.x] = ch.j[threadIdx.x];
+}
+}  // namespace
+
+hipError_t launch_put_jobs(UknJob* dst, const UknJob* jobs, int n,
+                           hipStream_t st) {
+  for (int first = 0; first < n; first += kJobChunk) {
+    JobChunk ch;
+    ch.n = n - first < kJobChunk ? n - first : kJobChunk;
+    for (int i = 0; i < ch.n; ++i) ch.j[i] = jobs[first + i];
+    hipLaunchKernelGGL(k_put_jobs, dim3(1), dim3(kJobChunk), 0, st,
+                       dst + first, ch);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
                                 int waves, const UknJob* d_jobs, int n_jobs,
                                 int64_t total, int group, int lds_bytes,
