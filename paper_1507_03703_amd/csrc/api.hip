@@ -80,6 +80,9 @@ struct LigHost {
   float* adam_v = nullptr;
   int64_t adam_t = 0;
   PropDev prop{};
+  // place in the batched pose-move tables (build_pose_tables): first task
+  // (= first row), first forward group and their count
+  int ptask0 = -1, pgroup0 = 0, n_pgroups = 0;
   // intramolecular nonbonded / implicit-solvent terms (bpmf_pair_setup)
   bool has_pairs = false;
   void* pair_arena = nullptr;
@@ -124,6 +127,18 @@ struct bpmf_ctx {
   size_t place_bytes = 0;
   // this device's address of the no-allocation job table (or null)
   void* scratch_addr = nullptr;
+  // batched pose moves over every ligand with a proposal: per-ligand
+  // proposal entries (zero without a proposal), tasks ordered by wavefront
+  // class, then ligand, then replica (a task's row is its index), and the
+  // forward pass's groups of up to 16 rows of one ligand
+  bool pose_dirty = true;
+  PropDev* d_props = nullptr;
+  PoseTask* d_ptasks = nullptr;
+  MlpGroup* d_pgroups = nullptr;
+  int n_ptasks = 0, n_pgroups = 0;
+  int ptask_off[kWaveClasses] = {0, 0, 0, 0};
+  int ptask_n[kWaveClasses] = {0, 0, 0, 0};
+  int ptask_lds[kWaveClasses] = {0, 0, 0, 0};
   // kernel timing
   static constexpr int kTimers = 4;
   static constexpr size_t kMaxPairs = 8192;
@@ -290,6 +305,7 @@ int rebuild_tables(bpmf_ctx* c) {
   c->dfree(c->d_tasks);
   c->d_ligs = (LigDev*)nd;
   c->d_tasks = (int2*)nt;
+  c->pose_dirty = true;
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
     c->class_off[q] = off[q];
     c->class_n[q] = (int)cls[q].size();
@@ -306,6 +322,8 @@ int rebuild_tables(bpmf_ctx* c) {
 int ensure_scratch(bpmf_ctx* c, void** mem, size_t* have, size_t need) {
   if (*have >= need) return BPMF_OK;
   HIP_TRY(hipStreamSynchronize(c->stream));
+  // a captured graph may address the old buffer: capture again
+  c->drop_graph();
   c->dfree(*mem);
   *mem = c->dalloc(need);
   if (!*mem) {
@@ -377,6 +395,9 @@ extern "C" int bpmf_destroy(bpmf_ctx* c) {
   c->dfree(c->grid_mem);
   c->dfree(c->d_ligs);
   c->dfree(c->d_tasks);
+  c->dfree(c->d_props);
+  c->dfree(c->d_ptasks);
+  c->dfree(c->d_pgroups);
   c->dfree(c->comps_mem);
   if (c->jobs_host) (void)hipHostFree(c->jobs_host);
   if (c->jobs_copied) (void)hipEventDestroy(c->jobs_copied);
@@ -770,7 +791,8 @@ struct MlpBufs {
   double* loss_part;
 };
 int mlp_scratch(bpmf_ctx* c, int B, MlpBufs* b);
-int pose_move_ligand(bpmf_ctx* c, int lid, hipStream_t st);
+int build_pose_tables(bpmf_ctx* c);
+int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st);
 int external_move_ligand(bpmf_ctx* c, int lid, int n_moves, int k_max,
                          double sigma, hipStream_t st);
 int check_external(int n_moves, int k_max, double sigma);
@@ -872,12 +894,10 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
   // one pose move of every ligand that has a proposal (when asked), then
   // the external moves of every ligand
   auto enqueue_pose = [&](hipStream_t st) -> int {
-    if (a->pose_move_every > 0)
-      for (int l = l0; l < l1; ++l)
-        if (c->ligs[l].has_prop) {
-          const int r = pose_move_ligand(c, l, st);
-          if (r) return r;
-        }
+    if (a->pose_move_every > 0) {
+      const int r = pose_move_batch(c, only, st);
+      if (r) return r;
+    }
     if (NX > 0)
       for (int l = l0; l < l1; ++l) {
         const int r = external_move_ligand(c, l, NX, a->external_k_max,
@@ -926,14 +946,10 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
   if (P > 0) {
     // units of P sweeps, each followed by the unit's moves; the network's
     // scratch is sized before any capture
-    int maxK = 0;
-    for (int l = l0; l < l1; ++l) {
-      const LigHost& h = c->ligs[l];
-      if (h.has_prop && a->pose_move_every > 0) maxK = std::max(maxK, h.dev.K);
-    }
-    if (maxK > 0) {
+    if (a->pose_move_every > 0) {
+      if ((rc = build_pose_tables(c))) return rc;
       MlpBufs b;
-      if ((rc = mlp_scratch(c, maxK, &b))) return rc;
+      if (c->n_ptasks > 0 && (rc = mlp_scratch(c, c->n_ptasks, &b))) return rc;
     }
     const int units = a->n_sweeps / P, rest = a->n_sweeps % P;
     auto unit = [&](hipStream_t st) -> int {
@@ -2192,6 +2208,7 @@ extern "C" int bpmf_proposal_setup(bpmf_ctx* c, int lid, const int* frame_atoms,
   h.prop = pd;
   h.adam_t = 0;
   h.has_prop = true;
+  c->pose_dirty = true;
   return BPMF_OK;
 }
 
@@ -2287,19 +2304,107 @@ extern "C" int bpmf_proposal_train(bpmf_ctx* c, int lid, const float* dev_feats,
 }
 
 namespace {
-int pose_move_ligand(bpmf_ctx* c, int lid, hipStream_t st) {
-  LigHost& h = c->ligs[lid];
-  const int K = h.dev.K;
+// Tables of the batched pose move (see bpmf_ctx), rebuilt when ligands or
+// proposals have changed; a rebuild invalidates captured graphs.
+int build_pose_tables(bpmf_ctx* c) {
+  if (!c->pose_dirty) return BPMF_OK;
+  const int nl = (int)c->ligs.size();
+  std::vector<PropDev> props(std::max(nl, 1));
+  std::vector<PoseTask> tasks;
+  std::vector<MlpGroup> groups;
+  int off[bpmf_ctx::kWaveClasses], cnt[bpmf_ctx::kWaveClasses],
+      lds[bpmf_ctx::kWaveClasses];
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+    off[q] = (int)tasks.size();
+    lds[q] = 0;
+    for (int l = 0; l < nl; ++l) {
+      LigHost& h = c->ligs[l];
+      if (!h.has_prop || wave_class(h.min_waves) != q) continue;
+      props[l] = h.prop;
+      h.ptask0 = (int)tasks.size();
+      h.pgroup0 = (int)groups.size();
+      for (int r = 0; r < h.dev.K; ++r) {
+        const int row = (int)tasks.size();
+        tasks.push_back(PoseTask{l, r, row, 0});
+      }
+      for (int r = 0; r < h.dev.K; r += 16)
+        groups.push_back(MlpGroup{h.params, h.ptask0 + r,
+                                  std::min(16, h.dev.K - r)});
+      h.n_pgroups = (int)groups.size() - h.pgroup0;
+      const LigDev& L = h.dev;
+      lds[q] = std::max(lds[q], block_lds_bytes(h.min_waves, false, L.n, 0, 0,
+                                                0));
+    }
+    cnt[q] = (int)tasks.size() - off[q];
+  }
+  void* np = c->dalloc(sizeof(PropDev) * props.size());
+  void* nt = c->dalloc(sizeof(PoseTask) * std::max<size_t>(tasks.size(), 1));
+  void* ng = c->dalloc(sizeof(MlpGroup) * std::max<size_t>(groups.size(), 1));
+  if (!np || !nt || !ng) {
+    c->dfree(np);
+    c->dfree(nt);
+    c->dfree(ng);
+    return fail(BPMF_E_NOMEM, "pose-move table allocation failed");
+  }
+  HIP_TRY(hipMemcpyAsync(np, props.data(), sizeof(PropDev) * props.size(),
+                         hipMemcpyHostToDevice, c->stream));
+  if (!tasks.empty())
+    HIP_TRY(hipMemcpyAsync(nt, tasks.data(), sizeof(PoseTask) * tasks.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  if (!groups.empty())
+    HIP_TRY(hipMemcpyAsync(ng, groups.data(),
+                           sizeof(MlpGroup) * groups.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->drop_graph();
+  ++c->table_version;
+  c->dfree(c->d_props);
+  c->dfree(c->d_ptasks);
+  c->dfree(c->d_pgroups);
+  c->d_props = (PropDev*)np;
+  c->d_ptasks = (PoseTask*)nt;
+  c->d_pgroups = (MlpGroup*)ng;
+  c->n_ptasks = (int)tasks.size();
+  c->n_pgroups = (int)groups.size();
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+    c->ptask_off[q] = off[q];
+    c->ptask_n[q] = cnt[q];
+    c->ptask_lds[q] = lds[q];
+  }
+  c->pose_dirty = false;
+  return BPMF_OK;
+}
+
+// One pose move of every replica of ligand `only` (-1: of every ligand
+// with a proposal): features, the network and the move, each one launch
+// over all of the ligands (the move one per wavefront class).  The tables
+// and the network's scratch must be ready (not rebuilt under capture).
+int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st) {
+  int t0 = 0, nt = c->n_ptasks, g0 = 0, ng = c->n_pgroups;
+  if (only >= 0) {
+    const LigHost& h = c->ligs[only];
+    if (!h.has_prop) return BPMF_OK;
+    t0 = h.ptask0;
+    nt = h.dev.K;
+    g0 = h.pgroup0;
+    ng = h.n_pgroups;
+  }
+  if (nt == 0) return BPMF_OK;
   MlpBufs b;
-  int rc = mlp_scratch(c, K, &b);
+  int rc = mlp_scratch(c, c->n_ptasks, &b);
   if (rc) return rc;
-  // features of the current replicas, network, move
-  HIP_TRY(launch_pose_features(c->d_ligs + lid, h.d_prop, h.dev.x, K, b.bf,
-                               b.bp, st));
-  if ((rc = mlp_forward(c, h.params, b.bf, K, b, b.out, st))) return rc;
-  HIP_TRY(launch_pose_move(c->grid, c->d_ligs + lid, h.d_prop, b.out, K,
-                           h.min_waves, lds_of(h, h.min_waves, false), c->seed,
-                           st));
+  HIP_TRY(launch_pose_features_tasks(c->d_ligs, c->d_props, c->d_ptasks + t0,
+                                     nt, b.bf, b.bp, st));
+  HIP_TRY(launch_mlp_forward_groups(c->d_pgroups + g0, ng, b.bf, b.out, st));
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+    // this class's tasks within [t0, t0 + nt)
+    const int a = std::max(t0, c->ptask_off[q]);
+    const int e = std::min(t0 + nt, c->ptask_off[q] + c->ptask_n[q]);
+    if (e <= a) continue;
+    HIP_TRY(launch_pose_move(c->grid, c->d_ligs, c->d_props, c->d_ptasks + a,
+                             e - a, b.out, 1 << q, c->ptask_lds[q], c->seed,
+                             st));
+  }
   return BPMF_OK;
 }
 }  // namespace
@@ -2309,12 +2414,9 @@ extern "C" int bpmf_pose_move(bpmf_ctx* c, int lid, int rounds) {
   if (rc) return rc;
   if (rounds < 0) return fail(BPMF_E_INVAL, "negative rounds");
   if (lid != -1 && (rc = check_prop(c, lid))) return rc;
+  if ((rc = build_pose_tables(c))) return rc;
   for (int r = 0; r < rounds; ++r)
-    for (size_t l = 0; l < c->ligs.size(); ++l) {
-      if (lid != -1 && (int)l != lid) continue;
-      if (!c->ligs[l].has_prop) continue;
-      if ((rc = pose_move_ligand(c, (int)l, c->stream))) return rc;
-    }
+    if ((rc = pose_move_batch(c, lid, c->stream))) return rc;
   return BPMF_OK;
 }
 

@@ -558,7 +558,11 @@ __device__ __forceinline__ void block_sync() {
 // where X0, X1 are block sums of the caller's per-thread extras; identical
 // on every thread.  f (FORCES): -grad(U_bonded + U_I + sum_c w_c Psi_c) of
 // the thread's atom.
-template <int C, int W, bool FORCES, bool ENERGY, bool LEAN = false>
+// BONDED false: the grid terms and the restraint only (terms[0..2] = 0; no
+// topology needs to be staged), for rigid moves, which leave the bonded
+// energy unchanged.
+template <int C, int W, bool FORCES, bool ENERGY, bool LEAN = false,
+          bool BONDED = true>
 __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
                                            const float* w, const float (&x)[3],
                                            float m, const float (&sc)[C],
@@ -591,7 +595,7 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
     const int ntp = (L.nt + kWave - 1) & ~(kWave - 1);
     const int nap = (L.na + kWave - 1) & ~(kWave - 1);
     const int n_index = ntp + nap + L.nb;
-    if (tb >= 0) {
+    if (BONDED && tb >= 0) {
       for (int u = tb; u < n_index; u += nthr) {
         if (u < ntp) {
           if (u < L.nt)

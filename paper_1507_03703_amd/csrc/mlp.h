@@ -35,6 +35,20 @@ struct PropDev {
   double* last_ln_alpha;         // K, ln alpha of each replica's last move
 };
 
+// One replica of a batch of pose moves over several ligands: its ligand's
+// table index, the replica, and its row in the batch's features, poses and
+// network outputs.
+struct PoseTask {
+  int lig, r, row, pad;
+};
+
+// One workgroup of a batched forward pass: rows [row0, row0 + rows) (at
+// most 16) through the network whose parameters start at P.
+struct MlpGroup {
+  const float* P;
+  int row0, rows;
+};
+
 enum { kEpiStore = 0, kEpiSilu = 1, kEpiDsilu = 2 };
 
 // C[m, n] = sum_k A(m, k) B(k, n) (+ bias[n]); A(m, k) = A[m*sam + k*sak],
@@ -71,10 +85,22 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n,
 hipError_t launch_pose_features(const LigDev* lig, const PropDev* prop,
                                 const float* xs, int64_t N, float* feats,
                                 float* poses, hipStream_t st);
-hipError_t launch_pose_move(const GridDev& g, const LigDev* lig,
-                            const PropDev* prop, const float* out, int K,
-                            int waves, int lds, uint64_t seed,
-                            hipStream_t st);
+// features of the current configurations of the n tasks (rows t.row)
+hipError_t launch_pose_features_tasks(const LigDev* ligs,
+                                      const PropDev* props,
+                                      const PoseTask* tasks, int n,
+                                      float* feats, float* poses,
+                                      hipStream_t st);
+// the network for several groups of rows, each with its own parameters
+hipError_t launch_mlp_forward_groups(const MlpGroup* groups, int n_groups,
+                                     const float* X, float* out,
+                                     hipStream_t st);
+// one pose move of each of the n tasks (all of `waves` wavefronts; props
+// indexed by ligand table index, out by task row)
+hipError_t launch_pose_move(const GridDev& g, const LigDev* ligs,
+                            const PropDev* props, const PoseTask* tasks,
+                            int n, const float* out, int waves, int lds,
+                            uint64_t seed, hipStream_t st);
 hipError_t launch_gather_batch(const float* feats, const float* poses,
                                int64_t N, int B, uint64_t seed,
                                uint64_t step, float* bf, float* bp,

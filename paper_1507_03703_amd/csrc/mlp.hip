@@ -185,7 +185,7 @@ __device__ __forceinline__ void dense_rows(
       if (HIDDEN) {
         const float h = silu(v);
         Hn[r][n] = bf16_bits(h);
-        if (m < B) {
+        if (m < B && Z) {
           Z[(int64_t)m * N + n] = v;
           H[(int64_t)m * N + n] = h;
         }
@@ -196,13 +196,24 @@ __device__ __forceinline__ void dense_rows(
   }
 }
 
+// groups (may be null): workgroup b runs rows [row0, row0 + rows) of
+// groups[b] with that group's parameters (several networks in one launch);
+// else workgroup b runs rows 16 b.. of the B rows with parameters P.  Z1,
+// H1, Z2, H2 may be null (the hidden activations are then not stored).
 __global__ __launch_bounds__(kFWaves * 64) void k_mlp_forward(
     const float* __restrict__ P, const float* __restrict__ X, int B,
     float* __restrict__ Z1, float* __restrict__ H1, float* __restrict__ Z2,
-    float* __restrict__ H2, float* __restrict__ out) {
+    float* __restrict__ H2, float* __restrict__ out,
+    const MlpGroup* __restrict__ groups) {
   __shared__ __align__(16) unsigned short S[2][kFRows][kFLd];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int row0 = blockIdx.x * kFRows;
+  int row0 = blockIdx.x * kFRows;
+  if (groups) {
+    const MlpGroup gr = groups[blockIdx.x];
+    P = gr.P;
+    row0 = gr.row0;
+    B = gr.row0 + gr.rows;
+  }
   for (int e = tid; e < kFRows * kNFeat; e += kFWaves * 64) {
     const int r = e / kNFeat, k = e - r * kNFeat, m = row0 + r;
     S[0][r][k] = bf16_bits(m < B ? X[(int64_t)m * kNFeat + k] : 0.f);
@@ -439,17 +450,10 @@ __device__ float dihedral_angle(const float* x, int4 q) {
   return atan2f(y, xx);
 }
 
-// one thread per configuration: pose (t, omega) and features
-__global__ __launch_bounds__(128) void k_pose_features(
-    const LigDev* __restrict__ lig, const PropDev* __restrict__ prop,
-    const float* __restrict__ xs, int64_t N, float* __restrict__ feats,
-    float* __restrict__ poses) {
-  const LigDev& L = *lig;
-  const PropDev& P = *prop;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// pose (t, omega) and features of one configuration x of ligand L
+__device__ void pose_features_one(const LigDev& L, const PropDev& P,
+                                  const float* x, float* po, float* fo) {
   const int n = L.n;
-  const float* x = xs + i * n * 3;
   double c[3] = {0, 0, 0}, M = 0;
   for (int a = 0; a < n; ++a) {
     const double m = L.mass[a];
@@ -462,12 +466,10 @@ __global__ __launch_bounds__(128) void k_pose_features(
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) R[a][b] = F.R[a][b];
   log_rot(R, w);
-  float* po = poses + i * 6;
   for (int d = 0; d < 3; ++d) {
     po[d] = (float)(c[d] / M - L.site[d]);
     po[3 + d] = (float)w[d];
   }
-  float* fo = feats + i * kNFeat;
   for (int q = 0; q < kNFeat; ++q) fo[q] = 0.f;
   for (int q = 0; q < P.n_cond; ++q) {
     const float phi = dihedral_angle(x, P.cond[q]);
@@ -476,6 +478,32 @@ __global__ __launch_bounds__(128) void k_pose_features(
     fo[2 * q] = s;
     fo[2 * q + 1] = cs;
   }
+}
+
+// one thread per configuration xs[i] of one ligand
+__global__ __launch_bounds__(128) void k_pose_features(
+    const LigDev* __restrict__ lig, const PropDev* __restrict__ prop,
+    const float* __restrict__ xs, int64_t N, float* __restrict__ feats,
+    float* __restrict__ poses) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const LigDev& L = *lig;
+  pose_features_one(L, *prop, xs + i * L.n * 3, poses + i * 6,
+                    feats + i * kNFeat);
+}
+
+// one thread per task: the current configuration of replica t.r of ligand
+// t.lig, into row t.row
+__global__ __launch_bounds__(128) void k_pose_features_tasks(
+    const LigDev* __restrict__ ligs, const PropDev* __restrict__ props,
+    const PoseTask* __restrict__ tasks, int n, float* __restrict__ feats,
+    float* __restrict__ poses) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const PoseTask t = tasks[i];
+  const LigDev& L = ligs[t.lig];
+  pose_features_one(L, props[t.lig], L.x + (size_t)t.r * L.n * 3,
+                    poses + (size_t)t.row * 6, feats + (size_t)t.row * kNFeat);
 }
 
 // wavefront maximum of a double (DPP tree as in wave_sum)
@@ -537,18 +565,26 @@ __device__ double log_q_se3_wave(const Mix& p, const double t[3],
   return mx + log(wave_sum(e));
 }
 
-// Independence MH pose move, one workgroup of W waves per replica.
+// Independence MH pose move, one workgroup of W waves per task (replica
+// t.r of ligand t.lig, network outputs in row t.row).  The move is rigid, so
+// the bonded energy does not change: only the grid terms and the restraint
+// are evaluated at the proposed pose, and the bonded part of the energy is
+// the cached one (the cached U_bond + U_angle + U_tors + U_I less the
+// restraint energy of the current centre of mass).
 template <int C, int W>
 __global__ __launch_bounds__(W * kWave) void k_pose_move(
-    GridDev g, const LigDev* __restrict__ lig, const PropDev* __restrict__ prop,
+    GridDev g, const LigDev* __restrict__ ligs,
+    const PropDev* __restrict__ props, const PoseTask* __restrict__ tasks,
     const float* __restrict__ out, uint64_t seed) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float sR[9], st[3], scom[3];
   __shared__ int s_ok;
-  const LigDev L = *lig;
-  const PropDev& P = *prop;
+  __shared__ double s_ui0;
+  const PoseTask task = tasks[blockIdx.x];
+  const LigDev L = ligs[task.lig];
+  const PropDev& P = props[task.lig];
   const int tid = threadIdx.x;
-  const int r = blockIdx.x;
+  const int r = task.r;
   const int n = L.n;
   const unsigned long long s = *L.counter;
   const int k = L.state_of_replica[r];
@@ -576,7 +612,7 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
       s_cp[4 * wv + 3] = cm;
     }
     if (tid < kNComp) {
-      const float* o = out + (size_t)r * kNOut + 13 * tid;
+      const float* o = out + (size_t)task.row * kNOut + 13 * tid;
       s_mix.lw[tid] = o[0];
       for (int a = 0; a < 3; ++a) {
         s_mix.mt[tid][a] = o[1 + a];
@@ -606,11 +642,16 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) R0[a][b] = F.R[a][b];
     log_rot(R0, w0);
+    double d2 = 0.0;
     for (int d = 0; d < 3; ++d) {
       c[d] /= M;
       s_pose[d] = c[d] - L.site[d];
       s_pose[3 + d] = w0[d];
+      d2 += s_pose[d] * s_pose[d];
     }
+    // restraint energy at the current centre of mass (Eq. binding_site)
+    const double ex0 = sqrt(d2) - (double)L.d0;
+    s_ui0 = ex0 > 0.0 ? 0.5 * (double)L.krest * ex0 * ex0 : 0.0;
     // component by inverse CDF, then (t, omega) by Gaussian draws
     const U4 o0 = draw(seed, 0u, L.id, r, s, kPose);
     const double u = u01d(o0.x);
@@ -658,16 +699,10 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     if (tid == 0) s_ok = isfinite(lq_ratio) ? 1 : 0;
   }
   __syncthreads();
-  Shared sh;
-  {
-    sh.pos = reinterpret_cast<float4*>(smem);
-    sh.red = reinterpret_cast<double*>(smem + 16 * kWave * W);
-    sh.com = reinterpret_cast<float*>(smem + 16 * kWave * W + 8 * W * kRedMax);
-    const int acc0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
-    sh.sl = Slots{reinterpret_cast<unsigned int*>(smem + acc0)};
-    stage_topology(L, smem + acc0, sh, tid, W * kWave);
-    __syncthreads();
-  }
+  Shared sh{};
+  sh.pos = reinterpret_cast<float4*>(smem);
+  sh.red = reinterpret_cast<double*>(smem + 16 * kWave * W);
+  sh.com = reinterpret_cast<float*>(smem + 16 * kWave * W + 8 * W * kRedMax);
   const bool owner = tid < n;
   float x2[3] = {0.f, 0.f, 0.f}, f[3];
   if (owner) {
@@ -683,10 +718,11 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
   float w[C];
   for (int c = 0; c < C; ++c) w[c] = L.wf[k * C + c];
   double t1e[6 + C];
-  eval_block<C, W, false, true>(g, L, w, x2, m, sc, f, t1e, 0.f, 0.f, sh, tid);
-  double E1 = t1e[0] + t1e[1] + t1e[2] + t1e[3], E0 = 0.0;
+  eval_block<C, W, false, true, false, false>(g, L, w, x2, m, sc, f, t1e, 0.f,
+                                              0.f, sh, tid);
   const double* cp = L.comps + (size_t)r * (1 + C);
-  E0 = cp[0];
+  const double ub = cp[0] - s_ui0;  // bonded energy, unchanged by the move
+  double E1 = ub + t1e[3], E0 = cp[0];
   for (int c = 0; c < C; ++c) {
     E1 += L.wd[k * C + c] * t1e[4 + c];
     E0 += L.wd[k * C + c] * cp[1 + c];
@@ -706,7 +742,7 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
       for (int d = 0; d < 3; ++d) L.x[(size_t)r * n * 3 + 3 * tid + d] = x2[d];
     if (tid == 0) {
       double* cw = L.comps + (size_t)r * (1 + C);
-      cw[0] = t1e[0] + t1e[1] + t1e[2] + t1e[3];
+      cw[0] = ub + t1e[3];
       for (int c = 0; c < C; ++c) cw[1 + c] = t1e[4 + c];
       L.fvalid[r] = 0;  // the stored start-of-trajectory forces are stale
     }
@@ -730,7 +766,19 @@ hipError_t launch_mlp_forward(const float* P, const float* X, int B,
                               float* out, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_forward, dim3((B + kFRows - 1) / kFRows),
-                     dim3(kFWaves * 64), 0, st, P, X, B, Z1, H1, Z2, H2, out);
+                     dim3(kFWaves * 64), 0, st, P, X, B, Z1, H1, Z2, H2, out,
+                     (const MlpGroup*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward_groups(const MlpGroup* groups, int n_groups,
+                                     const float* X, float* out,
+                                     hipStream_t st) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(n_groups), dim3(kFWaves * 64), 0, st,
+                     (const float*)nullptr, X, 0, (float*)nullptr,
+                     (float*)nullptr, (float*)nullptr, (float*)nullptr, out,
+                     groups);
   return hipGetLastError();
 }
 
@@ -765,26 +813,38 @@ hipError_t launch_pose_features(const LigDev* lig, const PropDev* prop,
   return hipGetLastError();
 }
 
-hipError_t launch_pose_move(const GridDev& g, const LigDev* lig,
-                            const PropDev* prop, const float* out, int K,
-                            int waves, int lds, uint64_t seed,
-                            hipStream_t st) {
+hipError_t launch_pose_features_tasks(const LigDev* ligs,
+                                      const PropDev* props,
+                                      const PoseTask* tasks, int n,
+                                      float* feats, float* poses,
+                                      hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pose_features_tasks, dim3((n + 127) / 128), dim3(128),
+                     0, st, ligs, props, tasks, n, feats, poses);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_move(const GridDev& g, const LigDev* ligs,
+                            const PropDev* props, const PoseTask* tasks,
+                            int n, const float* out, int waves, int lds,
+                            uint64_t seed, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
   switch (g.C) {
     case 3:
       if (waves == 1)
-        hipLaunchKernelGGL((k_pose_move<3, 1>), dim3(K), dim3(64), lds, st, g,
-                           lig, prop, out, seed);
+        hipLaunchKernelGGL((k_pose_move<3, 1>), dim3(n), dim3(64), lds, st, g,
+                           ligs, props, tasks, out, seed);
       else
-        hipLaunchKernelGGL((k_pose_move<3, 2>), dim3(K), dim3(128), lds, st, g,
-                           lig, prop, out, seed);
+        hipLaunchKernelGGL((k_pose_move<3, 2>), dim3(n), dim3(128), lds, st, g,
+                           ligs, props, tasks, out, seed);
       break;
     case 5:
       if (waves == 1)
-        hipLaunchKernelGGL((k_pose_move<5, 1>), dim3(K), dim3(64), lds, st, g,
-                           lig, prop, out, seed);
+        hipLaunchKernelGGL((k_pose_move<5, 1>), dim3(n), dim3(64), lds, st, g,
+                           ligs, props, tasks, out, seed);
       else
-        hipLaunchKernelGGL((k_pose_move<5, 2>), dim3(K), dim3(128), lds, st, g,
-                           lig, prop, out, seed);
+        hipLaunchKernelGGL((k_pose_move<5, 2>), dim3(n), dim3(128), lds, st, g,
+                           ligs, props, tasks, out, seed);
       break;
     default:
       return hipErrorInvalidValue;
