@@ -19,6 +19,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same source
+# (CPU checking only; loaded instead of LIB_PATH when BPMF_ORACLE_LIB names
+# it, in a process that preloads the sanitizer runtime)
+SAN_LIB_PATH = os.path.join(HERE, "liboracle_san.so")
+CLANG = "/opt/rocm/llvm/bin/clang"
 R_GAS = 8.314462618e-3  # kJ/(mol K)
 
 P_MOMENTA, P_ACCEPT, P_EXCHANGE, P_POSE = 1, 2, 3, 4
@@ -37,6 +42,22 @@ def build(force: bool = True) -> str:
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
+
+
+def build_sanitized(out: str = SAN_LIB_PATH) -> str:
+    """Compile oracle.c with clang's AddressSanitizer and
+    UndefinedBehaviorSanitizer (the runtime shared, so that one preloaded
+    runtime serves this library and the HIP library's sanitized host code
+    in one process); every undefined-behaviour report is fatal."""
+    src = os.path.join(HERE, "oracle.c")
+    tmp = out + ".tmp"
+    cmd = [CLANG, "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-shared-libsan", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-ffp-contract=off", src, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
 
 
 class _Grid(C.Structure):
@@ -66,9 +87,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("BPMF_ORACLE_LIB", LIB_PATH)
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             build(force=False)
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
         vp = C.c_void_p

@@ -115,12 +115,13 @@ def library():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
+    path = os.environ.get("BPMF_LIB", LIB_PATH)
+    if not os.path.exists(path):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with "
+            f"{path} is missing: build it with "
             "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, "
             "gfx950).  There is no fallback implementation.")
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(path)
     vp, dp, fp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_void_p, \
         C.POINTER(C.c_int)
     i64p = C.POINTER(C.c_int64)

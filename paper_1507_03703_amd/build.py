@@ -42,5 +42,36 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# host code instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
+# (device code is compiled as usual); for checking the host-side validation
+# and bookkeeping on the CPU, loaded through BPMF_LIB in a process that
+# preloads clang's shared sanitizer runtime
+SAN_LIB = os.path.join(HERE, "libbpmf_san.so")
+SAN_HOST_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host",
+                  "-fsanitize=undefined", "-Xarch_host",
+                  "-fno-sanitize-recover=all", "-Xarch_host",
+                  "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def build_sanitized(out: str = SAN_LIB) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objs = []
+    for s in SOURCES:
+        src = os.path.join(CSRC, s)
+        obj = os.path.join(CSRC, s.replace(".hip", ".san.o"))
+        cmd = [hipcc, *[f for f in FLAGS if f not in ("-shared", "-O3")],
+               "-O1", *SAN_HOST_FLAGS, "-c", src, "-o", obj]
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = out + ".tmp"
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o",
+           tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    for o in objs:
+        os.remove(o)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
