@@ -1,36 +1,39 @@
 """Benchmark of the BPMF sampling hot path on one MI355X.
 
-Workload (default): the production-size single-ligand system -- a 48-atom
-ligand, three float32 receptor grids of 128^3 nodes at 0.25 A from 2000
-point atoms, 64 replicas on a coupled temperature/lambda ladder (600 K,
-lambda 0 -> 300 K, lambda 1).  One step is one pass of the whole hot path:
-5000 sweeps of (one 20-step velocity-Verlet HMC move per replica + one
-neighbour replica-exchange sweep), a recorded sample per state every 10
-sweeps, the 64 x 32000 float64 reduced-energy matrix u_kn recomputed from the
-recorded configurations, and MBAR on it (BPMF_syn = f_{K-1} - f_0).
-Replicas carry over from step to step (a production run in cycles).
+Workload (default): the large batched workload with learned pose proposals
+-- 32 ligands of 40-100 atoms, each with a 32-state ladder (1024 replicas;
+600 K, lambda 0 -> 300 K, lambda 1), sharing three float32 receptor grids of
+256^3 nodes at 0.25 A from 8000 point atoms, and one pose-proposal network
+per ligand, trained before the timed steps on 200k poses that plain HMC
+samples at the ligand's coupled state.  One step is one pass of the whole
+hot path: 10000 sweeps of (one 10-step velocity-Verlet HMC move per replica
++ one neighbour replica-exchange sweep), a learned independence pose move
+of every replica every 5 sweeps, a recorded sample per state every 50
+sweeps, each ligand's 32 x 6400 float64 reduced-energy matrix u_kn
+recomputed from its recorded configurations (one batched call), and MBAR on
+all 32 (one batched call).  Replicas carry over from step to step (a
+production run in cycles).
 
 value = atom-grid energy+force evaluations of the HMC moves per second of
-whole-step time; one evaluation = one atom's trilinear interpolation of the
-three grids with gradient (96 algorithmic grid bytes) plus its share of the
-bonded terms and restraint.
+whole-step time (L per atom per sweep: the force at the start of a
+trajectory is the previous sweep's last one); one evaluation = one atom's
+trilinear interpolation of the three grids with gradient (96 algorithmic
+grid bytes) plus its share of the bonded terms and restraint.  The
+roofline's kernel time is the sweep kernel's mean launch time, measured
+with HIP events on the library's stream over plain sweeps of the same
+ligands after the timed steps.
 
-A second leg ("batched") runs the batched workload -- 256 ligands of 10-80
-atoms with 32 replicas each on one shared 160^3 grid, 2000 sweeps of 10
-steps, per-ligand u_kn and MBAR -- with the launch shape picked by the
-autotuner; --config 3 makes it the main workload instead.  A third leg
-("learned_proposal") compares plain HMC with HMC plus learned independence
-pose moves on the 24-atom, 64-state system (the paper's soft-grid switching
-protocol): BPMF error against a long plain run and effective samples per
-second of the fully coupled state, both continuing from the long run's
-equilibrated end.  A fourth leg ("initialization") builds that system's
-ladder with the paper's initialisation (50 seeds per state, 200 x 10-step
-HMC runs, 50 x 453 x 100 random placements as state 0's sample set, speed
-0.2) and compares neighbour exchange rates of the built ladder with the
-fixed 64-state ladder in a short production run.  A fifth leg
-("pair_terms") times the ligand's intramolecular nonbonded and OBC GB/SA
-energies and forces over the 32000 recorded samples of a production step,
-for the 48-atom production ligand and a 100-atom ligand.
+Further legs in the same JSON line: "production_single_ligand" (a 48-atom
+ligand, 64 replicas, 128^3 grids, 5000 sweeps of 20 steps, u_kn, MBAR),
+"batched" (256 ligands of 10-80 atoms x 32 replicas on 160^3 grids, 2000
+sweeps; the launch shape picked by the autotuner), "bulk_interpolation"
+(u_kn and the interpolation harness on the sample sets of the batched
+workloads), "learned_proposal" (plain HMC, the paper's external moves and
+learned pose moves on the 24-atom, 64-state soft-grid system: BPMF error
+against a long plain run and effective samples per second),
+"initialization" (the paper's ladder initialisation and production
+protocol) and "pair_terms" (the ligand's intramolecular nonbonded and OBC
+GB/SA energies and forces).  --config picks another main workload.
 """
 from __future__ import annotations
 
@@ -94,13 +97,19 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--config", type=int, default=2)
+    p.add_argument("--config", type=int, default=5)
     p.add_argument("--sweeps", type=int, default=None,
                    help="override sweeps per step (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cpu-seconds", type=float, default=16.0)
     p.add_argument("--no-batched", dest="batched", action="store_false",
                    help="skip the batched 256-ligand leg")
+    p.add_argument("--no-production", dest="production",
+                   action="store_false",
+                   help="skip the single-ligand production (config 2) leg")
+    p.add_argument("--no-proposals", dest="proposals", action="store_false",
+                   help="config 5 without its learned pose proposals")
+    p.add_argument("--proposal-train-steps", type=int, default=1500)
     p.add_argument("--no-bulk", dest="bulk", action="store_false",
                    help="skip the bulk interpolation leg")
     p.add_argument("--bulk-configs", default="3,5",
@@ -134,37 +143,134 @@ def parse():
     return p.parse_args()
 
 
-def cpu_baseline(system, target_s):
-    """The FP64 oracle running the same sweeps on the host cores, on a
-    bounded number of sweeps."""
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it, from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(system, target_s, n_ligands=2):
+    """The FP64 oracle's sampler (HMC moves + neighbour exchange, the same
+    sweeps as the library's) on a bounded sample of the workload: its first
+    `n_ligands` ligands, each for as many sweeps as fit about target_s / 2
+    seconds split over the ligands, once on one host thread and once on all
+    of them (OpenMP across replicas).  The oracle evaluates every atom L + 1
+    times per sweep (it recomputes the force at the start of a trajectory),
+    and its rate counts them all."""
     import numpy as np
     import oracle
     oracle.build(force=False)
-    lig = system.ligands[0]
-    og, ol = oracle.OGrid(system.grid), oracle.OLigand(lig)
-    s = oracle.Sampler(og, ol, seed=system.seed, x0=lig.x0)
     L = system.n_leapfrog
+    ligs = system.ligands[:n_ligands]
+    og = oracle.OGrid(system.grid)
+    all_threads = int(oracle.num_threads())
+    runs = {}
+    for threads in (1, all_threads):
+        oracle.set_num_threads(threads)
+        evals = sweeps_done = 0
+        el = 0.0
+        for q, lig in enumerate(ligs):
+            ol = oracle.OLigand(lig)
+            s = oracle.Sampler(og, ol, seed=system.seed, lig_id=q, x0=lig.x0)
+            t0 = time.perf_counter()
+            s.sweep(nleap=L, exchange_every=1)
+            one = time.perf_counter() - t0
+            n = max(2, int(target_s / 2 / len(ligs) / max(one, 1e-4)))
+            t0 = time.perf_counter()
+            for _ in range(n):
+                s.sweep(nleap=L, exchange_every=1)
+            el += time.perf_counter() - t0
+            evals += n * ol.K * lig.n_atoms * (L + 1)
+            sweeps_done += n
+        runs[threads] = (evals / el, sweeps_done, el)
+    oracle.set_num_threads(all_threads)
+    counts = [l.n_atoms for l in ligs]
+    v1, n1, e1 = runs[1]
+    va, na, ea = runs[all_threads]
+    return dict(value=va, unit="atom-evals/s", cores=all_threads,
+                kind="oracle", single_core_value=v1,
+                cpu_model=cpu_model(),
+                sample=f"{system.name}: ligands 0-{len(ligs) - 1} "
+                       f"({', '.join(map(str, counts))} atoms, "
+                       f"{ligs[0].n_states} replicas each), oracle sweeps of "
+                       f"{L} leapfrog steps + neighbour exchange, "
+                       f"{ligs[0].n_states} x n_atoms x {L + 1} energy+force "
+                       f"evaluations per ligand sweep; {n1} sweeps in "
+                       f"{e1:.1f} s on 1 thread, {na} sweeps in {ea:.1f} s "
+                       f"on {all_threads} threads")
+
+
+def train_proposals(pkg, torch, system, sweeps=31250, burn=400, every=5,
+                    steps=1500, batch=512, lr=2e-3):
+    """One pose proposal per ligand, trained as the learned workloads state
+    it: poses sampled by plain HMC at the coupled state (lambda = 1, 300 K;
+    K independent chains per ligand, every ligand in one context, a record
+    every `every` sweeps after `burn` sweeps: K x sweeps / every poses, 200k
+    at the defaults), then each ligand's network trained on its own poses
+    by the library's kernels (Adam, minibatches drawn with replacement).
+    Returns the parameters per ligand and what the training cost."""
+    import dataclasses
+    import numpy as np
+    g, ligs, L = system.grid, system.ligands, system.n_leapfrog
+    coupled = [dataclasses.replace(
+        l, T=np.full(l.n_states, l.T[-1]),
+        w=np.repeat(l.w[-1:], l.n_states, axis=0),
+        dt=np.full(l.n_states, float(l.dt[-1]))) for l in ligs]
+    records = sweeps // every
+    ctx = pkg.Context(seed=system.seed + 17, device=0)
+    ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+    ids = [ctx.ligand_setup(l, sample_capacity=records) for l in coupled]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.sweep(nleap=L, exchange_every=1)
-    one = time.perf_counter() - t0
-    n = max(2, int(target_s / max(one, 1e-4)))
-    t0 = time.perf_counter()
-    for _ in range(n):
-        s.sweep(nleap=L, exchange_every=1)
-    el = time.perf_counter() - t0
-    evals = n * ol.K * lig.n_atoms * (L + 1)
-    return dict(value=evals / el, unit="atom-evals/s",
-                cores=int(oracle.num_threads()), kind="oracle",
-                sample=f"{n} sweeps of the {system.name} workload "
-                       f"({ol.K} replicas x {lig.n_atoms} atoms x {L + 1} "
-                       f"energy+force evaluations per sweep, plus exchange), "
-                       f"{el:.1f} s")
+    ctx.hmc_sweep(burn, L, exchange_every=0)
+    ctx.hmc_sweep(sweeps, L, exchange_every=0, sample_every=every)
+    torch.cuda.synchronize()
+    sample_s = time.perf_counter() - t0
+    rng = np.random.default_rng(system.seed)
+    params, first, last = [], [], []
+    train_s = 0.0
+    for lid, l in zip(ids, coupled):
+        xs, _ = ctx.get_samples(lid)
+        xd = torch.from_numpy(xs.reshape(-1, l.n_atoms, 3)).to("cuda:0")
+        del xs
+        ctx.proposal_setup(lid, l.frame_atoms, l.tors[l.cond_tors],
+                           init_params(rng))
+        feats, poses = ctx.pose_features(lid, xd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = ctx.proposal_train(lid, feats, poses, batch=batch,
+                                    steps=steps, lr=lr, losses=True)
+        torch.cuda.synchronize()
+        train_s += time.perf_counter() - t0
+        params.append(ctx.proposal_params(lid))
+        first.append(float(np.mean(losses[:20])))
+        last.append(float(np.mean(losses[-20:])))
+        del xd, feats, poses
+    ctx.close()
+    return params, {"poses_per_ligand": records * ligs[0].n_states,
+                    "sampling_sweeps": burn + sweeps, "sampling_s": sample_s,
+                    "adam_steps": steps, "batch": batch, "lr": lr,
+                    "train_s": train_s,
+                    "loss_first_mean": float(np.mean(first)),
+                    "loss_last_mean": float(np.mean(last))}
 
 
 def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
-                 tune=False, waves=None):
+                 tune=False, waves=None, proposals=None, pose_every=5,
+                 kernel_sweeps=256):
     """Set up every ligand of `system`, run `warmup` + `steps` timed steps
-    of the hot path and return the measurements."""
+    of the hot path and return the measurements.  proposals: per-ligand
+    network parameters; the sweeps then carry a learned pose move of every
+    replica every `pose_every` sweeps.  After the timed steps,
+    `kernel_sweeps` plain sweeps (plain launches, every one bracketed by HIP
+    events on the library's stream) give the sweep kernel's own mean launch
+    time for the roofline."""
     import numpy as np
     g = system.grid
     ligs = system.ligands
@@ -176,6 +282,10 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
     ctx = pkg.Context(seed=system.seed, device=0)
     ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
     ids = [ctx.ligand_setup(l, sample_capacity=records) for l in ligs]
+    if proposals is not None:
+        for i, l, p in zip(ids, ligs, proposals):
+            ctx.proposal_setup(i, l.frame_atoms, l.tors[l.cond_tors], p)
+    moves = dict(pose_move_every=pose_every if proposals is not None else 0)
     ukn = [torch.empty((l.n_states, records * l.n_states),
                        dtype=torch.float64, device="cuda:0") for l in ligs]
     Nk = [np.full(l.n_states, records, np.int64) for l in ligs]
@@ -201,7 +311,7 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
         for i in ids:
             ctx.reset_samples(i)
         ctx.hmc_sweep(sweeps, L, exchange_every=1, exchange_scheme=0,
-                      sample_every=every)
+                      sample_every=every, **moves)
         # every ligand's u_kn, then every ligand's MBAR, in batched calls
         ctx.energy_matrix_batch(ids, n_samples=[u.shape[1] for u in ukn],
                                 outs=ukn)
@@ -221,15 +331,35 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
         results = step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    hmc_ms, hmc_n = ctx.get_timing(ctx.TIMER_HMC)
+    unit_ms, unit_n = ctx.get_timing(ctx.TIMER_HMC)
     cmp_ms, cmp_n = ctx.get_timing(ctx.TIMER_COMPONENTS)
     ctx.set_timing(False)
     stats = [ctx.get_stats(i) for i in ids]
+    pose = None
+    if proposals is not None:
+        ps = [ctx.get_pose_stats(i) for i in ids]
+        pose = {"pose_moves": int(sum(p["tries"].sum() for p in ps)),
+                "pose_acceptance": float(sum(p["acc"].sum() for p in ps) /
+                                         max(sum(p["tries"].sum()
+                                                 for p in ps), 1)),
+                "pose_acceptance_coupled_states": float(
+                    sum(p["acc"][-1] for p in ps) /
+                    max(sum(p["tries"][-1] for p in ps), 1))}
+    # the sweep kernel alone: plain launches, each timed
+    ctx.set_graph(0)
+    ctx.hmc_sweep(8, L, exchange_every=1)
+    torch.cuda.synchronize()
+    ctx.set_timing(True, every=1)
+    ctx.hmc_sweep(kernel_sweeps, L, exchange_every=1)
+    hmc_ms, hmc_n = ctx.get_timing(ctx.TIMER_HMC)
+    ctx.set_timing(False)
     waves = sorted({ctx.get_waves(i) for i in ids})
     ctx.close()
 
     ms_per_step = el / steps * 1e3
-    evals_per_sweep = sum(l.n_states * l.n_atoms for l in ligs) * (L + 1)
+    # the kernel evaluates every atom L times per sweep (the force at the
+    # start of a trajectory comes from the previous sweep's last step)
+    evals_per_sweep = sum(l.n_states * l.n_atoms for l in ligs) * L
     value = sweeps * evals_per_sweep / (ms_per_step * 1e-3)
     achieved = evals_per_sweep * GRID_BYTES_PER_EVAL / (hmc_ms * 1e-3) / 1e9
     f, var, it = results[0]
@@ -238,21 +368,22 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
     exa = sum(st["ex_acc"].sum() for st in stats) / max(
         sum(st["ex_try"].sum() for st in stats), 1)
     bpmf = np.array([r[0][-1] - r[0][0] for r in results])
+    res = {"bpmf_syn_kT": float(f[-1] - f[0]) if len(results) == 1 else None,
+           "sigma_kT": float(np.sqrt(max(var[-1], 0.0))),
+           "mbar_iterations": int(it),
+           "mbar_iterations_max": int(max(r[2] for r in results)),
+           "bpmf_syn_kT_mean": float(bpmf.mean()),
+           "bpmf_syn_kT_range": [float(bpmf.min()), float(bpmf.max())],
+           "hmc_acceptance": float(acc),
+           "exchange_acceptance": float(exa)}
+    if pose:
+        res.update(pose)
     return dict(value=value, ms_per_step=ms_per_step, sweeps=sweeps,
-                records=records, hmc_ms=hmc_ms, hmc_n=hmc_n, cmp_ms=cmp_ms,
+                records=records, hmc_ms=hmc_ms, hmc_n=hmc_n,
+                unit_ms=unit_ms, unit_n=unit_n, cmp_ms=cmp_ms,
                 achieved=achieved, evals_per_sweep=evals_per_sweep,
                 setup_s=setup_s, waves=waves, tuned=tuned,
-                result={"bpmf_syn_kT": float(f[-1] - f[0]) if len(results)
-                        == 1 else None,
-                        "sigma_kT": float(np.sqrt(max(var[-1], 0.0))),
-                        "mbar_iterations": int(it),
-                        "mbar_iterations_max": int(max(r[2] for r in
-                                                       results)),
-                        "bpmf_syn_kT_mean": float(bpmf.mean()),
-                        "bpmf_syn_kT_range": [float(bpmf.min()),
-                                              float(bpmf.max())],
-                        "hmc_acceptance": float(acc),
-                        "exchange_acceptance": float(exa)})
+                pose_every=moves["pose_move_every"], result=res)
 
 
 def bulk_leg(pkg, torch, system, reps=3, harness_min=10 ** 8):
@@ -356,25 +487,31 @@ def describe(system, r):
     g = system.grid
     L = system.n_leapfrog
     R = sum(l.n_states for l in ligs)
+    moves = (f" + a learned independence pose move per replica every "
+             f"{r['pose_every']} sweeps (one trained network per ligand)"
+             if r.get("pose_every") else "")
     if len(ligs) == 1:
         l = ligs[0]
         what = (f"{system.name}: {l.n_atoms}-atom ligand, {g.n[0]}^3 x 3 "
                 f"float32 grids at {g.spacing} A, {R} replicas, "
                 f"{r['sweeps']} sweeps x {L} leapfrog steps + neighbour "
-                f"exchange, u_kn {l.n_states}x{r['records'] * l.n_states} "
-                f"float64, MBAR")
+                f"exchange{moves}, u_kn "
+                f"{l.n_states}x{r['records'] * l.n_states} float64, MBAR")
     else:
         counts = [l.n_atoms for l in ligs]
         what = (f"{system.name}: {len(ligs)} ligands of {min(counts)}-"
                 f"{max(counts)} atoms x {ligs[0].n_states} replicas ({R} "
                 f"replicas), shared {g.n[0]}^3 x 3 float32 grids at "
                 f"{g.spacing} A, {r['sweeps']} sweeps x {L} leapfrog steps "
-                f"+ neighbour exchange, per-ligand u_kn and MBAR")
+                f"+ neighbour exchange{moves}, per-ligand u_kn "
+                f"({ligs[0].n_states} x {r['records'] * ligs[0].n_states}) "
+                f"and batched MBAR")
     return {"workload": what, "ligands": len(ligs), "replicas": R,
             "atoms": [l.n_atoms for l in ligs] if len(ligs) <= 4 else
             f"{sum(l.n_atoms for l in ligs)} total",
             "sweeps_per_step": r["sweeps"], "leapfrog": L,
-            "samples_per_state": r["records"]}
+            "samples_per_state": r["records"],
+            "pose_move_every": r.get("pose_every") or None}
 
 
 def roofline(r, workload):
@@ -383,6 +520,7 @@ def roofline(r, workload):
             "traffic": measured_traffic("k_hmc_sweep", workload, r["waves"]),
             "kernel": "k_hmc_sweep",
             "mean_launch_ms": r["hmc_ms"], "launches_timed": r["hmc_n"],
+            "evals_per_launch": r["evals_per_sweep"],
             "algorithmic_bytes_per_launch": r["evals_per_sweep"] *
             GRID_BYTES_PER_EVAL}
 
@@ -570,9 +708,13 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
         ctx.close()
         return out
 
+    progress("learned leg: reference run and training")
     plain = production("plain")
+    progress("learned leg: plain sampler")
     external = production("external")
+    progress("learned leg: external-move sampler")
     learned = production("learned")
+    progress("learned leg: learned sampler")
     return {
         "workload": f"{system.name} with the soft-grid switching protocol "
                     f"(5 channels): {n}-atom ligand, {g.n[0]}^3 grids, {K} "
@@ -842,6 +984,16 @@ def paper_production(pkg, torch, g, lig, res, L, seed, n_cycles=15,
             "cycle_sd_kT": float(blk.std(ddof=1)) if len(blk) > 1 else None}
 
 
+T_START = time.perf_counter()
+
+
+def progress(what):
+    """One line on stderr as each part of the run ends (the JSON result
+    line goes to stdout at the end)."""
+    print(f"bench: {what} ({time.perf_counter() - T_START:.1f} s)",
+          file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -889,9 +1041,15 @@ def main():
         return
 
     system = synth.make_system(args.config, grid_device=args.grid_device)
+    proposals = training = None
+    if args.config == 5 and args.proposals:
+        proposals, training = train_proposals(
+            pkg, torch, system, steps=args.proposal_train_steps)
+        progress("proposals trained")
     r = run_workload(pkg, torch, system, args.steps, args.warmup,
                      sweeps=args.sweeps, tune=len(system.ligands) > 1,
-                     waves=args.waves)
+                     waves=args.waves, proposals=proposals)
+    progress(f"{system.name}: {args.steps} timed steps")
     out = {
         "metric": "atom-grid energy+force evals/s & HBM fraction; effective "
                   "samples/s vs plain HMC",
@@ -908,29 +1066,47 @@ def main():
         "data": "synthetic",
         "config": describe(system, r),
         "roofline": roofline(r, system.name),
-        "kernels_ms": {"hmc_sweep": r["hmc_ms"], "energy_matrix": r["cmp_ms"]},
+        "kernels_ms": {"hmc_sweep": r["hmc_ms"],
+                       "sweep_unit_per_sweep": r["unit_ms"],
+                       "energy_matrix": r["cmp_ms"]},
         "result": r["result"],
         "setup_s": r["setup_s"],
     }
+    if training:
+        out["proposal_training"] = training
     if r["tuned"]:
         out["autotune"] = r["tuned"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_seconds)
+        progress("cpu baseline")
+    del system
+
+    def extra(config):
+        es = synth.make_system(config, grid_device=args.grid_device)
+        re = run_workload(pkg, torch, es, 1, 1, tune=len(es.ligands) > 1,
+                          waves=args.waves)
+        return {"value": re["value"], "unit": "atom-evals/s",
+                "ms_per_step": re["ms_per_step"], "steps": 1, "warmup": 1,
+                "config": describe(es, re),
+                "roofline": roofline(re, es.name),
+                "autotune": re["tuned"], "waves": re["waves"],
+                "result": re["result"]}
+
+    if args.production and args.config != 2:
+        out["production_single_ligand"] = extra(2)
+        progress("production single-ligand leg")
     if args.batched and args.config != 3:
-        bs = synth.make_system(3, grid_device=args.grid_device)
-        rb = run_workload(pkg, torch, bs, 1, 1, tune=True, waves=args.waves)
-        out["batched"] = {"value": rb["value"], "unit": "atom-evals/s",
-                          "ms_per_step": rb["ms_per_step"], "steps": 1,
-                          "warmup": 1, "config": describe(bs, rb),
-                          "roofline": roofline(rb, bs.name),
-                          "autotune": rb["tuned"], "waves": rb["waves"],
-                          "result": rb["result"]}
+        out["batched"] = extra(3)
+        progress("batched leg")
     if args.bulk:
         out["bulk_interpolation"] = bulk()
+        progress("bulk interpolation leg")
     if args.init:
         out["initialization"] = init_leg(pkg, torch)
+        progress("initialisation leg")
     if args.pairs:
         out["pair_terms"] = pair_leg(pkg, torch)
+        progress("pair-term leg")
     if args.learned:
         out["learned_proposal"] = learned_leg(
             pkg, torch, train_steps=args.train_steps, burn=args.burn_sweeps,

@@ -83,6 +83,10 @@ struct LigHost {
   // place in the batched pose-move tables (build_pose_tables): first task
   // (= first row), first forward group and their count
   int ptask0 = -1, pgroup0 = 0, n_pgroups = 0;
+  // bf16 transposed weights of the pose moves' forward pass (kTSize), stale
+  // while wt_dirty (after the fp32 parameters change)
+  unsigned short* wt = nullptr;
+  bool wt_dirty = true;
   // intramolecular nonbonded / implicit-solvent terms (bpmf_pair_setup)
   bool has_pairs = false;
   void* pair_arena = nullptr;
@@ -138,7 +142,6 @@ struct bpmf_ctx {
   int n_ptasks = 0, n_pgroups = 0;
   int ptask_off[kWaveClasses] = {0, 0, 0, 0};
   int ptask_n[kWaveClasses] = {0, 0, 0, 0};
-  int ptask_lds[kWaveClasses] = {0, 0, 0, 0};
   // kernel timing
   static constexpr int kTimers = 4;
   static constexpr size_t kMaxPairs = 8192;
@@ -792,6 +795,7 @@ struct MlpBufs {
 };
 int mlp_scratch(bpmf_ctx* c, int B, MlpBufs* b);
 int build_pose_tables(bpmf_ctx* c);
+int refresh_pose_weights(bpmf_ctx* c);
 int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st);
 int external_move_ligand(bpmf_ctx* c, int lid, int n_moves, int k_max,
                          double sigma, hipStream_t st);
@@ -947,7 +951,8 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
     // units of P sweeps, each followed by the unit's moves; the network's
     // scratch is sized before any capture
     if (a->pose_move_every > 0) {
-      if ((rc = build_pose_tables(c))) return rc;
+      if ((rc = build_pose_tables(c)) || (rc = refresh_pose_weights(c)))
+        return rc;
       MlpBufs b;
       if (c->n_ptasks > 0 && (rc = mlp_scratch(c, c->n_ptasks, &b))) return rc;
     }
@@ -2171,7 +2176,8 @@ extern "C" int bpmf_proposal_setup(bpmf_ctx* c, int lid, const int* frame_atoms,
   const size_t o_p = A.add(kNParams * 4), o_g = A.add(kNParams * 4),
                o_m = A.add(kNParams * 4), o_v = A.add(kNParams * 4),
                o_acc = A.add(K * 8), o_try = A.add(K * 8), o_la = A.add(K * 8),
-               o_dev = A.add(sizeof(PropDev));
+               o_dev = A.add(sizeof(PropDev)),
+               o_wt = A.add((size_t)kTSize * sizeof(unsigned short));
   char* base = (char*)c->dalloc(A.total);
   if (!base) return fail(BPMF_E_NOMEM, "proposal allocation failed");
   PropDev pd{};
@@ -2205,6 +2211,8 @@ extern "C" int bpmf_proposal_setup(bpmf_ctx* c, int lid, const int* frame_atoms,
   h.adam_m = (float*)(base + o_m);
   h.adam_v = (float*)(base + o_v);
   h.d_prop = (PropDev*)(base + o_dev);
+  h.wt = (unsigned short*)(base + o_wt);
+  h.wt_dirty = true;
   h.prop = pd;
   h.adam_t = 0;
   h.has_prop = true;
@@ -2218,9 +2226,11 @@ extern "C" int bpmf_proposal_params(bpmf_ctx* c, int lid, float* out,
   if (rc) return rc;
   if ((rc = check_prop(c, lid))) return rc;
   LigHost& h = c->ligs[lid];
-  if (in)
+  if (in) {
     HIP_TRY(hipMemcpyAsync(h.params, in, kNParams * 4, hipMemcpyHostToDevice,
                            c->stream));
+    h.wt_dirty = true;
+  }
   if (out)
     HIP_TRY(hipMemcpyAsync(out, h.params, kNParams * 4, hipMemcpyDeviceToHost,
                            c->stream));
@@ -2288,6 +2298,7 @@ extern "C" int bpmf_proposal_train(bpmf_ctx* c, int lid, const float* dev_feats,
   LigHost& h = c->ligs[lid];
   MlpBufs b;
   if ((rc = mlp_scratch(c, batch, &b))) return rc;
+  if (steps > 0) h.wt_dirty = true;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   for (int s = 0; s < steps; ++s) {
     HIP_TRY(launch_gather_batch(dev_feats, dev_poses, N, batch, c->seed,
@@ -2312,11 +2323,9 @@ int build_pose_tables(bpmf_ctx* c) {
   std::vector<PropDev> props(std::max(nl, 1));
   std::vector<PoseTask> tasks;
   std::vector<MlpGroup> groups;
-  int off[bpmf_ctx::kWaveClasses], cnt[bpmf_ctx::kWaveClasses],
-      lds[bpmf_ctx::kWaveClasses];
+  int off[bpmf_ctx::kWaveClasses], cnt[bpmf_ctx::kWaveClasses];
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
     off[q] = (int)tasks.size();
-    lds[q] = 0;
     for (int l = 0; l < nl; ++l) {
       LigHost& h = c->ligs[l];
       if (!h.has_prop || wave_class(h.min_waves) != q) continue;
@@ -2328,12 +2337,9 @@ int build_pose_tables(bpmf_ctx* c) {
         tasks.push_back(PoseTask{l, r, row, 0});
       }
       for (int r = 0; r < h.dev.K; r += 16)
-        groups.push_back(MlpGroup{h.params, h.ptask0 + r,
+        groups.push_back(MlpGroup{h.params, h.wt, h.ptask0 + r,
                                   std::min(16, h.dev.K - r)});
       h.n_pgroups = (int)groups.size() - h.pgroup0;
-      const LigDev& L = h.dev;
-      lds[q] = std::max(lds[q], block_lds_bytes(h.min_waves, false, L.n, 0, 0,
-                                                0));
     }
     cnt[q] = (int)tasks.size() - off[q];
   }
@@ -2369,9 +2375,19 @@ int build_pose_tables(bpmf_ctx* c) {
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
     c->ptask_off[q] = off[q];
     c->ptask_n[q] = cnt[q];
-    c->ptask_lds[q] = lds[q];
   }
   c->pose_dirty = false;
+  return BPMF_OK;
+}
+
+// Refresh the bf16 weight copies that are stale (enqueued on the stream;
+// called outside graph capture, before the moves that read them).
+int refresh_pose_weights(bpmf_ctx* c) {
+  for (auto& h : c->ligs)
+    if (h.has_prop && h.wt_dirty) {
+      HIP_TRY(launch_weights_bf16(h.params, h.wt, c->stream));
+      h.wt_dirty = false;
+    }
   return BPMF_OK;
 }
 
@@ -2394,17 +2410,21 @@ int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st) {
   int rc = mlp_scratch(c, c->n_ptasks, &b);
   if (rc) return rc;
   HIP_TRY(launch_pose_features_tasks(c->d_ligs, c->d_props, c->d_ptasks + t0,
-                                     nt, b.bf, b.bp, st));
+                                     nt, b.bf, st));
   HIP_TRY(launch_mlp_forward_groups(c->d_pgroups + g0, ng, b.bf, b.out, st));
+  // one launch at the widest class in the range: the move is latency-bound
+  // (one workgroup per replica), and narrower ligands run with idle
+  // wavefronts rather than in a launch of their own
+  int qmax = 0;
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
-    // this class's tasks within [t0, t0 + nt)
     const int a = std::max(t0, c->ptask_off[q]);
     const int e = std::min(t0 + nt, c->ptask_off[q] + c->ptask_n[q]);
-    if (e <= a) continue;
-    HIP_TRY(launch_pose_move(c->grid, c->d_ligs, c->d_props, c->d_ptasks + a,
-                             e - a, b.out, 1 << q, c->ptask_lds[q], c->seed,
-                             st));
+    if (e > a) qmax = q;
   }
+  HIP_TRY(launch_pose_move(c->grid, c->d_ligs, c->d_props, c->d_ptasks + t0,
+                           nt, b.out, 1 << qmax,
+                           block_lds_bytes(1 << qmax, false, 0, 0, 0, 0),
+                           c->seed, st));
   return BPMF_OK;
 }
 }  // namespace
@@ -2414,7 +2434,7 @@ extern "C" int bpmf_pose_move(bpmf_ctx* c, int lid, int rounds) {
   if (rc) return rc;
   if (rounds < 0) return fail(BPMF_E_INVAL, "negative rounds");
   if (lid != -1 && (rc = check_prop(c, lid))) return rc;
-  if ((rc = build_pose_tables(c))) return rc;
+  if ((rc = build_pose_tables(c)) || (rc = refresh_pose_weights(c))) return rc;
   for (int r = 0; r < rounds; ++r)
     if ((rc = pose_move_batch(c, lid, c->stream))) return rc;
   return BPMF_OK;

@@ -292,22 +292,27 @@ __device__ __forceinline__ float3 scale3(float s, float3 a) {
 }
 
 // Per-atom force accumulators in LDS, in 32-bit fixed point (2^-16
-// kJ/mol/A per unit): every bonded-term thread adds its contribution to
-// each of its atoms with an integer LDS atomic.  Integer addition is
+// kJ/mol/A per unit, contributions rounded toward zero): every bonded-term
+// thread adds its contribution to each of its atoms with an integer LDS
+// atomic.  Integer addition is
 // associative, so the sums do not depend on the order in which threads
-// arrive and results stay bitwise reproducible.  Quantisation is 7.6e-6
+// arrive and results stay bitwise reproducible.  Quantisation is 1.5e-5
 // kJ/mol/A per contribution; a contribution is clamped to +-32767 kJ/mol/A
 // (a bonded force that large only arises on a diverging trajectory, which
 // the exact energy rejects; leapfrog with any deterministic force keeps HMC
-// exact).
+// exact).  The term functions hand over contributions already in units of
+// 2^-16 (their force factor carries the 2^16, and scaling by a power of two
+// commutes with rounding, so the units are exact); a NaN contribution
+// becomes the lower clamp (its energy is NaN too, so the move is rejected).
 constexpr float kFix = 65536.0f;          // 2^16
 constexpr float kFixInv = 1.0f / 65536.0f;
 constexpr float kFixMax = 32767.0f;
+constexpr float kFixLim = kFixMax * kFix;  // 2^31 - 2^16, exact in float
 
-__device__ __forceinline__ unsigned int to_fix(float f) {
-  // NaN becomes 0; the energy still carries the NaN
-  f = (f == f) ? fminf(fmaxf(f, -kFixMax), kFixMax) : 0.f;
-  return (unsigned int)__float2int_rn(f * kFix);
+// rounds toward zero (one conversion instruction; the clamp keeps it in
+// range)
+__device__ __forceinline__ unsigned int to_fix_units(float f) {
+  return (unsigned int)(int)fminf(fmaxf(f, -kFixLim), kFixLim);
 }
 
 __device__ __forceinline__ float from_fix(unsigned int a) {
@@ -316,10 +321,11 @@ __device__ __forceinline__ float from_fix(unsigned int a) {
 
 struct Slots {
   unsigned int* acc;  // n x 3
+  // f: force contribution in units of 2^-16 kJ/mol/A
   __device__ __forceinline__ void put(int atom, float3 f) const {
-    atomicAdd(&acc[3 * atom], to_fix(f.x));
-    atomicAdd(&acc[3 * atom + 1], to_fix(f.y));
-    atomicAdd(&acc[3 * atom + 2], to_fix(f.z));
+    atomicAdd(&acc[3 * atom], to_fix_units(f.x));
+    atomicAdd(&acc[3 * atom + 1], to_fix_units(f.y));
+    atomicAdd(&acc[3 * atom + 2], to_fix_units(f.z));
   }
 };
 
@@ -329,9 +335,17 @@ struct Slots {
 // would wait on memory.  Accesses through this view are global ones.
 #define BPMF_GMEM(T, p) ((T __attribute__((address_space(1)))*)(p))
 
-// hardware reciprocal (1 ulp), for the bonded-term geometry
+// hardware reciprocal, square root and reciprocal square root (1 ulp, no
+// rescaling of denormal arguments: the bonded-term geometry never sees
+// one), for the bonded-term geometry
 __device__ __forceinline__ float rcp(float x) {
   return __builtin_amdgcn_rcpf(x);
+}
+__device__ __forceinline__ float hsqrt(float x) {
+  return __builtin_amdgcn_sqrtf(x);
+}
+__device__ __forceinline__ float hrsq(float x) {
+  return __builtin_amdgcn_rsqf(x);
 }
 
 __device__ __forceinline__ int atom_of(int p) { return p; }
@@ -342,10 +356,10 @@ template <bool FORCES>
 __device__ __forceinline__ float bond_term(const float4* pos, int2 ij,
                                            float2 par, const Slots& sl) {
   const float3 d = sub(f3(pos[atom_of(ij.x)]), f3(pos[atom_of(ij.y)]));
-  const float r = sqrtf(dot(d, d));
+  const float r = hsqrt(dot(d, d));
   const float dr = r - par.y;
   if (FORCES) {
-    const float f = -2.0f * par.x * dr * rcp(r);
+    const float f = -2.0f * par.x * dr * rcp(r) * kFix;
     sl.put(slot_of(ij.x), scale3(f, d));
     sl.put(slot_of(ij.y), scale3(-f, d));
   }
@@ -360,17 +374,17 @@ __device__ __forceinline__ float angle_term(const float4* pos, int4 ijk,
   const float3 a = sub(f3(pos[atom_of(ijk.x)]), xj);
   const float3 b = sub(f3(pos[atom_of(ijk.z)]), xj);
   const float3 c = cross(a, b);
-  const float s = sqrtf(dot(c, c)), co = dot(a, b);
+  const float s = hsqrt(dot(c, c)), co = dot(a, b);
   const float th = atan2f(s, co);
   const float dth = th - par.y;
   if (FORCES) {
-    const float la = sqrtf(dot(a, a)), lb = sqrtf(dot(b, b));
+    const float la = hsqrt(dot(a, a)), lb = hsqrt(dot(b, b));
     const float dE = 2.0f * par.x * dth;
     const float ila = rcp(la), ilb = rcp(lb);
     const float cth = co * ila * ilb, isth = la * lb * rcp(s);
     const float3 ah = scale3(ila, a), bh = scale3(ilb, b);
     // d theta / d xi = (cos a^ - b^) / (|a| sin), d theta / d xk likewise
-    const float ci = dE * isth * ila, ck = dE * isth * ilb;
+    const float ci = dE * isth * ila * kFix, ck = dE * isth * ilb * kFix;
     const float3 fi = make_float3(-ci * (cth * ah.x - bh.x),
                                   -ci * (cth * ah.y - bh.y),
                                   -ci * (cth * ah.z - bh.z));
@@ -398,12 +412,12 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
   const float3 xk = f3(pos[atom_of(ijkl.z)]), xl = f3(pos[atom_of(ijkl.w)]);
   const float3 b1 = sub(xj, xi), b2 = sub(xk, xj), b3 = sub(xl, xk);
   const float3 n1 = cross(b1, b2), n2 = cross(b2, b3);
-  const float lb2 = sqrtf(dot(b2, b2));
+  const float lb2 = hsqrt(dot(b2, b2));
   const float xx = dot(n1, n2), yy = lb2 * dot(b1, n2);
   // par: V/2, n, cos gamma, sin gamma; integer multiplicity in the sign-free
   // upper bits is not needed: n is an integer 1..6 (checked at setup)
   const int mult = (int)par.y;
-  const float ir = rsqrtf(xx * xx + yy * yy);
+  const float ir = hrsq(xx * xx + yy * yy);
   const float c1 = xx * ir, s1 = yy * ir;
   float cn = c1, sn = s1;
   for (int q = 1; q < mult; ++q) {
@@ -429,10 +443,11 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
     const float3 gk = make_float3(-gl.x - p12 * n1.x - p23 * n2.x,
                                   -gl.y - p12 * n1.y - p23 * n2.y,
                                   -gl.z - p12 * n1.z - p23 * n2.z);
-    sl.put(slot_of(ijkl.x), scale3(-dE, gi));
-    sl.put(slot_of(ijkl.y), scale3(-dE, gj));
-    sl.put(slot_of(ijkl.z), scale3(-dE, gk));
-    sl.put(slot_of(ijkl.w), scale3(-dE, gl));
+    const float dEs = -dE * kFix;
+    sl.put(slot_of(ijkl.x), scale3(dEs, gi));
+    sl.put(slot_of(ijkl.y), scale3(dEs, gj));
+    sl.put(slot_of(ijkl.z), scale3(dEs, gk));
+    sl.put(slot_of(ijkl.w), scale3(dEs, gl));
   }
   return par.x * (1.0f + cs);
 }

@@ -23,6 +23,16 @@ constexpr int kOffW3 = kOffB2 + kNHid;
 constexpr int kOffB3 = kOffW3 + kNHid * kNOut;
 constexpr int kNParams = kOffB3 + kNOut;
 
+// bf16 copy of the weights for the pose moves' forward pass, each matrix
+// transposed ([out][in]) with rows padded so that a lane's eight
+// consecutive k values are one 16-byte load and every 16-column output tile
+// is in range: W1^T 256 x 32, W2^T 256 x 256, W3^T 112 x 256 (padding 0)
+constexpr int kT1Ld = 32, kT2Ld = kNHid, kT3Ld = kNHid, kT3Rows = 112;
+constexpr int kTOff1 = 0;
+constexpr int kTOff2 = kTOff1 + kNHid * kT1Ld;
+constexpr int kTOff3 = kTOff2 + kNHid * kT2Ld;
+constexpr int kTSize = kTOff3 + kT3Rows * kT3Ld;
+
 enum Purpose2 : uint32_t { kPose = 4, kBatch = 5 };
 
 // Device state of one ligand's proposal.
@@ -45,7 +55,8 @@ struct PoseTask {
 // One workgroup of a batched forward pass: rows [row0, row0 + rows) (at
 // most 16) through the network whose parameters start at P.
 struct MlpGroup {
-  const float* P;
+  const float* P;             // fp32 parameters (the biases are read here)
+  const unsigned short* WT;   // bf16 transposed weights (kTSize)
   int row0, rows;
 };
 
@@ -85,16 +96,20 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n,
 hipError_t launch_pose_features(const LigDev* lig, const PropDev* prop,
                                 const float* xs, int64_t N, float* feats,
                                 float* poses, hipStream_t st);
-// features of the current configurations of the n tasks (rows t.row)
+// features (not poses) of the current configurations of the n tasks (rows
+// t.row)
 hipError_t launch_pose_features_tasks(const LigDev* ligs,
                                       const PropDev* props,
                                       const PoseTask* tasks, int n,
-                                      float* feats, float* poses,
-                                      hipStream_t st);
+                                      float* feats, hipStream_t st);
 // the network for several groups of rows, each with its own parameters
+// (bf16 transposed weights; the outputs equal launch_mlp_forward's)
 hipError_t launch_mlp_forward_groups(const MlpGroup* groups, int n_groups,
                                      const float* X, float* out,
                                      hipStream_t st);
+// the bf16 transposed copy of the weights of parameter vector P
+hipError_t launch_weights_bf16(const float* P, unsigned short* WT,
+                               hipStream_t st);
 // one pose move of each of the n tasks (all of `waves` wavefronts; props
 // indexed by ligand table index, out by task row)
 hipError_t launch_pose_move(const GridDev& g, const LigDev* ligs,

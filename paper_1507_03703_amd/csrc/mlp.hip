@@ -185,7 +185,7 @@ __device__ __forceinline__ void dense_rows(
       if (HIDDEN) {
         const float h = silu(v);
         Hn[r][n] = bf16_bits(h);
-        if (m < B && Z) {
+        if (m < B) {
           Z[(int64_t)m * N + n] = v;
           H[(int64_t)m * N + n] = h;
         }
@@ -196,24 +196,115 @@ __device__ __forceinline__ void dense_rows(
   }
 }
 
-// groups (may be null): workgroup b runs rows [row0, row0 + rows) of
-// groups[b] with that group's parameters (several networks in one launch);
-// else workgroup b runs rows 16 b.. of the B rows with parameters P.  Z1,
-// H1, Z2, H2 may be null (the hidden activations are then not stored).
+// dense_rows with the weights from their bf16 transposed copy (row n of WT
+// holds column n of W, KLD elements, zero past KIN and past N): a lane's
+// eight k values of a tile are one 16-byte load.  The operands, the k order
+// and the epilogue are dense_rows', so the results are the same bits.
+template <int KIN, int KLD, int N, bool HIDDEN>
+__device__ __forceinline__ void dense_rows_t(
+    const unsigned short (*A)[kFLd], const unsigned short* __restrict__ WT,
+    const float* __restrict__ bias, int row0, int B, float* __restrict__ H,
+    unsigned short (*Hn)[kFLd], int lane, int wv) {
+  constexpr int kTiles = (N + 15) / 16;
+  constexpr int kTPW = (kTiles + kFWaves - 1) / kFWaves;
+  typedef const bf16x8 __attribute__((address_space(1))) gbf;
+  const int kg = (lane >> 4) * 8;
+  f32x4 acc[kTPW];
+#pragma unroll
+  for (int i = 0; i < kTPW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int k0 = 0; k0 < KIN; k0 += kKStep) {
+    bf16x8 b[kTPW];
+#pragma unroll
+    for (int i = 0; i < kTPW; ++i) {
+      const int n = (wv + kFWaves * i) * 16 + (lane & 15);
+      if (wv + kFWaves * i < kTiles)  // uniform over the wave
+        b[i] = *(gbf*)(WT + (int64_t)n * KLD + k0 + kg);
+    }
+    bf16x8 a;
+    if (k0 + kg < KIN) {
+      a = *reinterpret_cast<const bf16x8*>(&A[lane & 15][k0 + kg]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[e] = __builtin_bit_cast(__bf16,
+                                                           (unsigned short)0);
+    }
+#pragma unroll
+    for (int i = 0; i < kTPW; ++i)
+      if (wv + kFWaves * i < kTiles)
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[i], acc[i], 0,
+                                                         0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < kTPW; ++i) {
+    const int n = (wv + kFWaves * i) * 16 + (lane & 15);
+    if (n >= N) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = (lane >> 4) * 4 + q, m = row0 + r;
+      const float v = acc[i][q] + bias[n];
+      if (HIDDEN)
+        Hn[r][n] = bf16_bits(silu(v));
+      else if (m < B)
+        H[(int64_t)m * N + n] = v;
+    }
+  }
+}
+
+// the network for groups of up to 16 rows, group b with its own parameters
+// (bf16 transposed weights), outputs only
+__global__ __launch_bounds__(kFWaves * 64) void k_mlp_forward_t(
+    const MlpGroup* __restrict__ groups, const float* __restrict__ X,
+    float* __restrict__ out) {
+  __shared__ __align__(16) unsigned short S[2][kFRows][kFLd];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const MlpGroup gr = groups[blockIdx.x];
+  const int row0 = gr.row0, B = gr.row0 + gr.rows;
+  for (int e = tid; e < kFRows * kNFeat; e += kFWaves * 64) {
+    const int r = e / kNFeat, k = e - r * kNFeat, m = row0 + r;
+    S[0][r][k] = bf16_bits(m < B ? X[(int64_t)m * kNFeat + k] : 0.f);
+  }
+  __syncthreads();
+  dense_rows_t<kNFeat, kT1Ld, kNHid, true>(S[0], gr.WT + kTOff1,
+                                           gr.P + kOffB1, row0, B, nullptr,
+                                           S[1], lane, wv);
+  __syncthreads();
+  dense_rows_t<kNHid, kT2Ld, kNHid, true>(S[1], gr.WT + kTOff2,
+                                          gr.P + kOffB2, row0, B, nullptr,
+                                          S[0], lane, wv);
+  __syncthreads();
+  dense_rows_t<kNHid, kT3Ld, kNOut, false>(S[0], gr.WT + kTOff3,
+                                           gr.P + kOffB3, row0, B, out,
+                                           nullptr, lane, wv);
+}
+
+// WT from the fp32 parameters: element (n, k) of each transposed matrix is
+// the bf16 rounding of W[k][n] (0 in the padding)
+__global__ __launch_bounds__(256) void k_weights_bf16(
+    const float* __restrict__ P, unsigned short* __restrict__ WT) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kTSize) return;
+  int off, ld, kin, nout;
+  const float* W;
+  if (i < kTOff2) {
+    off = kTOff1; ld = kT1Ld; kin = kNFeat; nout = kNHid; W = P + kOffW1;
+  } else if (i < kTOff3) {
+    off = kTOff2; ld = kT2Ld; kin = kNHid; nout = kNHid; W = P + kOffW2;
+  } else {
+    off = kTOff3; ld = kT3Ld; kin = kNHid; nout = kNOut; W = P + kOffW3;
+  }
+  const int n = (i - off) / ld, k = (i - off) - n * ld;
+  WT[i] = (n < nout && k < kin) ? bf16_bits(W[(int64_t)k * nout + n])
+                                : (unsigned short)0;
+}
+
 __global__ __launch_bounds__(kFWaves * 64) void k_mlp_forward(
     const float* __restrict__ P, const float* __restrict__ X, int B,
     float* __restrict__ Z1, float* __restrict__ H1, float* __restrict__ Z2,
-    float* __restrict__ H2, float* __restrict__ out,
-    const MlpGroup* __restrict__ groups) {
+    float* __restrict__ H2, float* __restrict__ out) {
   __shared__ __align__(16) unsigned short S[2][kFRows][kFLd];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int row0 = blockIdx.x * kFRows;
-  if (groups) {
-    const MlpGroup gr = groups[blockIdx.x];
-    P = gr.P;
-    row0 = gr.row0;
-    B = gr.row0 + gr.rows;
-  }
+  const int row0 = blockIdx.x * kFRows;
   for (int e = tid; e < kFRows * kNFeat; e += kFWaves * 64) {
     const int r = e / kNFeat, k = e - r * kNFeat, m = row0 + r;
     S[0][r][k] = bf16_bits(m < B ? X[(int64_t)m * kNFeat + k] : 0.f);
@@ -492,18 +583,29 @@ __global__ __launch_bounds__(128) void k_pose_features(
                     feats + i * kNFeat);
 }
 
-// one thread per task: the current configuration of replica t.r of ligand
-// t.lig, into row t.row
-__global__ __launch_bounds__(128) void k_pose_features_tasks(
+// features only (the move recomputes the pose itself): one thread per
+// (task, conditioning torsion slot), the current configuration of replica
+// t.r of ligand t.lig into row t.row
+__global__ __launch_bounds__(256) void k_pose_features_tasks(
     const LigDev* __restrict__ ligs, const PropDev* __restrict__ props,
-    const PoseTask* __restrict__ tasks, int n, float* __restrict__ feats,
-    float* __restrict__ poses) {
+    const PoseTask* __restrict__ tasks, int n, float* __restrict__ feats) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const PoseTask t = tasks[i];
+  const int task = i >> 3, q = i & 7;
+  if (task >= n) return;
+  const PoseTask t = tasks[task];
   const LigDev& L = ligs[t.lig];
-  pose_features_one(L, props[t.lig], L.x + (size_t)t.r * L.n * 3,
-                    poses + (size_t)t.row * 6, feats + (size_t)t.row * kNFeat);
+  const PropDev& P = props[t.lig];
+  float* fo = feats + (size_t)t.row * kNFeat + 2 * q;
+  if (q < P.n_cond) {
+    const float phi = dihedral_angle(L.x + (size_t)t.r * L.n * 3, P.cond[q]);
+    float s, cs;
+    sincosf(phi, &s, &cs);
+    fo[0] = s;
+    fo[1] = cs;
+  } else {
+    fo[0] = 0.f;
+    fo[1] = 0.f;
+  }
 }
 
 // wavefront maximum of a double (DPP tree as in wave_sum)
@@ -766,8 +868,7 @@ hipError_t launch_mlp_forward(const float* P, const float* X, int B,
                               float* out, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_forward, dim3((B + kFRows - 1) / kFRows),
-                     dim3(kFWaves * 64), 0, st, P, X, B, Z1, H1, Z2, H2, out,
-                     (const MlpGroup*)nullptr);
+                     dim3(kFWaves * 64), 0, st, P, X, B, Z1, H1, Z2, H2, out);
   return hipGetLastError();
 }
 
@@ -775,10 +876,15 @@ hipError_t launch_mlp_forward_groups(const MlpGroup* groups, int n_groups,
                                      const float* X, float* out,
                                      hipStream_t st) {
   if (n_groups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_forward, dim3(n_groups), dim3(kFWaves * 64), 0, st,
-                     (const float*)nullptr, X, 0, (float*)nullptr,
-                     (float*)nullptr, (float*)nullptr, (float*)nullptr, out,
-                     groups);
+  hipLaunchKernelGGL(k_mlp_forward_t, dim3(n_groups), dim3(kFWaves * 64), 0,
+                     st, groups, X, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights_bf16(const float* P, unsigned short* WT,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_weights_bf16, dim3((kTSize + 255) / 256), dim3(256), 0,
+                     st, P, WT);
   return hipGetLastError();
 }
 
@@ -816,11 +922,11 @@ hipError_t launch_pose_features(const LigDev* lig, const PropDev* prop,
 hipError_t launch_pose_features_tasks(const LigDev* ligs,
                                       const PropDev* props,
                                       const PoseTask* tasks, int n,
-                                      float* feats, float* poses,
-                                      hipStream_t st) {
+                                      float* feats, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pose_features_tasks, dim3((n + 127) / 128), dim3(128),
-                     0, st, ligs, props, tasks, n, feats, poses);
+  static_assert(kNFeat == 16, "eight torsion slots of sin, cos");
+  hipLaunchKernelGGL(k_pose_features_tasks, dim3((8 * n + 255) / 256),
+                     dim3(256), 0, st, ligs, props, tasks, n, feats);
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import List, Optional
 
 import numpy as np
@@ -441,6 +442,16 @@ def make_system(config: int, n_ligands: Optional[int] = None,
     edge = (n - 1) * h
     if with_grid:
         key = (config, len(counts), str(grid_device))
+        # optional on-disk cache of generated grids (a directory named by
+        # BPMF_GRID_CACHE): the generation is deterministic, so a cached
+        # grid equals a fresh one of the same config, ligand count and
+        # summing device
+        cdir = os.environ.get("BPMF_GRID_CACHE")
+        cfile = (os.path.join(cdir, f"grid_c{config}_l{len(counts)}_"
+                              f"{'cpu' if grid_device is None else str(grid_device).replace(':', '')}"
+                              f"_v{C_RELEASE}.npy") if cdir else None)
+        if key not in _GRID_CACHE and cfile and os.path.exists(cfile):
+            _GRID_CACHE[key] = np.load(cfile)
         if key not in _GRID_CACHE:
             rrng = np.random.default_rng([gen_seed, 7])
             avoid = np.concatenate([l.x0[0] for l in ligs], axis=0)
@@ -448,6 +459,10 @@ def make_system(config: int, n_ligands: Optional[int] = None,
                                              0.3 * edge, avoid_xyz=avoid)
             _GRID_CACHE[key] = grids_from_points(pts, q, sig, eps, n, h,
                                                  device=grid_device)
+            if cfile:
+                os.makedirs(cdir, exist_ok=True)
+                np.save(cfile + ".tmp.npy", _GRID_CACHE[key])
+                os.replace(cfile + ".tmp.npy", cfile)
         nodes = _GRID_CACHE[key].copy()
     else:
         nodes = np.zeros((0, 0, 0, 3), np.float32)
