@@ -263,14 +263,14 @@ def train_proposals(pkg, torch, system, sweeps=31250, burn=400, every=5,
 
 def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
                  tune=False, waves=None, proposals=None, pose_every=5,
-                 kernel_sweeps=256):
+                 kernel_sweeps=512):
     """Set up every ligand of `system`, run `warmup` + `steps` timed steps
     of the hot path and return the measurements.  proposals: per-ligand
     network parameters; the sweeps then carry a learned pose move of every
     replica every `pose_every` sweeps.  After the timed steps,
-    `kernel_sweeps` plain sweeps (plain launches, every one bracketed by HIP
-    events on the library's stream) give the sweep kernel's own mean launch
-    time for the roofline."""
+    `kernel_sweeps` plain sweeps (graph replays of 64 sweeps, each replay
+    bracketed by HIP events on the library's stream) give the sweep
+    kernel's own mean launch time for the roofline."""
     import numpy as np
     g = system.grid
     ligs = system.ligands
@@ -345,9 +345,11 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
                 "pose_acceptance_coupled_states": float(
                     sum(p["acc"][-1] for p in ps) /
                     max(sum(p["tries"][-1] for p in ps), 1))}
-    # the sweep kernel alone: plain launches, each timed
-    ctx.set_graph(0)
-    ctx.hmc_sweep(8, L, exchange_every=1)
+    # the sweep kernel alone: plain sweeps replayed from captured graphs of
+    # 64 (as the library runs them), each replay timed and counted as 64
+    # sweep launches
+    ctx.set_graph(64)
+    ctx.hmc_sweep(64, L, exchange_every=1)
     torch.cuda.synchronize()
     ctx.set_timing(True, every=1)
     ctx.hmc_sweep(kernel_sweeps, L, exchange_every=1)

@@ -504,6 +504,50 @@ extern "C" int bpmf_grid_upload(bpmf_ctx* c, const bpmf_grid_desc* d,
   return BPMF_OK;
 }
 
+// Balanced deal of a ligand's bonded chunks (see sched_row) to the
+// wavefronts of each launch width: chunks longest first, each to the
+// wavefront with the least work so far (ties: the lower one), the
+// wavefronts that hold atoms starting with their grid work.  The costs are the wave64 instruction counts of one
+// chunk of each kind in the sweep kernel (roughly: torsion 175, angle 135,
+// bond 45, an atom wavefront's grid work 250).  Each wavefront takes its
+// chunks in kind order.
+static std::vector<unsigned short> bonded_schedule(int n, int nb, int na,
+                                                   int nt) {
+  const int ntc = (nt + kWave - 1) / kWave, nac = (na + kWave - 1) / kWave;
+  const int nch = bonded_chunks(nb, na, nt), row = sched_row(nb, na, nt);
+  const int atom_waves = (n + kWave - 1) / kWave;
+  std::vector<unsigned short> out(4 * (size_t)row, 0);
+  auto cost = [&](int ch) { return ch < ntc ? 175 : ch < ntc + nac ? 135 : 45; };
+  std::vector<int> order(nch);
+  for (int ch = 0; ch < nch; ++ch) order[ch] = ch;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return cost(a) > cost(b); });
+  for (int q = 0; q < 4; ++q) {
+    const int W = 1 << q;
+    const int nbw = W;
+    std::vector<int> load(nbw, 0);
+    std::vector<std::vector<int>> mine(nbw);
+    for (int w = 0; w < nbw && w < atom_waves; ++w) load[w] = 250;
+    for (int ch : order) {
+      int best = 0;
+      for (int w = 1; w < nbw; ++w)
+        if (load[w] < load[best]) best = w;
+      load[best] += cost(ch);
+      mine[best].push_back(ch);
+    }
+    unsigned short* r = out.data() + (size_t)q * row;
+    int j = 0;
+    for (int w = 0; w < 9; ++w) {
+      r[w] = (unsigned short)j;
+      if (w < nbw) {
+        std::sort(mine[w].begin(), mine[w].end());
+        for (int ch : mine[w]) r[9 + j++] = (unsigned short)ch;
+      }
+    }
+  }
+  return out;
+}
+
 static bool supported_channels(int C) { return C == 3 || C == 5; }
 
 // ============================================================================
@@ -647,7 +691,9 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_scale = A.add((size_t)n * C * 4), o_bij = A.add(nb * 8),
                o_bpar = A.add(nb * 8), o_aijk = A.add(na * 16),
                o_apar = A.add(na * 8), o_tijkl = A.add(nt * 16),
-               o_tpar = A.add(nt * 16), o_beta = A.add(K * 8),
+               o_tpar = A.add(nt * 16),
+               o_sched = A.add((size_t)4 * sched_row(nb, na, nt) * 2),
+               o_beta = A.add(K * 8),
                o_Tf = A.add(K * 4), o_dt = A.add(K * 4),
                o_wf = A.add((size_t)K * C * 4), o_wd = A.add((size_t)K * C * 8),
                o_x = A.add((size_t)K * n * 12), o_comps = A.add((size_t)K * C1 * 8),
@@ -692,6 +738,8 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   chain(up(o_apar, apar.data(), na * 8));
   chain(up(o_tijkl, tijkl.data(), nt * 16));
   chain(up(o_tpar, tpar.data(), nt * 16));
+  const std::vector<unsigned short> sched = bonded_schedule(n, nb, na, nt);
+  chain(up(o_sched, sched.data(), sched.size() * 2));
   chain(up(o_beta, beta.data(), K * 8));
   chain(up(o_Tf, Tf.data(), K * 4));
   chain(up(o_dt, dtf.data(), K * 4));
@@ -735,6 +783,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.apar = (const float2*)(base + o_apar);
   L.tijkl = (const int4*)(base + o_tijkl);
   L.tpar = (const float4*)(base + o_tpar);
+  L.bsched = (const unsigned short*)(base + o_sched);
   L.beta = (const double*)(base + o_beta);
   L.Tf = (const float*)(base + o_Tf);
   L.dtf = (const float*)(base + o_dt);

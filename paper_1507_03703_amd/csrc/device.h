@@ -456,13 +456,16 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
 // one full evaluation of a configuration by one workgroup of W wavefronts
 // ----------------------------------------------------------------------------
 // Thread t owns atom t (n <= 64 W); the A = ceil(n / 64) wavefronts that
-// hold atoms are the atom waves.  Bonded terms run on bonded_first_wave(..)
-// onwards: with four or more wavefronts and at least as many spare as atom
-// waves, only the spare ones take bonded terms, so that the atom waves'
-// restraint and grid interpolation run beside them; otherwise every thread
-// takes terms.  The term index is segmented (torsions, angles, bonds) with
-// every segment starting on a wavefront boundary, so a wavefront never
-// diverges over term kinds.  The owners' grid gathers are issued before the
+// hold atoms are the atom waves.  Bonded terms come in chunks of 64 of one
+// kind, so a wavefront never diverges over term kinds, and the ligand's
+// schedule deals the chunks to the wavefronts so that their work is
+// balanced (each wavefront of a workgroup runs on its own SIMD, so the
+// busiest one sets the pace of the step); an atom wave takes chunks only
+// once the others carry as much as its grid work.  With four or more
+// wavefronts and at least as many spare as atom waves
+// (bonded_first_wave(..) > 0) the atom waves issue their gathers after the
+// first barrier, so that the spare waves start their chunks without waiting
+// for the address work; otherwise the owners' grid gathers are issued before the
 // first barrier so that their latency overlaps the bonded pass (a workgroup
 // barrier on gfx950 waits on LDS traffic only, not on outstanding global
 // loads).
@@ -480,6 +483,7 @@ struct Shared {
   const float2* apar;
   const int4* tijkl;
   const float4* tpar;
+  const unsigned short* sched;  // this launch width's schedule row
 };
 
 // Copy a ligand's constant topology into LDS (all threads; caller syncs).
@@ -495,6 +499,7 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
   float2* apar = reinterpret_cast<float2*>(aijk + L.na);
   int2* bij = reinterpret_cast<int2*>(apar + L.na);
   float2* bpar = reinterpret_cast<float2*>(bij + L.nb);
+  unsigned short* sched = reinterpret_cast<unsigned short*>(bpar + L.nb);
   // global (not flat) loads: they cannot alias the LDS stores, so several
   // stay in flight at once
   typedef float f4v __attribute__((ext_vector_type(4)));
@@ -523,6 +528,13 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
     bij[i] = make_int2(q.x, q.y);
     bpar[i] = make_float2(p.x, p.y);
   }
+  // the schedule row of this launch width (nthreads / 64 wavefronts)
+  const int row = sched_row(L.nb, L.na, L.nt);
+  const int q = nthreads <= kWave ? 0 : nthreads <= 2 * kWave ? 1
+                : nthreads <= 4 * kWave ? 2 : 3;
+  for (int i = tid; i < row; i += nthreads)
+    sched[i] = BPMF_GMEM(const unsigned short, L.bsched)[q * row + i];
+  sh.sched = sched;
   sh.bij = bij;
   sh.bpar = bpar;
   sh.aijk = aijk;
@@ -556,7 +568,9 @@ __device__ __forceinline__ void restraint_force(float fr, float m, float cx,
   ge[2] += fr * m * cz;
 }
 
-// first wavefront that takes bonded terms (see eval_block)
+// number of leading wavefronts (the atom waves) that issue their grid
+// gathers after the first barrier, 0 when they issue them before it (see
+// eval_block)
 __device__ __forceinline__ int bonded_first_wave(int waves, int atom_waves) {
   return (waves >= 4 && waves >= 2 * atom_waves) ? atom_waves : 0;
 }
@@ -602,27 +616,29 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   block_sync();
   if (wave_has_atoms && first != 0) grid_fetch<C>(g, x[0], x[1], x[2], cn);
 
-  // bonded terms over the wave-aligned segmented index
+  // bonded terms: the chunks the ligand's schedule gives this wavefront
   float eb = 0.f, ea = 0.f, et = 0.f;
-  {
-    const int tb = tid - kWave * first;
-    const int nthr = kWave * (W - first);
-    const int ntp = (L.nt + kWave - 1) & ~(kWave - 1);
-    const int nap = (L.na + kWave - 1) & ~(kWave - 1);
-    const int n_index = ntp + nap + L.nb;
-    if (BONDED && tb >= 0) {
-      for (int u = tb; u < n_index; u += nthr) {
-        if (u < ntp) {
-          if (u < L.nt)
-            et += torsion_term<FORCES>(sh.pos, sh.tijkl[u], sh.tpar[u],
+  if (BONDED) {
+    const int bw = __builtin_amdgcn_readfirstlane(wv);
+    {
+      const int ntc = (L.nt + kWave - 1) / kWave;
+      const int nac = (L.na + kWave - 1) / kWave;
+      const int j0 = sh.sched[bw], j1 = sh.sched[bw + 1];
+      for (int j = j0; j < j1; ++j) {
+        const int ch = sh.sched[9 + j];
+        if (ch < ntc) {
+          const int t = ch * kWave + lane;
+          if (t < L.nt)
+            et += torsion_term<FORCES>(sh.pos, sh.tijkl[t], sh.tpar[t],
                                        sh.sl);
-        } else if (u < ntp + nap) {
-          const int t = u - ntp;
+        } else if (ch < ntc + nac) {
+          const int t = (ch - ntc) * kWave + lane;
           if (t < L.na)
             ea += angle_term<FORCES>(sh.pos, sh.aijk[t], sh.apar[t], sh.sl);
         } else {
-          const int t = u - ntp - nap;
-          eb += bond_term<FORCES>(sh.pos, sh.bij[t], sh.bpar[t], sh.sl);
+          const int t = (ch - ntc - nac) * kWave + lane;
+          if (t < L.nb)
+            eb += bond_term<FORCES>(sh.pos, sh.bij[t], sh.bpar[t], sh.sl);
         }
       }
     }
@@ -725,19 +741,24 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
     // per-wave sums in double, then a fixed-order sum over the waves.
     // LEAN: only the bonded total (in terms[0]) and the grid sums; the
     // extras are not reduced (their terms are 0)
+    // a wavefront without bonded terms (or without atoms) contributes exact
+    // zeros to those sums: it skips them (wave-uniform branches)
+    const bool wave_bonded = BONDED && sh.sched[wv + 1] > sh.sched[wv];
     double v[6 + C];
-    if (LEAN) {
-      v[0] = wave_sum((double)eb + (double)ea + (double)et);
-      v[1] = 0.0;
-      v[2] = 0.0;
-    } else {
-      v[0] = wave_sum((double)eb);
-      v[1] = wave_sum((double)ea);
-      v[2] = wave_sum((double)et);
+    v[0] = v[1] = v[2] = 0.0;
+    if (wave_bonded) {
+      if (LEAN) {
+        v[0] = wave_sum((double)eb + (double)ea + (double)et);
+      } else {
+        v[0] = wave_sum((double)eb);
+        v[1] = wave_sum((double)ea);
+        v[2] = wave_sum((double)et);
+      }
     }
     v[3] = 0.0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) v[4 + c] = wave_sum((double)psi[c]);
+    for (int c = 0; c < C; ++c)
+      v[4 + c] = wave_has_atoms ? wave_sum((double)psi[c]) : 0.0;
     v[4 + C] = LEAN ? 0.0 : wave_sum((double)ex0);
     v[5 + C] = LEAN ? 0.0 : wave_sum((double)ex1);
     if (lane == 0) {

@@ -16,13 +16,29 @@ __host__ __device__ inline int acc_lds_bytes(int n) {
   return (12 * n + 15) & ~15;
 }
 
+// Bonded terms are taken in chunks of 64 terms of one kind (a wavefront
+// takes a chunk in one pass): torsion chunks, then angle chunks, then bond
+// chunks.  The schedule of a ligand gives, for each launch width (1, 2, 4,
+// 8 wavefronts), the chunks of each wavefront: a row of 9 offsets
+// (wavefront w takes entries off[w] .. off[w+1]-1) followed by the chunk
+// ids, stored as 16-bit values.
+__host__ __device__ inline int bonded_chunks(int nb, int na, int nt) {
+  return (nt + kWave - 1) / kWave + (na + kWave - 1) / kWave +
+         (nb + kWave - 1) / kWave;
+}
+__host__ __device__ inline int sched_row(int nb, int na, int nt) {
+  return 9 + bonded_chunks(nb, na, nt);
+}
+
 // dynamic LDS bytes of a W-wave evaluation block: per-evaluation areas,
-// force accumulators (forces only) and the staged topology
+// force accumulators (forces only) and the staged topology (with the
+// schedule row of this width)
 __host__ __device__ inline int block_lds_bytes(int waves, bool forces, int n,
                                                 int nb, int na, int nt) {
   const int head = 16 * kWave * waves + 8 * waves * kRedSlots + 16 * waves +
                    (forces ? acc_lds_bytes(n) : 0);
-  const int topo = 32 * nt + 24 * na + 16 * nb;
+  const int topo = 32 * nt + 24 * na + 16 * nb +
+                   ((2 * sched_row(nb, na, nt) + 15) & ~15);
   return head + topo;
 }
 
@@ -68,6 +84,7 @@ struct LigDev {
   const float2* apar;     // na: K_theta, theta0
   const int4* tijkl;      // nt
   const float4* tpar;     // nt: V/2, n (integer 1..6), cos gamma, sin gamma
+  const unsigned short* bsched;  // 4 x sched_row: bonded chunks per wavefront
   const double* beta;     // K: 1/(R T_k)
   const float* Tf;        // K
   const float* dtf;       // K

@@ -705,9 +705,11 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     v[d] = fmaf(hk, f[d], v[d]);
     x[d] = fmaf(dt, v[d], x[d]);
   }
-  eval_block<C, W, true, true>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid,
-                               owner ? fc_nxt + (size_t)tid * kFC : nullptr,
-                               L.frc + ((size_t)nxt * L.K + r) * 4);
+  // lean sums: the bonded total (the sweep needs no single bonded term)
+  eval_block<C, W, true, true, true>(
+      g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid,
+      owner ? fc_nxt + (size_t)tid * kFC : nullptr,
+      L.frc + ((size_t)nxt * L.K + r) * 4);
 #pragma unroll
   for (int d = 0; d < 3; ++d) v[d] = fmaf(hk, f[d], v[d]);
   double U1 = t1[0] + t1[1] + t1[2] + t1[3];
