@@ -504,6 +504,46 @@ extern "C" int bpmf_grid_upload(bpmf_ctx* c, const bpmf_grid_desc* d,
   return BPMF_OK;
 }
 
+// Order of a ligand's terms of one kind (arity atoms each, t-th term's
+// atoms at idx[arity t ..]) that spreads every atom over the 64-term
+// chunks: a chunk adds the force on its terms' atoms at one position
+// (first atom, second, ...) with one LDS atomic instruction per component,
+// and lanes of one such instruction that add into the same accumulator are
+// serialised.  Terms go, in their order, to the chunk with room where their
+// atoms have been met least so far at the same positions (ties: the lower
+// chunk); the terms of a chunk keep their relative order.  The order of the
+// terms does not change any force (integer accumulation), only which lane
+// sums which energy term.
+static std::vector<int> spread_order(const int* idx, int n_terms, int arity,
+                                     int n_atoms) {
+  const int nc = (n_terms + kWave - 1) / kWave;
+  std::vector<std::vector<int>> chunk(nc);
+  // seen[(c arity + a) n_atoms + atom]: terms of chunk c with `atom` at
+  // position a
+  std::vector<int> seen((size_t)nc * arity * n_atoms, 0);
+  auto cell = [&](int c, int a, int atom) -> int& {
+    return seen[((size_t)c * arity + a) * n_atoms + atom];
+  };
+  for (int t = 0; t < n_terms; ++t) {
+    int best = -1, best_score = 0;
+    for (int c = 0; c < nc; ++c) {
+      if ((int)chunk[c].size() >= kWave) continue;
+      int score = 0;
+      for (int a = 0; a < arity; ++a) score += cell(c, a, idx[arity * t + a]);
+      if (best < 0 || score < best_score) {
+        best = c;
+        best_score = score;
+      }
+    }
+    chunk[best].push_back(t);
+    for (int a = 0; a < arity; ++a) ++cell(best, a, idx[arity * t + a]);
+  }
+  std::vector<int> order;
+  order.reserve(n_terms);
+  for (auto& ch : chunk) order.insert(order.end(), ch.begin(), ch.end());
+  return order;
+}
+
 // Balanced deal of a ligand's bonded chunks (see sched_row) to the
 // wavefronts of each launch width: chunks longest first, each to the
 // wavefront with the least work so far (ties: the lower one), the
@@ -635,41 +675,45 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
     M += d->mass[i];
   }
   for (size_t i = 0; i < (size_t)n * C; ++i) scale[i] = (float)d->scale[i];
-  std::vector<int2> bij(nb);
-  std::vector<float2> bpar(nb);
-  for (int t = 0; t < nb; ++t) {
-    bpar[t] = make_float2((float)d->bond_k_r0[2 * t],
-                          (float)d->bond_k_r0[2 * t + 1]);
-  }
-  std::vector<int4> aijk(na);
-  std::vector<float2> apar(na);
-  for (int t = 0; t < na; ++t) {
-    apar[t] = make_float2((float)d->angle_k_t0[2 * t],
-                          (float)d->angle_k_t0[2 * t + 1]);
-  }
-  std::vector<int4> tijkl(nt);
-  std::vector<float4> tpar(nt);
   for (int t = 0; t < nt; ++t) {
     const double mult = d->tors_v_n_g[3 * t + 1];
     if (mult != floor(mult) || mult < 1 || mult > 6)
       return fail(BPMF_E_INVAL,
                   "torsion %d: multiplicity %g is not an integer in 1..6", t,
                   mult);
-    const double gam = d->tors_v_n_g[3 * t + 2];
-    tpar[t] = make_float4((float)d->tors_v_n_g[3 * t], (float)mult,
-                          (float)cos(gam), (float)sin(gam));
   }
-  for (int t = 0; t < nt; ++t) {
-    const int* q = d->tors_ijkl + 4 * t;
-    tijkl[t] = make_int4(q[0], q[1], q[2], q[3]);
-  }
-  for (int t = 0; t < na; ++t) {
-    const int* q = d->angle_ijk + 3 * t;
-    aijk[t] = make_int4(q[0], q[1], q[2], 0);
-  }
-  for (int t = 0; t < nb; ++t) {
+  // device order of the terms: spread over the chunks (spread_order)
+  const std::vector<int> bo = spread_order(d->bond_ij, nb, 2, n);
+  const std::vector<int> ao = spread_order(d->angle_ijk, na, 3, n);
+  const std::vector<int> to = spread_order(d->tors_ijkl, nt, 4, n);
+  std::vector<int2> bij(nb);
+  std::vector<float2> bpar(nb);
+  for (int u = 0; u < nb; ++u) {
+    const int t = bo[u];
     const int* q = d->bond_ij + 2 * t;
-    bij[t] = make_int2(q[0], q[1]);
+    bij[u] = make_int2(q[0], q[1]);
+    bpar[u] = make_float2((float)d->bond_k_r0[2 * t],
+                          (float)d->bond_k_r0[2 * t + 1]);
+  }
+  std::vector<int4> aijk(na);
+  std::vector<float2> apar(na);
+  for (int u = 0; u < na; ++u) {
+    const int t = ao[u];
+    const int* q = d->angle_ijk + 3 * t;
+    aijk[u] = make_int4(q[0], q[1], q[2], 0);
+    apar[u] = make_float2((float)d->angle_k_t0[2 * t],
+                          (float)d->angle_k_t0[2 * t + 1]);
+  }
+  std::vector<int4> tijkl(nt);
+  std::vector<float4> tpar(nt);
+  for (int u = 0; u < nt; ++u) {
+    const int t = to[u];
+    const int* q = d->tors_ijkl + 4 * t;
+    tijkl[u] = make_int4(q[0], q[1], q[2], q[3]);
+    const double gam = d->tors_v_n_g[3 * t + 2];
+    tpar[u] = make_float4((float)d->tors_v_n_g[3 * t],
+                          (float)d->tors_v_n_g[3 * t + 1], (float)cos(gam),
+                          (float)sin(gam));
   }
   std::vector<double> beta(K), wd((size_t)K * C);
   std::vector<float> Tf(K), dtf(K), wf((size_t)K * C);
