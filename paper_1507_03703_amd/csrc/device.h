@@ -320,12 +320,15 @@ __device__ __forceinline__ float from_fix(unsigned int a) {
 }
 
 struct Slots {
-  unsigned int* acc;  // n x 3
-  // f: force contribution in units of 2^-16 kJ/mol/A
+  unsigned int* acc;  // kAccCopies x n x 3
+  int stride;         // 3 n: words per copy
+  // f: force contribution in units of 2^-16 kJ/mol/A, into the lane's copy
   __device__ __forceinline__ void put(int atom, float3 f) const {
-    atomicAdd(&acc[3 * atom], to_fix_units(f.x));
-    atomicAdd(&acc[3 * atom + 1], to_fix_units(f.y));
-    atomicAdd(&acc[3 * atom + 2], to_fix_units(f.z));
+    unsigned int* a =
+        acc + (threadIdx.x & (kAccCopies - 1)) * stride + 3 * atom;
+    atomicAdd(&a[0], to_fix_units(f.x));
+    atomicAdd(&a[1], to_fix_units(f.y));
+    atomicAdd(&a[2], to_fix_units(f.z));
   }
 };
 
@@ -703,16 +706,24 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
     block_sync();
     if (owner) {
       if (n_atom_waves > 1) add_restraint();
-      // bonded forces: read and clear the atom's fixed-point accumulator
-      // (the next evaluation adds into it only after its first barrier)
-      unsigned int* a3 = sh.sl.acc + 3 * tid;
-      const float b[3] = {from_fix(a3[0]), from_fix(a3[1]), from_fix(a3[2])};
+      // bonded forces: read and clear the atom's fixed-point accumulators
+      // (the next evaluation adds into them only after its first barrier);
+      // the copies' integer sum does not depend on which lane used which
+      unsigned int s3[3] = {0u, 0u, 0u};
+#pragma unroll
+      for (int q = 0; q < kAccCopies; ++q) {
+        unsigned int* a3 = sh.sl.acc + q * sh.sl.stride + 3 * tid;
+        s3[0] += a3[0];
+        s3[1] += a3[1];
+        s3[2] += a3[2];
+        a3[0] = 0u;
+        a3[1] = 0u;
+        a3[2] = 0u;
+      }
+      const float b[3] = {from_fix(s3[0]), from_fix(s3[1]), from_fix(s3[2])};
       f[0] = b[0] + ge[0];
       f[1] = b[1] + ge[1];
       f[2] = b[2] + ge[2];
-      a3[0] = 0u;
-      a3[1] = 0u;
-      a3[2] = 0u;
       // the parts of the force that do not depend on the state weights
       if (cache_atom) {
         auto ca = BPMF_GMEM(float, cache_atom);

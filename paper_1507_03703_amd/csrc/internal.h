@@ -10,10 +10,16 @@ constexpr double kRGas = 8.314462618e-3;  // kJ/(mol K)
 #define BPMF_MAX_MBAR_STATES_DEV 128
 constexpr int kRedSlots = 4 + 8 + 2;  // per-wave partial sums (see Shared)
 
-// LDS bytes of the fixed-point force accumulators (n x 3 int32), rounded
-// up to 16 so that the topology staged after them stays 16-byte aligned
+// copies of the fixed-point force accumulators: a bonded-term lane adds
+// into copy (lane mod kAccCopies), which divides the lanes of one LDS
+// atomic instruction that meet the same atom among that many addresses
+constexpr int kAccCopies = 4;
+
+// LDS bytes of the fixed-point force accumulators (kAccCopies x n x 3
+// int32), rounded up to 16 so that the topology staged after them stays
+// 16-byte aligned
 __host__ __device__ inline int acc_lds_bytes(int n) {
-  return (12 * n + 15) & ~15;
+  return (kAccCopies * 12 * n + 15) & ~15;
 }
 
 // Bonded terms are taken in chunks of 64 terms of one kind (a wavefront
