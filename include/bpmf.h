@@ -544,6 +544,21 @@ BPMF_API int bpmf_pair_evaluate(bpmf_ctx* ctx, int ligand_id,
                                 const float* dev_x, int64_t n_conf,
                                 double* dev_terms, float* dev_forces);
 
+/* Put the ligand's pair terms (bpmf_pair_setup) into its sampled energy
+ * (on != 0) or take them out (on = 0): the Full pathway's ligand energy
+ * with its intramolecular nonbonded and implicit-solvent terms
+ * (Thermodynamic Cycle).  While on, U_k(x) of the sweeps (HMC moves,
+ * exchange, recorded components), of bpmf_energy_matrix(_batch) and of the
+ * external and pose moves (rigid moves: the terms do not change) includes
+ * E_LJ + E_Coul + E_GB + E_SA, summed with the bonded terms in the first
+ * cached component, and their force joins the HMC force; bpmf_evaluate
+ * keeps evaluating the bonded, restraint and grid terms only.  The cached
+ * components are recomputed, the stored start-of-trajectory forces
+ * dropped and captured graphs recaptured.  Synchronises.  Errors:
+ * BPMF_E_STATE (no pair parameters), BPMF_E_UNIMPL (the ligand's topology
+ * and pair parameters exceed 64 KB of LDS per replica). */
+BPMF_API int bpmf_pair_sample(bpmf_ctx* ctx, int ligand_id, int on);
+
 /* ------------------------------------------------------------------------
  * Ligand information, state parameters, single-ligand sweeps
  * ------------------------------------------------------------------------ */

@@ -78,7 +78,17 @@ class _Ligand(C.Structure):
                 ("nt", C.c_int), ("tijkl", C.POINTER(C.c_int)),
                 ("tpar", C.POINTER(C.c_double)),
                 ("c0", C.c_double * 3), ("d0", C.c_double),
-                ("krest", C.c_double)]
+                ("krest", C.c_double),
+                ("pair_on", C.c_int), ("pq", C.POINTER(C.c_double)),
+                ("psig", C.POINTER(C.c_double)),
+                ("peps", C.POINTER(C.c_double)),
+                ("prho", C.POINTER(C.c_double)),
+                ("pS", C.POINTER(C.c_double)),
+                ("pexcl", C.POINTER(C.c_ubyte)),
+                ("p14", C.POINTER(C.c_ubyte)),
+                ("lj14", C.c_double), ("el14", C.c_double),
+                ("eps_in", C.c_double), ("eps_out", C.c_double),
+                ("gamma", C.c_double), ("probe", C.c_double)]
 
 
 _lib = None
@@ -163,9 +173,11 @@ class OGrid:
 
 
 class OLigand:
-    """Ligand as the oracle sees it."""
+    """Ligand as the oracle sees it.  pairs: optional intramolecular
+    nonbonded / OBC GB-SA parameters (the dict synth.pair_params gives);
+    with them the pair terms are part of the ligand's energy."""
 
-    def __init__(self, lig):
+    def __init__(self, lig, pairs=None):
         self.n = lig.n_atoms
         self.mass = _d(lig.mass)
         self.scale = _d(lig.scale)
@@ -189,6 +201,35 @@ class OLigand:
                          _p(self.tpar, C.c_double), c0, float(lig.d0),
                          float(lig.k_restraint))
         self.K = len(lig.T)
+        self.pairs = pairs
+        if pairs is not None:
+            n = self.n
+            self.pq = _d(pairs["charge"])
+            self.psig = _d(pairs["sigma"])
+            self.peps = _d(pairs["eps"])
+            self.prho = _d(pairs["rho"])
+            self.pS = _d(pairs["S"])
+            ex = np.zeros((n, n), np.uint8)
+            for i, j in np.asarray(pairs["exclusions"], int).reshape(-1, 2):
+                ex[i, j] = ex[j, i] = 1
+            o4 = np.zeros((n, n), np.uint8)
+            for i, j in np.asarray(pairs["pairs14"], int).reshape(-1, 2):
+                if not ex[i, j]:
+                    o4[i, j] = o4[j, i] = 1
+            self.pexcl, self.p14 = ex, o4
+            s = self.s
+            s.pair_on = 1
+            s.pq = _p(self.pq, C.c_double)
+            s.psig = _p(self.psig, C.c_double)
+            s.peps = _p(self.peps, C.c_double)
+            s.prho = _p(self.prho, C.c_double)
+            s.pS = _p(self.pS, C.c_double)
+            s.pexcl = _p(self.pexcl, C.c_ubyte)
+            s.p14 = _p(self.p14, C.c_ubyte)
+            s.lj14, s.el14 = float(pairs["lj14"]), float(pairs["el14"])
+            s.eps_in = float(pairs["eps_solute"])
+            s.eps_out = float(pairs["eps_solvent"])
+            s.gamma, s.probe = float(pairs["gamma"]), float(pairs["probe"])
 
     @property
     def ref(self):

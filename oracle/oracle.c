@@ -74,6 +74,18 @@ typedef struct {
   const int* tijkl;     /* nt*4 */
   const double* tpar;   /* nt*3: V/2, n, gamma */
   double c0[3], d0, krest;
+  /* intramolecular nonbonded and OBC generalised-Born / surface-area terms
+     of the ligand (pair_on = 0: none); the excluded and 1-4 matrices are
+     n*n with 1 marking the pair */
+  int pair_on;
+  const double* pq;     /* n charges (e) */
+  const double* psig;   /* n LJ sigma (A) */
+  const double* peps;   /* n LJ epsilon (kJ/mol) */
+  const double* prho;   /* n intrinsic radii (A) */
+  const double* pS;     /* n descreening scale factors */
+  const unsigned char* pexcl;
+  const unsigned char* p14;
+  double lj14, el14, eps_in, eps_out, gamma, probe;
 } ora_ligand;
 
 /* ------------------------------------------------------------------------ */
@@ -223,10 +235,111 @@ double ora_angle(const double* xi, const double* xj, const double* xk) {
   return atan2(sqrt(dot3(c, c)), dot3(a, b));
 }
 
-/* terms: [U_bond, U_angle, U_tors, U_restr, Psi_0 .. Psi_{nc-1}]
+/* ------------------------------------------------------------------------ */
+/* Intramolecular nonbonded and implicit-solvent energy of the ligand       */
+/* (Thermodynamic Cycle: the ligand's force field with an OBC generalised-  */
+/* Born / surface-area solvent), by direct definition:                      */
+/*   E_LJ  = sum over pairs not excluded of 4 e_ij ((s_ij/r)^12 - (s_ij/r)^6) */
+/*           with s_ij = (s_i + s_j)/2, e_ij = sqrt(e_i e_j), 1-4 pairs x lj14;*/
+/*   E_C   = the same pairs' k_e q_i q_j / (eps_in r), 1-4 pairs x el14;     */
+/*   E_GB  = -(k_e/2)(1/eps_in - 1/eps_out) sum_i sum_j q_i q_j / f_ij, all  */
+/*           ordered pairs and i = j, f_ij = sqrt(r^2 + R_i R_j             */
+/*           exp(-r^2/(4 R_i R_j))), f_ii = R_i;                            */
+/*   Born radii (Onufriev, Bashford, Case 2004, OBC II): 1/R_i = 1/rt_i -    */
+/*           tanh(psi - 0.8 psi^2 + 4.85 psi^3)/rho_i, psi = I_i rt_i,       */
+/*           rt = rho - 0.09 A, I_i = sum_j of the Hawkins-Cramer-Truhlar    */
+/*           descreening integral of |x|^-4/(4 pi) over the ball of radius   */
+/*           S_j rt_j at distance r_ij, outside radius rt_i;                 */
+/*   E_SA  = sum_i 4 pi gamma (rho_i + probe)^2 (rho_i / R_i)^6.             */
+/* mag: the sum of the absolute values of the contributions.               */
+/* ------------------------------------------------------------------------ */
+#define ORA_KCOUL 1389.35457644382 /* kJ A / (mol e^2) */
+
+/* (1/4pi) x integral of |y|^-4 over the ball of radius s at distance r > 0
+   from the origin, outside the ball of radius a about the origin */
+static double ora_hct(double r, double a, double s) {
+  if (a >= r + s) return 0.0;
+  double L = fabs(r - s) > a ? fabs(r - s) : a;
+  double U = r + s;
+  double l = 1.0 / L, u = 1.0 / U;
+  double h = 0.5 * (l - u) + (s * s - r * r) * (l * l - u * u) / (8.0 * r) +
+             log(u / l) / (4.0 * r);
+  if (a < s - r) h += 1.0 / a - 1.0 / (s - r);
+  return h;
+}
+
+static double ora_pair_energy(const ora_ligand* L, const double* x,
+                              double* mag) {
+  const int n = L->n;
+  double e = 0.0, m = 0.0;
+  /* LJ and Coulomb */
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      if (L->pexcl[(size_t)i * n + j]) continue;
+      double d[3];
+      sub3(x + 3 * i, x + 3 * j, d);
+      double r = sqrt(dot3(d, d));
+      double sg = 0.5 * (L->psig[i] + L->psig[j]);
+      double ep = sqrt(L->peps[i] * L->peps[j]);
+      double sr6 = pow(sg / r, 6.0);
+      double lj = 4.0 * ep * (sr6 * sr6 - sr6);
+      double cl = ORA_KCOUL * L->pq[i] * L->pq[j] / (L->eps_in * r);
+      if (L->p14[(size_t)i * n + j]) {
+        lj *= L->lj14;
+        cl *= L->el14;
+      }
+      e += lj + cl;
+      m += fabs(lj) + fabs(cl);
+    }
+  /* Born radii */
+  double R[256];
+  for (int i = 0; i < n; ++i) {
+    double rt = L->prho[i] - 0.09, I = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double d[3];
+      sub3(x + 3 * i, x + 3 * j, d);
+      I += ora_hct(sqrt(dot3(d, d)), rt, L->pS[j] * (L->prho[j] - 0.09));
+    }
+    double psi = I * rt;
+    R[i] = 1.0 / (1.0 / rt -
+                  tanh(psi - 0.8 * psi * psi + 4.85 * psi * psi * psi) /
+                      L->prho[i]);
+  }
+  /* generalised Born and surface terms */
+  double tau = 1.0 / L->eps_in - 1.0 / L->eps_out;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double f;
+      if (i == j) {
+        f = R[i];
+      } else {
+        double d[3];
+        sub3(x + 3 * i, x + 3 * j, d);
+        double r2 = dot3(d, d), RR = R[i] * R[j];
+        f = sqrt(r2 + RR * exp(-r2 / (4.0 * RR)));
+      }
+      double gb = -0.5 * ORA_KCOUL * tau * L->pq[i] * L->pq[j] / f;
+      e += gb;
+      m += fabs(gb);
+    }
+  for (int i = 0; i < n; ++i) {
+    double rp = L->prho[i] + L->probe, q = L->prho[i] / R[i];
+    double sa = 4.0 * 3.14159265358979323846 * L->gamma * rp * rp * pow(q, 6.0);
+    e += sa;
+    m += fabs(sa);
+  }
+  if (mag) *mag = m;
+  return e;
+}
+
+/* terms: [U_bond, U_angle, U_tors, U_restr, Psi_0 .. Psi_{nc-1}]; with the
+ *        ligand's pair terms on, their energy is part of U_restr (the slot
+ *        of the state-independent non-bonded energy)
  * mag:   same layout, sum over contributions of |contribution|
  * F:     -grad( U_bond + U_angle + U_tors + U_restr + sum_c w_c Psi_c ),
- *        may be NULL */
+ *        may be NULL; the pair terms' part by central differences of their
+ *        energy (step 1e-5 A) */
 void ora_energy(const ora_grid* g, const ora_ligand* L, const double* w,
                 const double* x, double* terms, double* mag, double* F) {
   const int n = L->n, nc = g->nc;
@@ -328,6 +441,27 @@ void ora_energy(const ora_grid* g, const ora_ligand* L, const double* w,
           for (int a = 0; a < 3; ++a)
             F[3 * i + a] += f * (L->mass[i] / M) * c[a];
       }
+    }
+  }
+  /* intramolecular nonbonded and implicit-solvent terms */
+  if (L->pair_on) {
+    double mp = 0.0;
+    tl[3] += ora_pair_energy(L, x, &mp);
+    ml[3] += mp;
+    if (F) {
+      const double h = 1e-5;
+      double* y = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+      memcpy(y, x, sizeof(double) * 3 * (size_t)n);
+      for (int q = 0; q < 3 * n; ++q) {
+        const double x0 = y[q];
+        y[q] = x0 + h;
+        const double ep = ora_pair_energy(L, y, NULL);
+        y[q] = x0 - h;
+        const double em = ora_pair_energy(L, y, NULL);
+        y[q] = x0;
+        F[q] -= (ep - em) / (2.0 * h);
+      }
+      free(y);
     }
   }
   /* grid interaction energy */

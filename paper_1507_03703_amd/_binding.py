@@ -194,6 +194,7 @@ def library():
         "bpmf_initialize_ladder": [vp, C.POINTER(_InitArgs),
                                    C.POINTER(_InitResult)],
         "bpmf_pair_setup": [vp, C.c_int, C.POINTER(_PairDesc)],
+        "bpmf_pair_sample": [vp, C.c_int, C.c_int],
         "bpmf_pair_evaluate": [vp, C.c_int, vp, C.c_int64, vp, vp],
         "bpmf_version": [],
         "bpmf_last_error": [],
@@ -828,6 +829,12 @@ class Context:
         return terms, F
 
     # -- single-ligand control, ladder initialisation --------------------------
+    def pair_sample(self, ligand_id, on=True):
+        """Put the ligand's pair terms into its sampled energy (or take them
+        out); pair_setup must have been called."""
+        _check(self._lib.bpmf_pair_sample(self._h, int(ligand_id),
+                                          1 if on else 0))
+
     def ligand_info(self, ligand_id):
         v = [C.c_int(0) for _ in range(4)]
         _check(self._lib.bpmf_ligand_info(self._h, int(ligand_id),

@@ -115,6 +115,7 @@ struct bpmf_ctx {
   int class_n[kWaveClasses] = {0, 0, 0, 0};
   int class_lds[kWaveClasses] = {0, 0, 0, 0};
   int class_single[kWaveClasses] = {-1, -1, -1, -1};  // sole ligand or -1
+  bool class_pairs[kWaveClasses] = {false, false, false, false};
   int waves_override = 0;  // 0 = automatic choice
   int n_cu = 1;  // compute units of the device
   // scratch
@@ -235,7 +236,8 @@ int wave_class(int w) { return w == 1 ? 0 : (w == 2 ? 1 : (w == 4 ? 2 : 3)); }
 
 int lds_of(const LigHost& h, int waves, bool forces) {
   const LigDev& L = h.dev;
-  return block_lds_bytes(waves, forces, L.n, L.nb, L.na, L.nt);
+  return block_lds_bytes(waves, forces, L.n, L.nb, L.na, L.nt,
+                         L.pairs_on != 0);
 }
 
 // wavefronts per replica for the HMC sweep: enough to own every atom; when
@@ -272,6 +274,7 @@ int rebuild_tables(bpmf_ctx* c) {
   std::vector<LigDev> table(nl);
   std::vector<int2> cls[bpmf_ctx::kWaveClasses];
   int lds[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
+  bool pairs[bpmf_ctx::kWaveClasses] = {false, false, false, false};
   int total = 0;
   for (int l = 0; l < nl; ++l) total += c->ligs[l].dev.K;
   for (int l = 0; l < nl; ++l) {
@@ -281,6 +284,7 @@ int rebuild_tables(bpmf_ctx* c) {
     const int q = wave_class(h.sweep_waves);
     for (int r = 0; r < h.dev.K; ++r) cls[q].push_back(make_int2(l, r));
     lds[q] = std::max(lds[q], lds_of(h, h.sweep_waves, true));
+    pairs[q] = pairs[q] || h.dev.pairs_on;
   }
   std::vector<int2> all;
   int off[bpmf_ctx::kWaveClasses];
@@ -313,6 +317,7 @@ int rebuild_tables(bpmf_ctx* c) {
     c->class_off[q] = off[q];
     c->class_n[q] = (int)cls[q].size();
     c->class_lds[q] = lds[q];
+    c->class_pairs[q] = pairs[q];
     // a class holding the replicas of one ligand (0..K-1 in order) passes
     // that ligand's table entry as a kernel argument
     c->class_single[q] = -1;
@@ -874,7 +879,8 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   // initial cached components
   const LigDev* dl = c->d_ligs + (c->ligs.size() - 1);
   HIP_TRY(launch_recompute_comps(c->grid, dl, min_waves, K,
-                                 lds_of(c->ligs.back(), min_waves, false), c->stream));
+                                 lds_of(c->ligs.back(), min_waves, false),
+                                 false, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   *ligand_id = L.id;
   return BPMF_OK;
@@ -889,6 +895,7 @@ struct MlpBufs {
 int mlp_scratch(bpmf_ctx* c, int B, MlpBufs* b);
 int build_pose_tables(bpmf_ctx* c);
 int refresh_pose_weights(bpmf_ctx* c);
+int pair_sample_refresh(bpmf_ctx* c, int lid);
 int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st);
 int external_move_ligand(bpmf_ctx* c, int lid, int n_moves, int k_max,
                          double sigma, hipStream_t st);
@@ -955,7 +962,8 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
       const LigHost& h = c->ligs[only];
       HIP_TRY(launch_hmc_sweep(c->grid, c->d_ligs, nullptr, h.dev.K,
                                h.sweep_waves, lds_of(h, h.sweep_waves, true),
-                               a->n_leapfrog, c->seed, tail, &h.dev, st));
+                               a->n_leapfrog, c->seed, tail, &h.dev,
+                               h.dev.pairs_on != 0, st));
     } else {
       for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
         if (c->class_n[q])
@@ -964,7 +972,7 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
               1 << q, c->class_lds[q], a->n_leapfrog, c->seed, tail,
               c->class_single[q] >= 0 ? &c->ligs[c->class_single[q]].dev
                                       : nullptr,
-              st));
+              c->class_pairs[q], st));
     }
     if (tail.scheme == 1)
       HIP_TRY(launch_sweep_tail(dl, nl, tail.exchange_every, tail.scheme,
@@ -1163,6 +1171,7 @@ struct UknPlan {
   int off[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
   int cnt[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
   int lds[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
+  bool pairs[bpmf_ctx::kWaveClasses] = {false, false, false, false};
 };
 
 // Validates an energy-matrix batch and writes its job table into `jobs`
@@ -1238,6 +1247,7 @@ int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
       first += J.n;
       jobs[nj++] = J;
       p->lds[q] = std::max(p->lds[q], ukn_lds(h, W));
+      p->pairs[q] = p->pairs[q] || h.dev.pairs_on;
     }
     p->cnt[q] = nj - p->off[q];
     p->total[q] = first;
@@ -1261,7 +1271,8 @@ int ukn_launch(bpmf_ctx* c, const UknPlan& p, const UknJob* d_jobs,
     if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
     HIP_TRY(launch_energy_matrix(c->grid, c->d_ligs, 1 << q,
                                  d_jobs + p.off[q], p.cnt[q], p.total[q],
-                                 p.group, p.lds[q], c->n_cu, c->stream));
+                                 p.group, p.lds[q], c->n_cu, p.pairs[q],
+                                 c->stream));
     if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   }
   return BPMF_OK;
@@ -1794,7 +1805,8 @@ extern "C" int bpmf_set_replicas(bpmf_ctx* c, int ligand_id, const float* x,
   else
     HIP_TRY(launch_recompute_comps(c->grid, c->d_ligs + ligand_id,
                                    h.min_waves, L.K,
-                                   lds_of(h, h.min_waves, false), c->stream));
+                                   lds_of(h, h.min_waves, false),
+                                   L.pairs_on != 0, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   h.counter = counter;
   return BPMF_OK;
@@ -1980,7 +1992,49 @@ extern "C" int bpmf_pair_setup(bpmf_ctx* c, int ligand_id,
   P.sa = (float)(4.0 * M_PI * d->sa_gamma);
   P.probe = (float)d->probe_radius;
   h.has_pairs = true;
+  // pair terms already in the sampled energy: the new parameters take over
+  if (h.dev.pairs_on) return pair_sample_refresh(c, ligand_id);
   return BPMF_OK;
+}
+
+namespace {
+// After the pair terms of a ligand's energy changed (switched on or off, new
+// parameters): device table entry, LDS sizes, captured graphs, the cached
+// start-of-trajectory forces (invalid) and the cached energy components
+// (recomputed).  Synchronises.
+int pair_sample_refresh(bpmf_ctx* c, int lid) {
+  LigHost& h = c->ligs[lid];
+  h.dev.pair = h.pair;
+  int rc = rebuild_tables(c);
+  if (rc) return rc;
+  LigDev& L = h.dev;
+  HIP_TRY(hipMemsetAsync(L.fvalid, 0, (size_t)L.K * 4, c->stream));
+  HIP_TRY(launch_recompute_comps(c->grid, c->d_ligs + lid, h.min_waves, L.K,
+                                 lds_of(h, h.min_waves, false),
+                                 L.pairs_on != 0, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return BPMF_OK;
+}
+}  // namespace
+
+extern "C" int bpmf_pair_sample(bpmf_ctx* c, int ligand_id, int on) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  LigHost& h = c->ligs[ligand_id];
+  if (on && !h.has_pairs)
+    return fail(BPMF_E_STATE, "ligand %d has no pair parameters (call "
+                "bpmf_pair_setup)", ligand_id);
+  const LigDev& L = h.dev;
+  if (on) {
+    const int need = block_lds_bytes(8, true, L.n, L.nb, L.na, L.nt, true);
+    if (need > 65536)
+      return fail(BPMF_E_UNIMPL,
+                  "ligand %d: %d bytes of LDS per replica with pair terms "
+                  "(max 65536)", ligand_id, need);
+  }
+  h.dev.pairs_on = on ? 1 : 0;
+  return pair_sample_refresh(c, ligand_id);
 }
 
 extern "C" int bpmf_pair_evaluate(bpmf_ctx* c, int ligand_id,

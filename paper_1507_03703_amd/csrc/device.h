@@ -487,6 +487,13 @@ struct Shared {
   const int4* tijkl;
   const float4* tpar;
   const unsigned short* sched;  // this launch width's schedule row
+  // pair terms in the energy (L.pairs_on): staged parameters and scratch
+  const float4* pp0;        // n: q, sigma, sqrt(eps), rho
+  const float2* pp1;        // n: rt, S rt
+  const uint32_t* pex;      // n x kPairWords excluded-pair masks
+  const uint32_t* p14;      // n x kPairWords 1-4 masks
+  float* pR;                // n Born radii
+  float* pb;                // n chain-rule factors dE/dR_i dR_i/dI_i
 };
 
 // Copy a ligand's constant topology into LDS (all threads; caller syncs).
@@ -540,6 +547,37 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
   sh.sched = sched;
   sh.bij = bij;
   sh.bpar = bpar;
+  if (L.pairs_on) {
+    // pair parameters after the schedule row, 16-byte aligned (raw is)
+    unsigned char* pb0 =
+        raw + ((32 * L.nt + 24 * L.na + 16 * L.nb + 2 * row + 15) & ~15);
+    const int n = L.n;
+    float4* p0 = reinterpret_cast<float4*>(pb0);
+    float2* p1 = reinterpret_cast<float2*>(p0 + n);
+    uint32_t* ex = reinterpret_cast<uint32_t*>(p1 + n);
+    uint32_t* o4 = ex + n * kPairWords;
+    float* R = reinterpret_cast<float*>(o4 + n * kPairWords);
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef const f4v __attribute__((address_space(1))) gf4;
+    typedef const f2v __attribute__((address_space(1))) gf2;
+    for (int i = tid; i < n; i += nthreads) {
+      const f4v a = ((gf4*)L.pair.p0)[i];
+      const f2v b = ((gf2*)L.pair.p1)[i];
+      p0[i] = make_float4(a.x, a.y, a.z, a.w);
+      p1[i] = make_float2(b.x, b.y);
+    }
+    for (int i = tid; i < n * kPairWords; i += nthreads) {
+      ex[i] = BPMF_GMEM(const uint32_t, L.pair.excl)[i];
+      o4[i] = BPMF_GMEM(const uint32_t, L.pair.o14)[i];
+    }
+    sh.pp0 = p0;
+    sh.pp1 = p1;
+    sh.pex = ex;
+    sh.p14 = o4;
+    sh.pR = R;
+    sh.pb = R + n;
+  }
   sh.aijk = aijk;
   sh.apar = apar;
   sh.tijkl = tijkl;
@@ -584,6 +622,127 @@ __device__ __forceinline__ void block_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// The ligand's intramolecular nonbonded and OBC GB/SA energy (the terms of
+// bpmf_pair_evaluate) for the configuration in sh.pos: one owner thread per
+// atom sums its own row of pair terms (every pair is visited from both
+// ends, so forces need no atomics), in three passes with two workgroup
+// barriers, which every thread of the block calls: (1) LJ, Coulomb and the
+// descreening sum, giving the Born radius; (2) GB energy, its explicit
+// force and dE/dR_i, the surface term; (3) the chain rule through the Born
+// radii (FORCES).  e: the thread's share of the energy; pf: the force on
+// its atom (FORCES).
+template <bool FORCES>
+__device__ __forceinline__ void pair_stage(const Shared& sh, const PairDev& P,
+                                           int n, int tid, float& e,
+                                           float (&pf)[3]) {
+  const bool own = tid < n;
+  float e_lj = 0.f, e_c = 0.f, e_gb = 0.f, e_sa = 0.f;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  float I = 0.f, dRdI = 0.f, Ri = 0.f;
+  float4 xi = make_float4(0.f, 0.f, 0.f, 0.f), pi = xi;
+  float2 qi1 = make_float2(0.f, 0.f);
+  if (own) {
+    xi = sh.pos[tid];
+    pi = sh.pp0[tid];
+    qi1 = sh.pp1[tid];
+    for (int j = 0; j < n; ++j) {
+      if (j == tid) continue;
+      const float4 xj = sh.pos[j], pj = sh.pp0[j];
+      const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const float r = sqrtf(r2);
+      float H, dH;
+      hct(r, qi1.x, sh.pp1[j].y, H, dH);
+      I += H;
+      const int w = tid * kPairWords + (j >> 5);
+      const uint32_t bit = 1u << (j & 31);
+      if (sh.pex[w] & bit) continue;
+      const float sg = 0.5f * (pi.y + pj.y), ep = pi.z * pj.z;
+      const float ir2 = 1.f / r2;
+      const float sr2 = sg * sg * ir2, sr6 = sr2 * sr2 * sr2;
+      float lj = 4.f * ep * (sr6 * sr6 - sr6);
+      float flj = 24.f * ep * (2.f * sr6 * sr6 - sr6) * ir2;
+      float cl = P.kc * pi.x * pj.x / r;
+      float fcl = cl * ir2;
+      if (sh.p14[w] & bit) {
+        lj *= P.lj14;
+        flj *= P.lj14;
+        cl *= P.el14;
+        fcl *= P.el14;
+      }
+      e_lj += 0.5f * lj;
+      e_c += 0.5f * cl;
+      if (FORCES) {
+        const float f = flj + fcl;
+        fx += f * dx;
+        fy += f * dy;
+        fz += f * dz;
+      }
+    }
+    const float psi = I * qi1.x;
+    const float t = psi * (kObcA - psi * (kObcB - kObcC * psi));
+    const float th = tanhf(t);
+    Ri = 1.f / (1.f / qi1.x - th / pi.w);
+    dRdI = Ri * Ri * (1.f - th * th) *
+           (kObcA - psi * (2.f * kObcB - 3.f * kObcC * psi)) * qi1.x / pi.w;
+    sh.pR[tid] = Ri;
+  }
+  block_sync();
+  if (own) {
+    const float qi = pi.x;
+    e_gb = 0.5f * P.kgb * qi * qi / Ri;
+    float dEdR = -0.5f * P.kgb * qi * qi / (Ri * Ri);
+    for (int j = 0; j < n; ++j) {
+      if (j == tid) continue;
+      const float4 xj = sh.pos[j];
+      const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const float Rj = sh.pR[j];
+      const float RR = Ri * Rj;
+      const float D = expf(-0.25f * r2 / RR);
+      const float f2 = r2 + RR * D;
+      const float invf = rsqrtf(f2);
+      const float invf3 = invf * invf * invf;
+      const float kq = P.kgb * qi * sh.pp0[j].x;
+      e_gb += 0.5f * kq * invf;
+      if (FORCES) {
+        const float g = kq * (1.f - 0.25f * D) * invf3;
+        fx += g * dx;
+        fy += g * dy;
+        fz += g * dz;
+        dEdR -= 0.5f * kq * Rj * D * (1.f + 0.25f * r2 / RR) * invf3;
+      }
+    }
+    const float rp = pi.w + P.probe;
+    const float q6 = pi.w / Ri, q3 = q6 * q6 * q6;
+    e_sa = P.sa * rp * rp * q3 * q3;
+    dEdR -= 6.f * e_sa / Ri;
+    sh.pb[tid] = dEdR * dRdI;
+  }
+  block_sync();
+  if (FORCES && own) {
+    const float bi = sh.pb[tid];
+    for (int j = 0; j < n; ++j) {
+      if (j == tid) continue;
+      const float4 xj = sh.pos[j];
+      const float2 pj1 = sh.pp1[j];
+      const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+      float Hi, dHi, Hj, dHj;
+      hct(r, qi1.x, pj1.y, Hi, dHi);
+      hct(r, pj1.x, qi1.y, Hj, dHj);
+      const float g = -(bi * dHi + sh.pb[j] * dHj) / r;
+      fx += g * dx;
+      fy += g * dy;
+      fz += g * dz;
+    }
+  }
+  e = e_lj + e_c + e_gb + e_sa;
+  pf[0] = fx;
+  pf[1] = fy;
+  pf[2] = fz;
+}
+
 // sc: per-atom grid factors of the thread's atom (0 for non-owners).
 // terms (ENERGY): [U_bond, U_angle, U_tors, U_I, Psi_0..Psi_{C-1}, X0, X1]
 // (LEAN: [U_bond + U_angle + U_tors, 0, 0, U_I, Psi_c, 0, 0])
@@ -593,8 +752,11 @@ __device__ __forceinline__ void block_sync() {
 // BONDED false: the grid terms and the restraint only (terms[0..2] = 0; no
 // topology needs to be staged), for rigid moves, which leave the bonded
 // energy unchanged.
+// PAIRS: the ligand's pair terms join the energy when L.pairs_on (their
+// energy is summed with the bonded terms, in terms[0]; their force is part
+// of the state-independent force).
 template <int C, int W, bool FORCES, bool ENERGY, bool LEAN = false,
-          bool BONDED = true>
+          bool BONDED = true, bool PAIRS = false>
 __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
                                            const float* w, const float (&x)[3],
                                            float m, const float (&sc)[C],
@@ -671,6 +833,10 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
     for (int c = 0; c < C; ++c) psi[c] = e[c];
     if (FORCES) grid_force<C>(w, de, ge);
   }
+  // intramolecular nonbonded and implicit-solvent terms
+  float epair = 0.f, fpair[3] = {0.f, 0.f, 0.f};
+  const bool pairs = PAIRS && L.pairs_on;
+  if (pairs) pair_stage<FORCES>(sh, L.pair, n, tid, epair, fpair);
   // centre of mass offset from the site (fixed-order sum of the atom waves'
   // partials; with one atom wave its own sums are the total)
   float cx, cy, cz;
@@ -720,7 +886,9 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
         a3[1] = 0u;
         a3[2] = 0u;
       }
-      const float b[3] = {from_fix(s3[0]), from_fix(s3[1]), from_fix(s3[2])};
+      const float b[3] = {from_fix(s3[0]) + fpair[0],
+                          from_fix(s3[1]) + fpair[1],
+                          from_fix(s3[2]) + fpair[2]};
       f[0] = b[0] + ge[0];
       f[1] = b[1] + ge[1];
       f[2] = b[2] + ge[2];
@@ -754,14 +922,16 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
     // extras are not reduced (their terms are 0)
     // a wavefront without bonded terms (or without atoms) contributes exact
     // zeros to those sums: it skips them (wave-uniform branches)
-    const bool wave_bonded = BONDED && sh.sched[wv + 1] > sh.sched[wv];
+    const bool wave_bonded = (BONDED && sh.sched[wv + 1] > sh.sched[wv]) ||
+                             (pairs && wave_has_atoms);
     double v[6 + C];
     v[0] = v[1] = v[2] = 0.0;
     if (wave_bonded) {
       if (LEAN) {
-        v[0] = wave_sum((double)eb + (double)ea + (double)et);
+        v[0] = wave_sum((double)eb + (double)ea + (double)et +
+                        (double)epair);
       } else {
-        v[0] = wave_sum((double)eb);
+        v[0] = wave_sum((double)eb + (double)epair);
         v[1] = wave_sum((double)ea);
         v[2] = wave_sum((double)et);
       }

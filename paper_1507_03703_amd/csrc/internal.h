@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pairs.h"
+
 namespace bpmf {
 
 constexpr int kWave = 64;
@@ -37,15 +39,17 @@ __host__ __device__ inline int sched_row(int nb, int na, int nt) {
 }
 
 // dynamic LDS bytes of a W-wave evaluation block: per-evaluation areas,
-// force accumulators (forces only) and the staged topology (with the
-// schedule row of this width)
+// force accumulators (forces only), the staged topology (with the schedule
+// row of this width) and, with pair terms in the energy, the pair
+// parameters and scratch
 __host__ __device__ inline int block_lds_bytes(int waves, bool forces, int n,
-                                                int nb, int na, int nt) {
+                                                int nb, int na, int nt,
+                                                bool pairs = false) {
   const int head = 16 * kWave * waves + 8 * waves * kRedSlots + 16 * waves +
                    (forces ? acc_lds_bytes(n) : 0);
   const int topo = 32 * nt + 24 * na + 16 * nb +
                    ((2 * sched_row(nb, na, nt) + 15) & ~15);
-  return head + topo;
+  return head + topo + (pairs ? pair_lds_bytes(n) : 0);
 }
 
 enum Purpose : uint32_t { kMomenta = 1, kAccept = 2, kExchange = 3 };
@@ -127,6 +131,10 @@ struct LigDev {
   int* fvalid;                // K
   float* samp_x;                  // cap*K*n*3
   double* samp_c;                 // cap*K*(1+C)
+  // intramolecular nonbonded and OBC GB/SA terms in the sampled energy
+  // (bpmf_pair_sample): on when pairs_on, parameters in `pair`
+  int pairs_on;
+  PairDev pair;
 };
 
 // Launch wrappers (kernels.hip).  All return hipError_t of the launch.
@@ -139,10 +147,11 @@ struct TailArgs {
 };
 // one: the host copy of the table entry when the launch covers a single
 // ligand (its replicas 0..n_tasks-1 in order), else null
+// pairs: some ligand of the launch has its pair terms in the energy
 hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
                             const int2* d_tasks, int n_tasks, int waves,
                             int lds_bytes, int nleap, uint64_t seed,
-                            TailArgs tail, const LigDev* one,
+                            TailArgs tail, const LigDev* one, bool pairs,
                             hipStream_t st);
 hipError_t launch_sweep_tail(const LigDev* d_ligs, int n_ligs,
                              int exchange_every, int scheme, int max_sep,
@@ -174,7 +183,7 @@ struct UknJob {
 hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
                                 int waves, const UknJob* d_jobs, int n_jobs,
                                 int64_t total, int group, int lds_bytes,
-                                int n_cu, hipStream_t st);
+                                int n_cu, bool pairs, hipStream_t st);
 // copy n jobs from host memory into the device table dst by kernels that
 // take the jobs as arguments (no host staging buffer, no copy engine)
 hipError_t launch_put_jobs(UknJob* dst, const UknJob* jobs, int n,
@@ -191,7 +200,7 @@ hipError_t launch_grid_eval(const GridDev& g, const float* pos,
                             const float* scale, int64_t n, const double* w,
                             float* energy, float* force, hipStream_t st);
 hipError_t launch_recompute_comps(const GridDev& g, const LigDev* d_lig,
-                                  int waves, int K, int lds_bytes,
+                                  int waves, int K, int lds_bytes, bool pairs,
                                   hipStream_t st);
 
 // MBAR kernels (mbar.hip).  One entry per problem of a batch, in device

@@ -525,7 +525,9 @@ __global__ __launch_bounds__(256) void k_sweep_finish(
 // ONE: the launch covers the replicas of a single ligand, whose table entry
 // comes in the kernel arguments (block b = replica b) instead of through the
 // task list.
-template <int C, int W, bool ONE>
+// PAIRS: ligands whose pair terms are in the energy (L.pairs_on) evaluate
+// them too.
+template <int C, int W, bool ONE, bool PAIRS>
 __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     GridDev g, const LigDev* __restrict__ ligs, const int2* __restrict__ tasks,
     LigDev one, int nleap, uint64_t seed, TailArgs tail) {
@@ -677,7 +679,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     KE0 = ke * 1e4;
   } else {
     double t0[6 + C];
-    eval_block<C, W, true, true>(
+    eval_block<C, W, true, true, false, true, PAIRS>(
         g, L, w, x, m, sc, f, t0, ke0, 0.f, sh, tid,
         owner ? fc_cur + (size_t)tid * kFC : nullptr,
         L.frc + ((size_t)cur * L.K + r) * 4);
@@ -697,7 +699,8 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
       v[d] = fmaf(hk, f[d], v[d]);
       x[d] = fmaf(dt, v[d], x[d]);
     }
-    eval_block<C, W, true, false>(g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid);
+    eval_block<C, W, true, false, false, true, PAIRS>(g, L, w, x, m, sc, f,
+                                                      t1, 0.f, 0.f, sh, tid);
 #pragma unroll
     for (int d = 0; d < 3; ++d) v[d] = fmaf(hk, f[d], v[d]);
   }
@@ -707,7 +710,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     x[d] = fmaf(dt, v[d], x[d]);
   }
   // lean sums: the bonded total (the sweep needs no single bonded term)
-  eval_block<C, W, true, true, true>(
+  eval_block<C, W, true, true, true, true, PAIRS>(
       g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid,
       owner ? fc_nxt + (size_t)tid * kFC : nullptr,
       L.frc + ((size_t)nxt * L.K + r) * 4);
@@ -788,7 +791,7 @@ __global__ __launch_bounds__(256) void k_exchange(
 // segment.  Each sample's column (K entries) goes to LDS; every `group`
 // samples (at most 16: a 128-byte line of each row) the columns are written
 // out row by row by consecutive lanes.
-template <int C, int W>
+template <int C, int W, bool PAIRS>
 __global__ __launch_bounds__(W * kWave) void k_energy_matrix(
     GridDev g, const LigDev* __restrict__ ligs,
     const UknJob* __restrict__ jobs, int n_jobs, int64_t total,
@@ -822,7 +825,8 @@ __global__ __launch_bounds__(W * kWave) void k_energy_matrix(
     // writes before their reads)
     const int K = L.K;
     double* ew = reinterpret_cast<double*>(
-        smem + block_lds_bytes(W, false, L.n, L.nb, L.na, L.nt));
+        smem + block_lds_bytes(W, false, L.n, L.nb, L.na, L.nt,
+                               PAIRS && L.pairs_on));
     double* col = ew + K * (C + 1);
     for (int i = tid; i < K * (C + 1); i += W * kWave)
       ew[i] = i < K * C ? ((gcdouble*)L.wd)[i]
@@ -852,8 +856,8 @@ __global__ __launch_bounds__(W * kWave) void k_energy_matrix(
             xn[d] = owner ? xb[(size_t)(q + 1 - J.first) * n * 3 + d] : 0.f;
         }
         double t[6 + C];
-        eval_block<C, W, false, true, true>(g, L, w0, x, m, sc, f, t, 0.f,
-                                            0.f, sh, tid);
+        eval_block<C, W, false, true, true, true, PAIRS>(
+            g, L, w0, x, m, sc, f, t, 0.f, 0.f, sh, tid);
         const double U0 = t[0] + t[1] + t[2] + t[3];
         double* cs = col + (q - s) * K;
         for (int k = tid; k < K; k += W * kWave) {
@@ -918,7 +922,7 @@ __global__ __launch_bounds__(W * kWave) void k_evaluate(
 }
 
 // recompute cached components of every replica from its positions
-template <int C, int W>
+template <int C, int W, bool PAIRS>
 __global__ __launch_bounds__(W * kWave) void k_recompute(
     GridDev g, const LigDev* __restrict__ lig) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -938,7 +942,8 @@ __global__ __launch_bounds__(W * kWave) void k_recompute(
   for (int d = 0; d < 3; ++d)
     x[d] = owner ? L.x[((size_t)r * n + tid) * 3 + d] : 0.f;
   double t[6 + C];
-  eval_block<C, W, false, true>(g, L, w0, x, m, sc, f, t, 0.f, 0.f, sh, tid);
+  eval_block<C, W, false, true, false, true, PAIRS>(g, L, w0, x, m, sc, f, t,
+                                                    0.f, 0.f, sh, tid);
   if (tid == 0) {
     double* cp = L.comps + (size_t)r * (1 + C);
     cp[0] = t[0] + t[1] + t[2] + t[3];
@@ -1061,23 +1066,27 @@ int grid_blocks(int64_t work, int per_block, int cap) {
 hipError_t launch_hmc_sweep(const GridDev& g, const LigDev* d_ligs,
                             const int2* d_tasks, int n_tasks, int waves,
                             int lds_bytes, int nleap, uint64_t seed,
-                            TailArgs tail, const LigDev* one,
+                            TailArgs tail, const LigDev* one, bool pairs,
                             hipStream_t st) {
   if (n_tasks <= 0) return hipSuccess;
-  if (one) {
-    BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
-      hipLaunchKernelGGL((k_hmc_sweep<C, W, true>), dim3(n_tasks),
-                         dim3(W * kWave), lds_bytes, st, g, d_ligs, d_tasks,
-                         *one, nleap, seed, tail);
-    }));
+  const LigDev none{};
+  const LigDev& arg = one ? *one : none;
+#define BPMF_SWEEP(ONE_, PAIRS_)                                            \
+  BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {                             \
+    hipLaunchKernelGGL((k_hmc_sweep<C, W, ONE_, PAIRS_>), dim3(n_tasks),    \
+                       dim3(W * kWave), lds_bytes, st, g, d_ligs, d_tasks,  \
+                       arg, nleap, seed, tail);                             \
+  }))
+  if (one && pairs) {
+    BPMF_SWEEP(true, true);
+  } else if (one) {
+    BPMF_SWEEP(true, false);
+  } else if (pairs) {
+    BPMF_SWEEP(false, true);
   } else {
-    const LigDev none{};
-    BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
-      hipLaunchKernelGGL((k_hmc_sweep<C, W, false>), dim3(n_tasks),
-                         dim3(W * kWave), lds_bytes, st, g, d_ligs, d_tasks,
-                         none, nleap, seed, tail);
-    }));
+    BPMF_SWEEP(false, false);
   }
+#undef BPMF_SWEEP
   return hipGetLastError();
 }
 
@@ -1146,10 +1155,11 @@ hipError_t launch_put_jobs(UknJob* dst, const UknJob* jobs, int n,
 hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
                                 int waves, const UknJob* d_jobs, int n_jobs,
                                 int64_t total, int group, int lds_bytes,
-                                int n_cu, hipStream_t st) {
+                                int n_cu, bool pairs, hipStream_t st) {
   if (total <= 0) return hipSuccess;
   BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
-    auto kern = k_energy_matrix<C, W>;
+    auto kern = pairs ? k_energy_matrix<C, W, true>
+                      : k_energy_matrix<C, W, false>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, kern, W * kWave, lds_bytes);
@@ -1177,12 +1187,19 @@ hipError_t launch_evaluate(const GridDev& g, const LigDev* d_lig,
 }
 
 hipError_t launch_recompute_comps(const GridDev& g, const LigDev* d_lig,
-                                  int waves, int K, int lds_bytes,
+                                  int waves, int K, int lds_bytes, bool pairs,
                                   hipStream_t st) {
-  BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
-    hipLaunchKernelGGL((k_recompute<C, W>), dim3(K), dim3(W * kWave),
-                       lds_bytes, st, g, d_lig);
-  }));
+  if (pairs) {
+    BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
+      hipLaunchKernelGGL((k_recompute<C, W, true>), dim3(K), dim3(W * kWave),
+                         lds_bytes, st, g, d_lig);
+    }));
+  } else {
+    BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
+      hipLaunchKernelGGL((k_recompute<C, W, false>), dim3(K), dim3(W * kWave),
+                         lds_bytes, st, g, d_lig);
+    }));
+  }
   return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
   __shared__ float sRm[kBatch][9], stm[kBatch][3], sc0[3], st[3];
   __shared__ double s_lnu[kBatch];
   __shared__ double s_cp[4 * W];
+  __shared__ double s_ui;  // restraint energy of the current pose
   __shared__ int s_acc;
   const LigDev L = *lig;
   const int tid = threadIdx.x;
@@ -127,11 +128,16 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
         for (int d = 0; d < 3; ++d) c[d] += s_cp[4 * q + d];
         M += s_cp[4 * q + 3];
       }
+      double d2 = 0.0;
       for (int d = 0; d < 3; ++d) {
         c[d] /= M;
         sc0[d] = (float)c[d];
         st[d] = (float)(c[d] + (double)stm[j][d]);
+        d2 += (c[d] - (double)L.site[d]) * (c[d] - (double)L.site[d]);
       }
+      // restraint energy at the current centre of mass (Eq. binding_site)
+      const double ex = sqrt(d2) - (double)L.d0;
+      s_ui = ex > 0.0 ? 0.5 * (double)L.krest * ex * ex : 0.0;
     }
     __syncthreads();
     const float* sR = sRm[j];
@@ -143,10 +149,13 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
         xn[a] = st[a] + sR[3 * a] * y[0] + sR[3 * a + 1] * y[1] +
                 sR[3 * a + 2] * y[2];
     }
+    // the move is rigid: the bonded (and pair) energy is the cached one, the
+    // stored first component less the restraint energy of the current
+    // centre of mass; only the grid terms and the restraint are evaluated
     double t[6 + C];
-    eval_block<C, W, false, true, true>(g, L, w, xn, m, sc, f, t, 0.f, 0.f,
-                                        sh, tid);
-    const double u0 = t[0] + t[1] + t[2] + t[3];
+    eval_block<C, W, false, true, true, false>(g, L, w, xn, m, sc, f, t, 0.f,
+                                               0.f, sh, tid);
+    const double u0 = (comp[0] - s_ui) + t[3];
     double e_new = u0;
 #pragma unroll
     for (int c = 0; c < C; ++c) e_new += L.wd[k * C + c] * t[4 + c];

@@ -22,41 +22,6 @@ namespace bpmf {
 
 namespace {
 
-constexpr float kObcA = 1.0f, kObcB = 0.8f, kObcC = 4.85f;
-
-// descreening integral H(r; a, s) of a ball of radius s at distance r
-// outside radius a, and dH/dr
-__device__ __forceinline__ void hct(float r, float a, float s, float& H,
-                                   float& dH) {
-  if (a >= r + s) {
-    H = 0.f;
-    dH = 0.f;
-    return;
-  }
-  const float u = 1.f / (r + s), du = -u * u;
-  const float rs = r - s;
-  float l, dl;
-  if (a > fabsf(rs)) {
-    l = 1.f / a;
-    dl = 0.f;
-  } else {
-    l = 1.f / fabsf(rs);
-    dl = rs > 0.f ? -l * l : l * l;
-  }
-  const float ir = 1.f / r;
-  const float s2r2 = s * s - r * r;
-  const float l2u2 = l * l - u * u;
-  const float lg = logf(u / l);
-  H = 0.5f * (l - u) + 0.125f * s2r2 * l2u2 * ir + 0.25f * lg * ir;
-  dH = 0.5f * (dl - du) + (-0.25f - 0.125f * s2r2 * ir * ir) * l2u2 +
-       0.25f * s2r2 * (l * dl - u * du) * ir +
-       0.25f * (du / u - dl / l) * ir - 0.25f * lg * ir * ir;
-  if (a < s - r) {  // atom i inside the ball: the shells a .. s - r whole
-    H += 1.f / a - l;
-    dH -= dl;
-  }
-}
-
 template <int W, bool FORCES>
 __global__ __launch_bounds__(W * 64) void k_pair_terms(
     PairDev P, const float* __restrict__ xs, double* __restrict__ terms,

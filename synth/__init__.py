@@ -204,20 +204,29 @@ def _unit(rng):
 
 
 def random_tree(rng, n_atoms, box=6.0, bond=BOND_LEN, min_sep=1.2,
-                max_angle_deg=165.0):
+                max_angle_deg=165.0, far_sep=None):
     """Random tree-shaped ligand grown in a cube of edge `box` centred on 0.
 
     Atom 0 sits at the centre; each new atom attaches at distance `bond` in a
     uniform random direction to a random existing atom of degree < 4.  A
     placement is rejected when it leaves the box, comes closer than min_sep
-    to another atom, or makes a near-linear angle with a bond of its parent.
+    to another atom, or makes a near-linear angle with a bond of its parent;
+    with far_sep, also when it comes closer than far_sep to an atom three or
+    more bonds away (every atom but its parent and the parent's neighbours),
+    so that no pair the intramolecular nonbonded terms see starts in a
+    clash.
     """
     x = [np.zeros(3)]
     deg = [0]
     nbr = [[]]
     bonds = []
     cosmax = math.cos(math.radians(max_angle_deg))
+    misses = 0
     while len(x) < n_atoms:
+        misses += 1
+        if misses > 5000:
+            raise RuntimeError("random_tree: no room for atom %d of %d in a "
+                               "box of %g" % (len(x) + 1, n_atoms, box))
         cand = [i for i in range(len(x)) if deg[i] < 4]
         p = cand[rng.integers(len(cand))]
         for _ in range(100):
@@ -226,8 +235,15 @@ def random_tree(rng, n_atoms, box=6.0, bond=BOND_LEN, min_sep=1.2,
             if np.any(np.abs(y) > box / 2):
                 continue
             X = np.array(x)
-            if np.min(np.linalg.norm(X - y, axis=1)) < min_sep:
+            dist = np.linalg.norm(X - y, axis=1)
+            if np.min(dist) < min_sep:
                 continue
+            if far_sep is not None:
+                near = np.ones(len(x), bool)
+                near[p] = False
+                near[nbr[p]] = False
+                if np.any(dist[near] < far_sep):
+                    continue
             ok = True
             for q in nbr[p]:
                 u = (x[q] - x[p]) / np.linalg.norm(x[q] - x[p])
@@ -243,6 +259,7 @@ def random_tree(rng, n_atoms, box=6.0, bond=BOND_LEN, min_sep=1.2,
             deg[p] += 1
             nbr[p].append(j)
             bonds.append((p, j))
+            misses = 0
             break
     return np.array(x), np.array(bonds, np.int32), nbr
 
@@ -345,8 +362,8 @@ def add_soft_grids(grid, ligands, cap_energy=10.0):
 
 
 def make_ligand(rng, n_atoms, K, box=6.0, dt=1.0, n_channels=3,
-                mass=MASS_C, ligand_seed=0):
-    x, bonds, nbr = random_tree(rng, n_atoms, box=box)
+                mass=MASS_C, ligand_seed=0, far_sep=None):
+    x, bonds, nbr = random_tree(rng, n_atoms, box=box, far_sep=far_sep)
     x32 = x.astype(np.float32)
     xd = x32.astype(np.float64)
     angles, tors = angles_and_torsions(n_atoms, bonds, nbr)

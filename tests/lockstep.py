@@ -40,14 +40,15 @@ def exchange_margins(ol, comps, rep_of_state, sweep, seed, lig):
     return np.array(out) if out else np.array([np.inf])
 
 
-def lockstep(ctx, og, checked, seed, n_sweeps, nleap, label):
+def lockstep(ctx, og, checked, seed, n_sweeps, nleap, label, pairs=None):
     """Run n_sweeps single sweeps of every ligand in ctx (exchange every
     sweep) and check each (ligand_id, Ligand) pair of `checked` against its
-    own oracle sampler.  Returns, per checked ligand, the number of sweeps
-    whose decisions were all clear of the rounding margin."""
+    own oracle sampler (pairs: {ligand_id: pair parameters} of ligands whose
+    pair terms are in the energy).  Returns, per checked ligand, the number
+    of sweeps whose decisions were all clear of the rounding margin."""
     samplers = []
     for lid, lig in checked:
-        ol = oracle.OLigand(lig)
+        ol = oracle.OLigand(lig, pairs=(pairs or {}).get(lid))
         samplers.append((lid, lig, ol, oracle.Sampler(
             og, ol, seed=seed, lig_id=lid, x0=lig.x0)))
     n_clear = {lid: 0 for lid, _ in checked}

@@ -14,8 +14,11 @@ for the differences' own truncation and rounding)."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from gpu_util import dev, make_context, print_case, require_gpu, torch
+from lockstep import lockstep
+from oracle import external as Ex
 from oracle import pairs as O
 
 pytestmark = pytest.mark.gpu
@@ -154,4 +157,92 @@ def test_pair_setup_errors():
     bad["exclusions"] = np.array([[0, lig.n_atoms]])
     with pytest.raises(pkg.BPMFError):
         ctx.pair_setup(lid, bad)
+    ctx.close()
+
+
+# --------------------------------------------------------------------------
+# pair terms inside the sampled energy (bpmf_pair_sample): the Full
+# pathway's ligand energy in HMC, exchange, u_kn and the rigid moves
+# --------------------------------------------------------------------------
+
+def _full_pathway_system(n=24, K=6, seed=31):
+    """A ligand grown without nonbonded clashes (atoms three or more bonds
+    apart at least 3 A apart, 2.6 A above 32 atoms), its pair parameters,
+    and a 64^3 receptor
+    grid of 300 point atoms kept 3 A from its atoms."""
+    rng = np.random.default_rng(seed)
+    box, sep = (10.0, 3.0) if n <= 32 else (12.0, 2.6)
+    lig = synth.make_ligand(rng, n, K, box=box, far_sep=sep)
+    nn, h = 64, 0.25
+    edge = (nn - 1) * h
+    pts, q, sig, eps = synth.make_receptor(np.random.default_rng(seed + 1),
+                                           300, edge, 0.3 * edge,
+                                           avoid_xyz=lig.x0[0])
+    nodes = synth.grids_from_points(pts, q, sig, eps, nn, h)
+    grid = synth.Grid((nn,) * 3, (-(nn - 1) * h / 2,) * 3, h, (4, 0, 0),
+                      nodes)
+    return grid, lig, synth.pair_params(lig, seed=seed)
+
+
+@pytest.mark.parametrize("n,waves", [(24, 0), (24, 2), (70, 0)])
+def test_pair_terms_in_the_sampled_energy(n, waves):
+    """Components after switching the terms on, lock-step sweeps with them
+    (HMC force and energy, exchange, records), u_kn of samples, external
+    moves, and switching them off again, each against the oracle with the
+    same pair terms in the ligand's energy."""
+    print_case("pairs in the energy", n, waves)
+    g, lig, p = _full_pathway_system(n)
+    og = oracle.OGrid(g)
+    on, off = oracle.OLigand(lig, pairs=p), oracle.OLigand(lig)
+    ctx, (lid,) = make_context(g, [lig], seed=17)
+    ctx.set_waves(waves)
+    ctx.pair_setup(lid, p)
+    ctx.pair_sample(lid, True)
+
+    def check_comps(ol):
+        st = ctx.get_replicas(lid)
+        c, m = oracle.components(og, ol, st["x"])
+        assert np.all(np.abs(st["comps"] - c) <= 1e-5 * m.sum(1)[:, None] +
+                      1e-9)
+
+    check_comps(on)
+    n_clear = lockstep(ctx, og, [(lid, lig)], 17, 3, 8, "pairs",
+                       pairs={lid: p})
+    assert n_clear[lid] >= 1
+    # u_kn of perturbed configurations
+    rng = np.random.default_rng(3)
+    xs = (lig.x0[0][None] + rng.normal(scale=0.15, size=(12, n, 3))
+          ).astype(np.float32)
+    u = ctx.energy_matrix(lid, dev(xs, torch.float32)).cpu().numpy()
+    u64 = oracle.ukn(og, on, xs)
+    _, mags = oracle.components(og, on, xs)
+    beta = 1.0 / (oracle.R_GAS * lig.T)
+    assert np.all(np.abs(u - u64) <= 1e-5 * beta[:, None] *
+                  mags.sum(1)[None, :] + 1e-12)
+    # external moves (rigid: the pair energy is the cached one)
+    st = ctx.get_replicas(lid)
+    ctx.external_move(lid, n_moves=3, k_max=lig.n_states, sigma=0.3)
+    st2 = ctx.get_replicas(lid)
+    checked = 0
+    for r in range(lig.n_states):
+        k = st["state_of_replica"][r]
+        xo, n_acc, lns = Ex.external_moves(og, on, st["x"][r], k, 17, lid, r,
+                                           st["counter"], 3, 0.3)
+        if min(abs(lu - la) for la, lu in lns) < 5e-2:
+            continue
+        checked += 1
+        assert np.max(np.abs(st2["x"][r] - xo)) < 2e-4, r
+    assert checked >= 2
+    ctx.pair_sample(lid, False)
+    check_comps(off)
+    ctx.close()
+
+
+def test_pair_sample_needs_parameters():
+    print_case("pair_sample errors")
+    g, lig, p = _full_pathway_system(12, K=2)
+    ctx, (lid,) = make_context(g, [lig], seed=1)
+    with pytest.raises(RuntimeError, match="no pair parameters"):
+        ctx.pair_sample(lid, True)
+    ctx.pair_sample(lid, False)   # nothing to take out
     ctx.close()

@@ -138,3 +138,92 @@ def test_fd_forces_of_a_coulomb_pair():
     f = O.K_COULOMB * 0.25 / r ** 2
     assert F[1, 0] == pytest.approx(f, rel=1e-8)
     assert F[0, 0] == pytest.approx(-f, rel=1e-8)
+
+
+# --------------------------------------------------------------------------
+# the pair terms inside the sampled energy (oracle.c): the same definition
+# as the pair oracle above, its forces, and the integrator with them
+# --------------------------------------------------------------------------
+
+def _pair_system(n=12, seed=5, K=2):
+    import synth
+    lig = synth.make_ligand(np.random.default_rng(seed), n, K, box=10.0,
+                            far_sep=3.0)
+    p = synth.pair_params(lig, seed=seed)
+    return lig, p
+
+
+def _oracle_params(p, n):
+    ex, o4 = O.masks(n, p["exclusions"], p["pairs14"])
+    q = dict(p)
+    q.update(excluded=ex, one_four=o4)
+    return q
+
+
+def _zero_grid(n=4):
+    import synth
+    nodes = np.zeros((n, n, n, 3), np.float32)
+    return synth.Grid((n, n, n), (-1.0,) * 3, 0.5, (4, 0, 0), nodes)
+
+
+@pytest.mark.parametrize("n", [12, 30])
+def test_c_pair_energy_is_the_pair_oracle(oracle_lib, n):
+    import oracle
+    lig, p = _pair_system(n, seed=n)
+    og = oracle.OGrid(_zero_grid())
+    on, off = oracle.OLigand(lig, pairs=p), oracle.OLigand(lig)
+    q = _oracle_params(p, n)
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        x = lig.x0[0] + rng.normal(scale=0.2, size=(n, 3))
+        t1, m1, _ = oracle.energy(og, on, np.zeros(3), x, forces=False)
+        t0, m0, _ = oracle.energy(og, off, np.zeros(3), x, forces=False)
+        e = O.energy_terms(x, q)
+        assert abs((t1[3] - t0[3]) - e.sum()) <= 1e-12 * np.abs(e).sum()
+        assert np.all(t1[:3] == t0[:3]) and np.all(t1[4:] == t0[4:])
+        assert m1[3] - m0[3] >= abs(e.sum()) * (1 - 1e-12)
+
+
+def test_c_pair_forces_are_minus_the_gradient(oracle_lib):
+    import oracle
+    n = 10
+    lig, p = _pair_system(n, seed=3)
+    og = oracle.OGrid(_zero_grid())
+    on, off = oracle.OLigand(lig, pairs=p), oracle.OLigand(lig)
+    q = _oracle_params(p, n)
+    x = lig.x0[0] + np.random.default_rng(2).normal(scale=0.2, size=(n, 3))
+    _, _, F1 = oracle.energy(og, on, np.zeros(3), x)
+    _, _, F0 = oracle.energy(og, off, np.zeros(3), x)
+    Fp = F1 - F0
+    ref = np.zeros_like(x)
+    h = 1e-4
+    for i in range(n):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            ref[i, a] = -(O.energy_terms(xp, q).sum() -
+                          O.energy_terms(xm, q).sum()) / (2 * h)
+    assert np.max(np.abs(Fp - ref)) <= 1e-6 * np.max(np.abs(ref)) + 1e-8
+    # rigid-motion invariance of the pair energy: no net force or torque
+    s = np.max(np.abs(Fp))
+    assert np.max(np.abs(Fp.sum(0))) < 1e-6 * s
+    assert np.max(np.abs(np.cross(x, Fp).sum(0))) < 1e-5 * s
+
+
+def test_verlet_with_pair_terms_is_reversible_and_second_order(oracle_lib):
+    import oracle
+    lig, p = _pair_system(12, seed=7)
+    og, ol = oracle.OGrid(_zero_grid()), oracle.OLigand(lig, pairs=p)
+    x0 = lig.x0[0].astype(np.float64)
+    v0 = oracle.momenta(ol, 600.0, 7, 0, 0, 0)
+    x1, v1, H, _ = oracle.verlet(og, ol, np.zeros(3), 0.5, 40, x0, v0)
+    x2, v2, _, _ = oracle.verlet(og, ol, np.zeros(3), 0.5, 40, x1, -v1)
+    assert np.max(np.abs(x2 - x0)) < 1e-9 and np.max(np.abs(v2 + v0)) < 1e-9
+    errs = []
+    for dt in (0.4, 0.2, 0.1):
+        n = int(round(8.0 / dt))
+        _, _, H, _ = oracle.verlet(og, ol, np.zeros(3), dt, n, x0, v0)
+        errs.append(abs(H[1] - H[0]))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0, errs
