@@ -54,17 +54,15 @@ GRID_BYTES_PER_EVAL = 96  # 8 corners x 3 channels x 4 B
 # kernel and workload: one sweep launch (at the given wavefronts per
 # replica), one harness launch, one energy-matrix call (its launches
 # summed); valid only while the kernel sources hash to TRAFFIC_SOURCES
-TRAFFIC_SOURCES = "3ccfd885c7901473"
+TRAFFIC_SOURCES = "7b5e06cf47d1a0f8"
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
+    ("k_hmc_sweep", "c5_large_batched"):
+        {"waves": 4, "fetch_kib": 9157.522, "write_kib": 4431.213},
     ("k_hmc_sweep", "c2_plain_production"):
-        {"waves": None, "fetch_kib": 766.013, "write_kib": 201.280},
+        {"waves": None, "fetch_kib": 768.186, "write_kib": 198.214},
     ("k_hmc_sweep", "c3_batched_uneven"):
-        {"waves": 2, "fetch_kib": 36443.062, "write_kib": 24113.849},
-    ("k_grid_eval", "c3_batched_uneven"):
-        {"fetch_kib": 3389659.578, "write_kib": 3383700.000},
-    ("k_energy_matrix", "c3_batched_uneven"):
-        {"fetch_kib": 1134370.938, "write_kib": 427635.539},
+        {"waves": 2, "fetch_kib": 37662.407, "write_kib": 23628.451},
 }
 KERNEL_SOURCES = ("device.h", "kernels.hip", "internal.h")
 
