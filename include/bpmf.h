@@ -108,7 +108,7 @@ BPMF_API int bpmf_sync(bpmf_ctx* ctx);
  *   to edge), with zero normal gradient.
  * ------------------------------------------------------------------------ */
 typedef struct {
-  int nx, ny, nz;      /* nodes per axis, each >= 2 */
+  int nx, ny, nz;      /* nodes per axis, each 2..2^24 */
   int n_channels;      /* 1..BPMF_MAX_CHANNELS */
   double origin[3];    /* position of node (0,0,0) */
   double spacing;      /* node spacing, > 0 */

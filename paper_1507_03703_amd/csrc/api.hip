@@ -438,6 +438,10 @@ extern "C" int bpmf_grid_upload(bpmf_ctx* c, const bpmf_grid_desc* d,
   if (d->nx < 2 || d->ny < 2 || d->nz < 2)
     return fail(BPMF_E_INVAL, "grid needs >= 2 nodes per axis (got %d %d %d)",
                 d->nx, d->ny, d->nz);
+  if (d->nx > (1 << 24) || d->ny > (1 << 24) || d->nz > (1 << 24))
+    return fail(BPMF_E_INVAL,
+                "grid has more than 2^24 nodes on an axis (%d %d %d)", d->nx,
+                d->ny, d->nz);
   if (d->n_channels < 1 || d->n_channels > BPMF_MAX_CHANNELS)
     return fail(BPMF_E_INVAL, "n_channels %d outside 1..%d", d->n_channels,
                 BPMF_MAX_CHANNELS);

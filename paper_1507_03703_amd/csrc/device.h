@@ -200,12 +200,14 @@ __device__ __forceinline__ void grid_fetch(const GridDev& g, float px,
   k.ax = grid_axis(px, g.ox, g.inv_h, g.nx);
   k.ay = grid_axis(py, g.oy, g.inv_h, g.ny);
   k.az = grid_axis(pz, g.oz, g.inv_h, g.nz);
-  const size_t cell =
-      ((size_t)k.az.i * (g.ny - 1) + k.ay.i) * (size_t)(g.nx - 1) + k.ax.i;
+  // fewer than 2^31 cells and at most 2^24 nodes per axis (checked at
+  // upload): 24-bit products, a 32-bit index
+  const unsigned int cell =
+      __umul24(__umul24(k.az.i, g.ny - 1) + k.ay.i, g.nx - 1) + k.ax.i;
   // the grid lives in global memory: say so, so that the gathers are
   // global (not flat) loads and LDS waits do not wait on them
   typedef const f32x4 __attribute__((address_space(1))) gvec;
-  gvec* rec = (gvec*)g.cells + cell * (cell_stride(C) / 4);
+  gvec* rec = (gvec*)g.cells + (size_t)cell * (cell_stride(C) / 4);
   float b[8 * C];
 #pragma unroll
   for (int j = 0; j < 2 * C; ++j) {
@@ -297,38 +299,46 @@ __device__ __forceinline__ float3 scale3(float s, float3 a) {
 // atomic.  Integer addition is
 // associative, so the sums do not depend on the order in which threads
 // arrive and results stay bitwise reproducible.  Quantisation is 1.5e-5
-// kJ/mol/A per contribution; a contribution is clamped to +-32767 kJ/mol/A
-// (a bonded force that large only arises on a diverging trajectory, which
-// the exact energy rejects; leapfrog with any deterministic force keeps HMC
-// exact).  The term functions hand over contributions already in units of
-// 2^-16 (their force factor carries the 2^16, and scaling by a power of two
-// commutes with rounding, so the units are exact); a NaN contribution
-// becomes the lower clamp (its energy is NaN too, so the move is rejected).
+// kJ/mol/A per contribution; a contribution saturates at the int32 range,
+// +-32768 kJ/mol/A (a bonded force that large only arises on a diverging
+// trajectory, which the exact energy rejects; leapfrog with any
+// deterministic force keeps HMC exact).  The term functions hand over
+// contributions already in units of 2^-16 (their force factor carries the
+// 2^16, and scaling by a power of two commutes with rounding, so the units
+// are exact); a NaN contribution becomes 0 (its energy is NaN too, so the
+// move is rejected).
 constexpr float kFix = 65536.0f;          // 2^16
 constexpr float kFixInv = 1.0f / 65536.0f;
-constexpr float kFixMax = 32767.0f;
-constexpr float kFixLim = kFixMax * kFix;  // 2^31 - 2^16, exact in float
 
-// rounds toward zero (one conversion instruction; the clamp keeps it in
-// range)
+// rounds toward zero and saturates out-of-range values, NaN to 0: the
+// hardware conversion, written out because a C++ float-to-int conversion
+// of an out-of-range value is undefined
 __device__ __forceinline__ unsigned int to_fix_units(float f) {
-  return (unsigned int)(int)fminf(fmaxf(f, -kFixLim), kFixLim);
+  int r;
+  asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(f));
+  return (unsigned int)r;
 }
 
 __device__ __forceinline__ float from_fix(unsigned int a) {
   return (float)(int)a * kFixInv;
 }
 
+// a word of LDS, addressed with 32-bit arithmetic
+typedef __attribute__((address_space(3))) unsigned int lds_u32;
+
 struct Slots {
-  unsigned int* acc;  // kAccCopies x n x 3
-  int stride;         // 3 n: words per copy
+  lds_u32* acc;  // kAccCopies x n x 3
+  int stride;    // 3 n: words per copy
   // f: force contribution in units of 2^-16 kJ/mol/A, into the lane's copy
   __device__ __forceinline__ void put(int atom, float3 f) const {
-    unsigned int* a =
-        acc + (threadIdx.x & (kAccCopies - 1)) * stride + 3 * atom;
-    atomicAdd(&a[0], to_fix_units(f.x));
-    atomicAdd(&a[1], to_fix_units(f.y));
-    atomicAdd(&a[2], to_fix_units(f.z));
+    lds_u32* a = acc + __umul24(threadIdx.x & (kAccCopies - 1), stride) +
+                 __umul24(atom, 3);
+    __hip_atomic_fetch_add(a, to_fix_units(f.x), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(a + 1, to_fix_units(f.y), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(a + 2, to_fix_units(f.z), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 };
 
@@ -359,14 +369,39 @@ template <bool FORCES>
 __device__ __forceinline__ float bond_term(const float4* pos, int2 ij,
                                            float2 par, const Slots& sl) {
   const float3 d = sub(f3(pos[atom_of(ij.x)]), f3(pos[atom_of(ij.y)]));
-  const float r = hsqrt(dot(d, d));
+  const float d2 = dot(d, d), ir = hrsq(d2);
+  const float r = d2 > 0.f ? d2 * ir : 0.f;
   const float dr = r - par.y;
   if (FORCES) {
-    const float f = -2.0f * par.x * dr * rcp(r) * kFix;
+    const float f = -2.0f * par.x * dr * ir * kFix;
     sl.put(slot_of(ij.x), scale3(f, d));
     sl.put(slot_of(ij.y), scale3(-f, d));
   }
   return par.x * dr * dr;
+}
+
+// atan2(y, x) for y >= 0 (an angle in [0, pi]): the octant's ratio
+// t = min/max in [0, 1] and atan t = t P(t^2), P of degree 8 fitted to
+// atan(t)/t on [0, 1] by reweighted least squares (fit_atan.py beside the
+// package; 6e-9 absolute in exact arithmetic, within 1e-7 in float); 0 when
+// both arguments are 0
+__device__ __forceinline__ float angle_atan2(float y, float x) {
+  const float ax = fabsf(x);
+  const float lo = fminf(y, ax), hi = fmaxf(y, ax);
+  const float t = hi > 0.f ? lo * rcp(hi) : 0.f;
+  const float s = t * t;
+  float p = 2.456722575e-03f;
+  p = fmaf(p, s, -1.440135319e-02f);
+  p = fmaf(p, s, 3.978122321e-02f);
+  p = fmaf(p, s, -7.234858229e-02f);
+  p = fmaf(p, s, 1.049894713e-01f);
+  p = fmaf(p, s, -1.416122975e-01f);
+  p = fmaf(p, s, 1.998590691e-01f);
+  p = fmaf(p, s, -3.333259704e-01f);
+  p = fmaf(p, s, 9.999998864e-01f);
+  float th = p * t;
+  th = y > ax ? 1.57079632679f - th : th;
+  return x < 0.f ? 3.14159265359f - th : th;
 }
 
 // K (theta - theta0)^2, theta = atan2(|a x b|, a.b), a = xi-xj, b = xk-xj
@@ -377,17 +412,20 @@ __device__ __forceinline__ float angle_term(const float4* pos, int4 ijk,
   const float3 a = sub(f3(pos[atom_of(ijk.x)]), xj);
   const float3 b = sub(f3(pos[atom_of(ijk.z)]), xj);
   const float3 c = cross(a, b);
-  const float s = hsqrt(dot(c, c)), co = dot(a, b);
-  const float th = atan2f(s, co);
+  const float cc = dot(c, c), is = hrsq(cc), co = dot(a, b);
+  const float s = cc > 0.f ? cc * is : 0.f;
+  const float th = angle_atan2(s, co);
   const float dth = th - par.y;
   if (FORCES) {
-    const float la = hsqrt(dot(a, a)), lb = hsqrt(dot(b, b));
+    const float aa = dot(a, a), bb = dot(b, b);
+    const float ila = hrsq(aa), ilb = hrsq(bb);
     const float dE = 2.0f * par.x * dth;
-    const float ila = rcp(la), ilb = rcp(lb);
-    const float cth = co * ila * ilb, isth = la * lb * rcp(s);
+    const float cth = co * ila * ilb;
     const float3 ah = scale3(ila, a), bh = scale3(ilb, b);
-    // d theta / d xi = (cos a^ - b^) / (|a| sin), d theta / d xk likewise
-    const float ci = dE * isth * ila * kFix, ck = dE * isth * ilb * kFix;
+    // d theta / d xi = (cos a^ - b^) / (|a| sin), d theta / d xk likewise;
+    // 1 / (|a| sin) = |b| / |a x b|
+    const float ci = dE * (bb * ilb) * is * kFix;
+    const float ck = dE * (aa * ila) * is * kFix;
     const float3 fi = make_float3(-ci * (cth * ah.x - bh.x),
                                   -ci * (cth * ah.y - bh.y),
                                   -ci * (cth * ah.z - bh.z));
@@ -415,7 +453,8 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
   const float3 xk = f3(pos[atom_of(ijkl.z)]), xl = f3(pos[atom_of(ijkl.w)]);
   const float3 b1 = sub(xj, xi), b2 = sub(xk, xj), b3 = sub(xl, xk);
   const float3 n1 = cross(b1, b2), n2 = cross(b2, b3);
-  const float lb2 = hsqrt(dot(b2, b2));
+  const float b22 = dot(b2, b2), ilb2 = hrsq(b22);
+  const float lb2 = b22 * ilb2;
   const float xx = dot(n1, n2), yy = lb2 * dot(b1, n2);
   // par: V/2, n, cos gamma, sin gamma; integer multiplicity in the sign-free
   // upper bits is not needed: n is an integer 1..6 (checked at setup)
@@ -435,7 +474,6 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
   if (FORCES) {
     const float dE = -par.x * par.y * snm;
     const float in1 = rcp(dot(n1, n1)), in2 = rcp(dot(n2, n2));
-    const float ilb2 = rcp(lb2);
     const float p12 = dot(b1, b2) * ilb2 * in1;
     const float p23 = dot(b2, b3) * ilb2 * in2;
     const float3 gi = scale3(-lb2 * in1, n1);
@@ -772,7 +810,8 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   const int n_atom_waves = (n + kWave - 1) / kWave;
   const bool wave_has_atoms = wv < n_atom_waves;
   const int first = bonded_first_wave(W, n_atom_waves);
-  if (owner) sh.pos[tid] = make_float4(x[0], x[1], x[2], 0.f);
+  // positions with the atom's mass (w), for the centre of mass
+  if (owner) sh.pos[tid] = make_float4(x[0], x[1], x[2], m);
   // grid gathers: before the barrier when the atom waves also take bonded
   // terms (the loads fly during them), after it when they do not (the
   // bonded waves then start without waiting for the address work)
@@ -789,8 +828,10 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
       const int ntc = (L.nt + kWave - 1) / kWave;
       const int nac = (L.na + kWave - 1) / kWave;
       const int j0 = sh.sched[bw], j1 = sh.sched[bw + 1];
+      // the wavefront's chunk list, one entry per lane, read once
+      const int mine = j0 + lane < j1 ? sh.sched[9 + j0 + lane] : 0;
       for (int j = j0; j < j1; ++j) {
-        const int ch = sh.sched[9 + j];
+        const int ch = __builtin_amdgcn_readlane(mine, j - j0);
         if (ch < ntc) {
           const int t = ch * kWave + lane;
           if (t < L.nt)
@@ -809,8 +850,10 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
     }
   }
 
-  // atom waves: mass-weighted position sums (restraint) and the grid
-  // values and gradients, beside the bonded waves
+  // atom waves: mass-weighted position sums of all atoms (restraint; with
+  // two atom waves each sums both halves from the staged positions, lane l
+  // taking atoms l and l + 64, so that both hold the same total without a
+  // barrier) and the grid values and gradients, beside the bonded waves
   float psi[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) psi[c] = 0.f;
@@ -818,14 +861,28 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   float de[C][3];
   float px = 0.f, py = 0.f, pz = 0.f;
   if (wave_has_atoms) {
-    px = m * x[0];
-    py = m * x[1];
-    pz = m * x[2];
+    if (n_atom_waves == 1) {
+      px = m * x[0];
+      py = m * x[1];
+      pz = m * x[2];
+    } else {
+      const float4 a = sh.pos[lane];
+      px = a.w * a.x;
+      py = a.w * a.y;
+      pz = a.w * a.z;
+      if (lane + kWave < n) {
+        const float4 b = sh.pos[lane + kWave];
+        px += b.w * b.x;
+        py += b.w * b.y;
+        pz += b.w * b.z;
+      }
+    }
     wave_sumf3(px, py, pz);
-    if (lane == 0) {
-      sh.com[3 * wv] = px;
-      sh.com[3 * wv + 1] = py;
-      sh.com[3 * wv + 2] = pz;
+    // for the waves without atoms (restraint energy)
+    if (tid == 0) {
+      sh.com[0] = px;
+      sh.com[1] = py;
+      sh.com[2] = pz;
     }
     float e[C];
     grid_finish<C, FORCES>(g, cn, sc, e, de);
@@ -837,21 +894,18 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   float epair = 0.f, fpair[3] = {0.f, 0.f, 0.f};
   const bool pairs = PAIRS && L.pairs_on;
   if (pairs) pair_stage<FORCES>(sh, L.pair, n, tid, epair, fpair);
-  // centre of mass offset from the site (fixed-order sum of the atom waves'
-  // partials; with one atom wave its own sums are the total)
+  // centre of mass offset from the site (an atom wave's own total, which
+  // wave 0 publishes for the others)
   float cx, cy, cz;
   auto com_offset = [&]() {
-    if (n_atom_waves == 1 && wv == 0) {
+    if (wave_has_atoms) {
       cx = px;
       cy = py;
       cz = pz;
     } else {
-      cx = cy = cz = 0.f;
-      for (int q = 0; q < n_atom_waves; ++q) {
-        cx += sh.com[3 * q];
-        cy += sh.com[3 * q + 1];
-        cz += sh.com[3 * q + 2];
-      }
+      cx = sh.com[0];
+      cy = sh.com[1];
+      cz = sh.com[2];
     }
     cx = cx * L.inv_total_mass - L.site[0];
     cy = cy * L.inv_total_mass - L.site[1];
@@ -859,26 +913,24 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   };
   if (FORCES) {
     // restraint force -(m_i/M) k (d - d0) (c - c0)/d, before the barrier
-    // when this wave's sums are the whole centre of mass
     float fr = 0.f;
-    auto add_restraint = [&]() {
+    if (wave_has_atoms) {
       com_offset();
-      const float d = sqrtf(cx * cx + cy * cy + cz * cz);
+      const float d = hsqrt(cx * cx + cy * cy + cz * cz);
       const float excess = d - L.d0;
-      fr = excess > 0.f ? -L.krest * excess / d * L.inv_total_mass : 0.f;
+      fr = excess > 0.f ? -L.krest * excess * rcp(d) * L.inv_total_mass
+                        : 0.f;
       restraint_force(fr, m, cx, cy, cz, ge);
-    };
-    if (n_atom_waves == 1 && wv == 0) add_restraint();
+    }
     block_sync();
     if (owner) {
-      if (n_atom_waves > 1) add_restraint();
       // bonded forces: read and clear the atom's fixed-point accumulators
       // (the next evaluation adds into them only after its first barrier);
       // the copies' integer sum does not depend on which lane used which
       unsigned int s3[3] = {0u, 0u, 0u};
 #pragma unroll
       for (int q = 0; q < kAccCopies; ++q) {
-        unsigned int* a3 = sh.sl.acc + q * sh.sl.stride + 3 * tid;
+        lds_u32* a3 = sh.sl.acc + q * sh.sl.stride + 3 * tid;
         s3[0] += a3[0];
         s3[1] += a3[1];
         s3[2] += a3[2];

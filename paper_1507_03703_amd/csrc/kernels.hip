@@ -25,7 +25,7 @@ __device__ __forceinline__ Shared carve(unsigned char* raw, const LigDev& L,
   // offset arithmetic on the LDS base keeps the pointers in LDS space;
   // force accumulators exist when n_acc > 0 (force-evaluating kernels)
   const int acc0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
-  sh.sl = Slots{reinterpret_cast<unsigned int*>(raw + acc0), 3 * n_acc};
+  sh.sl = Slots{(lds_u32*)(raw + acc0), 3 * n_acc};
   for (int i = tid; i < kAccCopies * 3 * n_acc; i += W * kWave)
     sh.sl.acc[i] = 0u;
   stage_topology(L, raw + acc0 + acc_lds_bytes(n_acc), sh, tid, W * kWave);

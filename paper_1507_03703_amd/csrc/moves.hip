@@ -50,7 +50,7 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
     sh.red = reinterpret_cast<double*>(smem + 16 * kWave * W);
     sh.com = reinterpret_cast<float*>(smem + 16 * kWave * W + 8 * W * kRedMax);
     const int acc0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
-    sh.sl = Slots{reinterpret_cast<unsigned int*>(smem + acc0), 0};  // no forces
+    sh.sl = Slots{(lds_u32*)(smem + acc0), 0};  // no forces
     stage_topology(L, smem + acc0, sh, tid, W * kWave);
     __syncthreads();
   }
