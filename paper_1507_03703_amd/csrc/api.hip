@@ -900,7 +900,14 @@ int mlp_scratch(bpmf_ctx* c, int B, MlpBufs* b);
 int build_pose_tables(bpmf_ctx* c);
 int refresh_pose_weights(bpmf_ctx* c);
 int pair_sample_refresh(bpmf_ctx* c, int lid);
-int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st);
+// closing a unit of neighbour-scheme sweeps inside the pose-move launches:
+// the ligands [l0, l1) whose run ends there and the run's parameters
+struct UnitClose {
+  int l0 = 0, l1 = 0;
+  int exchange_every = 0, sample_every = 0;
+};
+int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st,
+                    const UnitClose* close = nullptr);
 int external_move_ligand(bpmf_ctx* c, int lid, int n_moves, int k_max,
                          double sigma, hipStream_t st);
 int check_external(int n_moves, int k_max, double sigma);
@@ -1000,6 +1007,16 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
                                   tail.sample_every, c->seed, st));
     return BPMF_OK;
   };
+  // units closed by pose moves alone, with every ligand of the call
+  // carrying a proposal: the run's end and the next run's start are folded
+  // into the pose-move launches (pose_move_batch with a UnitClose)
+  bool fused = a->pose_move_every > 0 && NX == 0 && tail.scheme == 0;
+  for (int l = l0; l < l1 && fused; ++l) fused = c->ligs[l].has_prop;
+  UnitClose uc;
+  uc.l0 = l0;
+  uc.l1 = l1;
+  uc.exchange_every = tail.exchange_every;
+  uc.sample_every = tail.sample_every;
   // one pose move of every ligand that has a proposal (when asked), then
   // the external moves of every ligand
   auto enqueue_pose = [&](hipStream_t st) -> int {
@@ -1063,16 +1080,26 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
     }
     const int units = a->n_sweeps / P, rest = a->n_sweeps % P;
     auto unit = [&](hipStream_t st) -> int {
+      if (fused) {
+        for (int s = 0; s < P; ++s) {
+          const int r = enqueue_sweep(st);
+          if (r) return r;
+        }
+        return pose_move_batch(c, only, st, &uc);
+      }
       const int r = enqueue_run(st, P);
       return r ? r : enqueue_pose(st);
     };
+    // a fused unit's first sweep reads the run state its predecessor's
+    // pose moves leave; the first unit's comes from a begin launch
+    if (fused && units > 0) HIP_TRY(launch_sweep_begin(dl, nl, c->stream));
     if (chunk > 0 && units > 0) {
       int sg[2];
       memcpy(sg, &a->external_sigma, sizeof(sg));
       const int key[bpmf_ctx::kKey] = {
           a->n_leapfrog, a->exchange_every, a->exchange_scheme, a->max_sep,
-          a->sample_every, 0, P, a->pose_move_every, NX, a->external_k_max,
-          sg[0], sg[1], n_sub, only};
+          a->sample_every, fused ? -1 : 0, P, a->pose_move_every, NX,
+          a->external_k_max, sg[0], sg[1], n_sub, only};
       if ((rc = ensure_graph(key, unit))) return rc;
       for (int u = 0; u < units; ++u)
         if ((rc = launch_timed(P, [&]() -> int {
@@ -2546,7 +2573,15 @@ int refresh_pose_weights(bpmf_ctx* c) {
 // with a proposal): features, the network and the move, each one launch
 // over all of the ligands (the move one per wavefront class).  The tables
 // and the network's scratch must be ready (not rebuilt under capture).
-int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st) {
+// One pose move of every replica of every ligand with a proposal (or of
+// ligand `only`): the network on the current configurations, then the
+// moves.  close: the run of sweeps before it ends in the network launch
+// (its extra blocks apply the last exchange and record of ligands
+// [l0, l1)) and the next one starts in the move launch, so that no begin or
+// finish kernel brackets the unit; every ligand in that range must have a
+// proposal.
+int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st,
+                    const UnitClose* close) {
   int t0 = 0, nt = c->n_ptasks, g0 = 0, ng = c->n_pgroups;
   if (only >= 0) {
     const LigHost& h = c->ligs[only];
@@ -2560,9 +2595,12 @@ int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st) {
   MlpBufs b;
   int rc = mlp_scratch(c, c->n_ptasks, &b);
   if (rc) return rc;
-  HIP_TRY(launch_pose_features_tasks(c->d_ligs, c->d_props, c->d_ptasks + t0,
-                                     nt, b.bf, st));
-  HIP_TRY(launch_mlp_forward_groups(c->d_pgroups + g0, ng, b.bf, b.out, st));
+  const int n_fin = close ? close->l1 - close->l0 : 0;
+  HIP_TRY(launch_pose_network(
+      c->d_pgroups + g0, ng, c->d_ligs, c->d_props, c->d_ptasks, b.out,
+      close ? c->d_ligs + close->l0 : nullptr, n_fin,
+      close ? close->exchange_every : 0, close ? close->sample_every : 0,
+      c->seed, st));
   // one launch at the widest class in the range: the move is latency-bound
   // (one workgroup per replica), and narrower ligands run with idle
   // wavefronts rather than in a launch of their own
@@ -2575,7 +2613,7 @@ int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st) {
   HIP_TRY(launch_pose_move(c->grid, c->d_ligs, c->d_props, c->d_ptasks + t0,
                            nt, b.out, 1 << qmax,
                            block_lds_bytes(1 << qmax, false, 0, 0, 0, 0),
-                           c->seed, st));
+                           c->seed, close != nullptr, st));
   return BPMF_OK;
 }
 }  // namespace

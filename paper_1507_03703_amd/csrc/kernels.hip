@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "deferred.h"
 #include "device.h"
 #include "internal.h"
 
@@ -364,158 +365,19 @@ __global__ __launch_bounds__(256) void k_sweep_tail(
              sample_every, seed);
 }
 
-// ----------------------------------------------------------------------------
-// neighbour-scheme exchange deferred into the next sweep
-// ----------------------------------------------------------------------------
-// State after the exchange that ends sweep s - 1 of the replica that held
-// state a during it, from buffer `pin` (components indexed by state).  Only
-// the replica's own pair (a, a +- 1) matters in the even/odd scheme; both
-// replicas of a pair evaluate the same expression as attempt_pair on the same
-// numbers and take the same decision.  `stats`: count the attempt (once per
-// pair, by its lower state).
-#pragma clang fp contract(off)
-
-// The neighbour pair (lo, hi) of state a in the exchange that ends sweep
-// s - 1, if that exchange is due and a has a partner.
-struct Pair {
-  int lo, hi;
-  bool active;
-};
-__device__ __forceinline__ Pair own_pair(int K, int a, unsigned long long s,
-                                         int exchange_every) {
-  Pair p{a, a, false};
-  if (exchange_every <= 0 || s == 0ull || K < 2) return p;
-  const unsigned long long sw = s - 1ull;
-  if (sw % (unsigned long long)exchange_every != 0ull) return p;
-  const int a0 = (int)(sw & 1ull);
-  if (a < a0) return p;
-  if (((a - a0) & 1) == 0) {
-    if (a + 1 >= K) return p;
-    p.lo = a;
-    p.hi = a + 1;
-  } else {
-    p.lo = a - 1;
-    p.hi = a;
-  }
-  p.active = true;
-  return p;
-}
-
-// Metropolis decision on pair p from buffer `pin` (attempt_pair's expression
-// on the same numbers), every operand loaded before the arithmetic.
-template <int C>
-__device__ bool pair_accepts(const LigDev& L, Pair p, int pin,
-                             unsigned long long s, uint64_t seed) {
-  constexpr int C1 = 1 + C;
-  auto sc = BPMF_GMEM(const double, L.scomp);
-  auto wd = BPMF_GMEM(const double, L.wd);
-  double clo[C1], chi[C1], wlo[C], whi[C];
-#pragma unroll
-  for (int e = 0; e < C1; ++e) {
-    clo[e] = sc[((size_t)pin * L.K + p.lo) * C1 + e];
-    chi[e] = sc[((size_t)pin * L.K + p.hi) * C1 + e];
-  }
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    wlo[c] = wd[p.lo * C + c];
-    whi[c] = wd[p.hi * C + c];
-  }
-  const double blo = BPMF_GMEM(const double, L.beta)[p.lo];
-  const double bhi = BPMF_GMEM(const double, L.beta)[p.hi];
-  // E_k(x) = U0 + sum_c w_kc Psi_c, channels in order
-  auto energy = [](const double* w, const double* cp) {
-    double E = cp[0];
-#pragma unroll
-    for (int c = 0; c < C; ++c) E += w[c] * cp[1 + c];
-    return E;
-  };
-  const double delta = blo * (energy(wlo, chi) - energy(wlo, clo)) +
-                       bhi * (energy(whi, clo) - energy(whi, chi));
-  const uint32_t purpose = (uint32_t)kExchange | (1u << 8);
-  const U4 o = draw(seed, (uint32_t)p.lo, L.id, 0, s - 1ull, purpose);
-  const double lnu = log(u01d(o.x));
-  return isfinite(delta) && (lnu < -delta);
-}
-
-__device__ int deferred_state(const LigDev& L, int a, unsigned long long s,
-                              int pin, int exchange_every, uint64_t seed,
-                              bool stats) {
-  const Pair p = own_pair(L.K, a, s, exchange_every);
-  if (!p.active) return a;
-  // the sweep kernels run 3 or 5 channels only
-  const bool ok = L.C == 5 ? pair_accepts<5>(L, p, pin, s, seed)
-                           : pair_accepts<3>(L, p, pin, s, seed);
-  if (stats && a == p.lo) {
-    atomicAdd(&L.ex_try[p.lo], 1ull);
-    if (ok) atomicAdd(&L.ex_acc[p.lo], 1ull);
-  }
-  return ok ? (a == p.lo ? p.hi : p.lo) : a;
-}
-#pragma clang fp contract(fast)
-
-// the exchange ending sweep s - 1 records a round when s % every == 0
-__device__ __forceinline__ bool record_due(unsigned long long s, int every) {
-  return every > 0 && s > 0ull && s % (unsigned long long)every == 0ull;
-}
-
 // Start of a run of neighbour-scheme sweeps: buffer (s-1)&1 from the
 // canonical state, nothing pending.  One block per ligand.
 __global__ __launch_bounds__(256) void k_sweep_begin(
     const LigDev* __restrict__ ligs) {
-  const LigDev& L = ligs[blockIdx.x];
-  const unsigned long long s = *L.counter, nrec = *L.n_rec;
-  const int pin = (int)((s - 1ull) & 1ull), K = L.K, C1 = 1 + L.C;
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    const int k = L.state_of_replica[r];
-    L.rsor[pin * K + r] = k;
-    L.rpend[pin * K + r] = 0;
-    L.rcnt[r] = s;
-    L.rnrec[r] = nrec;
-    for (int e = 0; e < C1; ++e)
-      L.scomp[((size_t)pin * K + k) * C1 + e] = L.comps[(size_t)r * C1 + e];
-  }
+  begin_ligand(ligs[blockIdx.x]);
 }
 
-// End of a run: apply the pending exchange and record of the last sweep and
-// write the canonical state maps, components and counters back.  One block
-// per ligand.
+// End of a run: the pending exchange and record of the last sweep, the
+// canonical state written back.  One block per ligand.
 __global__ __launch_bounds__(256) void k_sweep_finish(
     const LigDev* __restrict__ ligs, int exchange_every, int sample_every,
     uint64_t seed) {
-  const LigDev& L = ligs[blockIdx.x];
-  const unsigned long long s = L.rcnt[0];
-  const int pin = (int)((s - 1ull) & 1ull), K = L.K, C1 = 1 + L.C;
-  const bool pend = L.rpend[pin * K] != 0;
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    const int a = L.rsor[pin * K + r];
-    const int k =
-        pend ? deferred_state(L, a, s, pin, exchange_every, seed, true) : a;
-    L.state_of_replica[r] = k;
-    L.replica_of_state[k] = r;
-    for (int e = 0; e < C1; ++e)
-      L.comps[(size_t)r * C1 + e] = L.scomp[((size_t)pin * K + a) * C1 + e];
-  }
-  __syncthreads();
-  const unsigned long long rec = L.rnrec[0];
-  const bool record =
-      pend && record_due(s, sample_every) && rec < (unsigned long long)L.cap;
-  if (record) {
-    const int n3 = L.n * 3;
-    float* dx = L.samp_x + (size_t)rec * K * n3;
-    double* dc = L.samp_c + (size_t)rec * K * C1;
-    for (int q = threadIdx.x; q < K * n3; q += blockDim.x) {
-      const int k = q / n3, e = q - k * n3;
-      dx[q] = L.x[(size_t)L.replica_of_state[k] * n3 + e];
-    }
-    for (int q = threadIdx.x; q < K * C1; q += blockDim.x) {
-      const int k = q / C1, e = q - k * C1;
-      dc[q] = L.comps[(size_t)L.replica_of_state[k] * C1 + e];
-    }
-  }
-  if (threadIdx.x == 0) {
-    *L.counter = s;
-    *L.n_rec = record ? rec + 1ull : rec;
-  }
+  finish_ligand(ligs[blockIdx.x], exchange_every, sample_every, seed);
 }
 
 // ----------------------------------------------------------------------------

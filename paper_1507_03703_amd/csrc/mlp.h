@@ -96,26 +96,27 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n,
 hipError_t launch_pose_features(const LigDev* lig, const PropDev* prop,
                                 const float* xs, int64_t N, float* feats,
                                 float* poses, hipStream_t st);
-// features (not poses) of the current configurations of the n tasks (rows
-// t.row)
-hipError_t launch_pose_features_tasks(const LigDev* ligs,
-                                      const PropDev* props,
-                                      const PoseTask* tasks, int n,
-                                      float* feats, hipStream_t st);
-// the network for several groups of rows, each with its own parameters
-// (bf16 transposed weights; the outputs equal launch_mlp_forward's)
-hipError_t launch_mlp_forward_groups(const MlpGroup* groups, int n_groups,
-                                     const float* X, float* out,
-                                     hipStream_t st);
+// the network on the current configurations of tasks [row0, row0 + rows)
+// of every group (features computed in place), outputs only; n_fin further
+// blocks close the neighbour-scheme run of ligands fin[0..n_fin) as
+// launch_sweep_finish does
+hipError_t launch_pose_network(const MlpGroup* groups, int n_groups,
+                               const LigDev* ligs, const PropDev* props,
+                               const PoseTask* tasks, float* out,
+                               const LigDev* fin, int n_fin,
+                               int exchange_every, int sample_every,
+                               uint64_t seed, hipStream_t st);
 // the bf16 transposed copy of the weights of parameter vector P
 hipError_t launch_weights_bf16(const float* P, unsigned short* WT,
                                hipStream_t st);
 // one pose move of each of the n tasks (all of `waves` wavefronts; props
-// indexed by ligand table index, out by task row)
+// indexed by ligand table index, out by task row); begin_next: each task's
+// replica then starts the next run of neighbour-scheme sweeps
+// (begin_replica), in place of launch_sweep_begin
 hipError_t launch_pose_move(const GridDev& g, const LigDev* ligs,
                             const PropDev* props, const PoseTask* tasks,
                             int n, const float* out, int waves, int lds,
-                            uint64_t seed, hipStream_t st);
+                            uint64_t seed, bool begin_next, hipStream_t st);
 hipError_t launch_gather_batch(const float* feats, const float* poses,
                                int64_t N, int B, uint64_t seed,
                                uint64_t step, float* bf, float* bp,

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "deferred.h"
 #include "device.h"
 #include "internal.h"
 #include "mlp.h"
@@ -251,18 +252,47 @@ __device__ __forceinline__ void dense_rows_t(
   }
 }
 
-// the network for groups of up to 16 rows, group b with its own parameters
-// (bf16 transposed weights), outputs only
-__global__ __launch_bounds__(kFWaves * 64) void k_mlp_forward_t(
-    const MlpGroup* __restrict__ groups, const float* __restrict__ X,
-    float* __restrict__ out) {
+__device__ float dihedral_angle(const float* x, int4 q);
+
+// The network on the current configurations of pose-move tasks, for groups
+// of up to 16 rows (row m = task m), group b with its own parameters (bf16
+// transposed weights), outputs only; each row's features (sin and cos of
+// the conditioning torsions, the dihedral angles of the replica's
+// configuration) are computed in place, one thread per (row, torsion slot).
+// Blocks past n_groups close a run of neighbour-scheme sweeps instead, one
+// ligand of `fin` each (finish_ligand): the features need only positions,
+// which that leaves unchanged.
+__global__ __launch_bounds__(kFWaves * 64) void k_pose_network(
+    const MlpGroup* __restrict__ groups, int n_groups,
+    const LigDev* __restrict__ ligs, const PropDev* __restrict__ props,
+    const PoseTask* __restrict__ tasks, float* __restrict__ out,
+    const LigDev* __restrict__ fin, int exchange_every, int sample_every,
+    uint64_t seed) {
+  if ((int)blockIdx.x >= n_groups) {
+    finish_ligand(fin[blockIdx.x - n_groups], exchange_every, sample_every,
+                  seed);
+    return;
+  }
   __shared__ __align__(16) unsigned short S[2][kFRows][kFLd];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const MlpGroup gr = groups[blockIdx.x];
   const int row0 = gr.row0, B = gr.row0 + gr.rows;
-  for (int e = tid; e < kFRows * kNFeat; e += kFWaves * 64) {
-    const int r = e / kNFeat, k = e - r * kNFeat, m = row0 + r;
-    S[0][r][k] = bf16_bits(m < B ? X[(int64_t)m * kNFeat + k] : 0.f);
+  static_assert(kNFeat == 16, "eight torsion slots of sin, cos");
+  for (int e = tid; e < kFRows * 8; e += kFWaves * 64) {
+    const int r = e >> 3, q = e & 7, m = row0 + r;
+    float sn = 0.f, cs = 0.f;
+    if (m < B) {
+      const PoseTask t = tasks[m];
+      const LigDev& L = ligs[t.lig];
+      const PropDev& P = props[t.lig];
+      if (q < P.n_cond) {
+        const float phi =
+            dihedral_angle(L.x + (size_t)t.r * L.n * 3, P.cond[q]);
+        sincosf(phi, &sn, &cs);
+      }
+    }
+    S[0][r][2 * q] = bf16_bits(sn);
+    S[0][r][2 * q + 1] = bf16_bits(cs);
   }
   __syncthreads();
   dense_rows_t<kNFeat, kT1Ld, kNHid, true>(S[0], gr.WT + kTOff1,
@@ -583,31 +613,6 @@ __global__ __launch_bounds__(128) void k_pose_features(
                     feats + i * kNFeat);
 }
 
-// features only (the move recomputes the pose itself): one thread per
-// (task, conditioning torsion slot), the current configuration of replica
-// t.r of ligand t.lig into row t.row
-__global__ __launch_bounds__(256) void k_pose_features_tasks(
-    const LigDev* __restrict__ ligs, const PropDev* __restrict__ props,
-    const PoseTask* __restrict__ tasks, int n, float* __restrict__ feats) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int task = i >> 3, q = i & 7;
-  if (task >= n) return;
-  const PoseTask t = tasks[task];
-  const LigDev& L = ligs[t.lig];
-  const PropDev& P = props[t.lig];
-  float* fo = feats + (size_t)t.row * kNFeat + 2 * q;
-  if (q < P.n_cond) {
-    const float phi = dihedral_angle(L.x + (size_t)t.r * L.n * 3, P.cond[q]);
-    float s, cs;
-    sincosf(phi, &s, &cs);
-    fo[0] = s;
-    fo[1] = cs;
-  } else {
-    fo[0] = 0.f;
-    fo[1] = 0.f;
-  }
-}
-
 // wavefront maximum of a double (DPP tree as in wave_sum)
 __device__ __forceinline__ double wave_max_d(double v) {
   v = fmax(v, dpp_d<0xB1, 0xf>(v));
@@ -677,7 +682,7 @@ template <int C, int W>
 __global__ __launch_bounds__(W * kWave) void k_pose_move(
     GridDev g, const LigDev* __restrict__ ligs,
     const PropDev* __restrict__ props, const PoseTask* __restrict__ tasks,
-    const float* __restrict__ out, uint64_t seed) {
+    const float* __restrict__ out, uint64_t seed, int begin_next) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float sR[9], st[3], scom[3];
   __shared__ int s_ok;
@@ -849,6 +854,10 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
       L.fvalid[r] = 0;  // the stored start-of-trajectory forces are stale
     }
   }
+  // the next run of neighbour-scheme sweeps starts from this replica's
+  // state and (new or kept) components
+  if (begin_next && tid == 0)
+    begin_replica(L, r, k, s, *L.n_rec, L.comps + (size_t)r * (1 + C));
 }
 
 }  // namespace
@@ -872,12 +881,16 @@ hipError_t launch_mlp_forward(const float* P, const float* X, int B,
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward_groups(const MlpGroup* groups, int n_groups,
-                                     const float* X, float* out,
-                                     hipStream_t st) {
-  if (n_groups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_forward_t, dim3(n_groups), dim3(kFWaves * 64), 0,
-                     st, groups, X, out);
+hipError_t launch_pose_network(const MlpGroup* groups, int n_groups,
+                               const LigDev* ligs, const PropDev* props,
+                               const PoseTask* tasks, float* out,
+                               const LigDev* fin, int n_fin,
+                               int exchange_every, int sample_every,
+                               uint64_t seed, hipStream_t st) {
+  if (n_groups + n_fin <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pose_network, dim3(n_groups + n_fin),
+                     dim3(kFWaves * 64), 0, st, groups, n_groups, ligs, props,
+                     tasks, out, fin, exchange_every, sample_every, seed);
   return hipGetLastError();
 }
 
@@ -919,38 +932,28 @@ hipError_t launch_pose_features(const LigDev* lig, const PropDev* prop,
   return hipGetLastError();
 }
 
-hipError_t launch_pose_features_tasks(const LigDev* ligs,
-                                      const PropDev* props,
-                                      const PoseTask* tasks, int n,
-                                      float* feats, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  static_assert(kNFeat == 16, "eight torsion slots of sin, cos");
-  hipLaunchKernelGGL(k_pose_features_tasks, dim3((8 * n + 255) / 256),
-                     dim3(256), 0, st, ligs, props, tasks, n, feats);
-  return hipGetLastError();
-}
 
 hipError_t launch_pose_move(const GridDev& g, const LigDev* ligs,
                             const PropDev* props, const PoseTask* tasks,
                             int n, const float* out, int waves, int lds,
-                            uint64_t seed, hipStream_t st) {
+                            uint64_t seed, bool begin_next, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   switch (g.C) {
     case 3:
       if (waves == 1)
         hipLaunchKernelGGL((k_pose_move<3, 1>), dim3(n), dim3(64), lds, st, g,
-                           ligs, props, tasks, out, seed);
+                           ligs, props, tasks, out, seed, begin_next ? 1 : 0);
       else
         hipLaunchKernelGGL((k_pose_move<3, 2>), dim3(n), dim3(128), lds, st, g,
-                           ligs, props, tasks, out, seed);
+                           ligs, props, tasks, out, seed, begin_next ? 1 : 0);
       break;
     case 5:
       if (waves == 1)
         hipLaunchKernelGGL((k_pose_move<5, 1>), dim3(n), dim3(64), lds, st, g,
-                           ligs, props, tasks, out, seed);
+                           ligs, props, tasks, out, seed, begin_next ? 1 : 0);
       else
         hipLaunchKernelGGL((k_pose_move<5, 2>), dim3(n), dim3(128), lds, st, g,
-                           ligs, props, tasks, out, seed);
+                           ligs, props, tasks, out, seed, begin_next ? 1 : 0);
       break;
     default:
       return hipErrorInvalidValue;

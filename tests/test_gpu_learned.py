@@ -205,13 +205,15 @@ def test_pose_move_matches_oracle(which):
     ctx.close()
 
 
-def test_pose_moves_of_several_ligands_in_one_call():
-    """Three ligands of 24, 57 and 96 atoms, each with its own proposal, in
-    one context: every pose move call moves all three, each checked against
-    the oracle, and sweep calls with pose_move_every = 5 (graph and plain
-    launches) equal the host loop of five-sweep calls and pose moves bit
-    for bit."""
-    print_case("pose moves, three ligands")
+@pytest.mark.parametrize("all_props", [True, False])
+def test_pose_moves_of_several_ligands_in_one_call(all_props):
+    """Three ligands of 24, 57 and 96 atoms, each with its own proposal (or
+    the 57-atom one without: units then close with their own finish and
+    begin launches), in one context: every pose move call moves all of
+    them, each checked against the oracle, and sweep calls with
+    pose_move_every = 5 (graph and plain launches) equal the host loop of
+    five-sweep calls and pose moves bit for bit."""
+    print_case("pose moves, three ligands", all_props)
     system = synth.make_system(1)
     rng = np.random.default_rng(9)
     ligs = [system.ligands[0], synth.make_ligand(rng, 57, 8, box=8.0),
@@ -222,21 +224,26 @@ def test_pose_moves_of_several_ligands_in_one_call():
         for k in p:
             p[k] = p[k] + 0.05 * rng.normal(size=p[k].shape)
         params.append(flat(p))
+    has = [True, all_props, True]
     ctx, ids = make_context(system.grid, ligs, seed=system.seed)
-    for lid, lig, p in zip(ids, ligs, params):
-        ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors], p)
+    for lid, lig, p, h in zip(ids, ligs, params, has):
+        if h:
+            ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors],
+                               p)
     og = oracle.OGrid(system.grid)
-    for lid, lig in zip(ids, ligs):
-        checked = _check_pose_moves(ctx, og, lig, lid, system.seed, 2,
-                                    sweeps=1)
-        assert checked >= 6, (lid, checked)
+    if all_props:
+        for lid, lig in zip(ids, ligs):
+            checked = _check_pose_moves(ctx, og, lig, lid, system.seed, 2,
+                                        sweeps=1)
+            assert checked >= 6, (lid, checked)
     ctx.close()
     runs = []
     for mode in ("host", "graph", "plain"):
         ctx, ids = make_context(system.grid, ligs, seed=13, capacity=10)
-        for lid, lig, p in zip(ids, ligs, params):
-            ctx.proposal_setup(lid, lig.frame_atoms,
-                               lig.tors[lig.cond_tors], p)
+        for lid, lig, p, h in zip(ids, ligs, params, has):
+            if h:
+                ctx.proposal_setup(lid, lig.frame_atoms,
+                                   lig.tors[lig.cond_tors], p)
         if mode == "plain":
             ctx.set_graph(0)
         if mode == "host":
@@ -248,15 +255,20 @@ def test_pose_moves_of_several_ligands_in_one_call():
             ctx.hmc_sweep(23, 10, exchange_every=1, sample_every=3,
                           pose_move_every=5)
         runs.append([(ctx.get_replicas(i), ctx.get_samples(i),
-                      ctx.get_pose_stats(i)) for i in ids])
+                      ctx.get_pose_stats(i) if h else None, ctx.get_stats(i))
+                     for i, h in zip(ids, has)])
         ctx.close()
     for per in runs[1:]:
-        for (st, (xs, cs), ps), (st0, (xs0, cs0), ps0), lig in zip(
+        for (st, (xs, cs), ps, ss), (st0, (xs0, cs0), ps0, ss0), lig in zip(
                 per, runs[0], ligs):
-            assert ps0["tries"].sum() == 4 * lig.n_states
             for key in ("x", "state_of_replica", "comps", "counter"):
                 assert np.array_equal(st[key], st0[key]), key
             assert np.array_equal(xs, xs0) and np.array_equal(cs, cs0)
+            for key in ss0:
+                assert np.array_equal(ss[key], ss0[key]), key
+            if ps0 is None:
+                continue
+            assert ps0["tries"].sum() == 4 * lig.n_states
             assert np.array_equal(ps["acc"], ps0["acc"])
             assert np.array_equal(ps["tries"], ps0["tries"])
 
@@ -322,13 +334,15 @@ def test_pose_moves_inside_sweep_calls_match_host_loop():
         st = ctx.get_replicas(lid)
         xs, cs = ctx.get_samples(lid)
         ps = ctx.get_pose_stats(lid)
-        runs.append((st, xs, cs, ps))
+        runs.append((st, xs, cs, ps, ctx.get_stats(lid)))
         ctx.close()
-    st0, xs0, cs0, ps0 = runs[0]
+    st0, xs0, cs0, ps0, ss0 = runs[0]
     assert ps0["tries"].sum() == 6 * lig.n_states
-    for st, xs, cs, ps in runs[1:]:
+    for st, xs, cs, ps, ss in runs[1:]:
         for key in ("x", "state_of_replica", "comps", "counter"):
             assert np.array_equal(st[key], st0[key]), key
         assert np.array_equal(xs, xs0) and np.array_equal(cs, cs0)
         assert np.array_equal(ps["acc"], ps0["acc"])
         assert np.array_equal(ps["tries"], ps0["tries"])
+        for key in ss0:
+            assert np.array_equal(ss[key], ss0[key]), key
