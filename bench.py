@@ -33,7 +33,8 @@ learned pose moves on the 24-atom, 64-state soft-grid system: BPMF error
 against a long plain run and effective samples per second),
 "initialization" (the paper's ladder initialisation and production
 protocol) and "pair_terms" (the ligand's intramolecular nonbonded and OBC
-GB/SA energies and forces).  --config picks another main workload.
+GB/SA energies and forces, and their cost inside the sampler: the Full
+pathway's sweep against the plain one).  --config picks another main workload.
 """
 from __future__ import annotations
 
@@ -889,7 +890,56 @@ def pair_leg(pkg, torch, n_conf=32000, reps=5):
         ctx.close()
         out.append({"workload": name, "atoms": lig.n_atoms,
                     "configurations": n_conf, **res})
-    return out
+    return {"kernel": out, "in_sampler": full_pathway_cost(pkg, torch)}
+
+
+def full_pathway_cost(pkg, torch, sweeps=512):
+    """What the pair terms cost inside the sampler (the paper's Full
+    pathway): a 48-atom ligand grown without nonbonded clashes, 64 replicas
+    of the production ladder (L = 20) on 128^3 grids of 2000 receptor atoms
+    kept 3 A from it, the mean sweep time over graph replays of 64 sweeps
+    (HIP events on the library's stream) and the HMC acceptance, with the
+    ligand's pair terms out of and in its energy."""
+    import dataclasses
+    import numpy as np
+    import synth
+    c2 = synth.make_system(2, with_grid=False)
+    base = c2.ligands[0]
+    lig = synth.make_ligand(np.random.default_rng([102, 77]), base.n_atoms,
+                            base.n_states, box=10.0, far_sep=3.0)
+    nn, h = 128, 0.25
+    edge = (nn - 1) * h
+    pts, q, sig, eps = synth.make_receptor(
+        np.random.default_rng([102, 78]), 2000, edge, 0.3 * edge,
+        avoid_xyz=lig.x0[0])
+    nodes = synth.grids_from_points(pts, q, sig, eps, nn, h,
+                                    device="cuda:0")
+    g = synth.Grid((nn,) * 3, (-(nn - 1) * h / 2,) * 3, h, (4, 0, 0), nodes)
+    L = c2.n_leapfrog
+    ctx = pkg.Context(seed=c2.seed, device=0)
+    ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
+    lid = ctx.ligand_setup(lig)
+    ctx.pair_setup(lid, synth.pair_params(lig, seed=2))
+    res = {"atoms": lig.n_atoms, "replicas": lig.n_states, "leapfrog": L,
+           "sweeps_timed": sweeps}
+    for on in (False, True):
+        ctx.pair_sample(lid, on)
+        ctx.hmc_sweep(128, L, exchange_every=1)
+        torch.cuda.synchronize()
+        before = ctx.get_stats(lid)
+        ctx.set_timing(True, every=1)
+        ctx.hmc_sweep(sweeps, L, exchange_every=1)
+        ms, n = ctx.get_timing(ctx.TIMER_HMC)
+        ctx.set_timing(False)
+        after = ctx.get_stats(lid)
+        acc = (after["hmc_acc"].sum() - before["hmc_acc"].sum()) / max(
+            after["hmc_try"].sum() - before["hmc_try"].sum(), 1)
+        res["with_pair_terms" if on else "without"] = {
+            "sweep_us": ms * 1e3, "hmc_acceptance": float(acc)}
+    res["cost_ratio"] = (res["with_pair_terms"]["sweep_us"] /
+                         res["without"]["sweep_us"])
+    ctx.close()
+    return res
 
 
 def dataclasses_replace_states(lig, K):

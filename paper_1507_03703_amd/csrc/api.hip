@@ -1203,6 +1203,9 @@ struct UknPlan {
   int cnt[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
   int lds[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
   bool pairs[bpmf_ctx::kWaveClasses] = {false, false, false, false};
+  // one wavefront per sample (k_energy_matrix_wave) and its LDS
+  bool per_wave[bpmf_ctx::kWaveClasses] = {false, false, false, false};
+  int wave_lds[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
 };
 
 // Validates an energy-matrix batch and writes its job table into `jobs`
@@ -1279,7 +1282,15 @@ int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
       jobs[nj++] = J;
       p->lds[q] = std::max(p->lds[q], ukn_lds(h, W));
       p->pairs[q] = p->pairs[q] || h.dev.pairs_on;
+      if (W <= 2)
+        p->wave_lds[q] = std::max(
+            p->wave_lds[q],
+            ukn_wave_lds_bytes(h.dev.K, h.dev.C, W, h.dev.nb, h.dev.na,
+                               h.dev.nt));
     }
+    // a class whose ligands have no pair terms in their energy and whose
+    // per-wavefront LDS fits runs one wavefront per sample
+    p->per_wave[q] = W <= 2 && !p->pairs[q] && p->wave_lds[q] <= 65536;
     p->cnt[q] = nj - p->off[q];
     p->total[q] = first;
     UknJob end{};
@@ -1300,10 +1311,10 @@ int ukn_launch(bpmf_ctx* c, const UknPlan& p, const UknJob* d_jobs,
     const bool timed =
         timed_ok && c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
     if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
-    HIP_TRY(launch_energy_matrix(c->grid, c->d_ligs, 1 << q,
-                                 d_jobs + p.off[q], p.cnt[q], p.total[q],
-                                 p.group, p.lds[q], c->n_cu, p.pairs[q],
-                                 c->stream));
+    HIP_TRY(launch_energy_matrix(
+        c->grid, c->d_ligs, 1 << q, d_jobs + p.off[q], p.cnt[q], p.total[q],
+        p.group, p.per_wave[q] ? p.wave_lds[q] : p.lds[q], c->n_cu,
+        p.pairs[q], p.per_wave[q], c->stream));
     if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   }
   return BPMF_OK;

@@ -472,23 +472,26 @@ __device__ __forceinline__ float torsion_term(const float4* pos, int4 ijkl,
   const float cs = cn * cg + sn * sg;
   const float snm = sn * cg - cn * sg;
   if (FORCES) {
-    const float dE = -par.x * par.y * snm;
+    // -dE/dphi in force units of 2^-16, folded into the four scalars of
+    // the gradient: F_i = ai n1, F_l = al n2, F_j = -F_i + P n1 + Q n2,
+    // F_k = -F_l - P n1 - Q n2
+    const float dEs = par.x * par.y * snm * kFix;
     const float in1 = rcp(dot(n1, n1)), in2 = rcp(dot(n2, n2));
-    const float p12 = dot(b1, b2) * ilb2 * in1;
-    const float p23 = dot(b2, b3) * ilb2 * in2;
-    const float3 gi = scale3(-lb2 * in1, n1);
-    const float3 gl = scale3(lb2 * in2, n2);
-    const float3 gj = make_float3(-gi.x + p12 * n1.x + p23 * n2.x,
-                                  -gi.y + p12 * n1.y + p23 * n2.y,
-                                  -gi.z + p12 * n1.z + p23 * n2.z);
-    const float3 gk = make_float3(-gl.x - p12 * n1.x - p23 * n2.x,
-                                  -gl.y - p12 * n1.y - p23 * n2.y,
-                                  -gl.z - p12 * n1.z - p23 * n2.z);
-    const float dEs = -dE * kFix;
-    sl.put(slot_of(ijkl.x), scale3(dEs, gi));
-    sl.put(slot_of(ijkl.y), scale3(dEs, gj));
-    sl.put(slot_of(ijkl.z), scale3(dEs, gk));
-    sl.put(slot_of(ijkl.w), scale3(dEs, gl));
+    const float lin1 = lb2 * in1, lin2 = lb2 * in2;
+    const float P = dot(b1, b2) * ilb2 * in1 * dEs;
+    const float Q = dot(b2, b3) * ilb2 * in2 * dEs;
+    const float ai = -lin1 * dEs, al = lin2 * dEs;
+    const float3 fi = scale3(ai, n1), fl = scale3(al, n2);
+    sl.put(slot_of(ijkl.x), fi);
+    sl.put(slot_of(ijkl.y),
+           make_float3(fmaf(P, n1.x, fmaf(Q, n2.x, -fi.x)),
+                       fmaf(P, n1.y, fmaf(Q, n2.y, -fi.y)),
+                       fmaf(P, n1.z, fmaf(Q, n2.z, -fi.z))));
+    sl.put(slot_of(ijkl.z),
+           make_float3(fmaf(-P, n1.x, fmaf(-Q, n2.x, -fl.x)),
+                       fmaf(-P, n1.y, fmaf(-Q, n2.y, -fl.y)),
+                       fmaf(-P, n1.z, fmaf(-Q, n2.z, -fl.z))));
+    sl.put(slot_of(ijkl.w), fl);
   }
   return par.x * (1.0f + cs);
 }

@@ -52,6 +52,24 @@ __host__ __device__ inline int block_lds_bytes(int waves, bool forces, int n,
   return head + topo + (pairs ? pair_lds_bytes(n) : 0);
 }
 
+// LDS of a k_energy_matrix_wave block: the states' weights and beta_k, then
+// per wavefront its positions (64 AP float4) and the columns of a group of
+// kUknWaveGroup samples, then the ligand's topology (as stage_topology lays
+// it out)
+constexpr int kUknWaves = 4, kUknWaveGroup = 8;
+__host__ __device__ inline int ukn_wave_head_bytes(int K, int C) {
+  return (K * (C + 1) * 8 + 15) & ~15;
+}
+__host__ __device__ inline int ukn_wave_slot_bytes(int K, int ap) {
+  return 16 * kWave * ap + kUknWaveGroup * K * 8;
+}
+__host__ __device__ inline int ukn_wave_lds_bytes(int K, int C, int ap,
+                                                  int nb, int na, int nt) {
+  return ukn_wave_head_bytes(K, C) + kUknWaves * ukn_wave_slot_bytes(K, ap) +
+         32 * nt + 24 * na + 16 * nb +
+         ((2 * sched_row(nb, na, nt) + 15) & ~15);
+}
+
 enum Purpose : uint32_t { kMomenta = 1, kAccept = 2, kExchange = 3 };
 
 // Floats per cell record of the cell-major grid: the 8 corners x C channels
@@ -179,11 +197,15 @@ struct UknJob {
 };
 // d_jobs: n_jobs jobs in flat order, every ligand needing `waves`
 // wavefronts, then a sentinel with first = total; group = samples whose
-// columns are staged in LDS before they are written
+// columns are staged in LDS before they are written.  per_wave: one
+// wavefront per sample (k_energy_matrix_wave, for ligands whose pair terms
+// are not in the energy; `waves` is then the atoms per lane, 1 or 2, and
+// lds_bytes comes from ukn_wave_lds_bytes)
 hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
                                 int waves, const UknJob* d_jobs, int n_jobs,
                                 int64_t total, int group, int lds_bytes,
-                                int n_cu, bool pairs, hipStream_t st);
+                                int n_cu, bool pairs, bool per_wave,
+                                hipStream_t st);
 // copy n jobs from host memory into the device table dst by kernels that
 // take the jobs as arguments (no host staging buffer, no copy engine)
 hipError_t launch_put_jobs(UknJob* dst, const UknJob* jobs, int n,

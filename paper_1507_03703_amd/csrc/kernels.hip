@@ -15,7 +15,7 @@ namespace {
 // Dynamic LDS of a W-wave block: positions (64 W float4), per-wave partial
 // sums, centre-of-mass partials, n_acc x 3 fixed-point force accumulators,
 // then the ligand's topology (staged once per launch).
-template <int W>
+template <int W, bool SYNC = true>
 __device__ __forceinline__ Shared carve(unsigned char* raw, const LigDev& L,
                                         int n_acc, int tid) {
   Shared sh;
@@ -30,7 +30,8 @@ __device__ __forceinline__ Shared carve(unsigned char* raw, const LigDev& L,
   for (int i = tid; i < kAccCopies * 3 * n_acc; i += W * kWave)
     sh.sl.acc[i] = 0u;
   stage_topology(L, raw + acc0 + acc_lds_bytes(n_acc), sh, tid, W * kWave);
-  __syncthreads();
+  // SYNC false: the caller issues more work before its own barrier
+  if (SYNC) __syncthreads();
   return sh;
 }
 
@@ -432,6 +433,11 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
 #pragma unroll
   for (int d = 0; d < 3; ++d) x[d] = owner ? xr[tid * 3 + d] : 0.f;
 
+  // the ligand's topology goes to LDS now: its loads need only the table
+  // entry, so they overlap the replica's; the barrier comes after the
+  // loads below have been issued as well
+  const Shared sh = carve<W, false>(smem, L, L.n, tid);
+
   // scheme 0 first applies the exchange (and record) that ended the previous
   // sweep, from the double buffer; the parameters of both states of the
   // replica's pair are loaded with the pair's components
@@ -439,11 +445,15 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
                                      : Pair{a, a, false};
   const int kb = pr.active ? (a == pr.lo ? pr.hi : pr.lo) : a;
   float wa[C], wb[C];
+  double wda[C], wdb[C];
   auto wf = BPMF_GMEM(const float, L.wf);
+  auto wdp = BPMF_GMEM(const double, L.wd);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     wa[c] = wf[a * C + c];
     wb[c] = wf[kb * C + c];
+    wda[c] = wdp[a * C + c];
+    wdb[c] = wdp[kb * C + c];
   }
   auto Tf = BPMF_GMEM(const float, L.Tf);
   auto dtf = BPMF_GMEM(const float, L.dtf);
@@ -451,6 +461,34 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   const float Ta = Tf[a], Tb = Tf[kb];
   const float dta = dtf[a], dtb = dtf[kb];
   const double ba = bt[a], bb = bt[kb];
+  // the start of the trajectory's stored parts (state-independent force of
+  // the current positions, restraint factor, components), loaded beside
+  // the exchange's operands
+  constexpr int kFC = 3 + 3 * C;
+  const int C1 = 1 + C;
+  const int cur = fv > 0 ? fv - 1 : 0, nxt = 1 - cur;
+  float* const fc_cur = L.fcache + ((size_t)cur * L.K + r) * n * kFC;
+  float* const fc_nxt = L.fcache + ((size_t)nxt * L.K + r) * n * kFC;
+  float ca[kFC], cr[4];
+  double cp[1 + C];
+  if (fv > 0) {
+    if (owner) {
+      auto cap = BPMF_GMEM(const float, fc_cur + (size_t)tid * kFC);
+#pragma unroll
+      for (int q = 0; q < kFC; ++q) ca[q] = cap[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < kFC; ++q) ca[q] = 0.f;
+    }
+    auto crp = BPMF_GMEM(const float, L.frc + ((size_t)cur * L.K + r) * 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cr[q] = crp[q];
+    auto cpp = BPMF_GMEM(const double,
+                         deferred ? L.scomp + ((size_t)pin * L.K + a) * C1
+                                  : L.comps + (size_t)r * C1);
+#pragma unroll
+    for (int q = 0; q < 1 + C; ++q) cp[q] = cpp[q];
+  }
   bool swap = false;
   if (pr.active) {
     swap = pair_accepts<C>(L, pr, pin, s, seed);
@@ -461,15 +499,18 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   }
   const int k = swap ? kb : a;
   float w[C];
+  double wdk[C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) w[c] = swap ? wb[c] : wa[c];
+  for (int c = 0; c < C; ++c) {
+    w[c] = swap ? wb[c] : wa[c];
+    wdk[c] = swap ? wdb[c] : wda[c];
+  }
   const float T = swap ? Tb : Ta;
   const float dt = swap ? dtb : dta;
   const double beta = swap ? bb : ba;
+  __syncthreads();  // the staged topology
 
-  const Shared sh = carve<W>(smem, L, L.n, tid);
   __shared__ double fin[2 * W];
-  const int C1 = 1 + C;
   // the previous sweep's round: this replica's configuration and components
   // go to the slot of its state after that exchange.  The replica's record
   // counter is advanced at the end of the kernel, after the barriers, so that
@@ -507,22 +548,12 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   // start of the trajectory: force and energy at the current positions,
   // rebuilt from the state-independent parts stored when these positions
   // were last evaluated (same arithmetic, same bits), or evaluated
-  constexpr int kFC = 3 + 3 * C;
-  const int cur = fv > 0 ? fv - 1 : 0, nxt = 1 - cur;
-  float* const fc_cur = L.fcache + ((size_t)cur * L.K + r) * n * kFC;
-  float* const fc_nxt = L.fcache + ((size_t)nxt * L.K + r) * n * kFC;
   double U0, KE0;
   if (fv > 0) {
-    auto cp = BPMF_GMEM(const double,
-                        deferred ? L.scomp + ((size_t)pin * L.K + a) * C1
-                                 : L.comps + (size_t)r * C1);
-    auto wd = BPMF_GMEM(const double, L.wd);
     U0 = cp[0];
 #pragma unroll
-    for (int c = 0; c < C; ++c) U0 += wd[k * C + c] * cp[1 + c];
+    for (int c = 0; c < C; ++c) U0 += wdk[c] * cp[1 + c];
     if (owner) {
-      auto ca = BPMF_GMEM(const float, fc_cur + (size_t)tid * kFC);
-      auto cr = BPMF_GMEM(const float, L.frc + ((size_t)cur * L.K + r) * 4);
       float de[C][3], ge[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < C; ++c)
@@ -547,8 +578,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
         L.frc + ((size_t)cur * L.K + r) * 4);
     U0 = t0[0] + t0[1] + t0[2] + t0[3];
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      U0 += BPMF_GMEM(const double, L.wd)[k * C + c] * t0[4 + c];
+    for (int c = 0; c < C; ++c) U0 += wdk[c] * t0[4 + c];
     KE0 = t0[4 + C] * 1e4;
   }
 
@@ -580,8 +610,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   for (int d = 0; d < 3; ++d) v[d] = fmaf(hk, f[d], v[d]);
   double U1 = t1[0] + t1[1] + t1[2] + t1[3];
 #pragma unroll
-  for (int c = 0; c < C; ++c)
-    U1 += BPMF_GMEM(const double, L.wd)[k * C + c] * t1[4 + c];
+  for (int c = 0; c < C; ++c) U1 += wdk[c] * t1[4 + c];
   const float ke1 = 0.5f * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   const float bad =
       (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) ? 1.f : 0.f;
@@ -742,6 +771,173 @@ __global__ __launch_bounds__(W * kWave) void k_energy_matrix(
       }
       s = g1;
     }
+  }
+}
+
+// The same u_kn with one wavefront per sample and no workgroup barrier
+// inside a sample: for ligands whose pair terms are not in the energy.  A
+// block of kUknWaves wavefronts stages the topology of its current job once
+// (shared by its wavefronts); the job's samples are dealt to the wavefronts
+// in groups of kUknWaveGroup consecutive ones.  A wavefront evaluates a
+// sample alone: lane l owns atoms l and l + 64 (AP = 2) or l; the grid terms
+// of its atoms, every bonded chunk of the ligand (energies only), the
+// mass-weighted position sums of the restraint, then double sums over the
+// wavefront, as the lean block evaluation forms them: U0 = (bonded total) +
+// U_I, and the C channel sums.  Its LDS (positions, the group's columns) is
+// its own; LDS operations of one wavefront complete in order, so its lanes
+// see each other's stores after a wavefront-scope fence.
+template <int C, int AP>
+__global__ __launch_bounds__(kUknWaves * kWave) void k_energy_matrix_wave(
+    GridDev g, const LigDev* __restrict__ ligs,
+    const UknJob* __restrict__ jobs, int n_jobs, int64_t total) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = b0 + per < total ? b0 + per : total;
+  if (b0 >= b1) return;
+  int j = 0, hi = n_jobs;  // jobs[j].first <= b0 < jobs[hi].first
+  while (hi - j > 1) {
+    const int mid = (j + hi) / 2;
+    if (jobs[mid].first <= b0) j = mid; else hi = mid;
+  }
+  typedef const float __attribute__((address_space(1))) gfloat;
+  typedef const double __attribute__((address_space(1))) gcdouble;
+  auto wave_fence = []() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  const Slots no_forces{nullptr, 0};
+  for (int64_t s = b0; s < b1; ++j) {
+    const UknJob J = jobs[j];
+    const int64_t e = jobs[j + 1].first < b1 ? jobs[j + 1].first : b1;
+    if (s >= e) continue;  // empty job
+    const LigDev L = ligs[J.lig];
+    const int K = L.K, n = L.n;
+    double* ew = reinterpret_cast<double*>(smem);
+    unsigned char* slot =
+        smem + ukn_wave_head_bytes(K, C) + wv * ukn_wave_slot_bytes(K, AP);
+    float4* pos = reinterpret_cast<float4*>(slot);
+    double* col = reinterpret_cast<double*>(slot + 16 * kWave * AP);
+    unsigned char* topo = smem + ukn_wave_head_bytes(K, C) +
+                          kUknWaves * ukn_wave_slot_bytes(K, AP);
+    __syncthreads();  // the previous job's readers are done
+    Shared sh{};
+    stage_topology(L, topo, sh, tid, kUknWaves * kWave);
+    for (int i = tid; i < K * (C + 1); i += kUknWaves * kWave)
+      ew[i] = i < K * C ? ((gcdouble*)L.wd)[i]
+                        : ((gcdouble*)L.beta)[i - K * C];
+    __syncthreads();
+    const int ntc = (L.nt + kWave - 1) / kWave;
+    const int nac = (L.na + kWave - 1) / kWave;
+    const int nbc = (L.nb + kWave - 1) / kWave;
+    float m[AP], sc[AP][C];
+    bool own[AP];
+#pragma unroll
+    for (int a = 0; a < AP; ++a) {
+      const int at = lane + kWave * a;
+      own[a] = at < n;
+      m[a] = own[a] ? ((gfloat*)L.mass)[at] : 0.f;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        sc[a][c] = own[a] ? ((gfloat*)L.scale)[at * C + c] : 0.f;
+    }
+    const int64_t nseg = e - s;
+    for (int64_t gi = wv; gi * kUknWaveGroup < nseg; gi += kUknWaves) {
+      const int64_t q0 = s + gi * kUknWaveGroup;
+      const int64_t q1 = q0 + kUknWaveGroup < e ? q0 + kUknWaveGroup : e;
+      for (int64_t q = q0; q < q1; ++q) {
+        const gfloat* xq = (const gfloat*)J.xs + (size_t)(q - J.first) * n * 3;
+        float x[AP][3];
+#pragma unroll
+        for (int a = 0; a < AP; ++a)
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            x[a][d] = own[a] ? xq[(lane + kWave * a) * 3 + d] : 0.f;
+#pragma unroll
+        for (int a = 0; a < AP; ++a)
+          if (own[a])
+            pos[lane + kWave * a] =
+                make_float4(x[a][0], x[a][1], x[a][2], m[a]);
+        Corners<C> cn[AP];
+#pragma unroll
+        for (int a = 0; a < AP; ++a)
+          if (own[a]) grid_fetch<C>(g, x[a][0], x[a][1], x[a][2], cn[a]);
+        wave_fence();
+        // bonded terms, energies only, every chunk of the ligand
+        float eb = 0.f, ea = 0.f, et = 0.f;
+        for (int ch = 0; ch < ntc; ++ch) {
+          const int t = ch * kWave + lane;
+          if (t < L.nt)
+            et += torsion_term<false>(pos, sh.tijkl[t], sh.tpar[t],
+                                      no_forces);
+        }
+        for (int ch = 0; ch < nac; ++ch) {
+          const int t = ch * kWave + lane;
+          if (t < L.na)
+            ea += angle_term<false>(pos, sh.aijk[t], sh.apar[t], no_forces);
+        }
+        for (int ch = 0; ch < nbc; ++ch) {
+          const int t = ch * kWave + lane;
+          if (t < L.nb)
+            eb += bond_term<false>(pos, sh.bij[t], sh.bpar[t], no_forces);
+        }
+        // grid terms and the centre of mass
+        float psi[C], px = 0.f, py = 0.f, pz = 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) psi[c] = 0.f;
+#pragma unroll
+        for (int a = 0; a < AP; ++a) {
+          if (own[a]) {
+            float ev[C], dv[C][3];
+            grid_finish<C, false>(g, cn[a], sc[a], ev, dv);
+#pragma unroll
+            for (int c = 0; c < C; ++c) psi[c] += ev[c];
+          }
+          px += m[a] * x[a][0];
+          py += m[a] * x[a][1];
+          pz += m[a] * x[a][2];
+        }
+        wave_sumf3(px, py, pz);
+        const double U0b = wave_sum((double)eb + (double)ea + (double)et);
+        double ps[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) ps[c] = wave_sum((double)psi[c]);
+        const float cx = px * L.inv_total_mass - L.site[0];
+        const float cy = py * L.inv_total_mass - L.site[1];
+        const float cz = pz * L.inv_total_mass - L.site[2];
+        const float d = sqrtf(cx * cx + cy * cy + cz * cz);
+        const float excess = d - L.d0;
+        const double ui =
+            excess > 0.f
+                ? 0.5 * (double)L.krest * (double)excess * (double)excess
+                : 0.0;
+        const double U0 = U0b + 0.0 + 0.0 + ui;
+        double* cs = col + (q - q0) * K;
+        for (int k = lane; k < K; k += kWave) {
+          double E = U0;
+#pragma unroll
+          for (int c = 0; c < C; ++c) E = fma(ew[k * C + c], ps[c], E);
+          cs[k] = ew[K * C + k] * E;
+        }
+        // the next sample's position stores come after every lane's
+        // reads of this one
+        wave_fence();
+      }
+      // the group's columns, row by row: a run of consecutive samples of
+      // each row by consecutive lanes
+      wave_fence();
+      const int cnt = (int)(q1 - q0);
+      const int64_t n0 = q0 - J.first;
+      auto out = BPMF_GMEM(double, J.ukn);
+      for (int i = lane; i < cnt * K; i += kWave) {
+        const int k = i / cnt, qq = i - k * cnt;
+        out[(size_t)k * J.ld + n0 + qq] = col[qq * K + k];
+      }
+      wave_fence();
+    }
+    s = e;
   }
 }
 
@@ -1017,8 +1213,28 @@ hipError_t launch_put_jobs(UknJob* dst, const UknJob* jobs, int n,
 hipError_t launch_energy_matrix(const GridDev& g, const LigDev* d_ligs,
                                 int waves, const UknJob* d_jobs, int n_jobs,
                                 int64_t total, int group, int lds_bytes,
-                                int n_cu, bool pairs, hipStream_t st) {
+                                int n_cu, bool pairs, bool per_wave,
+                                hipStream_t st) {
   if (total <= 0) return hipSuccess;
+  if (per_wave) {
+    if (waves != 1 && waves != 2) return hipErrorInvalidValue;
+    BPMF_DISPATCH_C(g.C, {
+      auto kern = waves == 1 ? k_energy_matrix_wave<C, 1>
+                             : k_energy_matrix_wave<C, 2>;
+      int per_cu = 0;
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, kern, kUknWaves * kWave, lds_bytes);
+      if (e != hipSuccess) return e;
+      int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * n_cu;
+      // at least a group per wavefront
+      const int64_t most =
+          (total + kUknWaves * kUknWaveGroup - 1) / (kUknWaves * kUknWaveGroup);
+      if (blocks > most) blocks = most;
+      hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kUknWaves * kWave),
+                         lds_bytes, st, g, d_ligs, d_jobs, n_jobs, total);
+    });
+    return hipGetLastError();
+  }
   BPMF_DISPATCH_C(g.C, BPMF_DISPATCH_W(waves, {
     auto kern = pairs ? k_energy_matrix<C, W, true>
                       : k_energy_matrix<C, W, false>;

@@ -213,7 +213,9 @@ __device__ __forceinline__ void dense_rows_t(
   f32x4 acc[kTPW];
 #pragma unroll
   for (int i = 0; i < kTPW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+  // every k step's weight loads in flight at once (one 16-byte load per
+  // tile and step): one round trip to L2 per layer
+#pragma unroll
   for (int k0 = 0; k0 < KIN; k0 += kKStep) {
     bf16x8 b[kTPW];
 #pragma unroll
@@ -374,9 +376,19 @@ __device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z))
 
 // Mixture parameters of one output row (13 numbers per component).
 struct Mix {
-  float lw[kNComp];           // log weights (normalised)
+  float lw[kNComp];  // log weights (normalised by mixture_of; the pose move
+                     // keeps the raw logits and normalises them, mix_lse)
   float mt[kNComp][3], mw[kNComp][3], st[kNComp][3], sw[kNComp][3];
 };
+
+// log-normaliser of the raw mixture logits (the log-softmax's lse, float)
+__device__ __forceinline__ float mix_lse(const Mix& p) {
+  float mx = -INFINITY;
+  for (int j = 0; j < kNComp; ++j) mx = fmaxf(mx, p.lw[j]);
+  float sm = 0.f;
+  for (int j = 0; j < kNComp; ++j) sm += expf(p.lw[j] - mx);
+  return mx + logf(sm);
+}
 
 __device__ __forceinline__ void mixture_of(const float* o, Mix& p) {
   float mx = -INFINITY;
@@ -641,13 +653,14 @@ __device__ __forceinline__ double wave_max_d(double v) {
 __device__ double log_q_se3_wave(const Mix& p, const double t[3],
                                  const double w0[3]) {
   const int lane = threadIdx.x & 63;
+  const float lse = mix_lse(p);
   const double th = sqrt(w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2]);
   const bool small = th < 1e-9;
   const int n_terms = small ? kNComp : (2 * kFold + 1) * kNComp;
   double term = -INFINITY;
   if (lane < n_terms) {
     const int j = lane % kNComp, m = lane / kNComp - kFold;
-    double s = p.lw[j] - 3.0 * log(2.0 * M_PI);
+    double s = (double)(p.lw[j] - lse) - 3.0 * log(2.0 * M_PI);
     for (int d = 0; d < 3; ++d) {
       const double z = (t[d] - p.mt[j][d]) / p.st[j][d];
       s += -0.5 * z * z - log((double)p.st[j][d]) - log((double)p.sw[j][d]);
@@ -730,14 +743,15 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     }
   }
   __syncthreads();
+  // Two independent chains: A (thread 0) the current pose and the restraint
+  // energy at the current centre of mass, B (thread 64, or thread 0 after A
+  // in a one-wavefront block) the proposal; with two wavefronts they run
+  // side by side.  Each computes the log-normaliser of the mixture weights
+  // (log-softmax of the raw logits, float) with the same operations.
+  __shared__ double s_R[2][9];  // R0, R1
+  __shared__ double s_lq[2];
+  const int tb = W >= 2 ? kWave : 0;
   if (tid == 0) {
-    // normalised log weights (log-softmax of the raw logits)
-    float mx = -INFINITY;
-    for (int j = 0; j < kNComp; ++j) mx = fmaxf(mx, s_mix.lw[j]);
-    float sm = 0.f;
-    for (int j = 0; j < kNComp; ++j) sm += expf(s_mix.lw[j] - mx);
-    const float lse = mx + logf(sm);
-    for (int j = 0; j < kNComp; ++j) s_mix.lw[j] -= lse;
     double c[3] = {0, 0, 0}, M = 0;
     for (int q = 0; q < W; ++q) {
       for (int d = 0; d < 3; ++d) c[d] += s_cp[4 * q + d];
@@ -755,16 +769,22 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
       s_pose[d] = c[d] - L.site[d];
       s_pose[3 + d] = w0[d];
       d2 += s_pose[d] * s_pose[d];
+      scom[d] = (float)c[d];
     }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) s_R[0][3 * a + b] = R0[a][b];
     // restraint energy at the current centre of mass (Eq. binding_site)
     const double ex0 = sqrt(d2) - (double)L.d0;
     s_ui0 = ex0 > 0.0 ? 0.5 * (double)L.krest * ex0 * ex0 : 0.0;
+  }
+  if (tid == tb) {
+    const float lse = mix_lse(s_mix);
     // component by inverse CDF, then (t, omega) by Gaussian draws
     const U4 o0 = draw(seed, 0u, L.id, r, s, kPose);
     const double u = u01d(o0.x);
     double cum[kNComp], tot = 0.0;
     for (int j = 0; j < kNComp; ++j) {
-      tot += exp((double)s_mix.lw[j]);
+      tot += exp((double)(s_mix.lw[j] - lse));
       cum[j] = tot;
     }
     int j = 0;
@@ -784,28 +804,43 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     for (int d = 0; d < 3; ++d) {
       s_pose[6 + d] = t1[d];
       s_pose[9 + d] = w1p[d];
+      st[d] = (float)(L.site[d] + t1[d]);
     }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) s_R[1][3 * a + b] = R1[a][b];
+  }
+  __syncthreads();
+  // the two proposal densities, one term per lane: wave 0 at the current
+  // pose, wave 1 (or wave 0 after that) at the proposal
+  {
+    const int wv = tid >> 6;
+    if (W >= 2) {
+      if (wv < 2) {
+        const double lq =
+            log_q_se3_wave(s_mix, s_pose + 6 * wv, s_pose + 6 * wv + 3);
+        if ((tid & 63) == 0) s_lq[wv] = lq;
+      }
+    } else {
+      const double lq0 = log_q_se3_wave(s_mix, s_pose, s_pose + 3);
+      const double lq1 = log_q_se3_wave(s_mix, s_pose + 6, s_pose + 9);
+      if (tid == 0) {
+        s_lq[0] = lq0;
+        s_lq[1] = lq1;
+      }
+    }
+  }
+  if (tid == 0) {
     // x'_i = c0 + t' + R' R0^T (x_i - c): the rotation applied is R' R0^T
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
         double v = 0.0;
-        for (int q = 0; q < 3; ++q) v += R1[a][q] * R0[b][q];
+        for (int q = 0; q < 3; ++q) v += s_R[1][3 * a + q] * s_R[0][3 * b + q];
         sR[3 * a + b] = (float)v;
       }
-    for (int d = 0; d < 3; ++d) {
-      st[d] = (float)(L.site[d] + t1[d]);
-      scom[d] = (float)c[d];
-    }
   }
   __syncthreads();
-  if (tid < kWave) {
-    const Mix& p = s_mix;
-    const double lq0 = log_q_se3_wave(p, s_pose, s_pose + 3);
-    const double lq1 = log_q_se3_wave(p, s_pose + 6, s_pose + 9);
-    lq_ratio = lq0 - lq1;
-    if (tid == 0) s_ok = isfinite(lq_ratio) ? 1 : 0;
-  }
-  __syncthreads();
+  lq_ratio = s_lq[0] - s_lq[1];
+  if (tid == 0) s_ok = isfinite(lq_ratio) ? 1 : 0;
   Shared sh{};
   sh.pos = reinterpret_cast<float4*>(smem);
   sh.red = reinterpret_cast<double*>(smem + 16 * kWave * W);
@@ -825,8 +860,8 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
   float w[C];
   for (int c = 0; c < C; ++c) w[c] = L.wf[k * C + c];
   double t1e[6 + C];
-  eval_block<C, W, false, true, false, false>(g, L, w, x2, m, sc, f, t1e, 0.f,
-                                              0.f, sh, tid);
+  eval_block<C, W, false, true, true, false>(g, L, w, x2, m, sc, f, t1e, 0.f,
+                                             0.f, sh, tid);
   const double* cp = L.comps + (size_t)r * (1 + C);
   const double ub = cp[0] - s_ui0;  // bonded energy, unchanged by the move
   double E1 = ub + t1e[3], E0 = cp[0];
