@@ -535,6 +535,7 @@ struct Shared {
   const uint32_t* p14;      // n x kPairWords 1-4 masks
   float* pR;                // n Born radii
   float* pb;                // n chain-rule factors dE/dR_i dR_i/dI_i
+  float* pscr;              // slices x n x 9 partial sums (pair_stage)
 };
 
 // Copy a ligand's constant topology into LDS (all threads; caller syncs).
@@ -618,6 +619,7 @@ __device__ __forceinline__ void stage_topology(const LigDev& L,
     sh.p14 = o4;
     sh.pR = R;
     sh.pb = R + n;
+    sh.pscr = R + 2 * n;
   }
   sh.aijk = aijk;
   sh.apar = apar;
@@ -664,46 +666,68 @@ __device__ __forceinline__ void block_sync() {
 }
 
 // The ligand's intramolecular nonbonded and OBC GB/SA energy (the terms of
-// bpmf_pair_evaluate) for the configuration in sh.pos: one owner thread per
-// atom sums its own row of pair terms (every pair is visited from both
-// ends, so forces need no atomics), in three passes with two workgroup
-// barriers, which every thread of the block calls: (1) LJ, Coulomb and the
-// descreening sum, giving the Born radius; (2) GB energy, its explicit
-// force and dE/dR_i, the surface term; (3) the chain rule through the Born
-// radii (FORCES).  e: the thread's share of the energy; pf: the force on
-// its atom (FORCES).
+// bpmf_pair_evaluate) for the configuration in sh.pos.  Every atom's row of
+// pair terms (each pair is visited from both ends, so forces need no
+// atomics) is split over the block's wavefronts: thread t takes atom
+// i = lane + 64 (wave mod A) (A = atom waves) and slice k = wave / A of its
+// partners j (S = waves / A slices of [0, n)), and writes its partial sums
+// to LDS; the atom's owner adds the S partials in slice order.  Three
+// passes, each followed by a workgroup barrier and a combine (which every
+// thread of the block calls): (1) LJ, Coulomb and the descreening sum,
+// giving the Born radius, and v_i = sum_j dH(r_ij; a_i, s_j) (x_i - x_j) /
+// r_ij; (2) GB energy, its explicit force and dE/dR_i, then the self and
+// surface terms; (3) the chain rule through the Born radii (FORCES):
+// -b_i v_i - sum_j b_j dH(r_ij; a_j, s_i) (x_i - x_j) / r_ij, with
+// b = dE/dR dR/dI.  e: the owner's share of the energy; pf: the force on
+// its atom (FORCES); both 0 on other threads.
 template <bool FORCES>
 __device__ __forceinline__ void pair_stage(const Shared& sh, const PairDev& P,
-                                           int n, int tid, float& e,
-                                           float (&pf)[3]) {
-  const bool own = tid < n;
-  float e_lj = 0.f, e_c = 0.f, e_gb = 0.f, e_sa = 0.f;
-  float fx = 0.f, fy = 0.f, fz = 0.f;
-  float I = 0.f, dRdI = 0.f, Ri = 0.f;
+                                           int n, int tid, int nthreads,
+                                           float& e, float (&pf)[3]) {
+  const int A = (n + kWave - 1) / kWave;
+  const int S = pair_slices(n, nthreads / kWave);
+  const int wv = tid >> 6;
+  const int i = (tid & (kWave - 1)) + kWave * (wv % A);
+  const int k = wv / A;
+  const bool act = k < S && i < n;
+  const bool own = tid < n;  // slice 0's thread of atom tid
+  const int j0 = k * n / S, j1 = (k + 1) * n / S;
+  float* const part = sh.pscr + (size_t)(k * n + i) * 9;
   float4 xi = make_float4(0.f, 0.f, 0.f, 0.f), pi = xi;
   float2 qi1 = make_float2(0.f, 0.f);
-  if (own) {
-    xi = sh.pos[tid];
-    pi = sh.pp0[tid];
-    qi1 = sh.pp1[tid];
-    for (int j = 0; j < n; ++j) {
-      if (j == tid) continue;
+  if (act) {
+    xi = sh.pos[i];
+    pi = sh.pp0[i];
+    qi1 = sh.pp1[i];
+  }
+  // (1) LJ, Coulomb, descreening
+  if (act) {
+    float I = 0.f, e_lj = 0.f, e_c = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+    float vx = 0.f, vy = 0.f, vz = 0.f;
+    for (int j = j0; j < j1; ++j) {
+      if (j == i) continue;
       const float4 xj = sh.pos[j], pj = sh.pp0[j];
       const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
       const float r2 = dx * dx + dy * dy + dz * dz;
-      const float r = sqrtf(r2);
+      const float ir = __builtin_amdgcn_rsqf(r2), r = r2 * ir;
       float H, dH;
-      hct(r, qi1.x, sh.pp1[j].y, H, dH);
+      hct(r, ir, qi1.x, sh.pp1[j].y, H, dH);
       I += H;
-      const int w = tid * kPairWords + (j >> 5);
+      if (FORCES) {
+        const float h = dH * ir;
+        vx += h * dx;
+        vy += h * dy;
+        vz += h * dz;
+      }
+      const int w = i * kPairWords + (j >> 5);
       const uint32_t bit = 1u << (j & 31);
       if (sh.pex[w] & bit) continue;
       const float sg = 0.5f * (pi.y + pj.y), ep = pi.z * pj.z;
-      const float ir2 = 1.f / r2;
+      const float ir2 = ir * ir;
       const float sr2 = sg * sg * ir2, sr6 = sr2 * sr2 * sr2;
       float lj = 4.f * ep * (sr6 * sr6 - sr6);
       float flj = 24.f * ep * (2.f * sr6 * sr6 - sr6) * ir2;
-      float cl = P.kc * pi.x * pj.x / r;
+      float cl = P.kc * pi.x * pj.x * ir;
       float fcl = cl * ir2;
       if (sh.p14[w] & bit) {
         lj *= P.lj14;
@@ -720,6 +744,34 @@ __device__ __forceinline__ void pair_stage(const Shared& sh, const PairDev& P,
         fz += f * dz;
       }
     }
+    part[0] = I;
+    part[1] = e_lj;
+    part[2] = e_c;
+    part[3] = fx;
+    part[4] = fy;
+    part[5] = fz;
+    part[6] = vx;
+    part[7] = vy;
+    part[8] = vz;
+  }
+  block_sync();
+  float e_lj = 0.f, e_c = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+  float vx = 0.f, vy = 0.f, vz = 0.f;
+  float Ri = 0.f, dRdI = 0.f;
+  if (own) {
+    float I = 0.f;
+    for (int q = 0; q < S; ++q) {
+      const float* o = sh.pscr + (size_t)(q * n + tid) * 9;
+      I += o[0];
+      e_lj += o[1];
+      e_c += o[2];
+      fx += o[3];
+      fy += o[4];
+      fz += o[5];
+      vx += o[6];
+      vy += o[7];
+      vz += o[8];
+    }
     const float psi = I * qi1.x;
     const float t = psi * (kObcA - psi * (kObcB - kObcC * psi));
     const float th = tanhf(t);
@@ -729,18 +781,19 @@ __device__ __forceinline__ void pair_stage(const Shared& sh, const PairDev& P,
     sh.pR[tid] = Ri;
   }
   block_sync();
-  if (own) {
-    const float qi = pi.x;
-    e_gb = 0.5f * P.kgb * qi * qi / Ri;
-    float dEdR = -0.5f * P.kgb * qi * qi / (Ri * Ri);
-    for (int j = 0; j < n; ++j) {
-      if (j == tid) continue;
+  // (2) generalised Born pairs
+  if (act) {
+    const float qi = pi.x, Rii = sh.pR[i];
+    float e_gb = 0.f, dEdR = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+    for (int j = j0; j < j1; ++j) {
+      if (j == i) continue;
       const float4 xj = sh.pos[j];
       const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
       const float r2 = dx * dx + dy * dy + dz * dz;
       const float Rj = sh.pR[j];
-      const float RR = Ri * Rj;
-      const float D = expf(-0.25f * r2 / RR);
+      const float RR = Rii * Rj;
+      const float iRR = __builtin_amdgcn_rcpf(RR);
+      const float D = __expf(-0.25f * r2 * iRR);
       const float f2 = r2 + RR * D;
       const float invf = rsqrtf(f2);
       const float invf3 = invf * invf * invf;
@@ -748,40 +801,82 @@ __device__ __forceinline__ void pair_stage(const Shared& sh, const PairDev& P,
       e_gb += 0.5f * kq * invf;
       if (FORCES) {
         const float g = kq * (1.f - 0.25f * D) * invf3;
-        fx += g * dx;
-        fy += g * dy;
-        fz += g * dz;
-        dEdR -= 0.5f * kq * Rj * D * (1.f + 0.25f * r2 / RR) * invf3;
+        gx += g * dx;
+        gy += g * dy;
+        gz += g * dz;
+        dEdR -= 0.5f * kq * Rj * D * (1.f + 0.25f * r2 * iRR) * invf3;
       }
     }
+    part[0] = e_gb;
+    part[1] = dEdR;
+    part[2] = gx;
+    part[3] = gy;
+    part[4] = gz;
+  }
+  block_sync();
+  float e_gb = 0.f, e_sa = 0.f;
+  if (own) {
+    const float qi = pi.x;
+    float dEdR = 0.f;
+    for (int q = 0; q < S; ++q) {
+      const float* o = sh.pscr + (size_t)(q * n + tid) * 9;
+      e_gb += o[0];
+      dEdR += o[1];
+      fx += o[2];
+      fy += o[3];
+      fz += o[4];
+    }
+    // the atom's self term
+    e_gb += 0.5f * P.kgb * qi * qi / Ri;
+    dEdR -= 0.5f * P.kgb * qi * qi / (Ri * Ri);
     const float rp = pi.w + P.probe;
     const float q6 = pi.w / Ri, q3 = q6 * q6 * q6;
     e_sa = P.sa * rp * rp * q3 * q3;
     dEdR -= 6.f * e_sa / Ri;
     sh.pb[tid] = dEdR * dRdI;
   }
-  block_sync();
-  if (FORCES && own) {
-    const float bi = sh.pb[tid];
-    for (int j = 0; j < n; ++j) {
-      if (j == tid) continue;
-      const float4 xj = sh.pos[j];
-      const float2 pj1 = sh.pp1[j];
-      const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-      float Hi, dHi, Hj, dHj;
-      hct(r, qi1.x, pj1.y, Hi, dHi);
-      hct(r, pj1.x, qi1.y, Hj, dHj);
-      const float g = -(bi * dHi + sh.pb[j] * dHj) / r;
-      fx += g * dx;
-      fy += g * dy;
-      fz += g * dz;
+  if (FORCES) {
+    block_sync();
+    // (3) the chain rule through the Born radii: the partners' radii here,
+    // the atom's own from v_i
+    if (act) {
+      float gx = 0.f, gy = 0.f, gz = 0.f;
+      for (int j = j0; j < j1; ++j) {
+        if (j == i) continue;
+        const float4 xj = sh.pos[j];
+        const float2 pj1 = sh.pp1[j];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float ir = __builtin_amdgcn_rsqf(r2), r = r2 * ir;
+        float Hj, dHj;
+        hct(r, ir, pj1.x, qi1.y, Hj, dHj);
+        const float g = -sh.pb[j] * dHj * ir;
+        gx += g * dx;
+        gy += g * dy;
+        gz += g * dz;
+      }
+      part[0] = gx;
+      part[1] = gy;
+      part[2] = gz;
+    }
+    block_sync();
+    if (own) {
+      const float bi = sh.pb[tid];
+      fx -= bi * vx;
+      fy -= bi * vy;
+      fz -= bi * vz;
+      for (int q = 0; q < S; ++q) {
+        const float* o = sh.pscr + (size_t)(q * n + tid) * 9;
+        fx += o[0];
+        fy += o[1];
+        fz += o[2];
+      }
     }
   }
-  e = e_lj + e_c + e_gb + e_sa;
-  pf[0] = fx;
-  pf[1] = fy;
-  pf[2] = fz;
+  e = own ? e_lj + e_c + e_gb + e_sa : 0.f;
+  pf[0] = own ? fx : 0.f;
+  pf[1] = own ? fy : 0.f;
+  pf[2] = own ? fz : 0.f;
 }
 
 // sc: per-atom grid factors of the thread's atom (0 for non-owners).
@@ -896,7 +991,7 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
   // intramolecular nonbonded and implicit-solvent terms
   float epair = 0.f, fpair[3] = {0.f, 0.f, 0.f};
   const bool pairs = PAIRS && L.pairs_on;
-  if (pairs) pair_stage<FORCES>(sh, L.pair, n, tid, epair, fpair);
+  if (pairs) pair_stage<FORCES>(sh, L.pair, n, tid, W * kWave, epair, fpair);
   // centre of mass offset from the site (an atom wave's own total, which
   // wave 0 publishes for the others)
   float cx, cy, cz;

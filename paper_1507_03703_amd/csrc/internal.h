@@ -49,7 +49,7 @@ __host__ __device__ inline int block_lds_bytes(int waves, bool forces, int n,
                    (forces ? acc_lds_bytes(n) : 0);
   const int topo = 32 * nt + 24 * na + 16 * nb +
                    ((2 * sched_row(nb, na, nt) + 15) & ~15);
-  return head + topo + (pairs ? pair_lds_bytes(n) : 0);
+  return head + topo + (pairs ? pair_lds_bytes(n, waves) : 0);
 }
 
 // LDS of a k_energy_matrix_wave block: the states' weights and beta_k, then

@@ -63,19 +63,19 @@ __global__ __launch_bounds__(W * 64) void k_pair_terms(
       const float4 xj = s_x[j], pj = s_p0[j];
       const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
       const float r2 = dx * dx + dy * dy + dz * dz;
-      const float r = sqrtf(r2);
+      const float ir = __builtin_amdgcn_rsqf(r2), r = r2 * ir;
       float H, dH;
-      hct(r, qi1.x, s_p1[j].y, H, dH);
+      hct(r, ir, qi1.x, s_p1[j].y, H, dH);
       I += H;
       const int w = tid * kPairWords + (j >> 5);
       const uint32_t bit = 1u << (j & 31);
       if (s_ex[w] & bit) continue;
       const float sg = 0.5f * (pi.y + pj.y), ep = pi.z * pj.z;
-      const float ir2 = 1.f / r2;
+      const float ir2 = ir * ir;
       const float sr2 = sg * sg * ir2, sr6 = sr2 * sr2 * sr2;
       float lj = 4.f * ep * (sr6 * sr6 - sr6);
       float flj = 24.f * ep * (2.f * sr6 * sr6 - sr6) * ir2;
-      float cl = P.kc * pi.x * pj.x / r;
+      float cl = P.kc * pi.x * pj.x * ir;
       float fcl = cl * ir2;
       if (s_14[w] & bit) {
         lj *= P.lj14;
@@ -114,7 +114,8 @@ __global__ __launch_bounds__(W * 64) void k_pair_terms(
       const float r2 = dx * dx + dy * dy + dz * dz;
       const float Rj = s_R[j];
       const float RR = Ri * Rj;
-      const float D = expf(-0.25f * r2 / RR);
+      const float iRR = __builtin_amdgcn_rcpf(RR);
+      const float D = __expf(-0.25f * r2 * iRR);
       const float f2 = r2 + RR * D;
       const float invf = rsqrtf(f2);
       const float invf3 = invf * invf * invf;
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(W * 64) void k_pair_terms(
         fx += g * dx;
         fy += g * dy;
         fz += g * dz;
-        dEdR -= 0.5f * kq * Rj * D * (1.f + 0.25f * r2 / RR) * invf3;
+        dEdR -= 0.5f * kq * Rj * D * (1.f + 0.25f * r2 * iRR) * invf3;
       }
     }
     const float rp = pi.w + P.probe;
@@ -143,11 +144,12 @@ __global__ __launch_bounds__(W * 64) void k_pair_terms(
       const float4 xj = s_x[j];
       const float2 pj1 = s_p1[j];
       const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const float ir = __builtin_amdgcn_rsqf(r2), r = r2 * ir;
       float Hi, dHi, Hj, dHj;
-      hct(r, qi1.x, pj1.y, Hi, dHi);
-      hct(r, pj1.x, qi1.y, Hj, dHj);
-      const float g = -(bi * dHi + s_b[j] * dHj) / r;
+      hct(r, ir, qi1.x, pj1.y, Hi, dHi);
+      hct(r, ir, pj1.x, qi1.y, Hj, dHj);
+      const float g = -(bi * dHi + s_b[j] * dHj) * ir;
       fx += g * dx;
       fy += g * dy;
       fz += g * dz;
