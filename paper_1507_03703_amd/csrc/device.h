@@ -892,7 +892,7 @@ __device__ __forceinline__ void pair_stage(const Shared& sh, const PairDev& P,
 // energy is summed with the bonded terms, in terms[0]; their force is part
 // of the state-independent force).
 template <int C, int W, bool FORCES, bool ENERGY, bool LEAN = false,
-          bool BONDED = true, bool PAIRS = false>
+          bool BONDED = true, bool PAIRS = false, bool TERMS0 = false>
 __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
                                            const float* w, const float (&x)[3],
                                            float m, const float (&sc)[C],
@@ -1100,6 +1100,12 @@ __device__ __forceinline__ void eval_block(const GridDev& g, const LigDev& L,
     double acc[6 + C];
 #pragma unroll
     for (int q = 0; q < 6 + C; ++q) acc[q] = 0.0;
+    // TERMS0: the caller reads the terms in wavefront 0 only
+    if (TERMS0 && wv != 0) {
+#pragma unroll
+      for (int q = 0; q < 6 + C; ++q) terms[q] = 0.0;
+      return;
+    }
     // waves one at a time: an unrolled loop would hold W x (6 + C)
     // doubles in registers at once
 #pragma unroll 1

@@ -35,8 +35,9 @@ __device__ __forceinline__ Shared carve(unsigned char* raw, const LigDev& L,
   return sh;
 }
 
-// block-wide double sums of two per-thread floats (fixed order)
-template <int W>
+// block-wide double sums of two per-thread floats (fixed order); W0: the
+// sums are needed (and formed) in wavefront 0 only, 0 elsewhere
+template <int W, bool W0 = false>
 __device__ __forceinline__ void block_sum2(float a, float b, double* buf,
                                            int tid, double& sa, double& sb) {
   const double wa = wave_sum((double)a), wb = wave_sum((double)b);
@@ -47,6 +48,7 @@ __device__ __forceinline__ void block_sum2(float a, float b, double* buf,
   block_sync();
   sa = 0.0;
   sb = 0.0;
+  if (W0 && tid >= kWave) return;
 #pragma unroll
   for (int q = 0; q < W; ++q) {
     sa += buf[2 * q];
@@ -489,14 +491,21 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
 #pragma unroll
     for (int q = 0; q < 1 + C; ++q) cp[q] = cpp[q];
   }
-  bool swap = false;
-  if (pr.active) {
-    swap = pair_accepts<C>(L, pr, pin, s, seed);
-    if (tid == 0 && a == pr.lo) {
-      atomicAdd(&L.ex_try[pr.lo], 1ull);
-      if (swap) atomicAdd(&L.ex_acc[pr.lo], 1ull);
+  // the decision is the block's: wavefront 0 takes it and publishes it
+  // with the barrier that ends the staging
+  __shared__ int s_swap;
+  if (pr.active && tid < kWave) {
+    const bool sw = pair_accepts<C>(L, pr, pin, s, seed);
+    if (tid == 0) {
+      s_swap = sw ? 1 : 0;
+      if (a == pr.lo) {
+        atomicAdd(&L.ex_try[pr.lo], 1ull);
+        if (sw) atomicAdd(&L.ex_acc[pr.lo], 1ull);
+      }
     }
   }
+  __syncthreads();  // the staged topology and the decision
+  const bool swap = pr.active && s_swap != 0;
   const int k = swap ? kb : a;
   float w[C];
   double wdk[C];
@@ -508,7 +517,6 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   const float T = swap ? Tb : Ta;
   const float dt = swap ? dtb : dta;
   const double beta = swap ? bb : ba;
-  __syncthreads();  // the staged topology
 
   __shared__ double fin[2 * W];
   // the previous sweep's round: this replica's configuration and components
@@ -568,7 +576,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
       f[0] = f[1] = f[2] = 0.f;
     }
     double ke, unused;
-    block_sum2<W>(ke0, 0.f, fin, tid, ke, unused);
+    block_sum2<W, true>(ke0, 0.f, fin, tid, ke, unused);
     KE0 = ke * 1e4;
   } else {
     double t0[6 + C];
@@ -601,8 +609,10 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     v[d] = fmaf(hk, f[d], v[d]);
     x[d] = fmaf(dt, v[d], x[d]);
   }
-  // lean sums: the bonded total (the sweep needs no single bonded term)
-  eval_block<C, W, true, true, true, true, PAIRS>(
+  // lean sums: the bonded total (the sweep needs no single bonded term),
+  // formed in wavefront 0 only (its lanes take the decision and write the
+  // components)
+  eval_block<C, W, true, true, true, true, PAIRS, true>(
       g, L, w, x, m, sc, f, t1, 0.f, 0.f, sh, tid,
       owner ? fc_nxt + (size_t)tid * kFC : nullptr,
       L.frc + ((size_t)nxt * L.K + r) * 4);
@@ -615,13 +625,21 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   const float bad =
       (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) ? 1.f : 0.f;
   double KE1, nbad;
-  block_sum2<W>(ke1, bad, fin, tid, KE1, nbad);
-  KE1 *= 1e4;
-  const double dH = (U1 + KE1) - (U0 + KE0);
-  const U4 o = draw(seed, 0u, L.id, r, s, kAccept);
-  const double lnu = log(u01d(o.x));
-  const bool finite = isfinite(dH) && nbad == 0.0;
-  const bool accept = finite && (lnu < -beta * dH);
+  block_sum2<W, true>(ke1, bad, fin, tid, KE1, nbad);
+  // the Metropolis decision in wavefront 0, published through LDS
+  __shared__ int s_acc;
+  bool finite = true;
+  if (tid < kWave) {
+    KE1 *= 1e4;
+    const double dH = (U1 + KE1) - (U0 + KE0);
+    const U4 o = draw(seed, 0u, L.id, r, s, kAccept);
+    const double lnu = log(u01d(o.x));
+    finite = isfinite(dH) && nbad == 0.0;
+    const bool acc0 = finite && (lnu < -beta * dH);
+    if (tid == 0) s_acc = acc0 ? 1 : 0;
+  }
+  block_sync();
+  const bool accept = s_acc != 0;
   if (accept) {
     auto xw = BPMF_GMEM(float, L.x) + (size_t)r * n * 3;
     if (owner)
