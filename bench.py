@@ -29,8 +29,9 @@ ligand, 64 replicas, 128^3 grids, 5000 sweeps of 20 steps, u_kn, MBAR),
 sweeps; the launch shape picked by the autotuner), "bulk_interpolation"
 (u_kn and the interpolation harness on the sample sets of the batched
 workloads), "learned_proposal" (plain HMC, the paper's external moves and
-learned pose moves on the 24-atom, 64-state soft-grid system: BPMF error
-against a long plain run and effective samples per second),
+learned pose moves on the 24-atom, 64-state soft-grid system, each over
+independent ladders: BPMF error against a reference of 16 plain ladders and
+effective samples per second),
 "initialization" (the paper's ladder initialisation and production
 protocol) and "pair_terms" (the ligand's intramolecular nonbonded and OBC
 GB/SA energies and forces, and their cost inside the sampler: the Full
@@ -126,9 +127,11 @@ def parse():
     p.add_argument("--no-pairs", dest="pairs", action="store_false",
                    help="skip the intramolecular pair-term leg")
     p.add_argument("--pairs-only", action="store_true")
-    p.add_argument("--long-sweeps", type=int, default=1000000)
-    p.add_argument("--prod-sweeps", type=int, default=300000)
-    p.add_argument("--burn-sweeps", type=int, default=100000)
+    p.add_argument("--long-sweeps", type=int, default=500000,
+                   help="learned leg: sweeps of each reference ladder")
+    p.add_argument("--prod-sweeps", type=int, default=200000,
+                   help="learned leg: sweeps of each sampler's ladders")
+    p.add_argument("--burn-sweeps", type=int, default=200000)
     p.add_argument("--train-steps", type=int, default=4000)
     p.add_argument("--waves", type=int, default=None,
                    help="wavefronts per replica for every ligand instead of "
@@ -574,25 +577,29 @@ def init_params(rng):
 
 
 def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
-                long_sweeps=1000000, prod_sweeps=300000, n_blocks=10,
-                burn=100000):
-    """Plain HMC vs HMC + learned independence pose moves on the 24-atom,
-    64-state system with the paper's soft-grid switching protocol.
+                long_sweeps=500000, prod_sweeps=200000, burn=200000,
+                n_ref=16, n_seeds=8):
+    """Plain HMC, the paper's external moves and learned independence pose
+    moves on the 24-atom, 64-state system with the paper's soft-grid
+    switching protocol, each estimate over independent ladders.
 
-    After `burn` sweeps of equilibration, a long plain run (a record every
-    `sample_every` sweeps) gives the reference BPMF (MBAR over all its
-    records) with a batch-means standard error from `n_blocks` consecutive
-    blocks, and its coupled-state records are the poses the network is
-    trained on.  Three samplers then continue from the long run's final
-    state for `prod_sweeps` sweeps -- plain HMC, HMC with the paper's
-    external moves (20 per sweep in the states with alpha < 0.01) and HMC
-    with learned pose moves; each reports
-    its BPMF, the error against the reference, the spread of its own block
-    estimates, and effective samples per second of two observables of the
-    coupled state: its reduced potential (fast) and the distance of its
-    centre of mass from the site (the pose, which the learned move acts
-    on).  The BPMF's asymptotic MBAR error assumes independent samples; the
-    block estimates show how far slow modes make it understate the error."""
+    The reference: `n_ref` independent copies of the ladder in one context
+    (one launch per sweep covers all of them), `burn` sweeps of
+    equilibration, then `long_sweeps` sweeps with a record every
+    `sample_every`; each ladder's BPMF by MBAR over its records, the
+    reference the mean over ladders with its standard error (their spread
+    / sqrt(n_ref)).  The coupled state's records of every ladder are the
+    poses the network is trained on.  Each sampler then runs `n_seeds`
+    independent ladders in one context for `prod_sweeps` sweeps, started
+    from the final states of the first `n_seeds` reference ladders: plain
+    HMC, HMC with the paper's external moves (20 per sweep in the states
+    with alpha < 0.01) and HMC with a learned pose move every `pose_every`
+    sweeps.  Reported per sampler: the mean BPMF over its ladders, its error
+    against the reference with the standard error of that difference, the
+    spread of the per-ladder estimates, and effective samples per second of
+    two observables of the coupled state, summed over the ladders: its
+    reduced potential (fast) and the distance of its centre of mass from
+    the site (the pose, which the pose moves act on)."""
     import numpy as np
     import synth
     system = synth.make_system(4, grid_device="cuda:0")
@@ -601,58 +608,63 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
     every = system.sample_every
     mass = lig.mass / lig.mass.sum()
 
-    def fresh(capacity):
+    def fresh(copies, capacity):
         ctx = pkg.Context(seed=system.seed, device=0)
         ctx.grid_upload(g.nodes, g.origin, g.spacing, g.transform)
-        return ctx, ctx.ligand_setup(lig, sample_capacity=capacity)
+        ids = [ctx.ligand_setup(lig, sample_capacity=capacity)
+               for _ in range(copies)]
+        return ctx, ids
 
-    def estimate(ctx, lid, n_rec, blocks):
-        """BPMF over all records, the BPMF of `blocks` consecutive blocks
-        (one batched MBAR call) and the coupled state's observables."""
+    def estimate(ctx, lid, n_rec):
+        """One ladder: BPMF over all its records and the coupled state's
+        observables."""
         u = ctx.energy_matrix(lid, None, n_samples=n_rec * K)
         f, var, _ = ctx.mbar(u, np.full(K, n_rec), tol=1e-10, max_iter=200)
-        per = n_rec // blocks
-        parts = [u[:, b * per * K:(b + 1) * per * K] for b in range(blocks)]
-        fb = ctx.mbar_batch(parts, [np.full(K, per)] * blocks, tol=1e-10,
-                            max_iter=200)
-        blk = np.array([r[0][-1] - r[0][0] for r in fb])
         # the coupled state's reduced potential on its own samples
         # (round-major) and its pose: centre-of-mass distance from the site
         pot = u[K - 1, K - 1::K].cpu().numpy()
+        del u
         xs, _ = ctx.get_samples(lid)
         com = (xs[:, K - 1].astype(np.float64) * mass[None, :, None]).sum(1)
         dist = np.linalg.norm(com - lig.site_center[None, :], axis=1)
         return dict(bpmf=float(f[-1] - f[0]),
                     sigma_mbar=float(np.sqrt(max(var[-1], 0.0))),
-                    blocks=blk, block_sd=float(blk.std(ddof=1)),
                     g_pot=stat_inefficiency(pot),
-                    g_pose=batch_means_inefficiency(dist), n_rec=n_rec), xs
+                    g_pose=batch_means_inefficiency(dist)), xs
 
-    # long plain run: reference BPMF and training poses
+    # reference ladders: BPMF and training poses
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     long_rec = long_sweeps // every
-    ctx, lid = fresh(long_rec)
+    ctx, ids = fresh(n_ref, long_rec)
     ctx.hmc_sweep(burn, L, exchange_every=1)
     ctx.hmc_sweep(long_sweeps, L, exchange_every=1, sample_every=every)
     torch.cuda.synchronize()
     long_s = time.perf_counter() - t0
-    final = ctx.get_replicas(lid)
-    ref, xs = estimate(ctx, lid, long_rec, n_blocks)
-    ref_se = ref["block_sd"] / np.sqrt(n_blocks)
-    poses_x = torch.as_tensor(np.ascontiguousarray(xs[:, K - 1]),
-                              device="cuda:0")
-    del xs
-    ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors],
+    finals = [ctx.get_replicas(i) for i in ids]
+    ref_b, ref_gpose, pose_x = [], [], []
+    for i in ids:
+        e, xs = estimate(ctx, i, long_rec)
+        ref_b.append(e["bpmf"])
+        ref_gpose.append(e["g_pose"])
+        pose_x.append(np.ascontiguousarray(xs[:, K - 1]))
+        del xs
+    ref_b = np.array(ref_b)
+    ref_mean = float(ref_b.mean())
+    ref_se = float(ref_b.std(ddof=1) / np.sqrt(n_ref))
+    poses_x = torch.as_tensor(np.concatenate(pose_x), device="cuda:0")
+    del pose_x
+    lid0 = ids[0]
+    ctx.proposal_setup(lid0, lig.frame_atoms, lig.tors[lig.cond_tors],
                        init_params(np.random.default_rng(system.seed)))
-    feats, poses = ctx.pose_features(lid, poses_x)
+    feats, poses = ctx.pose_features(lid0, poses_x)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = ctx.proposal_train(lid, feats, poses, batch=512,
+    losses = ctx.proposal_train(lid0, feats, poses, batch=512,
                                 steps=train_steps, lr=2e-3, losses=True)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    params = ctx.proposal_params(lid)
+    params = ctx.proposal_params(lid0)
     n_poses = int(feats.shape[0])
     ctx.close()
     del poses_x, feats, poses
@@ -664,52 +676,68 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
 
     def production(mode):
         records = prod_sweeps // every
-        ctx, lid = fresh(records)
-        ctx.set_replicas(lid, final["x"], final["state_of_replica"],
-                         final["comps"], int(final["counter"]))
+        ctx, ids = fresh(n_seeds, records)
         learned = mode == "learned"
-        if learned:
-            ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors],
-                               params)
+        for q, i in enumerate(ids):
+            fq = finals[q]
+            ctx.set_replicas(i, fq["x"], fq["state_of_replica"], fq["comps"],
+                             int(fq["counter"]))
+            if learned:
+                ctx.proposal_setup(i, lig.frame_atoms,
+                                   lig.tors[lig.cond_tors], params)
         moves = dict(pose_move_every=pose_every if learned else 0)
         if mode == "external":
             moves.update(external_moves=20, external_k_max=k_ext,
                          external_sigma=0.6)
         ctx.hmc_sweep(2 * pose_every, L, exchange_every=1, **moves)
-        ctx.reset_samples(lid)
+        for i in ids:
+            ctx.reset_samples(i)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.hmc_sweep(prod_sweeps, L, exchange_every=1, sample_every=every,
                       **moves)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        e, _ = estimate(ctx, lid, records, 5)
-        err = abs(e["bpmf"] - ref["bpmf"])
-        out = dict(seconds=el, bpmf_kT=e["bpmf"],
-                   sigma_mbar_kT=e["sigma_mbar"],
-                   block_sd_kT=e["block_sd"],
-                   error_vs_long_run_kT=err, within_1kT=bool(err <= 1.0),
-                   stat_inefficiency_potential=e["g_pot"],
-                   stat_inefficiency_pose=e["g_pose"],
-                   ess_potential=records / e["g_pot"],
-                   ess_pose=records / e["g_pose"],
-                   ess_per_s=records / e["g_pot"] / el,
-                   ess_pose_per_s=records / e["g_pose"] / el)
+        es = [estimate(ctx, i, records)[0] for i in ids]
+        b = np.array([e["bpmf"] for e in es])
+        mean = float(b.mean())
+        sd = float(b.std(ddof=1))
+        err = mean - ref_mean
+        err_se = float(np.sqrt(sd ** 2 / n_seeds + ref_se ** 2))
+        ess_pot = sum(records / e["g_pot"] for e in es)
+        ess_pose = sum(records / e["g_pose"] for e in es)
+        out = dict(seconds=el, ladders=n_seeds, bpmf_kT=mean,
+                   ladder_bpmf_kT=[float(v) for v in b],
+                   ladder_sd_kT=sd,
+                   sigma_mbar_kT=float(np.mean([e["sigma_mbar"]
+                                                for e in es])),
+                   error_vs_reference_kT=float(err),
+                   error_standard_error_kT=err_se,
+                   within_1kT=bool(abs(err) <= 1.0),
+                   stat_inefficiency_potential=float(np.mean(
+                       [e["g_pot"] for e in es])),
+                   stat_inefficiency_pose=float(np.mean(
+                       [e["g_pose"] for e in es])),
+                   ess_potential=ess_pot, ess_pose=ess_pose,
+                   ess_per_s=ess_pot / el, ess_pose_per_s=ess_pose / el)
         if learned:
-            ps = ctx.get_pose_stats(lid)
-            out["pose_acceptance"] = float(ps["acc"].sum() /
-                                           max(ps["tries"].sum(), 1))
+            ps = [ctx.get_pose_stats(i) for i in ids]
+            out["pose_acceptance"] = float(
+                sum(p["acc"].sum() for p in ps) /
+                max(sum(p["tries"].sum() for p in ps), 1))
             out["pose_acceptance_coupled_state"] = float(
-                ps["acc"][-1] / max(ps["tries"][-1], 1))
+                sum(p["acc"][-1] for p in ps) /
+                max(sum(p["tries"][-1] for p in ps), 1))
         if mode == "external":
-            es = ctx.get_external_stats(lid)
+            xs_ = [ctx.get_external_stats(i) for i in ids]
             out["external_states"] = k_ext
-            out["external_acceptance"] = float(es["acc"].sum() /
-                                               max(es["tries"].sum(), 1))
+            out["external_acceptance"] = float(
+                sum(x["acc"].sum() for x in xs_) /
+                max(sum(x["tries"].sum() for x in xs_), 1))
         ctx.close()
         return out
 
-    progress("learned leg: reference run and training")
+    progress("learned leg: reference ladders and training")
     plain = production("plain")
     progress("learned leg: plain sampler")
     external = production("external")
@@ -719,26 +747,26 @@ def learned_leg(pkg, torch, pose_every=5, train_steps=4000,
     return {
         "workload": f"{system.name} with the soft-grid switching protocol "
                     f"(5 channels): {n}-atom ligand, {g.n[0]}^3 grids, {K} "
-                    f"replicas, {prod_sweeps} sweeps x {L} leapfrog steps "
-                    f"from the end of a {burn}-sweep burn-in and a "
-                    f"{long_sweeps}-sweep plain run, a "
-                    f"sample per state every {every}; learned: one "
-                    f"independence pose move per replica every "
-                    f"{pose_every} sweeps (captured with the sweeps); "
-                    f"external: 20 of the paper's external moves per sweep "
-                    f"in the states with alpha < 0.01",
+                    f"replicas per ladder; reference: {n_ref} independent "
+                    f"ladders, {burn} sweeps of burn-in and {long_sweeps} "
+                    f"sweeps each; samplers: {n_seeds} ladders each, "
+                    f"{prod_sweeps} sweeps x {L} leapfrog steps from "
+                    f"reference ladders' final states, a sample per state "
+                    f"every {every}; learned: one independence pose move "
+                    f"per replica every {pose_every} sweeps (captured with "
+                    f"the sweeps); external: 20 of the paper's external "
+                    f"moves per sweep in the states with alpha < 0.01",
         "ess_observables": "coupled state: reduced potential on its own "
                            "samples (initial positive autocorrelation sum); "
                            "centre-of-mass distance from the site (batch "
-                           "means over 30 batches)",
-        "reference": {"burn_in_sweeps": burn, "sweeps": long_sweeps,
-                      "seconds": long_s,
-                      "bpmf_kT": ref["bpmf"],
-                      "sigma_mbar_kT": ref["sigma_mbar"],
-                      "block_bpmf_kT": [float(v) for v in ref["blocks"]],
-                      "block_sd_kT": ref["block_sd"],
-                      "standard_error_kT": float(ref_se),
-                      "stat_inefficiency_pose": ref["g_pose"]},
+                           "means over 30 batches); summed over ladders",
+        "reference": {"ladders": n_ref, "burn_in_sweeps": burn,
+                      "sweeps": long_sweeps, "seconds": long_s,
+                      "bpmf_kT": ref_mean,
+                      "ladder_bpmf_kT": [float(v) for v in ref_b],
+                      "ladder_sd_kT": float(ref_b.std(ddof=1)),
+                      "standard_error_kT": ref_se,
+                      "stat_inefficiency_pose": float(np.mean(ref_gpose))},
         "plain": plain, "external": external, "learned": learned,
         "ess_per_s_ratio": learned["ess_per_s"] / plain["ess_per_s"],
         "ess_pose_per_s_ratio": learned["ess_pose_per_s"] /

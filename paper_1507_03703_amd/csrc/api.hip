@@ -865,8 +865,10 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.samp_c = (double*)(base + o_sc);
   h.arena = base;
   h.state_bytes = o_sx;
-  h.ext_acc = (unsigned long long*)(base + o_xacc);
-  h.ext_try = (unsigned long long*)(base + o_xtry);
+  L.ext_acc = (unsigned long long*)(base + o_xacc);
+  L.ext_try = (unsigned long long*)(base + o_xtry);
+  h.ext_acc = L.ext_acc;
+  h.ext_try = L.ext_try;
   h.min_waves = min_waves;
   h.sweep_waves = min_waves;
   h.counter = 0;
@@ -908,8 +910,8 @@ struct UnitClose {
 };
 int pose_move_batch(bpmf_ctx* c, int only, hipStream_t st,
                     const UnitClose* close = nullptr);
-int external_move_ligand(bpmf_ctx* c, int lid, int n_moves, int k_max,
-                         double sigma, hipStream_t st);
+int external_moves_range(bpmf_ctx* c, int l0, int l1, int n_moves,
+                         int k_max, double sigma, hipStream_t st);
 int check_external(int n_moves, int k_max, double sigma);
 }  // namespace
 
@@ -1025,11 +1027,8 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
       if (r) return r;
     }
     if (NX > 0)
-      for (int l = l0; l < l1; ++l) {
-        const int r = external_move_ligand(c, l, NX, a->external_k_max,
-                                           a->external_sigma, st);
-        if (r) return r;
-      }
+      return external_moves_range(c, l0, l1, NX, a->external_k_max,
+                                  a->external_sigma, st);
     return BPMF_OK;
   };
   // (re)capture `fn` into the context's graph under `key`; the kernels read
@@ -2644,13 +2643,23 @@ extern "C" int bpmf_pose_move(bpmf_ctx* c, int lid, int rounds) {
 // external-coordinate moves
 // ============================================================================
 namespace {
-int external_move_ligand(bpmf_ctx* c, int lid, int n_moves, int k_max,
-                         double sigma, hipStream_t st) {
-  LigHost& h = c->ligs[lid];
-  HIP_TRY(launch_external_move(c->grid, c->d_ligs + lid, h.dev.K, h.min_waves,
-                               n_moves, std::min(k_max, h.dev.K),
-                               (float)sigma, h.ext_acc, h.ext_try,
-                               lds_of(h, h.min_waves, false), c->seed, st));
+// the moves of ligands [l0, l1) in one launch per wavefront count present
+// (a ligand's blocks run in the launch of its own count)
+int external_moves_range(bpmf_ctx* c, int l0, int l1, int n_moves,
+                         int k_max, double sigma, hipStream_t st) {
+  for (int W = 1; W <= 2; ++W) {
+    int kg = 0, lds = 0;
+    for (int l = l0; l < l1; ++l) {
+      const LigHost& h = c->ligs[l];
+      if (h.min_waves != W) continue;
+      kg = std::max(kg, std::min(k_max, h.dev.K));
+      lds = std::max(lds, lds_of(h, W, false));
+    }
+    if (kg == 0) continue;
+    HIP_TRY(launch_external_moves(c->grid, c->d_ligs + l0, l1 - l0, kg, W,
+                                  n_moves, k_max, (float)sigma, lds, c->seed,
+                                  st));
+  }
   return BPMF_OK;
 }
 
@@ -2669,13 +2678,9 @@ extern "C" int bpmf_external_move(bpmf_ctx* c, int lid, int n_moves,
   if (rc) return rc;
   if (lid != -1 && (rc = check_lig(c, lid))) return rc;
   if ((rc = check_external(n_moves, k_max, sigma))) return rc;
-  for (size_t l = 0; l < c->ligs.size(); ++l) {
-    if (lid != -1 && (int)l != lid) continue;
-    if ((rc = external_move_ligand(c, (int)l, n_moves, k_max, sigma,
-                                   c->stream)))
-      return rc;
-  }
-  return BPMF_OK;
+  const int l0 = lid == -1 ? 0 : lid;
+  const int l1 = lid == -1 ? (int)c->ligs.size() : lid + 1;
+  return external_moves_range(c, l0, l1, n_moves, k_max, sigma, c->stream);
 }
 
 extern "C" int bpmf_get_external_stats(bpmf_ctx* c, int lid, int64_t* acc,

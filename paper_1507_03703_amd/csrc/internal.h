@@ -129,6 +129,8 @@ struct LigDev {
   unsigned long long* ex_acc;     // max(K-1,1)
   unsigned long long* ex_try;     // max(K-1,1)
   unsigned long long* nonfinite;  // 1
+  unsigned long long* ext_acc;    // K: external moves accepted per state
+  unsigned long long* ext_try;    // K: external moves tried per state
   // Neighbour-scheme sweeps apply the exchange (and record) that ends sweep
   // s-1 at the start of sweep s, in every replica's own block: sweep s
   // reads buffer (s-1)&1 and writes buffer s&1 (k_sweep_begin fills the

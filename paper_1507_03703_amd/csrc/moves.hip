@@ -17,32 +17,33 @@ namespace bpmf {
 
 namespace {
 
-// One workgroup of W waves per replica; replicas in states >= k_max return
-// at once (the paper attempts the moves only where the grids are nearly
-// off).  Move m of the call uses Philox draw 3m (three uniforms: the
-// quaternion by Shoemake's construction), 3m + 1 (three normals: the
-// translation) and 3m + 2 (the acceptance uniform), keyed by the ligand,
-// the replica and the sweep counter.  The moves are a chain, but their
+// One workgroup of W waves per (state k < k_max, ligand): the blocks of
+// grid row y move ligand ligs[y] when it needs W waves (else they return),
+// the replica in state k of it (the paper attempts the moves only where the
+// grids are nearly off).  Move m of the call uses Philox draw 3m (three
+// uniforms: the quaternion by Shoemake's construction), 3m + 1 (three
+// normals: the translation) and 3m + 2 (the acceptance uniform), keyed by
+// the ligand, the replica and the sweep counter.  The moves are a chain, but their
 // random numbers are not: each batch of up to kBatch moves has its
 // rotations, translations and ln u made first, one lane per move.
 constexpr int kBatch = 64;
 template <int C, int W>
 __global__ __launch_bounds__(W * kWave) void k_external_move(
-    GridDev g, const LigDev* __restrict__ lig, int n_moves, int k_max,
-    float sigma, unsigned long long* __restrict__ acc_k,
-    unsigned long long* __restrict__ try_k, uint64_t seed) {
+    GridDev g, const LigDev* __restrict__ ligs, int n_moves, int k_max,
+    float sigma, uint64_t seed) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float sRm[kBatch][9], stm[kBatch][3], sc0[3], st[3];
   __shared__ double s_lnu[kBatch];
   __shared__ double s_cp[4 * W];
   __shared__ double s_ui;  // restraint energy of the current pose
   __shared__ int s_acc;
-  const LigDev L = *lig;
+  const LigDev L = ligs[blockIdx.y];
   const int tid = threadIdx.x;
-  const int r = blockIdx.x;
   const int n = L.n;
-  const int k = L.state_of_replica[r];
-  if (k >= k_max || n_moves <= 0) return;  // uniform over the block
+  const int k = blockIdx.x;
+  // uniform over the block: another launch's ligand, or no such state
+  if ((n <= kWave ? 1 : 2) != W || k >= k_max || k >= L.K) return;
+  const int r = L.replica_of_state[k];
   const unsigned long long s = *L.counter;
   Shared sh;
   {
@@ -162,8 +163,8 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
     if (tid == 0) {
       const double ln_a = -beta * (e_new - e_cur);
       s_acc = (isfinite(ln_a) && s_lnu[j] < ln_a) ? 1 : 0;
-      atomicAdd(&try_k[k], 1ull);
-      if (s_acc) atomicAdd(&acc_k[k], 1ull);
+      atomicAdd(&L.ext_try[k], 1ull);
+      if (s_acc) atomicAdd(&L.ext_acc[k], 1ull);
     }
     __syncthreads();
     if (s_acc) {
@@ -188,16 +189,16 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
 }
 
 template <int C>
-hipError_t launch_c(const GridDev& g, const LigDev* lig, int K, int waves,
-                    int n_moves, int k_max, float sigma,
-                    unsigned long long* acc, unsigned long long* tries,
-                    int lds, uint64_t seed, hipStream_t st) {
+hipError_t launch_c(const GridDev& g, const LigDev* ligs, int n_lig, int kg,
+                    int waves, int n_moves, int k_max, float sigma, int lds,
+                    uint64_t seed, hipStream_t st) {
+  const dim3 grid(kg, n_lig);
   if (waves == 1)
-    hipLaunchKernelGGL((k_external_move<C, 1>), dim3(K), dim3(kWave), lds, st,
-                       g, lig, n_moves, k_max, sigma, acc, tries, seed);
+    hipLaunchKernelGGL((k_external_move<C, 1>), grid, dim3(kWave), lds, st, g,
+                       ligs, n_moves, k_max, sigma, seed);
   else if (waves == 2)
-    hipLaunchKernelGGL((k_external_move<C, 2>), dim3(K), dim3(2 * kWave), lds,
-                       st, g, lig, n_moves, k_max, sigma, acc, tries, seed);
+    hipLaunchKernelGGL((k_external_move<C, 2>), grid, dim3(2 * kWave), lds,
+                       st, g, ligs, n_moves, k_max, sigma, seed);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -205,18 +206,19 @@ hipError_t launch_c(const GridDev& g, const LigDev* lig, int K, int waves,
 
 }  // namespace
 
-hipError_t launch_external_move(const GridDev& g, const LigDev* lig, int K,
-                                int waves, int n_moves, int k_max,
-                                float sigma, unsigned long long* acc,
-                                unsigned long long* tries, int lds,
-                                uint64_t seed, hipStream_t st) {
-  if (K <= 0 || n_moves <= 0 || k_max <= 0) return hipSuccess;
+hipError_t launch_external_moves(const GridDev& g, const LigDev* ligs,
+                                 int n_lig, int k_grid, int waves, int n_moves,
+                                 int k_max, float sigma, int lds,
+                                 uint64_t seed, hipStream_t st) {
+  if (n_lig <= 0 || k_grid <= 0 || n_moves <= 0 || k_max <= 0)
+    return hipSuccess;
+  if (n_lig > 65535) return hipErrorInvalidValue;
   switch (g.C) {
     case 3:
-      return launch_c<3>(g, lig, K, waves, n_moves, k_max, sigma, acc, tries,
+      return launch_c<3>(g, ligs, n_lig, k_grid, waves, n_moves, k_max, sigma,
                          lds, seed, st);
     case 5:
-      return launch_c<5>(g, lig, K, waves, n_moves, k_max, sigma, acc, tries,
+      return launch_c<5>(g, ligs, n_lig, k_grid, waves, n_moves, k_max, sigma,
                          lds, seed, st);
     default:
       return hipErrorInvalidValue;

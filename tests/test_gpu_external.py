@@ -123,6 +123,39 @@ def test_external_moves_inside_sweep_calls_match_host_loop():
     b.close()
 
 
+def test_external_moves_of_several_ligands_in_one_launch():
+    """Ligands of one and two wavefronts and different state counts moved
+    by one sweep call (a launch per wavefront count, every ligand's states
+    below k_max in it) equal each ligand moved by its own call, bit for
+    bit; a ligand with fewer states than k_max has all of them moved."""
+    print_case("external, several ligands")
+    system = synth.make_system(1)
+    g = system.grid
+    ligs = [system.ligands[0],
+            synth.make_ligand(np.random.default_rng(91), 90, 8, box=9.0),
+            synth.make_ligand(np.random.default_rng(5), 30, 4)]
+    k_max, nx, sweeps = 6, 3, 4
+    a, ia = make_context(g, ligs, seed=system.seed)
+    b, ib = make_context(g, ligs, seed=system.seed)
+    a.hmc_sweep(sweeps, 10, exchange_every=1, external_moves=nx,
+                external_k_max=k_max, external_sigma=0.5)
+    for _ in range(sweeps):
+        b.hmc_sweep(1, 10, exchange_every=1)
+        for lb in ib:
+            b.external_move(lb, n_moves=nx, k_max=k_max, sigma=0.5)
+    for lig, la, lb in zip(ligs, ia, ib):
+        sa, sb = a.get_replicas(la), b.get_replicas(lb)
+        for key in ("x", "state_of_replica", "comps", "counter"):
+            assert np.array_equal(sa[key], sb[key]), (lig.n_atoms, key)
+        ea, eb = a.get_external_stats(la), b.get_external_stats(lb)
+        assert np.array_equal(ea["acc"], eb["acc"]), lig.n_atoms
+        kk = min(k_max, lig.n_states)
+        assert np.array_equal(ea["tries"], np.where(
+            np.arange(lig.n_states) < kk, sweeps * nx, 0)), lig.n_atoms
+    a.close()
+    b.close()
+
+
 def test_external_move_argument_errors():
     print_case("external errors")
     system = synth.make_system(1)
