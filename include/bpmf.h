@@ -223,8 +223,9 @@ typedef struct {
  * states below external_k_max (Sampling: the paper attempts them in the
  * states whose grid coupling is below 0.01, after each HMC move; here they
  * follow the unit's exchange, an equally valid order of moves that each
- * keep the target).  One unit is captured as a hipGraph and replayed (see
- * bpmf_set_graph).
+ * keep the target).  max(1, chunk / P) units (P = 1 without pose moves)
+ * are captured as one hipGraph and replayed, the units left over launched
+ * plainly (see bpmf_set_graph).
  * Random numbers: Philox-4x32-10 keyed by the context seed, counter
  * (index, ligand<<16 | replica, s, purpose) with purpose 1 = momenta
  * (index = atom), 2 = acceptance (index 0), 3 | sep<<8 = exchange
@@ -763,8 +764,9 @@ BPMF_API int bpmf_set_waves(bpmf_ctx* ctx, int waves);
  * 0 = plain launches).  The graph is captured on a private stream once per
  * (sweep arguments, ligand set) and launched on the context's stream; the
  * kernels read every per-sweep quantity from device memory, so replays are
- * identical to plain launches.  With timing enabled a graph launch is timed
- * as a whole and counts as `chunk` sweep launches. */
+ * identical to plain launches.  Units closed by moves are captured
+ * max(1, chunk / P) to a graph.  With timing enabled a graph launch is timed
+ * as a whole and counts as the sweeps it holds. */
 BPMF_API int bpmf_set_graph(bpmf_ctx* ctx, int chunk);
 
 /* Autotuner: time `n_sweeps` sweeps of n_leapfrog steps for each launch

@@ -1092,24 +1092,35 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
     // a fused unit's first sweep reads the run state its predecessor's
     // pose moves leave; the first unit's comes from a begin launch
     if (fused && units > 0) HIP_TRY(launch_sweep_begin(dl, nl, c->stream));
-    if (chunk > 0 && units > 0) {
+    // G units per captured graph (about `chunk` sweeps), so that the host
+    // launches one graph per chunk however short the units are; the units
+    // left over run as plain launches (the same kernels, the same bits)
+    const int G = chunk > 0 ? std::max(1, chunk / P) : 0;
+    int u = 0;
+    if (G > 0 && units >= G) {
       int sg[2];
       memcpy(sg, &a->external_sigma, sizeof(sg));
       const int key[bpmf_ctx::kKey] = {
           a->n_leapfrog, a->exchange_every, a->exchange_scheme, a->max_sep,
-          a->sample_every, fused ? -1 : 0, P, a->pose_move_every, NX,
+          a->sample_every, fused ? -G : G, P, a->pose_move_every, NX,
           a->external_k_max, sg[0], sg[1], n_sub, only};
-      if ((rc = ensure_graph(key, unit))) return rc;
-      for (int u = 0; u < units; ++u)
-        if ((rc = launch_timed(P, [&]() -> int {
+      if ((rc = ensure_graph(key, [&](hipStream_t st) -> int {
+             for (int q = 0; q < G; ++q) {
+               const int r = unit(st);
+               if (r) return r;
+             }
+             return BPMF_OK;
+           })))
+        return rc;
+      for (; u + G <= units; u += G)
+        if ((rc = launch_timed(G * P, [&]() -> int {
                HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
                return BPMF_OK;
              })))
           return rc;
-    } else {
-      for (int u = 0; u < units; ++u)
-        if ((rc = launch_timed(P, [&] { return unit(c->stream); }))) return rc;
     }
+    for (; u < units; ++u)
+      if ((rc = launch_timed(P, [&] { return unit(c->stream); }))) return rc;
     if (rest > 0 &&
         (rc = launch_timed(rest, [&] { return enqueue_run(c->stream, rest); })))
       return rc;
@@ -2648,17 +2659,14 @@ namespace {
 int external_moves_range(bpmf_ctx* c, int l0, int l1, int n_moves,
                          int k_max, double sigma, hipStream_t st) {
   for (int W = 1; W <= 2; ++W) {
-    int kg = 0, lds = 0;
+    int kg = 0;
     for (int l = l0; l < l1; ++l) {
       const LigHost& h = c->ligs[l];
-      if (h.min_waves != W) continue;
-      kg = std::max(kg, std::min(k_max, h.dev.K));
-      lds = std::max(lds, lds_of(h, W, false));
+      if (h.min_waves == W) kg = std::max(kg, std::min(k_max, h.dev.K));
     }
     if (kg == 0) continue;
     HIP_TRY(launch_external_moves(c->grid, c->d_ligs + l0, l1 - l0, kg, W,
-                                  n_moves, k_max, (float)sigma, lds, c->seed,
-                                  st));
+                                  n_moves, k_max, (float)sigma, c->seed, st));
   }
   return BPMF_OK;
 }

@@ -18,7 +18,7 @@ enum : uint32_t { kExternal = 6 };
 // the attempted and accepted moves per state
 hipError_t launch_external_moves(const GridDev& g, const LigDev* ligs,
                                  int n_lig, int k_grid, int waves, int n_moves,
-                                 int k_max, float sigma, int lds,
-                                 uint64_t seed, hipStream_t st);
+                                 int k_max, float sigma, uint64_t seed,
+                                 hipStream_t st);
 
 }  // namespace bpmf

@@ -23,51 +23,62 @@ namespace {
 // grids are nearly off).  Move m of the call uses Philox draw 3m (three
 // uniforms: the quaternion by Shoemake's construction), 3m + 1 (three
 // normals: the translation) and 3m + 2 (the acceptance uniform), keyed by
-// the ligand, the replica and the sweep counter.  The moves are a chain, but their
-// random numbers are not: each batch of up to kBatch moves has its
-// rotations, translations and ln u made first, one lane per move.
-constexpr int kBatch = 64;
+// the ligand, the replica and the sweep counter.
+//
+// The moves form a chain, but a candidate's position does not depend on
+// any energy: the candidates of the next kSpec moves, each made from the
+// one before as if that one were accepted, are built first and their grid
+// energies evaluated together (their gathers in flight at once); the
+// Metropolis decisions then run in order, and the round ends at the first
+// rejection (the later candidates were made from a configuration the chain
+// does not reach and are dropped).  The accepted chain is the sequential
+// one.  A move is rigid: the bonded (and pair) energy keeps its cached
+// value, the centre of mass moves by the translation (rotation is about
+// it), so only the grid terms and the restraint change.  The centre of mass
+// is summed from the positions at the start of every round and carried in
+// double within it.
+constexpr int kBatch = 64;  // moves whose random numbers are made at once
+constexpr int kSpec = 4;    // candidates per round
 template <int C, int W>
 __global__ __launch_bounds__(W * kWave) void k_external_move(
     GridDev g, const LigDev* __restrict__ ligs, int n_moves, int k_max,
     float sigma, uint64_t seed) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ float sRm[kBatch][9], stm[kBatch][3], sc0[3], st[3];
+  __shared__ float sRm[kBatch][9], stm[kBatch][3];
   __shared__ double s_lnu[kBatch];
-  __shared__ double s_cp[4 * W];
-  __shared__ double s_ui;  // restraint energy of the current pose
-  __shared__ int s_acc;
+  __shared__ double s_red[2][W][kSpec + 4];
   const LigDev L = ligs[blockIdx.y];
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wv = tid >> 6;
   const int n = L.n;
   const int k = blockIdx.x;
   // uniform over the block: another launch's ligand, or no such state
   if ((n <= kWave ? 1 : 2) != W || k >= k_max || k >= L.K) return;
   const int r = L.replica_of_state[k];
   const unsigned long long s = *L.counter;
-  Shared sh;
-  {
-    sh.pos = reinterpret_cast<float4*>(smem);
-    sh.red = reinterpret_cast<double*>(smem + 16 * kWave * W);
-    sh.com = reinterpret_cast<float*>(smem + 16 * kWave * W + 8 * W * kRedMax);
-    const int acc0 = 16 * kWave * W + 8 * W * kRedMax + 16 * W;
-    sh.sl = Slots{(lds_u32*)(smem + acc0), 0};  // no forces
-    stage_topology(L, smem + acc0, sh, tid, W * kWave);
-    __syncthreads();
-  }
   const bool owner = tid < n;
-  float x[3] = {0.f, 0.f, 0.f}, f[3];
+  float x[3] = {0.f, 0.f, 0.f};
   if (owner)
     for (int d = 0; d < 3; ++d) x[d] = L.x[(size_t)r * n * 3 + 3 * tid + d];
-  const float m = owner ? L.mass[tid] : 0.f;
-  float sc[C], w[C];
+  const double m = owner ? (double)L.mass[tid] : 0.0;
+  float sc[C];
+  double wd[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     sc[c] = owner ? L.scale[tid * C + c] : 0.f;
-    w[c] = L.wf[k * C + c];
+    wd[c] = L.wd[k * C + c];
   }
   const double beta = L.beta[k];
-  // energy and components of the current configuration (stored)
+  const double site[3] = {(double)L.site[0], (double)L.site[1],
+                          (double)L.site[2]};
+  const double d0 = (double)L.d0, krest = (double)L.krest;
+  // restraint energy at centre of mass c (Eq. binding_site)
+  auto restraint = [&](const double* c) {
+    double d2 = 0.0;
+    for (int d = 0; d < 3; ++d) d2 += (c[d] - site[d]) * (c[d] - site[d]);
+    const double ex = sqrt(d2) - d0;
+    return ex > 0.0 ? 0.5 * krest * ex * ex : 0.0;
+  };
+  // stored components of the current configuration and its energy
   double comp[1 + C];
   {
     const double* cp = L.comps + (size_t)r * (1 + C);
@@ -76,13 +87,22 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
   }
   double e_cur = comp[0];
 #pragma unroll
-  for (int c = 0; c < C; ++c) e_cur += L.wd[k * C + c] * comp[1 + c];
+  for (int c = 0; c < C; ++c) e_cur += wd[c] * comp[1 + c];
+  // grid values of this lane's atom in the current configuration (filled
+  // at the first acceptance; the stored channel sums hold until then)
+  float psi[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) psi[c] = 0.f;
   bool moved = false;
-  for (int mv = 0; mv < n_moves; ++mv) {
-    const int j = mv % kBatch;
-    if (j == 0) {
-      // this batch's rotations, translations and ln u (the previous
-      // batch's last reader passed the barrier that ended its move)
+  int batch0 = 0, batch1 = 0;  // moves whose random numbers are in LDS
+  int round = 0;
+  for (int mv = 0; mv < n_moves; ++round) {
+    if (mv + kSpec > batch1 && batch1 < n_moves) {
+      // random numbers of moves [mv, mv + kBatch), once every wave has
+      // taken the previous round's decisions from the old batch
+      __syncthreads();
+      batch0 = mv;
+      batch1 = mv + kBatch;
       const int b = mv + tid;
       if (tid < kBatch && b < n_moves) {
         // uniform unit quaternion (w, x, y, z) from three uniforms
@@ -108,81 +128,137 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
         s_lnu[tid] =
             log(u01d(draw(seed, 3u * b + 2u, L.id, r, s, kExternal).x));
       }
+      __syncthreads();
     }
-    // centre of mass in double (fixed-order: wave sums, then waves)
+    const int nd = min(kSpec, n_moves - mv);
+    // centre of mass of the current configuration, in double (fixed
+    // order: wave sums, then the waves in order); the round's partial slots
+    // alternate, so a wave one round ahead never overwrites what another
+    // still reads
+    double (*red)[kSpec + 4] = s_red[round & 1];
     {
-      const double mi = (double)m;
-      const double cx = wave_sum(mi * x[0]), cy = wave_sum(mi * x[1]);
-      const double cz = wave_sum(mi * x[2]), cm = wave_sum(mi);
-      if ((tid & (kWave - 1)) == 0) {
-        const int wv = tid >> 6;
-        s_cp[4 * wv] = cx;
-        s_cp[4 * wv + 1] = cy;
-        s_cp[4 * wv + 2] = cz;
-        s_cp[4 * wv + 3] = cm;
+      const double cx = wave_sum(m * x[0]), cy = wave_sum(m * x[1]);
+      const double cz = wave_sum(m * x[2]), cm = wave_sum(m);
+      if (lane == 0) {
+        red[wv][kSpec] = cx;
+        red[wv][kSpec + 1] = cy;
+        red[wv][kSpec + 2] = cz;
+        red[wv][kSpec + 3] = cm;
       }
     }
     __syncthreads();
-    if (tid == 0) {
-      double c[3] = {0.0, 0.0, 0.0}, M = 0.0;
-      for (int q = 0; q < W; ++q) {
-        for (int d = 0; d < 3; ++d) c[d] += s_cp[4 * q + d];
-        M += s_cp[4 * q + 3];
-      }
-      double d2 = 0.0;
-      for (int d = 0; d < 3; ++d) {
-        c[d] /= M;
-        sc0[d] = (float)c[d];
-        st[d] = (float)(c[d] + (double)stm[j][d]);
-        d2 += (c[d] - (double)L.site[d]) * (c[d] - (double)L.site[d]);
-      }
-      // restraint energy at the current centre of mass (Eq. binding_site)
-      const double ex = sqrt(d2) - (double)L.d0;
-      s_ui = ex > 0.0 ? 0.5 * (double)L.krest * ex * ex : 0.0;
+    double c0[3] = {0.0, 0.0, 0.0}, M = 0.0;
+    for (int q = 0; q < W; ++q) {
+      for (int d = 0; d < 3; ++d) c0[d] += red[q][kSpec + d];
+      M += red[q][kSpec + 3];
     }
-    __syncthreads();
-    const float* sR = sRm[j];
-    // x' = c + sigma z + R (x - c)
-    float xn[3] = {0.f, 0.f, 0.f};
-    if (owner) {
-      const float y[3] = {x[0] - sc0[0], x[1] - sc0[1], x[2] - sc0[2]};
-      for (int a = 0; a < 3; ++a)
-        xn[a] = st[a] + sR[3 * a] * y[0] + sR[3 * a + 1] * y[1] +
-                sR[3 * a + 2] * y[2];
-    }
-    // the move is rigid: the bonded (and pair) energy is the cached one, the
-    // stored first component less the restraint energy of the current
-    // centre of mass; only the grid terms and the restraint are evaluated
-    double t[6 + C];
-    eval_block<C, W, false, true, true, false>(g, L, w, xn, m, sc, f, t, 0.f,
-                                               0.f, sh, tid);
-    const double u0 = (comp[0] - s_ui) + t[3];
-    double e_new = u0;
+    for (int d = 0; d < 3; ++d) c0[d] /= M;
+    // candidates: y_j = c_j + t_j + R_j (y_{j-1} - c_j), c_j the centre of
+    // mass of y_{j-1} (c_0 of the current configuration, then carried)
+    float y[kSpec][3];
+    double cj[kSpec][3];
+    {
+      double c[3] = {c0[0], c0[1], c0[2]};
+      float p[3] = {x[0], x[1], x[2]};
 #pragma unroll
-    for (int c = 0; c < C; ++c) e_new += L.wd[k * C + c] * t[4 + c];
-    if (tid == 0) {
-      const double ln_a = -beta * (e_new - e_cur);
-      s_acc = (isfinite(ln_a) && s_lnu[j] < ln_a) ? 1 : 0;
-      atomicAdd(&L.ext_try[k], 1ull);
-      if (s_acc) atomicAdd(&L.ext_acc[k], 1ull);
+      for (int j = 0; j < kSpec; ++j) {
+        const int q = mv + j - batch0;
+        if (j < nd) {
+          const float* R = sRm[q];
+          float cf[3], tf[3];
+          for (int d = 0; d < 3; ++d) {
+            cf[d] = (float)c[d];
+            tf[d] = (float)(c[d] + (double)stm[q][d]);
+            c[d] += (double)stm[q][d];
+          }
+          const float u[3] = {p[0] - cf[0], p[1] - cf[1], p[2] - cf[2]};
+          for (int a = 0; a < 3; ++a)
+            p[a] = tf[a] + R[3 * a] * u[0] + R[3 * a + 1] * u[1] +
+                   R[3 * a + 2] * u[2];
+        }
+        for (int d = 0; d < 3; ++d) {
+          y[j][d] = p[d];
+          cj[j][d] = c[d];
+        }
+      }
     }
-    __syncthreads();
-    if (s_acc) {
-      for (int d = 0; d < 3; ++d) x[d] = xn[d];
-      e_cur = e_new;
-      comp[0] = u0;
+    // grid energies of every candidate: the gathers first, then the
+    // interpolation; per atom the weighted sum over channels
+    Corners<C> cn[kSpec];
 #pragma unroll
-      for (int c = 0; c < C; ++c) comp[1 + c] = t[4 + c];
+    for (int j = 0; j < kSpec; ++j)
+      if (j < nd) grid_fetch<C>(g, y[j][0], y[j][1], y[j][2], cn[j]);
+    float pj[kSpec][C];
+    double gj[kSpec];
+#pragma unroll
+    for (int j = 0; j < kSpec; ++j) {
+      gj[j] = 0.0;
+      if (j < nd) {
+        grid_finish<C, false>(g, cn[j], sc, pj[j], nullptr);
+#pragma unroll
+        for (int c = 0; c < C; ++c) gj[j] += wd[c] * (double)pj[j][c];
+        gj[j] = wave_sum(gj[j]);
+      }
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int j = 0; j < kSpec; ++j) red[wv][j] = gj[j];
+    __syncthreads();
+    // the decisions in order, by every thread from the same sums
+    const double base = comp[0] - restraint(c0);
+    int acc = 0;
+    double e_acc = e_cur, u_acc = comp[0];
+    for (int j = 0; j < nd; ++j) {
+      double G = 0.0;
+      for (int q = 0; q < W; ++q) G += red[q][j];
+      const double u0 = base + restraint(cj[j]);
+      const double e_new = u0 + G;
+      const double ln_a = -beta * (e_new - e_acc);
+      if (!(isfinite(ln_a) && s_lnu[mv + j - batch0] < ln_a)) break;
+      e_acc = e_new;
+      u_acc = u0;
+      ++acc;
+    }
+    const int used = acc < nd ? acc + 1 : nd;
+    if (tid == 0) {
+      atomicAdd(&L.ext_try[k], (unsigned long long)used);
+      if (acc) atomicAdd(&L.ext_acc[k], (unsigned long long)acc);
+    }
+    if (acc > 0) {
+#pragma unroll
+      for (int j = 0; j < kSpec; ++j)
+        if (j == acc - 1) {
+          for (int d = 0; d < 3; ++d) x[d] = y[j][d];
+#pragma unroll
+          for (int c = 0; c < C; ++c) psi[c] = pj[j][c];
+        }
+      e_cur = e_acc;
+      comp[0] = u_acc;
       moved = true;
     }
+    mv += used;
   }
   if (moved) {
+    // channel sums of the final configuration, in the slots the last round
+    // did not use (their readers, two rounds back, are done)
+    double (*red)[kSpec + 4] = s_red[round & 1];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const double v = wave_sum((double)psi[c]);
+      if (lane == 0) red[wv][c] = v;
+    }
+    __syncthreads();
     if (owner)
       for (int d = 0; d < 3; ++d) L.x[(size_t)r * n * 3 + 3 * tid + d] = x[d];
     if (tid == 0) {
       double* cw = L.comps + (size_t)r * (1 + C);
+      cw[0] = comp[0];
 #pragma unroll
-      for (int e = 0; e <= C; ++e) cw[e] = comp[e];
+      for (int c = 0; c < C; ++c) {
+        double v = 0.0;
+        for (int q = 0; q < W; ++q) v += red[q][c];
+        cw[1 + c] = v;
+      }
       L.fvalid[r] = 0;  // the stored start-of-trajectory forces are stale
     }
   }
@@ -190,15 +266,15 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
 
 template <int C>
 hipError_t launch_c(const GridDev& g, const LigDev* ligs, int n_lig, int kg,
-                    int waves, int n_moves, int k_max, float sigma, int lds,
+                    int waves, int n_moves, int k_max, float sigma,
                     uint64_t seed, hipStream_t st) {
   const dim3 grid(kg, n_lig);
   if (waves == 1)
-    hipLaunchKernelGGL((k_external_move<C, 1>), grid, dim3(kWave), lds, st, g,
+    hipLaunchKernelGGL((k_external_move<C, 1>), grid, dim3(kWave), 0, st, g,
                        ligs, n_moves, k_max, sigma, seed);
   else if (waves == 2)
-    hipLaunchKernelGGL((k_external_move<C, 2>), grid, dim3(2 * kWave), lds,
-                       st, g, ligs, n_moves, k_max, sigma, seed);
+    hipLaunchKernelGGL((k_external_move<C, 2>), grid, dim3(2 * kWave), 0, st,
+                       g, ligs, n_moves, k_max, sigma, seed);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -208,18 +284,18 @@ hipError_t launch_c(const GridDev& g, const LigDev* ligs, int n_lig, int kg,
 
 hipError_t launch_external_moves(const GridDev& g, const LigDev* ligs,
                                  int n_lig, int k_grid, int waves, int n_moves,
-                                 int k_max, float sigma, int lds,
-                                 uint64_t seed, hipStream_t st) {
+                                 int k_max, float sigma, uint64_t seed,
+                                 hipStream_t st) {
   if (n_lig <= 0 || k_grid <= 0 || n_moves <= 0 || k_max <= 0)
     return hipSuccess;
   if (n_lig > 65535) return hipErrorInvalidValue;
   switch (g.C) {
     case 3:
       return launch_c<3>(g, ligs, n_lig, k_grid, waves, n_moves, k_max, sigma,
-                         lds, seed, st);
+                         seed, st);
     case 5:
       return launch_c<5>(g, ligs, n_lig, k_grid, waves, n_moves, k_max, sigma,
-                         lds, seed, st);
+                         seed, st);
     default:
       return hipErrorInvalidValue;
   }

@@ -96,14 +96,16 @@ def test_replicas_above_k_max_are_untouched():
 
 
 def test_external_moves_inside_sweep_calls_match_host_loop():
-    """Units of one sweep closed by external moves (one captured graph,
-    replayed) equal sweep and move calls from the host, bit for bit, and
+    """Units of one sweep closed by external moves (three to a captured
+    graph, replayed, and the rest launched plainly) equal sweep and move
+    calls from the host, bit for bit, and
     the chain keeps sampling the same states' statistics."""
     print_case("external in sweeps")
     system = synth.make_system(1)
     lig, g = system.ligands[0], system.grid
     a, (la,) = make_context(g, [lig], seed=system.seed, capacity=8)
     b, (lb,) = make_context(g, [lig], seed=system.seed, capacity=8)
+    a.set_graph(3)  # three one-sweep units per graph, two left over
     a.hmc_sweep(8, 10, exchange_every=1, sample_every=2, external_moves=3,
                 external_k_max=4, external_sigma=0.4)
     for _ in range(8):
@@ -137,6 +139,7 @@ def test_external_moves_of_several_ligands_in_one_launch():
     k_max, nx, sweeps = 6, 3, 4
     a, ia = make_context(g, ligs, seed=system.seed)
     b, ib = make_context(g, ligs, seed=system.seed)
+    a.set_graph(2)  # two one-sweep units per graph
     a.hmc_sweep(sweeps, 10, exchange_every=1, external_moves=nx,
                 external_k_max=k_max, external_sigma=0.5)
     for _ in range(sweeps):

@@ -246,6 +246,8 @@ def test_pose_moves_of_several_ligands_in_one_call(all_props):
                                    lig.tors[lig.cond_tors], p)
         if mode == "plain":
             ctx.set_graph(0)
+        if mode == "graph":
+            ctx.set_graph(15)  # three units per graph, one left over
         if mode == "host":
             for _ in range(4):
                 ctx.hmc_sweep(5, 10, exchange_every=1, sample_every=3)
@@ -323,6 +325,8 @@ def test_pose_moves_inside_sweep_calls_match_host_loop():
         ctx.proposal_setup(lid, lig.frame_atoms, lig.tors[lig.cond_tors], p)
         if mode == "plain":
             ctx.set_graph(0)
+        if mode == "graph":
+            ctx.set_graph(15)  # three units per graph
         if mode == "host":
             for _ in range(6):
                 ctx.hmc_sweep(5, 10, exchange_every=1, sample_every=3)
