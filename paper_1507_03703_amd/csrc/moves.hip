@@ -154,7 +154,10 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
     }
     for (int d = 0; d < 3; ++d) c0[d] /= M;
     // candidates: y_j = c_j + t_j + R_j (y_{j-1} - c_j), c_j the centre of
-    // mass of y_{j-1} (c_0 of the current configuration, then carried)
+    // mass of y_{j-1} (c_0 of the current configuration, then carried).
+    // Every step below runs for all kSpec candidates without branches, so
+    // that the independent candidates interleave; those past the call's
+    // last move (j >= nd) repeat its random numbers and are never accepted.
     float y[kSpec][3];
     double cj[kSpec][3];
     {
@@ -162,63 +165,76 @@ __global__ __launch_bounds__(W * kWave) void k_external_move(
       float p[3] = {x[0], x[1], x[2]};
 #pragma unroll
       for (int j = 0; j < kSpec; ++j) {
-        const int q = mv + j - batch0;
-        if (j < nd) {
-          const float* R = sRm[q];
-          float cf[3], tf[3];
-          for (int d = 0; d < 3; ++d) {
-            cf[d] = (float)c[d];
-            tf[d] = (float)(c[d] + (double)stm[q][d]);
-            c[d] += (double)stm[q][d];
-          }
-          const float u[3] = {p[0] - cf[0], p[1] - cf[1], p[2] - cf[2]};
-          for (int a = 0; a < 3; ++a)
-            p[a] = tf[a] + R[3 * a] * u[0] + R[3 * a + 1] * u[1] +
-                   R[3 * a + 2] * u[2];
+        const int q = min(j, nd - 1) + mv - batch0;
+        const float* R = sRm[q];
+        float cf[3], tf[3];
+        for (int d = 0; d < 3; ++d) {
+          cf[d] = (float)c[d];
+          tf[d] = (float)(c[d] + (double)stm[q][d]);
+          c[d] += (double)stm[q][d];
         }
+        const float u[3] = {p[0] - cf[0], p[1] - cf[1], p[2] - cf[2]};
+        for (int a = 0; a < 3; ++a)
+          p[a] = tf[a] + R[3 * a] * u[0] + R[3 * a + 1] * u[1] +
+                 R[3 * a + 2] * u[2];
         for (int d = 0; d < 3; ++d) {
           y[j][d] = p[d];
           cj[j][d] = c[d];
         }
       }
     }
-    // grid energies of every candidate: the gathers first, then the
-    // interpolation; per atom the weighted sum over channels
+    // grid energies of every candidate: the gathers first (the restraint
+    // energies are computed while they fly), then the interpolation; per
+    // atom the weighted sum over channels
     Corners<C> cn[kSpec];
 #pragma unroll
     for (int j = 0; j < kSpec; ++j)
-      if (j < nd) grid_fetch<C>(g, y[j][0], y[j][1], y[j][2], cn[j]);
+      grid_fetch<C>(g, y[j][0], y[j][1], y[j][2], cn[j]);
+    double ui[kSpec];
+#pragma unroll
+    for (int j = 0; j < kSpec; ++j) ui[j] = restraint(cj[j]);
+    const double base = comp[0] - restraint(c0);
     float pj[kSpec][C];
     double gj[kSpec];
 #pragma unroll
     for (int j = 0; j < kSpec; ++j) {
+      grid_finish<C, false>(g, cn[j], sc, pj[j], nullptr);
       gj[j] = 0.0;
-      if (j < nd) {
-        grid_finish<C, false>(g, cn[j], sc, pj[j], nullptr);
 #pragma unroll
-        for (int c = 0; c < C; ++c) gj[j] += wd[c] * (double)pj[j][c];
-        gj[j] = wave_sum(gj[j]);
-      }
+      for (int c = 0; c < C; ++c) gj[j] += wd[c] * (double)pj[j][c];
     }
+#pragma unroll
+    for (int j = 0; j < kSpec; ++j) gj[j] = wave_sum(gj[j]);
     if (lane == 0)
 #pragma unroll
       for (int j = 0; j < kSpec; ++j) red[wv][j] = gj[j];
     __syncthreads();
-    // the decisions in order, by every thread from the same sums
-    const double base = comp[0] - restraint(c0);
-    int acc = 0;
-    double e_acc = e_cur, u_acc = comp[0];
-    for (int j = 0; j < nd; ++j) {
+    // the decisions in order, by every thread from the same sums: move j
+    // is accepted when every earlier one of the round was and its own test
+    // passes against the energy of candidate j - 1
+    double e_new[kSpec];
+#pragma unroll
+    for (int j = 0; j < kSpec; ++j) {
       double G = 0.0;
       for (int q = 0; q < W; ++q) G += red[q][j];
-      const double u0 = base + restraint(cj[j]);
-      const double e_new = u0 + G;
-      const double ln_a = -beta * (e_new - e_acc);
-      if (!(isfinite(ln_a) && s_lnu[mv + j - batch0] < ln_a)) break;
-      e_acc = e_new;
-      u_acc = u0;
-      ++acc;
+      e_new[j] = (base + ui[j]) + G;
     }
+    int acc = 0;
+    bool go = true;
+#pragma unroll
+    for (int j = 0; j < kSpec; ++j) {
+      const double ln_a = -beta * (e_new[j] - (j ? e_new[j - 1] : e_cur));
+      const double lnu = s_lnu[min(j, nd - 1) + mv - batch0];
+      go = go && j < nd && isfinite(ln_a) && lnu < ln_a;
+      acc += go ? 1 : 0;
+    }
+    double e_acc = e_cur, u_acc = comp[0];
+#pragma unroll
+    for (int j = 0; j < kSpec; ++j)
+      if (j == acc - 1) {
+        e_acc = e_new[j];
+        u_acc = base + ui[j];
+      }
     const int used = acc < nd ? acc + 1 : nd;
     if (tid == 0) {
       atomicAdd(&L.ext_try[k], (unsigned long long)used);
