@@ -79,8 +79,7 @@ __device__ bool pair_accepts(const LigDev& L, Pair p, int pin,
                        bhi * (energy(whi, clo) - energy(whi, chi));
   const uint32_t purpose = (uint32_t)kExchange | (1u << 8);
   const U4 o = draw(seed, (uint32_t)p.lo, L.id, 0, s - 1ull, purpose);
-  const double lnu = log(u01d(o.x));
-  return isfinite(delta) && (lnu < -delta);
+  return isfinite(delta) && ln_u_below(o.x, -delta);
 }
 
 __device__ int deferred_state(const LigDev& L, int a, unsigned long long s,

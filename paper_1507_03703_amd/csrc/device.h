@@ -141,6 +141,19 @@ __device__ __forceinline__ float u01f(uint32_t v) {
   return (float)((double)v + 1.0) * 2.3283064365386962890625e-10f;
 }
 
+// The Metropolis test ln u < t for u = u01d(v), decided exactly as in double
+// precision: u >= 2^-32 puts |ln u| below 22.2, where the single-precision
+// logarithm (of u rounded to float) is within 1e-5 of ln u, so outside a
+// band of 1e-4 about t its answer is the double one; inside the band the
+// double logarithm decides.  t must not be NaN.
+__device__ __forceinline__ bool ln_u_below(uint32_t v, double t) {
+  const double u = u01d(v);
+  const double lf = (double)logf((float)u);
+  if (lf < t - 1e-4) return true;
+  if (lf > t + 1e-4) return false;
+  return log(u) < t;
+}
+
 // three standard normals (Box-Muller on (x,y) and (z,w))
 __device__ __forceinline__ void normals3(const U4& o, float& a, float& b,
                                          float& c) {

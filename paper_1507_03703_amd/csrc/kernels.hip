@@ -491,18 +491,26 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
 #pragma unroll
     for (int q = 0; q < 1 + C; ++q) cp[q] = cpp[q];
   }
-  // the decision is the block's: wavefront 0 takes it and publishes it
-  // with the barrier that ends the staging
+  // the decision is the block's: the last wavefront (the one with the
+  // fewest atoms) takes it and publishes it with the barrier that ends the
+  // staging
   __shared__ int s_swap;
-  if (pr.active && tid < kWave) {
+  if (pr.active && (tid >> 6) == W - 1) {
     const bool sw = pair_accepts<C>(L, pr, pin, s, seed);
-    if (tid == 0) {
+    if (tid == (W - 1) * kWave) {
       s_swap = sw ? 1 : 0;
       if (a == pr.lo) {
         atomicAdd(&L.ex_try[pr.lo], 1ull);
         if (sw) atomicAdd(&L.ex_acc[pr.lo], 1ull);
       }
     }
+  }
+  // the momenta's standard normals do not depend on the state: drawn
+  // beside the decision
+  float z[3] = {0.f, 0.f, 0.f};
+  if (owner) {
+    const U4 o = draw(seed, (uint32_t)tid, L.id, r, s, kMomenta);
+    normals3(o, z[0], z[1], z[2]);
   }
   __syncthreads();  // the staged topology and the decision
   const bool swap = pr.active && s_swap != 0;
@@ -540,16 +548,11 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
                                              tid];
     }
   }
-  if (owner) {
-    const U4 o = draw(seed, (uint32_t)tid, L.id, r, s, kMomenta);
-    float z0, z1, z2;
-    normals3(o, z0, z1, z2);
-    const float sd = sqrtf((float)kRGas * T * im * 1e-4f);
-    v[0] = sd * z0;
-    v[1] = sd * z1;
-    v[2] = sd * z2;
-  } else {
-    v[0] = v[1] = v[2] = 0.f;
+  {
+    const float sd = owner ? sqrtf((float)kRGas * T * im * 1e-4f) : 0.f;
+    v[0] = sd * z[0];
+    v[1] = sd * z[1];
+    v[2] = sd * z[2];
   }
   const float ke0 = 0.5f * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
 
@@ -633,9 +636,8 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     KE1 *= 1e4;
     const double dH = (U1 + KE1) - (U0 + KE0);
     const U4 o = draw(seed, 0u, L.id, r, s, kAccept);
-    const double lnu = log(u01d(o.x));
     finite = isfinite(dH) && nbad == 0.0;
-    const bool acc0 = finite && (lnu < -beta * dH);
+    const bool acc0 = finite && ln_u_below(o.x, -beta * dH);
     if (tid == 0) s_acc = acc0 ? 1 : 0;
   }
   block_sync();
