@@ -56,15 +56,15 @@ GRID_BYTES_PER_EVAL = 96  # 8 corners x 3 channels x 4 B
 # kernel and workload: one sweep launch (at the given wavefronts per
 # replica), one harness launch, one energy-matrix call (its launches
 # summed); valid only while the kernel sources hash to TRAFFIC_SOURCES
-TRAFFIC_SOURCES = "7b5e06cf47d1a0f8"
+TRAFFIC_SOURCES = "72a9d599c9c2eb71"
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     ("k_hmc_sweep", "c5_large_batched"):
-        {"waves": 4, "fetch_kib": 9157.522, "write_kib": 4431.213},
+        {"waves": 4, "fetch_kib": 9067.416, "write_kib": 4431.2},
     ("k_hmc_sweep", "c2_plain_production"):
-        {"waves": None, "fetch_kib": 768.186, "write_kib": 198.214},
+        {"waves": None, "fetch_kib": 761.121, "write_kib": 198.215},
     ("k_hmc_sweep", "c3_batched_uneven"):
-        {"waves": 2, "fetch_kib": 37662.407, "write_kib": 23628.451},
+        {"waves": 2, "fetch_kib": 37142.211, "write_kib": 23627.091},
 }
 KERNEL_SOURCES = ("device.h", "kernels.hip", "internal.h")
 
