@@ -65,6 +65,10 @@ TRAFFIC = {
         {"waves": None, "fetch_kib": 761.121, "write_kib": 198.215},
     ("k_hmc_sweep", "c3_batched_uneven"):
         {"waves": 2, "fetch_kib": 37142.211, "write_kib": 23627.091},
+    ("k_grid_eval", "c3_batched_uneven"):
+        {"waves": None, "fetch_kib": 3379806.094, "write_kib": 3383700.0},
+    ("k_energy_matrix", "c3_batched_uneven"):
+        {"waves": None, "fetch_kib": 1170698.093, "write_kib": 525099.617},
 }
 KERNEL_SOURCES = ("device.h", "kernels.hip", "internal.h")
 
