@@ -77,6 +77,46 @@ def test_external_moves_match_oracle(which, sigma, n_moves):
     ctx.close()
 
 
+@pytest.mark.parametrize("which", ["c1", "wide90"])
+def test_long_move_chains_cross_random_number_batches(which):
+    """70 moves per call: the rounds of candidate moves cross the 64-move
+    batches of random numbers (a batch made anew mid-chain), one and two
+    wavefronts, against the oracle's sequential chain."""
+    print_case("external moves, 70 per call", which)
+    system = synth.make_system(1)
+    g = system.grid
+    lig = system.ligands[0] if which == "c1" else synth.make_ligand(
+        np.random.default_rng(91), 90, 8, box=9.0)
+    og, ol = oracle.OGrid(g), oracle.OLigand(lig)
+    ctx, (lid,) = make_context(g, [lig], seed=system.seed)
+    K, n_moves, sigma = lig.n_states, 70, 0.25
+    checked = 0
+    for rnd in range(2):
+        ctx.hmc_sweep(2, 10, exchange_every=1)
+        st = ctx.get_replicas(lid)
+        before = ctx.get_external_stats(lid)
+        ctx.external_move(lid, n_moves=n_moves, k_max=K, sigma=sigma)
+        st2 = ctx.get_replicas(lid)
+        after = ctx.get_external_stats(lid)
+        assert np.array_equal(after["tries"] - before["tries"],
+                              np.full(K, n_moves))
+        d_acc = after["acc"] - before["acc"]
+        for r in range(K):
+            k = st["state_of_replica"][r]
+            xo, n_acc, lns = Ex.external_moves(
+                og, ol, st["x"][r], k, system.seed, lid, r, st["counter"],
+                n_moves, sigma)
+            # ln alpha of a move is good to ~1e-4 in float32 (grid energies
+            # of some hundred kT): decisions within 2e-3 of ln u are left out
+            if min(abs(lu - la) for la, lu in lns) < 2e-3:
+                continue
+            checked += 1
+            assert d_acc[k] == n_acc, (rnd, r, d_acc[k], n_acc)
+            assert np.max(np.abs(st2["x"][r] - xo)) < 5e-4, (rnd, r)
+    assert checked >= 8, checked
+    ctx.close()
+
+
 def test_replicas_above_k_max_are_untouched():
     print_case("external k_max")
     system = synth.make_system(1)
