@@ -649,21 +649,22 @@ __device__ __forceinline__ double wave_max_d(double v) {
 // (2 (1 - cos|omega|)); one (preimage, component) term per lane of the
 // calling wavefront (all 64 lanes call; lanes past the terms add nothing)
 // and a log-sum-exp across the wavefront.  |omega| < 1e-9: the identity
-// rotation, one term per component.
-__device__ double log_q_se3_wave(const Mix& p, const double t[3],
-                                 const double w0[3]) {
+// rotation, one term per component.  c0[j]: the pose-free part of
+// component j's log-density, its normalised log weight less 3 ln 2 pi and
+// the logs of its six standard deviations.
+__device__ double log_q_se3_wave(const Mix& p, const double* c0,
+                                 const double t[3], const double w0[3]) {
   const int lane = threadIdx.x & 63;
-  const float lse = mix_lse(p);
   const double th = sqrt(w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2]);
   const bool small = th < 1e-9;
   const int n_terms = small ? kNComp : (2 * kFold + 1) * kNComp;
   double term = -INFINITY;
   if (lane < n_terms) {
     const int j = lane % kNComp, m = lane / kNComp - kFold;
-    double s = (double)(p.lw[j] - lse) - 3.0 * log(2.0 * M_PI);
+    double s = c0[j];
     for (int d = 0; d < 3; ++d) {
       const double z = (t[d] - p.mt[j][d]) / p.st[j][d];
-      s += -0.5 * z * z - log((double)p.st[j][d]) - log((double)p.sw[j][d]);
+      s += -0.5 * z * z;
     }
     if (small) {
       for (int d = 0; d < 3; ++d) {
@@ -716,6 +717,9 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
   __shared__ double s_cp[2 * W * 3];
   __shared__ Mix s_mix;
   __shared__ double s_pose[12];  // t0, w0, t1, w1p
+  // per component: -3 ln 2 pi - sum_d (ln st + ln sw), then (once the
+  // weights are normalised) plus its normalised log weight
+  __shared__ double s_c0[kNComp];
   double lq_ratio = 0.0;
   {
     const bool own = tid < n;
@@ -731,15 +735,25 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
       s_cp[4 * wv + 2] = cz;
       s_cp[4 * wv + 3] = cm;
     }
-    if (tid < kNComp) {
-      const float* o = out + (size_t)task.row * kNOut + 13 * tid;
-      s_mix.lw[tid] = o[0];
+    // the mixture on the last wavefront (the one with the fewest atoms),
+    // with each component's log-density constant but its weight
+    const int j = tid - (W - 1) * kWave;
+    if (j >= 0 && j < kNComp) {
+      const float* o = out + (size_t)task.row * kNOut + 13 * j;
+      s_mix.lw[j] = o[0];
+      double c = -3.0 * log(2.0 * M_PI);
       for (int a = 0; a < 3; ++a) {
-        s_mix.mt[tid][a] = o[1 + a];
-        s_mix.mw[tid][a] = (float)M_PI * tanhf(o[4 + a]);
-        s_mix.st[tid][a] = kSt0 + (kSt1 - kSt0) * sigm(o[7 + a]);
-        s_mix.sw[tid][a] = kSw0 + (kSw1 - kSw0) * sigm(o[10 + a]);
+        s_mix.mt[j][a] = o[1 + a];
+        s_mix.mw[j][a] = (float)M_PI * tanhf(o[4 + a]);
+        const float sd_t = kSt0 + (kSt1 - kSt0) * sigm(o[7 + a]);
+        const float sd_w = kSw0 + (kSw1 - kSw0) * sigm(o[10 + a]);
+        s_mix.st[j][a] = sd_t;
+        s_mix.sw[j][a] = sd_w;
+        // single-precision logs: within 1e-6 of the double ones on the
+        // deviations' range, far inside ln q's float error elsewhere
+        c += -(double)logf(sd_t) - (double)logf(sd_w);
       }
+      s_c0[j] = c;
     }
   }
   __syncthreads();
@@ -777,14 +791,33 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     const double ex0 = sqrt(d2) - (double)L.d0;
     s_ui0 = ex0 > 0.0 ? 0.5 * (double)L.krest * ex0 * ex0 : 0.0;
   }
-  if (tid == tb) {
+  // the wavefront of lane tb: the components' weights and log-density
+  // constants, one component per lane; the weights then go to every lane
+  double wt[kNComp];
+  if ((tid >> 6) == (tb >> 6)) {
     const float lse = mix_lse(s_mix);
+    const int jj = tid - tb;
+    double wj = 0.0;
+    if (jj < kNComp) {
+      const double lw = (double)(s_mix.lw[jj] - lse);
+      wj = exp(lw);
+      s_c0[jj] += lw;
+    }
+    for (int j = 0; j < kNComp; ++j) {
+      const long long b = __double_as_longlong(wj);
+      const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), j);
+      const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+      wt[j] = __longlong_as_double(((long long)hi << 32) |
+                                   (long long)(unsigned)lo);
+    }
+  }
+  if (tid == tb) {
     // component by inverse CDF, then (t, omega) by Gaussian draws
     const U4 o0 = draw(seed, 0u, L.id, r, s, kPose);
     const double u = u01d(o0.x);
     double cum[kNComp], tot = 0.0;
     for (int j = 0; j < kNComp; ++j) {
-      tot += exp((double)(s_mix.lw[j] - lse));
+      tot += wt[j];
       cum[j] = tot;
     }
     int j = 0;
@@ -816,13 +849,13 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
     const int wv = tid >> 6;
     if (W >= 2) {
       if (wv < 2) {
-        const double lq =
-            log_q_se3_wave(s_mix, s_pose + 6 * wv, s_pose + 6 * wv + 3);
+        const double lq = log_q_se3_wave(s_mix, s_c0, s_pose + 6 * wv,
+                                         s_pose + 6 * wv + 3);
         if ((tid & 63) == 0) s_lq[wv] = lq;
       }
     } else {
-      const double lq0 = log_q_se3_wave(s_mix, s_pose, s_pose + 3);
-      const double lq1 = log_q_se3_wave(s_mix, s_pose + 6, s_pose + 9);
+      const double lq0 = log_q_se3_wave(s_mix, s_c0, s_pose, s_pose + 3);
+      const double lq1 = log_q_se3_wave(s_mix, s_c0, s_pose + 6, s_pose + 9);
       if (tid == 0) {
         s_lq[0] = lq0;
         s_lq[1] = lq1;
@@ -872,8 +905,8 @@ __global__ __launch_bounds__(W * kWave) void k_pose_move(
   __shared__ int s_acc;
   if (tid == 0) {
     const double ln_a = -L.beta[k] * (E1 - E0) + lq_ratio;
-    const double lnu = log(u01d(draw(seed, 3u, L.id, r, s, kPose).x));
-    s_acc = (s_ok && isfinite(ln_a) && lnu < ln_a) ? 1 : 0;
+    const U4 ou = draw(seed, 3u, L.id, r, s, kPose);
+    s_acc = (s_ok && isfinite(ln_a) && ln_u_below(ou.x, ln_a)) ? 1 : 0;
     P.last_ln_alpha[r] = ln_a;
     atomicAdd(&P.pose_try[k], 1ull);
     if (s_acc) atomicAdd(&P.pose_acc[k], 1ull);
