@@ -26,7 +26,8 @@ ligands after the timed steps.
 Further legs in the same JSON line: "production_single_ligand" (a 48-atom
 ligand, 64 replicas, 128^3 grids, 5000 sweeps of 20 steps, u_kn, MBAR),
 "batched" (256 ligands of 10-80 atoms x 32 replicas on 160^3 grids, 2000
-sweeps; the launch shape picked by the autotuner), "bulk_interpolation"
+sweeps; the launch shape picked by the autotuner), each with the oracle
+timed on a bounded sample of it as well, "bulk_interpolation"
 (u_kn and the interpolation harness on the sample sets of the batched
 workloads), "learned_proposal" (plain HMC, the paper's external moves and
 learned pose moves on the 24-atom, 64-state soft-grid system, each over
@@ -1169,12 +1170,17 @@ def main():
         es = synth.make_system(config, grid_device=args.grid_device)
         re = run_workload(pkg, torch, es, 1, 1, tune=len(es.ligands) > 1,
                           waves=args.waves)
-        return {"value": re["value"], "unit": "atom-evals/s",
-                "ms_per_step": re["ms_per_step"], "steps": 1, "warmup": 1,
-                "config": describe(es, re),
-                "roofline": roofline(re, es.name),
-                "autotune": re["tuned"], "waves": re["waves"],
-                "result": re["result"]}
+        leg = {"value": re["value"], "unit": "atom-evals/s",
+               "ms_per_step": re["ms_per_step"], "steps": 1, "warmup": 1,
+               "config": describe(es, re),
+               "roofline": roofline(re, es.name),
+               "autotune": re["tuned"], "waves": re["waves"],
+               "result": re["result"]}
+        if not args.no_cpu_baseline:
+            # the oracle on a bounded sample of this workload too (half the
+            # headline's CPU time)
+            leg["cpu_baseline"] = cpu_baseline(es, args.cpu_seconds / 2)
+        return leg
 
     if args.production and args.config != 2:
         out["production_single_ligand"] = extra(2)
