@@ -107,6 +107,9 @@ def parse():
                    help="override sweeps per step (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=16.0)
+    p.add_argument("--metrics", default=None, metavar="PATH",
+                   help="append the main workload's per-ligand counters and "
+                        "throughput to this JSON-lines file")
     p.add_argument("--no-batched", dest="batched", action="store_false",
                    help="skip the batched 256-ligand leg")
     p.add_argument("--no-production", dest="production",
@@ -270,14 +273,16 @@ def train_proposals(pkg, torch, system, sweeps=31250, burn=400, every=5,
 
 def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
                  tune=False, waves=None, proposals=None, pose_every=5,
-                 kernel_sweeps=512):
+                 kernel_sweeps=512, metrics_path=None):
     """Set up every ligand of `system`, run `warmup` + `steps` timed steps
     of the hot path and return the measurements.  proposals: per-ligand
     network parameters; the sweeps then carry a learned pose move of every
     replica every `pose_every` sweeps.  After the timed steps,
     `kernel_sweeps` plain sweeps (graph replays of 64 sweeps, each replay
     bracketed by HIP events on the library's stream) give the sweep
-    kernel's own mean launch time for the roofline."""
+    kernel's own mean launch time for the roofline.  metrics_path: append
+    each ligand's counters (acceptances, round trips, non-finite moves) and
+    the run's throughput to this JSON-lines file."""
     import numpy as np
     g = system.grid
     ligs = system.ligands
@@ -363,6 +368,10 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
     hmc_ms, hmc_n = ctx.get_timing(ctx.TIMER_HMC)
     ctx.set_timing(False)
     waves = sorted({ctx.get_waves(i) for i in ids})
+    lig_metrics = None
+    if metrics_path:
+        from paper_1507_03703_amd import metrics as M
+        lig_metrics = [M.ligand_metrics(ctx, i) for i in ids]
     ctx.close()
 
     ms_per_step = el / steps * 1e3
@@ -387,6 +396,11 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
            "exchange_acceptance": float(exa)}
     if pose:
         res.update(pose)
+    if lig_metrics is not None:
+        M.MetricsLog(metrics_path).write(
+            lig_metrics, workload=system.name, atom_evals_per_s=value,
+            ms_per_step=ms_per_step, sweep_kernel_ms=hmc_ms,
+            effective_gbs=achieved)
     return dict(value=value, ms_per_step=ms_per_step, sweeps=sweeps,
                 records=records, hmc_ms=hmc_ms, hmc_n=hmc_n,
                 unit_ms=unit_ms, unit_n=unit_n, cmp_ms=cmp_ms,
@@ -1133,7 +1147,8 @@ def main():
         progress("proposals trained")
     r = run_workload(pkg, torch, system, args.steps, args.warmup,
                      sweeps=args.sweeps, tune=len(system.ligands) > 1,
-                     waves=args.waves, proposals=proposals)
+                     waves=args.waves, proposals=proposals,
+                     metrics_path=args.metrics)
     progress(f"{system.name}: {args.steps} timed steps")
     out = {
         "metric": "atom-grid energy+force evals/s & HBM fraction; effective "

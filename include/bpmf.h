@@ -372,8 +372,9 @@ BPMF_API int bpmf_get_replicas(bpmf_ctx* ctx, int ligand_id, float* x,
 
 /* Restore replica state (inverse of bpmf_get_replicas).  state_of_replica
  * must be a permutation of 0..K-1.  comps may be NULL: then they are
- * recomputed from x.  Clears nothing else (statistics and recorded samples
- * are kept; see bpmf_reset_samples). */
+ * recomputed from x.  Clears nothing else (statistics, the round-trip count
+ * and recorded samples are kept; see bpmf_reset_samples); round-trip
+ * tracking restarts from the given states. */
 BPMF_API int bpmf_set_replicas(bpmf_ctx* ctx, int ligand_id, const float* x,
                       const int* state_of_replica, const double* comps,
                       uint64_t counter);
@@ -384,6 +385,17 @@ BPMF_API int bpmf_set_replicas(bpmf_ctx* ctx, int ligand_id, const float* x,
 BPMF_API int bpmf_get_stats(bpmf_ctx* ctx, int ligand_id, int64_t* hmc_acc,
                    int64_t* hmc_try, int64_t* ex_acc, int64_t* ex_try,
                    int64_t* nonfinite);
+
+/* Replica round trips since setup (Sampling: the replica-exchange walk
+ * between the end states), *trips (host): the number of times a replica
+ * that visited state K-1 since it was last in state 0 returned to state 0.
+ * A replica starts on its way up only from state 0 (replica 0 at setup, or
+ * the replica bpmf_set_replicas places there).  States are observed after
+ * every exchange: with the all-separations scheme after the exchange
+ * sweeps of each sweep, not after each of them.  0 for a single state.
+ * Errors: BPMF_E_INVAL (null trips, bad ligand). */
+BPMF_API int bpmf_get_round_trips(bpmf_ctx* ctx, int ligand_id,
+                                  int64_t* trips);
 
 /* Recorded samples: *n_records rounds so far; x (records x K x n_atoms x 3
  * floats) and comps (records x K x (1 + n_channels) doubles), round-major,

@@ -157,6 +157,7 @@ def library():
         "bpmf_set_waves": [vp, C.c_int],
         "bpmf_set_graph": [vp, C.c_int],
         "bpmf_autotune": [vp, C.c_int, C.c_int, dp, ip],
+        "bpmf_get_round_trips": [vp, C.c_int, C.POINTER(C.c_int64)],
         "bpmf_proposal_setup": [vp, C.c_int, ip, C.c_int, ip,
                                 C.POINTER(C.c_float)],
         "bpmf_proposal_params": [vp, C.c_int, C.POINTER(C.c_float),
@@ -631,6 +632,13 @@ class Context:
                                         p(ea), p(et), C.byref(nf)))
         return dict(hmc_acc=ha, hmc_try=ht, ex_acc=ea[:K - 1],
                     ex_try=et[:K - 1], nonfinite=nf.value)
+
+    def get_round_trips(self, ligand_id):
+        """Replica round trips 0 -> K-1 -> 0 since setup."""
+        out = C.c_int64(0)
+        _check(self._lib.bpmf_get_round_trips(self._h, int(ligand_id),
+                                              C.byref(out)))
+        return out.value
 
     def get_samples(self, ligand_id):
         L = self.ligands[ligand_id]

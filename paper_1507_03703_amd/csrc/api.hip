@@ -760,6 +760,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_fcache = A.add((size_t)2 * K * n * (3 + 3 * C) * 4),
                o_frc = A.add((size_t)2 * K * 4 * 4), o_fvalid = A.add(K * 4),
                o_xacc = A.add(K * 8), o_xtry = A.add(K * 8),
+               o_rtend = A.add(K * 4),
                o_sx = A.add((size_t)cap * K * n * 12),
                o_sc = A.add((size_t)cap * K * C1 * 8);
   {
@@ -807,6 +808,10 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   chain(hipMemsetAsync(base + o_eacc, 0, Km1 * 8, c->stream));
   chain(hipMemsetAsync(base + o_etry, 0, Km1 * 8, c->stream));
   chain(hipMemsetAsync(base + o_rcnt, 0, o_sx - o_rcnt, c->stream));
+  // round trips: replica r starts in state r
+  std::vector<int> rte(K);
+  for (int r = 0; r < K; ++r) rte[r] = r == 0 ? 0 : -1;
+  chain(up(o_rtend, rte.data(), K * 4));
   chain(hipStreamSynchronize(c->stream));
   if (e != hipSuccess) {
     c->dfree(base);
@@ -849,6 +854,8 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.counter = (unsigned long long*)(base + o_counters);
   L.n_rec = L.counter + 1;
   L.nonfinite = L.counter + 2;
+  L.round_trips = L.counter + 3;
+  L.rt_end = (int*)(base + o_rtend);
   L.rcnt = (unsigned long long*)(base + o_rcnt);
   L.rnrec = (unsigned long long*)(base + o_rnrec);
   L.rpend = (int*)(base + o_rpend);
@@ -1849,6 +1856,11 @@ extern "C" int bpmf_set_replicas(bpmf_ctx* c, int ligand_id, const float* x,
                          hipMemcpyHostToDevice, c->stream));
   unsigned long long cnt = counter;
   HIP_TRY(hipMemcpyAsync(L.counter, &cnt, 8, hipMemcpyHostToDevice, c->stream));
+  // round-trip tracking restarts from the given states (the count is kept)
+  std::vector<int> rte(L.K);
+  for (int r = 0; r < L.K; ++r) rte[r] = sor[r] == 0 ? 0 : -1;
+  HIP_TRY(hipMemcpyAsync(L.rt_end, rte.data(), L.K * 4, hipMemcpyHostToDevice,
+                         c->stream));
   // new positions: no reusable start-of-trajectory forces
   HIP_TRY(hipMemsetAsync(L.fvalid, 0, (size_t)L.K * 4, c->stream));
   if (comps)
@@ -2116,6 +2128,20 @@ hipStream_t ctx_stream(bpmf_ctx* c) { return c->stream; }
 uint64_t ctx_seed(bpmf_ctx* c) { return c->seed; }
 int ctx_fail(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace bpmf
+
+extern "C" int bpmf_get_round_trips(bpmf_ctx* c, int ligand_id,
+                                    int64_t* trips) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  if (!trips) return fail(BPMF_E_INVAL, "null trips");
+  unsigned long long v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, c->ligs[ligand_id].dev.round_trips, 8,
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *trips = (int64_t)v;
+  return BPMF_OK;
+}
 
 extern "C" int bpmf_get_stats(bpmf_ctx* c, int ligand_id, int64_t* hmc_acc,
                               int64_t* hmc_try, int64_t* ex_acc,

@@ -98,6 +98,22 @@ __device__ int deferred_state(const LigDev& L, int a, unsigned long long s,
 }
 #pragma clang fp contract(fast)
 
+// Round trips (Sampling: the replica-exchange walk between the end
+// states): replica r has just entered state k.  A trip counts when a
+// replica that has visited state K-1 since it was last in state 0 returns
+// to state 0.  Only the replica's own thread writes its rt_end; entering
+// the same state again changes nothing.
+__device__ __forceinline__ void note_state(const LigDev& L, int r, int k) {
+  if (L.K < 2) return;
+  int* e = L.rt_end + r;
+  if (k == 0) {
+    if (*e == 1) atomicAdd(L.round_trips, 1ull);
+    *e = 0;
+  } else if (k == L.K - 1 && *e == 0) {
+    *e = 1;
+  }
+}
+
 // the exchange ending sweep s - 1 records a round when s % every == 0
 __device__ __forceinline__ bool record_due(unsigned long long s, int every) {
   return every > 0 && s > 0ull && s % (unsigned long long)every == 0ull;
@@ -142,6 +158,7 @@ __device__ __forceinline__ void finish_ligand(const LigDev& L,
     const int a = L.rsor[pin * K + r];
     const int k =
         pend ? deferred_state(L, a, s, pin, exchange_every, seed, true) : a;
+    if (k != a) note_state(L, r, k);
     L.state_of_replica[r] = k;
     L.replica_of_state[k] = r;
     for (int e = 0; e < C1; ++e)

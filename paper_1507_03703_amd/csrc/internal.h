@@ -129,6 +129,9 @@ struct LigDev {
   unsigned long long* ex_acc;     // max(K-1,1)
   unsigned long long* ex_try;     // max(K-1,1)
   unsigned long long* nonfinite;  // 1
+  unsigned long long* round_trips;  // 1: replicas' trips 0 -> K-1 -> 0
+  int* rt_end;  // K: per replica, the extreme state it last visited on its
+                // way (0 = state 0, 1 = state K-1, -1 = neither yet)
   unsigned long long* ext_acc;    // K: external moves accepted per state
   unsigned long long* ext_try;    // K: external moves tried per state
   // Neighbour-scheme sweeps apply the exchange (and record) that ends sweep

@@ -325,6 +325,10 @@ __device__ void exchange_block(const LigDev& L, uint64_t sweep, int scheme,
         for (int a = 0; a + d < K; ++a)
           attempt_pair(L, a, a + d, d, sweep, j, seed);
   }
+  // every replica's state after the exchange (round-trip bookkeeping)
+  __syncthreads();
+  for (int r = threadIdx.x; r < K; r += blockDim.x)
+    note_state(L, r, L.state_of_replica[r]);
 }
 
 // Tail of one ligand's sweep, run by one whole block: exchange (if due),
@@ -515,6 +519,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   __syncthreads();  // the staged topology and the decision
   const bool swap = pr.active && s_swap != 0;
   const int k = swap ? kb : a;
+  if (swap && tid == 0) note_state(L, r, k);
   float w[C];
   double wdk[C];
 #pragma unroll
