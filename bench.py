@@ -57,19 +57,19 @@ GRID_BYTES_PER_EVAL = 96  # 8 corners x 3 channels x 4 B
 # kernel and workload: one sweep launch (at the given wavefronts per
 # replica), one harness launch, one energy-matrix call (its launches
 # summed); valid only while the kernel sources hash to TRAFFIC_SOURCES
-TRAFFIC_SOURCES = "72a9d599c9c2eb71"
+TRAFFIC_SOURCES = "414f6810e6469c16"
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     ("k_hmc_sweep", "c5_large_batched"):
-        {"waves": 4, "fetch_kib": 9067.416, "write_kib": 4431.2},
+        {"waves": 4, "fetch_kib": 9071.729, "write_kib": 4431.636},
     ("k_hmc_sweep", "c2_plain_production"):
-        {"waves": None, "fetch_kib": 761.121, "write_kib": 198.215},
+        {"waves": None, "fetch_kib": 756.048, "write_kib": 198.227},
     ("k_hmc_sweep", "c3_batched_uneven"):
-        {"waves": 2, "fetch_kib": 37142.211, "write_kib": 23627.091},
+        {"waves": 2, "fetch_kib": 37144.342, "write_kib": 23628.212},
     ("k_grid_eval", "c3_batched_uneven"):
-        {"waves": None, "fetch_kib": 3379806.094, "write_kib": 3383700.0},
+        {"waves": None, "fetch_kib": 3380055.281, "write_kib": 3383700.0},
     ("k_energy_matrix", "c3_batched_uneven"):
-        {"waves": None, "fetch_kib": 1170698.093, "write_kib": 525099.617},
+        {"waves": None, "fetch_kib": 1170332.484, "write_kib": 522746.133},
 }
 KERNEL_SOURCES = ("device.h", "kernels.hip", "internal.h")
 
