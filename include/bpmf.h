@@ -787,12 +787,24 @@ BPMF_API int bpmf_set_graph(bpmf_ctx* ctx, int chunk);
  * bpmf_set_waves) -- on the ligands set up, with HIP events (eager launches
  * below the graph chunk, graph replays from it on); keep the fastest and
  * report it in *chosen (0 = automatic).  ms_out (host, 5 doubles, may be
- * NULL) receives the mean sweep time of each candidate in that order.  The
- * sampler state (positions, state maps, components, counters, statistics)
- * is snapshotted on the device before the trials and restored after, so
- * tuning does not change the run. */
+ * NULL) receives the mean sweep time of each candidate in that order.
+ * Then, one atom-count class at a time (up to 16, 32, 48, 64, 96 and 128
+ * atoms, largest first), the other wavefront counts are tried for that
+ * class's ligands alone and kept (as per-ligand choices, see
+ * bpmf_set_ligand_waves) where they save more than 2 % of the sweep; the
+ * classes' launches run side by side.  bpmf_get_waves reports each
+ * ligand's result.  The sampler state (positions, state maps, components,
+ * counters, statistics) is snapshotted on the device before the trials and
+ * restored after, so tuning does not change the run.  Per-ligand choices
+ * made before the call are replaced. */
 BPMF_API int bpmf_autotune(bpmf_ctx* ctx, int n_sweeps, int n_leapfrog,
                            double* ms_out, int* chosen);
+
+/* A ligand's own wavefronts per replica (1, 2, 4 or 8, raised to the
+ * minimum its atom count needs; 0 = none: the bpmf_set_waves choice
+ * applies).  Results depend on it only through the rounding of the
+ * per-wavefront energy partial sums.  Errors: BPMF_E_INVAL. */
+BPMF_API int bpmf_set_ligand_waves(bpmf_ctx* ctx, int ligand_id, int waves);
 
 /* Wavefronts per replica the sweep currently uses for a ligand. */
 BPMF_API int bpmf_get_waves(bpmf_ctx* ctx, int ligand_id, int* waves);

@@ -158,6 +158,7 @@ def library():
         "bpmf_set_graph": [vp, C.c_int],
         "bpmf_autotune": [vp, C.c_int, C.c_int, dp, ip],
         "bpmf_get_round_trips": [vp, C.c_int, C.POINTER(C.c_int64)],
+        "bpmf_set_ligand_waves": [vp, C.c_int, C.c_int],
         "bpmf_proposal_setup": [vp, C.c_int, ip, C.c_int, ip,
                                 C.POINTER(C.c_float)],
         "bpmf_proposal_params": [vp, C.c_int, C.POINTER(C.c_float),
@@ -744,21 +745,27 @@ class Context:
     def autotune(self, n_sweeps=20, n_leapfrog=10, cache_path=None,
                  signature=None):
         """Pick the wavefronts per replica of the HMC sweep by timing every
-        candidate on the ligands set up (state restored afterwards).  With
-        cache_path, the choice is stored in / reused from a JSON file keyed
-        by GPU architecture and `signature` (a string describing the
-        workload).  Returns (chosen, {candidate: ms})."""
+        candidate on the ligands set up, then refine them per atom-count
+        class (state restored afterwards).  With cache_path, the choice (the
+        context-wide one and every ligand's) is stored in / reused from a
+        JSON file keyed by GPU architecture and `signature` (a string
+        describing the workload).  Returns (chosen, {candidate: ms}) for
+        the context-wide candidates."""
         import json
         import os
         arch = self._torch.cuda.get_device_properties(
             self.device).gcnArchName
         key = f"{arch}|{signature}"
+        ids = range(len(self.ligands))
         if cache_path and signature and os.path.exists(cache_path):
             with open(cache_path) as fh:
                 cache = json.load(fh)
-            if key in cache:
-                self.set_waves(cache[key]["chosen"])
-                return cache[key]["chosen"], cache[key]["ms"]
+            hit = cache.get(key)
+            if hit and len(hit.get("waves", [])) == len(ids):
+                self.set_waves(hit["chosen"])
+                for i, w in zip(ids, hit["waves"]):
+                    self.set_ligand_waves(i, w)
+                return hit["chosen"], hit["ms"]
         ms = np.zeros(5)
         ch = C.c_int(0)
         _check(self._lib.bpmf_autotune(self._h, int(n_sweeps),
@@ -769,7 +776,8 @@ class Context:
             if os.path.exists(cache_path):
                 with open(cache_path) as fh:
                     cache = json.load(fh)
-            cache[key] = {"chosen": ch.value, "ms": table}
+            cache[key] = {"chosen": ch.value, "ms": table,
+                          "waves": [self.get_waves(i) for i in ids]}
             with open(cache_path, "w") as fh:
                 json.dump(cache, fh, indent=1)
         return ch.value, table
@@ -781,6 +789,12 @@ class Context:
     def set_waves(self, waves):
         """Wavefronts per replica (1, 2, 4; 0 = automatic)."""
         _check(self._lib.bpmf_set_waves(self._h, int(waves)))
+
+    def set_ligand_waves(self, ligand_id, waves):
+        """A ligand's own wavefronts per replica (0 = the context-wide
+        choice)."""
+        _check(self._lib.bpmf_set_ligand_waves(self._h, int(ligand_id),
+                                               int(waves)))
 
     def get_waves(self, ligand_id):
         out = C.c_int(0)

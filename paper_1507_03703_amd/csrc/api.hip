@@ -50,7 +50,7 @@ struct Arena {
   std::vector<size_t> offsets;
   size_t total = 0;
   size_t add(size_t bytes) {
-    total = align_up(total, 256);
+    total = align_up(total, kArenaAlign);
     const size_t o = total;
     offsets.push_back(o);
     total += bytes > 0 ? bytes : 1;
@@ -64,6 +64,8 @@ struct LigHost {
   size_t state_bytes;  // arena prefix holding everything but the samples
   int min_waves;   // wavefronts needed to give every atom a thread
   int sweep_waves; // wavefronts per replica in the HMC sweep
+  int waves_pin = 0;  // the ligand's own choice (bpmf_set_ligand_waves), 0 =
+                      // none: the context-wide one applies
   uint64_t counter;   // host mirror of *dev.counter
   int64_t n_rec;      // host mirror of *dev.n_rec
   std::vector<double> beta, wd;
@@ -156,6 +158,10 @@ struct bpmf_ctx {
   // `stream`)
   int graph_chunk = 64;  // 0 disables
   hipStream_t cap_stream = nullptr;
+  // the sweep's wavefront classes after the first run on streams of their
+  // own, forked from and joined to the launching stream (default priority)
+  hipStream_t class_stream[kWaveClasses] = {};
+  hipEvent_t class_fork = nullptr, class_join[kWaveClasses] = {};
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   uint64_t table_version = 0, graph_version = ~0ull;
@@ -244,6 +250,7 @@ int lds_of(const LigHost& h, int waves, bool forces) {
 // few replicas are in flight (latency-bound) spread each over up to four
 // wavefronts so that the bonded terms of a step run in parallel
 int choose_waves(const bpmf_ctx* c, const LigHost& h, int total_replicas) {
+  if (h.waves_pin) return std::max(h.waves_pin, h.min_waves);
   int w = c->waves_override ? c->waves_override : 1;
   if (!c->waves_override) {
     // enough waves to give every slot of the wave-aligned bonded index its
@@ -414,6 +421,11 @@ extern "C" int bpmf_destroy(bpmf_ctx* c) {
     for (hipEvent_t e : c->ev_pool[k]) (void)hipEventDestroy(e);
   c->drop_graph();
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+    if (c->class_stream[q]) (void)hipStreamDestroy(c->class_stream[q]);
+    if (c->class_join[q]) (void)hipEventDestroy(c->class_join[q]);
+  }
+  if (c->class_fork) (void)hipEventDestroy(c->class_fork);
   delete c;
   return BPMF_OK;
 }
@@ -759,8 +771,9 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
                o_scomp = A.add((size_t)2 * K * C1 * 8),
                o_fcache = A.add((size_t)2 * K * n * (3 + 3 * C) * 4),
                o_frc = A.add((size_t)2 * K * 4 * 4), o_fvalid = A.add(K * 4),
+               // right after fvalid: the kernels find it from that pointer
+               o_rtend = A.add(rt_region_bytes(K)),
                o_xacc = A.add(K * 8), o_xtry = A.add(K * 8),
-               o_rtend = A.add(K * 4),
                o_sx = A.add((size_t)cap * K * n * 12),
                o_sc = A.add((size_t)cap * K * C1 * 8);
   {
@@ -809,9 +822,9 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   chain(hipMemsetAsync(base + o_etry, 0, Km1 * 8, c->stream));
   chain(hipMemsetAsync(base + o_rcnt, 0, o_sx - o_rcnt, c->stream));
   // round trips: replica r starts in state r
-  std::vector<int> rte(K);
+  std::vector<int> rte(rt_region_bytes(K) / 4, 0);  // trip count 0
   for (int r = 0; r < K; ++r) rte[r] = r == 0 ? 0 : -1;
-  chain(up(o_rtend, rte.data(), K * 4));
+  chain(up(o_rtend, rte.data(), rt_region_bytes(K)));
   chain(hipStreamSynchronize(c->stream));
   if (e != hipSuccess) {
     c->dfree(base);
@@ -854,8 +867,7 @@ extern "C" int bpmf_ligand_setup(bpmf_ctx* c, const bpmf_ligand_desc* d,
   L.counter = (unsigned long long*)(base + o_counters);
   L.n_rec = L.counter + 1;
   L.nonfinite = L.counter + 2;
-  L.round_trips = L.counter + 3;
-  L.rt_end = (int*)(base + o_rtend);
+
   L.rcnt = (unsigned long long*)(base + o_rcnt);
   L.rnrec = (unsigned long long*)(base + o_rnrec);
   L.rpend = (int*)(base + o_rpend);
@@ -985,14 +997,48 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
                                a->n_leapfrog, c->seed, tail, &h.dev,
                                h.dev.pairs_on != 0, st));
     } else {
+      // classes hold different ligands: the first runs on `st`, each other
+      // one on a stream of its own forked from `st` and joined back after
+      // it, so that the launches overlap (in a captured graph: parallel
+      // branches)
+      int nq = 0;
+      for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) nq += c->class_n[q] > 0;
+      if (nq > 1) {
+        if (!c->class_fork)
+          HIP_TRY(hipEventCreateWithFlags(&c->class_fork,
+                                          hipEventDisableTiming));
+        for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+          if (!c->class_n[q]) continue;
+          if (!c->class_stream[q])
+            HIP_TRY(hipStreamCreateWithFlags(&c->class_stream[q],
+                                             hipStreamNonBlocking));
+          if (!c->class_join[q])
+            HIP_TRY(hipEventCreateWithFlags(&c->class_join[q],
+                                            hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(c->class_fork, st));
+      }
+      bool forked[bpmf_ctx::kWaveClasses] = {false, false, false, false};
+      bool first = true;
+      for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+        if (!c->class_n[q]) continue;
+        hipStream_t sq = st;
+        if (!first) {
+          sq = c->class_stream[q];
+          HIP_TRY(hipStreamWaitEvent(sq, c->class_fork, 0));
+          forked[q] = true;
+        }
+        first = false;
+        HIP_TRY(launch_hmc_sweep(
+            c->grid, c->d_ligs, c->d_tasks + c->class_off[q], c->class_n[q],
+            1 << q, c->class_lds[q], a->n_leapfrog, c->seed, tail,
+            c->class_single[q] >= 0 ? &c->ligs[c->class_single[q]].dev
+                                    : nullptr,
+            c->class_pairs[q], sq));
+        if (forked[q]) HIP_TRY(hipEventRecord(c->class_join[q], sq));
+      }
       for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
-        if (c->class_n[q])
-          HIP_TRY(launch_hmc_sweep(
-              c->grid, c->d_ligs, c->d_tasks + c->class_off[q], c->class_n[q],
-              1 << q, c->class_lds[q], a->n_leapfrog, c->seed, tail,
-              c->class_single[q] >= 0 ? &c->ligs[c->class_single[q]].dev
-                                      : nullptr,
-              c->class_pairs[q], st));
+        if (forked[q]) HIP_TRY(hipStreamWaitEvent(st, c->class_join[q], 0));
     }
     if (tail.scheme == 1)
       HIP_TRY(launch_sweep_tail(dl, nl, tail.exchange_every, tail.scheme,
@@ -1859,8 +1905,8 @@ extern "C" int bpmf_set_replicas(bpmf_ctx* c, int ligand_id, const float* x,
   // round-trip tracking restarts from the given states (the count is kept)
   std::vector<int> rte(L.K);
   for (int r = 0; r < L.K; ++r) rte[r] = sor[r] == 0 ? 0 : -1;
-  HIP_TRY(hipMemcpyAsync(L.rt_end, rte.data(), L.K * 4, hipMemcpyHostToDevice,
-                         c->stream));
+  HIP_TRY(hipMemcpyAsync(rt_end_of(L), rte.data(), L.K * 4,
+                         hipMemcpyHostToDevice, c->stream));
   // new positions: no reusable start-of-trajectory forces
   HIP_TRY(hipMemsetAsync(L.fvalid, 0, (size_t)L.K * 4, c->stream));
   if (comps)
@@ -2136,7 +2182,7 @@ extern "C" int bpmf_get_round_trips(bpmf_ctx* c, int ligand_id,
   if ((rc = check_lig(c, ligand_id))) return rc;
   if (!trips) return fail(BPMF_E_INVAL, "null trips");
   unsigned long long v = 0;
-  HIP_TRY(hipMemcpyAsync(&v, c->ligs[ligand_id].dev.round_trips, 8,
+  HIP_TRY(hipMemcpyAsync(&v, round_trips_of(c->ligs[ligand_id].dev), 8,
                          hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   *trips = (int64_t)v;
@@ -2257,6 +2303,16 @@ extern "C" int bpmf_set_waves(bpmf_ctx* c, int waves) {
   if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
     return fail(BPMF_E_INVAL, "waves must be 0 (automatic), 1, 2, 4 or 8");
   c->waves_override = waves;
+  return rebuild_tables(c);
+}
+
+extern "C" int bpmf_set_ligand_waves(bpmf_ctx* c, int ligand_id, int waves) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_lig(c, ligand_id))) return rc;
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(BPMF_E_INVAL, "waves must be 0 (none), 1, 2, 4 or 8");
+  c->ligs[ligand_id].waves_pin = waves;
   return rebuild_tables(c);
 }
 
@@ -2801,8 +2857,26 @@ extern "C" int bpmf_autotune(bpmf_ctx* c, int n_sweeps, int n_leapfrog,
     return BPMF_OK;
   };
   const int old_override = c->waves_override;
+  std::vector<int> old_pins;
+  for (auto& h : c->ligs) old_pins.push_back(h.waves_pin);
   const bool old_timing = c->timing;
   const int old_every = c->timing_every;
+  // mean sweep time of the current launch shape, the state restored after
+  auto trial = [&](double* ms) -> int {
+    int r;
+    if ((r = rebuild_tables(c))) return r;
+    bpmf_sweep_args a{2, n_leapfrog, 1, 0, 1, 0, 0};
+    if ((r = bpmf_hmc_sweep(c, &a))) return r;
+    c->timing = true;
+    c->timing_every = 1;
+    c->launches[BPMF_TIMER_HMC] = 0;
+    c->ev_used[BPMF_TIMER_HMC] = 0;
+    a.n_sweeps = n_sweeps;
+    if ((r = bpmf_hmc_sweep(c, &a))) return r;
+    int64_t cnt = 0;
+    if ((r = bpmf_get_timing(c, BPMF_TIMER_HMC, ms, &cnt))) return r;
+    return copy_all(false);
+  };
   const int cand[5] = {0, 1, 2, 4, 8};
   double best = INFINITY;
   int best_w = 0;
@@ -2810,28 +2884,44 @@ extern "C" int bpmf_autotune(bpmf_ctx* c, int n_sweeps, int n_leapfrog,
     c->dfree(snap);
     return rc;
   }
-  for (int q = 0; q < 5; ++q) {
+  for (auto& h : c->ligs) h.waves_pin = 0;
+  for (int q = 0; q < 5 && !rc; ++q) {
     double ms = INFINITY;
-    {
-      c->waves_override = cand[q];
-      if ((rc = rebuild_tables(c))) break;
-      bpmf_sweep_args a{2, n_leapfrog, 1, 0, 1, 0, 0};
-      if ((rc = bpmf_hmc_sweep(c, &a))) break;
-      c->timing = true;
-      c->timing_every = 1;
-      c->launches[BPMF_TIMER_HMC] = 0;
-      c->ev_used[BPMF_TIMER_HMC] = 0;
-      a.n_sweeps = n_sweeps;
-      if ((rc = bpmf_hmc_sweep(c, &a))) break;
-      int64_t cnt = 0;
-      if ((rc = bpmf_get_timing(c, BPMF_TIMER_HMC, &ms, &cnt))) break;
-      if ((rc = copy_all(false))) break;
-      if (ms < best) {
-        best = ms;
-        best_w = cand[q];
-      }
+    c->waves_override = cand[q];
+    if ((rc = trial(&ms))) break;
+    if (ms < best) {
+      best = ms;
+      best_w = cand[q];
     }
     if (ms_out) ms_out[q] = ms;
+  }
+  // refinement: per atom-count class (up to 16, 32, 48, 64, 96, 128 atoms),
+  // one class at a time, the other wavefront counts with the rest kept;
+  // a change stays when it saves more than 2 % (the classes' launches run
+  // side by side, so mixed shapes cost no serialisation)
+  c->waves_override = best_w;
+  auto size_class = [](int n) {
+    return n <= 16 ? 0 : n <= 32 ? 1 : n <= 48 ? 2 : n <= 64 ? 3
+           : n <= 96 ? 4 : 5;
+  };
+  bool present[6] = {false, false, false, false, false, false};
+  for (auto& h : c->ligs) present[size_class(h.dev.n)] = true;
+  for (int sc = 5; sc >= 0 && !rc; --sc) {
+    if (!present[sc]) continue;
+    int keep = 0;  // the class's pin so far (0: the context-wide choice)
+    for (int w : {1, 2, 4, 8}) {
+      if (w == (best_w ? best_w : -1)) continue;
+      for (auto& h : c->ligs)
+        if (size_class(h.dev.n) == sc) h.waves_pin = w;
+      double ms = INFINITY;
+      if ((rc = trial(&ms))) break;
+      if (ms < 0.98 * best) {
+        best = ms;
+        keep = w;
+      }
+    }
+    for (auto& h : c->ligs)
+      if (size_class(h.dev.n) == sc) h.waves_pin = keep;
   }
   c->timing = old_timing;
   c->timing_every = old_every;
@@ -2840,10 +2930,11 @@ extern "C" int bpmf_autotune(bpmf_ctx* c, int n_sweeps, int n_leapfrog,
   c->dfree(snap);
   if (rc) {
     c->waves_override = old_override;
+    for (size_t l = 0; l < c->ligs.size(); ++l)
+      c->ligs[l].waves_pin = old_pins[l];
     (void)rebuild_tables(c);
     return rc;
   }
-  c->waves_override = best_w;
   if ((rc = rebuild_tables(c))) return rc;
   if (chosen) *chosen = best_w;
   return BPMF_OK;

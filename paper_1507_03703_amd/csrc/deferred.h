@@ -103,16 +103,29 @@ __device__ int deferred_state(const LigDev& L, int a, unsigned long long s,
 // replica that has visited state K-1 since it was last in state 0 returns
 // to state 0.  Only the replica's own thread writes its rt_end; entering
 // the same state again changes nothing.
-__device__ __forceinline__ void note_state(const LigDev& L, int r, int k) {
-  if (L.K < 2) return;
-  int* e = L.rt_end + r;
+// The mark after entering state k with mark e (a trip completes: counted).
+__device__ __forceinline__ int rt_step(const LigDev& L, int e, int k) {
+  if (L.K < 2) return e;
   if (k == 0) {
-    if (*e == 1) atomicAdd(L.round_trips, 1ull);
-    *e = 0;
-  } else if (k == L.K - 1 && *e == 0) {
-    *e = 1;
+    if (e == 1) atomicAdd(round_trips_of(L), 1ull);
+    return 0;
   }
+  return (k == L.K - 1 && e == 0) ? 1 : e;
 }
+// the same on the canonical marks
+__device__ __forceinline__ void note_state(const LigDev& L, int r, int k) {
+  int* e = rt_end_of(L) + r;
+  const int e0 = *e, e1 = rt_step(L, e0, k);
+  if (e1 != e0) *e = e1;
+}
+
+// During a run of neighbour-scheme sweeps the state map's buffers also
+// carry each replica's mark: entry = state | (mark + 1) << 16.
+__device__ __forceinline__ int rsor_pack(int k, int e) {
+  return k | ((e + 1) << 16);
+}
+__device__ __forceinline__ int rsor_state(int v) { return v & 0xffff; }
+__device__ __forceinline__ int rsor_mark(int v) { return (v >> 16) - 1; }
 
 // the exchange ending sweep s - 1 records a round when s % every == 0
 __device__ __forceinline__ bool record_due(unsigned long long s, int every) {
@@ -127,7 +140,7 @@ __device__ __forceinline__ void begin_replica(const LigDev& L, int r, int k,
                                               unsigned long long nrec,
                                               const double* comps_r) {
   const int pin = (int)((s - 1ull) & 1ull), K = L.K, C1 = 1 + L.C;
-  L.rsor[pin * K + r] = k;
+  L.rsor[pin * K + r] = rsor_pack(k, rt_end_of(L)[r]);
   L.rpend[pin * K + r] = 0;
   L.rcnt[r] = s;
   L.rnrec[r] = nrec;
@@ -155,10 +168,11 @@ __device__ __forceinline__ void finish_ligand(const LigDev& L,
   const int pin = (int)((s - 1ull) & 1ull), K = L.K, C1 = 1 + L.C;
   const bool pend = L.rpend[pin * K] != 0;
   for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    const int a = L.rsor[pin * K + r];
+    const int v = L.rsor[pin * K + r];
+    const int a = rsor_state(v), e = rsor_mark(v);
     const int k =
         pend ? deferred_state(L, a, s, pin, exchange_every, seed, true) : a;
-    if (k != a) note_state(L, r, k);
+    rt_end_of(L)[r] = k != a ? rt_step(L, e, k) : e;
     L.state_of_replica[r] = k;
     L.replica_of_state[k] = r;
     for (int e = 0; e < C1; ++e)

@@ -129,9 +129,6 @@ struct LigDev {
   unsigned long long* ex_acc;     // max(K-1,1)
   unsigned long long* ex_try;     // max(K-1,1)
   unsigned long long* nonfinite;  // 1
-  unsigned long long* round_trips;  // 1: replicas' trips 0 -> K-1 -> 0
-  int* rt_end;  // K: per replica, the extreme state it last visited on its
-                // way (0 = state 0, 1 = state K-1, -1 = neither yet)
   unsigned long long* ext_acc;    // K: external moves accepted per state
   unsigned long long* ext_try;    // K: external moves tried per state
   // Neighbour-scheme sweeps apply the exchange (and record) that ends sweep
@@ -159,6 +156,26 @@ struct LigDev {
   int pairs_on;
   PairDev pair;
 };
+
+// Every region of a ligand's device arena starts on a 256-byte boundary.
+constexpr size_t kArenaAlign = 256;
+
+// Round-trip bookkeeping (kept out of the table, whose every field the
+// sweep kernel holds in scalar registers), in the arena region right after
+// fvalid: per replica the extreme state it last visited on its way (0 =
+// state 0, 1 = state K-1, -1 = neither yet), then, 8-byte aligned, the
+// ligand's trip count.
+__host__ __device__ inline int* rt_end_of(const LigDev& L) {
+  const size_t b = ((size_t)L.K * 4 + kArenaAlign - 1) & ~(kArenaAlign - 1);
+  return (int*)((char*)L.fvalid + b);
+}
+__host__ __device__ inline unsigned long long* round_trips_of(
+    const LigDev& L) {
+  return (unsigned long long*)(rt_end_of(L) + ((L.K + 1) & ~1));
+}
+__host__ __device__ inline size_t rt_region_bytes(int K) {
+  return (size_t)((K + 1) & ~1) * 4 + 8;
+}
 
 // Launch wrappers (kernels.hip).  All return hipError_t of the launch.
 // waves = wavefronts per replica (1, 2 or 4); n_atoms <= 64 * waves

@@ -411,7 +411,7 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   // per-replica state and per-atom data: issued before the topology is
   // staged so that both latencies overlap
   unsigned long long s;
-  int a = 0, pin = 0;
+  int a = 0, pin = 0, ain = 0;
   bool pend = false;
   if (deferred) {
     s = BPMF_GMEM(const unsigned long long, L.rcnt)[r];
@@ -420,7 +420,8 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     const int a0 = rsor[r], a1 = rsor[L.K + r];
     const int p0 = rpend[r], p1 = rpend[L.K + r];
     pin = (int)((s - 1ull) & 1ull);
-    a = pin ? a1 : a0;
+    ain = pin ? a1 : a0;
+    a = rsor_state(ain);
     pend = (pin ? p1 : p0) != 0;
   } else {
     s = *BPMF_GMEM(const unsigned long long, L.counter);
@@ -498,7 +499,11 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   // the decision is the block's: the last wavefront (the one with the
   // fewest atoms) takes it and publishes it with the barrier that ends the
   // staging
+  // The replica's next state-map entry (its state after this decision and
+  // its round-trip mark) is written here: only this block reads it, in the
+  // next sweep.
   __shared__ int s_swap;
+  int* const rsor_out = L.rsor + (1 - pin) * L.K + r;
   if (pr.active && (tid >> 6) == W - 1) {
     const bool sw = pair_accepts<C>(L, pr, pin, s, seed);
     if (tid == (W - 1) * kWave) {
@@ -507,8 +512,10 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
         atomicAdd(&L.ex_try[pr.lo], 1ull);
         if (sw) atomicAdd(&L.ex_acc[pr.lo], 1ull);
       }
+      *rsor_out = sw ? rsor_pack(kb, rt_step(L, rsor_mark(ain), kb)) : ain;
     }
   }
+  if (deferred && !pr.active && tid == 0) *rsor_out = ain;
   // the momenta's standard normals do not depend on the state: drawn
   // beside the decision
   float z[3] = {0.f, 0.f, 0.f};
@@ -519,7 +526,6 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
   __syncthreads();  // the staged topology and the decision
   const bool swap = pr.active && s_swap != 0;
   const int k = swap ? kb : a;
-  if (swap && tid == 0) note_state(L, r, k);
   float w[C];
   double wdk[C];
 #pragma unroll
@@ -681,7 +687,6 @@ __global__ __launch_bounds__(W * kWave) void k_hmc_sweep(
     if (!finite) atomicAdd(L.nonfinite, 1ull);
     if (deferred) {
       const int pout = (int)(s & 1ull);
-      BPMF_GMEM(int, L.rsor)[pout * L.K + r] = k;
       BPMF_GMEM(int, L.rpend)[pout * L.K + r] = 1;
       BPMF_GMEM(unsigned long long, L.rcnt)[r] = s + 1ull;
       if (recorded) BPMF_GMEM(unsigned long long, L.rnrec)[r] = rec + 1ull;

@@ -39,16 +39,26 @@ def _uneven_ligands():
     return c1.grid, ligs
 
 
-@pytest.mark.parametrize("waves", [0, 4])
+@pytest.mark.parametrize("waves", [0, 4, "pins"])
 def test_lockstep_uneven_batch(waves):
+    """Automatic, uniform and per-ligand launch shapes; the shapes' launches
+    of one sweep run side by side."""
     g, ligs = _uneven_ligands()
     print_case("batched lockstep", [l.n_atoms for l in ligs], "waves", waves)
     ctx, ids = make_context(g, ligs, seed=41)
-    ctx.set_waves(waves)
-    used = [ctx.get_waves(i) for i in ids]
+    if waves == "pins":
+        pins = [8, 1, 2, 4, 1, 2][:len(ids)]
+        for i, w in zip(ids, pins):
+            ctx.set_ligand_waves(i, w)
+        used = [ctx.get_waves(i) for i in ids]
+        assert used == [max(w, -(-l.n_atoms // 64))
+                        for w, l in zip(pins, ligs)]
+    else:
+        ctx.set_waves(waves)
+        used = [ctx.get_waves(i) for i in ids]
     for lig, w in zip(ligs, used):
         assert w >= -(-lig.n_atoms // 64)
-    if waves == 0:
+    if waves != 4:
         assert len(set(used)) >= 2       # several launch shapes in one sweep
     n = lockstep(ctx, oracle.OGrid(g), list(zip(ids, ligs)), 41, 3, 10,
                  "uneven")
@@ -94,14 +104,23 @@ def test_autotune_leaves_state_unchanged(tmp_path):
     b, ids_b = make_context(g, ligs, seed=5, capacity=12)
     b.hmc_sweep(3, 10, exchange_every=1, sample_every=1)
     b.set_waves(chosen)
+    tuned = [a.get_waves(i) for i in ids]
+    for j, w in zip(ids_b, tuned):
+        b.set_ligand_waves(j, w)
     b.hmc_sweep(5, 10, exchange_every=1, sample_every=1)
     for i, j in zip(ids, ids_b):
         assert _same(_state(a, i), _state(b, j)) is None, i
     # the cached choice is reused without timing
     rec = json.loads(cache.read_text())
     assert len(rec) == 1 and list(rec.values())[0]["chosen"] == chosen
+    assert list(rec.values())[0]["waves"] == tuned
+    for j in ids_b:
+        b.set_ligand_waves(j, 0)
     again, table2 = b.autotune(cache_path=str(cache), signature="uneven")
     assert again == chosen and table2 == table
+    assert [b.get_waves(j) for j in ids_b] == tuned
+    with pytest.raises(RuntimeError):
+        b.set_ligand_waves(ids_b[0], 3)
     a.close()
     b.close()
 
