@@ -890,10 +890,14 @@ __global__ __launch_bounds__(kUknWaves * kWave) void k_energy_matrix_wave(
           if (own[a])
             pos[lane + kWave * a] =
                 make_float4(x[a][0], x[a][1], x[a][2], m[a]);
-        Corners<C> cn[AP];
+        // the first atom's cell records load during the torsions, the
+        // second's (AP = 2) during the angles and bonds: one record set in
+        // registers at a time
+        float psi[C];
 #pragma unroll
-        for (int a = 0; a < AP; ++a)
-          if (own[a]) grid_fetch<C>(g, x[a][0], x[a][1], x[a][2], cn[a]);
+        for (int c = 0; c < C; ++c) psi[c] = 0.f;
+        Corners<C> cn;
+        if (own[0]) grid_fetch<C>(g, x[0][0], x[0][1], x[0][2], cn);
         wave_fence();
         // bonded terms, energies only, every chunk of the ligand
         float eb = 0.f, ea = 0.f, et = 0.f;
@@ -903,28 +907,44 @@ __global__ __launch_bounds__(kUknWaves * kWave) void k_energy_matrix_wave(
             et += torsion_term<false>(pos, sh.tijkl[t], sh.tpar[t],
                                       no_forces);
         }
-        for (int ch = 0; ch < nac; ++ch) {
-          const int t = ch * kWave + lane;
-          if (t < L.na)
-            ea += angle_term<false>(pos, sh.aijk[t], sh.apar[t], no_forces);
-        }
-        for (int ch = 0; ch < nbc; ++ch) {
-          const int t = ch * kWave + lane;
-          if (t < L.nb)
-            eb += bond_term<false>(pos, sh.bij[t], sh.bpar[t], no_forces);
-        }
-        // grid terms and the centre of mass
-        float psi[C], px = 0.f, py = 0.f, pz = 0.f;
-#pragma unroll
-        for (int c = 0; c < C; ++c) psi[c] = 0.f;
 #pragma unroll
         for (int a = 0; a < AP; ++a) {
           if (own[a]) {
             float ev[C], dv[C][3];
-            grid_finish<C, false>(g, cn[a], sc[a], ev, dv);
+            grid_finish<C, false>(g, cn, sc[a], ev, dv);
 #pragma unroll
             for (int c = 0; c < C; ++c) psi[c] += ev[c];
           }
+          if (a + 1 < AP && own[a + 1])
+            grid_fetch<C>(g, x[a + 1][0], x[a + 1][1], x[a + 1][2], cn);
+          if (a + 1 < AP) {
+            for (int ch = 0; ch < nac; ++ch) {
+              const int t = ch * kWave + lane;
+              if (t < L.na)
+                ea += angle_term<false>(pos, sh.aijk[t], sh.apar[t],
+                                        no_forces);
+            }
+            for (int ch = 0; ch < nbc; ++ch) {
+              const int t = ch * kWave + lane;
+              if (t < L.nb)
+                eb += bond_term<false>(pos, sh.bij[t], sh.bpar[t], no_forces);
+            }
+          }
+        }
+        for (int ch = 0; AP == 1 && ch < nac; ++ch) {
+          const int t = ch * kWave + lane;
+          if (t < L.na)
+            ea += angle_term<false>(pos, sh.aijk[t], sh.apar[t], no_forces);
+        }
+        for (int ch = 0; AP == 1 && ch < nbc; ++ch) {
+          const int t = ch * kWave + lane;
+          if (t < L.nb)
+            eb += bond_term<false>(pos, sh.bij[t], sh.bpar[t], no_forces);
+        }
+        // the centre of mass
+        float px = 0.f, py = 0.f, pz = 0.f;
+#pragma unroll
+        for (int a = 0; a < AP; ++a) {
           px += m[a] * x[a][0];
           py += m[a] * x[a][1];
           pz += m[a] * x[a][2];
