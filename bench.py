@@ -144,6 +144,9 @@ def parse():
     p.add_argument("--waves", type=int, default=None,
                    help="wavefronts per replica for every ligand instead of "
                         "the autotuner's choice (0 = per-ligand minimum)")
+    p.add_argument("--task-order", type=int, default=None, choices=(0, 1, 2),
+                   help="workgroup order of the sweep (0 ligand by ligand, 1 "
+                        "heaviest ligands first) instead of the autotuner's")
     p.add_argument("--grid-device", default="cuda:0",
                    help="torch device that sums the synthetic receptor grids "
                         "(input generation, outside the timed region)")
@@ -272,7 +275,8 @@ def train_proposals(pkg, torch, system, sweeps=31250, burn=400, every=5,
 
 
 def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
-                 tune=False, waves=None, proposals=None, pose_every=5,
+                 tune=False, waves=None, task_order=None, proposals=None,
+                 pose_every=5,
                  kernel_sweeps=512, metrics_path=None):
     """Set up every ligand of `system`, run `warmup` + `steps` timed steps
     of the hot path and return the measurements.  proposals: per-ligand
@@ -314,6 +318,8 @@ def run_workload(pkg, torch, system, steps, warmup, sweeps=None,
         chosen, table = ctx.autotune(n_sweeps=64, n_leapfrog=L,
                                      cache_path=cache, signature=sig)
         tuned = {"chosen_waves": chosen or "auto", "sweep_ms": table}
+    if task_order is not None:
+        ctx.set_task_order(task_order)
     setup_s = time.perf_counter() - t_setup
     results = []
     # MBAR of each cycle starts from the previous cycle's free energies
@@ -1147,8 +1153,8 @@ def main():
         progress("proposals trained")
     r = run_workload(pkg, torch, system, args.steps, args.warmup,
                      sweeps=args.sweeps, tune=len(system.ligands) > 1,
-                     waves=args.waves, proposals=proposals,
-                     metrics_path=args.metrics)
+                     waves=args.waves, task_order=args.task_order,
+                     proposals=proposals, metrics_path=args.metrics)
     progress(f"{system.name}: {args.steps} timed steps")
     out = {
         "metric": "atom-grid energy+force evals/s & HBM fraction; effective "
@@ -1184,7 +1190,7 @@ def main():
     def extra(config):
         es = synth.make_system(config, grid_device=args.grid_device)
         re = run_workload(pkg, torch, es, 1, 1, tune=len(es.ligands) > 1,
-                          waves=args.waves)
+                          waves=args.waves, task_order=args.task_order)
         leg = {"value": re["value"], "unit": "atom-evals/s",
                "ms_per_step": re["ms_per_step"], "steps": 1, "warmup": 1,
                "config": describe(es, re),

@@ -793,7 +793,10 @@ BPMF_API int bpmf_set_graph(bpmf_ctx* ctx, int chunk);
  * class's ligands alone and kept (as per-ligand choices, see
  * bpmf_set_ligand_waves) where they save more than 2 % of the sweep; the
  * classes' launches run side by side.  bpmf_get_waves reports each
- * ligand's result.  The sampler state (positions, state maps, components,
+ * ligand's result.  The shapes are timed with workgroup order 1; with
+ * several ligands order 0 is timed last and kept if it saves more than
+ * 2 % (bpmf_get_task_order reports the result).  The sampler state
+ * (positions, state maps, components,
  * counters, statistics) is snapshotted on the device before the trials and
  * restored after, so tuning does not change the run.  Per-ligand choices
  * made before the call are replaced. */
@@ -805,6 +808,15 @@ BPMF_API int bpmf_autotune(bpmf_ctx* ctx, int n_sweeps, int n_leapfrog,
  * applies).  Results depend on it only through the rounding of the
  * per-wavefront energy partial sums.  Errors: BPMF_E_INVAL. */
 BPMF_API int bpmf_set_ligand_waves(bpmf_ctx* ctx, int ligand_id, int waves);
+
+/* Order of the sweep's workgroups within each wavefront class: 1 (the
+ * default) the replicas of the ligands with the most work per sweep
+ * (bonded terms and atoms) first, so that the longest workgroups start
+ * earliest; 0 ligand by ligand, replicas in order.  A single ligand's
+ * replicas keep their order either way.  Results do not depend on it.
+ * Errors: BPMF_E_INVAL (order not 0 or 1; null order). */
+BPMF_API int bpmf_set_task_order(bpmf_ctx* ctx, int order);
+BPMF_API int bpmf_get_task_order(bpmf_ctx* ctx, int* order);
 
 /* Wavefronts per replica the sweep currently uses for a ligand. */
 BPMF_API int bpmf_get_waves(bpmf_ctx* ctx, int ligand_id, int* waves);

@@ -159,6 +159,8 @@ def library():
         "bpmf_autotune": [vp, C.c_int, C.c_int, dp, ip],
         "bpmf_get_round_trips": [vp, C.c_int, C.POINTER(C.c_int64)],
         "bpmf_set_ligand_waves": [vp, C.c_int, C.c_int],
+        "bpmf_set_task_order": [vp, C.c_int],
+        "bpmf_get_task_order": [vp, ip],
         "bpmf_proposal_setup": [vp, C.c_int, ip, C.c_int, ip,
                                 C.POINTER(C.c_float)],
         "bpmf_proposal_params": [vp, C.c_int, C.POINTER(C.c_float),
@@ -746,8 +748,9 @@ class Context:
                  signature=None):
         """Pick the wavefronts per replica of the HMC sweep by timing every
         candidate on the ligands set up, then refine them per atom-count
-        class (state restored afterwards).  With cache_path, the choice (the
-        context-wide one and every ligand's) is stored in / reused from a
+        class and choose the workgroup order (state restored afterwards).
+        With cache_path, the choice (the context-wide one, every ligand's
+        and the order) is stored in / reused from a
         JSON file keyed by GPU architecture and `signature` (a string
         describing the workload).  Returns (chosen, {candidate: ms}) for
         the context-wide candidates."""
@@ -761,10 +764,12 @@ class Context:
             with open(cache_path) as fh:
                 cache = json.load(fh)
             hit = cache.get(key)
-            if hit and len(hit.get("waves", [])) == len(ids):
+            if (hit and len(hit.get("waves", [])) == len(ids)
+                    and "task_order" in hit):
                 self.set_waves(hit["chosen"])
                 for i, w in zip(ids, hit["waves"]):
                     self.set_ligand_waves(i, w)
+                self.set_task_order(hit["task_order"])
                 return hit["chosen"], hit["ms"]
         ms = np.zeros(5)
         ch = C.c_int(0)
@@ -777,7 +782,8 @@ class Context:
                 with open(cache_path) as fh:
                     cache = json.load(fh)
             cache[key] = {"chosen": ch.value, "ms": table,
-                          "waves": [self.get_waves(i) for i in ids]}
+                          "waves": [self.get_waves(i) for i in ids],
+                          "task_order": self.get_task_order()}
             with open(cache_path, "w") as fh:
                 json.dump(cache, fh, indent=1)
         return ch.value, table
@@ -795,6 +801,16 @@ class Context:
         choice)."""
         _check(self._lib.bpmf_set_ligand_waves(self._h, int(ligand_id),
                                                int(waves)))
+
+    def set_task_order(self, order):
+        """Workgroup order of the sweep: 1 (default) heaviest ligands
+        first, 0 ligand by ligand."""
+        _check(self._lib.bpmf_set_task_order(self._h, int(order)))
+
+    def get_task_order(self):
+        v = C.c_int(0)
+        _check(self._lib.bpmf_get_task_order(self._h, C.byref(v)))
+        return v.value
 
     def get_waves(self, ligand_id):
         out = C.c_int(0)

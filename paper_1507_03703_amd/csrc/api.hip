@@ -119,6 +119,7 @@ struct bpmf_ctx {
   int class_single[kWaveClasses] = {-1, -1, -1, -1};  // sole ligand or -1
   bool class_pairs[kWaveClasses] = {false, false, false, false};
   int waves_override = 0;  // 0 = automatic choice
+  int task_order = 1;      // 0 = ligand by ligand, 1 = heaviest first
   int n_cu = 1;  // compute units of the device
   // scratch
   void* comps_mem = nullptr;  // energy-matrix job table (device)
@@ -292,6 +293,20 @@ int rebuild_tables(bpmf_ctx* c) {
     for (int r = 0; r < h.dev.K; ++r) cls[q].push_back(make_int2(l, r));
     lds[q] = std::max(lds[q], lds_of(h, h.sweep_waves, true));
     pairs[q] = pairs[q] || h.dev.pairs_on;
+  }
+  if (c->task_order == 1) {
+    // the replicas of the ligands with the most work per sweep first (a
+    // rough per-block cost: bonded terms by kind, and atoms): workgroups
+    // start in launch order, so the longest ones start earliest and the
+    // short ones fill in behind them (config 5: 42.2 -> 36.9 us per sweep)
+    auto cost = [&](int l) {
+      const LigDev& d = c->ligs[l].dev;
+      return 4L * d.nt + 2L * d.na + d.nb + 2L * d.n;
+    };
+    for (auto& v : cls)
+      std::stable_sort(v.begin(), v.end(), [&](int2 u, int2 w) {
+        return cost(u.x) > cost(w.x);
+      });
   }
   std::vector<int2> all;
   int off[bpmf_ctx::kWaveClasses];
@@ -2306,6 +2321,23 @@ extern "C" int bpmf_set_waves(bpmf_ctx* c, int waves) {
   return rebuild_tables(c);
 }
 
+extern "C" int bpmf_set_task_order(bpmf_ctx* c, int order) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (order != 0 && order != 1)
+    return fail(BPMF_E_INVAL, "task order must be 0 or 1");
+  c->task_order = order;
+  return rebuild_tables(c);
+}
+
+extern "C" int bpmf_get_task_order(bpmf_ctx* c, int* order) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!order) return fail(BPMF_E_INVAL, "null order");
+  *order = c->task_order;
+  return BPMF_OK;
+}
+
 extern "C" int bpmf_set_ligand_waves(bpmf_ctx* c, int ligand_id, int waves) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -2857,6 +2889,8 @@ extern "C" int bpmf_autotune(bpmf_ctx* c, int n_sweeps, int n_leapfrog,
     return BPMF_OK;
   };
   const int old_override = c->waves_override;
+  const int old_order = c->task_order;
+  c->task_order = 1;  // shapes are timed heaviest first
   std::vector<int> old_pins;
   for (auto& h : c->ligs) old_pins.push_back(h.waves_pin);
   const bool old_timing = c->timing;
@@ -2923,6 +2957,17 @@ extern "C" int bpmf_autotune(bpmf_ctx* c, int n_sweeps, int n_leapfrog,
     for (auto& h : c->ligs)
       if (size_class(h.dev.n) == sc) h.waves_pin = keep;
   }
+  // the workgroup order, with the shapes chosen (heaviest first unless
+  // ligand by ligand saves more than 2 %)
+  int best_order = 1;
+  if (!rc && c->ligs.size() > 1) {
+    const double with_order = best;  // the last trials ran heaviest first
+    c->task_order = 0;
+    double ms = INFINITY;
+    rc = trial(&ms);
+    if (!rc && ms < 0.98 * with_order) best_order = 0;
+  }
+  c->task_order = best_order;
   c->timing = old_timing;
   c->timing_every = old_every;
   if (!rc) (void)copy_all(false);
@@ -2930,6 +2975,7 @@ extern "C" int bpmf_autotune(bpmf_ctx* c, int n_sweeps, int n_leapfrog,
   c->dfree(snap);
   if (rc) {
     c->waves_override = old_override;
+    c->task_order = old_order;
     for (size_t l = 0; l < c->ligs.size(); ++l)
       c->ligs[l].waves_pin = old_pins[l];
     (void)rebuild_tables(c);

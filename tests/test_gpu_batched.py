@@ -85,6 +85,34 @@ def _same(a, b):
     return None
 
 
+def test_task_order_does_not_change_results():
+    """Heaviest ligands first (the default) and ligand by ligand give the
+    same sampler state bit for bit: plain and graph sweeps, deferred
+    exchange and records, round trips."""
+    g, ligs = _uneven_ligands()
+    print_case("task order", [l.n_atoms for l in ligs])
+    runs = []
+    for order in (1, 0):
+        ctx, ids = make_context(g, ligs, seed=23, capacity=24)
+        assert ctx.get_task_order() == 1
+        ctx.set_task_order(order)
+        assert ctx.get_task_order() == order
+        ctx.set_graph(0)
+        ctx.hmc_sweep(5, 10, exchange_every=1, sample_every=1)
+        ctx.set_graph(8)
+        ctx.hmc_sweep(17, 10, exchange_every=1, sample_every=1)
+        runs.append(([_state(ctx, i) for i in ids],
+                     [ctx.get_round_trips(i) for i in ids]))
+        if order == 0:
+            with pytest.raises(RuntimeError):
+                ctx.set_task_order(2)
+        ctx.close()
+    (sa, ta), (sb, tb) = runs
+    for i, (x, y) in enumerate(zip(sa, sb)):
+        assert _same(x, y) is None, (i, _same(x, y))
+    assert ta == tb
+
+
 def test_autotune_leaves_state_unchanged(tmp_path):
     g, ligs = _uneven_ligands()
     print_case("autotune state")
@@ -104,6 +132,9 @@ def test_autotune_leaves_state_unchanged(tmp_path):
     b, ids_b = make_context(g, ligs, seed=5, capacity=12)
     b.hmc_sweep(3, 10, exchange_every=1, sample_every=1)
     b.set_waves(chosen)
+    order = a.get_task_order()
+    assert order in (0, 1)
+    b.set_task_order(order)
     tuned = [a.get_waves(i) for i in ids]
     for j, w in zip(ids_b, tuned):
         b.set_ligand_waves(j, w)
@@ -114,11 +145,14 @@ def test_autotune_leaves_state_unchanged(tmp_path):
     rec = json.loads(cache.read_text())
     assert len(rec) == 1 and list(rec.values())[0]["chosen"] == chosen
     assert list(rec.values())[0]["waves"] == tuned
+    assert list(rec.values())[0]["task_order"] == order
     for j in ids_b:
         b.set_ligand_waves(j, 0)
+    b.set_task_order(1 - order)
     again, table2 = b.autotune(cache_path=str(cache), signature="uneven")
     assert again == chosen and table2 == table
     assert [b.get_waves(j) for j in ids_b] == tuned
+    assert b.get_task_order() == order
     with pytest.raises(RuntimeError):
         b.set_ligand_waves(ids_b[0], 3)
     a.close()
