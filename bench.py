@@ -502,7 +502,7 @@ def bulk_leg(pkg, torch, system, reps=3, harness_min=10 ** 8):
         "sampling_s": sample_s,
         "energy_matrix": dict(line(evals_ukn, ukn_s, 12, "k_energy_matrix"),
                               atom_evals=evals_ukn, kernel="k_energy_matrix",
-                              launches=cmp_n // reps,
+                              timed_intervals_per_call=cmp_n // reps,
                               kernel_ms_total=ukn_s * 1e3),
         "harness": dict(line(npts, ge_ms * 1e-3, io, "k_grid_eval"),
                         points=npts,

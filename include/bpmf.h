@@ -264,8 +264,10 @@ BPMF_API int bpmf_energy_matrix(bpmf_ctx* ctx, int ligand_id, const float* dev_s
 /* bpmf_energy_matrix for n ligands in one call (host arrays of n entries;
  * dev_samples may be NULL, or have NULL entries, for recorded samples).
  * Every sample of every listed ligand is evaluated by one persistent
- * launch per wavefront class, so many small ligands fill the chip together;
- * each entry's u_kn is the one bpmf_energy_matrix writes.  Errors:
+ * launch per wavefront class (the classes' launches side by side; each
+ * workgroup takes a contiguous share of the samples of equal estimated
+ * cost), so many small ligands fill the chip together; each entry's u_kn
+ * is the one bpmf_energy_matrix writes.  Errors:
  * BPMF_E_INVAL naming the entry (nothing is launched). */
 BPMF_API int bpmf_energy_matrix_batch(bpmf_ctx* ctx, int n,
                                       const int* ligand_ids,
@@ -834,8 +836,9 @@ enum {
 /* While enabled, every `every`-th launch of each timed kernel (HMC: the
  * kernels of one sweep, which with scheme 0 also apply the previous sweep's
  * exchange and record, with scheme 1 followed by the tail kernel; TAIL: the
- * kernel that closes a scheme-0 call; COMPONENTS: per-sample components of
- * energy_matrix; GRID_EVAL: the kernel of bpmf_grid_eval) is bracketed by a
+ * kernel that closes a scheme-0 call; COMPONENTS: the launches of one
+ * energy-matrix call, which run side by side, as one interval; GRID_EVAL:
+ * the kernel of bpmf_grid_eval) is bracketed by a
  * pair of HIP events recorded on the context's stream (at most 8192 pairs
  * per kernel between reads).  Enabling clears earlier records. */
 BPMF_API int bpmf_set_timing(bpmf_ctx* ctx, int enable, int every);

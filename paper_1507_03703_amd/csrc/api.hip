@@ -1286,6 +1286,18 @@ struct UknPlan {
   int wave_lds[bpmf_ctx::kWaveClasses] = {0, 0, 0, 0};
 };
 
+// Estimated issue cost of one u_kn sample of a ligand whose atoms need W
+// wavefronts (one wavefront per sample: W atoms per lane): the grid terms
+// of each lane's atoms, the 64-term chunks of each bonded kind (roughly
+// 150, 90 and 40 instructions per term), the sums and the column.  Only
+// its proportions matter: it splits a launch's samples into shares of
+// equal work.
+int ukn_sample_cost(const LigDev& d, int W) {
+  auto chunks = [](int m) { return (m + kWave - 1) / kWave; };
+  return 100 * W + 150 * chunks(d.nt) + 90 * chunks(d.na) +
+         40 * chunks(d.nb) + 200 + 4 * d.K;
+}
+
 // Validates an energy-matrix batch and writes its job table into `jobs`
 // (room for n + kWaveClasses entries); allocates nothing.
 int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
@@ -1344,13 +1356,15 @@ int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
     const int W = 1 << q;
     p->off[q] = nj;
-    int64_t first = 0;
+    int64_t first = 0, cfirst = 0;
     for (int i = 0; i < n; ++i) {
       const LigHost& h = c->ligs[ligand_ids[i]];
       if (h.min_waves != W || n_samples[i] == 0) continue;
       UknJob J;
       J.lig = ligand_ids[i];
-      J.pad = 0;
+      J.cost = ukn_sample_cost(h.dev, W);
+      J.cfirst = cfirst;
+      cfirst += J.cost * n_samples[i];
       J.xs = dev_samples && dev_samples[i] ? dev_samples[i] : h.dev.samp_x;
       J.ukn = dev_ukn[i];
       J.n = n_samples[i];
@@ -1373,6 +1387,8 @@ int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
     p->total[q] = first;
     UknJob end{};
     end.first = first;
+    end.cfirst = cfirst;
+    end.cost = 1;
     jobs[nj++] = end;
   }
   p->group = group;
@@ -1380,21 +1396,53 @@ int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
   return BPMF_OK;
 }
 
-// the launches of a planned batch, the job table at d_jobs on the device
+// the launches of a planned batch, the job table at d_jobs on the device.
+// overlap: the classes' launches run side by side, the first on the
+// context's stream and each other one on a stream of its own forked from
+// it and joined back (the streams and events are created on first use);
+// otherwise one after the other.  Timed as one interval.
 int ukn_launch(bpmf_ctx* c, const UknPlan& p, const UknJob* d_jobs,
-               bool timed_ok) {
-  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
-    if (p.total[q] == 0) continue;
-    hipEvent_t t0, t1;
-    const bool timed =
-        timed_ok && c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
-    if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+               bool timed_ok, bool overlap) {
+  int act[bpmf_ctx::kWaveClasses], na = 0;
+  for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q)
+    if (p.total[q] != 0) act[na++] = q;
+  if (na == 0) return BPMF_OK;
+  hipEvent_t t0, t1;
+  const bool timed =
+      timed_ok && c->timer_begin(BPMF_TIMER_COMPONENTS, &t0, &t1);
+  if (timed) HIP_TRY(hipEventRecord(t0, c->stream));
+  const bool fork = overlap && na > 1;
+  if (fork) {
+    if (!c->class_fork)
+      HIP_TRY(hipEventCreateWithFlags(&c->class_fork, hipEventDisableTiming));
+    for (int i = 1; i < na; ++i) {
+      const int q = act[i];
+      if (!c->class_stream[q])
+        HIP_TRY(hipStreamCreateWithFlags(&c->class_stream[q],
+                                         hipStreamNonBlocking));
+      if (!c->class_join[q])
+        HIP_TRY(hipEventCreateWithFlags(&c->class_join[q],
+                                        hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(c->class_fork, c->stream));
+  }
+  for (int i = 0; i < na; ++i) {
+    const int q = act[i];
+    hipStream_t sq = c->stream;
+    if (fork && i > 0) {
+      sq = c->class_stream[q];
+      HIP_TRY(hipStreamWaitEvent(sq, c->class_fork, 0));
+    }
     HIP_TRY(launch_energy_matrix(
         c->grid, c->d_ligs, 1 << q, d_jobs + p.off[q], p.cnt[q], p.total[q],
         p.group, p.per_wave[q] ? p.wave_lds[q] : p.lds[q], c->n_cu,
-        p.pairs[q], p.per_wave[q], c->stream));
-    if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
+        p.pairs[q], p.per_wave[q], sq));
+    if (fork && i > 0) HIP_TRY(hipEventRecord(c->class_join[q], sq));
   }
+  if (fork)
+    for (int i = 1; i < na; ++i)
+      HIP_TRY(hipStreamWaitEvent(c->stream, c->class_join[act[i]], 0));
+  if (timed) HIP_TRY(hipEventRecord(t1, c->stream));
   return BPMF_OK;
 }
 }  // namespace
@@ -1427,7 +1475,7 @@ extern "C" int bpmf_energy_matrix_batch(bpmf_ctx* c, int n,
   HIP_TRY(hipMemcpyAsync(d_jobs, c->jobs_host, p.n_jobs * sizeof(UknJob),
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipEventRecord(c->jobs_copied, c->stream));
-  return ukn_launch(c, p, d_jobs, true);
+  return ukn_launch(c, p, d_jobs, true, true);
 }
 
 // ----------------------------------------------------------------------------
@@ -1486,7 +1534,7 @@ extern "C" int bpmf_energy_matrix_batch_noalloc(
     return rc;
   UknJob* d_jobs = (UknJob*)c->scratch_addr;
   HIP_TRY(launch_put_jobs(d_jobs, jobs, p.n_jobs, c->stream));
-  return ukn_launch(c, p, d_jobs, false);
+  return ukn_launch(c, p, d_jobs, false, false);
 }
 
 extern "C" int bpmf_energy_matrix(bpmf_ctx* c, int ligand_id,

@@ -210,15 +210,17 @@ hipError_t launch_exchange(const LigDev* d_lig, int n_ligs, int scheme,
 // 3), output u_kn (K x ld); its samples are [first, first + n) of the
 // launch's flat sample index
 struct UknJob {
-  int lig;  // index into the ligand table
-  int pad;
+  int lig;   // index into the ligand table
+  int cost;  // estimated cost of one sample (instruction-issue units)
   const float* xs;
   double* ukn;
   int64_t n, ld;
-  int64_t first;
+  int64_t first;   // flat index of the job's first sample
+  int64_t cfirst;  // cost of the launch's samples before the job's first
 };
 // d_jobs: n_jobs jobs in flat order, every ligand needing `waves`
-// wavefronts, then a sentinel with first = total; group = samples whose
+// wavefronts, then a sentinel with first = total and cfirst = the launch's
+// total cost (each block takes a contiguous share of equal cost); group = samples whose
 // columns are staged in LDS before they are written.  per_wave: one
 // wavefront per sample (k_energy_matrix_wave, for ligands whose pair terms
 // are not in the energy; `waves` is then the atoms per lane, 1 or 2, and

@@ -705,9 +705,30 @@ __global__ __launch_bounds__(256) void k_exchange(
 // reduced-energy matrix u_kn = beta_k (U0_n + sum_c w_kc Psi_cn) of samples
 // of one or many ligands (Estimation), energy only
 // ----------------------------------------------------------------------------
+// First sample of block b's share of a launch (b = nblocks: the end): the
+// shares are contiguous runs of the flat sample index of equal estimated
+// cost, so a block holding a large ligand's samples takes fewer of them.
+// Position P = b * total_cost / nblocks falls in job j (jobs[j].cfirst <= P
+// < jobs[j + 1].cfirst; the sentinel ends the list) and the share starts at
+// the first of its samples whose cost starts at or after P.  j: that job.
+__device__ __forceinline__ int64_t ukn_share_start(
+    const UknJob* __restrict__ jobs, int n_jobs, int b, int nblocks, int& j) {
+  const int64_t P = (int64_t)b * jobs[n_jobs].cfirst / nblocks;
+  int lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (jobs[mid].cfirst <= P) lo = mid; else hi = mid;
+  }
+  j = lo;
+  const int64_t c = jobs[lo].cost;
+  int64_t k = (P - jobs[lo].cfirst + c - 1) / c;
+  if (k > jobs[lo].n) k = jobs[lo].n;
+  return jobs[lo].first + k;
+}
+
 // One W-wave block evaluates one sample at a time, persistent over the
-// launch: block b takes the b-th contiguous share of the flat sample index
-// over all jobs (job j's samples are [jobs[j].first, jobs[j+1].first); a
+// launch: block b takes the b-th contiguous share (by cost) of the flat
+// sample index over all jobs (job j's samples are [jobs[j].first, jobs[j+1].first); a
 // sentinel ends the list), so it stages a ligand's topology once per
 // segment.  Each sample's column (K entries) goes to LDS; every `group`
 // samples (at most 16: a 128-byte line of each row) the columns are written
@@ -720,17 +741,13 @@ __global__ __launch_bounds__(W * kWave) void k_energy_matrix(
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const float w0[C] = {};
-  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-  const int64_t b0 = (int64_t)blockIdx.x * per;
-  const int64_t b1 = b0 + per < total ? b0 + per : total;
-  if (b0 >= b1) return;
   // ligands and jobs come from restrict arguments: the u_kn stores cannot
   // clobber them, so they load into scalar registers
-  int j = 0, hi = n_jobs;  // jobs[j].first <= b0 < jobs[hi].first
-  while (hi - j > 1) {
-    const int mid = (j + hi) / 2;
-    if (jobs[mid].first <= b0) j = mid; else hi = mid;
-  }
+  int j, j_end;
+  const int64_t b0 = ukn_share_start(jobs, n_jobs, blockIdx.x, gridDim.x, j);
+  const int64_t b1 =
+      ukn_share_start(jobs, n_jobs, blockIdx.x + 1, gridDim.x, j_end);
+  if (b0 >= b1) return;
   typedef const float __attribute__((address_space(1))) gfloat;
   typedef const double __attribute__((address_space(1))) gcdouble;
   for (int64_t s = b0; s < b1; ++j) {
@@ -822,15 +839,11 @@ __global__ __launch_bounds__(kUknWaves * kWave) void k_energy_matrix_wave(
     const UknJob* __restrict__ jobs, int n_jobs, int64_t total) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
-  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-  const int64_t b0 = (int64_t)blockIdx.x * per;
-  const int64_t b1 = b0 + per < total ? b0 + per : total;
+  int j, j_end;
+  const int64_t b0 = ukn_share_start(jobs, n_jobs, blockIdx.x, gridDim.x, j);
+  const int64_t b1 =
+      ukn_share_start(jobs, n_jobs, blockIdx.x + 1, gridDim.x, j_end);
   if (b0 >= b1) return;
-  int j = 0, hi = n_jobs;  // jobs[j].first <= b0 < jobs[hi].first
-  while (hi - j > 1) {
-    const int mid = (j + hi) / 2;
-    if (jobs[mid].first <= b0) j = mid; else hi = mid;
-  }
   typedef const float __attribute__((address_space(1))) gfloat;
   typedef const double __attribute__((address_space(1))) gcdouble;
   auto wave_fence = []() {
