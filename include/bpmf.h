@@ -263,11 +263,12 @@ BPMF_API int bpmf_energy_matrix(bpmf_ctx* ctx, int ligand_id, const float* dev_s
 
 /* bpmf_energy_matrix for n ligands in one call (host arrays of n entries;
  * dev_samples may be NULL, or have NULL entries, for recorded samples).
- * Every sample of every listed ligand is evaluated by one persistent
- * launch per wavefront class (the classes' launches side by side; each
- * workgroup takes a contiguous share of the samples of equal estimated
- * cost), so many small ligands fill the chip together; each entry's u_kn
- * is the one bpmf_energy_matrix writes.  Errors:
+ * Every sample of every listed ligand is evaluated by persistent launches
+ * (ligands of up to 64 and of 65-128 atoms side by side, or in one launch
+ * when the larger ones hold most of the work; each workgroup takes a
+ * contiguous share of the samples of equal estimated cost), so many small
+ * ligands fill the chip together; each entry's u_kn is the one
+ * bpmf_energy_matrix writes.  Errors:
  * BPMF_E_INVAL naming the entry (nothing is launched). */
 BPMF_API int bpmf_energy_matrix_batch(bpmf_ctx* ctx, int n,
                                       const int* ligand_ids,

@@ -1352,6 +1352,31 @@ int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
                   "states' weights and columns; max 65536)",
                   i, need, h.dev.K);
   }
+  // Ligands of up to 64 and of 65-128 atoms run as two launches side by
+  // side, or, when the larger ones hold at least 40 % of the estimated
+  // cost, as one launch of the two-atoms-per-lane kernel (its occupancy
+  // equals the one-atom kernel's; a lane without a second atom skips it):
+  // a minority of large ligands fits in the tail of the small ligands'
+  // launch, a majority would leave two tails (config-3 sample set, 27 %:
+  // 3.9e10 atom-evals/s side by side against 3.7e10 merged; config 5,
+  // 60 %: 2.9e10 against 3.1e10).  Not when one of them has pair terms in
+  // its energy or needs more LDS per wavefront than that kernel has.
+  bool merge = true;
+  double cost1 = 0.0, cost2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const LigHost& h = c->ligs[ligand_ids[i]];
+    if (h.min_waves > 2) continue;
+    if (h.dev.pairs_on ||
+        ukn_wave_lds_bytes(h.dev.K, h.dev.C, 2, h.dev.nb, h.dev.na,
+                           h.dev.nt) > 65536)
+      merge = false;
+    (h.min_waves == 1 ? cost1 : cost2) +=
+        (double)ukn_sample_cost(h.dev, h.min_waves) * (double)n_samples[i];
+  }
+  if (cost2 < 0.4 * (cost1 + cost2)) merge = false;
+  auto class_waves = [&](const LigHost& h) {
+    return merge && h.min_waves <= 2 ? 2 : h.min_waves;
+  };
   int nj = 0;
   for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
     const int W = 1 << q;
@@ -1359,10 +1384,10 @@ int ukn_plan(bpmf_ctx* c, int n, const int* ligand_ids,
     int64_t first = 0, cfirst = 0;
     for (int i = 0; i < n; ++i) {
       const LigHost& h = c->ligs[ligand_ids[i]];
-      if (h.min_waves != W || n_samples[i] == 0) continue;
+      if (class_waves(h) != W || n_samples[i] == 0) continue;
       UknJob J;
       J.lig = ligand_ids[i];
-      J.cost = ukn_sample_cost(h.dev, W);
+      J.cost = ukn_sample_cost(h.dev, h.min_waves);
       J.cfirst = cfirst;
       cfirst += J.cost * n_samples[i];
       J.xs = dev_samples && dev_samples[i] ? dev_samples[i] : h.dev.samp_x;

@@ -719,11 +719,16 @@ __device__ __forceinline__ int64_t ukn_share_start(
     const int mid = (lo + hi) / 2;
     if (jobs[mid].cfirst <= P) lo = mid; else hi = mid;
   }
-  j = lo;
   const int64_t c = jobs[lo].cost;
   int64_t k = (P - jobs[lo].cfirst + c - 1) / c;
   if (k > jobs[lo].n) k = jobs[lo].n;
-  return jobs[lo].first + k;
+  // block-uniform results, held in scalar registers (the 64-bit division
+  // is vector code)
+  j = __builtin_amdgcn_readfirstlane(lo);
+  const int64_t r = jobs[lo].first + k;
+  const uint32_t rlo = __builtin_amdgcn_readfirstlane((uint32_t)r);
+  const uint32_t rhi = __builtin_amdgcn_readfirstlane((uint32_t)(r >> 32));
+  return (int64_t)(((uint64_t)rhi << 32) | rlo);
 }
 
 // One W-wave block evaluates one sample at a time, persistent over the
