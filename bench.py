@@ -57,19 +57,19 @@ GRID_BYTES_PER_EVAL = 96  # 8 corners x 3 channels x 4 B
 # kernel and workload: one sweep launch (at the given wavefronts per
 # replica), one harness launch, one energy-matrix call (its launches
 # summed); valid only while the kernel sources hash to TRAFFIC_SOURCES
-TRAFFIC_SOURCES = "e0e891440375ce5d"
+TRAFFIC_SOURCES = "5bbe1275acda510c"
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = {
     ("k_hmc_sweep", "c5_large_batched"):
-        {"waves": 4, "fetch_kib": 9087.392, "write_kib": 4431.249},
+        {"waves": 4, "fetch_kib": 9087.386, "write_kib": 4431.231},
     ("k_hmc_sweep", "c2_plain_production"):
-        {"waves": None, "fetch_kib": 761.006, "write_kib": 198.215},
+        {"waves": None, "fetch_kib": 761.004, "write_kib": 198.215},
     ("k_hmc_sweep", "c3_batched_uneven"):
-        {"waves": 2, "fetch_kib": 37092.677, "write_kib": 23616.103},
+        {"waves": 2, "fetch_kib": 37105.157, "write_kib": 23616.926},
     ("k_grid_eval", "c3_batched_uneven"):
-        {"waves": None, "fetch_kib": 3380142.281, "write_kib": 3383700.0},
+        {"waves": None, "fetch_kib": 3379937.406, "write_kib": 3383700.0},
     ("k_energy_matrix", "c3_batched_uneven"):
-        {"waves": None, "fetch_kib": 1173620.891, "write_kib": 527227.125},
+        {"waves": None, "fetch_kib": 1178483.14, "write_kib": 535488.633},
 }
 KERNEL_SOURCES = ("device.h", "kernels.hip", "internal.h")
 
