@@ -283,13 +283,14 @@ BPMF_API int bpmf_energy_matrix_batch(bpmf_ctx* ctx, int n,
  * the call allocates nothing -- no device, pinned or staging memory, no
  * events.  Its job table (one entry per listed ligand with samples, plus
  * one per wavefront class) lives in a fixed device array of
- * BPMF_NOALLOC_MAX_JOBS + 4 entries (about 49 KB) that each device running
+ * BPMF_NOALLOC_MAX_JOBS + 4 entries (about 56 KB) that each device running
  * the library holds until the process ends; it is written by small kernels
  * on the context's stream, then read by the u_kn launches.  Every call on a
  * device shares that array: calls that overlap on one device (different
  * streams or contexts, not ordered by the caller) race and may compute
- * wrong results; calls ordered on one stream do not.  Its launches are not
- * covered by bpmf_set_timing.  Errors: as bpmf_energy_matrix_batch, plus
+ * wrong results; calls ordered on one stream do not.  Its launches run one
+ * after the other on the context's stream and are not covered by
+ * bpmf_set_timing.  Errors: as bpmf_energy_matrix_batch, plus
  * BPMF_E_INVAL when n exceeds BPMF_NOALLOC_MAX_JOBS and BPMF_E_UNIMPL when
  * the device index is 64 or more (no table address kept for it). */
 #define BPMF_NOALLOC_MAX_JOBS 1024

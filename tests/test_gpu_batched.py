@@ -223,18 +223,26 @@ def test_large_grid_workload_sampled_ligands():
     ctx.close()
 
 
-def test_energy_matrix_batch_equals_per_ligand_calls():
+@pytest.mark.parametrize("large", ["most", "few"])
+def test_energy_matrix_batch_equals_per_ligand_calls(large):
     """One batched u_kn call over ligands of one and two wavefronts (recorded
     samples for some, explicit device samples for others) writes exactly
-    the matrices of per-ligand calls, and matches the oracle's brute force."""
+    the matrices of per-ligand calls, and matches the oracle's brute force.
+    "most": the ligands of over 64 atoms hold most of the work (one launch
+    for all); "few": three samples each (the two launches side by side)."""
     g, ligs = _uneven_ligands()
-    print_case("energy_matrix batch", [l.n_atoms for l in ligs])
+    print_case("energy_matrix batch", [l.n_atoms for l in ligs], large)
     ctx, ids = make_context(g, ligs, seed=9, capacity=6)
     ctx.hmc_sweep(12, 10, exchange_every=1, sample_every=2)
     rng = np.random.default_rng(9)
     samples, ns = [], []
     for p, l in enumerate(ligs):
-        if p % 2:
+        if large == "few" and l.n_atoms > 64:
+            x = l.x0[0][None] + rng.normal(scale=0.3, size=(3, l.n_atoms, 3))
+            samples.append(torch.tensor(x, dtype=torch.float32,
+                                        device="cuda:0"))
+            ns.append(3)
+        elif p % 2:
             x = l.x0[0][None] + rng.normal(scale=0.3, size=(37, l.n_atoms, 3))
             samples.append(torch.tensor(x, dtype=torch.float32,
                                         device="cuda:0"))
