@@ -1035,7 +1035,9 @@ static int hmc_sweep_impl(bpmf_ctx* c, const bpmf_sweep_args* a, int only) {
       }
       bool forked[bpmf_ctx::kWaveClasses] = {false, false, false, false};
       bool first = true;
-      for (int q = 0; q < bpmf_ctx::kWaveClasses; ++q) {
+      // widest class first: it usually holds the heaviest ligands
+      for (int qi = 0; qi < bpmf_ctx::kWaveClasses; ++qi) {
+        const int q = bpmf_ctx::kWaveClasses - 1 - qi;
         if (!c->class_n[q]) continue;
         hipStream_t sq = st;
         if (!first) {
